@@ -169,7 +169,10 @@ void orc_fe_apply(int dim, const int32_t *n, const double *h, const double *kapp
     }
 }
 
-/* diagonal of A (Jacobi preconditioner, Sec. 3.2), assembled element-wise */
+/* diagonal A_ii of the assembled matrix (Jacobi preconditioner, Sec. 3.2),
+ * assembled element-wise: every element entry K_ab whose two local nodes are
+ * the same global node contributes (on an axis with a single voxel both
+ * node layers of an element are one node). */
 void orc_jacobi_diag(int dim, const int32_t *n, const double *h, const double *kappa, double *diag)
 {
     orc_grid g = mk_grid(dim, n, h);
@@ -181,7 +184,11 @@ void orc_jacobi_diag(int dim, const int32_t *n, const double *h, const double *k
     for (int64_t le = 0; le < nn; ++le) {
         int e[ORC_MAXD];
         unlin(&g, le, e);
-        for (int a = 0; a < na; ++a) diag[elem_node(&g, e, a)] += kappa[le] * K[a * na + a];
+        for (int a = 0; a < na; ++a)
+            for (int bb = 0; bb < na; ++bb) {
+                int64_t ga = elem_node(&g, e, a);
+                if (ga == elem_node(&g, e, bb)) diag[ga] += kappa[le] * K[a * na + bb];
+            }
     }
 }
 

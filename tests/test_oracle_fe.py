@@ -99,6 +99,15 @@ def test_jacobi_diagonal_closed_form(orc, dim):
     assert np.allclose(orc.jacobi_diag(kap).ravel(), np.diag(dense.assemble(kap)), rtol=1e-13)
 
 
+@pytest.mark.parametrize("shape", [(1, 5, 3), (2, 4, 3), (1, 6), (5, 1, 1)])
+def test_jacobi_diagonal_is_assembled_diagonal_on_thin_grids(orc, shape):
+    """P_Jac = 1 / A_ii of the assembled matrix (Sec. 3.2), also where an
+    axis has one or two voxels and element nodes coincide."""
+    from oracle import dense
+    kap = si.random_field(shape, 12, 0.5, 2.0)
+    assert np.allclose(orc.jacobi_diag(kap).ravel(), np.diag(dense.assemble(kap)), rtol=1e-13)
+
+
 @pytest.mark.parametrize("shape", [(8, 8), (6, 5, 4)])
 def test_rhs_invariants(orc, shape):
     """Sum f = 0 (f lies in the range of the periodic operator) and f = 0 for
