@@ -1,0 +1,206 @@
+/*
+ * unocg.h -- C ABI of the MI355X (gfx950) UNO-CG hot path.
+ *
+ * Implements the solver of Herb & Fritzen, "Accelerating Conjugate Gradient
+ * Solvers for Homogenization Problems with Unitary Neural Operators"
+ * (arXiv 2508.02681): the matrix-free linear finite-element operator of a
+ * periodic voxel cell with per-voxel conductivities (Sec. 3.1, Sec. 5.1),
+ * the Jacobi preconditioner (Sec. 3.2), the UNO preconditioner
+ * s = T^H Q T r with a unitary DFT T and per-mode weights (Sec. 4.2,
+ * eq. (fnocg-operator), Algorithm 2), preconditioned CG (Algorithm 1) and the
+ * effective conductivity of the cell (Sec. 5.1).
+ *
+ * Conventions shared by every entry point
+ *   Grid      d = 2 or 3; n[0..d-1] voxels per axis; domain [-L0/2, L0/2]^d,
+ *             voxel edge h_b = L0 / n[b] (Sec. 5).  Periodic boundary
+ *             conditions: n = prod n[b] free nodes (Sec. 3.1).
+ *   Layout    every field is a dense C-order array of n values, last axis
+ *             contiguous.  Node (i_1..i_d) is the lower corner of voxel
+ *             (i_1..i_d); voxel e owns the nodes e + s (mod n) for s in {0,1}^d.
+ *   Memory    every array argument is a DEVICE pointer owned by the caller,
+ *             except where a comment says "host".  The library never frees
+ *             caller memory.
+ *   Streams   `stream` is a hipStream_t (NULL = the default stream).  Work is
+ *             enqueued on it; calls return before it completes unless stated.
+ *   Errors    every call returns a uno_status; on failure nothing has been
+ *             written to the outputs unless stated.  uno_status_string()
+ *             names a status.
+ *   Precision UNO_F64 arrays are double, UNO_F32 arrays are float.
+ */
+#ifndef UNOCG_H
+#define UNOCG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    UNO_OK = 0,
+    UNO_ERR_ARG = -1,       /* null pointer, bad enum, bad tolerance, ... */
+    UNO_ERR_SHAPE = -2,     /* unsupported grid, or weight count mismatch */
+    UNO_ERR_NOT_SPD = -3,   /* safety check of Sec. 4.2.4 failed */
+    UNO_ERR_BREAKDOWN = -4, /* CG scalar non-finite or non-positive */
+    UNO_ERR_DEVICE = -5,    /* a HIP runtime call failed */
+    UNO_ERR_NOMEM = -6      /* device allocation failed */
+} uno_status;
+
+typedef enum { UNO_F64 = 0, UNO_F32 = 1, UNO_BF16 = 2 } uno_dtype;
+
+typedef struct {
+    int32_t dim;   /* 2 or 3 */
+    int32_t n[3];  /* voxels per axis; n[2] ignored for dim = 2 */
+    double L0;     /* edge of the cubic domain, > 0 */
+} uno_grid;
+
+/* Per-voxel conductivity kappa (phase-wise constant and isotropic in the
+ * paper, Sec. 5.1), n values, each > 0. dtype UNO_F64 or UNO_F32. */
+typedef struct {
+    const void *kappa;
+    uno_dtype dtype;
+} uno_material;
+
+const char *uno_status_string(uno_status s);
+
+/* y = A(kappa) u: matrix-free stiffness apply of the periodic linear FE
+ * discretization (Sec. 3.1, eq. (fem-linear-system); operator of Sec. 5.1).
+ * u, y: n values of dtype vec_t (UNO_F64 or UNO_F32), y must not alias u.
+ * material->dtype must equal vec_t. */
+uno_status fe_apply(const uno_grid *grid, const uno_material *mat, const void *u, void *y,
+                    uno_dtype vec_t, void *stream);
+
+/* s = D^-1 r with D = diag A(kappa): the Jacobi preconditioner (Sec. 3.2).
+ * The diagonal is formed from kappa on the fly; same dtypes as fe_apply.
+ * s may alias r. */
+uno_status jac_precond_apply(const uno_grid *grid, const uno_material *mat, const void *r, void *s,
+                             uno_dtype vec_t, void *stream);
+
+/* f = right-hand side of the fluctuation problem for the macroscopic
+ * temperature gradient gbar (host, d values): f_i = -int kappa grad N_i . gbar
+ * (decomposition of Sec. 5.1, eq. (thermal-decomposition)).  f: n values of
+ * dtype vec_t.  sum f = 0 up to rounding. */
+uno_status uno_macro_rhs(const uno_grid *grid, const uno_material *mat, const double *gbar, void *f,
+                         uno_dtype vec_t, void *stream);
+
+/* ---- UNO preconditioner (Sec. 4.2) ---------------------------------- */
+typedef struct uno_precond uno_precond; /* opaque; owns its device table and scratch */
+
+/* Builds Q of eq. (prec-sparse-def) for c = 1 from the weights
+ * theta (host, ntheta = (2M+1)^(d-1) (M+1) values):
+ *   theta[0]   bypass, W = theta[0]^2                          (psi(t) = t^2)
+ *   theta[i]   learned mode i of K = [-M..M]^(d-1) x [0..M] \ {0}, modes in
+ *              lexicographic order of (k_1..k_d) with the zero mode skipped;
+ *   Phi(k) = W + theta[i]^2 on k in K and on its point reflection -k,
+ *            W elsewhere, 0 at k = 0 (the preconditioner shares the constant
+ *            null space of A, Sec. 4.2.4 remark); on the plane k_d = 0, where
+ *            k and -k are both learned, the mean of the two values is used
+ *            so that the output is real.
+ * Requires 2M+1 <= n[b] on every axis.  The safety check of Sec. 4.2.4 is
+ * run on the host: every Phi(k), k != 0, must exceed eps_spd, else
+ * UNO_ERR_NOT_SPD.  table_t: UNO_F64, UNO_F32 or UNO_BF16 storage of the
+ * table (arithmetic in the vector precision of each apply).  Allocates
+ * device memory on the current device; synchronous. */
+uno_status uno_precond_create(const uno_grid *grid, int32_t M, const double *theta, int64_t ntheta,
+                              double eps_spd, uno_dtype table_t, uno_precond **out);
+
+/* FANS reference preconditioner (Sec. 3.3.4, eq. (FANS-prec-fields)) as a
+ * UNO table: Phi(k) = 1 / (kappa_ref lambda(k)), lambda the symbol of the
+ * homogeneous unit-conductivity operator, 0 at k = 0 (the UNO with this
+ * table reproduces FANS, Sec. 4.2.2). */
+uno_status uno_precond_create_fans(const uno_grid *grid, double kappa_ref, uno_dtype table_t,
+                                   uno_precond **out);
+
+/* s = T^H Q T r (Algorithm 2, preconditioner lines) with T the unitary DFT.
+ * r, s: n values of dtype vec_t; s may alias r.  Uses the precond's scratch,
+ * so concurrent applies of one precond on different streams race. */
+uno_status uno_precond_apply(const uno_precond *p, const void *r, void *s, uno_dtype vec_t, void *stream);
+
+/* Copies the half-spectrum table (n[0] x .. x n[d-2] x (n[d-1]/2+1) values,
+ * C order, unscaled Phi) to host memory `out` (host). For inspection. */
+uno_status uno_precond_table(const uno_precond *p, double *out, int64_t nout);
+
+uno_status uno_precond_destroy(uno_precond *p);
+
+/* ---- Preconditioned CG (Algorithm 1 / Algorithm 2) ------------------ */
+enum { UNO_PREC_NONE = 0, UNO_PREC_JACOBI = 1, UNO_PREC_UNO = 2 };
+
+typedef struct {
+    int32_t kind;            /* UNO_PREC_* */
+    const uno_precond *uno;  /* required for UNO_PREC_UNO */
+    double rtol;             /* stop when ||r||_inf <= rtol ||r_0||_inf */
+    int32_t max_iter;        /* > 0 */
+    uno_dtype op_t;          /* precision of the operator apply: UNO_F64 or UNO_F32 */
+    uno_dtype prec_t;        /* precision of the preconditioner apply: UNO_F64 or UNO_F32 */
+    int32_t graph_chunk;     /* iterations per host check; 0 = adaptive */
+} uno_solve_opts;
+
+typedef struct {
+    int32_t iters;        /* loop passes = preconditioner applies = matvecs */
+    int32_t converged;    /* 1 if ||r||_inf <= rtol ||r_0||_inf */
+    double rel_res;       /* recurrence residual ||r||_inf / ||r_0||_inf */
+    double true_rel_res;  /* ||f - A u||_inf / ||f||_inf recomputed in FP64 */
+    double r0_norm;       /* ||r_0||_inf */
+} uno_solve_info;
+
+/* Solves A(kappa) u = f for the zero-mean periodic fluctuation.
+ * f is uno_macro_rhs(gbar = macro_load) when macro_load (host, d values) is
+ * non-NULL, else `rhs` (device, n doubles).  u (device, n doubles) holds the
+ * initial guess on entry and the zero-mean solution on exit.
+ * Reductions, the residual recurrence and the stopping test are FP64 in
+ * every mode.  Non-convergence within max_iter is not an error (converged =
+ * 0); a non-finite or non-positive r.s or d.A d gives UNO_ERR_BREAKDOWN.
+ * res_hist (host, nullable, max_iter + 1 doubles) receives ||r||_inf per
+ * pass.  Synchronous: returns after the solve has finished on `stream`.
+ * Workspace is cached per grid and released by uno_shutdown(). */
+uno_status pcg_solve(const uno_grid *grid, const uno_material *mat, const double *macro_load,
+                     const double *rhs, double *u, const uno_solve_opts *opts, uno_solve_info *info,
+                     double *res_hist, void *stream);
+
+/* Effective conductivity (Sec. 5.1; the homogenized property handed back to
+ * the macro scale, Sec. 1): for load j with gradient g_j (host loads,
+ * nload x d) and solution u_j (device, nload x n doubles, C order),
+ *   q_j = (1/|Omega|) int kappa (g_j + grad u_j) dx,
+ * and out (host, d x d, row-major) = Q G^-1 with Q = [q_1..q_d],
+ * G = [g_1..g_d]; nload must equal d and G be invertible.  Synchronous. */
+uno_status effective_tensor(const uno_grid *grid, const uno_material *mat, int32_t nload,
+                            const double *loads, const double *u, double *out, void *stream);
+
+/* ---- Second-order training of the weights (Sec. 4.4, c = 1) ---------- */
+/* Accumulates the features of eq. (features-c-1) over ns samples:
+ *   alpha(k) += (1/ns_total) |f^(k)|^2, beta(k) += (2/ns_total) Re(conj(f^) u^)
+ * with hats = unitary DFT, on the half spectrum (n[0] x .. x (n[d-1]/2+1)
+ * doubles each, device, caller-zeroed before the first call).  f, u: device,
+ * ns x n doubles.  Asynchronous. */
+uno_status uno_train_accumulate(const uno_grid *grid, int32_t ns, const double *f, const double *u,
+                                double ns_total, double *alpha, double *beta, void *stream);
+
+/* Exact minimiser over theta (host, ntheta values) of the loss
+ * L = alpha.(Phi o Phi) - beta.Phi with Phi parametrized as in
+ * uno_precond_create; alpha, beta: device half-spectrum features.
+ * Synchronous. */
+uno_status uno_train_fit(const uno_grid *grid, int32_t M, const double *alpha, const double *beta,
+                         double *theta, int64_t ntheta, void *stream);
+
+/* ---- Timing of one kernel family (for roofline accounting) ----------- */
+enum {
+    UNO_KT_NONE = 0,
+    UNO_KT_MATVEC = 1,   /* operator apply inside CG (direction update + A d + d.Ad) */
+    UNO_KT_UPDATE = 2,   /* residual/solution update (+ Jacobi + r.s) */
+    UNO_KT_FFT_FWD = 3,  /* first transform pass of the UNO apply */
+    UNO_KT_FFT_MID = 4,  /* middle pass: transform, Phi multiply, inverse */
+    UNO_KT_FFT_INV = 5   /* last inverse pass (+ r.s) */
+};
+/* Brackets every launch of kernel family `which` with HIP events on its
+ * stream (UNO_KT_NONE disables); uno_timing_read synchronizes those events
+ * and returns the summed duration (ms) and launch count since enabling. */
+uno_status uno_timing_enable(int32_t which);
+uno_status uno_timing_read(double *total_ms, int64_t *launches);
+
+/* Releases cached workspaces (all devices). */
+uno_status uno_shutdown(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* UNOCG_H */

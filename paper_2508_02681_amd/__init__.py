@@ -1,0 +1,325 @@
+"""Python binding of the gfx950 UNO-CG library (libunocg.so, C ABI in
+include/unocg.h).
+
+Argument marshalling only: every step of the solver runs in the HIP kernels
+of the library.  Tensors must be contiguous CUDA (HIP) tensors; work is
+enqueued on torch's current stream.  The binding refuses to run when the
+library has not been built (``python -m paper_2508_02681_amd.build``).
+
+Entry points mirror the C ABI: fe_apply, jac_precond_apply, uno_macro_rhs,
+UnoPrecond (uno_precond_create / _create_fans / _apply / _destroy),
+pcg_solve, effective_tensor, uno_train_accumulate, uno_train_fit.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libunocg.so")
+
+UNO_F64, UNO_F32, UNO_BF16 = 0, 1, 2
+UNO_PREC_NONE, UNO_PREC_JACOBI, UNO_PREC_UNO = 0, 1, 2
+KT_NONE, KT_MATVEC, KT_UPDATE, KT_FFT_FWD, KT_FFT_MID, KT_FFT_INV = 0, 1, 2, 3, 4, 5
+STATUS = {0: "UNO_OK", -1: "UNO_ERR_ARG", -2: "UNO_ERR_SHAPE", -3: "UNO_ERR_NOT_SPD",
+          -4: "UNO_ERR_BREAKDOWN", -5: "UNO_ERR_DEVICE", -6: "UNO_ERR_NOMEM"}
+
+
+class UnoError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        super().__init__("%s failed: %s (%d)" % (where, STATUS.get(status, "?"), status))
+
+
+class uno_grid(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("n", ctypes.c_int32 * 3), ("L0", ctypes.c_double)]
+
+
+class uno_material(ctypes.Structure):
+    _fields_ = [("kappa", ctypes.c_void_p), ("dtype", ctypes.c_int)]
+
+
+class uno_solve_opts(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("uno", ctypes.c_void_p), ("rtol", ctypes.c_double),
+                ("max_iter", ctypes.c_int32), ("op_t", ctypes.c_int), ("prec_t", ctypes.c_int),
+                ("graph_chunk", ctypes.c_int32)]
+
+
+class uno_solve_info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32), ("rel_res", ctypes.c_double),
+                ("true_rel_res", ctypes.c_double), ("r0_norm", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Loads libunocg.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libunocg.so is not built (run python -m paper_2508_02681_amd.build); "
+                           "there is no fallback path")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    vp, i32, i64, f64, i = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_int
+    G, Mt = P(uno_grid), P(uno_material)
+    sig = {
+        "uno_status_string": ([i], ctypes.c_char_p),
+        "fe_apply": ([G, Mt, vp, vp, i, vp], i),
+        "jac_precond_apply": ([G, Mt, vp, vp, i, vp], i),
+        "uno_macro_rhs": ([G, Mt, P(f64), vp, i, vp], i),
+        "uno_precond_create": ([G, i32, P(f64), i64, f64, i, P(vp)], i),
+        "uno_precond_create_fans": ([G, f64, i, P(vp)], i),
+        "uno_precond_apply": ([vp, vp, vp, i, vp], i),
+        "uno_precond_table": ([vp, P(f64), i64], i),
+        "uno_precond_destroy": ([vp], i),
+        "pcg_solve": ([G, Mt, P(f64), vp, vp, P(uno_solve_opts), P(uno_solve_info), P(f64), vp], i),
+        "effective_tensor": ([G, Mt, i32, P(f64), vp, P(f64), vp], i),
+        "uno_train_accumulate": ([G, i32, vp, vp, f64, vp, vp, vp], i),
+        "uno_train_fit": ([G, i32, vp, vp, P(f64), i64, vp], i),
+        "uno_timing_enable": ([i32], i),
+        "uno_timing_read": ([P(f64), P(i64)], i),
+        "uno_shutdown": ([], i),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = L
+    return L
+
+
+def _check(st, where):
+    if st != 0:
+        raise UnoError(st, where)
+
+
+def _dt(t: torch.dtype) -> int:
+    if t == torch.float64:
+        return UNO_F64
+    if t == torch.float32:
+        return UNO_F32
+    if t == torch.bfloat16:
+        return UNO_BF16
+    raise TypeError("unsupported dtype %s" % t)
+
+
+def make_grid(shape, L0=1.0) -> uno_grid:
+    shape = tuple(int(s) for s in shape)
+    if len(shape) not in (2, 3):
+        raise ValueError("grid must be 2D or 3D")
+    g = uno_grid()
+    g.dim = len(shape)
+    for b in range(3):
+        g.n[b] = shape[b] if b < len(shape) else 1
+    g.L0 = float(L0)
+    return g
+
+
+def _dev(t: torch.Tensor, name: str, dtype=None):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA (HIP) tensor" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _mat(kappa: torch.Tensor) -> uno_material:
+    m = uno_material()
+    m.kappa = _dev(kappa, "kappa")
+    m.dtype = _dt(kappa.dtype)
+    return m
+
+
+def fe_apply(kappa: torch.Tensor, u: torch.Tensor, y: torch.Tensor | None = None, L0=1.0) -> torch.Tensor:
+    """y = A(kappa) u (matrix-free periodic FE operator)."""
+    if y is None:
+        y = torch.empty_like(u)
+    g = make_grid(kappa.shape, L0)
+    _check(lib().fe_apply(ctypes.byref(g), ctypes.byref(_mat(kappa)), _dev(u, "u", kappa.dtype),
+                          _dev(y, "y", kappa.dtype), _dt(u.dtype), _stream()), "fe_apply")
+    return y
+
+
+def jac_precond_apply(kappa: torch.Tensor, r: torch.Tensor, s: torch.Tensor | None = None, L0=1.0):
+    if s is None:
+        s = torch.empty_like(r)
+    g = make_grid(kappa.shape, L0)
+    _check(lib().jac_precond_apply(ctypes.byref(g), ctypes.byref(_mat(kappa)), _dev(r, "r", kappa.dtype),
+                                   _dev(s, "s", kappa.dtype), _dt(r.dtype), _stream()), "jac_precond_apply")
+    return s
+
+
+def uno_macro_rhs(kappa: torch.Tensor, gbar, out: torch.Tensor | None = None, dtype=torch.float64, L0=1.0):
+    if out is None:
+        out = torch.empty(kappa.shape, dtype=dtype, device=kappa.device)
+    g = make_grid(kappa.shape, L0)
+    gb = np.ascontiguousarray(gbar, dtype=np.float64)
+    if gb.size != len(kappa.shape):
+        raise ValueError("gbar needs one value per axis")
+    _check(lib().uno_macro_rhs(ctypes.byref(g), ctypes.byref(_mat(kappa)),
+                               gb.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _dev(out, "f"),
+                               _dt(out.dtype), _stream()), "uno_macro_rhs")
+    return out
+
+
+def num_weights(dim: int, M: int) -> int:
+    return (2 * M + 1) ** (dim - 1) * (M + 1)
+
+
+class UnoPrecond:
+    """Owns a uno_precond handle (device table + scratch)."""
+
+    def __init__(self, handle, shape, L0):
+        self._h = handle
+        self.shape = tuple(shape)
+        self.L0 = L0
+
+    @classmethod
+    def create(cls, shape, M, theta, eps_spd=1e-300, table_dtype=torch.float64, L0=1.0):
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        g = make_grid(shape, L0)
+        h = ctypes.c_void_p()
+        _check(lib().uno_precond_create(ctypes.byref(g), int(M), th.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                        th.size, float(eps_spd), _dt(table_dtype), ctypes.byref(h)),
+               "uno_precond_create")
+        return cls(h, shape, L0)
+
+    @classmethod
+    def fans(cls, shape, kappa_ref, table_dtype=torch.float64, L0=1.0):
+        g = make_grid(shape, L0)
+        h = ctypes.c_void_p()
+        _check(lib().uno_precond_create_fans(ctypes.byref(g), float(kappa_ref), _dt(table_dtype), ctypes.byref(h)),
+               "uno_precond_create_fans")
+        return cls(h, shape, L0)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def apply(self, r: torch.Tensor, s: torch.Tensor | None = None) -> torch.Tensor:
+        if s is None:
+            s = torch.empty_like(r)
+        _check(lib().uno_precond_apply(self._h, _dev(r, "r"), _dev(s, "s", r.dtype), _dt(r.dtype), _stream()),
+               "uno_precond_apply")
+        return s
+
+    def table(self) -> np.ndarray:
+        shp = list(self.shape)
+        shp[-1] = shp[-1] // 2 + 1
+        out = np.empty(shp, dtype=np.float64)
+        _check(lib().uno_precond_table(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), out.size),
+               "uno_precond_table")
+        return out
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            lib().uno_precond_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def pcg_solve(kappa: torch.Tensor, macro_load=None, rhs: torch.Tensor | None = None, u: torch.Tensor | None = None,
+              kind="jacobi", precond: UnoPrecond | None = None, rtol=1e-6, max_iter=100000,
+              op_dtype=torch.float64, prec_dtype=torch.float64, graph_chunk=0, history=False, L0=1.0):
+    """Preconditioned CG (Algorithm 1/2).  Returns (u, info dict[, hist])."""
+    kinds = {"none": UNO_PREC_NONE, "jacobi": UNO_PREC_JACOBI, "uno": UNO_PREC_UNO}
+    g = make_grid(kappa.shape, L0)
+    if u is None:
+        u = torch.zeros(kappa.shape, dtype=torch.float64, device=kappa.device)
+    o = uno_solve_opts()
+    o.kind = kinds[kind]
+    o.uno = precond.handle if (precond is not None and kind == "uno") else None
+    o.rtol = float(rtol)
+    o.max_iter = int(max_iter)
+    o.op_t = _dt(op_dtype)
+    o.prec_t = _dt(prec_dtype)
+    o.graph_chunk = int(graph_chunk)
+    info = uno_solve_info()
+    ml = None
+    if macro_load is not None:
+        ml = np.ascontiguousarray(macro_load, dtype=np.float64)
+        if ml.size != len(kappa.shape):
+            raise ValueError("macro_load needs one value per axis")
+    hist = np.zeros(max_iter + 1) if history else None
+    st = lib().pcg_solve(
+        ctypes.byref(g), ctypes.byref(_mat(kappa)),
+        ml.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if ml is not None else None,
+        _dev(rhs, "rhs", torch.float64) if rhs is not None else None,
+        _dev(u, "u", torch.float64), ctypes.byref(o), ctypes.byref(info),
+        hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if hist is not None else None, _stream())
+    _check(st, "pcg_solve")
+    d = dict(iters=info.iters, converged=bool(info.converged), rel_res=info.rel_res,
+             true_rel_res=info.true_rel_res, r0_norm=info.r0_norm)
+    if history:
+        return u, d, hist[: info.iters + 1].copy()
+    return u, d
+
+
+def effective_tensor(kappa: torch.Tensor, loads, solutions: torch.Tensor, L0=1.0) -> np.ndarray:
+    """kappa_bar (d x d) from the solutions of the d load cases."""
+    g = make_grid(kappa.shape, L0)
+    ld = np.ascontiguousarray(loads, dtype=np.float64)
+    d = len(kappa.shape)
+    out = np.zeros((d, d))
+    _check(lib().effective_tensor(ctypes.byref(g), ctypes.byref(_mat(kappa)), ld.shape[0],
+                                  ld.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                  _dev(solutions, "solutions", torch.float64),
+                                  out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _stream()), "effective_tensor")
+    return out
+
+
+def half_shape(shape):
+    s = list(shape)
+    s[-1] = s[-1] // 2 + 1
+    return tuple(s)
+
+
+def uno_train_accumulate(f: torch.Tensor, u: torch.Tensor, alpha: torch.Tensor, beta: torch.Tensor, ns_total,
+                         L0=1.0):
+    """alpha, beta (half spectrum, float64) += features of the samples f, u (ns x shape)."""
+    shape = tuple(f.shape[1:])
+    g = make_grid(shape, L0)
+    _check(lib().uno_train_accumulate(ctypes.byref(g), f.shape[0], _dev(f, "f", torch.float64),
+                                      _dev(u, "u", torch.float64), float(ns_total), _dev(alpha, "alpha", torch.float64),
+                                      _dev(beta, "beta", torch.float64), _stream()), "uno_train_accumulate")
+
+
+def uno_train_fit(shape, M, alpha: torch.Tensor, beta: torch.Tensor, L0=1.0) -> np.ndarray:
+    g = make_grid(shape, L0)
+    th = np.zeros(num_weights(len(shape), M))
+    _check(lib().uno_train_fit(ctypes.byref(g), int(M), _dev(alpha, "alpha", torch.float64),
+                               _dev(beta, "beta", torch.float64), th.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                               th.size, _stream()), "uno_train_fit")
+    return th
+
+
+def timing_enable(which: int):
+    _check(lib().uno_timing_enable(int(which)), "uno_timing_enable")
+
+
+def timing_read():
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    _check(lib().uno_timing_read(ctypes.byref(ms), ctypes.byref(n)), "uno_timing_read")
+    return ms.value, n.value
+
+
+def shutdown():
+    _check(lib().uno_shutdown(), "uno_shutdown")

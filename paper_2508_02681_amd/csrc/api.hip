@@ -1,0 +1,510 @@
+// C ABI of the library (declared in include/unocg.h): argument checks, grid
+// set-up, the UNO weight table (Sec. 4.2.2, eq. (fnocg-parametrization),
+// mode table for periodic BC), the FANS table (Sec. 3.3.4), the effective
+// tensor (Sec. 5.1) and the closed-form c = 1 training fit (Sec. 4.4).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "unocg_internal.h"
+#include "reduce.h"
+
+namespace unocg {
+
+uno_status ws_release_all();
+uno_status pcg_run(const Grid& g, const double* kappa, const double* macro_load3, const double* rhs, double* u,
+                   const uno_solve_opts* o, uno_solve_info* info, double* res_hist, hipStream_t st);
+
+uno_status hip_status(hipError_t e)
+{
+    if (e == hipSuccess) return UNO_OK;
+    if (e == hipErrorOutOfMemory) return UNO_ERR_NOMEM;
+    return UNO_ERR_DEVICE;
+}
+
+// Element stiffness of a brick with edges h (exact integration): the
+// coupling of two corners depends only on the axes along which they differ,
+// K(m) = sum_a prod_b f_ab(m_b), f_ab = (a == b) ? stiffness 1D : mass 1D,
+// 1D stiffness (1/h)[1 -1; -1 1], 1D mass (h/6)[2 1; 1 2].
+static double brick_weight(const double h[3], int m)
+{
+    double tot = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        double pr = 1.0;
+        for (int b = 0; b < 3; ++b) {
+            const bool diff = (m >> (2 - b)) & 1;
+            if (a == b) pr *= diff ? -1.0 / h[b] : 1.0 / h[b];
+            else pr *= diff ? h[b] / 6.0 : h[b] / 3.0;
+        }
+        tot += pr;
+    }
+    return tot;
+}
+
+uno_status make_grid(const uno_grid* gi, Grid* g)
+{
+    if (!gi || !g) return UNO_ERR_ARG;
+    if (gi->dim != 2 && gi->dim != 3) return UNO_ERR_SHAPE;
+    if (!(gi->L0 > 0.0) || !std::isfinite(gi->L0)) return UNO_ERR_ARG;
+    for (int b = 0; b < gi->dim; ++b)
+        if (gi->n[b] < 1 || gi->n[b] > (1 << 20)) return UNO_ERR_SHAPE;
+    memset(g, 0, sizeof(*g));
+    g->dim = gi->dim;
+    if (gi->dim == 3) {
+        for (int b = 0; b < 3; ++b) {
+            g->n[b] = gi->n[b];
+            g->h[b] = gi->L0 / gi->n[b];
+        }
+    } else {
+        g->n[0] = 1;
+        g->h[0] = 1.0;  // dummy axis: one voxel layer of unit thickness
+        for (int b = 0; b < 2; ++b) {
+            g->n[b + 1] = gi->n[b];
+            g->h[b + 1] = gi->L0 / gi->n[b];
+        }
+    }
+    g->total = (int64_t)g->n[0] * g->n[1] * g->n[2];
+    GridDev& d = g->dev;
+    d.n0 = g->n[0];
+    d.n1 = g->n[1];
+    d.n2 = g->n[2];
+    d.n = g->total;
+    for (int m = 0; m < 8; ++m) d.w[m] = brick_weight(g->h, m);
+    // diagonal: offsets that land on the node itself (only along axes of
+    // length 1 can a non-zero offset wrap onto the node)
+    double cd = 0.0;
+    for (int m = 0; m < 8; ++m) {
+        bool ok = true;
+        for (int b = 0; b < 3; ++b)
+            if (((m >> (2 - b)) & 1) && g->n[b] != 1) ok = false;
+        if (ok) cd += d.w[m];
+    }
+    d.cdiag = cd;
+    d.hvol = g->h[0] * g->h[1] * g->h[2];
+    for (int b = 0; b < 3; ++b) d.gcoef[b] = 1.0 / (4.0 * g->h[b]);
+    return UNO_OK;
+}
+
+// ---------------------------------------------------------------------------
+// kernel-family timing
+namespace {
+std::mutex g_tmu;
+int g_twhich = UNO_KT_NONE;
+std::vector<std::pair<hipEvent_t, hipEvent_t>> g_tev;
+}  // namespace
+
+void ktimer_begin(KTimer* t, int which, hipStream_t s)
+{
+    t->active = false;
+    if (g_twhich == UNO_KT_NONE || which != g_twhich) return;
+    t->which = which;
+    t->stream = s;
+    if (hipEventCreate(&t->a) != hipSuccess) return;
+    if (hipEventCreate(&t->b) != hipSuccess) {
+        (void)hipEventDestroy(t->a);
+        return;
+    }
+    (void)hipEventRecord(t->a, s);
+    t->active = true;
+}
+
+void ktimer_end(KTimer* t)
+{
+    if (!t->active) return;
+    (void)hipEventRecord(t->b, t->stream);
+    std::lock_guard<std::mutex> lk(g_tmu);
+    g_tev.emplace_back(t->a, t->b);
+    t->active = false;
+}
+
+}  // namespace unocg
+
+using namespace unocg;
+
+static hipStream_t S(void* s) { return (hipStream_t)s; }
+
+extern "C" {
+
+const char* uno_status_string(uno_status s)
+{
+    switch (s) {
+        case UNO_OK: return "ok";
+        case UNO_ERR_ARG: return "invalid argument";
+        case UNO_ERR_SHAPE: return "unsupported shape";
+        case UNO_ERR_NOT_SPD: return "preconditioner failed the SPD safety check";
+        case UNO_ERR_BREAKDOWN: return "CG breakdown (non-finite or non-positive scalar)";
+        case UNO_ERR_DEVICE: return "HIP runtime error";
+        case UNO_ERR_NOMEM: return "device allocation failed";
+    }
+    return "unknown status";
+}
+
+uno_status fe_apply(const uno_grid* grid, const uno_material* mat, const void* u, void* y, uno_dtype vec_t,
+                    void* stream)
+{
+    Grid g;
+    uno_status e = make_grid(grid, &g);
+    if (e != UNO_OK) return e;
+    if (!mat || !mat->kappa || !u || !y || u == y) return UNO_ERR_ARG;
+    if ((vec_t != UNO_F64 && vec_t != UNO_F32) || mat->dtype != vec_t) return UNO_ERR_ARG;
+    KTimer kt;
+    ktimer_begin(&kt, UNO_KT_MATVEC, S(stream));
+    e = launch_fe_apply(g, mat->kappa, u, y, vec_t, S(stream));
+    ktimer_end(&kt);
+    return e;
+}
+
+uno_status jac_precond_apply(const uno_grid* grid, const uno_material* mat, const void* r, void* s, uno_dtype vec_t,
+                             void* stream)
+{
+    Grid g;
+    uno_status e = make_grid(grid, &g);
+    if (e != UNO_OK) return e;
+    if (!mat || !mat->kappa || !r || !s) return UNO_ERR_ARG;
+    if ((vec_t != UNO_F64 && vec_t != UNO_F32) || mat->dtype != vec_t) return UNO_ERR_ARG;
+    return launch_jacobi(g, mat->kappa, r, s, vec_t, S(stream));
+}
+
+uno_status uno_macro_rhs(const uno_grid* grid, const uno_material* mat, const double* gbar, void* f, uno_dtype vec_t,
+                         void* stream)
+{
+    Grid g;
+    uno_status e = make_grid(grid, &g);
+    if (e != UNO_OK) return e;
+    if (!mat || !mat->kappa || !gbar || !f) return UNO_ERR_ARG;
+    double g3[3] = {0.0, 0.0, 0.0};
+    for (int b = 0; b < grid->dim; ++b) g3[3 - grid->dim + b] = gbar[b];
+    return launch_rhs(g, mat->kappa, mat->dtype, g3, f, vec_t, S(stream));
+}
+
+// ----------------------------------------------------------------------------
+// UNO table (host).  Mode k (original dimension d) of a half-spectrum entry.
+
+static int centred(int i, int n) { return (2 * i <= n) ? i : i - n; }
+
+// slot 1..k_max of k in K = [-M..M]^(d-1) x [0..M] \ {0} (lexicographic,
+// zero skipped), 0 when k is not a learned mode
+static int64_t uno_slot(int d, int M, const int* k)
+{
+    int64_t lin = 0, zero = 0;
+    bool nz = false;
+    for (int b = 0; b < d; ++b) {
+        const bool last = (b == d - 1);
+        const int lo = last ? 0 : -M;
+        if (k[b] < lo || k[b] > M) return 0;
+        const int span = last ? (M + 1) : (2 * M + 1);
+        lin = lin * span + (k[b] - lo);
+        zero = zero * span + (0 - lo);
+        if (k[b] != 0) nz = true;
+    }
+    if (!nz) return 0;
+    return lin < zero ? lin + 1 : lin;
+}
+
+static int64_t uno_nweights(int d, int M)
+{
+    int64_t w = M + 1;
+    for (int b = 0; b + 1 < d; ++b) w *= 2 * M + 1;
+    return w;
+}
+
+// Phi before symmetrization: W + theta_i^2 on K and on -K (conjugate set),
+// W elsewhere, 0 at the zero mode.
+static double uno_phi(int d, int M, const double* theta, const int* k)
+{
+    bool nz = false;
+    for (int b = 0; b < d; ++b) nz |= (k[b] != 0);
+    if (!nz) return 0.0;
+    const double W = theta[0] * theta[0];
+    int64_t s = uno_slot(d, M, k);
+    if (s == 0 && k[d - 1] < 0) {
+        int mk[3];
+        for (int b = 0; b < d; ++b) mk[b] = -k[b];
+        s = uno_slot(d, M, mk);
+    }
+    return s ? W + theta[s] * theta[s] : W;
+}
+
+// original-dimension mode of half-spectrum entry (ix, iy, ikz) of the embedded grid
+static void entry_mode(const Grid& g, int ix, int iy, int ikz, int* k)
+{
+    if (g.dim == 3) {
+        k[0] = centred(ix, g.n[0]);
+        k[1] = centred(iy, g.n[1]);
+        k[2] = ikz;
+    } else {
+        k[0] = centred(iy, g.n[1]);
+        k[1] = ikz;
+    }
+}
+
+static uno_status precond_finish(uno_precond* p, const std::vector<double>& phi, double eps_spd, uno_dtype table_t,
+                                 bool check)
+{
+    const Grid& g = p->grid;
+    const int64_t ns = p->plan.nspec;
+    if (check) {
+        for (int64_t l = 1; l < ns; ++l) {
+            // the zero mode is the only entry allowed below eps (it is 0)
+            if (!(phi[l] > eps_spd)) return UNO_ERR_NOT_SPD;
+        }
+    }
+    p->table_host = (double*)malloc(sizeof(double) * ns);
+    if (!p->table_host) return UNO_ERR_NOMEM;
+    memcpy(p->table_host, phi.data(), sizeof(double) * ns);
+    const double inv_n = 1.0 / (double)g.total;
+    p->table_t = table_t;
+    if (table_t == UNO_F64) {
+        std::vector<double> sc(ns);
+        for (int64_t l = 0; l < ns; ++l) sc[l] = phi[l] * inv_n;
+        if (hipMalloc(&p->table, sizeof(double) * ns) != hipSuccess) return UNO_ERR_NOMEM;
+        UNO_HIP(hipMemcpy(p->table, sc.data(), sizeof(double) * ns, hipMemcpyHostToDevice));
+    } else if (table_t == UNO_F32) {
+        std::vector<float> sc(ns);
+        for (int64_t l = 0; l < ns; ++l) sc[l] = (float)(phi[l] * inv_n);
+        if (hipMalloc(&p->table, sizeof(float) * ns) != hipSuccess) return UNO_ERR_NOMEM;
+        UNO_HIP(hipMemcpy(p->table, sc.data(), sizeof(float) * ns, hipMemcpyHostToDevice));
+    } else {
+        return UNO_ERR_ARG;
+    }
+    if (hipMalloc(&p->spec, sizeof(double2) * ns) != hipSuccess) return UNO_ERR_NOMEM;
+    return UNO_OK;
+}
+
+static void precond_free(uno_precond* p)
+{
+    if (!p) return;
+    fft_plan_destroy(&p->plan);
+    if (p->table) (void)hipFree(p->table);
+    if (p->spec) (void)hipFree(p->spec);
+    free(p->table_host);
+    delete p;
+}
+
+uno_status uno_precond_create(const uno_grid* grid, int32_t M, const double* theta, int64_t ntheta, double eps_spd,
+                              uno_dtype table_t, uno_precond** out)
+{
+    if (!out || !theta) return UNO_ERR_ARG;
+    *out = nullptr;
+    uno_precond* p = new uno_precond();
+    memset(p, 0, sizeof(*p));
+    uno_status e = make_grid(grid, &p->grid);
+    if (e != UNO_OK) { delete p; return e; }
+    const int d = grid->dim;
+    if (M < 0) { delete p; return UNO_ERR_ARG; }
+    for (int b = 0; b < d; ++b)
+        if (2 * M + 1 > grid->n[b]) { delete p; return UNO_ERR_SHAPE; }
+    if (ntheta != uno_nweights(d, M)) { delete p; return UNO_ERR_SHAPE; }
+    for (int64_t i = 0; i < ntheta; ++i)
+        if (!std::isfinite(theta[i])) { delete p; return UNO_ERR_ARG; }
+    e = fft_plan_create(p->grid, &p->plan);
+    if (e != UNO_OK) { precond_free(p); return e; }
+    p->M = M;
+    const Grid& g = p->grid;
+    const int nh = p->plan.nh;
+    std::vector<double> phi(p->plan.nspec);
+    for (int ix = 0; ix < g.n[0]; ++ix)
+        for (int iy = 0; iy < g.n[1]; ++iy)
+            for (int kz = 0; kz < nh; ++kz) {
+                int k[3], mk[3];
+                entry_mode(g, ix, iy, kz, k);
+                for (int b = 0; b < d; ++b) mk[b] = -k[b];
+                phi[((int64_t)ix * g.n[1] + iy) * nh + kz] =
+                    0.5 * (uno_phi(d, M, theta, k) + uno_phi(d, M, theta, mk));
+            }
+    e = precond_finish(p, phi, eps_spd, table_t, true);
+    if (e != UNO_OK) { precond_free(p); return e; }
+    UNO_HIP(hipGetDevice(&p->device));
+    *out = p;
+    return UNO_OK;
+}
+
+uno_status uno_precond_create_fans(const uno_grid* grid, double kappa_ref, uno_dtype table_t, uno_precond** out)
+{
+    if (!out || !(kappa_ref > 0.0)) return UNO_ERR_ARG;
+    *out = nullptr;
+    uno_precond* p = new uno_precond();
+    memset(p, 0, sizeof(*p));
+    uno_status e = make_grid(grid, &p->grid);
+    if (e != UNO_OK) { delete p; return e; }
+    e = fft_plan_create(p->grid, &p->plan);
+    if (e != UNO_OK) { precond_free(p); return e; }
+    const Grid& g = p->grid;
+    const int nh = p->plan.nh;
+    std::vector<double> phi(p->plan.nspec);
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int ix = 0; ix < g.n[0]; ++ix)
+        for (int iy = 0; iy < g.n[1]; ++iy)
+            for (int kz = 0; kz < nh; ++kz) {
+                const int kk[3] = {ix, iy, kz};
+                // symbol of the homogeneous unit-conductivity operator:
+                // sum over offsets of w(m) * (#voxels sharing both nodes) * cos(phase)
+                double lam = 0.0;
+                for (int a = -1; a <= 1; ++a)
+                    for (int b = -1; b <= 1; ++b)
+                        for (int c = -1; c <= 1; ++c) {
+                            const int dl[3] = {a, b, c};
+                            int m = 0, mult = 1;
+                            double ph = 0.0;
+                            for (int q = 0; q < 3; ++q) {
+                                if (dl[q] != 0) m |= 1 << (2 - q);
+                                else mult *= 2;
+                                ph += two_pi * (double)kk[q] * dl[q] / (double)g.n[q];
+                            }
+                            lam += g.dev.w[m] * mult * std::cos(ph);
+                        }
+                const int64_t l = ((int64_t)ix * g.n[1] + iy) * nh + kz;
+                phi[l] = (l == 0) ? 0.0 : 1.0 / (kappa_ref * lam);
+            }
+    e = precond_finish(p, phi, 0.0, table_t, false);
+    if (e != UNO_OK) { precond_free(p); return e; }
+    UNO_HIP(hipGetDevice(&p->device));
+    *out = p;
+    return UNO_OK;
+}
+
+uno_status uno_precond_apply(const uno_precond* p, const void* r, void* s, uno_dtype vec_t, void* stream)
+{
+    if (!p || !r || !s) return UNO_ERR_ARG;
+    if (vec_t != UNO_F64 && vec_t != UNO_F32) return UNO_ERR_ARG;
+    if (vec_t == UNO_F64 && p->table_t != UNO_F64) return UNO_ERR_ARG;
+    if (vec_t == UNO_F32 && p->table_t != UNO_F32) return UNO_ERR_ARG;
+    return uno_apply_passes(p->grid, p->plan, p->table, p->table_t, r, s, vec_t, p->spec, nullptr, nullptr, S(stream));
+}
+
+uno_status uno_precond_table(const uno_precond* p, double* out, int64_t nout)
+{
+    if (!p || !out || nout != p->plan.nspec) return UNO_ERR_ARG;
+    memcpy(out, p->table_host, sizeof(double) * nout);
+    return UNO_OK;
+}
+
+uno_status uno_precond_destroy(uno_precond* p)
+{
+    if (!p) return UNO_ERR_ARG;
+    precond_free(p);
+    return UNO_OK;
+}
+
+uno_status pcg_solve(const uno_grid* grid, const uno_material* mat, const double* macro_load, const double* rhs,
+                     double* u, const uno_solve_opts* opts, uno_solve_info* info, double* res_hist, void* stream)
+{
+    Grid g;
+    uno_status e = make_grid(grid, &g);
+    if (e != UNO_OK) return e;
+    if (!mat || !mat->kappa || !u || !opts) return UNO_ERR_ARG;
+    if (!macro_load && !rhs) return UNO_ERR_ARG;
+    if (!(opts->rtol >= 0.0) || opts->max_iter < 1) return UNO_ERR_ARG;
+    if (opts->kind < UNO_PREC_NONE || opts->kind > UNO_PREC_UNO) return UNO_ERR_ARG;
+    if (opts->kind == UNO_PREC_UNO) {
+        if (!opts->uno) return UNO_ERR_ARG;
+        const Grid& pg = opts->uno->grid;
+        if (pg.n[0] != g.n[0] || pg.n[1] != g.n[1] || pg.n[2] != g.n[2]) return UNO_ERR_SHAPE;
+    }
+    if (mat->dtype != UNO_F64) return UNO_ERR_ARG;
+    if (opts->op_t != UNO_F64 || opts->prec_t != UNO_F64) return UNO_ERR_ARG;
+    if (opts->kind == UNO_PREC_UNO && opts->uno->table_t != UNO_F64) return UNO_ERR_ARG;
+    double g3[3] = {0.0, 0.0, 0.0};
+    if (macro_load)
+        for (int b = 0; b < grid->dim; ++b) g3[3 - grid->dim + b] = macro_load[b];
+    return pcg_run(g, (const double*)mat->kappa, macro_load ? g3 : nullptr, rhs, u, opts, info, res_hist, S(stream));
+}
+
+uno_status effective_tensor(const uno_grid* grid, const uno_material* mat, int32_t nload, const double* loads,
+                            const double* u, double* out, void* stream)
+{
+    Grid g;
+    uno_status e = make_grid(grid, &g);
+    if (e != UNO_OK) return e;
+    const int d = grid->dim;
+    if (!mat || !mat->kappa || !loads || !u || !out || nload != d) return UNO_ERR_ARG;
+    if (mat->dtype != UNO_F64 && mat->dtype != UNO_F32) return UNO_ERR_ARG;
+    const int nb = (int)((g.total + kBlock - 1) / kBlock);
+    double* dpart = nullptr;
+    if (hipMalloc(&dpart, sizeof(double) * 3 * nb) != hipSuccess) return UNO_ERR_NOMEM;
+    std::vector<double> hpart(3 * (size_t)nb);
+    double Q[3][3] = {{0}};  // Q[i][j]: component i of load j
+    for (int j = 0; j < d; ++j) {
+        double g3[3] = {0.0, 0.0, 0.0};
+        for (int b = 0; b < d; ++b) g3[3 - d + b] = loads[j * d + b];
+        int nbo = 0;
+        e = launch_flux(g, mat->kappa, mat->dtype, g3, u + (int64_t)j * g.total, dpart, &nbo, S(stream));
+        if (e != UNO_OK) break;
+        if (hipMemcpyAsync(hpart.data(), dpart, sizeof(double) * 3 * nb, hipMemcpyDeviceToHost, S(stream)) !=
+                hipSuccess ||
+            hipStreamSynchronize(S(stream)) != hipSuccess) {
+            e = UNO_ERR_DEVICE;
+            break;
+        }
+        for (int c = 0; c < d; ++c) {
+            double acc = 0.0;
+            for (int b = 0; b < nb; ++b) acc += hpart[3 * (size_t)b + (3 - d + c)];
+            Q[c][j] = acc / (double)g.total;
+        }
+    }
+    (void)hipFree(dpart);
+    if (e != UNO_OK) return e;
+    // out = Q G^-1 with G[:, j] = g_j  (Gauss-Jordan on the tiny d x d system)
+    double G[3][6];
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) {
+            G[i][j] = loads[j * d + i];
+            G[i][d + j] = (i == j) ? 1.0 : 0.0;
+        }
+    for (int c = 0; c < d; ++c) {
+        int piv = c;
+        for (int i = c + 1; i < d; ++i)
+            if (std::fabs(G[i][c]) > std::fabs(G[piv][c])) piv = i;
+        if (!(std::fabs(G[piv][c]) > 0.0)) return UNO_ERR_ARG;
+        if (piv != c)
+            for (int j = 0; j < 2 * d; ++j) std::swap(G[c][j], G[piv][j]);
+        const double inv = 1.0 / G[c][c];
+        for (int j = 0; j < 2 * d; ++j) G[c][j] *= inv;
+        for (int i = 0; i < d; ++i) {
+            if (i == c) continue;
+            const double f = G[i][c];
+            for (int j = 0; j < 2 * d; ++j) G[i][j] -= f * G[c][j];
+        }
+    }
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) {
+            double acc = 0.0;
+            for (int k = 0; k < d; ++k) acc += Q[i][k] * G[k][d + j];
+            out[i * d + j] = acc;
+        }
+    return UNO_OK;
+}
+
+uno_status uno_timing_enable(int32_t which)
+{
+    std::lock_guard<std::mutex> lk(g_tmu);
+    for (auto& pr : g_tev) {
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
+    }
+    g_tev.clear();
+    g_twhich = which;
+    return UNO_OK;
+}
+
+uno_status uno_timing_read(double* total_ms, int64_t* launches)
+{
+    if (!total_ms || !launches) return UNO_ERR_ARG;
+    std::lock_guard<std::mutex> lk(g_tmu);
+    double tot = 0.0;
+    for (auto& pr : g_tev) {
+        UNO_HIP(hipEventSynchronize(pr.second));
+        float ms = 0.0f;
+        UNO_HIP(hipEventElapsedTime(&ms, pr.first, pr.second));
+        tot += ms;
+    }
+    *total_ms = tot;
+    *launches = (int64_t)g_tev.size();
+    return UNO_OK;
+}
+
+uno_status uno_shutdown(void) { return ws_release_all(); }
+
+}  // extern "C"

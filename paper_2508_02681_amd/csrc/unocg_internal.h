@@ -1,0 +1,154 @@
+// Internal declarations of the gfx950 UNO-CG library (not part of the ABI).
+//
+// Every grid is handled as a 3D periodic voxel grid n0 x n1 x n2 (last axis
+// contiguous).  A 2D problem n1 x n2 is embedded as 1 x n1 x n2 with a unit
+// voxel edge along the dummy axis: with one voxel layer the trilinear element
+// collapses onto the bilinear one (both node layers coincide), so operator,
+// rhs and fluxes are exactly the 2D ones.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <cstdio>
+#include <vector>
+
+#include "../../include/unocg.h"
+
+namespace unocg {
+
+constexpr int kBlock = 256;          // threads per workgroup of streaming kernels
+constexpr int kMaxFftStages = 16;
+
+// Grid descriptor passed to kernels by value.
+struct GridDev {
+    int n0, n1, n2;   // voxels = nodes per axis
+    int64_t n;        // n0 n1 n2
+    double w[8];      // stencil weight per offset pattern m = (m0<<2)|(m1<<1)|m2,
+                      // m_b = 1 iff the neighbour differs along axis b
+    double cdiag;     // diag A = cdiag * sum of the 8 voxel conductivities at a node
+    double hvol;      // voxel volume
+    double gcoef[3];  // element-centre gradient factor per axis: 1 / (4 h_b)
+};
+
+// Host view of a problem grid.
+struct Grid {
+    int dim;          // 2 or 3 as given by the caller
+    int n[3];         // embedded 3D sizes
+    double h[3];      // embedded voxel edges
+    int64_t total;
+    GridDev dev;
+};
+
+uno_status make_grid(const uno_grid* g, Grid* out);
+
+// complex helpers
+template <typename T> struct cplx_t;
+template <> struct cplx_t<double> { using type = double2; };
+template <> struct cplx_t<float> { using type = float2; };
+
+// Launch bookkeeping for the optional per-family kernel timing.
+struct KTimer {
+    int which;
+    hipStream_t stream;
+    bool active;
+    hipEvent_t a, b;
+};
+void ktimer_begin(KTimer* t, int which, hipStream_t s);
+void ktimer_end(KTimer* t);
+
+// Status of the last HIP error inside a launch helper
+uno_status hip_status(hipError_t e);
+
+#define UNO_HIP(call)                                   \
+    do {                                                \
+        hipError_t e_ = (call);                         \
+        if (e_ != hipSuccess) return hip_status(e_);    \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Stencil family (stencil.hip)
+uno_status launch_fe_apply(const Grid& g, const void* kappa, const void* u, void* y, uno_dtype t,
+                           hipStream_t s);
+uno_status launch_jacobi(const Grid& g, const void* kappa, const void* r, void* out, uno_dtype t,
+                         hipStream_t s);
+uno_status launch_rhs(const Grid& g, const void* kappa, uno_dtype kt, const double gbar[3], void* f,
+                      uno_dtype t, hipStream_t s);
+// per-block partial flux sums: out has 3 * nblocks doubles, returns nblocks
+uno_status launch_flux(const Grid& g, const void* kappa, uno_dtype kt, const double gbar[3],
+                       const double* u, double* partials, int* nblocks, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// FFT family (fft.hip)
+struct AxisPlan {
+    int n;
+    int nstages;
+    int radix[kMaxFftStages];
+    double2* tw64;    // exp(-2 pi i j / n), j < n
+    float2* tw32;
+};
+
+struct FftPlan {
+    AxisPlan ax[3];
+    int nh;           // n2 / 2 + 1
+    int64_t nspec;    // n0 n1 nh complex values
+};
+
+uno_status fft_plan_create(const Grid& g, FftPlan* p);
+void fft_plan_destroy(FftPlan* p);
+
+// Per-CG-iteration reduction target: when non-null the inverse pass adds
+// r.s partials and finalizes gamma in `state`.
+struct CgState;
+struct RsReduce {
+    const double* r;     // FP64 residual
+    double* partials;
+    CgState* state;
+};
+
+// s = (1/n) F^H diag(table) F r.  `spec` scratch holds nspec complex values of
+// the vector precision.  gate != nullptr: every pass returns at once when the
+// solver state says the iteration is finished.
+uno_status uno_apply_passes(const Grid& g, const FftPlan& p, const void* table, uno_dtype table_t,
+                            const void* r, void* s, uno_dtype vec_t, void* spec, const RsReduce* red,
+                            const CgState* gate, hipStream_t stream);
+
+// Forward transform of nbatch real fields into half spectra (training).
+uno_status fft_forward_real(const Grid& g, const FftPlan& p, const double* x, double2* spec,
+                            hipStream_t stream);
+
+// ---------------------------------------------------------------------------
+// CG (cg.hip)
+struct CgState {
+    double gamma0, gamma1;   // r.s of the previous and the current pass
+    double dp;               // d . A d
+    double rmax;             // ||r||_inf after the last update
+    double r0max;            // ||r_0||_inf
+    double tol_abs;          // rtol * r0max
+    double mean;             // scratch: mean of u at the end
+    double fmax, dmax;       // true-residual check
+    int iters;               // completed passes
+    int max_iter;
+    int status;              // 0 ok, 1 breakdown
+    int hist_len;            // capacity of the history buffer
+    unsigned counter;        // last-block arrival counter (always 0 between kernels)
+    unsigned pad;
+};
+
+__host__ __device__ inline bool cg_done(const CgState* st)
+{
+    return st->status != 0 || st->rmax <= st->tol_abs || st->iters >= st->max_iter;
+}
+
+}  // namespace unocg
+
+// uno_precond layout (opaque to callers)
+struct uno_precond {
+    unocg::Grid grid;
+    unocg::FftPlan plan;
+    int M;
+    uno_dtype table_t;
+    void* table;          // device half spectrum, scaled by 1/n, table_t
+    double* table_host;   // unscaled Phi on the half spectrum
+    void* spec;           // scratch spectrum (FP64 complex, nspec values)
+    int device;
+};

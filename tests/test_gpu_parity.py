@@ -1,0 +1,227 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs.  Tolerances: single FP64 applies <= 1e-12 relative to the
+largest output value; FP64 solves run to rtol 1e-12 on both sides agree to
+<= 1e-8; FP32 applies <= 1e-5."""
+import numpy as np
+import pytest
+import torch
+
+import synth_inputs as si
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+@pytest.fixture(scope="module")
+def uno():
+    import paper_2508_02681_amd as u
+    u.lib()
+    assert torch.cuda.is_available()
+    return u
+
+
+def T(a, dtype=torch.float64):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dtype, device=DEV)
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+SHAPES = [(8, 8), (33, 20), (5, 7), (12, 10, 8), (17, 9, 24), (3, 4, 5), (1, 6, 4), (40, 40, 40)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_fe_apply_f64(orc, uno, shape):
+    print("fe_apply f64", shape, flush=True)
+    kap = si.random_field(shape, 1, 0.1, 10.0)
+    u = si.random_field(shape, 2)
+    y = uno.fe_apply(T(kap), T(u)).cpu().numpy()
+    assert rel(y, orc.fe_apply(kap, u)) < 1e-12
+
+
+@pytest.mark.parametrize("shape", [(16, 16), (12, 10, 8)])
+def test_fe_apply_f32(orc, uno, shape):
+    kap = si.random_field(shape, 3, 0.1, 10.0)
+    u = si.random_field(shape, 4)
+    y = uno.fe_apply(T(kap, torch.float32), T(u, torch.float32)).cpu().numpy()
+    assert rel(y, orc.fe_apply(kap.astype(np.float32), u.astype(np.float32))) < 1e-5
+
+
+@pytest.mark.parametrize("shape", [(8, 8), (12, 10, 8), (1, 5, 3)])
+def test_jacobi_and_rhs_f64(orc, uno, shape):
+    kap = si.random_field(shape, 5, 0.1, 10.0)
+    r = si.random_field(shape, 6)
+    s = uno.jac_precond_apply(T(kap), T(r)).cpu().numpy()
+    assert rel(s, r / orc.jacobi_diag(kap)) < 1e-13
+    g = np.linspace(0.4, 1.3, len(shape))
+    f = uno.uno_macro_rhs(T(kap), g).cpu().numpy()
+    assert rel(f, orc.rhs(kap, g)) < 1e-13
+
+
+UNO_CASES = [((8, 8), 2), ((12, 10), 3), ((15, 9), 2), ((10, 12, 8), 2), ((9, 15, 10), 3), ((6, 6, 5), 1),
+             ((20, 18, 24), 4), ((48, 48, 48), 8)]
+
+
+@pytest.mark.parametrize("shape,M", UNO_CASES)
+def test_uno_apply_f64(orc, uno, shape, M):
+    print("uno apply", shape, M, flush=True)
+    th = si.random_theta(uno.num_weights(len(shape), M), 7)
+    r = si.random_field(shape, 8)
+    p = uno.UnoPrecond.create(shape, M, th)
+    s = p.apply(T(r)).cpu().numpy()
+    assert rel(s, orc.uno_apply(th, M, r)) < 1e-12
+    # half-spectrum table equals the oracle's full table on those modes
+    tab = orc.uno_table(shape, M, th)
+    half = tab[..., : shape[-1] // 2 + 1]
+    assert rel(p.table(), half) < 1e-14
+
+
+@pytest.mark.parametrize("shape", [(8, 8), (10, 6), (6, 8, 10)])
+def test_fans_apply_f64(orc, uno, shape):
+    r = si.random_field(shape, 9)
+    p = uno.UnoPrecond.fans(shape, 0.6)
+    s = p.apply(T(r)).cpu().numpy()
+    assert rel(s, orc.table_apply(orc.fans_table(0.6, shape), r)) < 1e-12
+
+
+def test_uno_apply_f32(orc, uno):
+    shape, M = (16, 12, 10), 3
+    th = si.random_theta(uno.num_weights(3, M), 10)
+    r = si.random_field(shape, 11)
+    p = uno.UnoPrecond.create(shape, M, th, table_dtype=torch.float32)
+    s = p.apply(T(r, torch.float32)).cpu().numpy()
+    assert rel(s, orc.uno_apply(th, M, r)) < 1e-5
+
+
+def _config1():
+    cfg = si.CONFIG_2D_32
+    return [si.microstructure(cfg, s)[0] for s in cfg["seeds"][:3]]
+
+
+@pytest.mark.parametrize("kind", ["jacobi", "none"])
+def test_pcg_2d_config1_matches_oracle(orc, uno, kind):
+    """2D 32x32, inclusions kappa 10 in matrix 1, 2 loads: solutions at rtol
+    1e-12 agree to 1e-8; iteration counts at rtol 1e-10 within +-1; kappa_bar
+    to 1e-8."""
+    for kap in _config1()[:2]:
+        loads = np.eye(2)
+        sols = []
+        for g in loads:
+            u, info = uno.pcg_solve(T(kap), macro_load=g, kind=kind, rtol=1e-12)
+            uo, ito, _, _ = orc.pcg(kap, orc.rhs(kap, g), kind, rtol=1e-12)
+            assert info["converged"] and info["true_rel_res"] < 1e-10
+            assert rel(u.cpu().numpy(), uo) < 1e-8
+            sols.append(u)
+            _, info10 = uno.pcg_solve(T(kap), macro_load=g, kind=kind, rtol=1e-10)
+            _, it10, _, _ = orc.pcg(kap, orc.rhs(kap, g), kind, rtol=1e-10)
+            assert abs(info10["iters"] - it10) <= 1
+        kb = uno.effective_tensor(T(kap), loads, torch.stack(sols))
+        kbo = orc.effective_tensor(kap, [s.cpu().numpy() for s in sols], list(loads))
+        assert rel(kb, kbo) < 1e-8
+
+
+@pytest.mark.parametrize("shape,M", [((32, 32), 4), ((16, 16, 16), 3), ((12, 10, 14), 2)])
+def test_pcg_uno_matches_oracle(orc, uno, shape, M):
+    ph, _ = si.rsa_inclusions(shape, 2, 4, 0.3, 21)
+    kap = si.two_phase_kappa(ph, 1.0, 100.0)
+    th = si.random_theta(uno.num_weights(len(shape), M), 5, scale=0.05)
+    p = uno.UnoPrecond.create(shape, M, th)
+    tab = orc.uno_table(shape, M, th)
+    g = np.zeros(len(shape))
+    g[0] = 1.0
+    f = orc.rhs(kap, g)
+    u, info, hist = uno.pcg_solve(T(kap), macro_load=g, kind="uno", precond=p, rtol=1e-12, history=True)
+    uo, ito, ho, _ = orc.pcg(kap, f, "uno", table=tab, rtol=1e-12)
+    assert info["converged"]
+    assert rel(u.cpu().numpy(), uo) < 1e-8
+    # a random theta makes a poor preconditioner (hundreds of passes); late
+    # passes amplify the different rounding of the two implementations
+    assert abs(info["iters"] - ito) <= max(1, int(0.01 * ito))
+    n = min(len(hist), len(ho), 10)
+    assert rel(hist[:n], ho[:n]) < 1e-8
+
+
+def test_pcg_3d_jacobi_history_matches(orc, uno):
+    shape = (12, 12, 12)
+    ph, _ = si.rsa_inclusions(shape, 2, 3, 0.25, 3)
+    kap = si.two_phase_kappa(ph, 1.0, 100.0)
+    g = np.array([0.0, 1.0, 0.0])
+    u, info, hist = uno.pcg_solve(T(kap), macro_load=g, kind="jacobi", rtol=1e-10, history=True)
+    uo, ito, ho, _ = orc.pcg(kap, orc.rhs(kap, g), "jacobi", rtol=1e-10)
+    assert abs(info["iters"] - ito) <= 1
+    n = min(len(hist), len(ho)) - 1
+    assert rel(hist[:n], ho[:n]) < 1e-6  # late residuals amplify rounding differences
+    assert rel(u.cpu().numpy(), uo) < 1e-8
+
+
+def test_train_features_and_fit_match_oracle(orc, uno):
+    shape, M = (16, 16), 3
+    fs, us = [], []
+    for s in (1, 2, 3):
+        ph, _ = si.rsa_inclusions(shape, 1.5, 2.5, 0.3, s)
+        kap = si.two_phase_kappa(ph, 1.0, 10.0)
+        for g in np.eye(2):
+            f = orc.rhs(kap, g)
+            u, _, _, _ = orc.pcg(kap, f, "jacobi", rtol=1e-12)
+            fs.append(f)
+            us.append(u)
+    a_o, b_o, _ = orc.train_features(fs, us)
+    th_o = orc.train_closed_form(M, a_o, b_o)
+    hs = uno.half_shape(shape)
+    A = torch.zeros(hs, dtype=torch.float64, device=DEV)
+    B = torch.zeros(hs, dtype=torch.float64, device=DEV)
+    uno.uno_train_accumulate(T(np.stack(fs)), T(np.stack(us)), A, B, len(fs))
+    assert rel(A.cpu().numpy(), a_o[..., : hs[-1]]) < 1e-12
+    assert rel(B.cpu().numpy(), b_o[..., : hs[-1]]) < 1e-10
+    th = uno.uno_train_fit(shape, M, A, B)
+    assert rel(th, th_o) < 1e-8
+
+
+# ---- edge cases and failure handling --------------------------------------
+
+def test_homogeneous_zero_rhs_returns_immediately(uno):
+    kap = np.full((8, 8, 8), 2.0)
+    u, info = uno.pcg_solve(T(kap), macro_load=[1.0, 0.0, 0.0], kind="jacobi", rtol=1e-6, max_iter=50)
+    assert np.abs(u.cpu().numpy()).max() < 1e-12
+
+
+def test_max_iter_reports_not_converged(uno):
+    kap = si.random_field((16, 16), 1, 0.1, 10.0)
+    u, info = uno.pcg_solve(T(kap), macro_load=[1.0, 0.0], kind="jacobi", rtol=1e-12, max_iter=3)
+    assert info["iters"] == 3 and not info["converged"]
+
+
+def test_nan_kappa_is_breakdown(uno):
+    kap = si.random_field((8, 8), 1, 0.5, 1.5)
+    kap[3, 3] = np.nan
+    with pytest.raises(uno.UnoError) as ei:
+        uno.pcg_solve(T(kap), macro_load=[1.0, 0.0], kind="jacobi", rtol=1e-6, max_iter=20)
+    assert ei.value.status == -4
+
+
+def test_spd_check_and_shape_errors(uno):
+    th = np.zeros(uno.num_weights(2, 2))
+    with pytest.raises(uno.UnoError) as ei:
+        uno.UnoPrecond.create((8, 8), 2, th, eps_spd=1e-12)
+    assert ei.value.status == -3
+    with pytest.raises(uno.UnoError) as ei:
+        uno.UnoPrecond.create((8, 8), 4, np.ones(uno.num_weights(2, 4)))
+    assert ei.value.status == -2
+    with pytest.raises(uno.UnoError) as ei:
+        uno.UnoPrecond.create((14, 8), 1, np.ones(uno.num_weights(2, 1)))  # 14 = 2 * 7: no radix 7
+    assert ei.value.status == -2
+
+
+def test_solve_is_deterministic(uno):
+    shape = (24, 20, 16)
+    kap = si.random_field(shape, 4, 0.1, 10.0)
+    th = si.random_theta(uno.num_weights(3, 3), 2, scale=0.02)
+    p = uno.UnoPrecond.create(shape, 3, th)
+    a, ia = uno.pcg_solve(T(kap), macro_load=[1.0, 0.5, 0.0], kind="uno", precond=p, rtol=1e-8)
+    b, ib = uno.pcg_solve(T(kap), macro_load=[1.0, 0.5, 0.0], kind="uno", precond=p, rtol=1e-8)
+    assert ia["iters"] == ib["iters"]
+    assert torch.equal(a, b)
