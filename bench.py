@@ -1,0 +1,249 @@
+#!/usr/bin/env python3
+"""Benchmark: UNO-CG vs Jacobi-CG on 3D 64^3 periodic thermal RVEs, one GPU.
+
+Workload: trilinear hex8 FE on a 64^3 periodic voxel grid, two phases
+(non-overlapping random spheres, radius 4-8 voxels, volume fraction 0.25,
+conductivity 100 in a matrix of conductivity 1), three unit macroscopic
+gradient load cases per microstructure, relative residual 1e-6 in the
+infinity norm.  Synthetic seeded microstructures stand in for the paper's
+voxel datasets.
+
+One step = the whole hot path over one microstructure: for each of the 3
+loads, rhs + UNO-CG solve (operator apply, UNO preconditioner apply, CG
+recurrences) to 1e-6, then the effective 3x3 conductivity.  Inputs are
+resident in device memory before the timed region.  The UNO weights are
+trained beforehand (untimed) on solver-generated pairs: seeded random
+weights -> UNO-CG solves of training microstructures -> closed-form fit
+-> more solves -> refit.
+
+Prints one JSON line; `value` is UNO-CG FP64 DOF*iterations/s.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+SHAPE = (64, 64, 64)
+LOADS = np.eye(3)
+RTOL = 1e-6
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=16)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--train-seeds", type=int, default=16)
+    ap.add_argument("--M", type=int, default=0, help="mode parameter (0 = pick from a small sweep)")
+    ap.add_argument("--jac-steps", type=int, default=4)
+    ap.add_argument("--cpu-iters", type=int, default=20, help="oracle UNO-CG passes timed for cpu_baseline")
+    ap.add_argument("--no-cpu", action="store_true")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build runs every solve on a single MI355X "
+              "(multi-GPU sharding is design-only); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2508_02681_amd as uno
+    import synth_inputs as si
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    uno.lib()
+    cfg = dict(si.CONFIG_3D_64)
+    n_dof = int(np.prod(SHAPE))
+
+    # ---------------- inputs (untimed) ----------------
+    t0 = time.time()
+    test_seeds = cfg["test_seeds"]
+    kap_test = [torch.tensor(si.microstructure(cfg, s)[0], device=dev) for s in test_seeds]
+    train_seeds = cfg["train_seeds"][: args.train_seeds]
+    kap_train = [torch.tensor(si.microstructure(cfg, s)[0], device=dev) for s in train_seeds]
+    log("inputs: %d test + %d train microstructures in %.1fs" % (len(kap_test), len(kap_train), time.time() - t0))
+
+    # ---------------- training (untimed) ----------------
+    t0 = time.time()
+    hs = uno.half_shape(SHAPE)
+
+    def solve_pairs(kaps, precond, kind):
+        F, U, its = [], [], []
+        for k in kaps:
+            for g in LOADS:
+                u, info = uno.pcg_solve(k, macro_load=g, kind=kind, precond=precond, rtol=1e-10, max_iter=20000)
+                F.append(uno.uno_macro_rhs(k, g))
+                U.append(u)
+                its.append(info["iters"])
+        return F, U, its
+
+    def fit(F, U, M):
+        A = torch.zeros(hs, dtype=torch.float64, device=dev)
+        B = torch.zeros(hs, dtype=torch.float64, device=dev)
+        uno.uno_train_accumulate(torch.stack(F), torch.stack(U), A, B, len(F))
+        return uno.uno_train_fit(SHAPE, M, A, B)
+
+    # seeded random start: theta0^2 near the inverse Jacobi scale of the matrix phase
+    M0 = 8
+    h = 1.0 / SHAPE[0]
+    scale = math.sqrt(1.0 / (8.0 * h / 3.0 * 8.0 * cfg["k_matrix"]))
+    theta0 = si.random_theta(uno.num_weights(3, M0), 12345, scale=scale, spread=0.1)
+    p0 = uno.UnoPrecond.create(SHAPE, M0, theta0)
+    nboot = max(1, len(kap_train) // 4)
+    F, U, its0 = solve_pairs(kap_train[:nboot], p0, "uno")
+    theta1 = fit(F, U, M0)
+    p1 = uno.UnoPrecond.create(SHAPE, M0, theta1)
+    F2, U2, its1 = solve_pairs(kap_train[nboot:], p1, "uno")
+    F += F2
+    U += U2
+    log("training pairs: %d (random-theta UNO-CG mean %.0f passes, refit UNO-CG mean %.0f)" %
+        (len(F), np.mean(its0), np.mean(its1) if its1 else float("nan")))
+    # mode parameter: sweep on a validation microstructure (a training one)
+    Ms = [args.M] if args.M > 0 else [4, 8, 12, 16, 24]
+    best = None
+    for M in Ms:
+        th = fit(F, U, M)
+        p = uno.UnoPrecond.create(SHAPE, M, th)
+        it = 0
+        for g in LOADS:
+            _, info = uno.pcg_solve(kap_train[0], macro_load=g, kind="uno", precond=p, rtol=RTOL)
+            it += info["iters"]
+        log("  M=%d: %d passes on validation" % (M, it))
+        if best is None or it < best[0]:
+            best = (it, M, th, p)
+    _, M, theta, prec = best
+    train_s = time.time() - t0
+    log("trained M=%d in %.1fs" % (M, train_s))
+
+    sols = torch.zeros((3,) + SHAPE, dtype=torch.float64, device=dev)
+
+    def step(i, kind, precond):
+        k = kap_test[i % len(kap_test)]
+        sols.zero_()
+        its = []
+        for j, g in enumerate(LOADS):
+            _, info = uno.pcg_solve(k, macro_load=g, u=sols[j], kind=kind, precond=precond, rtol=RTOL,
+                                    max_iter=50000)
+            if not info["converged"]:
+                raise RuntimeError("solve did not converge: %s" % info)
+            its.append(info["iters"])
+        kb = uno.effective_tensor(k, LOADS, sols)
+        return its, kb
+
+    def timed(kind, precond, steps, warmup):
+        for i in range(warmup):
+            step(i, kind, precond)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        all_its, kbs = [], []
+        for i in range(steps):
+            its, kb = step(i, kind, precond)
+            all_its += its
+            kbs.append(kb)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, all_its, kbs
+
+    # ---------------- timed: UNO-CG FP64 (headline) ----------------
+    dt, its, kbs = timed("uno", prec, args.steps, args.warmup)
+    ms_step = dt / args.steps * 1e3
+    value = n_dof * sum(its) / dt
+    uno_t_solve = dt / len(its) * 1e3
+    log("UNO-CG: %.2f ms/step, %.1f passes/solve, %.3e DOF*it/s, %.3f ms per solve" %
+        (ms_step, np.mean(its), value, uno_t_solve))
+    # ---------------- Jacobi-CG on the same microstructures ----------------
+    dtj, itsj, _ = timed("jacobi", None, args.jac_steps, 1)
+    jac_t_solve = dtj / len(itsj) * 1e3
+    jac_rate = n_dof * sum(itsj) / dtj
+    log("Jac-CG: %.1f passes/solve, %.3e DOF*it/s, %.3f ms per solve" % (np.mean(itsj), jac_rate, jac_t_solve))
+
+    # ---------------- dominant kernel: live HIP-event timing ----------------
+    fams = {uno.KT_MATVEC: "k_cg_matvec", uno.KT_UPDATE: "k_cg_update", uno.KT_FFT_FWD: "k_fft_r2c_z",
+            uno.KT_FFT_MID: "k_fft_strided(mid)", uno.KT_FFT_INV: "k_fft_c2r_z"}
+    fam_ms = {}
+    for fam in fams:
+        uno.timing_enable(fam)
+        step(0, "uno", prec)
+        torch.cuda.synchronize()
+        tot, nl = uno.timing_read()
+        uno.timing_enable(uno.KT_NONE)
+        fam_ms[fam] = (tot, nl)
+    dom = max(fam_ms, key=lambda f: fam_ms[f][0])
+    # algorithmic bytes per launch (FP64, 64^3): the minimum each kernel must move
+    nspec = SHAPE[0] * SHAPE[1] * (SHAPE[2] // 2 + 1)
+    bytes_per = {
+        uno.KT_MATVEC: n_dof * 8 * 5,        # read s, d_old, kappa; write d_new, p
+        uno.KT_UPDATE: n_dof * 8 * 6,        # read r, p, u, d; write r, u
+        uno.KT_FFT_FWD: n_dof * 8 + nspec * 16,     # read r; write half spectrum
+        uno.KT_FFT_MID: nspec * 16 * 2 + nspec * 8,  # spectrum in/out + table
+        uno.KT_FFT_INV: nspec * 16 + n_dof * 8 * 2,  # spectrum in; write s; read r (r.s)
+    }
+    tot, nl = fam_ms[dom]
+    avg_s = tot / max(nl, 1) / 1e3
+    achieved = bytes_per[dom] / avg_s / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": fams[dom], "avg_us": round(avg_s * 1e6, 2), "bytes_per_launch": bytes_per[dom],
+                "per_family_us": {fams[f]: round(fam_ms[f][0] / max(fam_ms[f][1], 1) * 1e3, 2) for f in fams}}
+
+    # ---------------- CPU baseline: the oracle, bounded sample ----------------
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        kap0 = kap_test[0].cpu().numpy()
+        tab = oracle.uno_table(SHAPE, M, theta)
+        f = oracle.rhs(kap0, LOADS[0])
+        t = time.perf_counter()
+        _, it_cpu, _, _ = oracle.pcg(kap0, f, "uno", table=tab, rtol=RTOL, max_iter=args.cpu_iters)
+        dtc = time.perf_counter() - t
+        cpu = {"value": n_dof * it_cpu / dtc, "unit": "DOF*iters/s", "cores": 1, "kind": "oracle",
+               "sample": "oracle UNO-CG (FP64, single thread) on test microstructure 1000, load e1, "
+                         "first %d passes of the same solve (%.1f s)" % (it_cpu, dtc)}
+
+    out = {
+        "metric": "DOF*iters/s (UNO-CG FP64, 3D 64^3, contrast 100, rel. residual 1e-6)",
+        "value": value,
+        "unit": "DOF*iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "3D thermal 64^3 periodic hex8, spheres r 4-8 vf 0.25, kappa 1/100, "
+                               "3 loads per step, UNO-CG to 1e-6 + effective tensor",
+                   "grid": list(SHAPE), "loads_per_step": 3, "M": M, "train_pairs": len(F),
+                   "microstructures": len(kap_test)},
+        "uno_cg": {"passes_mean": float(np.mean(its)), "ms_per_solve": uno_t_solve, "dof_iters_per_s": value},
+        "jac_cg": {"passes_mean": float(np.mean(itsj)), "ms_per_solve": jac_t_solve, "dof_iters_per_s": jac_rate},
+        "time_to_tol_speedup_uno_vs_jac": jac_t_solve / uno_t_solve,
+        "kappa_bar_first": np.round(kbs[0], 6).tolist(),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

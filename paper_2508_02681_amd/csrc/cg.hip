@@ -1,28 +1,31 @@
 // Preconditioned conjugate gradients (Algorithm 1; Algorithm 2 with the UNO
 // preconditioner) with every scalar kept on the device.
 //
-// One pass of the while loop is a short fixed sequence of kernels:
-//   [preconditioner passes (UNO) ->] matvec -> update
-// matvec : beta = gamma1 / gamma0 (0 on the first pass), d <- s + beta d,
-//          p <- A d, and d.p;
-// update : alpha = gamma1 / (d.p), r <- r - alpha p, u <- u + alpha d,
-//          ||r||_inf, and for Jacobi / no preconditioner also s <- P r and
-//          r.s of the next pass.
-// Each kernel first reads the solver state and returns at once when the loop
-// has ended (converged, max_iter reached, or breakdown), so the host can
-// enqueue passes ahead of the convergence decision and only reads the state
-// every few passes.  Reductions are FP64 and combined in a fixed order by
-// the last workgroup to finish, which also updates the state.
-//
-// The search direction is double-buffered (d_old read at the halo, d_new
-// written), so the direction update is fused into the operator apply.
+// One pass k of the while loop is a short fixed sequence of kernels:
+//   [UNO passes (the first one tests convergence) ->] matvec -> update
+// matvec : gamma_k = r.s (combined from partials), beta = gamma_k /
+//          gamma_{k-1} (0 on the first pass), d <- s + beta d, p <- A d,
+//          partials of d.p;
+// update : alpha = gamma_k / (d.p), r <- r - alpha p, u <- u + alpha d,
+//          partials of ||r||_inf, and for Jacobi / no preconditioner also
+//          s <- P r and partials of r.s for the next pass.
+// The host enqueues passes without waiting; every kernel returns at once when
+// the loop has ended (converged or breakdown), so the host reads the state
+// only between chunks of passes.  Reductions are FP64, written as one partial
+// per workgroup and combined in a fixed order by the kernels that need them.
+// The search direction is double-buffered (d_old read around the node,
+// d_new written), which fuses the direction update into the operator apply.
+#include <climits>
 #include <cmath>
 #include <cstring>
 
 #include "unocg_internal.h"
 #include "reduce.h"
+#include "cg_ctl.h"
 
 namespace unocg {
+
+int fft_c2r_blocks(const Grid& g, const FftPlan& p);
 
 __device__ __forceinline__ int wrap_i(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
@@ -41,96 +44,94 @@ __device__ __forceinline__ void voxel_kappa(const GridDev& g, const T* __restric
             }
 }
 
-// Initial state: ||r0||_inf, and for Jacobi / none s0 = P r0 and r0.s0.
-// MODE 0: none (s aliases r), 1: Jacobi, 2: UNO (only the norm).
+template <typename T>
+__device__ __forceinline__ double diag_at(const GridDev& g, const T* __restrict__ kappa, int64_t i)
+{
+    int z = (int)(i % g.n2);
+    int64_t t = i / g.n2;
+    int y = (int)(t % g.n1), x = (int)(t / g.n1);
+    T k[2][2][2];
+    voxel_kappa(g, kappa, x, y, z, k);
+    double ks = 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) ks += (double)k[q >> 2][(q >> 1) & 1][q & 1];
+    return g.cdiag * ks;
+}
+
+// Initial partials: ||r_0||_inf and, for Jacobi / none, s_0 = P r_0 and r_0.s_0.
+// MODE 0: none (s is r), 1: Jacobi, 2: UNO (only the norm).
 template <int MODE>
-__global__ void __launch_bounds__(kBlock) k_cg_init(GridDev g, const double* __restrict__ kappa, const double* __restrict__ r,
-                                                    double* __restrict__ s, double* __restrict__ part_max,
-                                                    double* __restrict__ part_dot, CgState* state, double rtol,
-                                                    int max_iter, double* hist, int hist_len)
+__global__ void __launch_bounds__(kBlock) k_cg_init(GridDev g, const double* __restrict__ kappa,
+                                                    const double* __restrict__ r, double* __restrict__ s,
+                                                    double* __restrict__ part_rmax, double* __restrict__ part_rs,
+                                                    CgState* st)
 {
     __shared__ double slots[kBlock / 64];
-    __shared__ int lastflag;
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double m = 0.0, dt = 0.0;
-    if (i < g.n) {
-        double ri = r[i];
-        m = fabs(ri);
-        if (MODE == 0) dt = ri * ri;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double ri = r[i];
+        m = OpMax::apply(m, fabs(ri));
+        if (MODE == 0) dt += ri * ri;
         if (MODE == 1) {
-            int z = (int)(i % g.n2);
-            int64_t t = i / g.n2;
-            int y = (int)(t % g.n1), x = (int)(t / g.n1);
-            double k[2][2][2];
-            voxel_kappa(g, kappa, x, y, z, k);
-            double ks = 0.0;
-#pragma unroll
-            for (int q = 0; q < 8; ++q) ks += k[q >> 2][(q >> 1) & 1][q & 1];
-            double si = ri / (g.cdiag * ks);
+            const double si = ri / diag_at(g, kappa, i);
             s[i] = si;
-            dt = ri * si;
+            dt += ri * si;
         }
     }
-    double bm = block_reduce<OpMax>(m, slots);
-    double bd = block_reduce<OpSum>(dt, slots);
+    const double bm = block_reduce<OpMax>(m, slots);
+    const double bd = block_reduce<OpSum>(dt, slots);
     if (threadIdx.x == 0) {
-        part_max[blockIdx.x] = bm;
-        part_dot[blockIdx.x] = bd;
-    }
-    if (arrive_last(&state->counter, &lastflag)) {
-        double r0 = combine_partials<OpMax>(part_max, gridDim.x, slots);
-        double gsum = combine_partials<OpSum>(part_dot, gridDim.x, slots);
-        if (threadIdx.x == 0) {
-            state->r0max = r0;
-            state->rmax = r0;
-            state->tol_abs = rtol * r0;
-            state->iters = 0;
-            state->max_iter = max_iter;
-            state->status = (r0 == r0) ? 0 : 1;
-            state->hist_len = hist_len;
-            state->dp = 0.0;
-            if (MODE == 2) {
-                state->gamma0 = 1.0;
-                state->gamma1 = 1.0;
-            } else {
-                state->gamma0 = 1.0;
-                state->gamma1 = gsum;
-                if (r0 > state->tol_abs && (!(gsum > 0.0) || !isfinite(gsum))) state->status = 1;
-            }
-            if (hist && hist_len > 0) hist[0] = r0;
-            state->counter = 0;
+        part_rmax[blockIdx.x] = bm;
+        part_rs[blockIdx.x] = bd;
+        if (blockIdx.x == 0) {
+            st->done = INT_MAX;
+            st->status = 0;
+            st->fail_iter = -1;
+            st->k_last = -1;
         }
     }
 }
 
-// d_new = s + beta d_old, p = A d_new, d_new . p   (one node per thread)
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_cg_matvec(GridDev g, const T* __restrict__ kappa, const T* __restrict__ s,
-                                                      const T* __restrict__ dold, T* __restrict__ dnew,
-                                                      T* __restrict__ p, double* __restrict__ part, CgState* state)
+// matvec of pass k (see file comment).  HEAD: also the convergence test.
+template <typename T, bool HEAD>
+__global__ void __launch_bounds__(kBlock) k_cg_matvec(GridDev g, const T* __restrict__ kappa,
+                                                      const T* __restrict__ s, const T* __restrict__ dold,
+                                                      T* __restrict__ dnew, T* __restrict__ p,
+                                                      double* __restrict__ part_dp, CgIter it,
+                                                      const double* __restrict__ part_rs, int np_rs, double* gam)
 {
     __shared__ double slots[kBlock / 64];
-    __shared__ int lastflag;
-    if (cg_done(state)) return;
-    const bool first = state->iters == 0;
-    const T beta = first ? (T)0 : (T)(state->gamma1 / state->gamma0);
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (HEAD) {
+        if (head_check(it, slots)) return;
+    } else if (loop_ended(it.st, it.k)) {
+        return;
+    }
+    const int k = it.k;
+    const double gk = reduce_parts<OpSum>(part_rs, np_rs, slots);
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    if (lead) gam[k] = gk;
+    if (!(gk > 0.0) || !isfinite(gk)) {
+        if (lead) { it.st->status = 1; it.st->fail_iter = k; }
+        return;
+    }
+    const bool first = (k == 0);
+    const T beta = first ? (T)0 : (T)(gk / gam[k - 1]);
     double dot = 0.0;
-    if (i < g.n) {
-        int z = (int)(i % g.n2);
-        int64_t t = i / g.n2;
-        int y = (int)(t % g.n1), x = (int)(t / g.n1);
-        T k[2][2][2];
-        voxel_kappa(g, kappa, x, y, z, k);
-        // compatible-voxel sums per offset
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int z = (int)(i % g.n2);
+        const int64_t t = i / g.n2;
+        const int y = (int)(t % g.n1), x = (int)(t / g.n1);
+        T kv[2][2][2];
+        voxel_kappa(g, kappa, x, y, z, kv);
+        // conductivity sums of the voxels shared by the node and each neighbour
         T A[2][2][3], B[2][3][3], K3[3][3][3];
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
             for (int b = 0; b < 2; ++b) {
-                A[a][b][0] = k[a][b][0];
-                A[a][b][1] = k[a][b][0] + k[a][b][1];
-                A[a][b][2] = k[a][b][1];
+                A[a][b][0] = kv[a][b][0];
+                A[a][b][1] = kv[a][b][0] + kv[a][b][1];
+                A[a][b][2] = kv[a][b][1];
             }
 #pragma unroll
         for (int a = 0; a < 2; ++a)
@@ -151,17 +152,17 @@ __global__ void __launch_bounds__(kBlock) k_cg_matvec(GridDev g, const T* __rest
         T acc = 0, dself = 0;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            int xx = wrap_i(x + a - 1, g.n0);
+            const int xx = wrap_i(x + a - 1, g.n0);
 #pragma unroll
             for (int b = 0; b < 3; ++b) {
-                int yy = wrap_i(y + b - 1, g.n1);
-                int64_t row = ((int64_t)xx * g.n1 + yy) * g.n2;
+                const int yy = wrap_i(y + b - 1, g.n1);
+                const int64_t row = ((int64_t)xx * g.n1 + yy) * g.n2;
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    int zz = wrap_i(z + c - 1, g.n2);
+                    const int zz = wrap_i(z + c - 1, g.n2);
                     T dv = s[row + zz];
                     if (!first) dv += beta * dold[row + zz];
-                    int m = ((a != 1) << 2) | ((b != 1) << 1) | (c != 1);
+                    const int m = ((a != 1) << 2) | ((b != 1) << 1) | (c != 1);
                     acc += (T)g.w[m] * K3[a][b][c] * dv;
                     if (a == 1 && b == 1 && c == 1) dself = dv;
                 }
@@ -169,140 +170,117 @@ __global__ void __launch_bounds__(kBlock) k_cg_matvec(GridDev g, const T* __rest
         }
         dnew[i] = dself;
         p[i] = acc;
-        dot = (double)dself * (double)acc;
+        dot += (double)dself * (double)acc;
     }
-    double bd = block_reduce<OpSum>(dot, slots);
-    if (threadIdx.x == 0) part[blockIdx.x] = bd;
-    if (arrive_last(&state->counter, &lastflag)) {
-        double v = combine_partials<OpSum>(part, gridDim.x, slots);
-        if (threadIdx.x == 0) {
-            state->dp = v;
-            if (!(v > 0.0) || !isfinite(v)) state->status = 1;
-            state->counter = 0;
-        }
-    }
+    const double bd = block_reduce<OpSum>(dot, slots);
+    if (threadIdx.x == 0) part_dp[blockIdx.x] = bd;
 }
 
-// r -= alpha p; u += alpha d; ||r||_inf; MODE 0/1 also s = P r and r.s.
+// update of pass k.  MODE 0: none, 1: Jacobi (both also form s and r.s for
+// pass k + 1), 2: UNO.
 template <typename T, int MODE>
 __global__ void __launch_bounds__(kBlock) k_cg_update(GridDev g, const T* __restrict__ kappa, double* __restrict__ r,
                                                       double* __restrict__ u, const T* __restrict__ d,
-                                                      const T* __restrict__ p, T* __restrict__ s,
-                                                      double* __restrict__ part_max, double* __restrict__ part_dot,
-                                                      CgState* state, double* hist)
+                                                      const T* __restrict__ p, T* __restrict__ s, CgIter it,
+                                                      const double* __restrict__ part_dp, int np_dp,
+                                                      const double* __restrict__ gam, double* __restrict__ part_rmax,
+                                                      double* __restrict__ part_rs_next)
 {
     __shared__ double slots[kBlock / 64];
-    __shared__ int lastflag;
-    if (cg_done(state)) return;
-    const double alpha = state->gamma1 / state->dp;
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (loop_ended(it.st, it.k)) return;
+    const double dp = reduce_parts<OpSum>(part_dp, np_dp, slots);
+    if (!(dp > 0.0) || !isfinite(dp)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) { it.st->status = 1; it.st->fail_iter = it.k; }
+        return;
+    }
+    const double alpha = gam[it.k] / dp;
     double m = 0.0, dt = 0.0;
-    if (i < g.n) {
-        double ri = r[i] - alpha * (double)p[i];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double ri = r[i] - alpha * (double)p[i];
         r[i] = ri;
         u[i] += alpha * (double)d[i];
-        m = fabs(ri);
-        if (MODE == 0) dt = ri * ri;
+        m = OpMax::apply(m, fabs(ri));
+        if (MODE == 0) dt += ri * ri;
         if (MODE == 1) {
-            int z = (int)(i % g.n2);
-            int64_t t = i / g.n2;
-            int y = (int)(t % g.n1), x = (int)(t / g.n1);
-            T k[2][2][2];
-            voxel_kappa(g, kappa, x, y, z, k);
-            double ks = 0.0;
-#pragma unroll
-            for (int q = 0; q < 8; ++q) ks += (double)k[q >> 2][(q >> 1) & 1][q & 1];
-            T si = (T)(ri / (g.cdiag * ks));
+            const T si = (T)(ri / diag_at(g, kappa, i));
             s[i] = si;
-            dt = ri * (double)si;
+            dt += ri * (double)si;
         }
-        if (MODE == 3) s[i] = (T)ri;  // low-precision copy of r for the preconditioner
     }
-    double bm = block_reduce<OpMax>(m, slots);
-    double bd = (MODE <= 1) ? block_reduce<OpSum>(dt, slots) : 0.0;
+    const double bm = block_reduce<OpMax>(m, slots);
+    const double bd = (MODE <= 1) ? block_reduce<OpSum>(dt, slots) : 0.0;
     if (threadIdx.x == 0) {
-        part_max[blockIdx.x] = bm;
-        if (MODE <= 1) part_dot[blockIdx.x] = bd;
-    }
-    if (arrive_last(&state->counter, &lastflag)) {
-        double rm = combine_partials<OpMax>(part_max, gridDim.x, slots);
-        double gs = (MODE <= 1) ? combine_partials<OpSum>(part_dot, gridDim.x, slots) : 0.0;
-        if (threadIdx.x == 0) {
-            state->rmax = rm;
-            int it = state->iters + 1;
-            state->iters = it;
-            if (hist && it < state->hist_len) hist[it] = rm;
-            if (!(rm == rm)) state->status = 1;
-            if (MODE <= 1) {
-                state->gamma0 = state->gamma1;
-                state->gamma1 = gs;
-                if (rm > state->tol_abs && (!(gs > 0.0) || !isfinite(gs))) state->status = 1;
-            }
-            state->counter = 0;
-        }
+        part_rmax[blockIdx.x] = bm;
+        if (MODE <= 1) part_rs_next[blockIdx.x] = bd;
     }
 }
 
-// r = f - A u0 (y holds A u0)
+// convergence test after the last pass of a chunk (one workgroup)
+__global__ void __launch_bounds__(kBlock) k_cg_check(CgIter it)
+{
+    __shared__ double slots[kBlock / 64];
+    (void)head_check(it, slots);
+}
+
+// r = f - y
 __global__ void __launch_bounds__(kBlock) k_sub(int64_t n, const double* __restrict__ f, const double* __restrict__ y,
                                                 double* __restrict__ r)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) r[i] = f[i] - y[i];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        r[i] = f[i] - y[i];
 }
 
-// mean of u into state->mean (last-block combination)
-__global__ void __launch_bounds__(kBlock) k_mean(int64_t n, const double* __restrict__ u, double* __restrict__ part,
-                                                 CgState* state)
+// partial sums of u
+__global__ void __launch_bounds__(kBlock) k_sum_parts(int64_t n, const double* __restrict__ u,
+                                                      double* __restrict__ part)
 {
     __shared__ double slots[kBlock / 64];
-    __shared__ int lastflag;
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    double v = (i < n) ? u[i] : 0.0;
-    double b = block_reduce<OpSum>(v, slots);
+    double v = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        v += u[i];
+    const double b = block_reduce<OpSum>(v, slots);
     if (threadIdx.x == 0) part[blockIdx.x] = b;
-    if (arrive_last(&state->counter, &lastflag)) {
-        double s = combine_partials<OpSum>(part, gridDim.x, slots);
-        if (threadIdx.x == 0) {
-            state->mean = s / (double)n;
-            state->counter = 0;
-        }
-    }
 }
 
-__global__ void __launch_bounds__(kBlock) k_sub_mean(int64_t n, double* __restrict__ u, const CgState* state)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) u[i] -= state->mean;
-}
-
-// ||f - y||_inf and ||f||_inf into state->dmax / fmax
-__global__ void __launch_bounds__(kBlock) k_resid_norms(int64_t n, const double* __restrict__ f,
-                                                        const double* __restrict__ y, double* __restrict__ pa,
-                                                        double* __restrict__ pb, CgState* state)
+// u -= mean(u), the mean combined from the partials in every workgroup
+__global__ void __launch_bounds__(kBlock) k_sub_mean(int64_t n, double* __restrict__ u, const double* __restrict__ part,
+                                                     int np, CgState* st)
 {
     __shared__ double slots[kBlock / 64];
-    __shared__ int lastflag;
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const double mean = reduce_parts<OpSum>(part, np, slots) / (double)n;
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->mean = mean;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        u[i] -= mean;
+}
+
+// partials of ||f - y||_inf and ||f||_inf
+__global__ void __launch_bounds__(kBlock) k_resid_parts(int64_t n, const double* __restrict__ f,
+                                                        const double* __restrict__ y, double* __restrict__ pa,
+                                                        double* __restrict__ pb)
+{
+    __shared__ double slots[kBlock / 64];
     double a = 0.0, b = 0.0;
-    if (i < n) {
-        a = fabs(f[i] - y[i]);
-        b = fabs(f[i]);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        a = OpMax::apply(a, fabs(f[i] - y[i]));
+        b = OpMax::apply(b, fabs(f[i]));
     }
-    double ba = block_reduce<OpMax>(a, slots);
-    double bb = block_reduce<OpMax>(b, slots);
+    const double ra = block_reduce<OpMax>(a, slots);
+    const double rb = block_reduce<OpMax>(b, slots);
     if (threadIdx.x == 0) {
-        pa[blockIdx.x] = ba;
-        pb[blockIdx.x] = bb;
+        pa[blockIdx.x] = ra;
+        pb[blockIdx.x] = rb;
     }
-    if (arrive_last(&state->counter, &lastflag)) {
-        double A = combine_partials<OpMax>(pa, gridDim.x, slots);
-        double B = combine_partials<OpMax>(pb, gridDim.x, slots);
-        if (threadIdx.x == 0) {
-            state->dmax = A;
-            state->fmax = B;
-            state->counter = 0;
-        }
+}
+
+__global__ void __launch_bounds__(kBlock) k_resid_final(const double* __restrict__ pa, const double* __restrict__ pb,
+                                                        int np, CgState* st)
+{
+    __shared__ double slots[kBlock / 64];
+    const double a = reduce_parts<OpMax>(pa, np, slots);
+    const double b = reduce_parts<OpMax>(pb, np, slots);
+    if (threadIdx.x == 0) {
+        st->dmax = a;
+        st->fmax = b;
     }
 }
 
@@ -311,17 +289,22 @@ __global__ void __launch_bounds__(kBlock) k_resid_norms(int64_t n, const double*
 
 namespace {
 
+constexpr int kMaxStreamBlocks = 512;
+
 struct Workspace {
     int device = -1;
     int n[3] = {0, 0, 0};
     int64_t total = 0;
+    int nbr = 0;              // workgroups of the streaming CG kernels
+    int npart = 0;            // capacity of each partial buffer
     double *f = nullptr, *r = nullptr, *s = nullptr, *d[2] = {nullptr, nullptr}, *p = nullptr;
-    double* part = nullptr;   // 2 * nblocks
-    double2* spec = nullptr;  // nspec
+    double* part = nullptr;   // 4 partial buffers: rmax, rs[2], dp
+    double2* spec = nullptr;
     int64_t nspec = 0;
     CgState* state = nullptr;
     CgState* host_state = nullptr;  // pinned
     double* hist = nullptr;
+    double* gam = nullptr;
     int hist_cap = 0;
 };
 
@@ -340,10 +323,11 @@ void ws_free(Workspace* w)
     (void)hipFree(w->state);
     (void)hipHostFree(w->host_state);
     (void)hipFree(w->hist);
+    (void)hipFree(w->gam);
     delete w;
 }
 
-uno_status ws_get(const Grid& g, int64_t nspec, int hist_need, Workspace** out)
+uno_status ws_get(const Grid& g, const FftPlan* plan, int hist_need, Workspace** out)
 {
     int dev = 0;
     UNO_HIP(hipGetDevice(&dev));
@@ -355,12 +339,12 @@ uno_status ws_get(const Grid& g, int64_t nspec, int hist_need, Workspace** out)
         w->device = dev;
         for (int b = 0; b < 3; ++b) w->n[b] = g.n[b];
         w->total = g.total;
-        const size_t vb = sizeof(double) * (size_t)g.total;
         const int64_t nb = (g.total + kBlock - 1) / kBlock;
+        w->nbr = (int)(nb < kMaxStreamBlocks ? nb : kMaxStreamBlocks);
+        const size_t vb = sizeof(double) * (size_t)g.total;
         bool ok = hipMalloc(&w->f, vb) == hipSuccess && hipMalloc(&w->r, vb) == hipSuccess &&
                   hipMalloc(&w->s, vb) == hipSuccess && hipMalloc(&w->d[0], vb) == hipSuccess &&
                   hipMalloc(&w->d[1], vb) == hipSuccess && hipMalloc(&w->p, vb) == hipSuccess &&
-                  hipMalloc(&w->part, sizeof(double) * 3 * nb + 64) == hipSuccess &&
                   hipMalloc(&w->state, sizeof(CgState)) == hipSuccess &&
                   hipHostMalloc(&w->host_state, sizeof(CgState), hipHostMallocDefault) == hipSuccess;
         if (!ok) {
@@ -370,16 +354,29 @@ uno_status ws_get(const Grid& g, int64_t nspec, int hist_need, Workspace** out)
         UNO_HIP(hipMemset(w->state, 0, sizeof(CgState)));
         g_ws.push_back(w);
     }
-    if (nspec > w->nspec) {
+    int need = w->nbr;
+    if (plan) {
+        const int nc = fft_c2r_blocks(g, *plan);
+        if (nc > need) need = nc;
+    }
+    if (need > w->npart) {
+        (void)hipFree(w->part);
+        w->part = nullptr;
+        if (hipMalloc(&w->part, sizeof(double) * 4 * (size_t)need) != hipSuccess) return UNO_ERR_NOMEM;
+        w->npart = need;
+    }
+    if (plan && plan->nspec > w->nspec) {
         (void)hipFree(w->spec);
         w->spec = nullptr;
-        if (hipMalloc(&w->spec, sizeof(double2) * nspec) != hipSuccess) return UNO_ERR_NOMEM;
-        w->nspec = nspec;
+        if (hipMalloc(&w->spec, sizeof(double2) * plan->nspec) != hipSuccess) return UNO_ERR_NOMEM;
+        w->nspec = plan->nspec;
     }
     if (hist_need > w->hist_cap) {
         (void)hipFree(w->hist);
-        w->hist = nullptr;
+        (void)hipFree(w->gam);
+        w->hist = w->gam = nullptr;
         if (hipMalloc(&w->hist, sizeof(double) * hist_need) != hipSuccess) return UNO_ERR_NOMEM;
+        if (hipMalloc(&w->gam, sizeof(double) * hist_need) != hipSuccess) return UNO_ERR_NOMEM;
         w->hist_cap = hist_need;
     }
     *out = w;
@@ -395,36 +392,78 @@ uno_status ws_release_all()
     return UNO_OK;
 }
 
-static uno_status enqueue_pass(const Grid& g, Workspace* w, int kind, const uno_precond* pc, const double* kappa,
-                               double* u, int64_t k, hipStream_t st, int nb)
+namespace {
+
+struct Parts {
+    double* rmax;
+    double* rs[2];
+    double* dp;
+};
+
+Parts parts_of(Workspace* w)
 {
+    Parts P;
+    P.rmax = w->part;
+    P.rs[0] = w->part + w->npart;
+    P.rs[1] = w->part + 2 * (size_t)w->npart;
+    P.dp = w->part + 3 * (size_t)w->npart;
+    return P;
+}
+
+CgIter iter_of(Workspace* w, const Parts& P, int k, double rtol, int hist_len)
+{
+    CgIter it;
+    memset(&it, 0, sizeof(it));
+    it.k = k;
+    it.st = w->state;
+    it.part_rmax = P.rmax;
+    it.np_rmax = w->nbr;
+    it.rtol = rtol;
+    it.hist = w->hist;
+    it.hist_len = hist_len;
+    it.r = w->r;
+    it.part_rs = P.rs[k & 1];
+    return it;
+}
+
+}  // namespace
+
+static uno_status enqueue_pass(const Grid& g, Workspace* w, int kind, const uno_precond* pc, const double* kappa,
+                               double* u, int k, double rtol, int hist_len, hipStream_t st)
+{
+    const Parts P = parts_of(w);
+    const int nb = w->nbr;
     double* dold = w->d[k & 1];
     double* dnew = w->d[(k + 1) & 1];
-    double* part_a = w->part;
-    double* part_b = w->part + nb;
+    CgIter it = iter_of(w, P, k, rtol, hist_len);
     KTimer kt;
     const double* s = (kind == UNO_PREC_NONE) ? w->r : w->s;
+    int np_rs = nb;
     if (kind == UNO_PREC_UNO) {
-        RsReduce red{w->r, part_b, w->state};
-        uno_status e = uno_apply_passes(g, pc->plan, pc->table, pc->table_t, w->r, w->s, UNO_F64, w->spec, &red,
-                                        w->state, st);
+        uno_status e = uno_apply_passes(g, pc->plan, pc->table, pc->table_t, w->r, w->s, UNO_F64, w->spec, &it,
+                                        &np_rs, st);
         if (e != UNO_OK) return e;
     }
     ktimer_begin(&kt, UNO_KT_MATVEC, st);
-    hipLaunchKernelGGL(k_cg_matvec<double>, dim3(nb), dim3(kBlock), 0, st, g.dev, kappa, s, dold, dnew, w->p, part_a,
-                       w->state);
+    if (kind == UNO_PREC_UNO)
+        hipLaunchKernelGGL((k_cg_matvec<double, false>), dim3(nb), dim3(kBlock), 0, st, g.dev, kappa, s, dold, dnew,
+                           w->p, P.dp, it, (const double*)P.rs[k & 1], np_rs, w->gam);
+    else
+        hipLaunchKernelGGL((k_cg_matvec<double, true>), dim3(nb), dim3(kBlock), 0, st, g.dev, kappa, s, dold, dnew,
+                           w->p, P.dp, it, (const double*)P.rs[k & 1], np_rs, w->gam);
     ktimer_end(&kt);
     UNO_HIP(hipGetLastError());
     ktimer_begin(&kt, UNO_KT_UPDATE, st);
+    double* rs_next = P.rs[(k + 1) & 1];
     if (kind == UNO_PREC_NONE)
         hipLaunchKernelGGL((k_cg_update<double, 0>), dim3(nb), dim3(kBlock), 0, st, g.dev, kappa, w->r, u, dnew, w->p,
-                           w->s, part_a, part_b, w->state, w->hist);
+                           w->s, it, (const double*)P.dp, nb, (const double*)w->gam, P.rmax, rs_next);
     else if (kind == UNO_PREC_JACOBI)
         hipLaunchKernelGGL((k_cg_update<double, 1>), dim3(nb), dim3(kBlock), 0, st, g.dev, kappa, w->r, u, dnew, w->p,
-                           w->s, part_a, part_b, w->state, w->hist);
+                           w->s, it, (const double*)P.dp, nb, (const double*)w->gam, P.rmax, rs_next);
     else
         hipLaunchKernelGGL((k_cg_update<double, 2>), dim3(nb), dim3(kBlock), 0, st, g.dev, kappa, w->r, u, dnew, w->p,
-                           w->s, part_a, part_b, w->state, w->hist);
+                           w->s, it, (const double*)P.dp, nb, (const double*)w->gam, P.rmax, rs_next);
     ktimer_end(&kt);
     UNO_HIP(hipGetLastError());
     return UNO_OK;
@@ -433,13 +472,14 @@ static uno_status enqueue_pass(const Grid& g, Workspace* w, int kind, const uno_
 uno_status pcg_run(const Grid& g, const double* kappa, const double* macro_load3, const double* rhs, double* u,
                    const uno_solve_opts* o, uno_solve_info* info, double* res_hist, hipStream_t st)
 {
-    const uno_precond* pc = o->uno;
+    const uno_precond* pc = (o->kind == UNO_PREC_UNO) ? o->uno : nullptr;
     Workspace* w = nullptr;
-    const int hist_need = o->max_iter + 1;
-    uno_status e = ws_get(g, pc ? pc->plan.nspec : 0, hist_need, &w);
+    const int hist_len = o->max_iter + 1;
+    uno_status e = ws_get(g, pc ? &pc->plan : nullptr, hist_len, &w);
     if (e != UNO_OK) return e;
-    const int nb = (int)((g.total + kBlock - 1) / kBlock);
-    // rhs and initial residual
+    const int nb = w->nbr;
+    const Parts P = parts_of(w);
+    // rhs and initial residual r_0 = f - A u_0
     if (macro_load3) {
         e = launch_rhs(g, kappa, UNO_F64, macro_load3, w->f, UNO_F64, st);
         if (e != UNO_OK) return e;
@@ -448,72 +488,74 @@ uno_status pcg_run(const Grid& g, const double* kappa, const double* macro_load3
     }
     e = launch_fe_apply(g, kappa, u, w->p, UNO_F64, st);
     if (e != UNO_OK) return e;
-    hipLaunchKernelGGL(k_sub, dim3(nb), dim3(kBlock), 0, st, g.total, w->f, w->p, w->r);
+    hipLaunchKernelGGL(k_sub, dim3(nb), dim3(kBlock), 0, st, g.total, (const double*)w->f, (const double*)w->p, w->r);
     UNO_HIP(hipGetLastError());
-    double* part_a = w->part;
-    double* part_b = w->part + nb;
     if (o->kind == UNO_PREC_NONE)
-        hipLaunchKernelGGL(k_cg_init<0>, dim3(nb), dim3(kBlock), 0, st, g.dev, kappa, w->r, w->s, part_a, part_b,
-                           w->state, o->rtol, o->max_iter, w->hist, hist_need);
+        hipLaunchKernelGGL(k_cg_init<0>, dim3(nb), dim3(kBlock), 0, st, g.dev, kappa, w->r, w->s, P.rmax, P.rs[0],
+                           w->state);
     else if (o->kind == UNO_PREC_JACOBI)
-        hipLaunchKernelGGL(k_cg_init<1>, dim3(nb), dim3(kBlock), 0, st, g.dev, kappa, w->r, w->s, part_a, part_b,
-                           w->state, o->rtol, o->max_iter, w->hist, hist_need);
+        hipLaunchKernelGGL(k_cg_init<1>, dim3(nb), dim3(kBlock), 0, st, g.dev, kappa, w->r, w->s, P.rmax, P.rs[0],
+                           w->state);
     else
-        hipLaunchKernelGGL(k_cg_init<2>, dim3(nb), dim3(kBlock), 0, st, g.dev, kappa, w->r, w->s, part_a, part_b,
-                           w->state, o->rtol, o->max_iter, w->hist, hist_need);
+        hipLaunchKernelGGL(k_cg_init<2>, dim3(nb), dim3(kBlock), 0, st, g.dev, kappa, w->r, w->s, P.rmax, P.rs[0],
+                           w->state);
     UNO_HIP(hipGetLastError());
 
     // passes in chunks; the host reads the state between chunks
-    int64_t k = 0;
+    int k = 0;
     int chunk = o->graph_chunk > 0 ? o->graph_chunk : 8;
-    int prev_it = 0;
+    int prev_k = -1;
     double prev_r = -1.0;
     for (;;) {
+        if (chunk > o->max_iter - k) chunk = o->max_iter - k;
         for (int c = 0; c < chunk; ++c, ++k) {
-            e = enqueue_pass(g, w, o->kind, pc, kappa, u, k, st, nb);
+            e = enqueue_pass(g, w, o->kind, pc, kappa, u, k, o->rtol, hist_len, st);
             if (e != UNO_OK) return e;
         }
+        CgIter it = iter_of(w, P, k, o->rtol, hist_len);
+        hipLaunchKernelGGL(k_cg_check, dim3(1), dim3(kBlock), 0, st, it);
+        UNO_HIP(hipGetLastError());
         UNO_HIP(hipMemcpyAsync(w->host_state, w->state, sizeof(CgState), hipMemcpyDeviceToHost, st));
         UNO_HIP(hipStreamSynchronize(st));
         const CgState& hs = *w->host_state;
-        if (cg_done(&hs)) break;
+        if (hs.status != 0 || hs.done != INT_MAX || k >= o->max_iter) break;
         if (o->graph_chunk <= 0) {
             // predict the passes still needed from the observed contraction rate
             int next = 16;
-            if (prev_r > 0.0 && hs.rmax > 0.0 && hs.iters > prev_it && hs.rmax < prev_r) {
-                double rate = std::pow(hs.rmax / prev_r, 1.0 / (hs.iters - prev_it));
-                double need = std::log(hs.tol_abs / hs.rmax) / std::log(rate);
+            if (prev_r > 0.0 && hs.rmax_last > 0.0 && hs.k_last > prev_k && hs.rmax_last < prev_r) {
+                const double rate = std::pow(hs.rmax_last / prev_r, 1.0 / (hs.k_last - prev_k));
+                const double need = std::log(hs.tol_abs / hs.rmax_last) / std::log(rate);
                 next = (int)std::ceil(need * 1.05) + 1;
             }
-            if (next < 4) next = 4;
-            if (next > 256) next = 256;
-            int left = hs.max_iter - hs.iters;
-            if (next > left) next = left;
-            chunk = next < 1 ? 1 : next;
+            chunk = next < 4 ? 4 : (next > 256 ? 256 : next);
         }
-        prev_it = hs.iters;
-        prev_r = hs.rmax;
+        prev_k = hs.k_last;
+        prev_r = hs.rmax_last;
     }
     const CgState hs = *w->host_state;
     // zero-mean fluctuation (Sec. 5.1) and the true residual in FP64
-    hipLaunchKernelGGL(k_mean, dim3(nb), dim3(kBlock), 0, st, g.total, u, part_a, w->state);
-    hipLaunchKernelGGL(k_sub_mean, dim3(nb), dim3(kBlock), 0, st, g.total, u, (const CgState*)w->state);
+    hipLaunchKernelGGL(k_sum_parts, dim3(nb), dim3(kBlock), 0, st, g.total, (const double*)u, P.dp);
+    hipLaunchKernelGGL(k_sub_mean, dim3(nb), dim3(kBlock), 0, st, g.total, u, (const double*)P.dp, nb, w->state);
     e = launch_fe_apply(g, kappa, u, w->p, UNO_F64, st);
     if (e != UNO_OK) return e;
-    hipLaunchKernelGGL(k_resid_norms, dim3(nb), dim3(kBlock), 0, st, g.total, w->f, w->p, part_a, part_b, w->state);
+    hipLaunchKernelGGL(k_resid_parts, dim3(nb), dim3(kBlock), 0, st, g.total, (const double*)w->f,
+                       (const double*)w->p, P.rs[0], P.rs[1]);
+    hipLaunchKernelGGL(k_resid_final, dim3(1), dim3(kBlock), 0, st, (const double*)P.rs[0], (const double*)P.rs[1], nb,
+                       w->state);
     UNO_HIP(hipGetLastError());
     UNO_HIP(hipMemcpyAsync(w->host_state, w->state, sizeof(CgState), hipMemcpyDeviceToHost, st));
+    const int iters = (hs.done != INT_MAX) ? hs.done : (hs.status != 0 ? hs.fail_iter : k);
     if (res_hist) {
-        int nh = hs.iters + 1;
-        if (nh > hist_need) nh = hist_need;
+        int nh = iters + 1;
+        if (nh > hist_len) nh = hist_len;
         UNO_HIP(hipMemcpyAsync(res_hist, w->hist, sizeof(double) * nh, hipMemcpyDeviceToHost, st));
     }
     UNO_HIP(hipStreamSynchronize(st));
     const CgState& fin = *w->host_state;
     if (info) {
-        info->iters = hs.iters;
-        info->converged = (hs.status == 0 && hs.rmax <= hs.tol_abs) ? 1 : 0;
-        info->rel_res = hs.r0max > 0.0 ? hs.rmax / hs.r0max : 0.0;
+        info->iters = iters;
+        info->converged = (hs.status == 0 && hs.done != INT_MAX) ? 1 : 0;
+        info->rel_res = hs.r0max > 0.0 ? hs.rmax_last / hs.r0max : 0.0;
         info->true_rel_res = fin.fmax > 0.0 ? fin.dmax / fin.fmax : 0.0;
         info->r0_norm = hs.r0max;
     }

@@ -17,6 +17,7 @@
 
 #include "unocg_internal.h"
 #include "reduce.h"
+#include "cg_ctl.h"
 
 namespace unocg {
 
@@ -169,16 +170,15 @@ __device__ typename V2<T>::t* transform_lds(typename V2<T>::t* buf0, typename V2
     return in;
 }
 
-__device__ __forceinline__ bool gated_out(const CgState* gate) { return gate != nullptr && cg_done(gate); }
-
 // Pass 1: real rows (length n2) -> half spectra, nl row pairs per workgroup.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_fft_r2c_z(int64_t rows, int nl, AxisDev ax, int nh,
                                                       const T* __restrict__ x, typename V2<T>::t* __restrict__ S,
-                                                      const CgState* gate)
+                                                      CgIter it)
 {
     using C = typename V2<T>::t;
-    if (gated_out(gate)) return;
+    __shared__ double slots[kBlock / 64];
+    if (it.st && head_check(it, slots)) return;
     extern __shared__ __align__(16) unsigned char smem[];
     const int n = ax.n;
     C* buf0 = (C*)smem;
@@ -210,10 +210,10 @@ __global__ void __launch_bounds__(kBlock) k_fft_r2c_z(int64_t rows, int nl, Axis
 template <typename T, int SIGN, bool MID, typename TT>
 __global__ void __launch_bounds__(kBlock) k_fft_strided(int64_t nlines, int64_t st, int nl, AxisDev ax,
                                                         typename V2<T>::t* __restrict__ S, const TT* __restrict__ table,
-                                                        const CgState* gate)
+                                                        CgIter it)
 {
     using C = typename V2<T>::t;
-    if (gated_out(gate)) return;
+    if (it.st && loop_ended(it.st, it.k)) return;
     extern __shared__ __align__(16) unsigned char smem[];
     const int n = ax.n;
     C* buf0 = (C*)smem;
@@ -256,19 +256,18 @@ __global__ void __launch_bounds__(kBlock) k_fft_strided(int64_t nlines, int64_t 
     }
 }
 
-// Pass 5: half spectra -> real rows, two rows per complex transform.  With
-// `red`, also accumulates r.s in FP64 and the last workgroup updates gamma.
+// Pass 5: half spectra -> real rows, two rows per complex transform.  Inside
+// CG it also writes the per-workgroup partials of r.s (FP64).
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_fft_c2r_z(int64_t rows, int nl, AxisDev ax, int nh,
                                                       const typename V2<T>::t* __restrict__ S, T* __restrict__ out,
-                                                      const double* __restrict__ rdot, double* __restrict__ partials,
-                                                      CgState* state, const CgState* gate)
+                                                      CgIter it)
 {
     using C = typename V2<T>::t;
-    if (gated_out(gate)) return;
+    if (it.st && loop_ended(it.st, it.k)) return;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double slots[kBlock / 64];
-    __shared__ int lastflag;
+    const double* __restrict__ rdot = it.st ? it.r : nullptr;
     const int n = ax.n;
     C* buf0 = (C*)smem;
     C* buf1 = buf0 + (size_t)nl * n;
@@ -303,16 +302,7 @@ __global__ void __launch_bounds__(kBlock) k_fft_c2r_z(int64_t rows, int nl, Axis
     }
     if (rdot) {
         double bsum = block_reduce<OpSum>(acc, slots);
-        if (threadIdx.x == 0) partials[blockIdx.x] = bsum;
-        if (arrive_last(&state->counter, &lastflag)) {
-            double g = combine_partials<OpSum>(partials, gridDim.x, slots);
-            if (threadIdx.x == 0) {
-                state->gamma0 = state->gamma1;
-                state->gamma1 = g;
-                if (!(g > 0.0) || !isfinite(g)) state->status = 1;
-                state->counter = 0;
-            }
-        }
+        if (threadIdx.x == 0) it.part_rs[blockIdx.x] = bsum;
     }
 }
 
@@ -384,12 +374,22 @@ static AxisDev axis_dev(const AxisPlan& a, bool f64)
 // lines per workgroup: about 512 complex values in LDS per buffer
 static int lines_per_block(int n) { return n >= 512 ? 1 : 512 / n; }
 
+// workgroups of the last (complex-to-real) pass = number of r.s partials
+int fft_c2r_blocks(const Grid& g, const FftPlan& p)
+{
+    const int nl = lines_per_block(p.ax[2].n);
+    const int64_t pairs = ((int64_t)g.n[0] * g.n[1] + 1) / 2;
+    return (int)((pairs + nl - 1) / nl);
+}
+
 template <typename T, typename TT>
 static uno_status run_passes(const Grid& g, const FftPlan& p, const TT* table, const T* r, T* s,
-                             typename V2<T>::t* S, const RsReduce* red, const CgState* gate, hipStream_t stream,
-                             bool f64)
+                             typename V2<T>::t* S, const CgIter* itp, int* np_rs, hipStream_t stream, bool f64)
 {
     using C = typename V2<T>::t;
+    CgIter it;
+    memset(&it, 0, sizeof(it));
+    if (itp) it = *itp;
     const int64_t rows = (int64_t)g.n[0] * g.n[1];
     const int nh = p.nh;
     KTimer kt;
@@ -401,7 +401,7 @@ static uno_status run_passes(const Grid& g, const FftPlan& p, const TT* table, c
         int nb = (int)((pairs + nl - 1) / nl);
         size_t sh = 2 * sizeof(C) * (size_t)nl * az.n;
         ktimer_begin(&kt, UNO_KT_FFT_FWD, stream);
-        hipLaunchKernelGGL(k_fft_r2c_z<T>, dim3(nb), dim3(kBlock), sh, stream, rows, nl, az, nh, r, S, gate);
+        hipLaunchKernelGGL(k_fft_r2c_z<T>, dim3(nb), dim3(kBlock), sh, stream, rows, nl, az, nh, r, S, it);
         ktimer_end(&kt);
         UNO_HIP(hipGetLastError());
     }
@@ -413,7 +413,7 @@ static uno_status run_passes(const Grid& g, const FftPlan& p, const TT* table, c
         int nb = (int)((nlines + nl - 1) / nl);
         size_t sh = 2 * sizeof(C) * (size_t)nl * ay.n;
         hipLaunchKernelGGL((k_fft_strided<T, -1, false, TT>), dim3(nb), dim3(kBlock), sh, stream, nlines, (int64_t)nh, nl,
-                           ay, S, table, gate);
+                           ay, S, table, it);
         UNO_HIP(hipGetLastError());
     }
     // pass 3: x forward, multiply, inverse (st = n1 nh, outer = 1)
@@ -425,7 +425,7 @@ static uno_status run_passes(const Grid& g, const FftPlan& p, const TT* table, c
         size_t sh = 2 * sizeof(C) * (size_t)nl * ax.n;
         ktimer_begin(&kt, UNO_KT_FFT_MID, stream);
         hipLaunchKernelGGL((k_fft_strided<T, -1, true, TT>), dim3(nb), dim3(kBlock), sh, stream, nlines, nlines, nl, ax,
-                           S, table, gate);
+                           S, table, it);
         ktimer_end(&kt);
         UNO_HIP(hipGetLastError());
     }
@@ -436,7 +436,7 @@ static uno_status run_passes(const Grid& g, const FftPlan& p, const TT* table, c
         int nb = (int)((nlines + nl - 1) / nl);
         size_t sh = 2 * sizeof(C) * (size_t)nl * ay.n;
         hipLaunchKernelGGL((k_fft_strided<T, +1, false, TT>), dim3(nb), dim3(kBlock), sh, stream, nlines, (int64_t)nh, nl,
-                           ay, S, table, gate);
+                           ay, S, table, it);
         UNO_HIP(hipGetLastError());
     }
     // pass 5
@@ -447,8 +447,8 @@ static uno_status run_passes(const Grid& g, const FftPlan& p, const TT* table, c
         int nb = (int)((pairs + nl - 1) / nl);
         size_t sh = 2 * sizeof(C) * (size_t)nl * az.n;
         ktimer_begin(&kt, UNO_KT_FFT_INV, stream);
-        hipLaunchKernelGGL(k_fft_c2r_z<T>, dim3(nb), dim3(kBlock), sh, stream, rows, nl, az, nh, (const C*)S, s,
-                           red ? red->r : nullptr, red ? red->partials : nullptr, red ? red->state : nullptr, gate);
+        hipLaunchKernelGGL(k_fft_c2r_z<T>, dim3(nb), dim3(kBlock), sh, stream, rows, nl, az, nh, (const C*)S, s, it);
+        if (np_rs) *np_rs = nb;
         ktimer_end(&kt);
         UNO_HIP(hipGetLastError());
     }
@@ -456,19 +456,18 @@ static uno_status run_passes(const Grid& g, const FftPlan& p, const TT* table, c
 }
 
 uno_status uno_apply_passes(const Grid& g, const FftPlan& p, const void* table, uno_dtype table_t, const void* r,
-                            void* s, uno_dtype vec_t, void* spec, const RsReduce* red, const CgState* gate,
-                            hipStream_t stream)
+                            void* s, uno_dtype vec_t, void* spec, const CgIter* it, int* np_rs, hipStream_t stream)
 {
     if (vec_t == UNO_F64) {
         if (table_t != UNO_F64) return UNO_ERR_ARG;
-        return run_passes<double, double>(g, p, (const double*)table, (const double*)r, (double*)s, (double2*)spec, red,
-                                          gate, stream, true);
+        return run_passes<double, double>(g, p, (const double*)table, (const double*)r, (double*)s, (double2*)spec, it,
+                                          np_rs, stream, true);
     }
     if (vec_t == UNO_F32) {
-        if (red) return UNO_ERR_ARG;  // r.s of the FP32 path is formed by the CG update kernels
+        if (it) return UNO_ERR_ARG;  // the FP32 path forms r.s in the CG update kernels
         if (table_t == UNO_F32)
             return run_passes<float, float>(g, p, (const float*)table, (const float*)r, (float*)s, (float2*)spec,
-                                            nullptr, gate, stream, false);
+                                            nullptr, nullptr, stream, false);
         return UNO_ERR_ARG;
     }
     return UNO_ERR_ARG;
@@ -478,6 +477,8 @@ uno_status uno_apply_passes(const Grid& g, const FftPlan& p, const void* table, 
 // for feature accumulation: spec receives F x on the half spectrum.
 uno_status fft_forward_real(const Grid& g, const FftPlan& p, const double* x, double2* spec, hipStream_t stream)
 {
+    CgIter none;
+    memset(&none, 0, sizeof(none));
     const int64_t rows = (int64_t)g.n[0] * g.n[1];
     const int nh = p.nh;
     AxisDev az = axis_dev(p.ax[2], true);
@@ -486,8 +487,7 @@ uno_status fft_forward_real(const Grid& g, const FftPlan& p, const double* x, do
         int64_t pairs = (rows + 1) / 2;
         int nb = (int)((pairs + nl - 1) / nl);
         size_t sh = 2 * sizeof(double2) * (size_t)nl * az.n;
-        hipLaunchKernelGGL(k_fft_r2c_z<double>, dim3(nb), dim3(kBlock), sh, stream, rows, nl, az, nh, x, spec,
-                           (const CgState*)nullptr);
+        hipLaunchKernelGGL(k_fft_r2c_z<double>, dim3(nb), dim3(kBlock), sh, stream, rows, nl, az, nh, x, spec, none);
         UNO_HIP(hipGetLastError());
     }
     AxisDev ay = axis_dev(p.ax[1], true);
@@ -497,7 +497,7 @@ uno_status fft_forward_real(const Grid& g, const FftPlan& p, const double* x, do
         int nb = (int)((nlines + nl - 1) / nl);
         size_t sh = 2 * sizeof(double2) * (size_t)nl * ay.n;
         hipLaunchKernelGGL((k_fft_strided<double, -1, false, double>), dim3(nb), dim3(kBlock), sh, stream, nlines,
-                           (int64_t)nh, nl, ay, spec, (const double*)nullptr, (const CgState*)nullptr);
+                           (int64_t)nh, nl, ay, spec, (const double*)nullptr, none);
         UNO_HIP(hipGetLastError());
     }
     AxisDev ax = axis_dev(p.ax[0], true);
@@ -507,7 +507,7 @@ uno_status fft_forward_real(const Grid& g, const FftPlan& p, const double* x, do
         int nb = (int)((nlines + nl - 1) / nl);
         size_t sh = 2 * sizeof(double2) * (size_t)nl * ax.n;
         hipLaunchKernelGGL((k_fft_strided<double, -1, false, double>), dim3(nb), dim3(kBlock), sh, stream, nlines,
-                           nlines, nl, ax, spec, (const double*)nullptr, (const CgState*)nullptr);
+                           nlines, nl, ax, spec, (const double*)nullptr, none);
         UNO_HIP(hipGetLastError());
     }
     return UNO_OK;

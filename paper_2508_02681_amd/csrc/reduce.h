@@ -1,10 +1,10 @@
 // Deterministic FP64 reductions for wave64 workgroups.
 //
 // A workgroup reduces its values with cross-lane shuffles and one LDS slot
-// per wavefront, writes one partial per workgroup, and the last workgroup to
-// arrive (device-scope counter) combines all partials in a fixed order.  The
-// result therefore does not depend on scheduling, and the counter is left at
-// zero for the next kernel.
+// per wavefront and writes one partial per workgroup.  The kernel that needs
+// the scalar combines the partials itself, in every workgroup, in a fixed
+// order: the result does not depend on scheduling and no device-scope fence
+// (which would write back the whole L2 on this chip) is needed.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -43,31 +43,21 @@ __device__ inline double block_reduce(double v, double* slots)
     return r;
 }
 
-// Publishes thread 0's block value(s) and tells whether this workgroup is the
-// last to arrive.  Call from all threads; returns the same flag in all.
-__device__ inline bool arrive_last(unsigned* counter, int* flag_lds)
-{
-    if (threadIdx.x == 0) {
-        __threadfence();
-        unsigned t = atomicAdd(counter, 1u);
-        *flag_lds = (t == gridDim.x - 1) ? 1 : 0;
-    }
-    __syncthreads();
-    bool last = *flag_lds != 0;
-    if (last) __threadfence();
-    return last;
-}
-
-// Fixed-order combination of nparts partials by the whole (last) workgroup.
-// Result valid in thread 0.
+// Fixed-order combination of nparts partials (written by an earlier kernel)
+// by a whole workgroup; every thread receives the result.  Kernel boundaries
+// make the partials visible, so no fences are needed.
 template <class Op>
-__device__ inline double combine_partials(const double* parts, int nparts, double* slots)
+__device__ inline double reduce_parts(const double* parts, int nparts, double* slots)
 {
     double v = Op::ident();
-    for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
-        v = Op::apply(v, parts[i]);
-    }
-    return block_reduce<Op>(v, slots);
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) v = Op::apply(v, parts[i]);
+    v = block_reduce<Op>(v, slots);
+    __syncthreads();
+    if (threadIdx.x == 0) slots[0] = v;
+    __syncthreads();
+    v = slots[0];
+    __syncthreads();
+    return v;
 }
 
 }  // namespace unocg

@@ -96,48 +96,34 @@ struct FftPlan {
 uno_status fft_plan_create(const Grid& g, FftPlan* p);
 void fft_plan_destroy(FftPlan* p);
 
-// Per-CG-iteration reduction target: when non-null the inverse pass adds
-// r.s partials and finalizes gamma in `state`.
-struct CgState;
-struct RsReduce {
-    const double* r;     // FP64 residual
-    double* partials;
-    CgState* state;
-};
+struct CgIter;  // per-pass control of the CG loop (cg_ctl.h)
 
 // s = (1/n) F^H diag(table) F r.  `spec` scratch holds nspec complex values of
-// the vector precision.  gate != nullptr: every pass returns at once when the
-// solver state says the iteration is finished.
+// the vector precision.  it != nullptr: the passes belong to CG pass it->k,
+// the first one runs the convergence test of that pass, every one returns at
+// once when the loop has ended, and the last one writes per-workgroup r.s
+// partials (their count is returned in *np_rs).
 uno_status uno_apply_passes(const Grid& g, const FftPlan& p, const void* table, uno_dtype table_t,
-                            const void* r, void* s, uno_dtype vec_t, void* spec, const RsReduce* red,
-                            const CgState* gate, hipStream_t stream);
+                            const void* r, void* s, uno_dtype vec_t, void* spec, const CgIter* it, int* np_rs,
+                            hipStream_t stream);
 
 // Forward transform of nbatch real fields into half spectra (training).
 uno_status fft_forward_real(const Grid& g, const FftPlan& p, const double* x, double2* spec,
                             hipStream_t stream);
 
 // ---------------------------------------------------------------------------
-// CG (cg.hip)
+// CG (cg.hip): solver state kept on the device
 struct CgState {
-    double gamma0, gamma1;   // r.s of the previous and the current pass
-    double dp;               // d . A d
-    double rmax;             // ||r||_inf after the last update
-    double r0max;            // ||r_0||_inf
-    double tol_abs;          // rtol * r0max
-    double mean;             // scratch: mean of u at the end
-    double fmax, dmax;       // true-residual check
-    int iters;               // completed passes
-    int max_iter;
-    int status;              // 0 ok, 1 breakdown
-    int hist_len;            // capacity of the history buffer
-    unsigned counter;        // last-block arrival counter (always 0 between kernels)
-    unsigned pad;
+    double r0max;     // ||r_0||_inf
+    double tol_abs;   // rtol * r0max
+    double rmax_last; // last reduced ||r||_inf
+    double mean;      // mean of u at the end
+    double fmax, dmax;  // ||f||_inf, ||f - A u||_inf at the end
+    int done;         // passes completed when the loop ended (INT_MAX while running)
+    int status;       // 0 ok, 1 breakdown
+    int k_last;       // pass index of rmax_last
+    int fail_iter;    // pass of a breakdown
 };
-
-__host__ __device__ inline bool cg_done(const CgState* st)
-{
-    return st->status != 0 || st->rmax <= st->tol_abs || st->iters >= st->max_iter;
-}
 
 }  // namespace unocg
 
