@@ -47,7 +47,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=16)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--train-seeds", type=int, default=16)
+    ap.add_argument("--train-seeds", type=int, default=64)
     ap.add_argument("--M", type=int, default=0, help="mode parameter (0 = pick from a small sweep)")
     ap.add_argument("--jac-steps", type=int, default=4)
     ap.add_argument("--cpu-iters", type=int, default=20, help="oracle UNO-CG passes timed for cpu_baseline")
@@ -117,19 +117,26 @@ def main():
     U += U2
     log("training pairs: %d (random-theta UNO-CG mean %.0f passes, refit UNO-CG mean %.0f)" %
         (len(F), np.mean(its0), np.mean(its1) if its1 else float("nan")))
-    # mode parameter: sweep on a validation microstructure (a training one)
-    Ms = [args.M] if args.M > 0 else [4, 8, 12, 16, 24]
+    # mode parameter M (tuned, as in the paper): fastest time to tolerance on a
+    # held-out validation microstructure
+    kap_val = torch.tensor(si.microstructure(cfg, 5000)[0], device=dev)
+    Ms = [args.M] if args.M > 0 else [8, 12, 16, 20, 24]
     best = None
     for M in Ms:
         th = fit(F, U, M)
         p = uno.UnoPrecond.create(SHAPE, M, th)
-        it = 0
-        for g in LOADS:
-            _, info = uno.pcg_solve(kap_train[0], macro_load=g, kind="uno", precond=p, rtol=RTOL)
-            it += info["iters"]
-        log("  M=%d: %d passes on validation" % (M, it))
-        if best is None or it < best[0]:
-            best = (it, M, th, p)
+        for rep in range(2):  # first pass warms up
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            it = 0
+            for g in LOADS:
+                _, info = uno.pcg_solve(kap_val, macro_load=g, kind="uno", precond=p, rtol=RTOL)
+                it += info["iters"]
+            torch.cuda.synchronize()
+            tv = time.perf_counter() - t1
+        log("  M=%d: %d passes, %.2f ms on validation" % (M, it, tv * 1e3))
+        if best is None or tv < best[0]:
+            best = (tv, M, th, p)
     _, M, theta, prec = best
     train_s = time.time() - t0
     log("trained M=%d in %.1fs" % (M, train_s))
@@ -174,6 +181,11 @@ def main():
     jac_t_solve = dtj / len(itsj) * 1e3
     jac_rate = n_dof * sum(itsj) / dtj
     log("Jac-CG: %.1f passes/solve, %.3e DOF*it/s, %.3f ms per solve" % (np.mean(itsj), jac_rate, jac_t_solve))
+
+    # ---------------- FANS (reference-medium preconditioner) for context ----------------
+    pf = uno.UnoPrecond.fans(SHAPE, 0.5 * (cfg["k_matrix"] + cfg["k_incl"]))
+    dtf, itsf, _ = timed("uno", pf, 1, 0)
+    log("FANS-CG: %.1f passes/solve, %.3f ms per solve" % (np.mean(itsf), dtf / len(itsf) * 1e3))
 
     # ---------------- dominant kernel: live HIP-event timing ----------------
     fams = {uno.KT_MATVEC: "k_cg_matvec", uno.KT_UPDATE: "k_cg_update", uno.KT_FFT_FWD: "k_fft_r2c_z",
@@ -237,6 +249,7 @@ def main():
                    "microstructures": len(kap_test)},
         "uno_cg": {"passes_mean": float(np.mean(its)), "ms_per_solve": uno_t_solve, "dof_iters_per_s": value},
         "jac_cg": {"passes_mean": float(np.mean(itsj)), "ms_per_solve": jac_t_solve, "dof_iters_per_s": jac_rate},
+        "fans_cg": {"passes_mean": float(np.mean(itsf)), "ms_per_solve": dtf / len(itsf) * 1e3},
         "time_to_tol_speedup_uno_vs_jac": jac_t_solve / uno_t_solve,
         "kappa_bar_first": np.round(kbs[0], 6).tolist(),
         "roofline": roofline,

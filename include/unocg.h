@@ -116,6 +116,16 @@ uno_status uno_precond_create_fans(const uno_grid *grid, double kappa_ref, uno_d
  * so concurrent applies of one precond on different streams race. */
 uno_status uno_precond_apply(const uno_precond *p, const void *r, void *s, uno_dtype vec_t, void *stream);
 
+/* Selects how FP64 applies of a UNO preconditioner are computed; both give
+ * the same operator.  UNO_PATH_AUTO (default) and UNO_PATH_LEARNED use the
+ * learned-mode passes when the preconditioner has them (UNO tables whose
+ * learned block is small against the grid): since Phi equals the bypass W
+ * outside the learned block, s = W r + T^H ((Phi - W) o T r) needs the
+ * transform of r on the learned modes only.  UNO_PATH_SPECTRAL always runs the
+ * full transform over the half spectrum. */
+enum { UNO_PATH_AUTO = 0, UNO_PATH_SPECTRAL = 1, UNO_PATH_LEARNED = 2 };
+uno_status uno_precond_set_path(uno_precond *p, int32_t path);
+
 /* Copies the half-spectrum table (n[0] x .. x n[d-2] x (n[d-1]/2+1) values,
  * C order, unscaled Phi) to host memory `out` (host). For inspection. */
 uno_status uno_precond_table(const uno_precond *p, double *out, int64_t nout);

@@ -77,6 +77,7 @@ def lib():
         "uno_precond_create_fans": ([G, f64, i, P(vp)], i),
         "uno_precond_apply": ([vp, vp, vp, i, vp], i),
         "uno_precond_table": ([vp, P(f64), i64], i),
+        "uno_precond_set_path": ([vp, i32], i),
         "uno_precond_destroy": ([vp], i),
         "pcg_solve": ([G, Mt, P(f64), vp, vp, P(uno_solve_opts), P(uno_solve_info), P(f64), vp], i),
         "effective_tensor": ([G, Mt, i32, P(f64), vp, P(f64), vp], i),
@@ -214,6 +215,12 @@ class UnoPrecond:
         _check(lib().uno_precond_apply(self._h, _dev(r, "r"), _dev(s, "s", r.dtype), _dt(r.dtype), _stream()),
                "uno_precond_apply")
         return s
+
+    PATH_AUTO, PATH_SPECTRAL, PATH_LEARNED = 0, 1, 2
+
+    def set_path(self, path: int):
+        """0 auto, 1 full spectral passes, 2 learned-mode passes (FP64)."""
+        _check(lib().uno_precond_set_path(self._h, int(path)), "uno_precond_set_path")
 
     def table(self) -> np.ndarray:
         shp = list(self.shape)

@@ -276,6 +276,7 @@ static uno_status precond_finish(uno_precond* p, const std::vector<double>& phi,
 static void precond_free(uno_precond* p)
 {
     if (!p) return;
+    lowrank_destroy(p->lr);
     fft_plan_destroy(&p->plan);
     if (p->table) (void)hipFree(p->table);
     if (p->spec) (void)hipFree(p->spec);
@@ -316,6 +317,32 @@ uno_status uno_precond_create(const uno_grid* grid, int32_t M, const double* the
             }
     e = precond_finish(p, phi, eps_spd, table_t, true);
     if (e != UNO_OK) { precond_free(p); return e; }
+    // learned-mode passes: table correction C = Phi - W on the block
+    // [-mx..mx] x [-M..M] x [0..M] (mx = 0 for one voxel layer), stored with
+    // the real-transform weight (1 at k_z = 0, else 2) and 1/n
+    {
+        const int mx = (g.n[0] == 1) ? 0 : M;
+        const int kxn = 2 * mx + 1, kyn = 2 * M + 1, kzn = M + 1;
+        const int64_t nblock = (int64_t)kxn * kyn * kzn;
+        if (nblock * 8 <= g.total) {
+            const double W = theta[0] * theta[0];
+            const double inv_n = 1.0 / (double)g.total;
+            std::vector<double> cb(nblock);
+            for (int kxi = 0; kxi < kxn; ++kxi)
+                for (int kyi = 0; kyi < kyn; ++kyi)
+                    for (int kz = 0; kz < kzn; ++kz) {
+                        const int ix = ((kxi - mx) % g.n[0] + g.n[0]) % g.n[0];
+                        const int iy = ((kyi - M) % g.n[1] + g.n[1]) % g.n[1];
+                        const double ph = phi[((int64_t)ix * g.n[1] + iy) * nh + kz];
+                        cb[((int64_t)kxi * kyn + kyi) * kzn + kz] = (ph - W) * (kz == 0 ? 1.0 : 2.0) * inv_n;
+                    }
+            e = lowrank_create(g, p->plan, M, W, cb, &p->lr);
+            if (e == UNO_ERR_SHAPE) p->lr = nullptr;  // block too large for the LDS staging: full passes only
+            else if (e != UNO_OK) { precond_free(p); return e; }
+        }
+    }
+    p->rs_blocks = fft_c2r_blocks(g, p->plan);
+    if (p->lr && lowrank_rs_blocks(p->lr) > p->rs_blocks) p->rs_blocks = lowrank_rs_blocks(p->lr);
     UNO_HIP(hipGetDevice(&p->device));
     *out = p;
     return UNO_OK;
@@ -360,6 +387,7 @@ uno_status uno_precond_create_fans(const uno_grid* grid, double kappa_ref, uno_d
             }
     e = precond_finish(p, phi, 0.0, table_t, false);
     if (e != UNO_OK) { precond_free(p); return e; }
+    p->rs_blocks = fft_c2r_blocks(g, p->plan);
     UNO_HIP(hipGetDevice(&p->device));
     *out = p;
     return UNO_OK;
@@ -371,7 +399,19 @@ uno_status uno_precond_apply(const uno_precond* p, const void* r, void* s, uno_d
     if (vec_t != UNO_F64 && vec_t != UNO_F32) return UNO_ERR_ARG;
     if (vec_t == UNO_F64 && p->table_t != UNO_F64) return UNO_ERR_ARG;
     if (vec_t == UNO_F32 && p->table_t != UNO_F32) return UNO_ERR_ARG;
+    if (vec_t == UNO_F64 && uno_use_lowrank(p)) {
+        if (r == s) return UNO_ERR_ARG;  // the learned-mode passes read r after writing s
+        return lowrank_apply(p->lr, (const double*)r, (double*)s, nullptr, nullptr, S(stream));
+    }
     return uno_apply_passes(p->grid, p->plan, p->table, p->table_t, r, s, vec_t, p->spec, nullptr, nullptr, S(stream));
+}
+
+uno_status uno_precond_set_path(uno_precond* p, int32_t path)
+{
+    if (!p || path < UNO_PATH_AUTO || path > UNO_PATH_LEARNED) return UNO_ERR_ARG;
+    if (path == UNO_PATH_LEARNED && !p->lr) return UNO_ERR_SHAPE;
+    p->path = path;
+    return UNO_OK;
 }
 
 uno_status uno_precond_table(const uno_precond* p, double* out, int64_t nout)

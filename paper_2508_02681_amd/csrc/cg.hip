@@ -22,10 +22,9 @@
 #include "unocg_internal.h"
 #include "reduce.h"
 #include "cg_ctl.h"
+#include "stencil_tile.h"
 
 namespace unocg {
-
-int fft_c2r_blocks(const Grid& g, const FftPlan& p);
 
 __device__ __forceinline__ int wrap_i(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
@@ -92,90 +91,6 @@ __global__ void __launch_bounds__(kBlock) k_cg_init(GridDev g, const double* __r
     }
 }
 
-// matvec of pass k (see file comment).  HEAD: also the convergence test.
-template <typename T, bool HEAD>
-__global__ void __launch_bounds__(kBlock) k_cg_matvec(GridDev g, const T* __restrict__ kappa,
-                                                      const T* __restrict__ s, const T* __restrict__ dold,
-                                                      T* __restrict__ dnew, T* __restrict__ p,
-                                                      double* __restrict__ part_dp, CgIter it,
-                                                      const double* __restrict__ part_rs, int np_rs, double* gam)
-{
-    __shared__ double slots[kBlock / 64];
-    if (HEAD) {
-        if (head_check(it, slots)) return;
-    } else if (loop_ended(it.st, it.k)) {
-        return;
-    }
-    const int k = it.k;
-    const double gk = reduce_parts<OpSum>(part_rs, np_rs, slots);
-    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
-    if (lead) gam[k] = gk;
-    if (!(gk > 0.0) || !isfinite(gk)) {
-        if (lead) { it.st->status = 1; it.st->fail_iter = k; }
-        return;
-    }
-    const bool first = (k == 0);
-    const T beta = first ? (T)0 : (T)(gk / gam[k - 1]);
-    double dot = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.n; i += (int64_t)gridDim.x * blockDim.x) {
-        const int z = (int)(i % g.n2);
-        const int64_t t = i / g.n2;
-        const int y = (int)(t % g.n1), x = (int)(t / g.n1);
-        T kv[2][2][2];
-        voxel_kappa(g, kappa, x, y, z, kv);
-        // conductivity sums of the voxels shared by the node and each neighbour
-        T A[2][2][3], B[2][3][3], K3[3][3][3];
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int b = 0; b < 2; ++b) {
-                A[a][b][0] = kv[a][b][0];
-                A[a][b][1] = kv[a][b][0] + kv[a][b][1];
-                A[a][b][2] = kv[a][b][1];
-            }
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                B[a][0][c] = A[a][0][c];
-                B[a][1][c] = A[a][0][c] + A[a][1][c];
-                B[a][2][c] = A[a][1][c];
-            }
-#pragma unroll
-        for (int b = 0; b < 3; ++b)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                K3[0][b][c] = B[0][b][c];
-                K3[1][b][c] = B[0][b][c] + B[1][b][c];
-                K3[2][b][c] = B[1][b][c];
-            }
-        T acc = 0, dself = 0;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const int xx = wrap_i(x + a - 1, g.n0);
-#pragma unroll
-            for (int b = 0; b < 3; ++b) {
-                const int yy = wrap_i(y + b - 1, g.n1);
-                const int64_t row = ((int64_t)xx * g.n1 + yy) * g.n2;
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    const int zz = wrap_i(z + c - 1, g.n2);
-                    T dv = s[row + zz];
-                    if (!first) dv += beta * dold[row + zz];
-                    const int m = ((a != 1) << 2) | ((b != 1) << 1) | (c != 1);
-                    acc += (T)g.w[m] * K3[a][b][c] * dv;
-                    if (a == 1 && b == 1 && c == 1) dself = dv;
-                }
-            }
-        }
-        dnew[i] = dself;
-        p[i] = acc;
-        dot += (double)dself * (double)acc;
-    }
-    const double bd = block_reduce<OpSum>(dot, slots);
-    if (threadIdx.x == 0) part_dp[blockIdx.x] = bd;
-}
-
 // update of pass k.  MODE 0: none, 1: Jacobi (both also form s and r.s for
 // pass k + 1), 2: UNO.
 template <typename T, int MODE>
@@ -188,6 +103,15 @@ __global__ void __launch_bounds__(kBlock) k_cg_update(GridDev g, const T* __rest
 {
     __shared__ double slots[kBlock / 64];
     if (loop_ended(it.st, it.k)) return;
+    // the first element's operands are loaded before the d.p combination
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double r0 = 0.0, p0 = 0.0, u0 = 0.0, d0 = 0.0;
+    if (i0 < g.n) {
+        r0 = r[i0];
+        p0 = (double)p[i0];
+        u0 = u[i0];
+        d0 = (double)d[i0];
+    }
     const double dp = reduce_parts<OpSum>(part_dp, np_dp, slots);
     if (!(dp > 0.0) || !isfinite(dp)) {
         if (blockIdx.x == 0 && threadIdx.x == 0) { it.st->status = 1; it.st->fail_iter = it.k; }
@@ -195,10 +119,16 @@ __global__ void __launch_bounds__(kBlock) k_cg_update(GridDev g, const T* __rest
     }
     const double alpha = gam[it.k] / dp;
     double m = 0.0, dt = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.n; i += (int64_t)gridDim.x * blockDim.x) {
-        const double ri = r[i] - alpha * (double)p[i];
+    for (int64_t i = i0; i < g.n; i += (int64_t)gridDim.x * blockDim.x) {
+        if (i != i0) {
+            r0 = r[i];
+            p0 = (double)p[i];
+            u0 = u[i];
+            d0 = (double)d[i];
+        }
+        const double ri = r0 - alpha * p0;
         r[i] = ri;
-        u[i] += alpha * (double)d[i];
+        u[i] = u0 + alpha * d0;
         m = OpMax::apply(m, fabs(ri));
         if (MODE == 0) dt += ri * ri;
         if (MODE == 1) {
@@ -327,7 +257,7 @@ void ws_free(Workspace* w)
     delete w;
 }
 
-uno_status ws_get(const Grid& g, const FftPlan* plan, int hist_need, Workspace** out)
+uno_status ws_get(const Grid& g, const FftPlan* plan, int extra_parts, int hist_need, Workspace** out)
 {
     int dev = 0;
     UNO_HIP(hipGetDevice(&dev));
@@ -355,10 +285,9 @@ uno_status ws_get(const Grid& g, const FftPlan* plan, int hist_need, Workspace**
         g_ws.push_back(w);
     }
     int need = w->nbr;
-    if (plan) {
-        const int nc = fft_c2r_blocks(g, *plan);
-        if (nc > need) need = nc;
-    }
+    const int ntile = choose_tile(g).blocks;
+    if (ntile > need) need = ntile;
+    if (extra_parts > need) need = extra_parts;
     if (need > w->npart) {
         (void)hipFree(w->part);
         w->part = nullptr;
@@ -440,30 +369,31 @@ static uno_status enqueue_pass(const Grid& g, Workspace* w, int kind, const uno_
     const double* s = (kind == UNO_PREC_NONE) ? w->r : w->s;
     int np_rs = nb;
     if (kind == UNO_PREC_UNO) {
-        uno_status e = uno_apply_passes(g, pc->plan, pc->table, pc->table_t, w->r, w->s, UNO_F64, w->spec, &it,
-                                        &np_rs, st);
+        uno_status e = uno_use_lowrank(pc)
+                           ? lowrank_apply(pc->lr, w->r, w->s, &it, &np_rs, st)
+                           : uno_apply_passes(g, pc->plan, pc->table, pc->table_t, w->r, w->s, UNO_F64, w->spec, &it,
+                                              &np_rs, st);
         if (e != UNO_OK) return e;
     }
     ktimer_begin(&kt, UNO_KT_MATVEC, st);
+    int np_dp;
     if (kind == UNO_PREC_UNO)
-        hipLaunchKernelGGL((k_cg_matvec<double, false>), dim3(nb), dim3(kBlock), 0, st, g.dev, kappa, s, dold, dnew,
-                           w->p, P.dp, it, (const double*)P.rs[k & 1], np_rs, w->gam);
+        np_dp = launch_tile<double, true, false>(g, kappa, s, dold, dnew, w->p, P.dp, it, P.rs[k & 1], np_rs, w->gam, st);
     else
-        hipLaunchKernelGGL((k_cg_matvec<double, true>), dim3(nb), dim3(kBlock), 0, st, g.dev, kappa, s, dold, dnew,
-                           w->p, P.dp, it, (const double*)P.rs[k & 1], np_rs, w->gam);
+        np_dp = launch_tile<double, true, true>(g, kappa, s, dold, dnew, w->p, P.dp, it, P.rs[k & 1], np_rs, w->gam, st);
     ktimer_end(&kt);
     UNO_HIP(hipGetLastError());
     ktimer_begin(&kt, UNO_KT_UPDATE, st);
     double* rs_next = P.rs[(k + 1) & 1];
     if (kind == UNO_PREC_NONE)
         hipLaunchKernelGGL((k_cg_update<double, 0>), dim3(nb), dim3(kBlock), 0, st, g.dev, kappa, w->r, u, dnew, w->p,
-                           w->s, it, (const double*)P.dp, nb, (const double*)w->gam, P.rmax, rs_next);
+                           w->s, it, (const double*)P.dp, np_dp, (const double*)w->gam, P.rmax, rs_next);
     else if (kind == UNO_PREC_JACOBI)
         hipLaunchKernelGGL((k_cg_update<double, 1>), dim3(nb), dim3(kBlock), 0, st, g.dev, kappa, w->r, u, dnew, w->p,
-                           w->s, it, (const double*)P.dp, nb, (const double*)w->gam, P.rmax, rs_next);
+                           w->s, it, (const double*)P.dp, np_dp, (const double*)w->gam, P.rmax, rs_next);
     else
         hipLaunchKernelGGL((k_cg_update<double, 2>), dim3(nb), dim3(kBlock), 0, st, g.dev, kappa, w->r, u, dnew, w->p,
-                           w->s, it, (const double*)P.dp, nb, (const double*)w->gam, P.rmax, rs_next);
+                           w->s, it, (const double*)P.dp, np_dp, (const double*)w->gam, P.rmax, rs_next);
     ktimer_end(&kt);
     UNO_HIP(hipGetLastError());
     return UNO_OK;
@@ -475,7 +405,7 @@ uno_status pcg_run(const Grid& g, const double* kappa, const double* macro_load3
     const uno_precond* pc = (o->kind == UNO_PREC_UNO) ? o->uno : nullptr;
     Workspace* w = nullptr;
     const int hist_len = o->max_iter + 1;
-    uno_status e = ws_get(g, pc ? &pc->plan : nullptr, hist_len, &w);
+    uno_status e = ws_get(g, pc ? &pc->plan : nullptr, pc ? pc->rs_blocks : 0, hist_len, &w);
     if (e != UNO_OK) return e;
     const int nb = w->nbr;
     const Parts P = parts_of(w);

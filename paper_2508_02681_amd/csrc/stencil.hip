@@ -11,42 +11,13 @@
 // (axis b: delta_b = -1 -> sigma_b = -1; +1 -> sigma_b = 0; 0 -> both).
 #include "unocg_internal.h"
 #include "reduce.h"
+#include "stencil_tile.h"
+
+#include <cstring>
 
 namespace unocg {
 
 __device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
-
-// 27 compatible-voxel sums K3[a][b][c], a/b/c in {0: delta=-1, 1: delta=0, 2: delta=+1}
-template <typename T>
-__device__ __forceinline__ void kappa_sums(const T k[2][2][2], T K3[3][3][3])
-{
-    T A[2][2][3];
-#pragma unroll
-    for (int s0 = 0; s0 < 2; ++s0)
-#pragma unroll
-        for (int s1 = 0; s1 < 2; ++s1) {
-            A[s0][s1][0] = k[s0][s1][0];
-            A[s0][s1][1] = k[s0][s1][0] + k[s0][s1][1];
-            A[s0][s1][2] = k[s0][s1][1];
-        }
-    T B[2][3][3];
-#pragma unroll
-    for (int s0 = 0; s0 < 2; ++s0)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            B[s0][0][c] = A[s0][0][c];
-            B[s0][1][c] = A[s0][0][c] + A[s0][1][c];
-            B[s0][2][c] = A[s0][1][c];
-        }
-#pragma unroll
-    for (int b = 0; b < 3; ++b)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            K3[0][b][c] = B[0][b][c];
-            K3[1][b][c] = B[0][b][c] + B[1][b][c];
-            K3[2][b][c] = B[1][b][c];
-        }
-}
 
 template <typename T>
 __device__ __forceinline__ void load_kappa8(const GridDev& g, const T* __restrict__ kappa, int x, int y, int z,
@@ -61,39 +32,6 @@ __device__ __forceinline__ void load_kappa8(const GridDev& g, const T* __restric
                 int xx = wrapi(x - 1 + s0, g.n0), yy = wrapi(y - 1 + s1, g.n1), zz = wrapi(z - 1 + s2, g.n2);
                 k[s0][s1][s2] = kappa[((int64_t)xx * g.n1 + yy) * g.n2 + zz];
             }
-}
-
-// y = A u, one node per thread, neighbours read through the caches.
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_fe_apply_node(GridDev g, const T* __restrict__ kappa,
-                                                          const T* __restrict__ u, T* __restrict__ y)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= g.n) return;
-    int z = (int)(i % g.n2);
-    int64_t t = i / g.n2;
-    int yy = (int)(t % g.n1);
-    int x = (int)(t / g.n1);
-    T k[2][2][2], K3[3][3][3];
-    load_kappa8(g, kappa, x, yy, z, k);
-    kappa_sums(k, K3);
-    T acc = 0;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        int xx = wrapi(x + a - 1, g.n0);
-#pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            int y2 = wrapi(yy + b - 1, g.n1);
-            const T* row = u + ((int64_t)xx * g.n1 + y2) * g.n2;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                int zz = wrapi(z + c - 1, g.n2);
-                int m = ((a != 1) << 2) | ((b != 1) << 1) | (c != 1);
-                acc += (T)g.w[m] * K3[a][b][c] * row[zz];
-            }
-        }
-    }
-    y[i] = acc;
 }
 
 // out = r / diag(A), diag = cdiag * sum of the 8 voxel conductivities.
@@ -190,13 +128,14 @@ static int nblocks_for(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
 
 uno_status launch_fe_apply(const Grid& g, const void* kappa, const void* u, void* y, uno_dtype t, hipStream_t s)
 {
-    int nb = nblocks_for(g.total);
+    CgIter none;
+    memset(&none, 0, sizeof(none));
     if (t == UNO_F64)
-        hipLaunchKernelGGL(k_fe_apply_node<double>, dim3(nb), dim3(kBlock), 0, s, g.dev, (const double*)kappa,
-                           (const double*)u, (double*)y);
+        launch_tile<double, false, false>(g, (const double*)kappa, (const double*)u, nullptr, nullptr, (double*)y,
+                                          nullptr, none, nullptr, 0, nullptr, s);
     else
-        hipLaunchKernelGGL(k_fe_apply_node<float>, dim3(nb), dim3(kBlock), 0, s, g.dev, (const float*)kappa,
-                           (const float*)u, (float*)y);
+        launch_tile<float, false, false>(g, (const float*)kappa, (const float*)u, nullptr, nullptr, (float*)y, nullptr,
+                                         none, nullptr, 0, nullptr, s);
     return hip_status(hipGetLastError());
 }
 

@@ -1,0 +1,278 @@
+// LDS-tiled matrix-free operator apply (Sec. 3.1: the stiffness matrix of the
+// periodic linear FE discretization, applied without assembly).
+//
+// A workgroup of 256 threads owns a TX x TY x TZ tile of nodes (TY = 256 /
+// TZ).  It stages the vector on the tile plus a one-node halo and the
+// conductivities of the (TX+1) x (TY+1) x (TZ+1) voxels touching the tile in
+// LDS (periodic wrap on each coordinate), then each thread walks one (y, z)
+// column of the tile along x, keeping the 3 x 3 neighbourhood of three node
+// planes and the 2 x 2 voxel conductivities of two voxel planes in
+// registers: 9 + 4 LDS reads per node.
+//
+// Node-centred form of the assembled operator: node i touches the 8 voxels
+// i + sigma, sigma in {-1,0}^3, and
+//   (A u)_i = sum_{delta in {-1,0,1}^3} w[m(delta)] * ksum(i, delta) * u_{i+delta},
+// m(delta) flagging the axes where delta != 0, ksum adding the voxels that
+// contain both nodes (axis b: delta_b = -1 -> sigma_b = -1, +1 -> 0,
+// 0 -> both); w[m] is the brick element's corner coupling.
+//
+// CG variant (fused into Algorithm 1's direction update and matvec): the
+// staged vector is d = s + beta d_old, the tile's own d is written to d_new,
+// p = A d, and per-workgroup partials of d.p are written.
+#pragma once
+
+#include "unocg_internal.h"
+#include "reduce.h"
+#include "cg_ctl.h"
+
+namespace unocg {
+
+struct TileGeom {
+    int tiles_y, tiles_z;
+};
+
+__device__ __forceinline__ int wrap_mod(int v, int n)
+{
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+
+template <typename T>
+__device__ __forceinline__ T stencil_node(const GridDev& g, const T dm[3][3], const T d0[3][3], const T dp[3][3],
+                                          const T km[2][2], const T kp[2][2])
+{
+    // conductivity sums over compatible voxels, per offset (a, b, c) in {-1,0,1}^3
+    T S[3][2][2];  // along x: [0] sigma0=-1, [1] both, [2] sigma0=0
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            S[0][b][c] = km[b][c];
+            S[1][b][c] = km[b][c] + kp[b][c];
+            S[2][b][c] = kp[b][c];
+        }
+    T acc = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        T K3[3][3];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            T lo = (b == 2) ? (T)0 : S[a][0][0];
+            T hi = (b == 0) ? (T)0 : S[a][1][0];
+            T lo1 = (b == 2) ? (T)0 : S[a][0][1];
+            T hi1 = (b == 0) ? (T)0 : S[a][1][1];
+            T c0 = lo + hi;     // sigma2 = -1 column
+            T c1 = lo1 + hi1;   // sigma2 = 0 column
+            K3[b][0] = c0;
+            K3[b][1] = c0 + c1;
+            K3[b][2] = c1;
+        }
+        const T(*D)[3] = (a == 0) ? dm : (a == 1 ? d0 : dp);
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const int m = ((a != 1) << 2) | ((b != 1) << 1) | (c != 1);
+                acc += (T)g.w[m] * K3[b][c] * D[b][c];
+            }
+    }
+    return acc;
+}
+
+template <typename T, int TX, int TZ, bool CG, bool HEAD>
+__global__ void __launch_bounds__(256) k_stencil_tile(GridDev g, TileGeom tg, const T* __restrict__ kappa,
+                                                      const T* __restrict__ s, const T* __restrict__ dold,
+                                                      T* __restrict__ dnew, T* __restrict__ p,
+                                                      double* __restrict__ part_dp, CgIter it,
+                                                      const double* __restrict__ part_rs, int np_rs, double* gam)
+{
+    constexpr int TY = 256 / TZ;
+    constexpr int DX = TX + 2, DY = TY + 2, DZ = TZ + 2;
+    constexpr int KX = TX + 1, KY = TY + 1, KZ = TZ + 1;
+    __shared__ T Dl[DX * DY * DZ];
+    __shared__ T Kl[KX * KY * KZ];
+    __shared__ double slots[4];
+
+    int b = blockIdx.x;
+    const int tzi = b % tg.tiles_z;
+    b /= tg.tiles_z;
+    const int tyi = b % tg.tiles_y;
+    const int txi = b / tg.tiles_y;
+    const int x0 = txi * TX, y0 = tyi * TY, z0 = tzi * TZ;
+
+    // issue the staging loads first: they overlap the scalar reductions below
+    constexpr int ND = DX * DY * DZ, NK = KX * KY * KZ;
+    constexpr int PD = (ND + 255) / 256, PK = (NK + 255) / 256;
+    T sv[PD], dv[PD], kv[PK];
+#pragma unroll
+    for (int j = 0; j < PD; ++j) {
+        const int q = threadIdx.x + 256 * j;
+        sv[j] = dv[j] = (T)0;
+        if (q < ND) {
+            const int zl = q % DZ, t = q / DZ;
+            const int yl = t % DY, xl = t / DY;
+            const int x = wrap_mod(x0 - 1 + xl, g.n0), y = wrap_mod(y0 - 1 + yl, g.n1), z = wrap_mod(z0 - 1 + zl, g.n2);
+            const int64_t idx = ((int64_t)x * g.n1 + y) * g.n2 + z;
+            sv[j] = s[idx];
+            if (CG) dv[j] = dold[idx];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < PK; ++j) {
+        const int q = threadIdx.x + 256 * j;
+        kv[j] = (T)0;
+        if (q < NK) {
+            const int zl = q % KZ, t = q / KZ;
+            const int yl = t % KY, xl = t / KY;
+            const int x = wrap_mod(x0 - 1 + xl, g.n0), y = wrap_mod(y0 - 1 + yl, g.n1), z = wrap_mod(z0 - 1 + zl, g.n2);
+            kv[j] = kappa[((int64_t)x * g.n1 + y) * g.n2 + z];
+        }
+    }
+    T beta = 0;
+    bool first = true;
+    if (CG) {
+        if (HEAD) {
+            if (head_check(it, slots)) return;
+        } else if (loop_ended(it.st, it.k)) {
+            return;
+        }
+        const int k = it.k;
+        const double gk = reduce_parts<OpSum>(part_rs, np_rs, slots);
+        const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+        if (lead) gam[k] = gk;
+        if (!(gk > 0.0) || !isfinite(gk)) {
+            if (lead) { it.st->status = 1; it.st->fail_iter = k; }
+            return;
+        }
+        first = (k == 0);
+        beta = first ? (T)0 : (T)(gk / gam[k - 1]);
+    }
+#pragma unroll
+    for (int j = 0; j < PD; ++j) {
+        const int q = threadIdx.x + 256 * j;
+        if (q < ND) Dl[q] = (CG && !first) ? sv[j] + beta * dv[j] : sv[j];
+    }
+#pragma unroll
+    for (int j = 0; j < PK; ++j) {
+        const int q = threadIdx.x + 256 * j;
+        if (q < NK) Kl[q] = kv[j];
+    }
+    __syncthreads();
+
+    const int tz = threadIdx.x % TZ, ty = threadIdx.x / TZ;
+    const int y = y0 + ty, z = z0 + tz;
+    const bool yz_ok = (y < g.n1) && (z < g.n2);
+    T dm[3][3], d0[3][3], dq[3][3], km[2][2], kp[2][2];
+#pragma unroll
+    for (int bb = 0; bb < 3; ++bb)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            dm[bb][c] = Dl[(0 * DY + ty + bb) * DZ + tz + c];
+            d0[bb][c] = Dl[(1 * DY + ty + bb) * DZ + tz + c];
+        }
+#pragma unroll
+    for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) km[bb][c] = Kl[(0 * KY + ty + bb) * KZ + tz + c];
+    double dot = 0.0;
+#pragma unroll
+    for (int xi = 0; xi < TX; ++xi) {
+#pragma unroll
+        for (int bb = 0; bb < 3; ++bb)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) dq[bb][c] = Dl[((xi + 2) * DY + ty + bb) * DZ + tz + c];
+#pragma unroll
+        for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) kp[bb][c] = Kl[((xi + 1) * KY + ty + bb) * KZ + tz + c];
+        const int x = x0 + xi;
+        if (yz_ok && x < g.n0) {
+            const T acc = stencil_node<T>(g, dm, d0, dq, km, kp);
+            const int64_t i = ((int64_t)x * g.n1 + y) * g.n2 + z;
+            p[i] = acc;
+            if (CG) {
+                dnew[i] = d0[1][1];
+                dot += (double)d0[1][1] * (double)acc;
+            }
+        }
+#pragma unroll
+        for (int bb = 0; bb < 3; ++bb)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                dm[bb][c] = d0[bb][c];
+                d0[bb][c] = dq[bb][c];
+            }
+#pragma unroll
+        for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) km[bb][c] = kp[bb][c];
+    }
+    if (CG) {
+        const double bd = block_reduce<OpSum>(dot, slots);
+        if (threadIdx.x == 0) part_dp[blockIdx.x] = bd;
+    }
+}
+
+// Tile shape for a grid: TZ covers the contiguous axis, TX = 1 for a single
+// voxel layer (2D problems), otherwise 4 (2 on small grids, for parallelism).
+struct TileChoice {
+    int tx, tz;
+    TileGeom geom;
+    int blocks;
+};
+
+inline TileChoice choose_tile(const Grid& g)
+{
+    TileChoice c;
+    c.tz = g.n[2] >= 48 ? 64 : (g.n[2] >= 24 ? 32 : 16);
+    const int ty = 256 / c.tz;
+    const int tiles_y = (g.n[1] + ty - 1) / ty, tiles_z = (g.n[2] + c.tz - 1) / c.tz;
+    if (g.n[0] == 1) c.tx = 1;
+    else {
+        c.tx = 4;
+        const int64_t t4 = (int64_t)((g.n[0] + 3) / 4) * tiles_y * tiles_z;
+        if (t4 < 256) c.tx = 2;
+    }
+    c.geom.tiles_y = tiles_y;
+    c.geom.tiles_z = tiles_z;
+    c.blocks = ((g.n[0] + c.tx - 1) / c.tx) * tiles_y * tiles_z;
+    return c;
+}
+
+template <typename T, bool CG, bool HEAD, int TX>
+inline void launch_tile_tx(const TileChoice& c, const GridDev& g, const T* kappa, const T* s, const T* dold, T* dnew,
+                           T* p, double* part_dp, const CgIter& it, const double* part_rs, int np_rs, double* gam,
+                           hipStream_t st)
+{
+    switch (c.tz) {
+        case 64:
+            hipLaunchKernelGGL((k_stencil_tile<T, TX, 64, CG, HEAD>), dim3(c.blocks), dim3(256), 0, st, g, c.geom,
+                               kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam);
+            break;
+        case 32:
+            hipLaunchKernelGGL((k_stencil_tile<T, TX, 32, CG, HEAD>), dim3(c.blocks), dim3(256), 0, st, g, c.geom,
+                               kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam);
+            break;
+        default:
+            hipLaunchKernelGGL((k_stencil_tile<T, TX, 16, CG, HEAD>), dim3(c.blocks), dim3(256), 0, st, g, c.geom,
+                               kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam);
+            break;
+    }
+}
+
+// Launches the tiled operator; returns the number of workgroups (= d.p partials).
+template <typename T, bool CG, bool HEAD>
+inline int launch_tile(const Grid& g, const T* kappa, const T* s, const T* dold, T* dnew, T* p, double* part_dp,
+                       const CgIter& it, const double* part_rs, int np_rs, double* gam, hipStream_t st)
+{
+    const TileChoice c = choose_tile(g);
+    if (c.tx == 1)
+        launch_tile_tx<T, CG, HEAD, 1>(c, g.dev, kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam, st);
+    else if (c.tx == 2)
+        launch_tile_tx<T, CG, HEAD, 2>(c, g.dev, kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam, st);
+    else
+        launch_tile_tx<T, CG, HEAD, 4>(c, g.dev, kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam, st);
+    return c.blocks;
+}
+
+}  // namespace unocg

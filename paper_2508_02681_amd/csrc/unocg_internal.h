@@ -125,6 +125,17 @@ struct CgState {
     int fail_iter;    // pass of a breakdown
 };
 
+// ---------------------------------------------------------------------------
+// UNO apply restricted to the learned modes (lowrank.hip)
+struct LowRankPlan;
+uno_status lowrank_create(const Grid& g, const FftPlan& fp, int M, double W, const std::vector<double>& cblock,
+                          LowRankPlan** out);
+void lowrank_destroy(LowRankPlan* p);
+int lowrank_rs_blocks(const LowRankPlan* p);
+uno_status lowrank_apply(const LowRankPlan* p, const double* r, double* s, const CgIter* it, int* np_rs,
+                         hipStream_t st);
+int fft_c2r_blocks(const Grid& g, const FftPlan& p);
+
 }  // namespace unocg
 
 // uno_precond layout (opaque to callers)
@@ -136,5 +147,14 @@ struct uno_precond {
     void* table;          // device half spectrum, scaled by 1/n, table_t
     double* table_host;   // unscaled Phi on the half spectrum
     void* spec;           // scratch spectrum (FP64 complex, nspec values)
+    unocg::LowRankPlan* lr;  // learned-mode passes (UNO tables only), or null
+    int path;             // UNO_PATH_*
+    int rs_blocks;        // most r.s partials any apply path writes
     int device;
 };
+
+// apply path of a preconditioner in FP64
+inline bool uno_use_lowrank(const uno_precond* p)
+{
+    return p->lr != nullptr && p->path != UNO_PATH_SPECTRAL;
+}
