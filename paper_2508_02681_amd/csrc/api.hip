@@ -342,7 +342,7 @@ uno_status uno_precond_create(const uno_grid* grid, int32_t M, const double* the
         }
     }
     p->rs_blocks = fft_c2r_blocks(g, p->plan);
-    if (p->lr && lowrank_rs_blocks(p->lr) > p->rs_blocks) p->rs_blocks = lowrank_rs_blocks(p->lr);
+    if (p->lr && lowrank_max_blocks(p->lr) > p->rs_blocks) p->rs_blocks = lowrank_max_blocks(p->lr);
     UNO_HIP(hipGetDevice(&p->device));
     *out = p;
     return UNO_OK;
@@ -401,7 +401,7 @@ uno_status uno_precond_apply(const uno_precond* p, const void* r, void* s, uno_d
     if (vec_t == UNO_F32 && p->table_t != UNO_F32) return UNO_ERR_ARG;
     if (vec_t == UNO_F64 && uno_use_lowrank(p)) {
         if (r == s) return UNO_ERR_ARG;  // the learned-mode passes read r after writing s
-        return lowrank_apply(p->lr, (const double*)r, (double*)s, nullptr, nullptr, S(stream));
+        return lowrank_apply(p->lr, (const double*)r, (double*)s, S(stream));
     }
     return uno_apply_passes(p->grid, p->plan, p->table, p->table_t, r, s, vec_t, p->spec, nullptr, nullptr, S(stream));
 }

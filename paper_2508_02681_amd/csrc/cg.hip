@@ -59,8 +59,16 @@ __device__ __forceinline__ double diag_at(const GridDev& g, const T* __restrict_
 
 // Initial partials: ||r_0||_inf and, for Jacobi / none, s_0 = P r_0 and r_0.s_0.
 // MODE 0: none (s is r), 1: Jacobi, 2: UNO (only the norm).
+// inverse of the assembled diagonal (Jacobi), formed once per solve
+__global__ void __launch_bounds__(kBlock) k_inv_diag(GridDev g, const double* __restrict__ kappa,
+                                                     double* __restrict__ dinv)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.n; i += (int64_t)gridDim.x * blockDim.x)
+        dinv[i] = 1.0 / diag_at(g, kappa, i);
+}
+
 template <int MODE>
-__global__ void __launch_bounds__(kBlock) k_cg_init(GridDev g, const double* __restrict__ kappa,
+__global__ void __launch_bounds__(kBlock) k_cg_init(GridDev g, const double* __restrict__ dinv,
                                                     const double* __restrict__ r, double* __restrict__ s,
                                                     double* __restrict__ part_rmax, double* __restrict__ part_rs,
                                                     CgState* st)
@@ -72,7 +80,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_init(GridDev g, const double* __r
         m = OpMax::apply(m, fabs(ri));
         if (MODE == 0) dt += ri * ri;
         if (MODE == 1) {
-            const double si = ri / diag_at(g, kappa, i);
+            const double si = ri * dinv[i];
             s[i] = si;
             dt += ri * si;
         }
@@ -94,7 +102,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_init(GridDev g, const double* __r
 // update of pass k.  MODE 0: none, 1: Jacobi (both also form s and r.s for
 // pass k + 1), 2: UNO.
 template <typename T, int MODE>
-__global__ void __launch_bounds__(kBlock) k_cg_update(GridDev g, const T* __restrict__ kappa, double* __restrict__ r,
+__global__ void __launch_bounds__(kBlock) k_cg_update(GridDev g, const T* __restrict__ dinv, double* __restrict__ r,
                                                       double* __restrict__ u, const T* __restrict__ d,
                                                       const T* __restrict__ p, T* __restrict__ s, CgIter it,
                                                       const double* __restrict__ part_dp, int np_dp,
@@ -102,8 +110,10 @@ __global__ void __launch_bounds__(kBlock) k_cg_update(GridDev g, const T* __rest
                                                       double* __restrict__ part_rs_next)
 {
     __shared__ double slots[kBlock / 64];
-    if (loop_ended(it.st, it.k)) return;
-    // the first element's operands are loaded before the d.p combination
+    // all loads first: state, d.p partials, gamma_k and the first element's operands
+    const StateLoad sl = load_state(it.st);
+    const double dp_share = load_share<OpSum>(part_dp, np_dp);
+    const double gk = gam[it.k];
     const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double r0 = 0.0, p0 = 0.0, u0 = 0.0, d0 = 0.0;
     if (i0 < g.n) {
@@ -112,12 +122,13 @@ __global__ void __launch_bounds__(kBlock) k_cg_update(GridDev g, const T* __rest
         u0 = u[i0];
         d0 = (double)d[i0];
     }
-    const double dp = reduce_parts<OpSum>(part_dp, np_dp, slots);
+    if (ended(sl, it.k)) return;
+    const double dp = combine_share<OpSum>(dp_share, slots);
     if (!(dp > 0.0) || !isfinite(dp)) {
         if (blockIdx.x == 0 && threadIdx.x == 0) { it.st->status = 1; it.st->fail_iter = it.k; }
         return;
     }
-    const double alpha = gam[it.k] / dp;
+    const double alpha = gk / dp;
     double m = 0.0, dt = 0.0;
     for (int64_t i = i0; i < g.n; i += (int64_t)gridDim.x * blockDim.x) {
         if (i != i0) {
@@ -132,7 +143,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_update(GridDev g, const T* __rest
         m = OpMax::apply(m, fabs(ri));
         if (MODE == 0) dt += ri * ri;
         if (MODE == 1) {
-            const T si = (T)(ri / diag_at(g, kappa, i));
+            const T si = (T)(ri * (double)dinv[i]);
             s[i] = si;
             dt += ri * (double)si;
         }
@@ -228,6 +239,7 @@ struct Workspace {
     int nbr = 0;              // workgroups of the streaming CG kernels
     int npart = 0;            // capacity of each partial buffer
     double *f = nullptr, *r = nullptr, *s = nullptr, *d[2] = {nullptr, nullptr}, *p = nullptr;
+    double* dinv = nullptr;   // inverse Jacobi diagonal of the current solve
     double* part = nullptr;   // 4 partial buffers: rmax, rs[2], dp
     double2* spec = nullptr;
     int64_t nspec = 0;
@@ -248,6 +260,7 @@ void ws_free(Workspace* w)
     (void)hipFree(w->d[0]);
     (void)hipFree(w->d[1]);
     (void)hipFree(w->p);
+    (void)hipFree(w->dinv);
     (void)hipFree(w->part);
     (void)hipFree(w->spec);
     (void)hipFree(w->state);
@@ -275,6 +288,7 @@ uno_status ws_get(const Grid& g, const FftPlan* plan, int extra_parts, int hist_
         bool ok = hipMalloc(&w->f, vb) == hipSuccess && hipMalloc(&w->r, vb) == hipSuccess &&
                   hipMalloc(&w->s, vb) == hipSuccess && hipMalloc(&w->d[0], vb) == hipSuccess &&
                   hipMalloc(&w->d[1], vb) == hipSuccess && hipMalloc(&w->p, vb) == hipSuccess &&
+                  hipMalloc(&w->dinv, vb) == hipSuccess &&
                   hipMalloc(&w->state, sizeof(CgState)) == hipSuccess &&
                   hipHostMalloc(&w->host_state, sizeof(CgState), hipHostMallocDefault) == hipSuccess;
         if (!ok) {
@@ -339,14 +353,16 @@ Parts parts_of(Workspace* w)
     return P;
 }
 
-CgIter iter_of(Workspace* w, const Parts& P, int k, double rtol, int hist_len)
+// np_update: workgroups of the update kernel (they write the ||r||_inf
+// partials read at the head of pass k > 0; pass 0 reads the init kernel's)
+CgIter iter_of(Workspace* w, const Parts& P, int k, double rtol, int hist_len, int np_update)
 {
     CgIter it;
     memset(&it, 0, sizeof(it));
     it.k = k;
     it.st = w->state;
     it.part_rmax = P.rmax;
-    it.np_rmax = w->nbr;
+    it.np_rmax = (k == 0) ? w->nbr : np_update;
     it.rtol = rtol;
     it.hist = w->hist;
     it.hist_len = hist_len;
@@ -364,15 +380,25 @@ static uno_status enqueue_pass(const Grid& g, Workspace* w, int kind, const uno_
     const int nb = w->nbr;
     double* dold = w->d[k & 1];
     double* dnew = w->d[(k + 1) & 1];
-    CgIter it = iter_of(w, P, k, rtol, hist_len);
     KTimer kt;
     const double* s = (kind == UNO_PREC_NONE) ? w->r : w->s;
     int np_rs = nb;
+    if (kind == UNO_PREC_UNO && uno_use_lowrank(pc)) {
+        // learned-mode flow: [B (head) + C] -> matvec -> [update + A of pass k+1]
+        CgIter it = iter_of(w, P, k, rtol, hist_len, lowrank_update_blocks(pc->lr));
+        uno_status e = lowrank_finish(pc->lr, w->r, w->s, &it, &np_rs, st);
+        if (e != UNO_OK) return e;
+        ktimer_begin(&kt, UNO_KT_MATVEC, st);
+        const int np_dp =
+            launch_tile<double, true, false>(g, kappa, s, dold, dnew, w->p, P.dp, it, P.rs[k & 1], np_rs, w->gam, st);
+        ktimer_end(&kt);
+        UNO_HIP(hipGetLastError());
+        return lowrank_update_forward(pc->lr, w->r, u, dnew, w->p, it, P.dp, np_dp, w->gam, P.rmax, st);
+    }
+    CgIter it = iter_of(w, P, k, rtol, hist_len, nb);
     if (kind == UNO_PREC_UNO) {
-        uno_status e = uno_use_lowrank(pc)
-                           ? lowrank_apply(pc->lr, w->r, w->s, &it, &np_rs, st)
-                           : uno_apply_passes(g, pc->plan, pc->table, pc->table_t, w->r, w->s, UNO_F64, w->spec, &it,
-                                              &np_rs, st);
+        uno_status e = uno_apply_passes(g, pc->plan, pc->table, pc->table_t, w->r, w->s, UNO_F64, w->spec, &it,
+                                        &np_rs, st);
         if (e != UNO_OK) return e;
     }
     ktimer_begin(&kt, UNO_KT_MATVEC, st);
@@ -386,13 +412,13 @@ static uno_status enqueue_pass(const Grid& g, Workspace* w, int kind, const uno_
     ktimer_begin(&kt, UNO_KT_UPDATE, st);
     double* rs_next = P.rs[(k + 1) & 1];
     if (kind == UNO_PREC_NONE)
-        hipLaunchKernelGGL((k_cg_update<double, 0>), dim3(nb), dim3(kBlock), 0, st, g.dev, kappa, w->r, u, dnew, w->p,
+        hipLaunchKernelGGL((k_cg_update<double, 0>), dim3(nb), dim3(kBlock), 0, st, g.dev, (const double*)w->dinv, w->r, u, dnew, w->p,
                            w->s, it, (const double*)P.dp, np_dp, (const double*)w->gam, P.rmax, rs_next);
     else if (kind == UNO_PREC_JACOBI)
-        hipLaunchKernelGGL((k_cg_update<double, 1>), dim3(nb), dim3(kBlock), 0, st, g.dev, kappa, w->r, u, dnew, w->p,
+        hipLaunchKernelGGL((k_cg_update<double, 1>), dim3(nb), dim3(kBlock), 0, st, g.dev, (const double*)w->dinv, w->r, u, dnew, w->p,
                            w->s, it, (const double*)P.dp, np_dp, (const double*)w->gam, P.rmax, rs_next);
     else
-        hipLaunchKernelGGL((k_cg_update<double, 2>), dim3(nb), dim3(kBlock), 0, st, g.dev, kappa, w->r, u, dnew, w->p,
+        hipLaunchKernelGGL((k_cg_update<double, 2>), dim3(nb), dim3(kBlock), 0, st, g.dev, (const double*)w->dinv, w->r, u, dnew, w->p,
                            w->s, it, (const double*)P.dp, np_dp, (const double*)w->gam, P.rmax, rs_next);
     ktimer_end(&kt);
     UNO_HIP(hipGetLastError());
@@ -420,16 +446,24 @@ uno_status pcg_run(const Grid& g, const double* kappa, const double* macro_load3
     if (e != UNO_OK) return e;
     hipLaunchKernelGGL(k_sub, dim3(nb), dim3(kBlock), 0, st, g.total, (const double*)w->f, (const double*)w->p, w->r);
     UNO_HIP(hipGetLastError());
+    const double* dinv = w->dinv;
     if (o->kind == UNO_PREC_NONE)
-        hipLaunchKernelGGL(k_cg_init<0>, dim3(nb), dim3(kBlock), 0, st, g.dev, kappa, w->r, w->s, P.rmax, P.rs[0],
+        hipLaunchKernelGGL(k_cg_init<0>, dim3(nb), dim3(kBlock), 0, st, g.dev, dinv, w->r, w->s, P.rmax, P.rs[0],
                            w->state);
-    else if (o->kind == UNO_PREC_JACOBI)
-        hipLaunchKernelGGL(k_cg_init<1>, dim3(nb), dim3(kBlock), 0, st, g.dev, kappa, w->r, w->s, P.rmax, P.rs[0],
+    else if (o->kind == UNO_PREC_JACOBI) {
+        hipLaunchKernelGGL(k_inv_diag, dim3(nb), dim3(kBlock), 0, st, g.dev, kappa, w->dinv);
+        hipLaunchKernelGGL(k_cg_init<1>, dim3(nb), dim3(kBlock), 0, st, g.dev, dinv, w->r, w->s, P.rmax, P.rs[0],
                            w->state);
-    else
-        hipLaunchKernelGGL(k_cg_init<2>, dim3(nb), dim3(kBlock), 0, st, g.dev, kappa, w->r, w->s, P.rmax, P.rs[0],
+    } else
+        hipLaunchKernelGGL(k_cg_init<2>, dim3(nb), dim3(kBlock), 0, st, g.dev, dinv, w->r, w->s, P.rmax, P.rs[0],
                            w->state);
     UNO_HIP(hipGetLastError());
+    const bool lowrank = pc && uno_use_lowrank(pc);
+    const int np_update = lowrank ? lowrank_update_blocks(pc->lr) : nb;
+    if (lowrank) {
+        e = lowrank_forward(pc->lr, w->r, st);  // transform of r_0 for the first pass
+        if (e != UNO_OK) return e;
+    }
 
     // passes in chunks; the host reads the state between chunks
     int k = 0;
@@ -442,7 +476,7 @@ uno_status pcg_run(const Grid& g, const double* kappa, const double* macro_load3
             e = enqueue_pass(g, w, o->kind, pc, kappa, u, k, o->rtol, hist_len, st);
             if (e != UNO_OK) return e;
         }
-        CgIter it = iter_of(w, P, k, o->rtol, hist_len);
+        CgIter it = iter_of(w, P, k, o->rtol, hist_len, np_update);
         hipLaunchKernelGGL(k_cg_check, dim3(1), dim3(kBlock), 0, st, it);
         UNO_HIP(hipGetLastError());
         UNO_HIP(hipMemcpyAsync(w->host_state, w->state, sizeof(CgState), hipMemcpyDeviceToHost, st));

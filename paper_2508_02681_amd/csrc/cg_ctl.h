@@ -31,12 +31,54 @@ __device__ __forceinline__ bool loop_ended(const CgState* st, int k)
     return st->status != 0 || st->done <= k;
 }
 
-// Convergence test at the head of pass k; true when the workgroup must exit.
-__device__ inline bool head_check(const CgIter& c, double* slots)
+// This thread's share of a partial array, combined with Op (loads only).
+template <class Op>
+__device__ __forceinline__ double load_share(const double* __restrict__ parts, int np)
 {
-    if (loop_ended(c.st, c.k)) return true;
-    const double rm = reduce_parts<OpMax>(c.part_rmax, c.np_rmax, slots);
-    const double tol = (c.k == 0) ? c.rtol * rm : c.st->tol_abs;
+    double v = Op::ident();
+    for (int i = threadIdx.x; i < np; i += blockDim.x) v = Op::apply(v, parts[i]);
+    return v;
+}
+
+// Block-wide combination of the per-thread shares; every thread gets it.
+template <class Op>
+__device__ __forceinline__ double combine_share(double v, double* slots)
+{
+    v = block_reduce<Op>(v, slots);
+    __syncthreads();
+    if (threadIdx.x == 0) slots[0] = v;
+    __syncthreads();
+    v = slots[0];
+    __syncthreads();
+    return v;
+}
+
+// Values a kernel of pass k reads from the loop state, loaded at entry
+// together with everything else so that all global loads overlap.
+struct StateLoad {
+    int done, status;
+    double tol_abs;
+};
+
+__device__ __forceinline__ StateLoad load_state(const CgState* st)
+{
+    StateLoad s;
+    s.done = st->done;
+    s.status = st->status;
+    s.tol_abs = st->tol_abs;
+    return s;
+}
+
+__device__ __forceinline__ bool ended(const StateLoad& s, int k) { return s.status != 0 || s.done <= k; }
+
+// Convergence test at the head of pass k from preloaded values (`share` is
+// this thread's share of the ||r_k||_inf partials); true when the workgroup
+// must exit.
+__device__ inline bool head_decide(const CgIter& c, const StateLoad& sl, double share, double* slots)
+{
+    if (ended(sl, c.k)) return true;
+    const double rm = combine_share<OpMax>(share, slots);
+    const double tol = (c.k == 0) ? c.rtol * rm : sl.tol_abs;
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
     if (lead) {
         if (c.k == 0) {
@@ -56,6 +98,14 @@ __device__ inline bool head_check(const CgIter& c, double* slots)
         return true;
     }
     return false;
+}
+
+// Convergence test at the head of pass k; true when the workgroup must exit.
+__device__ inline bool head_check(const CgIter& c, double* slots)
+{
+    const StateLoad sl = load_state(c.st);
+    const double share = load_share<OpMax>(c.part_rmax, c.np_rmax);
+    return head_decide(c, sl, share, slots);
 }
 
 }  // namespace unocg

@@ -44,30 +44,100 @@ __device__ __forceinline__ int mod_n(int64_t v, int n)
     return r < 0 ? r + n : r;
 }
 
-// Pass A: one workgroup per (x-slab, k_z chunk).
-__global__ void __launch_bounds__(256) k_lr_fwd(LowRankDev L, int kz_chunk, const double* __restrict__ r,
-                                                double2* __restrict__ G, CgIter it)
+// Pass A on the rows y0 .. y0+ny-1 of slab x: Z[y][kz] = sum_z r e^{-i kz z},
+// then the partial y-sum of these rows, Gp[x][chunk][ky][kz] =
+// sum_{y in rows} Z[y][kz] e^{-i ky y}; pass B adds the chunks in order.
+// UPDATE (inside CG): the rows are first updated, r <- r - alpha p,
+// u <- u + alpha d, and partials of ||r||_inf are written; the transformed
+// rows are then those of the new residual (for the next pass).
+template <bool UPDATE>
+__global__ void __launch_bounds__(256) k_lr_fwd(LowRankDev L, int ny_chunk, double* __restrict__ r,
+                                                double* __restrict__ u, const double* __restrict__ d,
+                                                const double* __restrict__ p, double2* __restrict__ Gp, CgIter it,
+                                                const double* __restrict__ part_dp, int np_dp,
+                                                const double* __restrict__ gam, double* __restrict__ part_rmax)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double slots[4];
-    if (it.st && head_check(it, slots)) return;
-    const int nchunks = (L.kzn + kz_chunk - 1) / kz_chunk;
-    const int x = blockIdx.x / nchunks;
-    const int kz0 = (blockIdx.x % nchunks) * kz_chunk;
-    const int nkz = min(kz_chunk, L.kzn - kz0);
-    double2* twz = (double2*)smem;          // n2
-    double2* twy = twz + L.n2;              // n1
-    double2* Z = twy + L.n1;                // n1 x nkz
-    for (int j = threadIdx.x; j < L.n2; j += blockDim.x) twz[j] = L.twz[j];
-    for (int j = threadIdx.x; j < L.n1; j += blockDim.x) twy[j] = L.twy[j];
+    const int nch = (L.n1 + ny_chunk - 1) / ny_chunk;
+    const int x = blockIdx.x / nch, ch = blockIdx.x % nch;
+    const int y0 = ch * ny_chunk;
+    const int ny = min(ny_chunk, L.n1 - y0);
+    double2* twz = (double2*)smem;                 // n2
+    double2* twy = twz + L.n2;                     // n1
+    double2* Z = twy + L.n1;                       // ny_chunk x kzn
+    double* R = (double*)(Z + ny_chunk * L.kzn);   // ny_chunk x n2
+    const int64_t base = ((int64_t)x * L.n1 + y0) * L.n2;
+    const int cnt = ny * L.n2;
+    double m = 0.0;
+    // all global loads first (state, partials, gamma, the first PF elements
+    // of the four vectors, twiddles); decisions come after
+    constexpr int PF = 4;
+    StateLoad sl;
+    double dp_share = 0.0, gk = 0.0;
+    double rv[PF], pv[PF], uv[PF], dv[PF];
+    if (UPDATE) {
+        sl = load_state(it.st);
+        dp_share = load_share<OpSum>(part_dp, np_dp);
+        gk = gam[it.k];
+    }
+#pragma unroll
+    for (int j = 0; j < PF; ++j) {
+        const int q = threadIdx.x + 256 * j;
+        rv[j] = pv[j] = uv[j] = dv[j] = 0.0;
+        if (q < cnt) {
+            rv[j] = r[base + q];
+            if (UPDATE) {
+                pv[j] = p[base + q];
+                uv[j] = u[base + q];
+                dv[j] = d[base + q];
+            }
+        }
+    }
+    for (int j = threadIdx.x; j < L.n2; j += 256) twz[j] = L.twz[j];
+    for (int j = threadIdx.x; j < L.n1; j += 256) twy[j] = L.twy[j];
+    if (UPDATE) {
+        if (ended(sl, it.k)) return;
+        const double dp = combine_share<OpSum>(dp_share, slots);
+        if (!(dp > 0.0) || !isfinite(dp)) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) { it.st->status = 1; it.st->fail_iter = it.k; }
+            return;
+        }
+        const double alpha = gk / dp;
+#pragma unroll
+        for (int j = 0; j < PF; ++j) {
+            const int q = threadIdx.x + 256 * j;
+            if (q < cnt) {
+                const double rn = rv[j] - alpha * pv[j];
+                r[base + q] = rn;
+                u[base + q] = uv[j] + alpha * dv[j];
+                R[q] = rn;
+                m = OpMax::apply(m, fabs(rn));
+            }
+        }
+        for (int q = threadIdx.x + 256 * PF; q < cnt; q += 256) {
+            const int64_t i = base + q;
+            const double rn = r[i] - alpha * p[i];
+            r[i] = rn;
+            u[i] += alpha * d[i];
+            R[q] = rn;
+            m = OpMax::apply(m, fabs(rn));
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < PF; ++j) {
+            const int q = threadIdx.x + 256 * j;
+            if (q < cnt) R[q] = rv[j];
+        }
+        for (int q = threadIdx.x + 256 * PF; q < cnt; q += 256) R[q] = r[base + q];
+    }
     __syncthreads();
-    const double* slab = r + (int64_t)x * L.n1 * L.n2;
-    // Z[y][kz] = sum_z r(x, y, z) exp(-2 pi i kz z / n2)
-    for (int q = threadIdx.x; q < L.n1 * nkz; q += blockDim.x) {
-        const int y = q / nkz, kz = kz0 + q % nkz;
-        const double* row = slab + (int64_t)y * L.n2;
+    for (int q = threadIdx.x; q < ny * L.kzn; q += 256) {
+        const int yl = q / L.kzn, kz = q % L.kzn;
+        const double* row = R + yl * L.n2;
         double re = 0.0, im = 0.0;
         int t = 0;
+#pragma unroll 8
         for (int z = 0; z < L.n2; ++z) {
             const double v = row[z];
             const double2 w = twz[t];
@@ -79,46 +149,67 @@ __global__ void __launch_bounds__(256) k_lr_fwd(LowRankDev L, int kz_chunk, cons
         Z[q] = make_double2(re, im);
     }
     __syncthreads();
-    // G[x][ky][kz] = sum_y Z[y][kz] exp(-2 pi i ky y / n1), ky in [-m, m]
-    for (int q = threadIdx.x; q < L.kyn * nkz; q += blockDim.x) {
-        const int kyi = q / nkz, kzl = q % nkz;
-        const int ky = kyi - L.m;
-        const int step = mod_n(ky, L.n1);
+    const int plane = L.kyn * L.kzn;
+    for (int q = threadIdx.x; q < plane; q += 256) {
+        const int kyi = q / L.kzn, kz = q % L.kzn;
+        const int step = mod_n(kyi - L.m, L.n1);
+        int t = mod_n((int64_t)(kyi - L.m) * y0, L.n1);
         double re = 0.0, im = 0.0;
-        int t = 0;
-        for (int y = 0; y < L.n1; ++y) {
-            const double2 a = Z[y * nkz + kzl];
+#pragma unroll 4
+        for (int yl = 0; yl < ny; ++yl) {
+            const double2 a = Z[yl * L.kzn + kz];
             const double2 w = twy[t];
             re += a.x * w.x - a.y * w.y;
             im += a.x * w.y + a.y * w.x;
             t += step;
             if (t >= L.n1) t -= L.n1;
         }
-        G[((int64_t)x * L.kyn + kyi) * L.kzn + kz0 + kzl] = make_double2(re, im);
+        Gp[((int64_t)x * nch + ch) * plane + q] = make_double2(re, im);
+    }
+    if (UPDATE) {
+        const double bm = block_reduce<OpMax>(m, slots);
+        if (threadIdx.x == 0) part_rmax[blockIdx.x] = bm;
     }
 }
 
-// Pass B: one wavefront per (k_y, k_z) column.
-__global__ void __launch_bounds__(64) k_lr_mid(LowRankDev L, const double* __restrict__ C,
-                                               const double2* __restrict__ G, double2* __restrict__ H, CgIter it)
+// Pass B: one wavefront per (k_y, k_z) column: add the row-chunk partials,
+// transform along x, multiply by the table, transform back.  Inside CG it is
+// the first kernel of a pass and runs the convergence test.
+__global__ void __launch_bounds__(64) k_lr_mid(LowRankDev L, int nch, const double* __restrict__ C,
+                                               const double2* __restrict__ Gp, double2* __restrict__ H, CgIter it)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    if (it.st && loop_ended(it.st, it.k)) return;
+    __shared__ double slots[4];
     const int col = blockIdx.x;  // ky index * kzn + kz
     const int plane = L.kyn * L.kzn;
     double2* twx = (double2*)smem;  // n0
     double2* gx = twx + L.n0;       // n0
     double2* X = gx + L.n0;         // kxn
+    // loads first: state and ||r||_inf partials (head of the CG pass), the
+    // row-chunk partials of this column, twiddles and the table entries
+    StateLoad sl;
+    double share = 0.0;
+    if (it.st) {
+        sl = load_state(it.st);
+        share = load_share<OpMax>(it.part_rmax, it.np_rmax);
+    }
     for (int j = threadIdx.x; j < L.n0; j += blockDim.x) {
         twx[j] = L.twx[j];
-        gx[j] = G[(int64_t)j * plane + col];
+        double re = 0.0, im = 0.0;
+        for (int c = 0; c < nch; ++c) {
+            const double2 a = Gp[((int64_t)j * nch + c) * plane + col];
+            re += a.x;
+            im += a.y;
+        }
+        gx[j] = make_double2(re, im);
     }
+    if (it.st && head_decide(it, sl, share, slots)) return;
     __syncthreads();
     for (int kxi = threadIdx.x; kxi < L.kxn; kxi += blockDim.x) {
-        const int kx = kxi - L.mx;
-        const int step = mod_n(kx, L.n0);
+        const int step = mod_n(kxi - L.mx, L.n0);
         double re = 0.0, im = 0.0;
         int t = 0;
+#pragma unroll 8
         for (int x = 0; x < L.n0; ++x) {
             const double2 a = gx[x];
             const double2 w = twx[t];
@@ -132,13 +223,16 @@ __global__ void __launch_bounds__(64) k_lr_mid(LowRankDev L, const double* __res
     }
     __syncthreads();
     for (int x = threadIdx.x; x < L.n0; x += blockDim.x) {
+        const int step = mod_n(x, L.n0);
+        int t = mod_n((int64_t)(-L.mx) * x, L.n0);
         double re = 0.0, im = 0.0;
         for (int kxi = 0; kxi < L.kxn; ++kxi) {
-            const int kx = kxi - L.mx;
-            const double2 w = twx[mod_n((int64_t)kx * x, L.n0)];  // conj gives exp(+i ...)
+            const double2 w = twx[t];  // conj(w) = exp(+2 pi i kx x / n0)
             const double2 a = X[kxi];
             re += a.x * w.x + a.y * w.y;
             im += a.y * w.x - a.x * w.y;
+            t += step;
+            if (t >= L.n0) t -= L.n0;
         }
         H[(int64_t)x * plane + col] = make_double2(re, im);
     }
@@ -151,7 +245,6 @@ __global__ void __launch_bounds__(256) k_lr_inv(LowRankDev L, int y_chunk, const
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double slots[4];
-    if (CG && loop_ended(it.st, it.k)) return;
     const int nch = (L.n1 + y_chunk - 1) / y_chunk;
     const int x = blockIdx.x / nch;
     const int y0 = (blockIdx.x % nch) * y_chunk;
@@ -161,31 +254,47 @@ __global__ void __launch_bounds__(256) k_lr_inv(LowRankDev L, int y_chunk, const
     double2* twy = twz + L.n2;           // n1
     double2* Hs = twy + L.n1;            // kyn x kzn
     double2* V = Hs + plane;             // ny x kzn
+    // loads first: state, the coefficient plane, twiddles and this thread's r
+    StateLoad sl;
+    if (CG) sl = load_state(it.st);
+    const int cnt = ny * L.n2;
+    const int64_t base = ((int64_t)x * L.n1 + y0) * L.n2;
+    constexpr int PF = 4;
+    double rv[PF];
+#pragma unroll
+    for (int j = 0; j < PF; ++j) {
+        const int q = threadIdx.x + 256 * j;
+        rv[j] = (q < cnt) ? r[base + q] : 0.0;
+    }
     for (int j = threadIdx.x; j < L.n2; j += blockDim.x) twz[j] = L.twz[j];
     for (int j = threadIdx.x; j < L.n1; j += blockDim.x) twy[j] = L.twy[j];
     for (int j = threadIdx.x; j < plane; j += blockDim.x) Hs[j] = H[(int64_t)x * plane + j];
+    if (CG && ended(sl, it.k)) return;
     __syncthreads();
     // V[y][kz] = sum_ky H[x][ky][kz] exp(+2 pi i ky y / n1)
     for (int q = threadIdx.x; q < ny * L.kzn; q += blockDim.x) {
         const int yl = q / L.kzn, kz = q % L.kzn;
         const int y = y0 + yl;
+        const int step = mod_n(y, L.n1);
+        int t = mod_n((int64_t)(-L.m) * y, L.n1);
         double re = 0.0, im = 0.0;
         for (int kyi = 0; kyi < L.kyn; ++kyi) {
-            const int ky = kyi - L.m;
-            const double2 w = twy[mod_n((int64_t)ky * y, L.n1)];
+            const double2 w = twy[t];
             const double2 a = Hs[kyi * L.kzn + kz];
             re += a.x * w.x + a.y * w.y;
             im += a.y * w.x - a.x * w.y;
+            t += step;
+            if (t >= L.n1) t -= L.n1;
         }
         V[q] = make_double2(re, im);
     }
     __syncthreads();
     // s = W r + Re sum_kz V[y][kz] exp(+2 pi i kz z / n2)
-    double acc = 0.0;
-    for (int q = threadIdx.x; q < ny * L.n2; q += blockDim.x) {
+    auto node = [&](int q, double rq) -> double {
         const int yl = q / L.n2, z = q % L.n2;
         double c = 0.0;
         int t = 0;
+#pragma unroll 4
         for (int kz = 0; kz < L.kzn; ++kz) {
             const double2 w = twz[t];
             const double2 a = V[yl * L.kzn + kz];
@@ -193,12 +302,17 @@ __global__ void __launch_bounds__(256) k_lr_inv(LowRankDev L, int y_chunk, const
             t += z;
             if (t >= L.n2) t -= L.n2;
         }
-        const int64_t i = ((int64_t)x * L.n1 + y0 + yl) * L.n2 + z;
-        const double rv = r[i];
-        const double sv = L.W * rv + c;
-        s[i] = sv;
-        if (CG) acc += rv * sv;
+        const double sv = L.W * rq + c;
+        s[base + q] = sv;
+        return rq * sv;
+    };
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < PF; ++j) {
+        const int q = threadIdx.x + 256 * j;
+        if (q < cnt) acc += node(q, rv[j]);
     }
+    for (int q = threadIdx.x + 256 * PF; q < cnt; q += 256) acc += node(q, r[base + q]);
     if (CG) {
         const double b = block_reduce<OpSum>(acc, slots);
         if (threadIdx.x == 0) it.part_rs[blockIdx.x] = b;
@@ -211,13 +325,13 @@ __global__ void __launch_bounds__(256) k_lr_inv(LowRankDev L, int y_chunk, const
 struct LowRankPlan {
     LowRankDev dev;
     double* table;    // kxn x kyn x kzn, w(kz) C(k) / n
-    double2* G;       // n0 x kyn x kzn
-    double2* H;
-    int kz_chunk, y_chunk;
+    double2* Gp;      // n0 x nch_a x kyn x kzn row-chunk partials
+    double2* H;       // n0 x kyn x kzn
+    int ya, yc;       // rows per workgroup of passes A and C
+    int nch_a;
     int blocks_a, blocks_c;
+    size_t lds_a, lds_b, lds_c;
 };
-
-static int pick_chunk(int total, int per_slab_target) { return (total + per_slab_target - 1) / per_slab_target; }
 
 uno_status lowrank_create(const Grid& g, const FftPlan& fp, int M, double W, const std::vector<double>& cblock,
                           LowRankPlan** out)
@@ -238,27 +352,31 @@ uno_status lowrank_create(const Grid& g, const FftPlan& fp, int M, double W, con
     L.twy = fp.ax[1].tw64;
     L.twz = fp.ax[2].tw64;
     const int64_t nb = (int64_t)L.kxn * L.kyn * L.kzn;
-    const int64_t ng = (int64_t)L.n0 * L.kyn * L.kzn;
     if ((int64_t)cblock.size() != nb) { delete p; return UNO_ERR_ARG; }
-    // about four workgroups per slab in passes A and C
-    p->kz_chunk = pick_chunk(L.kzn, g.n[0] >= 64 ? 4 : (g.n[0] >= 16 ? 8 : 16));
-    p->y_chunk = pick_chunk(L.n1, g.n[0] >= 64 ? 4 : (g.n[0] >= 16 ? 8 : 16));
-    if (p->kz_chunk < 1) p->kz_chunk = 1;
-    if (p->y_chunk < 1) p->y_chunk = 1;
-    const size_t lds_a = sizeof(double2) * ((size_t)L.n2 + L.n1 + (size_t)L.n1 * p->kz_chunk);
-    const size_t lds_c = sizeof(double2) * ((size_t)L.n2 + L.n1 + (size_t)L.kyn * L.kzn + (size_t)p->y_chunk * L.kzn);
-    const size_t lds_b = sizeof(double2) * (2 * (size_t)L.n0 + L.kxn);
-    if (lds_a > 60 * 1024 || lds_b > 60 * 1024 || lds_c > 60 * 1024) { delete p; return UNO_ERR_SHAPE; }
-    if (hipMalloc(&p->table, sizeof(double) * nb) != hipSuccess || hipMalloc(&p->G, sizeof(double2) * ng) != hipSuccess ||
-        hipMalloc(&p->H, sizeof(double2) * ng) != hipSuccess) {
+    // rows per workgroup: about 1024 nodes, so the streaming part of pass A
+    // (the CG update) and pass C spread over n / 1024 workgroups
+    int rows = 1024 / L.n2;
+    if (rows < 1) rows = 1;
+    if (rows > L.n1) rows = L.n1;
+    p->ya = p->yc = rows;
+    p->nch_a = (L.n1 + p->ya - 1) / p->ya;
+    p->blocks_a = L.n0 * p->nch_a;
+    p->blocks_c = L.n0 * ((L.n1 + p->yc - 1) / p->yc);
+    const int plane = L.kyn * L.kzn;
+    p->lds_a = sizeof(double2) * ((size_t)L.n2 + L.n1 + (size_t)p->ya * L.kzn) + sizeof(double) * (size_t)p->ya * L.n2;
+    p->lds_b = sizeof(double2) * (2 * (size_t)L.n0 + L.kxn);
+    p->lds_c = sizeof(double2) * ((size_t)L.n2 + L.n1 + (size_t)plane + (size_t)p->yc * L.kzn);
+    if (p->lds_a > 60 * 1024 || p->lds_b > 60 * 1024 || p->lds_c > 60 * 1024) { delete p; return UNO_ERR_SHAPE; }
+    const int64_t ngp = (int64_t)L.n0 * p->nch_a * plane;
+    const int64_t nh = (int64_t)L.n0 * plane;
+    if (hipMalloc(&p->table, sizeof(double) * nb) != hipSuccess ||
+        hipMalloc(&p->Gp, sizeof(double2) * ngp) != hipSuccess || hipMalloc(&p->H, sizeof(double2) * nh) != hipSuccess) {
         (void)hipFree(p->table);
-        (void)hipFree(p->G);
+        (void)hipFree(p->Gp);
         delete p;
         return UNO_ERR_NOMEM;
     }
     UNO_HIP(hipMemcpy(p->table, cblock.data(), sizeof(double) * nb, hipMemcpyHostToDevice));
-    p->blocks_a = L.n0 * ((L.kzn + p->kz_chunk - 1) / p->kz_chunk);
-    p->blocks_c = L.n0 * ((L.n1 + p->y_chunk - 1) / p->y_chunk);
     *out = p;
     return UNO_OK;
 }
@@ -267,50 +385,76 @@ void lowrank_destroy(LowRankPlan* p)
 {
     if (!p) return;
     (void)hipFree(p->table);
-    (void)hipFree(p->G);
+    (void)hipFree(p->Gp);
     (void)hipFree(p->H);
     delete p;
 }
 
-int lowrank_rs_blocks(const LowRankPlan* p) { return p->blocks_c; }
+int lowrank_max_blocks(const LowRankPlan* p) { return p->blocks_a > p->blocks_c ? p->blocks_a : p->blocks_c; }
+int lowrank_update_blocks(const LowRankPlan* p) { return p->blocks_a; }
 
-uno_status lowrank_apply(const LowRankPlan* p, const double* r, double* s, const CgIter* itp, int* np_rs,
-                         hipStream_t st)
+static CgIter no_iter()
 {
-    const LowRankDev& L = p->dev;
     CgIter it;
     memset(&it, 0, sizeof(it));
-    if (itp) it = *itp;
+    return it;
+}
+
+// pass A on r (no update); also the initial transform of the CG loop
+uno_status lowrank_forward(const LowRankPlan* p, const double* r, hipStream_t st)
+{
     KTimer kt;
-    {
-        size_t sh = sizeof(double2) * ((size_t)L.n2 + L.n1 + (size_t)L.n1 * p->kz_chunk);
-        ktimer_begin(&kt, UNO_KT_FFT_FWD, st);
-        hipLaunchKernelGGL(k_lr_fwd, dim3(p->blocks_a), dim3(256), sh, st, L, p->kz_chunk, r, p->G, it);
-        ktimer_end(&kt);
-        UNO_HIP(hipGetLastError());
-    }
-    {
-        size_t sh = sizeof(double2) * (2 * (size_t)L.n0 + L.kxn);
-        ktimer_begin(&kt, UNO_KT_FFT_MID, st);
-        hipLaunchKernelGGL(k_lr_mid, dim3(L.kyn * L.kzn), dim3(64), sh, st, L, (const double*)p->table,
-                           (const double2*)p->G, p->H, it);
-        ktimer_end(&kt);
-        UNO_HIP(hipGetLastError());
-    }
-    {
-        size_t sh = sizeof(double2) * ((size_t)L.n2 + L.n1 + (size_t)L.kyn * L.kzn + (size_t)p->y_chunk * L.kzn);
-        ktimer_begin(&kt, UNO_KT_FFT_INV, st);
-        if (itp)
-            hipLaunchKernelGGL(k_lr_inv<true>, dim3(p->blocks_c), dim3(256), sh, st, L, p->y_chunk, r,
-                               (const double2*)p->H, s, it);
-        else
-            hipLaunchKernelGGL(k_lr_inv<false>, dim3(p->blocks_c), dim3(256), sh, st, L, p->y_chunk, r,
-                               (const double2*)p->H, s, it);
-        ktimer_end(&kt);
-        UNO_HIP(hipGetLastError());
-    }
+    ktimer_begin(&kt, UNO_KT_FFT_FWD, st);
+    hipLaunchKernelGGL(k_lr_fwd<false>, dim3(p->blocks_a), dim3(256), p->lds_a, st, p->dev, p->ya, (double*)r,
+                       (double*)nullptr, (const double*)nullptr, (const double*)nullptr, p->Gp, no_iter(),
+                       (const double*)nullptr, 0, (const double*)nullptr, (double*)nullptr);
+    ktimer_end(&kt);
+    return hip_status(hipGetLastError());
+}
+
+// CG update of pass k fused with pass A of pass k + 1
+uno_status lowrank_update_forward(const LowRankPlan* p, double* r, double* u, const double* d, const double* pv,
+                                  const CgIter& it, const double* part_dp, int np_dp, const double* gam,
+                                  double* part_rmax, hipStream_t st)
+{
+    KTimer kt;
+    ktimer_begin(&kt, UNO_KT_UPDATE, st);
+    hipLaunchKernelGGL(k_lr_fwd<true>, dim3(p->blocks_a), dim3(256), p->lds_a, st, p->dev, p->ya, r, u, d, pv, p->Gp,
+                       it, part_dp, np_dp, gam, part_rmax);
+    ktimer_end(&kt);
+    return hip_status(hipGetLastError());
+}
+
+// passes B and C (B tests convergence inside CG); C writes s and r.s partials
+uno_status lowrank_finish(const LowRankPlan* p, const double* r, double* s, const CgIter* itp, int* np_rs,
+                          hipStream_t st)
+{
+    const LowRankDev& L = p->dev;
+    const CgIter it = itp ? *itp : no_iter();
+    KTimer kt;
+    ktimer_begin(&kt, UNO_KT_FFT_MID, st);
+    hipLaunchKernelGGL(k_lr_mid, dim3(L.kyn * L.kzn), dim3(64), p->lds_b, st, L, p->nch_a, (const double*)p->table,
+                       (const double2*)p->Gp, p->H, it);
+    ktimer_end(&kt);
+    UNO_HIP(hipGetLastError());
+    ktimer_begin(&kt, UNO_KT_FFT_INV, st);
+    if (itp)
+        hipLaunchKernelGGL(k_lr_inv<true>, dim3(p->blocks_c), dim3(256), p->lds_c, st, L, p->yc, r,
+                           (const double2*)p->H, s, it);
+    else
+        hipLaunchKernelGGL(k_lr_inv<false>, dim3(p->blocks_c), dim3(256), p->lds_c, st, L, p->yc, r,
+                           (const double2*)p->H, s, it);
+    ktimer_end(&kt);
+    UNO_HIP(hipGetLastError());
     if (np_rs) *np_rs = p->blocks_c;
     return UNO_OK;
+}
+
+uno_status lowrank_apply(const LowRankPlan* p, const double* r, double* s, hipStream_t st)
+{
+    uno_status e = lowrank_forward(p, r, st);
+    if (e != UNO_OK) return e;
+    return lowrank_finish(p, r, s, nullptr, nullptr, st);
 }
 
 }  // namespace unocg

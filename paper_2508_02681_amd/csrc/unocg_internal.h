@@ -131,9 +131,15 @@ struct LowRankPlan;
 uno_status lowrank_create(const Grid& g, const FftPlan& fp, int M, double W, const std::vector<double>& cblock,
                           LowRankPlan** out);
 void lowrank_destroy(LowRankPlan* p);
-int lowrank_rs_blocks(const LowRankPlan* p);
-uno_status lowrank_apply(const LowRankPlan* p, const double* r, double* s, const CgIter* it, int* np_rs,
-                         hipStream_t st);
+int lowrank_max_blocks(const LowRankPlan* p);
+int lowrank_update_blocks(const LowRankPlan* p);
+uno_status lowrank_apply(const LowRankPlan* p, const double* r, double* s, hipStream_t st);
+uno_status lowrank_forward(const LowRankPlan* p, const double* r, hipStream_t st);
+uno_status lowrank_update_forward(const LowRankPlan* p, double* r, double* u, const double* d, const double* pv,
+                                  const CgIter& it, const double* part_dp, int np_dp, const double* gam,
+                                  double* part_rmax, hipStream_t st);
+uno_status lowrank_finish(const LowRankPlan* p, const double* r, double* s, const CgIter* it, int* np_rs,
+                          hipStream_t st);
 int fft_c2r_blocks(const Grid& g, const FftPlan& p);
 
 }  // namespace unocg
