@@ -143,27 +143,27 @@ def main():
 
     sols = torch.zeros((3,) + SHAPE, dtype=torch.float64, device=dev)
 
-    def step(i, kind, precond):
+    def step(i, kind, precond, **kw):
         k = kap_test[i % len(kap_test)]
         sols.zero_()
         its = []
         for j, g in enumerate(LOADS):
             _, info = uno.pcg_solve(k, macro_load=g, u=sols[j], kind=kind, precond=precond, rtol=RTOL,
-                                    max_iter=50000)
+                                    max_iter=50000, **kw)
             if not info["converged"]:
                 raise RuntimeError("solve did not converge: %s" % info)
             its.append(info["iters"])
         kb = uno.effective_tensor(k, LOADS, sols)
         return its, kb
 
-    def timed(kind, precond, steps, warmup):
+    def timed(kind, precond, steps, warmup, **kw):
         for i in range(warmup):
-            step(i, kind, precond)
+            step(i, kind, precond, **kw)
         torch.cuda.synchronize()
         t = time.perf_counter()
         all_its, kbs = [], []
         for i in range(steps):
-            its, kb = step(i, kind, precond)
+            its, kb = step(i, kind, precond, **kw)
             all_its += its
             kbs.append(kb)
         torch.cuda.synchronize()
@@ -181,6 +181,19 @@ def main():
     jac_t_solve = dtj / len(itsj) * 1e3
     jac_rate = n_dof * sum(itsj) / dtj
     log("Jac-CG: %.1f passes/solve, %.3e DOF*it/s, %.3f ms per solve" % (np.mean(itsj), jac_rate, jac_t_solve))
+
+    # ---------------- mixed precision: FP32 operator / preconditioner ----------------
+    f32 = dict(op_dtype=torch.float32, prec_dtype=torch.float32)
+    nmix = max(1, min(args.steps, 4))
+    dtm, itsm, kbm = timed("uno", prec, nmix, 1, **f32)
+    kb_err = max(float(np.abs(a - b).max() / np.abs(b).max()) for a, b in zip(kbm, kbs[:nmix]))
+    log("UNO-CG FP32 op/prec: %.1f passes/solve, %.3f ms per solve, kappa_bar rel diff vs FP64 %.1e" %
+        (np.mean(itsm), dtm / len(itsm) * 1e3, kb_err))
+    prec_bf16 = uno.UnoPrecond.create(SHAPE, M, theta, table_dtype=torch.bfloat16)
+    dtb, itsb, kbb = timed("uno", prec_bf16, nmix, 1, **f32)
+    kb_err_b = max(float(np.abs(a - b).max() / np.abs(b).max()) for a, b in zip(kbb, kbs[:nmix]))
+    log("UNO-CG BF16 table: %.1f passes/solve, %.3f ms per solve, kappa_bar rel diff %.1e" %
+        (np.mean(itsb), dtb / len(itsb) * 1e3, kb_err_b))
 
     # ---------------- FANS (reference-medium preconditioner) for context ----------------
     pf = uno.UnoPrecond.fans(SHAPE, 0.5 * (cfg["k_matrix"] + cfg["k_incl"]))
@@ -250,6 +263,10 @@ def main():
         "uno_cg": {"passes_mean": float(np.mean(its)), "ms_per_solve": uno_t_solve, "dof_iters_per_s": value},
         "jac_cg": {"passes_mean": float(np.mean(itsj)), "ms_per_solve": jac_t_solve, "dof_iters_per_s": jac_rate},
         "fans_cg": {"passes_mean": float(np.mean(itsf)), "ms_per_solve": dtf / len(itsf) * 1e3},
+        "uno_cg_fp32": {"passes_mean": float(np.mean(itsm)), "ms_per_solve": dtm / len(itsm) * 1e3,
+                        "kappa_bar_rel_diff_vs_fp64": kb_err},
+        "uno_cg_bf16_table": {"passes_mean": float(np.mean(itsb)), "ms_per_solve": dtb / len(itsb) * 1e3,
+                              "kappa_bar_rel_diff_vs_fp64": kb_err_b},
         "time_to_tol_speedup_uno_vs_jac": jac_t_solve / uno_t_solve,
         "kappa_bar_first": np.round(kbs[0], 6).tolist(),
         "roofline": roofline,

@@ -98,9 +98,10 @@ typedef struct uno_precond uno_precond; /* opaque; owns its device table and scr
  *            so that the output is real.
  * Requires 2M+1 <= n[b] on every axis.  The safety check of Sec. 4.2.4 is
  * run on the host: every Phi(k), k != 0, must exceed eps_spd, else
- * UNO_ERR_NOT_SPD.  table_t: UNO_F64, UNO_F32 or UNO_BF16 storage of the
- * table (arithmetic in the vector precision of each apply).  Allocates
- * device memory on the current device; synchronous. */
+ * UNO_ERR_NOT_SPD.  table_t (UNO_F64, UNO_F32 or UNO_BF16): precision the
+ * table values are rounded to (BF16: 8-bit significand, round to nearest
+ * even) before the check; applies compute in the vector precision.
+ * Allocates device memory on the current device; synchronous. */
 uno_status uno_precond_create(const uno_grid *grid, int32_t M, const double *theta, int64_t ntheta,
                               double eps_spd, uno_dtype table_t, uno_precond **out);
 
@@ -140,8 +141,10 @@ typedef struct {
     const uno_precond *uno;  /* required for UNO_PREC_UNO */
     double rtol;             /* stop when ||r||_inf <= rtol ||r_0||_inf */
     int32_t max_iter;        /* > 0 */
-    uno_dtype op_t;          /* precision of the operator apply: UNO_F64 or UNO_F32 */
-    uno_dtype prec_t;        /* precision of the preconditioner apply: UNO_F64 or UNO_F32 */
+    uno_dtype op_t;          /* operator apply: UNO_F64, or UNO_F32 (with prec_t = UNO_F32) */
+    uno_dtype prec_t;        /* preconditioner apply: UNO_F64, or UNO_F32 (with op_t = UNO_F32);
+                                FP32 mode keeps r, u, all reductions and the stop test in FP64
+                                and needs, for UNO, the learned-mode passes (uno_precond_set_path) */
     int32_t graph_chunk;     /* iterations per host check; 0 = adaptive */
 } uno_solve_opts;
 

@@ -240,11 +240,31 @@ static void entry_mode(const Grid& g, int ix, int iy, int ikz, int* k)
     }
 }
 
-static uno_status precond_finish(uno_precond* p, const std::vector<double>& phi, double eps_spd, uno_dtype table_t,
+// value rounded to the precision the table is kept in (BF16: 8-bit
+// significand, round to nearest even, like a bfloat16 store)
+static double round_to(double v, uno_dtype t)
+{
+    if (t == UNO_F64) return v;
+    float f = (float)v;
+    if (t == UNO_F32) return (double)f;
+    uint32_t b;
+    memcpy(&b, &f, 4);
+    if ((b & 0x7f800000u) != 0x7f800000u) {  // finite
+        const uint32_t lsb = (b >> 16) & 1u;
+        b += 0x7fffu + lsb;
+    }
+    b &= 0xffff0000u;
+    memcpy(&f, &b, 4);
+    return (double)f;
+}
+
+static uno_status precond_finish(uno_precond* p, std::vector<double>& phi, double eps_spd, uno_dtype table_t,
                                  bool check)
 {
     const Grid& g = p->grid;
     const int64_t ns = p->plan.nspec;
+    if (table_t != UNO_F64 && table_t != UNO_F32 && table_t != UNO_BF16) return UNO_ERR_ARG;
+    for (int64_t l = 0; l < ns; ++l) phi[l] = round_to(phi[l], table_t);
     if (check) {
         for (int64_t l = 1; l < ns; ++l) {
             // the zero mode is the only entry allowed below eps (it is 0)
@@ -256,19 +276,16 @@ static uno_status precond_finish(uno_precond* p, const std::vector<double>& phi,
     memcpy(p->table_host, phi.data(), sizeof(double) * ns);
     const double inv_n = 1.0 / (double)g.total;
     p->table_t = table_t;
-    if (table_t == UNO_F64) {
-        std::vector<double> sc(ns);
-        for (int64_t l = 0; l < ns; ++l) sc[l] = phi[l] * inv_n;
-        if (hipMalloc(&p->table, sizeof(double) * ns) != hipSuccess) return UNO_ERR_NOMEM;
-        UNO_HIP(hipMemcpy(p->table, sc.data(), sizeof(double) * ns, hipMemcpyHostToDevice));
-    } else if (table_t == UNO_F32) {
-        std::vector<float> sc(ns);
-        for (int64_t l = 0; l < ns; ++l) sc[l] = (float)(phi[l] * inv_n);
-        if (hipMalloc(&p->table, sizeof(float) * ns) != hipSuccess) return UNO_ERR_NOMEM;
-        UNO_HIP(hipMemcpy(p->table, sc.data(), sizeof(float) * ns, hipMemcpyHostToDevice));
-    } else {
-        return UNO_ERR_ARG;
+    std::vector<double> sc(ns);
+    std::vector<float> sc32(ns);
+    for (int64_t l = 0; l < ns; ++l) {
+        sc[l] = phi[l] * inv_n;
+        sc32[l] = (float)sc[l];
     }
+    if (hipMalloc(&p->table, sizeof(double) * ns) != hipSuccess) return UNO_ERR_NOMEM;
+    if (hipMalloc(&p->table32, sizeof(float) * ns) != hipSuccess) return UNO_ERR_NOMEM;
+    UNO_HIP(hipMemcpy(p->table, sc.data(), sizeof(double) * ns, hipMemcpyHostToDevice));
+    UNO_HIP(hipMemcpy(p->table32, sc32.data(), sizeof(float) * ns, hipMemcpyHostToDevice));
     if (hipMalloc(&p->spec, sizeof(double2) * ns) != hipSuccess) return UNO_ERR_NOMEM;
     return UNO_OK;
 }
@@ -279,6 +296,7 @@ static void precond_free(uno_precond* p)
     lowrank_destroy(p->lr);
     fft_plan_destroy(&p->plan);
     if (p->table) (void)hipFree(p->table);
+    if (p->table32) (void)hipFree(p->table32);
     if (p->spec) (void)hipFree(p->spec);
     free(p->table_host);
     delete p;
@@ -325,7 +343,7 @@ uno_status uno_precond_create(const uno_grid* grid, int32_t M, const double* the
         const int kxn = 2 * mx + 1, kyn = 2 * M + 1, kzn = M + 1;
         const int64_t nblock = (int64_t)kxn * kyn * kzn;
         if (nblock * 8 <= g.total) {
-            const double W = theta[0] * theta[0];
+            const double W = round_to(theta[0] * theta[0], table_t);
             const double inv_n = 1.0 / (double)g.total;
             std::vector<double> cb(nblock);
             for (int kxi = 0; kxi < kxn; ++kxi)
@@ -396,14 +414,17 @@ uno_status uno_precond_create_fans(const uno_grid* grid, double kappa_ref, uno_d
 uno_status uno_precond_apply(const uno_precond* p, const void* r, void* s, uno_dtype vec_t, void* stream)
 {
     if (!p || !r || !s) return UNO_ERR_ARG;
-    if (vec_t != UNO_F64 && vec_t != UNO_F32) return UNO_ERR_ARG;
-    if (vec_t == UNO_F64 && p->table_t != UNO_F64) return UNO_ERR_ARG;
-    if (vec_t == UNO_F32 && p->table_t != UNO_F32) return UNO_ERR_ARG;
-    if (vec_t == UNO_F64 && uno_use_lowrank(p)) {
-        if (r == s) return UNO_ERR_ARG;  // the learned-mode passes read r after writing s
-        return lowrank_apply(p->lr, (const double*)r, (double*)s, S(stream));
+    if (vec_t == UNO_F64) {
+        if (uno_use_lowrank(p)) {
+            if (r == s) return UNO_ERR_ARG;  // the learned-mode passes read r after writing s
+            return lowrank_apply(p->lr, (const double*)r, (double*)s, S(stream));
+        }
+        return uno_apply_passes(p->grid, p->plan, p->table, UNO_F64, r, s, vec_t, p->spec, nullptr, nullptr, S(stream));
     }
-    return uno_apply_passes(p->grid, p->plan, p->table, p->table_t, r, s, vec_t, p->spec, nullptr, nullptr, S(stream));
+    if (vec_t == UNO_F32)
+        return uno_apply_passes(p->grid, p->plan, p->table32, UNO_F32, r, s, vec_t, p->spec, nullptr, nullptr,
+                                S(stream));
+    return UNO_ERR_ARG;
 }
 
 uno_status uno_precond_set_path(uno_precond* p, int32_t path)
@@ -444,8 +465,11 @@ uno_status pcg_solve(const uno_grid* grid, const uno_material* mat, const double
         if (pg.n[0] != g.n[0] || pg.n[1] != g.n[1] || pg.n[2] != g.n[2]) return UNO_ERR_SHAPE;
     }
     if (mat->dtype != UNO_F64) return UNO_ERR_ARG;
-    if (opts->op_t != UNO_F64 || opts->prec_t != UNO_F64) return UNO_ERR_ARG;
-    if (opts->kind == UNO_PREC_UNO && opts->uno->table_t != UNO_F64) return UNO_ERR_ARG;
+    // FP64 throughout, or the mixed mode: FP32 operator and preconditioner
+    // applies, FP64 residual / solution recurrences, reductions and stop test
+    const bool f64 = opts->op_t == UNO_F64 && opts->prec_t == UNO_F64;
+    const bool mixed = opts->op_t == UNO_F32 && opts->prec_t == UNO_F32;
+    if (!f64 && !mixed) return UNO_ERR_ARG;
     double g3[3] = {0.0, 0.0, 0.0};
     if (macro_load)
         for (int b = 0; b < grid->dim; ++b) g3[3 - grid->dim + b] = macro_load[b];

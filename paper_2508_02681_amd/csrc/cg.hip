@@ -60,36 +60,53 @@ __device__ __forceinline__ double diag_at(const GridDev& g, const T* __restrict_
 // Initial partials: ||r_0||_inf and, for Jacobi / none, s_0 = P r_0 and r_0.s_0.
 // MODE 0: none (s is r), 1: Jacobi, 2: UNO (only the norm).
 // inverse of the assembled diagonal (Jacobi), formed once per solve
+template <typename T>
 __global__ void __launch_bounds__(kBlock) k_inv_diag(GridDev g, const double* __restrict__ kappa,
-                                                     double* __restrict__ dinv)
+                                                     T* __restrict__ dinv)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.n; i += (int64_t)gridDim.x * blockDim.x)
-        dinv[i] = 1.0 / diag_at(g, kappa, i);
+        dinv[i] = (T)(1.0 / diag_at(g, kappa, i));
 }
 
-template <int MODE>
-__global__ void __launch_bounds__(kBlock) k_cg_init(GridDev g, const double* __restrict__ dinv,
-                                                    const double* __restrict__ r, double* __restrict__ s,
+// vector precision copy (conductivities for the FP32 operator)
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_convert(int64_t n, const double* __restrict__ a, T* __restrict__ b)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        b[i] = (T)a[i];
+}
+
+template <typename T, int MODE>
+__global__ void __launch_bounds__(kBlock) k_cg_init(GridDev g, const T* __restrict__ dinv,
+                                                    const double* __restrict__ r, T* __restrict__ s,
                                                     double* __restrict__ part_rmax, double* __restrict__ part_rs,
-                                                    CgState* st)
+                                                    double* __restrict__ part_ss, CgState* st)
 {
     __shared__ double slots[kBlock / 64];
-    double m = 0.0, dt = 0.0;
+    double m = 0.0, dt = 0.0, ss = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.n; i += (int64_t)gridDim.x * blockDim.x) {
         const double ri = r[i];
         m = OpMax::apply(m, fabs(ri));
-        if (MODE == 0) dt += ri * ri;
-        if (MODE == 1) {
-            const double si = ri * dinv[i];
+        if (MODE == 0) {
+            const T si = (T)ri;
             s[i] = si;
-            dt += ri * si;
+            dt += ri * (double)si;
+            ss += (double)si;
+        }
+        if (MODE == 1) {
+            const T si = (T)(ri * (double)dinv[i]);
+            s[i] = si;
+            dt += ri * (double)si;
+            ss += (double)si;
         }
     }
     const double bm = block_reduce<OpMax>(m, slots);
     const double bd = block_reduce<OpSum>(dt, slots);
+    const double bs = block_reduce<OpSum>(ss, slots);
     if (threadIdx.x == 0) {
         part_rmax[blockIdx.x] = bm;
         part_rs[blockIdx.x] = bd;
+        part_ss[blockIdx.x] = bs;
         if (blockIdx.x == 0) {
             st->done = INT_MAX;
             st->status = 0;
@@ -107,7 +124,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_update(GridDev g, const T* __rest
                                                       const T* __restrict__ p, T* __restrict__ s, CgIter it,
                                                       const double* __restrict__ part_dp, int np_dp,
                                                       const double* __restrict__ gam, double* __restrict__ part_rmax,
-                                                      double* __restrict__ part_rs_next)
+                                                      double* __restrict__ part_rs_next, double* __restrict__ part_ss_next)
 {
     __shared__ double slots[kBlock / 64];
     // all loads first: state, d.p partials, gamma_k and the first element's operands
@@ -129,7 +146,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_update(GridDev g, const T* __rest
         return;
     }
     const double alpha = gk / dp;
-    double m = 0.0, dt = 0.0;
+    double m = 0.0, dt = 0.0, ss = 0.0;
     for (int64_t i = i0; i < g.n; i += (int64_t)gridDim.x * blockDim.x) {
         if (i != i0) {
             r0 = r[i];
@@ -141,18 +158,28 @@ __global__ void __launch_bounds__(kBlock) k_cg_update(GridDev g, const T* __rest
         r[i] = ri;
         u[i] = u0 + alpha * d0;
         m = OpMax::apply(m, fabs(ri));
-        if (MODE == 0) dt += ri * ri;
+        if (MODE == 0) {
+            const T si = (T)ri;
+            s[i] = si;
+            dt += ri * (double)si;
+            ss += (double)si;
+        }
         if (MODE == 1) {
             const T si = (T)(ri * (double)dinv[i]);
             s[i] = si;
             dt += ri * (double)si;
+            ss += (double)si;
         }
     }
     const double bm = block_reduce<OpMax>(m, slots);
     const double bd = (MODE <= 1) ? block_reduce<OpSum>(dt, slots) : 0.0;
+    const double bs = (MODE <= 1) ? block_reduce<OpSum>(ss, slots) : 0.0;
     if (threadIdx.x == 0) {
         part_rmax[blockIdx.x] = bm;
-        if (MODE <= 1) part_rs_next[blockIdx.x] = bd;
+        if (MODE <= 1) {
+            part_rs_next[blockIdx.x] = bd;
+            part_ss_next[blockIdx.x] = bs;
+        }
     }
 }
 
@@ -240,7 +267,9 @@ struct Workspace {
     int npart = 0;            // capacity of each partial buffer
     double *f = nullptr, *r = nullptr, *s = nullptr, *d[2] = {nullptr, nullptr}, *p = nullptr;
     double* dinv = nullptr;   // inverse Jacobi diagonal of the current solve
-    double* part = nullptr;   // 4 partial buffers: rmax, rs[2], dp
+    float* kap32 = nullptr;   // FP32 conductivities (mixed precision)
+    double* y64 = nullptr;    // FP64 operator output for residual replacement (mixed precision)
+    double* part = nullptr;   // 8 partial buffers: rmax, rs[2], dp, ss[2], ds[2]
     double2* spec = nullptr;
     int64_t nspec = 0;
     CgState* state = nullptr;
@@ -261,6 +290,8 @@ void ws_free(Workspace* w)
     (void)hipFree(w->d[1]);
     (void)hipFree(w->p);
     (void)hipFree(w->dinv);
+    (void)hipFree(w->kap32);
+    (void)hipFree(w->y64);
     (void)hipFree(w->part);
     (void)hipFree(w->spec);
     (void)hipFree(w->state);
@@ -305,7 +336,7 @@ uno_status ws_get(const Grid& g, const FftPlan* plan, int extra_parts, int hist_
     if (need > w->npart) {
         (void)hipFree(w->part);
         w->part = nullptr;
-        if (hipMalloc(&w->part, sizeof(double) * 4 * (size_t)need) != hipSuccess) return UNO_ERR_NOMEM;
+        if (hipMalloc(&w->part, sizeof(double) * 8 * (size_t)need) != hipSuccess) return UNO_ERR_NOMEM;
         w->npart = need;
     }
     if (plan && plan->nspec > w->nspec) {
@@ -341,87 +372,196 @@ struct Parts {
     double* rmax;
     double* rs[2];
     double* dp;
+    double* ss[2];  // sum(s), by pass parity
+    double* ds[2];  // sum(d_new), by the parity of the d buffer
 };
 
 Parts parts_of(Workspace* w)
 {
     Parts P;
+    const size_t np = (size_t)w->npart;
     P.rmax = w->part;
-    P.rs[0] = w->part + w->npart;
-    P.rs[1] = w->part + 2 * (size_t)w->npart;
-    P.dp = w->part + 3 * (size_t)w->npart;
+    P.rs[0] = w->part + np;
+    P.rs[1] = w->part + 2 * np;
+    P.dp = w->part + 3 * np;
+    P.ss[0] = w->part + 4 * np;
+    P.ss[1] = w->part + 5 * np;
+    P.ds[0] = w->part + 6 * np;
+    P.ds[1] = w->part + 7 * np;
     return P;
 }
 
 // np_update: workgroups of the update kernel (they write the ||r||_inf
-// partials read at the head of pass k > 0; pass 0 reads the init kernel's)
-CgIter iter_of(Workspace* w, const Parts& P, int k, double rtol, int hist_len, int np_update)
+// partials read at the head of pass k > k0; pass k0 reads the init kernel's)
+CgIter iter_of(Workspace* w, const Parts& P, int k, int k0, double rtol, int hist_len, int np_update)
 {
     CgIter it;
     memset(&it, 0, sizeof(it));
     it.k = k;
+    it.k0 = k0;
     it.st = w->state;
     it.part_rmax = P.rmax;
-    it.np_rmax = (k == 0) ? w->nbr : np_update;
+    it.np_rmax = (k == k0) ? w->nbr : np_update;
     it.rtol = rtol;
     it.hist = w->hist;
     it.hist_len = hist_len;
     it.r = w->r;
     it.part_rs = P.rs[k & 1];
+    it.part_ssum = P.ss[k & 1];
     return it;
 }
 
 }  // namespace
 
-static uno_status enqueue_pass(const Grid& g, Workspace* w, int kind, const uno_precond* pc, const double* kappa,
-                               double* u, int k, double rtol, int hist_len, hipStream_t st)
+// One CG pass k.  T: precision of the operator / preconditioner vectors
+// (s, d, p, conductivities, D^-1); r, u and every reduction stay FP64.
+template <typename T>
+static uno_status enqueue_pass(const Grid& g, Workspace* w, int kind, const uno_precond* pc, const T* kappa,
+                               double* u, int k, int k0, double rtol, int hist_len, hipStream_t st)
 {
     const Parts P = parts_of(w);
     const int nb = w->nbr;
-    double* dold = w->d[k & 1];
-    double* dnew = w->d[(k + 1) & 1];
+    T* dold = (T*)w->d[k & 1];
+    T* dnew = (T*)w->d[(k + 1) & 1];
+    T* sv = (T*)w->s;
+    T* pv = (T*)w->p;
     KTimer kt;
-    const double* s = (kind == UNO_PREC_NONE) ? w->r : w->s;
     int np_rs = nb;
+    const MeanFree mf{P.ss[k & 1], P.ds[k & 1], P.ds[(k + 1) & 1]};
     if (kind == UNO_PREC_UNO && uno_use_lowrank(pc)) {
         // learned-mode flow: [B (head) + C] -> matvec -> [update + A of pass k+1]
-        CgIter it = iter_of(w, P, k, rtol, hist_len, lowrank_update_blocks(pc->lr));
-        uno_status e = lowrank_finish(pc->lr, w->r, w->s, &it, &np_rs, st);
+        CgIter it = iter_of(w, P, k, k0, rtol, hist_len, lowrank_update_blocks(pc->lr));
+        uno_status e = lowrank_finish<T>(pc->lr, w->r, sv, &it, &np_rs, st);
         if (e != UNO_OK) return e;
         ktimer_begin(&kt, UNO_KT_MATVEC, st);
         const int np_dp =
-            launch_tile<double, true, false>(g, kappa, s, dold, dnew, w->p, P.dp, it, P.rs[k & 1], np_rs, w->gam, st);
+            launch_tile<T, true, false>(g, kappa, sv, dold, dnew, pv, P.dp, it, P.rs[k & 1], np_rs, w->gam, st, mf);
         ktimer_end(&kt);
         UNO_HIP(hipGetLastError());
-        return lowrank_update_forward(pc->lr, w->r, u, dnew, w->p, it, P.dp, np_dp, w->gam, P.rmax, st);
+        return lowrank_update_forward<T>(pc->lr, w->r, u, dnew, pv, it, P.dp, np_dp, w->gam, P.rmax, st);
     }
-    CgIter it = iter_of(w, P, k, rtol, hist_len, nb);
+    CgIter it = iter_of(w, P, k, k0, rtol, hist_len, nb);
     if (kind == UNO_PREC_UNO) {
-        uno_status e = uno_apply_passes(g, pc->plan, pc->table, pc->table_t, w->r, w->s, UNO_F64, w->spec, &it,
-                                        &np_rs, st);
+        if (sizeof(T) != sizeof(double)) return UNO_ERR_ARG;  // spectral passes run in FP64 only inside CG
+        uno_status e = uno_apply_passes(g, pc->plan, pc->table, UNO_F64, w->r, w->s, UNO_F64, w->spec, &it, &np_rs, st);
         if (e != UNO_OK) return e;
     }
     ktimer_begin(&kt, UNO_KT_MATVEC, st);
     int np_dp;
     if (kind == UNO_PREC_UNO)
-        np_dp = launch_tile<double, true, false>(g, kappa, s, dold, dnew, w->p, P.dp, it, P.rs[k & 1], np_rs, w->gam, st);
+        np_dp = launch_tile<T, true, false>(g, kappa, sv, dold, dnew, pv, P.dp, it, P.rs[k & 1], np_rs, w->gam, st, mf);
     else
-        np_dp = launch_tile<double, true, true>(g, kappa, s, dold, dnew, w->p, P.dp, it, P.rs[k & 1], np_rs, w->gam, st);
+        np_dp = launch_tile<T, true, true>(g, kappa, sv, dold, dnew, pv, P.dp, it, P.rs[k & 1], np_rs, w->gam, st, mf);
     ktimer_end(&kt);
     UNO_HIP(hipGetLastError());
     ktimer_begin(&kt, UNO_KT_UPDATE, st);
     double* rs_next = P.rs[(k + 1) & 1];
+    double* ss_next = P.ss[(k + 1) & 1];
+    const T* dinv = (const T*)w->dinv;
     if (kind == UNO_PREC_NONE)
-        hipLaunchKernelGGL((k_cg_update<double, 0>), dim3(nb), dim3(kBlock), 0, st, g.dev, (const double*)w->dinv, w->r, u, dnew, w->p,
-                           w->s, it, (const double*)P.dp, np_dp, (const double*)w->gam, P.rmax, rs_next);
+        hipLaunchKernelGGL((k_cg_update<T, 0>), dim3(nb), dim3(kBlock), 0, st, g.dev, dinv, w->r, u, (const T*)dnew,
+                           (const T*)pv, sv, it, (const double*)P.dp, np_dp, (const double*)w->gam, P.rmax, rs_next, ss_next);
     else if (kind == UNO_PREC_JACOBI)
-        hipLaunchKernelGGL((k_cg_update<double, 1>), dim3(nb), dim3(kBlock), 0, st, g.dev, (const double*)w->dinv, w->r, u, dnew, w->p,
-                           w->s, it, (const double*)P.dp, np_dp, (const double*)w->gam, P.rmax, rs_next);
+        hipLaunchKernelGGL((k_cg_update<T, 1>), dim3(nb), dim3(kBlock), 0, st, g.dev, dinv, w->r, u, (const T*)dnew,
+                           (const T*)pv, sv, it, (const double*)P.dp, np_dp, (const double*)w->gam, P.rmax, rs_next, ss_next);
     else
-        hipLaunchKernelGGL((k_cg_update<double, 2>), dim3(nb), dim3(kBlock), 0, st, g.dev, (const double*)w->dinv, w->r, u, dnew, w->p,
-                           w->s, it, (const double*)P.dp, np_dp, (const double*)w->gam, P.rmax, rs_next);
+        hipLaunchKernelGGL((k_cg_update<T, 2>), dim3(nb), dim3(kBlock), 0, st, g.dev, dinv, w->r, u, (const T*)dnew,
+                           (const T*)pv, sv, it, (const double*)P.dp, np_dp, (const double*)w->gam, P.rmax, rs_next, ss_next);
     ktimer_end(&kt);
     UNO_HIP(hipGetLastError());
+    return UNO_OK;
+}
+
+// Residual replacement of the FP32 mode: when ||r|| has dropped by this
+// factor since the last (re)start, r is recomputed as f - A u in FP64 and
+// the recurrence restarts (d = s).  FP32 stencil sums lose accuracy on smooth
+// directions (cancellation ~ 1e-7 cond(A)); the restart keeps the recursive
+// residual equal to the true one.
+constexpr double kRestartFactor = 1e-3;
+
+template <typename T>
+static uno_status pcg_loop(const Grid& g, Workspace* w, const double* kappa64, const T* kappa, double* u,
+                           const uno_solve_opts* o, const uno_precond* pc, int hist_len, hipStream_t st, int* k_end)
+{
+    const int nb = w->nbr;
+    const Parts P = parts_of(w);
+    T* sv = (T*)w->s;
+    T* dinv = (T*)w->dinv;
+    const bool lowrank = pc && uno_use_lowrank(pc);
+    const int np_update = lowrank ? lowrank_update_blocks(pc->lr) : nb;
+    const bool restarts = sizeof(T) == sizeof(float);
+    if (o->kind == UNO_PREC_JACOBI)
+        hipLaunchKernelGGL(k_inv_diag<T>, dim3(nb), dim3(kBlock), 0, st, g.dev, kappa64, dinv);
+    // (re)start of the recurrence from the residual in w->r: s_0 = P r_0 and
+    // the partials of the first pass
+    auto start = [&]() -> uno_status {
+        if (o->kind == UNO_PREC_NONE)
+            hipLaunchKernelGGL((k_cg_init<T, 0>), dim3(nb), dim3(kBlock), 0, st, g.dev, (const T*)dinv,
+                               (const double*)w->r, sv, P.rmax, P.rs[0], P.ss[0], w->state);
+        else if (o->kind == UNO_PREC_JACOBI)
+            hipLaunchKernelGGL((k_cg_init<T, 1>), dim3(nb), dim3(kBlock), 0, st, g.dev, (const T*)dinv,
+                               (const double*)w->r, sv, P.rmax, P.rs[0], P.ss[0], w->state);
+        else
+            hipLaunchKernelGGL((k_cg_init<T, 2>), dim3(nb), dim3(kBlock), 0, st, g.dev, (const T*)dinv,
+                               (const double*)w->r, sv, P.rmax, P.rs[0], P.ss[0], w->state);
+        UNO_HIP(hipGetLastError());
+        if (lowrank) return lowrank_forward(pc->lr, w->r, st);  // transform of r for the first pass
+        return UNO_OK;
+    };
+    uno_status e = start();
+    if (e != UNO_OK) return e;
+    // passes in chunks; the host reads the state between chunks
+    int k = 0, k0 = 0;
+    int chunk = o->graph_chunk > 0 ? o->graph_chunk : 8;
+    int prev_k = -1;
+    double prev_r = -1.0, cycle_r = -1.0;
+    for (;;) {
+        if (chunk > o->max_iter - k) chunk = o->max_iter - k;
+        for (int c = 0; c < chunk; ++c, ++k) {
+            e = enqueue_pass<T>(g, w, o->kind, pc, kappa, u, k, k0, o->rtol, hist_len, st);
+            if (e != UNO_OK) return e;
+        }
+        CgIter it = iter_of(w, P, k, k0, o->rtol, hist_len, np_update);
+        hipLaunchKernelGGL(k_cg_check, dim3(1), dim3(kBlock), 0, st, it);
+        UNO_HIP(hipGetLastError());
+        UNO_HIP(hipMemcpyAsync(w->host_state, w->state, sizeof(CgState), hipMemcpyDeviceToHost, st));
+        UNO_HIP(hipStreamSynchronize(st));
+        const CgState& hs = *w->host_state;
+        if (hs.status != 0 || hs.done != INT_MAX || k >= o->max_iter) break;
+        if (cycle_r < 0.0) cycle_r = hs.r0max;
+        double target = hs.tol_abs;
+        if (restarts) {
+            if (hs.rmax_last <= kRestartFactor * cycle_r) {
+                // residual replacement: r = f - A u (FP64), restart at pass k
+                e = launch_fe_apply(g, kappa64, u, w->y64, UNO_F64, st);
+                if (e != UNO_OK) return e;
+                hipLaunchKernelGGL(k_sub, dim3(nb), dim3(kBlock), 0, st, g.total, (const double*)w->f,
+                                   (const double*)w->y64, w->r);
+                e = start();
+                if (e != UNO_OK) return e;
+                k0 = k;
+                cycle_r = hs.rmax_last;
+                prev_r = -1.0;
+                chunk = o->graph_chunk > 0 ? o->graph_chunk : 8;
+                continue;
+            }
+            const double lvl = kRestartFactor * cycle_r;
+            if (lvl > target) target = lvl;
+        }
+        if (o->graph_chunk <= 0) {
+            // predict the passes still needed from the observed contraction rate
+            int next = 16;
+            if (prev_r > 0.0 && hs.rmax_last > 0.0 && hs.k_last > prev_k && hs.rmax_last < prev_r) {
+                const double rate = std::pow(hs.rmax_last / prev_r, 1.0 / (hs.k_last - prev_k));
+                const double need = std::log(target / hs.rmax_last) / std::log(rate);
+                next = (int)std::ceil(need * 1.05) + 1;
+            }
+            chunk = next < 4 ? 4 : (next > 256 ? 256 : next);
+        }
+        prev_k = hs.k_last;
+        prev_r = hs.rmax_last;
+    }
+    *k_end = k;
     return UNO_OK;
 }
 
@@ -429,13 +569,15 @@ uno_status pcg_run(const Grid& g, const double* kappa, const double* macro_load3
                    const uno_solve_opts* o, uno_solve_info* info, double* res_hist, hipStream_t st)
 {
     const uno_precond* pc = (o->kind == UNO_PREC_UNO) ? o->uno : nullptr;
+    const bool mixed = (o->op_t == UNO_F32);
+    if (mixed && pc && !uno_use_lowrank(pc)) return UNO_ERR_ARG;
     Workspace* w = nullptr;
     const int hist_len = o->max_iter + 1;
     uno_status e = ws_get(g, pc ? &pc->plan : nullptr, pc ? pc->rs_blocks : 0, hist_len, &w);
     if (e != UNO_OK) return e;
     const int nb = w->nbr;
     const Parts P = parts_of(w);
-    // rhs and initial residual r_0 = f - A u_0
+    // rhs and initial residual r_0 = f - A u_0 (FP64)
     if (macro_load3) {
         e = launch_rhs(g, kappa, UNO_F64, macro_load3, w->f, UNO_F64, st);
         if (e != UNO_OK) return e;
@@ -446,56 +588,16 @@ uno_status pcg_run(const Grid& g, const double* kappa, const double* macro_load3
     if (e != UNO_OK) return e;
     hipLaunchKernelGGL(k_sub, dim3(nb), dim3(kBlock), 0, st, g.total, (const double*)w->f, (const double*)w->p, w->r);
     UNO_HIP(hipGetLastError());
-    const double* dinv = w->dinv;
-    if (o->kind == UNO_PREC_NONE)
-        hipLaunchKernelGGL(k_cg_init<0>, dim3(nb), dim3(kBlock), 0, st, g.dev, dinv, w->r, w->s, P.rmax, P.rs[0],
-                           w->state);
-    else if (o->kind == UNO_PREC_JACOBI) {
-        hipLaunchKernelGGL(k_inv_diag, dim3(nb), dim3(kBlock), 0, st, g.dev, kappa, w->dinv);
-        hipLaunchKernelGGL(k_cg_init<1>, dim3(nb), dim3(kBlock), 0, st, g.dev, dinv, w->r, w->s, P.rmax, P.rs[0],
-                           w->state);
-    } else
-        hipLaunchKernelGGL(k_cg_init<2>, dim3(nb), dim3(kBlock), 0, st, g.dev, dinv, w->r, w->s, P.rmax, P.rs[0],
-                           w->state);
-    UNO_HIP(hipGetLastError());
-    const bool lowrank = pc && uno_use_lowrank(pc);
-    const int np_update = lowrank ? lowrank_update_blocks(pc->lr) : nb;
-    if (lowrank) {
-        e = lowrank_forward(pc->lr, w->r, st);  // transform of r_0 for the first pass
-        if (e != UNO_OK) return e;
-    }
-
-    // passes in chunks; the host reads the state between chunks
     int k = 0;
-    int chunk = o->graph_chunk > 0 ? o->graph_chunk : 8;
-    int prev_k = -1;
-    double prev_r = -1.0;
-    for (;;) {
-        if (chunk > o->max_iter - k) chunk = o->max_iter - k;
-        for (int c = 0; c < chunk; ++c, ++k) {
-            e = enqueue_pass(g, w, o->kind, pc, kappa, u, k, o->rtol, hist_len, st);
-            if (e != UNO_OK) return e;
-        }
-        CgIter it = iter_of(w, P, k, o->rtol, hist_len, np_update);
-        hipLaunchKernelGGL(k_cg_check, dim3(1), dim3(kBlock), 0, st, it);
-        UNO_HIP(hipGetLastError());
-        UNO_HIP(hipMemcpyAsync(w->host_state, w->state, sizeof(CgState), hipMemcpyDeviceToHost, st));
-        UNO_HIP(hipStreamSynchronize(st));
-        const CgState& hs = *w->host_state;
-        if (hs.status != 0 || hs.done != INT_MAX || k >= o->max_iter) break;
-        if (o->graph_chunk <= 0) {
-            // predict the passes still needed from the observed contraction rate
-            int next = 16;
-            if (prev_r > 0.0 && hs.rmax_last > 0.0 && hs.k_last > prev_k && hs.rmax_last < prev_r) {
-                const double rate = std::pow(hs.rmax_last / prev_r, 1.0 / (hs.k_last - prev_k));
-                const double need = std::log(hs.tol_abs / hs.rmax_last) / std::log(rate);
-                next = (int)std::ceil(need * 1.05) + 1;
-            }
-            chunk = next < 4 ? 4 : (next > 256 ? 256 : next);
-        }
-        prev_k = hs.k_last;
-        prev_r = hs.rmax_last;
+    if (mixed) {
+        if (!w->kap32 && hipMalloc(&w->kap32, sizeof(float) * g.total) != hipSuccess) return UNO_ERR_NOMEM;
+        if (!w->y64 && hipMalloc(&w->y64, sizeof(double) * g.total) != hipSuccess) return UNO_ERR_NOMEM;
+        hipLaunchKernelGGL(k_convert<float>, dim3(nb), dim3(kBlock), 0, st, g.total, kappa, w->kap32);
+        e = pcg_loop<float>(g, w, kappa, w->kap32, u, o, pc, hist_len, st, &k);
+    } else {
+        e = pcg_loop<double>(g, w, kappa, kappa, u, o, pc, hist_len, st, &k);
     }
+    if (e != UNO_OK) return e;
     const CgState hs = *w->host_state;
     // zero-mean fluctuation (Sec. 5.1) and the true residual in FP64
     hipLaunchKernelGGL(k_sum_parts, dim3(nb), dim3(kBlock), 0, st, g.total, (const double*)u, P.dp);

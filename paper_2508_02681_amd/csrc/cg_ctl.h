@@ -16,6 +16,7 @@ namespace unocg {
 
 struct CgIter {
     int k;                    // pass index
+    int k0;                   // first pass of the current cycle (0, or a residual replacement)
     CgState* st;
     const double* part_rmax;  // ||r_k||_inf partials (init kernel or update of pass k-1)
     int np_rmax;
@@ -24,6 +25,7 @@ struct CgIter {
     int hist_len;
     const double* r;          // FP64 residual (for r.s in the preconditioner's last pass)
     double* part_rs;          // r.s partials of pass k
+    double* part_ssum;        // sum(s) partials of pass k (FP32 mode: mean removal)
 };
 
 __device__ __forceinline__ bool loop_ended(const CgState* st, int k)

@@ -50,10 +50,10 @@ __device__ __forceinline__ int mod_n(int64_t v, int n)
 // UPDATE (inside CG): the rows are first updated, r <- r - alpha p,
 // u <- u + alpha d, and partials of ||r||_inf are written; the transformed
 // rows are then those of the new residual (for the next pass).
-template <bool UPDATE>
+template <bool UPDATE, typename TD>
 __global__ void __launch_bounds__(256) k_lr_fwd(LowRankDev L, int ny_chunk, double* __restrict__ r,
-                                                double* __restrict__ u, const double* __restrict__ d,
-                                                const double* __restrict__ p, double2* __restrict__ Gp, CgIter it,
+                                                double* __restrict__ u, const TD* __restrict__ d,
+                                                const TD* __restrict__ p, double2* __restrict__ Gp, CgIter it,
                                                 const double* __restrict__ part_dp, int np_dp,
                                                 const double* __restrict__ gam, double* __restrict__ part_rmax)
 {
@@ -88,9 +88,9 @@ __global__ void __launch_bounds__(256) k_lr_fwd(LowRankDev L, int ny_chunk, doub
         if (q < cnt) {
             rv[j] = r[base + q];
             if (UPDATE) {
-                pv[j] = p[base + q];
+                pv[j] = (double)p[base + q];
                 uv[j] = u[base + q];
-                dv[j] = d[base + q];
+                dv[j] = (double)d[base + q];
             }
         }
     }
@@ -117,9 +117,9 @@ __global__ void __launch_bounds__(256) k_lr_fwd(LowRankDev L, int ny_chunk, doub
         }
         for (int q = threadIdx.x + 256 * PF; q < cnt; q += 256) {
             const int64_t i = base + q;
-            const double rn = r[i] - alpha * p[i];
+            const double rn = r[i] - alpha * (double)p[i];
             r[i] = rn;
-            u[i] += alpha * d[i];
+            u[i] += alpha * (double)d[i];
             R[q] = rn;
             m = OpMax::apply(m, fabs(rn));
         }
@@ -239,9 +239,9 @@ __global__ void __launch_bounds__(64) k_lr_mid(LowRankDev L, int nch, const doub
 }
 
 // Pass C: one workgroup per (x-slab, chunk of rows y).
-template <bool CG>
+template <bool CG, typename TS>
 __global__ void __launch_bounds__(256) k_lr_inv(LowRankDev L, int y_chunk, const double* __restrict__ r,
-                                                const double2* __restrict__ H, double* __restrict__ s, CgIter it)
+                                                const double2* __restrict__ H, TS* __restrict__ s, CgIter it)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double slots[4];
@@ -290,7 +290,7 @@ __global__ void __launch_bounds__(256) k_lr_inv(LowRankDev L, int y_chunk, const
     }
     __syncthreads();
     // s = W r + Re sum_kz V[y][kz] exp(+2 pi i kz z / n2)
-    auto node = [&](int q, double rq) -> double {
+    auto node = [&](int q, double rq, double& ss) -> double {
         const int yl = q / L.n2, z = q % L.n2;
         double c = 0.0;
         int t = 0;
@@ -302,20 +302,25 @@ __global__ void __launch_bounds__(256) k_lr_inv(LowRankDev L, int y_chunk, const
             t += z;
             if (t >= L.n2) t -= L.n2;
         }
-        const double sv = L.W * rq + c;
+        const TS sv = (TS)(L.W * rq + c);
         s[base + q] = sv;
-        return rq * sv;
+        ss += (double)sv;
+        return rq * (double)sv;
     };
-    double acc = 0.0;
+    double acc = 0.0, ssum = 0.0;
 #pragma unroll
     for (int j = 0; j < PF; ++j) {
         const int q = threadIdx.x + 256 * j;
-        if (q < cnt) acc += node(q, rv[j]);
+        if (q < cnt) acc += node(q, rv[j], ssum);
     }
-    for (int q = threadIdx.x + 256 * PF; q < cnt; q += 256) acc += node(q, r[base + q]);
+    for (int q = threadIdx.x + 256 * PF; q < cnt; q += 256) acc += node(q, r[base + q], ssum);
     if (CG) {
         const double b = block_reduce<OpSum>(acc, slots);
         if (threadIdx.x == 0) it.part_rs[blockIdx.x] = b;
+        if (sizeof(TS) == 4) {
+            const double bs = block_reduce<OpSum>(ssum, slots);
+            if (threadIdx.x == 0) it.part_ssum[blockIdx.x] = bs;
+        }
     }
 }
 
@@ -405,7 +410,7 @@ uno_status lowrank_forward(const LowRankPlan* p, const double* r, hipStream_t st
 {
     KTimer kt;
     ktimer_begin(&kt, UNO_KT_FFT_FWD, st);
-    hipLaunchKernelGGL(k_lr_fwd<false>, dim3(p->blocks_a), dim3(256), p->lds_a, st, p->dev, p->ya, (double*)r,
+    hipLaunchKernelGGL((k_lr_fwd<false, double>), dim3(p->blocks_a), dim3(256), p->lds_a, st, p->dev, p->ya, (double*)r,
                        (double*)nullptr, (const double*)nullptr, (const double*)nullptr, p->Gp, no_iter(),
                        (const double*)nullptr, 0, (const double*)nullptr, (double*)nullptr);
     ktimer_end(&kt);
@@ -413,20 +418,22 @@ uno_status lowrank_forward(const LowRankPlan* p, const double* r, hipStream_t st
 }
 
 // CG update of pass k fused with pass A of pass k + 1
-uno_status lowrank_update_forward(const LowRankPlan* p, double* r, double* u, const double* d, const double* pv,
+template <typename T>
+uno_status lowrank_update_forward(const LowRankPlan* p, double* r, double* u, const T* d, const T* pv,
                                   const CgIter& it, const double* part_dp, int np_dp, const double* gam,
                                   double* part_rmax, hipStream_t st)
 {
     KTimer kt;
     ktimer_begin(&kt, UNO_KT_UPDATE, st);
-    hipLaunchKernelGGL(k_lr_fwd<true>, dim3(p->blocks_a), dim3(256), p->lds_a, st, p->dev, p->ya, r, u, d, pv, p->Gp,
-                       it, part_dp, np_dp, gam, part_rmax);
+    hipLaunchKernelGGL((k_lr_fwd<true, T>), dim3(p->blocks_a), dim3(256), p->lds_a, st, p->dev, p->ya, r, u, d, pv,
+                       p->Gp, it, part_dp, np_dp, gam, part_rmax);
     ktimer_end(&kt);
     return hip_status(hipGetLastError());
 }
 
 // passes B and C (B tests convergence inside CG); C writes s and r.s partials
-uno_status lowrank_finish(const LowRankPlan* p, const double* r, double* s, const CgIter* itp, int* np_rs,
+template <typename T>
+uno_status lowrank_finish(const LowRankPlan* p, const double* r, T* s, const CgIter* itp, int* np_rs,
                           hipStream_t st)
 {
     const LowRankDev& L = p->dev;
@@ -439,10 +446,10 @@ uno_status lowrank_finish(const LowRankPlan* p, const double* r, double* s, cons
     UNO_HIP(hipGetLastError());
     ktimer_begin(&kt, UNO_KT_FFT_INV, st);
     if (itp)
-        hipLaunchKernelGGL(k_lr_inv<true>, dim3(p->blocks_c), dim3(256), p->lds_c, st, L, p->yc, r,
+        hipLaunchKernelGGL((k_lr_inv<true, T>), dim3(p->blocks_c), dim3(256), p->lds_c, st, L, p->yc, r,
                            (const double2*)p->H, s, it);
     else
-        hipLaunchKernelGGL(k_lr_inv<false>, dim3(p->blocks_c), dim3(256), p->lds_c, st, L, p->yc, r,
+        hipLaunchKernelGGL((k_lr_inv<false, T>), dim3(p->blocks_c), dim3(256), p->lds_c, st, L, p->yc, r,
                            (const double2*)p->H, s, it);
     ktimer_end(&kt);
     UNO_HIP(hipGetLastError());
@@ -454,7 +461,14 @@ uno_status lowrank_apply(const LowRankPlan* p, const double* r, double* s, hipSt
 {
     uno_status e = lowrank_forward(p, r, st);
     if (e != UNO_OK) return e;
-    return lowrank_finish(p, r, s, nullptr, nullptr, st);
+    return lowrank_finish<double>(p, r, s, nullptr, nullptr, st);
 }
+
+template uno_status lowrank_finish<double>(const LowRankPlan*, const double*, double*, const CgIter*, int*, hipStream_t);
+template uno_status lowrank_finish<float>(const LowRankPlan*, const double*, float*, const CgIter*, int*, hipStream_t);
+template uno_status lowrank_update_forward<double>(const LowRankPlan*, double*, double*, const double*, const double*,
+                                                   const CgIter&, const double*, int, const double*, double*, hipStream_t);
+template uno_status lowrank_update_forward<float>(const LowRankPlan*, double*, double*, const float*, const float*,
+                                                  const CgIter&, const double*, int, const double*, double*, hipStream_t);
 
 }  // namespace unocg

@@ -86,13 +86,28 @@ __device__ __forceinline__ T stencil_node(const GridDev& g, const T dm[3][3], co
     return acc;
 }
 
+// Mean removal of the search direction (FP32 operator mode): partial sums of
+// s (count np_s, same producer as r.s) and of the previous d_new (count =
+// this grid), and where to write the partial sums of the new d.
+struct MeanFree {
+    const double* part_s;
+    const double* part_dold;
+    double* part_dnew;
+};
+
 template <typename T, int TX, int TZ, bool CG, bool HEAD>
 __global__ void __launch_bounds__(256) k_stencil_tile(GridDev g, TileGeom tg, const T* __restrict__ kappa,
                                                       const T* __restrict__ s, const T* __restrict__ dold,
                                                       T* __restrict__ dnew, T* __restrict__ p,
                                                       double* __restrict__ part_dp, CgIter it,
-                                                      const double* __restrict__ part_rs, int np_rs, double* gam)
+                                                      const double* __restrict__ part_rs, int np_rs, double* gam,
+                                                      MeanFree mf)
 {
+    // In FP32 the direction is kept mean-free: A 1 = 0 and sum(A d) = 0, so
+    // shifting d by a constant leaves p, d.p, alpha, r and beta unchanged and
+    // moves u by a constant (removed at the end); it avoids the cancellation
+    // a large constant component causes in the FP32 stencil sums.
+    constexpr bool MF = CG && sizeof(T) == 4;
     constexpr int TY = 256 / TZ;
     constexpr int DX = TX + 2, DY = TY + 2, DZ = TZ + 2;
     constexpr int KX = TX + 1, KY = TY + 1, KZ = TZ + 1;
@@ -110,12 +125,16 @@ __global__ void __launch_bounds__(256) k_stencil_tile(GridDev g, TileGeom tg, co
     // every global load is issued before the first decision, so the loop
     // state, the partials, the previous gamma and the staged data overlap
     StateLoad sl;
-    double head_share = 0.0, rs_share = 0.0, gprev = 1.0;
+    double head_share = 0.0, rs_share = 0.0, gprev = 1.0, ssum_share = 0.0, dsum_share = 0.0;
     if (CG) {
         sl = load_state(it.st);
         if (HEAD) head_share = load_share<OpMax>(it.part_rmax, it.np_rmax);
         rs_share = load_share<OpSum>(part_rs, np_rs);
-        if (it.k > 0) gprev = gam[it.k - 1];
+        if (it.k > it.k0) gprev = gam[it.k - 1];
+        if (MF) {
+            ssum_share = load_share<OpSum>(mf.part_s, np_rs);
+            if (it.k > it.k0) dsum_share = load_share<OpSum>(mf.part_dold, gridDim.x);
+        }
     }
     constexpr int ND = DX * DY * DZ, NK = KX * KY * KZ;
     constexpr int PD = (ND + 255) / 256, PK = (NK + 255) / 256;
@@ -134,7 +153,7 @@ __global__ void __launch_bounds__(256) k_stencil_tile(GridDev g, TileGeom tg, co
             const int x = wrapc(x0 - 1 + xl, g.n0), y = wrapc(y0 - 1 + yl, g.n1), z = wrapc(z0 - 1 + zl, g.n2);
             const int64_t idx = ((int64_t)x * g.n1 + y) * g.n2 + z;
             sv[j] = s[idx];
-            if (CG && it.k > 0) dv[j] = dold[idx];
+            if (CG && it.k > it.k0) dv[j] = dold[idx];
         }
     }
 #pragma unroll
@@ -164,13 +183,19 @@ __global__ void __launch_bounds__(256) k_stencil_tile(GridDev g, TileGeom tg, co
             if (lead) { it.st->status = 1; it.st->fail_iter = k; }
             return;
         }
-        first = (k == 0);
+        first = (k == it.k0);  // d = s on the first pass of a cycle (Algorithm 1: d_0 = 0)
         beta = first ? (T)0 : (T)(gk / gprev);
+    }
+    T shift = (T)0;
+    if (MF) {
+        const double ssum = combine_share<OpSum>(ssum_share, slots);
+        const double dsum = first ? 0.0 : combine_share<OpSum>(dsum_share, slots);
+        shift = (T)((ssum + (double)beta * dsum) / (double)g.n);
     }
 #pragma unroll
     for (int j = 0; j < PD; ++j) {
         const int q = threadIdx.x + 256 * j;
-        if (q < ND) Dl[q] = (CG && !first) ? sv[j] + beta * dv[j] : sv[j];
+        if (q < ND) Dl[q] = ((CG && !first) ? sv[j] + beta * dv[j] : sv[j]) - shift;
     }
 #pragma unroll
     for (int j = 0; j < PK; ++j) {
@@ -194,7 +219,7 @@ __global__ void __launch_bounds__(256) k_stencil_tile(GridDev g, TileGeom tg, co
     for (int bb = 0; bb < 2; ++bb)
 #pragma unroll
         for (int c = 0; c < 2; ++c) km[bb][c] = Kl[(0 * KY + ty + bb) * KZ + tz + c];
-    double dot = 0.0;
+    double dot = 0.0, dsum_own = 0.0;
 #pragma unroll
     for (int xi = 0; xi < TX; ++xi) {
 #pragma unroll
@@ -213,6 +238,7 @@ __global__ void __launch_bounds__(256) k_stencil_tile(GridDev g, TileGeom tg, co
             if (CG) {
                 dnew[i] = d0[1][1];
                 dot += (double)d0[1][1] * (double)acc;
+                if (MF) dsum_own += (double)d0[1][1];
             }
         }
 #pragma unroll
@@ -230,6 +256,10 @@ __global__ void __launch_bounds__(256) k_stencil_tile(GridDev g, TileGeom tg, co
     if (CG) {
         const double bd = block_reduce<OpSum>(dot, slots);
         if (threadIdx.x == 0) part_dp[blockIdx.x] = bd;
+        if (MF) {
+            const double bs = block_reduce<OpSum>(dsum_own, slots);
+            if (threadIdx.x == 0) mf.part_dnew[blockIdx.x] = bs;
+        }
     }
 }
 
@@ -263,20 +293,20 @@ inline TileChoice choose_tile(const Grid& g)
 template <typename T, bool CG, bool HEAD, int TX>
 inline void launch_tile_tx(const TileChoice& c, const GridDev& g, const T* kappa, const T* s, const T* dold, T* dnew,
                            T* p, double* part_dp, const CgIter& it, const double* part_rs, int np_rs, double* gam,
-                           hipStream_t st)
+                           hipStream_t st, const MeanFree& mf)
 {
     switch (c.tz) {
         case 64:
             hipLaunchKernelGGL((k_stencil_tile<T, TX, 64, CG, HEAD>), dim3(c.blocks), dim3(256), 0, st, g, c.geom,
-                               kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam);
+                               kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam, mf);
             break;
         case 32:
             hipLaunchKernelGGL((k_stencil_tile<T, TX, 32, CG, HEAD>), dim3(c.blocks), dim3(256), 0, st, g, c.geom,
-                               kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam);
+                               kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam, mf);
             break;
         default:
             hipLaunchKernelGGL((k_stencil_tile<T, TX, 16, CG, HEAD>), dim3(c.blocks), dim3(256), 0, st, g, c.geom,
-                               kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam);
+                               kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam, mf);
             break;
     }
 }
@@ -284,15 +314,16 @@ inline void launch_tile_tx(const TileChoice& c, const GridDev& g, const T* kappa
 // Launches the tiled operator; returns the number of workgroups (= d.p partials).
 template <typename T, bool CG, bool HEAD>
 inline int launch_tile(const Grid& g, const T* kappa, const T* s, const T* dold, T* dnew, T* p, double* part_dp,
-                       const CgIter& it, const double* part_rs, int np_rs, double* gam, hipStream_t st)
+                       const CgIter& it, const double* part_rs, int np_rs, double* gam, hipStream_t st,
+                       const MeanFree& mf = MeanFree{nullptr, nullptr, nullptr})
 {
     const TileChoice c = choose_tile(g);
     if (c.tx == 1)
-        launch_tile_tx<T, CG, HEAD, 1>(c, g.dev, kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam, st);
+        launch_tile_tx<T, CG, HEAD, 1>(c, g.dev, kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam, st, mf);
     else if (c.tx == 2)
-        launch_tile_tx<T, CG, HEAD, 2>(c, g.dev, kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam, st);
+        launch_tile_tx<T, CG, HEAD, 2>(c, g.dev, kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam, st, mf);
     else
-        launch_tile_tx<T, CG, HEAD, 4>(c, g.dev, kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam, st);
+        launch_tile_tx<T, CG, HEAD, 4>(c, g.dev, kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam, st, mf);
     return c.blocks;
 }
 

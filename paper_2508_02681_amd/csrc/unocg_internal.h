@@ -135,10 +135,12 @@ int lowrank_max_blocks(const LowRankPlan* p);
 int lowrank_update_blocks(const LowRankPlan* p);
 uno_status lowrank_apply(const LowRankPlan* p, const double* r, double* s, hipStream_t st);
 uno_status lowrank_forward(const LowRankPlan* p, const double* r, hipStream_t st);
-uno_status lowrank_update_forward(const LowRankPlan* p, double* r, double* u, const double* d, const double* pv,
+template <typename T>
+uno_status lowrank_update_forward(const LowRankPlan* p, double* r, double* u, const T* d, const T* pv,
                                   const CgIter& it, const double* part_dp, int np_dp, const double* gam,
                                   double* part_rmax, hipStream_t st);
-uno_status lowrank_finish(const LowRankPlan* p, const double* r, double* s, const CgIter* it, int* np_rs,
+template <typename T>
+uno_status lowrank_finish(const LowRankPlan* p, const double* r, T* s, const CgIter* it, int* np_rs,
                           hipStream_t st);
 int fft_c2r_blocks(const Grid& g, const FftPlan& p);
 
@@ -149,9 +151,10 @@ struct uno_precond {
     unocg::Grid grid;
     unocg::FftPlan plan;
     int M;
-    uno_dtype table_t;
-    void* table;          // device half spectrum, scaled by 1/n, table_t
-    double* table_host;   // unscaled Phi on the half spectrum
+    uno_dtype table_t;    // precision the table values were rounded to
+    double* table;        // device half spectrum, scaled by 1/n (FP64 applies)
+    float* table32;       // the same in FP32 (FP32 applies)
+    double* table_host;   // unscaled Phi on the half spectrum (after rounding)
     void* spec;           // scratch spectrum (FP64 complex, nspec values)
     unocg::LowRankPlan* lr;  // learned-mode passes (UNO tables only), or null
     int path;             // UNO_PATH_*

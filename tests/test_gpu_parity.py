@@ -242,3 +242,62 @@ def test_solve_is_deterministic(uno):
     b, ib = uno.pcg_solve(T(kap), macro_load=[1.0, 0.5, 0.0], kind="uno", precond=p, rtol=1e-8)
     assert ia["iters"] == ib["iters"]
     assert torch.equal(a, b)
+
+
+# ---- mixed precision: FP32 operator / preconditioner, FP64 recurrences -----
+
+def _two_phase(shape, seed, contrast=100.0):
+    ph, _ = si.rsa_inclusions(shape, 2, 4, 0.25, seed)
+    return si.two_phase_kappa(ph, 1.0, contrast)
+
+
+def _kbar_gpu(uno, kap, **kw):
+    loads = np.eye(kap.ndim)
+    sols = []
+    infos = []
+    for g in loads:
+        u, info = uno.pcg_solve(T(kap), macro_load=g, **kw)
+        sols.append(u)
+        infos.append(info)
+    return uno.effective_tensor(T(kap), loads, torch.stack(sols)), infos
+
+
+def _kbar_oracle(orc, kap):
+    loads = [np.eye(kap.ndim)[i] for i in range(kap.ndim)]
+    sols = [orc.pcg(kap, orc.rhs(kap, g), "jacobi", rtol=1e-11)[0] for g in loads]
+    return orc.effective_tensor(kap, sols, loads)
+
+
+@pytest.mark.parametrize("kind", ["jacobi", "uno"])
+def test_mixed_precision_kbar_within_1e5(orc, uno, kind):
+    """FP32 operator and preconditioner, FP64 recurrences: kappa_bar within
+    1e-5 of the FP64 oracle; the true FP64 residual meets the tolerance."""
+    shape, M = (24, 24, 24), 4
+    kap = _two_phase(shape, 31)
+    kw = dict(kind=kind, rtol=1e-8, op_dtype=torch.float32, prec_dtype=torch.float32)
+    if kind == "uno":
+        th = si.random_theta(uno.num_weights(3, M), 5, scale=0.05, spread=0.2)
+        p = uno.UnoPrecond.create(shape, M, th)
+        p.set_path(2)
+        kw["precond"] = p
+    kb, infos = _kbar_gpu(uno, kap, **kw)
+    kbo = _kbar_oracle(orc, kap)
+    err = rel(kb, kbo)
+    print("mixed", kind, "kappa_bar rel err %.2e" % err, [i["iters"] for i in infos], flush=True)
+    assert all(i["converged"] for i in infos)
+    assert all(i["true_rel_res"] < 1e-6 for i in infos)
+    assert err < 1e-5
+
+
+def test_bf16_table_converges_to_same_solution(orc, uno):
+    """A table rounded to bfloat16 changes the preconditioner, not the
+    solution: FP64 UNO-CG still matches the oracle to 1e-8."""
+    shape, M = (20, 20, 20), 3
+    kap = _two_phase(shape, 32)
+    th = si.random_theta(uno.num_weights(3, M), 6, scale=0.05, spread=0.2)
+    p = uno.UnoPrecond.create(shape, M, th, table_dtype=torch.bfloat16)
+    tab = p.table()
+    bits = np.frombuffer(tab.astype(np.float32).tobytes(), dtype=np.uint32)
+    assert np.all((bits & 0xFFFF) == 0)  # representable in bfloat16
+    kb, infos = _kbar_gpu(uno, kap, kind="uno", precond=p, rtol=1e-12)
+    assert rel(kb, _kbar_oracle(orc, kap)) < 1e-8
