@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--jac-steps", type=int, default=4)
     ap.add_argument("--cpu-iters", type=int, default=20, help="oracle UNO-CG passes timed for cpu_baseline")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run one device-to-device copy of this size first (reference for HBM counters)")
     return ap.parse_args()
 
 
@@ -71,6 +73,13 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     uno.lib()
+    if args.calib_copy_mib > 0:  # a plain copy of known size: the scale of the FETCH/WRITE counters
+        nb = args.calib_copy_mib << 20
+        src = torch.ones(nb, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     cfg = dict(si.CONFIG_3D_64)
     n_dof = int(np.prod(SHAPE))
 
@@ -201,8 +210,34 @@ def main():
     log("FANS-CG: %.1f passes/solve, %.3f ms per solve" % (np.mean(itsf), dtf / len(itsf) * 1e3))
 
     # ---------------- dominant kernel: live HIP-event timing ----------------
-    fams = {uno.KT_MATVEC: "k_cg_matvec", uno.KT_UPDATE: "k_cg_update", uno.KT_FFT_FWD: "k_fft_r2c_z",
-            uno.KT_FFT_MID: "k_fft_strided(mid)", uno.KT_FFT_INV: "k_fft_c2r_z"}
+    try:  # the learned-mode passes are in use when the table has them (AUTO == LEARNED then)
+        prec.set_path(prec.PATH_LEARNED)
+        learned = True
+    except RuntimeError:
+        learned = False
+    prec.set_path(prec.PATH_AUTO)
+    nspec = SHAPE[0] * SHAPE[1] * (SHAPE[2] // 2 + 1)
+    nblk = SHAPE[0] * (2 * M + 1) * (M + 1)   # learned block after the two partial DFTs (y, z)
+    if learned:
+        fams = {uno.KT_MATVEC: "k_stencil_tile<double,CG>", uno.KT_UPDATE: "k_lr_fwd<update,double>",
+                uno.KT_FFT_MID: "k_lr_mid", uno.KT_FFT_INV: "k_lr_inv<double>"}
+        # algorithmic bytes per launch (FP64): the minimum each kernel must move
+        bytes_per = {
+            uno.KT_MATVEC: n_dof * 8 * 5,            # read s, d_old, kappa; write d_new, p
+            uno.KT_UPDATE: n_dof * 8 * 6 + nblk * 16,  # read r, u, d, p; write r, u, block spectrum
+            uno.KT_FFT_MID: nblk * 16 * 2 + nblk * 8,  # block spectrum in/out + table
+            uno.KT_FFT_INV: n_dof * 8 * 2 + nblk * 16,  # read r and block; write s
+        }
+    else:
+        fams = {uno.KT_MATVEC: "k_stencil_tile<double,CG>", uno.KT_UPDATE: "k_cg_update<double>",
+                uno.KT_FFT_FWD: "k_fft_r2c_z", uno.KT_FFT_MID: "k_fft_strided(mid)", uno.KT_FFT_INV: "k_fft_c2r_z"}
+        bytes_per = {
+            uno.KT_MATVEC: n_dof * 8 * 5,
+            uno.KT_UPDATE: n_dof * 8 * 6,             # read r, p, u, d; write r, u
+            uno.KT_FFT_FWD: n_dof * 8 + nspec * 16,   # read r; write half spectrum
+            uno.KT_FFT_MID: nspec * 16 * 2 + nspec * 8,  # spectrum in/out + table
+            uno.KT_FFT_INV: nspec * 16 + n_dof * 8 * 2,  # spectrum in; write s; read r (r.s)
+        }
     fam_ms = {}
     for fam in fams:
         uno.timing_enable(fam)
@@ -212,15 +247,6 @@ def main():
         uno.timing_enable(uno.KT_NONE)
         fam_ms[fam] = (tot, nl)
     dom = max(fam_ms, key=lambda f: fam_ms[f][0])
-    # algorithmic bytes per launch (FP64, 64^3): the minimum each kernel must move
-    nspec = SHAPE[0] * SHAPE[1] * (SHAPE[2] // 2 + 1)
-    bytes_per = {
-        uno.KT_MATVEC: n_dof * 8 * 5,        # read s, d_old, kappa; write d_new, p
-        uno.KT_UPDATE: n_dof * 8 * 6,        # read r, p, u, d; write r, u
-        uno.KT_FFT_FWD: n_dof * 8 + nspec * 16,     # read r; write half spectrum
-        uno.KT_FFT_MID: nspec * 16 * 2 + nspec * 8,  # spectrum in/out + table
-        uno.KT_FFT_INV: nspec * 16 + n_dof * 8 * 2,  # spectrum in; write s; read r (r.s)
-    }
     tot, nl = fam_ms[dom]
     avg_s = tot / max(nl, 1) / 1e3
     achieved = bytes_per[dom] / avg_s / 1e9

@@ -204,13 +204,16 @@ enum {
     UNO_KT_FFT_MID = 4,  /* middle pass: transform, Phi multiply, inverse */
     UNO_KT_FFT_INV = 5   /* last inverse pass (+ r.s) */
 };
-/* Brackets every launch of kernel family `which` with HIP events on its
- * stream (UNO_KT_NONE disables); uno_timing_read synchronizes those events
- * and returns the summed duration (ms) and launch count since enabling. */
+/* Brackets every launch of kernel family `which` with start/stop HIP events
+ * of the launch itself (hipExtLaunchKernelGGL) on its stream; UNO_KT_NONE
+ * disables.  The events come from a pool and carry no system-scope fence.
+ * uno_timing_read synchronizes those events and returns the summed duration
+ * (ms) and launch count since enabling.  Host-global; not for concurrent use
+ * from several threads with different families. */
 uno_status uno_timing_enable(int32_t which);
 uno_status uno_timing_read(double *total_ms, int64_t *launches);
 
-/* Releases cached workspaces (all devices). */
+/* Releases cached workspaces (all devices) and the timing event pool. */
 uno_status uno_shutdown(void);
 
 #ifdef __cplusplus

@@ -95,28 +95,37 @@ int g_twhich = UNO_KT_NONE;
 std::vector<std::pair<hipEvent_t, hipEvent_t>> g_tev;
 }  // namespace
 
-void ktimer_begin(KTimer* t, int which, hipStream_t s)
+// Timing events are pooled and created without the system-scope fence at
+// completion, so that a timed launch runs as it does untimed (no cache
+// write-back between it and its neighbours, no event creation on the way).
+static std::vector<hipEvent_t> g_tpool;
+
+static bool pool_pop(hipEvent_t* e)
 {
-    t->active = false;
-    if (g_twhich == UNO_KT_NONE || which != g_twhich) return;
-    t->which = which;
-    t->stream = s;
-    if (hipEventCreate(&t->a) != hipSuccess) return;
-    if (hipEventCreate(&t->b) != hipSuccess) {
-        (void)hipEventDestroy(t->a);
-        return;
+    if (!g_tpool.empty()) {
+        *e = g_tpool.back();
+        g_tpool.pop_back();
+        return true;
     }
-    (void)hipEventRecord(t->a, s);
-    t->active = true;
+    return hipEventCreateWithFlags(e, hipEventDisableSystemFence) == hipSuccess;
 }
 
-void ktimer_end(KTimer* t)
+bool ktimer_take(int fam, hipEvent_t* a, hipEvent_t* b)
 {
-    if (!t->active) return;
-    (void)hipEventRecord(t->b, t->stream);
     std::lock_guard<std::mutex> lk(g_tmu);
-    g_tev.emplace_back(t->a, t->b);
-    t->active = false;
+    if (g_twhich == UNO_KT_NONE || fam != g_twhich) return false;
+    if (!pool_pop(a)) return false;
+    if (!pool_pop(b)) {
+        g_tpool.push_back(*a);
+        return false;
+    }
+    return true;
+}
+
+void ktimer_push(hipEvent_t a, hipEvent_t b)
+{
+    std::lock_guard<std::mutex> lk(g_tmu);
+    g_tev.emplace_back(a, b);
 }
 
 }  // namespace unocg
@@ -149,11 +158,7 @@ uno_status fe_apply(const uno_grid* grid, const uno_material* mat, const void* u
     if (e != UNO_OK) return e;
     if (!mat || !mat->kappa || !u || !y || u == y) return UNO_ERR_ARG;
     if ((vec_t != UNO_F64 && vec_t != UNO_F32) || mat->dtype != vec_t) return UNO_ERR_ARG;
-    KTimer kt;
-    ktimer_begin(&kt, UNO_KT_MATVEC, S(stream));
-    e = launch_fe_apply(g, mat->kappa, u, y, vec_t, S(stream));
-    ktimer_end(&kt);
-    return e;
+    return launch_fe_apply(g, mat->kappa, u, y, vec_t, S(stream));
 }
 
 uno_status jac_precond_apply(const uno_grid* grid, const uno_material* mat, const void* r, void* s, uno_dtype vec_t,
@@ -544,9 +549,10 @@ uno_status effective_tensor(const uno_grid* grid, const uno_material* mat, int32
 uno_status uno_timing_enable(int32_t which)
 {
     std::lock_guard<std::mutex> lk(g_tmu);
-    for (auto& pr : g_tev) {
-        (void)hipEventDestroy(pr.first);
-        (void)hipEventDestroy(pr.second);
+    for (auto& pr : g_tev) {  // events of earlier launches go back to the pool once recorded
+        (void)hipEventSynchronize(pr.second);
+        g_tpool.push_back(pr.first);
+        g_tpool.push_back(pr.second);
     }
     g_tev.clear();
     g_twhich = which;
@@ -569,6 +575,21 @@ uno_status uno_timing_read(double* total_ms, int64_t* launches)
     return UNO_OK;
 }
 
-uno_status uno_shutdown(void) { return ws_release_all(); }
+uno_status uno_shutdown(void)
+{
+    {
+        std::lock_guard<std::mutex> lk(g_tmu);
+        for (auto& pr : g_tev) {
+            (void)hipEventSynchronize(pr.second);
+            g_tpool.push_back(pr.first);
+            g_tpool.push_back(pr.second);
+        }
+        g_tev.clear();
+        g_twhich = UNO_KT_NONE;
+        for (hipEvent_t e : g_tpool) (void)hipEventDestroy(e);
+        g_tpool.clear();
+    }
+    return ws_release_all();
+}
 
 }  // extern "C"

@@ -425,7 +425,6 @@ static uno_status enqueue_pass(const Grid& g, Workspace* w, int kind, const uno_
     T* dnew = (T*)w->d[(k + 1) & 1];
     T* sv = (T*)w->s;
     T* pv = (T*)w->p;
-    KTimer kt;
     int np_rs = nb;
     const MeanFree mf{P.ss[k & 1], P.ds[k & 1], P.ds[(k + 1) & 1]};
     if (kind == UNO_PREC_UNO && uno_use_lowrank(pc)) {
@@ -433,10 +432,8 @@ static uno_status enqueue_pass(const Grid& g, Workspace* w, int kind, const uno_
         CgIter it = iter_of(w, P, k, k0, rtol, hist_len, lowrank_update_blocks(pc->lr));
         uno_status e = lowrank_finish<T>(pc->lr, w->r, sv, &it, &np_rs, st);
         if (e != UNO_OK) return e;
-        ktimer_begin(&kt, UNO_KT_MATVEC, st);
         const int np_dp =
             launch_tile<T, true, false>(g, kappa, sv, dold, dnew, pv, P.dp, it, P.rs[k & 1], np_rs, w->gam, st, mf);
-        ktimer_end(&kt);
         UNO_HIP(hipGetLastError());
         return lowrank_update_forward<T>(pc->lr, w->r, u, dnew, pv, it, P.dp, np_dp, w->gam, P.rmax, st);
     }
@@ -446,28 +443,24 @@ static uno_status enqueue_pass(const Grid& g, Workspace* w, int kind, const uno_
         uno_status e = uno_apply_passes(g, pc->plan, pc->table, UNO_F64, w->r, w->s, UNO_F64, w->spec, &it, &np_rs, st);
         if (e != UNO_OK) return e;
     }
-    ktimer_begin(&kt, UNO_KT_MATVEC, st);
     int np_dp;
     if (kind == UNO_PREC_UNO)
         np_dp = launch_tile<T, true, false>(g, kappa, sv, dold, dnew, pv, P.dp, it, P.rs[k & 1], np_rs, w->gam, st, mf);
     else
         np_dp = launch_tile<T, true, true>(g, kappa, sv, dold, dnew, pv, P.dp, it, P.rs[k & 1], np_rs, w->gam, st, mf);
-    ktimer_end(&kt);
     UNO_HIP(hipGetLastError());
-    ktimer_begin(&kt, UNO_KT_UPDATE, st);
     double* rs_next = P.rs[(k + 1) & 1];
     double* ss_next = P.ss[(k + 1) & 1];
     const T* dinv = (const T*)w->dinv;
     if (kind == UNO_PREC_NONE)
-        hipLaunchKernelGGL((k_cg_update<T, 0>), dim3(nb), dim3(kBlock), 0, st, g.dev, dinv, w->r, u, (const T*)dnew,
+        uno_launch(UNO_KT_UPDATE, k_cg_update<T, 0>, dim3(nb), dim3(kBlock), 0, st, g.dev, dinv, w->r, u, (const T*)dnew,
                            (const T*)pv, sv, it, (const double*)P.dp, np_dp, (const double*)w->gam, P.rmax, rs_next, ss_next);
     else if (kind == UNO_PREC_JACOBI)
-        hipLaunchKernelGGL((k_cg_update<T, 1>), dim3(nb), dim3(kBlock), 0, st, g.dev, dinv, w->r, u, (const T*)dnew,
+        uno_launch(UNO_KT_UPDATE, k_cg_update<T, 1>, dim3(nb), dim3(kBlock), 0, st, g.dev, dinv, w->r, u, (const T*)dnew,
                            (const T*)pv, sv, it, (const double*)P.dp, np_dp, (const double*)w->gam, P.rmax, rs_next, ss_next);
     else
-        hipLaunchKernelGGL((k_cg_update<T, 2>), dim3(nb), dim3(kBlock), 0, st, g.dev, dinv, w->r, u, (const T*)dnew,
+        uno_launch(UNO_KT_UPDATE, k_cg_update<T, 2>, dim3(nb), dim3(kBlock), 0, st, g.dev, dinv, w->r, u, (const T*)dnew,
                            (const T*)pv, sv, it, (const double*)P.dp, np_dp, (const double*)w->gam, P.rmax, rs_next, ss_next);
-    ktimer_end(&kt);
     UNO_HIP(hipGetLastError());
     return UNO_OK;
 }

@@ -392,7 +392,6 @@ static uno_status run_passes(const Grid& g, const FftPlan& p, const TT* table, c
     if (itp) it = *itp;
     const int64_t rows = (int64_t)g.n[0] * g.n[1];
     const int nh = p.nh;
-    KTimer kt;
     // pass 1
     {
         AxisDev az = axis_dev(p.ax[2], f64);
@@ -400,9 +399,7 @@ static uno_status run_passes(const Grid& g, const FftPlan& p, const TT* table, c
         int64_t pairs = (rows + 1) / 2;
         int nb = (int)((pairs + nl - 1) / nl);
         size_t sh = 2 * sizeof(C) * (size_t)nl * az.n;
-        ktimer_begin(&kt, UNO_KT_FFT_FWD, stream);
-        hipLaunchKernelGGL(k_fft_r2c_z<T>, dim3(nb), dim3(kBlock), sh, stream, rows, nl, az, nh, r, S, it);
-        ktimer_end(&kt);
+        uno_launch(UNO_KT_FFT_FWD, k_fft_r2c_z<T>, dim3(nb), dim3(kBlock), sh, stream, rows, nl, az, nh, r, S, it);
         UNO_HIP(hipGetLastError());
     }
     // pass 2: y forward (st = nh, outer = n0)
@@ -423,10 +420,8 @@ static uno_status run_passes(const Grid& g, const FftPlan& p, const TT* table, c
         int64_t nlines = (int64_t)g.n[1] * nh;
         int nb = (int)((nlines + nl - 1) / nl);
         size_t sh = 2 * sizeof(C) * (size_t)nl * ax.n;
-        ktimer_begin(&kt, UNO_KT_FFT_MID, stream);
-        hipLaunchKernelGGL((k_fft_strided<T, -1, true, TT>), dim3(nb), dim3(kBlock), sh, stream, nlines, nlines, nl, ax,
-                           S, table, it);
-        ktimer_end(&kt);
+        uno_launch(UNO_KT_FFT_MID, k_fft_strided<T, -1, true, TT>, dim3(nb), dim3(kBlock), sh, stream, nlines, nlines, nl,
+                   ax, S, table, it);
         UNO_HIP(hipGetLastError());
     }
     // pass 4: y inverse
@@ -446,10 +441,8 @@ static uno_status run_passes(const Grid& g, const FftPlan& p, const TT* table, c
         int64_t pairs = (rows + 1) / 2;
         int nb = (int)((pairs + nl - 1) / nl);
         size_t sh = 2 * sizeof(C) * (size_t)nl * az.n;
-        ktimer_begin(&kt, UNO_KT_FFT_INV, stream);
-        hipLaunchKernelGGL(k_fft_c2r_z<T>, dim3(nb), dim3(kBlock), sh, stream, rows, nl, az, nh, (const C*)S, s, it);
+        uno_launch(UNO_KT_FFT_INV, k_fft_c2r_z<T>, dim3(nb), dim3(kBlock), sh, stream, rows, nl, az, nh, (const C*)S, s, it);
         if (np_rs) *np_rs = nb;
-        ktimer_end(&kt);
         UNO_HIP(hipGetLastError());
     }
     return UNO_OK;

@@ -408,12 +408,9 @@ static CgIter no_iter()
 // pass A on r (no update); also the initial transform of the CG loop
 uno_status lowrank_forward(const LowRankPlan* p, const double* r, hipStream_t st)
 {
-    KTimer kt;
-    ktimer_begin(&kt, UNO_KT_FFT_FWD, st);
-    hipLaunchKernelGGL((k_lr_fwd<false, double>), dim3(p->blocks_a), dim3(256), p->lds_a, st, p->dev, p->ya, (double*)r,
-                       (double*)nullptr, (const double*)nullptr, (const double*)nullptr, p->Gp, no_iter(),
-                       (const double*)nullptr, 0, (const double*)nullptr, (double*)nullptr);
-    ktimer_end(&kt);
+    uno_launch(UNO_KT_FFT_FWD, k_lr_fwd<false, double>, dim3(p->blocks_a), dim3(256), p->lds_a, st, p->dev, p->ya,
+               (double*)r, (double*)nullptr, (const double*)nullptr, (const double*)nullptr, p->Gp, no_iter(),
+               (const double*)nullptr, 0, (const double*)nullptr, (double*)nullptr);
     return hip_status(hipGetLastError());
 }
 
@@ -423,11 +420,8 @@ uno_status lowrank_update_forward(const LowRankPlan* p, double* r, double* u, co
                                   const CgIter& it, const double* part_dp, int np_dp, const double* gam,
                                   double* part_rmax, hipStream_t st)
 {
-    KTimer kt;
-    ktimer_begin(&kt, UNO_KT_UPDATE, st);
-    hipLaunchKernelGGL((k_lr_fwd<true, T>), dim3(p->blocks_a), dim3(256), p->lds_a, st, p->dev, p->ya, r, u, d, pv,
-                       p->Gp, it, part_dp, np_dp, gam, part_rmax);
-    ktimer_end(&kt);
+    uno_launch(UNO_KT_UPDATE, k_lr_fwd<true, T>, dim3(p->blocks_a), dim3(256), p->lds_a, st, p->dev, p->ya, r, u, d, pv,
+               p->Gp, it, part_dp, np_dp, gam, part_rmax);
     return hip_status(hipGetLastError());
 }
 
@@ -438,20 +432,15 @@ uno_status lowrank_finish(const LowRankPlan* p, const double* r, T* s, const CgI
 {
     const LowRankDev& L = p->dev;
     const CgIter it = itp ? *itp : no_iter();
-    KTimer kt;
-    ktimer_begin(&kt, UNO_KT_FFT_MID, st);
-    hipLaunchKernelGGL(k_lr_mid, dim3(L.kyn * L.kzn), dim3(64), p->lds_b, st, L, p->nch_a, (const double*)p->table,
-                       (const double2*)p->Gp, p->H, it);
-    ktimer_end(&kt);
+    uno_launch(UNO_KT_FFT_MID, k_lr_mid, dim3(L.kyn * L.kzn), dim3(64), p->lds_b, st, L, p->nch_a,
+               (const double*)p->table, (const double2*)p->Gp, p->H, it);
     UNO_HIP(hipGetLastError());
-    ktimer_begin(&kt, UNO_KT_FFT_INV, st);
     if (itp)
-        hipLaunchKernelGGL((k_lr_inv<true, T>), dim3(p->blocks_c), dim3(256), p->lds_c, st, L, p->yc, r,
-                           (const double2*)p->H, s, it);
+        uno_launch(UNO_KT_FFT_INV, k_lr_inv<true, T>, dim3(p->blocks_c), dim3(256), p->lds_c, st, L, p->yc, r,
+                   (const double2*)p->H, s, it);
     else
-        hipLaunchKernelGGL((k_lr_inv<false, T>), dim3(p->blocks_c), dim3(256), p->lds_c, st, L, p->yc, r,
-                           (const double2*)p->H, s, it);
-    ktimer_end(&kt);
+        uno_launch(UNO_KT_FFT_INV, k_lr_inv<false, T>, dim3(p->blocks_c), dim3(256), p->lds_c, st, L, p->yc, r,
+                   (const double2*)p->H, s, it);
     UNO_HIP(hipGetLastError());
     if (np_rs) *np_rs = p->blocks_c;
     return UNO_OK;

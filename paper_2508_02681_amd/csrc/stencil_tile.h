@@ -297,16 +297,16 @@ inline void launch_tile_tx(const TileChoice& c, const GridDev& g, const T* kappa
 {
     switch (c.tz) {
         case 64:
-            hipLaunchKernelGGL((k_stencil_tile<T, TX, 64, CG, HEAD>), dim3(c.blocks), dim3(256), 0, st, g, c.geom,
-                               kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam, mf);
+            uno_launch(UNO_KT_MATVEC, k_stencil_tile<T, TX, 64, CG, HEAD>, dim3(c.blocks), dim3(256), 0, st, g, c.geom,
+                       kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam, mf);
             break;
         case 32:
-            hipLaunchKernelGGL((k_stencil_tile<T, TX, 32, CG, HEAD>), dim3(c.blocks), dim3(256), 0, st, g, c.geom,
-                               kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam, mf);
+            uno_launch(UNO_KT_MATVEC, k_stencil_tile<T, TX, 32, CG, HEAD>, dim3(c.blocks), dim3(256), 0, st, g, c.geom,
+                       kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam, mf);
             break;
         default:
-            hipLaunchKernelGGL((k_stencil_tile<T, TX, 16, CG, HEAD>), dim3(c.blocks), dim3(256), 0, st, g, c.geom,
-                               kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam, mf);
+            uno_launch(UNO_KT_MATVEC, k_stencil_tile<T, TX, 16, CG, HEAD>, dim3(c.blocks), dim3(256), 0, st, g, c.geom,
+                       kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam, mf);
             break;
     }
 }

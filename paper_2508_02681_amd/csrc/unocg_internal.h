@@ -8,6 +8,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <cstdint>
 #include <cstdio>
 #include <vector>
@@ -46,15 +47,24 @@ template <typename T> struct cplx_t;
 template <> struct cplx_t<double> { using type = double2; };
 template <> struct cplx_t<float> { using type = float2; };
 
-// Launch bookkeeping for the optional per-family kernel timing.
-struct KTimer {
-    int which;
-    hipStream_t stream;
-    bool active;
+// Optional per-family kernel timing: when family `fam` is being timed the
+// launch carries start/stop events recorded around the dispatch itself
+// (hipExtLaunchKernelGGL), otherwise it is a plain launch.
+bool ktimer_take(int fam, hipEvent_t* a, hipEvent_t* b);
+void ktimer_push(hipEvent_t a, hipEvent_t b);
+
+template <typename... Formals, typename... Args>
+inline void uno_launch(int fam, void (*kernel)(Formals...), dim3 grid, dim3 block, size_t sh, hipStream_t st,
+                       Args... args)
+{
     hipEvent_t a, b;
-};
-void ktimer_begin(KTimer* t, int which, hipStream_t s);
-void ktimer_end(KTimer* t);
+    if (fam != UNO_KT_NONE && ktimer_take(fam, &a, &b)) {
+        hipExtLaunchKernelGGL(kernel, grid, block, (std::uint32_t)sh, st, a, b, 0u, args...);
+        ktimer_push(a, b);
+    } else {
+        hipLaunchKernelGGL(kernel, grid, block, sh, st, args...);
+    }
+}
 
 // Status of the last HIP error inside a launch helper
 uno_status hip_status(hipError_t e);
