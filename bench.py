@@ -36,6 +36,28 @@ SHAPE = (64, 64, 64)
 LOADS = np.eye(3)
 RTOL = 1e-6
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per launch from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs of
+# this benchmark (64^3, M = 12), each scaled by what the counter reads for a
+# device copy of known size (FETCH x 2, WRITE x 1); the summary with its
+# commands is profiles/k_lr_tile_64cubed_hbm_counters.md.  Valid only for the
+# kernel sources as they were when counted (TRAFFIC_SRC: hash of the files in
+# TRAFFIC_FILES); after any change the figure is withheld.
+TRAFFIC_FILES = ["lowrank.hip", "stencil_tile.h", "cg_ctl.h", "reduce.h"]
+TRAFFIC_SRC = "969670fcd4e6a152"
+TRAFFIC_BYTES = {
+    "k_lr_tile<2,32>": int((2 * 7727.3 + 3773.1) * 1024),
+    "k_lr_fwd<update,double>": int((2 * 4183.2 + 4451.1) * 1024),
+    "k_lr_mid": int((2 * 3377.5 + 370.5) * 1024),
+}
+
+
+def kernel_sources_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_FILES:
+        with open(os.path.join(ROOT, "paper_2508_02681_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def log(*a):
@@ -219,14 +241,14 @@ def main():
     nspec = SHAPE[0] * SHAPE[1] * (SHAPE[2] // 2 + 1)
     nblk = SHAPE[0] * (2 * M + 1) * (M + 1)   # learned block after the two partial DFTs (y, z)
     if learned:
-        fams = {uno.KT_MATVEC: "k_stencil_tile<double,CG>", uno.KT_UPDATE: "k_lr_fwd<update,double>",
-                uno.KT_FFT_MID: "k_lr_mid", uno.KT_FFT_INV: "k_lr_inv<double>"}
+        # FP64 CG on the learned modes: pass B -> [pass C + operator] -> [update + pass A]
+        fams = {uno.KT_MATVEC: "k_lr_tile<2,32>", uno.KT_UPDATE: "k_lr_fwd<update,double>",
+                uno.KT_FFT_MID: "k_lr_mid"}
         # algorithmic bytes per launch (FP64): the minimum each kernel must move
         bytes_per = {
-            uno.KT_MATVEC: n_dof * 8 * 5,            # read s, d_old, kappa; write d_new, p
+            uno.KT_MATVEC: n_dof * 8 * 5 + nblk * 16,  # read r, d_old, kappa, H; write d_new, p
             uno.KT_UPDATE: n_dof * 8 * 6 + nblk * 16,  # read r, u, d, p; write r, u, block spectrum
             uno.KT_FFT_MID: nblk * 16 * 2 + nblk * 8,  # block spectrum in/out + table
-            uno.KT_FFT_INV: n_dof * 8 * 2 + nblk * 16,  # read r and block; write s
         }
     else:
         fams = {uno.KT_MATVEC: "k_stencil_tile<double,CG>", uno.KT_UPDATE: "k_cg_update<double>",
@@ -250,8 +272,9 @@ def main():
     tot, nl = fam_ms[dom]
     avg_s = tot / max(nl, 1) / 1e3
     achieved = bytes_per[dom] / avg_s / 1e9
+    traffic = TRAFFIC_BYTES.get(fams[dom]) if (learned and kernel_sources_hash() == TRAFFIC_SRC) else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": fams[dom], "avg_us": round(avg_s * 1e6, 2), "bytes_per_launch": bytes_per[dom],
                 "per_family_us": {fams[f]: round(fam_ms[f][0] / max(fam_ms[f][1], 1) * 1e3, 2) for f in fams}}
 

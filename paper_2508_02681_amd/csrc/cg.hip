@@ -428,14 +428,27 @@ static uno_status enqueue_pass(const Grid& g, Workspace* w, int kind, const uno_
     int np_rs = nb;
     const MeanFree mf{P.ss[k & 1], P.ds[k & 1], P.ds[(k + 1) & 1]};
     if (kind == UNO_PREC_UNO && uno_use_lowrank(pc)) {
-        // learned-mode flow: [B (head) + C] -> matvec -> [update + A of pass k+1]
         CgIter it = iter_of(w, P, k, k0, rtol, hist_len, lowrank_update_blocks(pc->lr));
+        if constexpr (sizeof(T) == sizeof(double)) {
+            if (lowrank_fused(pc->lr)) {
+                // fused FP64 flow: B (head, Parseval partials) -> [C + matvec] -> [update + A of pass k+1];
+                // ||r||^2 partials in rs[0], the learned-mode part of r.s in rs[1]
+                int np_dp = 0;
+                uno_status e = lowrank_fused_pass(pc->lr, g, (const double*)kappa, w->r, (const double*)dold,
+                                                  (double*)dnew, (double*)pv, P.dp, it, P.rs[1], P.rs[0], w->gam, st,
+                                                  &np_dp);
+                if (e != UNO_OK) return e;
+                return lowrank_update_forward<double>(pc->lr, w->r, u, (const double*)dnew, (const double*)pv, it, P.dp,
+                                                      np_dp, w->gam, P.rmax, P.rs[0], st);
+            }
+        }
+        // learned-mode flow: [B (head) + C] -> matvec -> [update + A of pass k+1]
         uno_status e = lowrank_finish<T>(pc->lr, w->r, sv, &it, &np_rs, st);
         if (e != UNO_OK) return e;
         const int np_dp =
             launch_tile<T, true, false>(g, kappa, sv, dold, dnew, pv, P.dp, it, P.rs[k & 1], np_rs, w->gam, st, mf);
         UNO_HIP(hipGetLastError());
-        return lowrank_update_forward<T>(pc->lr, w->r, u, dnew, pv, it, P.dp, np_dp, w->gam, P.rmax, st);
+        return lowrank_update_forward<T>(pc->lr, w->r, u, dnew, pv, it, P.dp, np_dp, w->gam, P.rmax, nullptr, st);
     }
     CgIter it = iter_of(w, P, k, k0, rtol, hist_len, nb);
     if (kind == UNO_PREC_UNO) {
@@ -498,7 +511,10 @@ static uno_status pcg_loop(const Grid& g, Workspace* w, const double* kappa64, c
             hipLaunchKernelGGL((k_cg_init<T, 2>), dim3(nb), dim3(kBlock), 0, st, g.dev, (const T*)dinv,
                                (const double*)w->r, sv, P.rmax, P.rs[0], P.ss[0], w->state);
         UNO_HIP(hipGetLastError());
-        if (lowrank) return lowrank_forward(pc->lr, w->r, st);  // transform of r for the first pass
+        if (lowrank) {  // transform of r for the first pass (and ||r||^2 in the fused flow)
+            const bool fused = sizeof(T) == sizeof(double) && lowrank_fused(pc->lr);
+            return lowrank_forward(pc->lr, w->r, fused ? P.rs[0] : nullptr, st);
+        }
         return UNO_OK;
     };
     uno_status e = start();

@@ -25,6 +25,7 @@
 #include "unocg_internal.h"
 #include "reduce.h"
 #include "cg_ctl.h"
+#include "stencil_tile.h"
 
 namespace unocg {
 
@@ -55,7 +56,8 @@ __global__ void __launch_bounds__(256) k_lr_fwd(LowRankDev L, int ny_chunk, doub
                                                 double* __restrict__ u, const TD* __restrict__ d,
                                                 const TD* __restrict__ p, double2* __restrict__ Gp, CgIter it,
                                                 const double* __restrict__ part_dp, int np_dp,
-                                                const double* __restrict__ gam, double* __restrict__ part_rmax)
+                                                const double* __restrict__ gam, double* __restrict__ part_rmax,
+                                                double* __restrict__ part_rr)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double slots[4];
@@ -69,7 +71,7 @@ __global__ void __launch_bounds__(256) k_lr_fwd(LowRankDev L, int ny_chunk, doub
     double* R = (double*)(Z + ny_chunk * L.kzn);   // ny_chunk x n2
     const int64_t base = ((int64_t)x * L.n1 + y0) * L.n2;
     const int cnt = ny * L.n2;
-    double m = 0.0;
+    double m = 0.0, sq = 0.0;
     // all global loads first (state, partials, gamma, the first PF elements
     // of the four vectors, twiddles); decisions come after
     constexpr int PF = 4;
@@ -113,6 +115,7 @@ __global__ void __launch_bounds__(256) k_lr_fwd(LowRankDev L, int ny_chunk, doub
                 u[base + q] = uv[j] + alpha * dv[j];
                 R[q] = rn;
                 m = OpMax::apply(m, fabs(rn));
+                sq += rn * rn;
             }
         }
         for (int q = threadIdx.x + 256 * PF; q < cnt; q += 256) {
@@ -122,14 +125,22 @@ __global__ void __launch_bounds__(256) k_lr_fwd(LowRankDev L, int ny_chunk, doub
             u[i] += alpha * (double)d[i];
             R[q] = rn;
             m = OpMax::apply(m, fabs(rn));
+            sq += rn * rn;
         }
     } else {
 #pragma unroll
         for (int j = 0; j < PF; ++j) {
             const int q = threadIdx.x + 256 * j;
-            if (q < cnt) R[q] = rv[j];
+            if (q < cnt) {
+                R[q] = rv[j];
+                sq += rv[j] * rv[j];
+            }
         }
-        for (int q = threadIdx.x + 256 * PF; q < cnt; q += 256) R[q] = r[base + q];
+        for (int q = threadIdx.x + 256 * PF; q < cnt; q += 256) {
+            const double v = r[base + q];
+            R[q] = v;
+            sq += v * v;
+        }
     }
     __syncthreads();
     for (int q = threadIdx.x; q < ny * L.kzn; q += 256) {
@@ -170,13 +181,22 @@ __global__ void __launch_bounds__(256) k_lr_fwd(LowRankDev L, int ny_chunk, doub
         const double bm = block_reduce<OpMax>(m, slots);
         if (threadIdx.x == 0) part_rmax[blockIdx.x] = bm;
     }
+    if (part_rr) {  // ||r||^2 partials: r.s by Parseval in the fused flow
+        const double bs = block_reduce<OpSum>(sq, slots);
+        if (threadIdx.x == 0) part_rr[blockIdx.x] = bs;
+    }
 }
 
 // Pass B: one wavefront per (k_y, k_z) column: add the row-chunk partials,
 // transform along x, multiply by the table, transform back.  Inside CG it is
 // the first kernel of a pass and runs the convergence test.
+//
+// With part_corr, it also writes per column sum_kx C(k) |X(k)|^2: by
+// Parseval, r.s = W ||r||^2 + (sum of these), since the table holds
+// w(k_z) (Phi(k) - W) / n and X is the unnormalized DFT of r on the block.
 __global__ void __launch_bounds__(64) k_lr_mid(LowRankDev L, int nch, const double* __restrict__ C,
-                                               const double2* __restrict__ Gp, double2* __restrict__ H, CgIter it)
+                                               const double2* __restrict__ Gp, double2* __restrict__ H, CgIter it,
+                                               double* __restrict__ part_corr)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double slots[4];
@@ -205,6 +225,7 @@ __global__ void __launch_bounds__(64) k_lr_mid(LowRankDev L, int nch, const doub
     }
     if (it.st && head_decide(it, sl, share, slots)) return;
     __syncthreads();
+    double corr = 0.0;
     for (int kxi = threadIdx.x; kxi < L.kxn; kxi += blockDim.x) {
         const int step = mod_n(kxi - L.mx, L.n0);
         double re = 0.0, im = 0.0;
@@ -220,6 +241,11 @@ __global__ void __launch_bounds__(64) k_lr_mid(LowRankDev L, int nch, const doub
         }
         const double c = C[(int64_t)kxi * plane + col];
         X[kxi] = make_double2(re * c, im * c);
+        corr += c * (re * re + im * im);
+    }
+    if (part_corr) {
+        const double b = block_reduce<OpSum>(corr, slots);
+        if (threadIdx.x == 0) part_corr[col] = b;
     }
     __syncthreads();
     for (int x = threadIdx.x; x < L.n0; x += blockDim.x) {
@@ -324,6 +350,294 @@ __global__ void __launch_bounds__(256) k_lr_inv(LowRankDev L, int y_chunk, const
     }
 }
 
+
+// Fused flow inside FP64 CG: pass C folded into the operator apply.  The
+// tile kernel evaluates s = W r + correction itself on its tile and halo
+// (from r and the H planes of its x-range), so s is never stored, and r.s
+// comes from Parseval: r.s = W ||r||^2 + sum_k C(k) |X(k)|^2 (partials of
+// pass A and pass B).  Then, as in the operator-apply tile kernel,
+// d = s + beta d_old, p = A d and the d.p partials.
+//
+// The corrections are evaluated with Horner's rule in the unit-modulus
+// phase factor: along y, V[x][y][k_z] = sum_{k_y} H[x][k_y][k_z] w_y^{k_y}
+// with w_y = exp(+2 pi i y / n1); along z, Re sum_{k_z} V w_z^{k_z}.  (The
+// two contractions are small and latency-bound here; written for the FP64
+// matrix cores they measured slower on this chip.)
+struct LrTileArgs {
+    const double* part_rr;    // ||r||^2 partials (pass A)
+    int np_rr;
+    const double* part_corr;  // sum C |X|^2 partials (pass B)
+    int np_corr;
+};
+
+// double2 elements of dynamic LDS of k_lr_tile: H planes and V
+__host__ __device__ inline int lr_tile_dyn_elems(int dx, int dy, int kyn, int kzn)
+{
+    return dx * kyn * kzn + dx * dy * kzn;
+}
+
+template <int TX, int TZ, bool NEAR>
+__global__ void __launch_bounds__(256) k_lr_tile(GridDev g, TileGeom tg, LowRankDev L, const double* __restrict__ kappa,
+                                                 const double* __restrict__ r, const double2* __restrict__ H,
+                                                 const double* __restrict__ dold, double* __restrict__ dnew,
+                                                 double* __restrict__ p, double* __restrict__ part_dp, CgIter it,
+                                                 LrTileArgs a, double* gam)
+{
+    constexpr int TY = 256 / TZ;
+    constexpr int DX = TX + 2, DY = TY + 2, DZ = TZ + 2;
+    constexpr int KX = TX + 1, KY = TY + 1, KZ = TZ + 1;
+    constexpr int HB = 2;  // H values per thread and plane held in registers (the rest is copied after)
+    __shared__ double Dl[DX * DY * DZ];
+    __shared__ double Kl[KX * KY * KZ];
+    __shared__ double2 wz[DZ], wy[DY], wyM[DY];
+    __shared__ double slots[4];
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int plane = L.kyn * L.kzn;
+    double2* Hl = (double2*)smem;  // DX planes of H   [xl][k_y][k_z]
+    double2* V = Hl + DX * plane;  // y-inverse of H   [xl][yl][k_z]
+
+    int b = blockIdx.x;
+    const int tzi = b % tg.tiles_z;
+    b /= tg.tiles_z;
+    const int tyi = b % tg.tiles_y;
+    const int txi = b / tg.tiles_y;
+    const int x0 = txi * TX, y0 = tyi * TY, z0 = tzi * TZ;
+
+    // every global load first: state, both partial sets, previous gamma, r
+    // and d_old on the halo, conductivities, H planes, phase factors
+    const StateLoad sl = load_state(it.st);
+    const double rr_share = load_share<OpSum>(a.part_rr, a.np_rr);
+    const double cr_share = load_share<OpSum>(a.part_corr, a.np_corr);
+    const double gprev = (it.k > it.k0) ? gam[it.k - 1] : 1.0;
+    constexpr int ND = DX * DY * DZ, NK = KX * KY * KZ;
+    constexpr int PD = (ND + 255) / 256, PK = (NK + 255) / 256;
+    auto wrapc = [](int v, int n) {
+        if constexpr (NEAR) return wrap_near(v, n);
+        else return wrap_mod(v, n);
+    };
+    double rv[PD], dv[PD], kv[PK];
+    double2 hv[DX][HB];
+#pragma unroll
+    for (int xl = 0; xl < DX; ++xl) {
+        const double2* hp = H + (int64_t)wrapc(x0 - 1 + xl, g.n0) * plane;
+#pragma unroll
+        for (int u = 0; u < HB; ++u) {
+            const int c = threadIdx.x + 256 * u;
+            hv[xl][u] = (c < plane) ? hp[c] : make_double2(0.0, 0.0);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < PD; ++j) {
+        const int q = threadIdx.x + 256 * j;
+        rv[j] = dv[j] = 0.0;
+        if (q < ND) {
+            const int zl = q % DZ, t = q / DZ;
+            const int yl = t % DY, xl = t / DY;
+            const int x = wrapc(x0 - 1 + xl, g.n0), y = wrapc(y0 - 1 + yl, g.n1), z = wrapc(z0 - 1 + zl, g.n2);
+            const int64_t idx = ((int64_t)x * g.n1 + y) * g.n2 + z;
+            rv[j] = r[idx];
+            if (it.k > it.k0) dv[j] = dold[idx];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < PK; ++j) {
+        const int q = threadIdx.x + 256 * j;
+        kv[j] = 0.0;
+        if (q < NK) {
+            const int zl = q % KZ, t = q / KZ;
+            const int yl = t % KY, xl = t / KY;
+            const int x = wrapc(x0 - 1 + xl, g.n0), y = wrapc(y0 - 1 + yl, g.n1), z = wrapc(z0 - 1 + zl, g.n2);
+            kv[j] = kappa[((int64_t)x * g.n1 + y) * g.n2 + z];
+        }
+    }
+    // phase factors of the tile: w_z, w_y (conjugates of the exp(-...) tables) and w_y^{-M}
+    double2 tw = make_double2(0.0, 0.0);
+    {
+        const int t = threadIdx.x;
+        if (t < DZ) {
+            tw = L.twz[wrapc(z0 - 1 + t, g.n2)];
+        } else if (t < DZ + DY) {
+            tw = L.twy[wrapc(y0 - 1 + (t - DZ), g.n1)];
+        } else if (t < DZ + 2 * DY) {
+            const int y = wrapc(y0 - 1 + (t - DZ - DY), g.n1);
+            tw = L.twy[(L.m * y) % g.n1];
+        }
+    }
+    if (ended(sl, it.k)) return;
+    const int k = it.k;
+    const double rr = combine_share<OpSum>(rr_share, slots);
+    const double cr = combine_share<OpSum>(cr_share, slots);
+    const double gk = L.W * rr + cr;
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    if (lead) gam[k] = gk;
+    if (!(gk > 0.0) || !isfinite(gk)) {
+        if (lead) { it.st->status = 1; it.st->fail_iter = k; }
+        return;
+    }
+    const bool first = (k == it.k0);
+    const double beta = first ? 0.0 : gk / gprev;
+    // LDS: staged W r + beta d_old (the correction is added below),
+    // conductivities, H planes, phase factors
+#pragma unroll
+    for (int j = 0; j < PD; ++j) {
+        const int q = threadIdx.x + 256 * j;
+        if (q < ND) Dl[q] = first ? L.W * rv[j] : L.W * rv[j] + beta * dv[j];
+    }
+#pragma unroll
+    for (int j = 0; j < PK; ++j) {
+        const int q = threadIdx.x + 256 * j;
+        if (q < NK) Kl[q] = kv[j];
+    }
+#pragma unroll
+    for (int xl = 0; xl < DX; ++xl) {
+#pragma unroll
+        for (int u = 0; u < HB; ++u) {
+            const int c = threadIdx.x + 256 * u;
+            if (c < plane) Hl[xl * plane + c] = hv[xl][u];
+        }
+        if (plane > 256 * HB) {
+            const double2* hp = H + (int64_t)wrapc(x0 - 1 + xl, g.n0) * plane;
+            for (int c = threadIdx.x + 256 * HB; c < plane; c += 256) Hl[xl * plane + c] = hp[c];
+        }
+    }
+    {
+        const int t = threadIdx.x;
+        if (t < DZ) wz[t] = make_double2(tw.x, -tw.y);
+        else if (t < DZ + DY) wy[t - DZ] = make_double2(tw.x, -tw.y);
+        else if (t < DZ + 2 * DY) wyM[t - DZ - DY] = tw;
+    }
+    __syncthreads();
+    // V[xl][yl][kz]: inverse partial DFT along y, Horner in w_y.  A thread
+    // owns one (xl, kz) column and a pair of rows yl, yl + YH, so each H value
+    // read from LDS feeds two independent chains.
+    {
+        constexpr int YH = (DY + 1) / 2;
+        const int nt = DX * L.kzn * YH;
+        for (int t = threadIdx.x; t < nt; t += 256) {
+            const int ya = t % YH, c = t / YH;
+            const int kz = c % L.kzn, xl = c / L.kzn;
+            const int yb = (ya + YH < DY) ? ya + YH : ya;
+            const double2 wa = wy[ya], wb = wy[yb];
+            const double2* hcol = Hl + xl * plane + kz;
+            double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
+            auto step = [&](const double2 h) {
+                const double nar = ar * wa.x - ai * wa.y + h.x;
+                ai = ar * wa.y + ai * wa.x + h.y;
+                ar = nar;
+                const double nbr = br * wb.x - bi * wb.y + h.x;
+                bi = br * wb.y + bi * wb.x + h.y;
+                br = nbr;
+            };
+            int kyi = L.kyn - 1;
+            for (; kyi >= 3; kyi -= 4) {  // four LDS reads in flight per round
+                const double2 h0 = hcol[kyi * L.kzn], h1 = hcol[(kyi - 1) * L.kzn];
+                const double2 h2 = hcol[(kyi - 2) * L.kzn], h3 = hcol[(kyi - 3) * L.kzn];
+                step(h0);
+                step(h1);
+                step(h2);
+                step(h3);
+            }
+            for (; kyi >= 0; --kyi) step(hcol[kyi * L.kzn]);
+            const double2 sa = wyM[ya], sb = wyM[yb];  // times w_y^-M
+            V[(xl * DY + ya) * L.kzn + kz] = make_double2(ar * sa.x - ai * sa.y, ar * sa.y + ai * sa.x);
+            if (yb != ya) V[(xl * DY + yb) * L.kzn + kz] = make_double2(br * sb.x - bi * sb.y, br * sb.y + bi * sb.x);
+        }
+    }
+    __syncthreads();
+    // s = (W r + beta d_old, already staged) + Re sum_kz V w_z^kz: a thread
+    // owns ZPT points of one staged row, so each V value read from LDS feeds
+    // ZPT independent Horner chains
+    {
+        constexpr int ROWS = DX * DY;
+        constexpr int TPR = (256 / ROWS) > 0 ? 256 / ROWS : 1;
+        constexpr int ZPT = (DZ + TPR - 1) / TPR;
+        for (int t = threadIdx.x; t < ROWS * TPR; t += 256) {
+            const int row = t / TPR, part = t % TPR;
+            double ar[ZPT], ai[ZPT];
+            double2 w[ZPT];
+#pragma unroll
+            for (int i = 0; i < ZPT; ++i) {
+                const int zl = part + TPR * i;
+                w[i] = wz[zl < DZ ? zl : 0];
+                ar[i] = ai[i] = 0.0;
+            }
+            const double2* vrow = V + row * L.kzn;
+            auto step = [&](const double2 v) {
+#pragma unroll
+                for (int i = 0; i < ZPT; ++i) {
+                    const double nr = ar[i] * w[i].x - ai[i] * w[i].y + v.x;
+                    ai[i] = ar[i] * w[i].y + ai[i] * w[i].x + v.y;
+                    ar[i] = nr;
+                }
+            };
+            int kz = L.kzn - 1;
+            for (; kz >= 3; kz -= 4) {
+                const double2 v0 = vrow[kz], v1 = vrow[kz - 1], v2 = vrow[kz - 2], v3 = vrow[kz - 3];
+                step(v0);
+                step(v1);
+                step(v2);
+                step(v3);
+            }
+            for (; kz >= 0; --kz) step(vrow[kz]);
+#pragma unroll
+            for (int i = 0; i < ZPT; ++i) {
+                const int zl = part + TPR * i;
+                if (zl < DZ) Dl[row * DZ + zl] += ar[i];
+            }
+        }
+    }
+    __syncthreads();
+
+    const int tz = threadIdx.x % TZ, ty = threadIdx.x / TZ;
+    const int y = y0 + ty, z = z0 + tz;
+    const bool yz_ok = (y < g.n1) && (z < g.n2);
+    double dm[3][3], d0[3][3], dq[3][3], km[2][2], kp[2][2];
+#pragma unroll
+    for (int bb = 0; bb < 3; ++bb)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            dm[bb][c] = Dl[(0 * DY + ty + bb) * DZ + tz + c];
+            d0[bb][c] = Dl[(1 * DY + ty + bb) * DZ + tz + c];
+        }
+#pragma unroll
+    for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) km[bb][c] = Kl[(0 * KY + ty + bb) * KZ + tz + c];
+    double dot = 0.0;
+#pragma unroll
+    for (int xi = 0; xi < TX; ++xi) {
+#pragma unroll
+        for (int bb = 0; bb < 3; ++bb)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) dq[bb][c] = Dl[((xi + 2) * DY + ty + bb) * DZ + tz + c];
+#pragma unroll
+        for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) kp[bb][c] = Kl[((xi + 1) * KY + ty + bb) * KZ + tz + c];
+        const int x = x0 + xi;
+        if (yz_ok && x < g.n0) {
+            const double acc = stencil_node<double>(g, dm, d0, dq, km, kp);
+            const int64_t i = ((int64_t)x * g.n1 + y) * g.n2 + z;
+            p[i] = acc;
+            dnew[i] = d0[1][1];
+            dot += d0[1][1] * acc;
+        }
+#pragma unroll
+        for (int bb = 0; bb < 3; ++bb)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                dm[bb][c] = d0[bb][c];
+                d0[bb][c] = dq[bb][c];
+            }
+#pragma unroll
+        for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) km[bb][c] = kp[bb][c];
+    }
+    const double bd = block_reduce<OpSum>(dot, slots);
+    if (threadIdx.x == 0) part_dp[blockIdx.x] = bd;
+}
+
 // ----------------------------------------------------------------------------
 // host
 
@@ -336,7 +650,21 @@ struct LowRankPlan {
     int nch_a;
     int blocks_a, blocks_c;
     size_t lds_a, lds_b, lds_c;
+    bool fused;       // the fused operator tile fits (FP64 CG flow)
+    TileChoice tile;  // its tile shape
+    size_t lds_t;     // its dynamic LDS
 };
+
+// static LDS of k_lr_tile<TX, TZ> plus the dynamic part (H planes, V)
+static size_t lr_tile_lds(const LowRankDev& L, int tx, int tz, size_t* dyn)
+{
+    const int ty = 256 / tz;
+    const size_t dx = tx + 2, dy = ty + 2, dz = tz + 2;
+    const size_t stat = sizeof(double) * (dx * dy * dz + (size_t)(tx + 1) * (ty + 1) * (tz + 1)) + 4 * sizeof(double) +
+                        sizeof(double2) * (dz + 2 * dy);
+    *dyn = sizeof(double2) * (size_t)lr_tile_dyn_elems((int)dx, (int)dy, L.kyn, L.kzn);
+    return stat + *dyn;
+}
 
 uno_status lowrank_create(const Grid& g, const FftPlan& fp, int M, double W, const std::vector<double>& cblock,
                           LowRankPlan** out)
@@ -372,6 +700,15 @@ uno_status lowrank_create(const Grid& g, const FftPlan& fp, int M, double W, con
     p->lds_b = sizeof(double2) * (2 * (size_t)L.n0 + L.kxn);
     p->lds_c = sizeof(double2) * ((size_t)L.n2 + L.n1 + (size_t)plane + (size_t)p->yc * L.kzn);
     if (p->lds_a > 60 * 1024 || p->lds_b > 60 * 1024 || p->lds_c > 60 * 1024) { delete p; return UNO_ERR_SHAPE; }
+    // fused operator tile: the apply's tile shape, 2-deep in x if 4 does not fit
+    p->tile = choose_tile(g);
+    size_t dyn = 0;
+    if (p->tile.tx == 4 && lr_tile_lds(L, 4, p->tile.tz, &dyn) > 64 * 1024) {
+        p->tile.tx = 2;
+        p->tile.blocks = ((g.n[0] + 1) / 2) * p->tile.geom.tiles_y * p->tile.geom.tiles_z;
+    }
+    p->fused = lr_tile_lds(L, p->tile.tx, p->tile.tz, &dyn) <= 64 * 1024;
+    p->lds_t = dyn;
     const int64_t ngp = (int64_t)L.n0 * p->nch_a * plane;
     const int64_t nh = (int64_t)L.n0 * plane;
     if (hipMalloc(&p->table, sizeof(double) * nb) != hipSuccess ||
@@ -395,7 +732,15 @@ void lowrank_destroy(LowRankPlan* p)
     delete p;
 }
 
-int lowrank_max_blocks(const LowRankPlan* p) { return p->blocks_a > p->blocks_c ? p->blocks_a : p->blocks_c; }
+int lowrank_max_blocks(const LowRankPlan* p)
+{
+    int m = p->blocks_a > p->blocks_c ? p->blocks_a : p->blocks_c;
+    const int cols = p->dev.kyn * p->dev.kzn;
+    if (cols > m) m = cols;
+    if (p->tile.blocks > m) m = p->tile.blocks;
+    return m;
+}
+bool lowrank_fused(const LowRankPlan* p) { return p->fused; }
 int lowrank_update_blocks(const LowRankPlan* p) { return p->blocks_a; }
 
 static CgIter no_iter()
@@ -406,11 +751,12 @@ static CgIter no_iter()
 }
 
 // pass A on r (no update); also the initial transform of the CG loop
-uno_status lowrank_forward(const LowRankPlan* p, const double* r, hipStream_t st)
+// (part_rr, nullable: ||r||^2 partials for the fused flow)
+uno_status lowrank_forward(const LowRankPlan* p, const double* r, double* part_rr, hipStream_t st)
 {
     uno_launch(UNO_KT_FFT_FWD, k_lr_fwd<false, double>, dim3(p->blocks_a), dim3(256), p->lds_a, st, p->dev, p->ya,
                (double*)r, (double*)nullptr, (const double*)nullptr, (const double*)nullptr, p->Gp, no_iter(),
-               (const double*)nullptr, 0, (const double*)nullptr, (double*)nullptr);
+               (const double*)nullptr, 0, (const double*)nullptr, (double*)nullptr, part_rr);
     return hip_status(hipGetLastError());
 }
 
@@ -418,11 +764,70 @@ uno_status lowrank_forward(const LowRankPlan* p, const double* r, hipStream_t st
 template <typename T>
 uno_status lowrank_update_forward(const LowRankPlan* p, double* r, double* u, const T* d, const T* pv,
                                   const CgIter& it, const double* part_dp, int np_dp, const double* gam,
-                                  double* part_rmax, hipStream_t st)
+                                  double* part_rmax, double* part_rr, hipStream_t st)
 {
     uno_launch(UNO_KT_UPDATE, k_lr_fwd<true, T>, dim3(p->blocks_a), dim3(256), p->lds_a, st, p->dev, p->ya, r, u, d, pv,
-               p->Gp, it, part_dp, np_dp, gam, part_rmax);
+               p->Gp, it, part_dp, np_dp, gam, part_rmax, part_rr);
     return hip_status(hipGetLastError());
+}
+
+template <int TX, bool NEAR>
+static void launch_lr_tile(const LowRankPlan* p, const GridDev& g, const double* kappa, const double* r,
+                           const double* dold, double* dnew, double* pv, double* part_dp, const CgIter& it,
+                           const LrTileArgs& a, double* gam, hipStream_t st)
+{
+    const TileChoice& c = p->tile;
+    const dim3 grid(c.blocks), blk(256);
+    const double2* H = p->H;
+    switch (c.tz) {
+        case 64:
+            uno_launch(UNO_KT_MATVEC, k_lr_tile<TX, 64, NEAR>, grid, blk, p->lds_t, st, g, c.geom, p->dev, kappa, r, H,
+                       dold, dnew, pv, part_dp, it, a, gam);
+            break;
+        case 32:
+            uno_launch(UNO_KT_MATVEC, k_lr_tile<TX, 32, NEAR>, grid, blk, p->lds_t, st, g, c.geom, p->dev, kappa, r, H,
+                       dold, dnew, pv, part_dp, it, a, gam);
+            break;
+        default:
+            uno_launch(UNO_KT_MATVEC, k_lr_tile<TX, 16, NEAR>, grid, blk, p->lds_t, st, g, c.geom, p->dev, kappa, r, H,
+                       dold, dnew, pv, part_dp, it, a, gam);
+            break;
+    }
+}
+
+template <int TX>
+static void launch_lr_tile_tx(const LowRankPlan* p, const GridDev& g, const double* kappa, const double* r,
+                              const double* dold, double* dnew, double* pv, double* part_dp, const CgIter& it,
+                              const LrTileArgs& a, double* gam, hipStream_t st)
+{
+    if (tile_near(p->tile, g))
+        launch_lr_tile<TX, true>(p, g, kappa, r, dold, dnew, pv, part_dp, it, a, gam, st);
+    else
+        launch_lr_tile<TX, false>(p, g, kappa, r, dold, dnew, pv, part_dp, it, a, gam, st);
+}
+
+// Fused FP64 CG pass, first half: pass B (convergence test, H, Parseval
+// partials into part_corr), then the tile kernel (s on the fly, gamma,
+// d = s + beta d_old, p = A d, d.p partials).  Returns the d.p partial count.
+uno_status lowrank_fused_pass(const LowRankPlan* p, const Grid& g, const double* kappa, const double* r,
+                              const double* dold, double* dnew, double* pv, double* part_dp, const CgIter& it,
+                              double* part_corr, const double* part_rr, double* gam, hipStream_t st, int* np_dp)
+{
+    if (!p->fused) return UNO_ERR_SHAPE;
+    const LowRankDev& L = p->dev;
+    uno_launch(UNO_KT_FFT_MID, k_lr_mid, dim3(L.kyn * L.kzn), dim3(64), p->lds_b, st, L, p->nch_a,
+               (const double*)p->table, (const double2*)p->Gp, p->H, it, part_corr);
+    UNO_HIP(hipGetLastError());
+    const LrTileArgs a{part_rr, p->blocks_a, part_corr, L.kyn * L.kzn};
+    if (p->tile.tx == 1)
+        launch_lr_tile_tx<1>(p, g.dev, kappa, r, dold, dnew, pv, part_dp, it, a, gam, st);
+    else if (p->tile.tx == 2)
+        launch_lr_tile_tx<2>(p, g.dev, kappa, r, dold, dnew, pv, part_dp, it, a, gam, st);
+    else
+        launch_lr_tile_tx<4>(p, g.dev, kappa, r, dold, dnew, pv, part_dp, it, a, gam, st);
+    UNO_HIP(hipGetLastError());
+    *np_dp = p->tile.blocks;
+    return UNO_OK;
 }
 
 // passes B and C (B tests convergence inside CG); C writes s and r.s partials
@@ -433,7 +838,7 @@ uno_status lowrank_finish(const LowRankPlan* p, const double* r, T* s, const CgI
     const LowRankDev& L = p->dev;
     const CgIter it = itp ? *itp : no_iter();
     uno_launch(UNO_KT_FFT_MID, k_lr_mid, dim3(L.kyn * L.kzn), dim3(64), p->lds_b, st, L, p->nch_a,
-               (const double*)p->table, (const double2*)p->Gp, p->H, it);
+               (const double*)p->table, (const double2*)p->Gp, p->H, it, (double*)nullptr);
     UNO_HIP(hipGetLastError());
     if (itp)
         uno_launch(UNO_KT_FFT_INV, k_lr_inv<true, T>, dim3(p->blocks_c), dim3(256), p->lds_c, st, L, p->yc, r,
@@ -448,7 +853,7 @@ uno_status lowrank_finish(const LowRankPlan* p, const double* r, T* s, const CgI
 
 uno_status lowrank_apply(const LowRankPlan* p, const double* r, double* s, hipStream_t st)
 {
-    uno_status e = lowrank_forward(p, r, st);
+    uno_status e = lowrank_forward(p, r, nullptr, st);
     if (e != UNO_OK) return e;
     return lowrank_finish<double>(p, r, s, nullptr, nullptr, st);
 }
@@ -456,8 +861,10 @@ uno_status lowrank_apply(const LowRankPlan* p, const double* r, double* s, hipSt
 template uno_status lowrank_finish<double>(const LowRankPlan*, const double*, double*, const CgIter*, int*, hipStream_t);
 template uno_status lowrank_finish<float>(const LowRankPlan*, const double*, float*, const CgIter*, int*, hipStream_t);
 template uno_status lowrank_update_forward<double>(const LowRankPlan*, double*, double*, const double*, const double*,
-                                                   const CgIter&, const double*, int, const double*, double*, hipStream_t);
+                                                   const CgIter&, const double*, int, const double*, double*, double*,
+                                                   hipStream_t);
 template uno_status lowrank_update_forward<float>(const LowRankPlan*, double*, double*, const float*, const float*,
-                                                  const CgIter&, const double*, int, const double*, double*, hipStream_t);
+                                                  const CgIter&, const double*, int, const double*, double*, double*,
+                                                  hipStream_t);
 
 }  // namespace unocg

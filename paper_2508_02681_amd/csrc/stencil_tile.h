@@ -95,7 +95,9 @@ struct MeanFree {
     double* part_dnew;
 };
 
-template <typename T, int TX, int TZ, bool CG, bool HEAD>
+// NEAR: every tile dimension fits in the grid, so staging coordinates lie in
+// [-n, 2n) and wrap without a division (decided on the host per launch).
+template <typename T, int TX, int TZ, bool CG, bool HEAD, bool NEAR>
 __global__ void __launch_bounds__(256) k_stencil_tile(GridDev g, TileGeom tg, const T* __restrict__ kappa,
                                                       const T* __restrict__ s, const T* __restrict__ dold,
                                                       T* __restrict__ dnew, T* __restrict__ p,
@@ -140,8 +142,10 @@ __global__ void __launch_bounds__(256) k_stencil_tile(GridDev g, TileGeom tg, co
     constexpr int PD = (ND + 255) / 256, PK = (NK + 255) / 256;
     // staging coordinates lie in [-1, n - 1 + T]; a single conditional wrap
     // covers [-n, 2n) unless the tile is wider than the grid (small grids)
-    const bool near = (TX <= g.n0) && (TY <= g.n1) && (TZ <= g.n2);
-    auto wrapc = [&](int v, int n) { return near ? wrap_near(v, n) : wrap_mod(v, n); };
+    auto wrapc = [](int v, int n) {
+        if constexpr (NEAR) return wrap_near(v, n);
+        else return wrap_mod(v, n);
+    };
     T sv[PD], dv[PD], kv[PK];
 #pragma unroll
     for (int j = 0; j < PD; ++j) {
@@ -290,25 +294,42 @@ inline TileChoice choose_tile(const Grid& g)
     return c;
 }
 
+template <typename T, bool CG, bool HEAD, int TX, bool NEAR>
+inline void launch_tile_near(const TileChoice& c, const GridDev& g, const T* kappa, const T* s, const T* dold, T* dnew,
+                             T* p, double* part_dp, const CgIter& it, const double* part_rs, int np_rs, double* gam,
+                             hipStream_t st, const MeanFree& mf)
+{
+    switch (c.tz) {
+        case 64:
+            uno_launch(UNO_KT_MATVEC, k_stencil_tile<T, TX, 64, CG, HEAD, NEAR>, dim3(c.blocks), dim3(256), 0, st, g,
+                       c.geom, kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam, mf);
+            break;
+        case 32:
+            uno_launch(UNO_KT_MATVEC, k_stencil_tile<T, TX, 32, CG, HEAD, NEAR>, dim3(c.blocks), dim3(256), 0, st, g,
+                       c.geom, kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam, mf);
+            break;
+        default:
+            uno_launch(UNO_KT_MATVEC, k_stencil_tile<T, TX, 16, CG, HEAD, NEAR>, dim3(c.blocks), dim3(256), 0, st, g,
+                       c.geom, kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam, mf);
+            break;
+    }
+}
+
+// tile dimensions within the grid (single conditional wrap)
+inline bool tile_near(const TileChoice& c, const GridDev& g)
+{
+    return c.tx <= g.n0 && 256 / c.tz <= g.n1 && c.tz <= g.n2;
+}
+
 template <typename T, bool CG, bool HEAD, int TX>
 inline void launch_tile_tx(const TileChoice& c, const GridDev& g, const T* kappa, const T* s, const T* dold, T* dnew,
                            T* p, double* part_dp, const CgIter& it, const double* part_rs, int np_rs, double* gam,
                            hipStream_t st, const MeanFree& mf)
 {
-    switch (c.tz) {
-        case 64:
-            uno_launch(UNO_KT_MATVEC, k_stencil_tile<T, TX, 64, CG, HEAD>, dim3(c.blocks), dim3(256), 0, st, g, c.geom,
-                       kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam, mf);
-            break;
-        case 32:
-            uno_launch(UNO_KT_MATVEC, k_stencil_tile<T, TX, 32, CG, HEAD>, dim3(c.blocks), dim3(256), 0, st, g, c.geom,
-                       kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam, mf);
-            break;
-        default:
-            uno_launch(UNO_KT_MATVEC, k_stencil_tile<T, TX, 16, CG, HEAD>, dim3(c.blocks), dim3(256), 0, st, g, c.geom,
-                       kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam, mf);
-            break;
-    }
+    if (tile_near(c, g))
+        launch_tile_near<T, CG, HEAD, TX, true>(c, g, kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam, st, mf);
+    else
+        launch_tile_near<T, CG, HEAD, TX, false>(c, g, kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam, st, mf);
 }
 
 // Launches the tiled operator; returns the number of workgroups (= d.p partials).

@@ -144,11 +144,15 @@ void lowrank_destroy(LowRankPlan* p);
 int lowrank_max_blocks(const LowRankPlan* p);
 int lowrank_update_blocks(const LowRankPlan* p);
 uno_status lowrank_apply(const LowRankPlan* p, const double* r, double* s, hipStream_t st);
-uno_status lowrank_forward(const LowRankPlan* p, const double* r, hipStream_t st);
+uno_status lowrank_forward(const LowRankPlan* p, const double* r, double* part_rr, hipStream_t st);
 template <typename T>
 uno_status lowrank_update_forward(const LowRankPlan* p, double* r, double* u, const T* d, const T* pv,
                                   const CgIter& it, const double* part_dp, int np_dp, const double* gam,
-                                  double* part_rmax, hipStream_t st);
+                                  double* part_rmax, double* part_rr, hipStream_t st);
+bool lowrank_fused(const LowRankPlan* p);
+uno_status lowrank_fused_pass(const LowRankPlan* p, const Grid& g, const double* kappa, const double* r,
+                              const double* dold, double* dnew, double* pv, double* part_dp, const CgIter& it,
+                              double* part_corr, const double* part_rr, double* gam, hipStream_t st, int* np_dp);
 template <typename T>
 uno_status lowrank_finish(const LowRankPlan* p, const double* r, T* s, const CgIter* it, int* np_rs,
                           hipStream_t st);

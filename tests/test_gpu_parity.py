@@ -156,8 +156,11 @@ def test_pcg_uno_matches_oracle(orc, uno, shape, M, path):
     assert info["converged"]
     assert rel(u.cpu().numpy(), uo) < 1e-8
     # a random theta makes a poor preconditioner (hundreds of passes); late
-    # passes amplify the different rounding of the two implementations
-    assert abs(info["iters"] - ito) <= max(1, int(0.01 * ito))
+    # passes amplify the different rounding of the two implementations: on
+    # the 32x32 case the oracle's own count moves between 399 and 407 when
+    # r.s is perturbed by 1e-15 relative or summed by Parseval, so counts
+    # agree to 3 per hundred
+    assert abs(info["iters"] - ito) <= max(1, int(0.03 * ito))
     n = min(len(hist), len(ho), 10)
     assert rel(hist[:n], ho[:n]) < 1e-8
 
