@@ -120,11 +120,12 @@ def main():
     def solve_pairs(kaps, precond, kind):
         F, U, its = [], [], []
         for k in kaps:
-            for g in LOADS:
-                u, info = uno.pcg_solve(k, macro_load=g, kind=kind, precond=precond, rtol=1e-10, max_iter=20000)
+            u, infos = uno.pcg_solve_batch(k, macro_loads=LOADS, kind=kind, precond=precond, rtol=1e-10,
+                                           max_iter=20000)
+            for j, g in enumerate(LOADS):
                 F.append(uno.uno_macro_rhs(k, g))
-                U.append(u)
-                its.append(info["iters"])
+                U.append(u[j])
+                its.append(infos[j]["iters"])
         return F, U, its
 
     def fit(F, U, M):
@@ -159,10 +160,8 @@ def main():
         for rep in range(2):  # first pass warms up
             torch.cuda.synchronize()
             t1 = time.perf_counter()
-            it = 0
-            for g in LOADS:
-                _, info = uno.pcg_solve(kap_val, macro_load=g, kind="uno", precond=p, rtol=RTOL)
-                it += info["iters"]
+            _, infos = uno.pcg_solve_batch(kap_val, macro_loads=LOADS, kind="uno", precond=p, rtol=RTOL)
+            it = sum(i["iters"] for i in infos)
             torch.cuda.synchronize()
             tv = time.perf_counter() - t1
         log("  M=%d: %d passes, %.2f ms on validation" % (M, it, tv * 1e3))
@@ -174,18 +173,22 @@ def main():
 
     sols = torch.zeros((3,) + SHAPE, dtype=torch.float64, device=dev)
 
-    def step(i, kind, precond, **kw):
+    def step(i, kind, precond, together=True, **kw):
+        """The 3 load cases of microstructure i (solved together, every pass
+        kernel carrying the three; or one after another), then kappa_bar."""
         k = kap_test[i % len(kap_test)]
         sols.zero_()
-        its = []
-        for j, g in enumerate(LOADS):
-            _, info = uno.pcg_solve(k, macro_load=g, u=sols[j], kind=kind, precond=precond, rtol=RTOL,
-                                    max_iter=50000, **kw)
+        if together:
+            _, infos = uno.pcg_solve_batch(k, macro_loads=LOADS, u=sols, kind=kind, precond=precond, rtol=RTOL,
+                                           max_iter=50000, **kw)
+        else:
+            infos = [uno.pcg_solve(k, macro_load=g, u=sols[j], kind=kind, precond=precond, rtol=RTOL,
+                                   max_iter=50000, **kw)[1] for j, g in enumerate(LOADS)]
+        for info in infos:
             if not info["converged"]:
                 raise RuntimeError("solve did not converge: %s" % info)
-            its.append(info["iters"])
         kb = uno.effective_tensor(k, LOADS, sols)
-        return its, kb
+        return [info["iters"] for info in infos], kb
 
     def timed(kind, precond, steps, warmup, **kw):
         for i in range(warmup):
@@ -207,6 +210,12 @@ def main():
     uno_t_solve = dt / len(its) * 1e3
     log("UNO-CG: %.2f ms/step, %.1f passes/solve, %.3e DOF*it/s, %.3f ms per solve" %
         (ms_step, np.mean(its), value, uno_t_solve))
+    # the same loads one solve at a time (context for the batched step)
+    nseq = max(1, min(args.steps, 4))
+    dts, itss, _ = timed("uno", prec, nseq, 1, together=False)
+    seq_t_solve = dts / len(itss) * 1e3
+    log("UNO-CG one load at a time: %.3f ms per solve (%.2fx slower than together)" %
+        (seq_t_solve, seq_t_solve / uno_t_solve))
     # ---------------- Jacobi-CG on the same microstructures ----------------
     dtj, itsj, _ = timed("jacobi", None, args.jac_steps, 1)
     jac_t_solve = dtj / len(itsj) * 1e3
@@ -245,10 +254,12 @@ def main():
         fams = {uno.KT_MATVEC: "k_lr_tile<2,32>", uno.KT_UPDATE: "k_lr_fwd<update,double>",
                 uno.KT_FFT_MID: "k_lr_mid"}
         # algorithmic bytes per launch (FP64): the minimum each kernel must move
+        # (a launch carries the 3 load cases; kappa and the table are shared)
+        nr = len(LOADS)
         bytes_per = {
-            uno.KT_MATVEC: n_dof * 8 * 5 + nblk * 16,  # read r, d_old, kappa, H; write d_new, p
-            uno.KT_UPDATE: n_dof * 8 * 6 + nblk * 16,  # read r, u, d, p; write r, u, block spectrum
-            uno.KT_FFT_MID: nblk * 16 * 2 + nblk * 8,  # block spectrum in/out + table
+            uno.KT_MATVEC: nr * (n_dof * 8 * 4 + nblk * 16) + n_dof * 8,  # read r, d_old, H; write d_new, p; kappa
+            uno.KT_UPDATE: nr * (n_dof * 8 * 6 + nblk * 16),  # read r, u, d, p; write r, u, block spectrum
+            uno.KT_FFT_MID: nr * nblk * 16 * 2 + nblk * 8,     # block spectrum in/out; table
         }
     else:
         fams = {uno.KT_MATVEC: "k_stencil_tile<double,CG>", uno.KT_UPDATE: "k_cg_update<double>",
@@ -306,10 +317,11 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "3D thermal 64^3 periodic hex8, spheres r 4-8 vf 0.25, kappa 1/100, "
-                               "3 loads per step, UNO-CG to 1e-6 + effective tensor",
+                               "3 loads per step solved together, UNO-CG to 1e-6 + effective tensor",
                    "grid": list(SHAPE), "loads_per_step": 3, "M": M, "train_pairs": len(F),
                    "microstructures": len(kap_test)},
-        "uno_cg": {"passes_mean": float(np.mean(its)), "ms_per_solve": uno_t_solve, "dof_iters_per_s": value},
+        "uno_cg": {"passes_mean": float(np.mean(its)), "ms_per_solve": uno_t_solve, "dof_iters_per_s": value,
+                   "loads_together": 3, "ms_per_solve_one_at_a_time": seq_t_solve},
         "jac_cg": {"passes_mean": float(np.mean(itsj)), "ms_per_solve": jac_t_solve, "dof_iters_per_s": jac_rate},
         "fans_cg": {"passes_mean": float(np.mean(itsf)), "ms_per_solve": dtf / len(itsf) * 1e3},
         "uno_cg_fp32": {"passes_mean": float(np.mean(itsm)), "ms_per_solve": dtm / len(itsm) * 1e3,

@@ -170,6 +170,23 @@ uno_status pcg_solve(const uno_grid *grid, const uno_material *mat, const double
                      const double *rhs, double *u, const uno_solve_opts *opts, uno_solve_info *info,
                      double *res_hist, void *stream);
 
+/* nrhs independent solves with one conductivity field and preconditioner:
+ * the load cases of one microstructure (Sec. 5.1: one cell problem per unit
+ * macroscopic gradient; Sec. 4.5: batched solution of many problems).
+ * Load j is uno_macro_rhs(gbar = macro_loads + d j) (host, nrhs x d) when
+ * macro_loads is non-NULL, else rhs + n j (device, nrhs x n doubles).
+ * u (device, nrhs x n doubles) holds the initial guesses and receives the
+ * zero-mean solutions; info (host, nullable) receives nrhs records.
+ * Every pass kernel carries all right-hand sides (grid y), each with its own
+ * scalars and stopping test: a load that has converged stops updating, and
+ * every result equals that of pcg_solve on the same load.  Preconditioners
+ * without the learned-mode passes and the FP32 mode are run load by load.
+ * 1 <= nrhs <= 64.  Returns UNO_ERR_BREAKDOWN if any load broke down (see
+ * info).  Synchronous. */
+uno_status pcg_solve_batch(const uno_grid *grid, const uno_material *mat, int32_t nrhs,
+                           const double *macro_loads, const double *rhs, double *u,
+                           const uno_solve_opts *opts, uno_solve_info *info, void *stream);
+
 /* Effective conductivity (Sec. 5.1; the homogenized property handed back to
  * the macro scale, Sec. 1): for load j with gradient g_j (host loads,
  * nload x d) and solution u_j (device, nload x n doubles, C order),

@@ -80,6 +80,7 @@ def lib():
         "uno_precond_set_path": ([vp, i32], i),
         "uno_precond_destroy": ([vp], i),
         "pcg_solve": ([G, Mt, P(f64), vp, vp, P(uno_solve_opts), P(uno_solve_info), P(f64), vp], i),
+        "pcg_solve_batch": ([G, Mt, i32, P(f64), vp, vp, P(uno_solve_opts), P(uno_solve_info), vp], i),
         "effective_tensor": ([G, Mt, i32, P(f64), vp, P(f64), vp], i),
         "uno_train_accumulate": ([G, i32, vp, vp, f64, vp, vp, vp], i),
         "uno_train_fit": ([G, i32, vp, vp, P(f64), i64, vp], i),
@@ -277,6 +278,49 @@ def pcg_solve(kappa: torch.Tensor, macro_load=None, rhs: torch.Tensor | None = N
     if history:
         return u, d, hist[: info.iters + 1].copy()
     return u, d
+
+
+def _opts(kind, precond, rtol, max_iter, op_dtype, prec_dtype, graph_chunk):
+    kinds = {"none": UNO_PREC_NONE, "jacobi": UNO_PREC_JACOBI, "uno": UNO_PREC_UNO}
+    o = uno_solve_opts()
+    o.kind = kinds[kind]
+    o.uno = precond.handle if (precond is not None and kind == "uno") else None
+    o.rtol = float(rtol)
+    o.max_iter = int(max_iter)
+    o.op_t = _dt(op_dtype)
+    o.prec_t = _dt(prec_dtype)
+    o.graph_chunk = int(graph_chunk)
+    return o
+
+
+def pcg_solve_batch(kappa: torch.Tensor, macro_loads=None, rhs: torch.Tensor | None = None,
+                    u: torch.Tensor | None = None, kind="jacobi", precond: UnoPrecond | None = None, rtol=1e-6,
+                    max_iter=100000, op_dtype=torch.float64, prec_dtype=torch.float64, graph_chunk=0, L0=1.0):
+    """nrhs solves with one conductivity field (the load cases of one
+    microstructure), all carried by every pass kernel.  macro_loads: nrhs x d
+    (host) or rhs: nrhs x shape (device).  Returns (u (nrhs x shape), [info])."""
+    g = make_grid(kappa.shape, L0)
+    d = len(kappa.shape)
+    ml = None
+    if macro_loads is not None:
+        ml = np.ascontiguousarray(macro_loads, dtype=np.float64).reshape(-1, d)
+        nrhs = ml.shape[0]
+    else:
+        nrhs = rhs.shape[0]
+    if u is None:
+        u = torch.zeros((nrhs,) + tuple(kappa.shape), dtype=torch.float64, device=kappa.device)
+    if tuple(u.shape) != (nrhs,) + tuple(kappa.shape):
+        raise ValueError("u must be nrhs x grid")
+    o = _opts(kind, precond, rtol, max_iter, op_dtype, prec_dtype, graph_chunk)
+    infos = (uno_solve_info * nrhs)()
+    st = lib().pcg_solve_batch(
+        ctypes.byref(g), ctypes.byref(_mat(kappa)), nrhs,
+        ml.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if ml is not None else None,
+        _dev(rhs, "rhs", torch.float64) if rhs is not None else None,
+        _dev(u, "u", torch.float64), ctypes.byref(o), infos, _stream())
+    _check(st, "pcg_solve_batch")
+    return u, [dict(iters=I.iters, converged=bool(I.converged), rel_res=I.rel_res, true_rel_res=I.true_rel_res,
+                    r0_norm=I.r0_norm) for I in infos]
 
 
 def effective_tensor(kappa: torch.Tensor, loads, solutions: torch.Tensor, L0=1.0) -> np.ndarray:

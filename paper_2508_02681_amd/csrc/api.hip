@@ -16,6 +16,8 @@ namespace unocg {
 uno_status ws_release_all();
 uno_status pcg_run(const Grid& g, const double* kappa, const double* macro_load3, const double* rhs, double* u,
                    const uno_solve_opts* o, uno_solve_info* info, double* res_hist, hipStream_t st);
+uno_status pcg_run_batch(const Grid& g, const double* kappa, int nrhs, const double* macro_loads3, const double* rhs,
+                         double* u, const uno_solve_opts* o, uno_solve_info* info, double* res_hist, hipStream_t st);
 
 uno_status hip_status(hipError_t e)
 {
@@ -454,20 +456,17 @@ uno_status uno_precond_destroy(uno_precond* p)
     return UNO_OK;
 }
 
-uno_status pcg_solve(const uno_grid* grid, const uno_material* mat, const double* macro_load, const double* rhs,
-                     double* u, const uno_solve_opts* opts, uno_solve_info* info, double* res_hist, void* stream)
+static uno_status check_solve(const uno_grid* grid, const uno_material* mat, const uno_solve_opts* opts, Grid* g)
 {
-    Grid g;
-    uno_status e = make_grid(grid, &g);
+    uno_status e = make_grid(grid, g);
     if (e != UNO_OK) return e;
-    if (!mat || !mat->kappa || !u || !opts) return UNO_ERR_ARG;
-    if (!macro_load && !rhs) return UNO_ERR_ARG;
+    if (!mat || !mat->kappa || !opts) return UNO_ERR_ARG;
     if (!(opts->rtol >= 0.0) || opts->max_iter < 1) return UNO_ERR_ARG;
     if (opts->kind < UNO_PREC_NONE || opts->kind > UNO_PREC_UNO) return UNO_ERR_ARG;
     if (opts->kind == UNO_PREC_UNO) {
         if (!opts->uno) return UNO_ERR_ARG;
         const Grid& pg = opts->uno->grid;
-        if (pg.n[0] != g.n[0] || pg.n[1] != g.n[1] || pg.n[2] != g.n[2]) return UNO_ERR_SHAPE;
+        if (pg.n[0] != g->n[0] || pg.n[1] != g->n[1] || pg.n[2] != g->n[2]) return UNO_ERR_SHAPE;
     }
     if (mat->dtype != UNO_F64) return UNO_ERR_ARG;
     // FP64 throughout, or the mixed mode: FP32 operator and preconditioner
@@ -475,10 +474,38 @@ uno_status pcg_solve(const uno_grid* grid, const uno_material* mat, const double
     const bool f64 = opts->op_t == UNO_F64 && opts->prec_t == UNO_F64;
     const bool mixed = opts->op_t == UNO_F32 && opts->prec_t == UNO_F32;
     if (!f64 && !mixed) return UNO_ERR_ARG;
+    return UNO_OK;
+}
+
+uno_status pcg_solve(const uno_grid* grid, const uno_material* mat, const double* macro_load, const double* rhs,
+                     double* u, const uno_solve_opts* opts, uno_solve_info* info, double* res_hist, void* stream)
+{
+    Grid g;
+    uno_status e = check_solve(grid, mat, opts, &g);
+    if (e != UNO_OK) return e;
+    if (!u || (!macro_load && !rhs)) return UNO_ERR_ARG;
     double g3[3] = {0.0, 0.0, 0.0};
     if (macro_load)
         for (int b = 0; b < grid->dim; ++b) g3[3 - grid->dim + b] = macro_load[b];
     return pcg_run(g, (const double*)mat->kappa, macro_load ? g3 : nullptr, rhs, u, opts, info, res_hist, S(stream));
+}
+
+uno_status pcg_solve_batch(const uno_grid* grid, const uno_material* mat, int32_t nrhs, const double* macro_loads,
+                           const double* rhs, double* u, const uno_solve_opts* opts, uno_solve_info* info,
+                           void* stream)
+{
+    Grid g;
+    uno_status e = check_solve(grid, mat, opts, &g);
+    if (e != UNO_OK) return e;
+    if (nrhs < 1 || nrhs > 64 || !u || (!macro_loads && !rhs)) return UNO_ERR_ARG;
+    std::vector<double> g3;
+    if (macro_loads) {
+        g3.assign(3 * (size_t)nrhs, 0.0);
+        for (int j = 0; j < nrhs; ++j)
+            for (int b = 0; b < grid->dim; ++b) g3[3 * j + 3 - grid->dim + b] = macro_loads[grid->dim * j + b];
+    }
+    return pcg_run_batch(g, (const double*)mat->kappa, nrhs, macro_loads ? g3.data() : nullptr, rhs, u, opts, info,
+                         nullptr, S(stream));
 }
 
 uno_status effective_tensor(const uno_grid* grid, const uno_material* mat, int32_t nload, const double* loads,

@@ -80,9 +80,18 @@ template <typename T, int MODE>
 __global__ void __launch_bounds__(kBlock) k_cg_init(GridDev g, const T* __restrict__ dinv,
                                                     const double* __restrict__ r, T* __restrict__ s,
                                                     double* __restrict__ part_rmax, double* __restrict__ part_rs,
-                                                    double* __restrict__ part_ss, CgState* st)
+                                                    double* __restrict__ part_ss, CgState* st, int ps)
 {
     __shared__ double slots[kBlock / 64];
+    if (blockIdx.y > 0) {  // right-hand side blockIdx.y of a batch
+        const int64_t vo = (int64_t)blockIdx.y * g.n, po = (int64_t)blockIdx.y * ps;
+        r += vo;
+        s += vo;
+        part_rmax += po;
+        part_rs += po;
+        part_ss += po;
+        st += blockIdx.y;
+    }
     double m = 0.0, dt = 0.0, ss = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.n; i += (int64_t)gridDim.x * blockDim.x) {
         const double ri = r[i];
@@ -127,6 +136,20 @@ __global__ void __launch_bounds__(kBlock) k_cg_update(GridDev g, const T* __rest
                                                       double* __restrict__ part_rs_next, double* __restrict__ part_ss_next)
 {
     __shared__ double slots[kBlock / 64];
+    if (blockIdx.y > 0) {  // right-hand side blockIdx.y of a batch
+        const int64_t vo = (int64_t)blockIdx.y * it.vs, po = (int64_t)blockIdx.y * it.ps;
+        r += vo;
+        u += vo;
+        d += vo;
+        p += vo;
+        s += vo;
+        part_dp += po;
+        gam += (int64_t)blockIdx.y * it.hs;
+        part_rmax += po;
+        part_rs_next += po;
+        part_ss_next += po;
+        it = rhs_iter(it);
+    }
     // all loads first: state, d.p partials, gamma_k and the first element's operands
     const StateLoad sl = load_state(it.st);
     const double dp_share = load_share<OpSum>(part_dp, np_dp);
@@ -187,7 +210,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_update(GridDev g, const T* __rest
 __global__ void __launch_bounds__(kBlock) k_cg_check(CgIter it)
 {
     __shared__ double slots[kBlock / 64];
-    (void)head_check(it, slots);
+    (void)head_check(rhs_iter(it), slots);
 }
 
 // r = f - y
@@ -259,12 +282,17 @@ namespace {
 
 constexpr int kMaxStreamBlocks = 512;
 
+// Per-grid CG workspace.  Vectors, partial buffers, loop states and scalar
+// histories are held for up to nrhs_cap right-hand sides solved together:
+// vector b at + b n, partial buffer `kind` of b at part + (kind nrhs_cap + b)
+// npart, state b at state + b, history b at hist + b hist_cap.
 struct Workspace {
     int device = -1;
     int n[3] = {0, 0, 0};
     int64_t total = 0;
     int nbr = 0;              // workgroups of the streaming CG kernels
-    int npart = 0;            // capacity of each partial buffer
+    int npart = 0;            // capacity of each partial buffer (per right-hand side)
+    int nrhs_cap = 0;
     double *f = nullptr, *r = nullptr, *s = nullptr, *d[2] = {nullptr, nullptr}, *p = nullptr;
     double* dinv = nullptr;   // inverse Jacobi diagonal of the current solve
     float* kap32 = nullptr;   // FP32 conductivities (mixed precision)
@@ -272,6 +300,10 @@ struct Workspace {
     double* part = nullptr;   // 8 partial buffers: rmax, rs[2], dp, ss[2], ds[2]
     double2* spec = nullptr;
     int64_t nspec = 0;
+    double2* lr_gp = nullptr; // learned-mode scratch per right-hand side
+    double2* lr_h = nullptr;
+    int64_t lr_ngp = 0, lr_nh = 0;
+    int lr_cap = 0;
     CgState* state = nullptr;
     CgState* host_state = nullptr;  // pinned
     double* hist = nullptr;
@@ -281,7 +313,7 @@ struct Workspace {
 
 std::vector<Workspace*> g_ws;
 
-void ws_free(Workspace* w)
+void ws_free_vectors(Workspace* w)
 {
     (void)hipFree(w->f);
     (void)hipFree(w->r);
@@ -289,19 +321,29 @@ void ws_free(Workspace* w)
     (void)hipFree(w->d[0]);
     (void)hipFree(w->d[1]);
     (void)hipFree(w->p);
+    (void)hipFree(w->state);
+    (void)hipHostFree(w->host_state);
+    w->f = w->r = w->s = w->d[0] = w->d[1] = w->p = nullptr;
+    w->state = w->host_state = nullptr;
+}
+
+void ws_free(Workspace* w)
+{
+    ws_free_vectors(w);
     (void)hipFree(w->dinv);
     (void)hipFree(w->kap32);
     (void)hipFree(w->y64);
     (void)hipFree(w->part);
     (void)hipFree(w->spec);
-    (void)hipFree(w->state);
-    (void)hipHostFree(w->host_state);
+    (void)hipFree(w->lr_gp);
+    (void)hipFree(w->lr_h);
     (void)hipFree(w->hist);
     (void)hipFree(w->gam);
     delete w;
 }
 
-uno_status ws_get(const Grid& g, const FftPlan* plan, int extra_parts, int hist_need, Workspace** out)
+uno_status ws_get(const Grid& g, const FftPlan* plan, const LowRankPlan* lr, int extra_parts, int hist_need, int nrhs,
+                  Workspace** out)
 {
     int dev = 0;
     UNO_HIP(hipGetDevice(&dev));
@@ -315,19 +357,33 @@ uno_status ws_get(const Grid& g, const FftPlan* plan, int extra_parts, int hist_
         w->total = g.total;
         const int64_t nb = (g.total + kBlock - 1) / kBlock;
         w->nbr = (int)(nb < kMaxStreamBlocks ? nb : kMaxStreamBlocks);
-        const size_t vb = sizeof(double) * (size_t)g.total;
-        bool ok = hipMalloc(&w->f, vb) == hipSuccess && hipMalloc(&w->r, vb) == hipSuccess &&
-                  hipMalloc(&w->s, vb) == hipSuccess && hipMalloc(&w->d[0], vb) == hipSuccess &&
-                  hipMalloc(&w->d[1], vb) == hipSuccess && hipMalloc(&w->p, vb) == hipSuccess &&
-                  hipMalloc(&w->dinv, vb) == hipSuccess &&
-                  hipMalloc(&w->state, sizeof(CgState)) == hipSuccess &&
-                  hipHostMalloc(&w->host_state, sizeof(CgState), hipHostMallocDefault) == hipSuccess;
-        if (!ok) {
+        if (hipMalloc(&w->dinv, sizeof(double) * (size_t)g.total) != hipSuccess) {
             ws_free(w);
             return UNO_ERR_NOMEM;
         }
-        UNO_HIP(hipMemset(w->state, 0, sizeof(CgState)));
         g_ws.push_back(w);
+    }
+    if (nrhs > w->nrhs_cap) {
+        ws_free_vectors(w);
+        const size_t vb = sizeof(double) * (size_t)g.total * nrhs;
+        bool ok = hipMalloc(&w->f, vb) == hipSuccess && hipMalloc(&w->r, vb) == hipSuccess &&
+                  hipMalloc(&w->s, vb) == hipSuccess && hipMalloc(&w->d[0], vb) == hipSuccess &&
+                  hipMalloc(&w->d[1], vb) == hipSuccess && hipMalloc(&w->p, vb) == hipSuccess &&
+                  hipMalloc(&w->state, sizeof(CgState) * nrhs) == hipSuccess &&
+                  hipHostMalloc(&w->host_state, sizeof(CgState) * nrhs, hipHostMallocDefault) == hipSuccess;
+        if (!ok) {
+            ws_free_vectors(w);
+            w->nrhs_cap = 0;
+            return UNO_ERR_NOMEM;
+        }
+        UNO_HIP(hipMemset(w->state, 0, sizeof(CgState) * nrhs));
+        // partial buffers and histories are laid out per right-hand side
+        (void)hipFree(w->part);
+        (void)hipFree(w->hist);
+        (void)hipFree(w->gam);
+        w->part = w->hist = w->gam = nullptr;
+        w->npart = w->hist_cap = 0;
+        w->nrhs_cap = nrhs;
     }
     int need = w->nbr;
     const int ntile = choose_tile(g).blocks;
@@ -336,7 +392,7 @@ uno_status ws_get(const Grid& g, const FftPlan* plan, int extra_parts, int hist_
     if (need > w->npart) {
         (void)hipFree(w->part);
         w->part = nullptr;
-        if (hipMalloc(&w->part, sizeof(double) * 8 * (size_t)need) != hipSuccess) return UNO_ERR_NOMEM;
+        if (hipMalloc(&w->part, sizeof(double) * 8 * (size_t)need * w->nrhs_cap) != hipSuccess) return UNO_ERR_NOMEM;
         w->npart = need;
     }
     if (plan && plan->nspec > w->nspec) {
@@ -345,12 +401,29 @@ uno_status ws_get(const Grid& g, const FftPlan* plan, int extra_parts, int hist_
         if (hipMalloc(&w->spec, sizeof(double2) * plan->nspec) != hipSuccess) return UNO_ERR_NOMEM;
         w->nspec = plan->nspec;
     }
+    if (lr) {
+        int64_t ngp = 0, nh = 0;
+        lowrank_scratch_size(lr, &ngp, &nh);
+        if (ngp != w->lr_ngp || nh != w->lr_nh || w->lr_cap < w->nrhs_cap) {
+            (void)hipFree(w->lr_gp);
+            (void)hipFree(w->lr_h);
+            w->lr_gp = w->lr_h = nullptr;
+            w->lr_cap = 0;
+            if (hipMalloc(&w->lr_gp, sizeof(double2) * (size_t)ngp * w->nrhs_cap) != hipSuccess ||
+                hipMalloc(&w->lr_h, sizeof(double2) * (size_t)nh * w->nrhs_cap) != hipSuccess)
+                return UNO_ERR_NOMEM;
+            w->lr_ngp = ngp;
+            w->lr_nh = nh;
+            w->lr_cap = w->nrhs_cap;
+        }
+    }
     if (hist_need > w->hist_cap) {
         (void)hipFree(w->hist);
         (void)hipFree(w->gam);
         w->hist = w->gam = nullptr;
-        if (hipMalloc(&w->hist, sizeof(double) * hist_need) != hipSuccess) return UNO_ERR_NOMEM;
-        if (hipMalloc(&w->gam, sizeof(double) * hist_need) != hipSuccess) return UNO_ERR_NOMEM;
+        w->hist_cap = 0;
+        if (hipMalloc(&w->hist, sizeof(double) * (size_t)hist_need * w->nrhs_cap) != hipSuccess) return UNO_ERR_NOMEM;
+        if (hipMalloc(&w->gam, sizeof(double) * (size_t)hist_need * w->nrhs_cap) != hipSuccess) return UNO_ERR_NOMEM;
         w->hist_cap = hist_need;
     }
     *out = w;
@@ -368,6 +441,7 @@ uno_status ws_release_all()
 
 namespace {
 
+// partial buffers of right-hand side 0 (right-hand side b: + b npart)
 struct Parts {
     double* rmax;
     double* rs[2];
@@ -379,7 +453,7 @@ struct Parts {
 Parts parts_of(Workspace* w)
 {
     Parts P;
-    const size_t np = (size_t)w->npart;
+    const size_t np = (size_t)w->npart * w->nrhs_cap;
     P.rmax = w->part;
     P.rs[0] = w->part + np;
     P.rs[1] = w->part + 2 * np;
@@ -408,16 +482,22 @@ CgIter iter_of(Workspace* w, const Parts& P, int k, int k0, double rtol, int his
     it.r = w->r;
     it.part_rs = P.rs[k & 1];
     it.part_ssum = P.ss[k & 1];
+    it.vs = w->total;
+    it.ps = w->npart;
+    it.hs = w->hist_cap;
     return it;
 }
 
+LrBatch lr_batch(Workspace* w, int nrhs) { return LrBatch{w->lr_gp, w->lr_h, nrhs}; }
+
 }  // namespace
 
-// One CG pass k.  T: precision of the operator / preconditioner vectors
-// (s, d, p, conductivities, D^-1); r, u and every reduction stay FP64.
+// One CG pass k for nrhs right-hand sides (grid y).  T: precision of the
+// operator / preconditioner vectors (s, d, p, conductivities, D^-1); r, u
+// and every reduction stay FP64.
 template <typename T>
 static uno_status enqueue_pass(const Grid& g, Workspace* w, int kind, const uno_precond* pc, const T* kappa,
-                               double* u, int k, int k0, double rtol, int hist_len, hipStream_t st)
+                               double* u, int k, int k0, double rtol, int hist_len, int nrhs, hipStream_t st)
 {
     const Parts P = parts_of(w);
     const int nb = w->nbr;
@@ -429,51 +509,55 @@ static uno_status enqueue_pass(const Grid& g, Workspace* w, int kind, const uno_
     const MeanFree mf{P.ss[k & 1], P.ds[k & 1], P.ds[(k + 1) & 1]};
     if (kind == UNO_PREC_UNO && uno_use_lowrank(pc)) {
         CgIter it = iter_of(w, P, k, k0, rtol, hist_len, lowrank_update_blocks(pc->lr));
+        const LrBatch bt = lr_batch(w, nrhs);
         if constexpr (sizeof(T) == sizeof(double)) {
             if (lowrank_fused(pc->lr)) {
                 // fused FP64 flow: B (head, Parseval partials) -> [C + matvec] -> [update + A of pass k+1];
                 // ||r||^2 partials in rs[0], the learned-mode part of r.s in rs[1]
                 int np_dp = 0;
                 uno_status e = lowrank_fused_pass(pc->lr, g, (const double*)kappa, w->r, (const double*)dold,
-                                                  (double*)dnew, (double*)pv, P.dp, it, P.rs[1], P.rs[0], w->gam, st,
-                                                  &np_dp);
+                                                  (double*)dnew, (double*)pv, P.dp, it, P.rs[1], P.rs[0], w->gam, bt,
+                                                  st, &np_dp);
                 if (e != UNO_OK) return e;
                 return lowrank_update_forward<double>(pc->lr, w->r, u, (const double*)dnew, (const double*)pv, it, P.dp,
-                                                      np_dp, w->gam, P.rmax, P.rs[0], st);
+                                                      np_dp, w->gam, P.rmax, P.rs[0], bt, st);
             }
         }
         // learned-mode flow: [B (head) + C] -> matvec -> [update + A of pass k+1]
-        uno_status e = lowrank_finish<T>(pc->lr, w->r, sv, &it, &np_rs, st);
+        uno_status e = lowrank_finish<T>(pc->lr, w->r, sv, &it, &np_rs, bt, st);
         if (e != UNO_OK) return e;
-        const int np_dp =
-            launch_tile<T, true, false>(g, kappa, sv, dold, dnew, pv, P.dp, it, P.rs[k & 1], np_rs, w->gam, st, mf);
+        const int np_dp = launch_tile<T, true, false>(g, kappa, sv, dold, dnew, pv, P.dp, it, P.rs[k & 1], np_rs,
+                                                      w->gam, st, mf, nrhs);
         UNO_HIP(hipGetLastError());
-        return lowrank_update_forward<T>(pc->lr, w->r, u, dnew, pv, it, P.dp, np_dp, w->gam, P.rmax, nullptr, st);
+        return lowrank_update_forward<T>(pc->lr, w->r, u, dnew, pv, it, P.dp, np_dp, w->gam, P.rmax, nullptr, bt, st);
     }
     CgIter it = iter_of(w, P, k, k0, rtol, hist_len, nb);
     if (kind == UNO_PREC_UNO) {
-        if (sizeof(T) != sizeof(double)) return UNO_ERR_ARG;  // spectral passes run in FP64 only inside CG
+        if (sizeof(T) != sizeof(double) || nrhs != 1) return UNO_ERR_ARG;  // spectral passes: FP64, one rhs
         uno_status e = uno_apply_passes(g, pc->plan, pc->table, UNO_F64, w->r, w->s, UNO_F64, w->spec, &it, &np_rs, st);
         if (e != UNO_OK) return e;
     }
     int np_dp;
     if (kind == UNO_PREC_UNO)
-        np_dp = launch_tile<T, true, false>(g, kappa, sv, dold, dnew, pv, P.dp, it, P.rs[k & 1], np_rs, w->gam, st, mf);
+        np_dp = launch_tile<T, true, false>(g, kappa, sv, dold, dnew, pv, P.dp, it, P.rs[k & 1], np_rs, w->gam, st, mf,
+                                            nrhs);
     else
-        np_dp = launch_tile<T, true, true>(g, kappa, sv, dold, dnew, pv, P.dp, it, P.rs[k & 1], np_rs, w->gam, st, mf);
+        np_dp = launch_tile<T, true, true>(g, kappa, sv, dold, dnew, pv, P.dp, it, P.rs[k & 1], np_rs, w->gam, st, mf,
+                                           nrhs);
     UNO_HIP(hipGetLastError());
     double* rs_next = P.rs[(k + 1) & 1];
     double* ss_next = P.ss[(k + 1) & 1];
     const T* dinv = (const T*)w->dinv;
+    const dim3 grid(nb, nrhs);
     if (kind == UNO_PREC_NONE)
-        uno_launch(UNO_KT_UPDATE, k_cg_update<T, 0>, dim3(nb), dim3(kBlock), 0, st, g.dev, dinv, w->r, u, (const T*)dnew,
-                           (const T*)pv, sv, it, (const double*)P.dp, np_dp, (const double*)w->gam, P.rmax, rs_next, ss_next);
+        uno_launch(UNO_KT_UPDATE, k_cg_update<T, 0>, grid, dim3(kBlock), 0, st, g.dev, dinv, w->r, u, (const T*)dnew,
+                   (const T*)pv, sv, it, (const double*)P.dp, np_dp, (const double*)w->gam, P.rmax, rs_next, ss_next);
     else if (kind == UNO_PREC_JACOBI)
-        uno_launch(UNO_KT_UPDATE, k_cg_update<T, 1>, dim3(nb), dim3(kBlock), 0, st, g.dev, dinv, w->r, u, (const T*)dnew,
-                           (const T*)pv, sv, it, (const double*)P.dp, np_dp, (const double*)w->gam, P.rmax, rs_next, ss_next);
+        uno_launch(UNO_KT_UPDATE, k_cg_update<T, 1>, grid, dim3(kBlock), 0, st, g.dev, dinv, w->r, u, (const T*)dnew,
+                   (const T*)pv, sv, it, (const double*)P.dp, np_dp, (const double*)w->gam, P.rmax, rs_next, ss_next);
     else
-        uno_launch(UNO_KT_UPDATE, k_cg_update<T, 2>, dim3(nb), dim3(kBlock), 0, st, g.dev, dinv, w->r, u, (const T*)dnew,
-                           (const T*)pv, sv, it, (const double*)P.dp, np_dp, (const double*)w->gam, P.rmax, rs_next, ss_next);
+        uno_launch(UNO_KT_UPDATE, k_cg_update<T, 2>, grid, dim3(kBlock), 0, st, g.dev, dinv, w->r, u, (const T*)dnew,
+                   (const T*)pv, sv, it, (const double*)P.dp, np_dp, (const double*)w->gam, P.rmax, rs_next, ss_next);
     UNO_HIP(hipGetLastError());
     return UNO_OK;
 }
@@ -485,9 +569,11 @@ static uno_status enqueue_pass(const Grid& g, Workspace* w, int kind, const uno_
 // residual equal to the true one.
 constexpr double kRestartFactor = 1e-3;
 
+// The CG loop for nrhs right-hand sides (restarts only with nrhs = 1).
 template <typename T>
 static uno_status pcg_loop(const Grid& g, Workspace* w, const double* kappa64, const T* kappa, double* u,
-                           const uno_solve_opts* o, const uno_precond* pc, int hist_len, hipStream_t st, int* k_end)
+                           const uno_solve_opts* o, const uno_precond* pc, int hist_len, int nrhs, hipStream_t st,
+                           int* k_end)
 {
     const int nb = w->nbr;
     const Parts P = parts_of(w);
@@ -496,50 +582,58 @@ static uno_status pcg_loop(const Grid& g, Workspace* w, const double* kappa64, c
     const bool lowrank = pc && uno_use_lowrank(pc);
     const int np_update = lowrank ? lowrank_update_blocks(pc->lr) : nb;
     const bool restarts = sizeof(T) == sizeof(float);
+    if (restarts && nrhs != 1) return UNO_ERR_ARG;
     if (o->kind == UNO_PREC_JACOBI)
         hipLaunchKernelGGL(k_inv_diag<T>, dim3(nb), dim3(kBlock), 0, st, g.dev, kappa64, dinv);
     // (re)start of the recurrence from the residual in w->r: s_0 = P r_0 and
     // the partials of the first pass
     auto start = [&]() -> uno_status {
+        const dim3 grid(nb, nrhs);
         if (o->kind == UNO_PREC_NONE)
-            hipLaunchKernelGGL((k_cg_init<T, 0>), dim3(nb), dim3(kBlock), 0, st, g.dev, (const T*)dinv,
-                               (const double*)w->r, sv, P.rmax, P.rs[0], P.ss[0], w->state);
+            hipLaunchKernelGGL((k_cg_init<T, 0>), grid, dim3(kBlock), 0, st, g.dev, (const T*)dinv,
+                               (const double*)w->r, sv, P.rmax, P.rs[0], P.ss[0], w->state, w->npart);
         else if (o->kind == UNO_PREC_JACOBI)
-            hipLaunchKernelGGL((k_cg_init<T, 1>), dim3(nb), dim3(kBlock), 0, st, g.dev, (const T*)dinv,
-                               (const double*)w->r, sv, P.rmax, P.rs[0], P.ss[0], w->state);
+            hipLaunchKernelGGL((k_cg_init<T, 1>), grid, dim3(kBlock), 0, st, g.dev, (const T*)dinv,
+                               (const double*)w->r, sv, P.rmax, P.rs[0], P.ss[0], w->state, w->npart);
         else
-            hipLaunchKernelGGL((k_cg_init<T, 2>), dim3(nb), dim3(kBlock), 0, st, g.dev, (const T*)dinv,
-                               (const double*)w->r, sv, P.rmax, P.rs[0], P.ss[0], w->state);
+            hipLaunchKernelGGL((k_cg_init<T, 2>), grid, dim3(kBlock), 0, st, g.dev, (const T*)dinv,
+                               (const double*)w->r, sv, P.rmax, P.rs[0], P.ss[0], w->state, w->npart);
         UNO_HIP(hipGetLastError());
         if (lowrank) {  // transform of r for the first pass (and ||r||^2 in the fused flow)
             const bool fused = sizeof(T) == sizeof(double) && lowrank_fused(pc->lr);
-            return lowrank_forward(pc->lr, w->r, fused ? P.rs[0] : nullptr, st);
+            const CgIter strides = iter_of(w, P, 0, 0, 0.0, 0, nb);
+            return lowrank_forward(pc->lr, w->r, fused ? P.rs[0] : nullptr, lr_batch(w, nrhs), strides, st);
         }
         return UNO_OK;
     };
     uno_status e = start();
     if (e != UNO_OK) return e;
-    // passes in chunks; the host reads the state between chunks
+    // passes in chunks; the host reads the states between chunks
     int k = 0, k0 = 0;
     int chunk = o->graph_chunk > 0 ? o->graph_chunk : 8;
-    int prev_k = -1;
-    double prev_r = -1.0, cycle_r = -1.0;
+    std::vector<int> prev_k(nrhs, -1);
+    std::vector<double> prev_r(nrhs, -1.0);
+    double cycle_r = -1.0;
     for (;;) {
         if (chunk > o->max_iter - k) chunk = o->max_iter - k;
         for (int c = 0; c < chunk; ++c, ++k) {
-            e = enqueue_pass<T>(g, w, o->kind, pc, kappa, u, k, k0, o->rtol, hist_len, st);
+            e = enqueue_pass<T>(g, w, o->kind, pc, kappa, u, k, k0, o->rtol, hist_len, nrhs, st);
             if (e != UNO_OK) return e;
         }
         CgIter it = iter_of(w, P, k, k0, o->rtol, hist_len, np_update);
-        hipLaunchKernelGGL(k_cg_check, dim3(1), dim3(kBlock), 0, st, it);
+        hipLaunchKernelGGL(k_cg_check, dim3(1, nrhs), dim3(kBlock), 0, st, it);
         UNO_HIP(hipGetLastError());
-        UNO_HIP(hipMemcpyAsync(w->host_state, w->state, sizeof(CgState), hipMemcpyDeviceToHost, st));
+        UNO_HIP(hipMemcpyAsync(w->host_state, w->state, sizeof(CgState) * nrhs, hipMemcpyDeviceToHost, st));
         UNO_HIP(hipStreamSynchronize(st));
-        const CgState& hs = *w->host_state;
-        if (hs.status != 0 || hs.done != INT_MAX || k >= o->max_iter) break;
-        if (cycle_r < 0.0) cycle_r = hs.r0max;
-        double target = hs.tol_abs;
+        bool running = false;
+        for (int b = 0; b < nrhs; ++b) {
+            const CgState& hs = w->host_state[b];
+            if (hs.status == 0 && hs.done == INT_MAX) running = true;
+        }
+        if (!running || k >= o->max_iter) break;
         if (restarts) {
+            const CgState& hs = w->host_state[0];
+            if (cycle_r < 0.0) cycle_r = hs.r0max;
             if (hs.rmax_last <= kRestartFactor * cycle_r) {
                 // residual replacement: r = f - A u (FP64), restart at pass k
                 e = launch_fe_apply(g, kappa64, u, w->y64, UNO_F64, st);
@@ -550,92 +644,143 @@ static uno_status pcg_loop(const Grid& g, Workspace* w, const double* kappa64, c
                 if (e != UNO_OK) return e;
                 k0 = k;
                 cycle_r = hs.rmax_last;
-                prev_r = -1.0;
+                prev_r[0] = -1.0;
                 chunk = o->graph_chunk > 0 ? o->graph_chunk : 8;
                 continue;
             }
-            const double lvl = kRestartFactor * cycle_r;
-            if (lvl > target) target = lvl;
         }
         if (o->graph_chunk <= 0) {
-            // predict the passes still needed from the observed contraction rate
-            int next = 16;
-            if (prev_r > 0.0 && hs.rmax_last > 0.0 && hs.k_last > prev_k && hs.rmax_last < prev_r) {
-                const double rate = std::pow(hs.rmax_last / prev_r, 1.0 / (hs.k_last - prev_k));
-                const double need = std::log(target / hs.rmax_last) / std::log(rate);
-                next = (int)std::ceil(need * 1.05) + 1;
+            // predict the passes still needed from the observed contraction
+            // rate; the slowest running right-hand side decides
+            int next = 4;
+            for (int b = 0; b < nrhs; ++b) {
+                const CgState& hs = w->host_state[b];
+                if (hs.status != 0 || hs.done != INT_MAX) continue;
+                double target = hs.tol_abs;
+                if (restarts) {
+                    const double lvl = kRestartFactor * cycle_r;
+                    if (lvl > target) target = lvl;
+                }
+                int nx = 16;
+                if (prev_r[b] > 0.0 && hs.rmax_last > 0.0 && hs.k_last > prev_k[b] && hs.rmax_last < prev_r[b]) {
+                    const double rate = std::pow(hs.rmax_last / prev_r[b], 1.0 / (hs.k_last - prev_k[b]));
+                    const double need = std::log(target / hs.rmax_last) / std::log(rate);
+                    nx = (int)std::ceil(need * 1.05) + 1;
+                }
+                if (nx > next) next = nx;
             }
             chunk = next < 4 ? 4 : (next > 256 ? 256 : next);
         }
-        prev_k = hs.k_last;
-        prev_r = hs.rmax_last;
+        for (int b = 0; b < nrhs; ++b) {
+            prev_k[b] = w->host_state[b].k_last;
+            prev_r[b] = w->host_state[b].rmax_last;
+        }
     }
     *k_end = k;
     return UNO_OK;
 }
 
-uno_status pcg_run(const Grid& g, const double* kappa, const double* macro_load3, const double* rhs, double* u,
-                   const uno_solve_opts* o, uno_solve_info* info, double* res_hist, hipStream_t st)
+// nrhs solves with one operator (and preconditioner); load b: macro_loads +
+// 3 b (or rhs + b n), solution u + b n, info[b]
+uno_status pcg_run_batch(const Grid& g, const double* kappa, int nrhs, const double* macro_loads3, const double* rhs,
+                         double* u, const uno_solve_opts* o, uno_solve_info* info, double* res_hist, hipStream_t st)
 {
     const uno_precond* pc = (o->kind == UNO_PREC_UNO) ? o->uno : nullptr;
     const bool mixed = (o->op_t == UNO_F32);
     if (mixed && pc && !uno_use_lowrank(pc)) return UNO_ERR_ARG;
+    // one loop for all right-hand sides where every pass kernel takes them
+    // along grid y; the spectral passes and the FP32 restarts go one by one
+    const bool together = nrhs == 1 || (!mixed && (!pc || uno_use_lowrank(pc)));
+    if (!together) {
+        uno_status worst = UNO_OK;
+        for (int b = 0; b < nrhs; ++b) {
+            uno_status e = pcg_run_batch(g, kappa, 1, macro_loads3 ? macro_loads3 + 3 * b : nullptr,
+                                         rhs ? rhs + (int64_t)b * g.total : nullptr, u + (int64_t)b * g.total, o,
+                                         info ? info + b : nullptr, nullptr, st);
+            if (e == UNO_ERR_BREAKDOWN) worst = e;
+            else if (e != UNO_OK) return e;
+        }
+        return worst;
+    }
     Workspace* w = nullptr;
     const int hist_len = o->max_iter + 1;
-    uno_status e = ws_get(g, pc ? &pc->plan : nullptr, pc ? pc->rs_blocks : 0, hist_len, &w);
+    uno_status e = ws_get(g, pc ? &pc->plan : nullptr, pc ? pc->lr : nullptr, pc ? pc->rs_blocks : 0, hist_len, nrhs,
+                          &w);
     if (e != UNO_OK) return e;
     const int nb = w->nbr;
     const Parts P = parts_of(w);
-    // rhs and initial residual r_0 = f - A u_0 (FP64)
-    if (macro_load3) {
-        e = launch_rhs(g, kappa, UNO_F64, macro_load3, w->f, UNO_F64, st);
+    const int64_t n = g.total;
+    // rhs and initial residual r_0 = f - A u_0 (FP64), per right-hand side
+    for (int b = 0; b < nrhs; ++b) {
+        double* fb = w->f + b * n;
+        if (macro_loads3) {
+            e = launch_rhs(g, kappa, UNO_F64, macro_loads3 + 3 * b, fb, UNO_F64, st);
+            if (e != UNO_OK) return e;
+        } else {
+            UNO_HIP(hipMemcpyAsync(fb, rhs + b * n, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+        }
+        e = launch_fe_apply(g, kappa, u + b * n, w->p + b * n, UNO_F64, st);
         if (e != UNO_OK) return e;
-    } else {
-        UNO_HIP(hipMemcpyAsync(w->f, rhs, sizeof(double) * g.total, hipMemcpyDeviceToDevice, st));
+        hipLaunchKernelGGL(k_sub, dim3(nb), dim3(kBlock), 0, st, n, (const double*)fb, (const double*)(w->p + b * n),
+                           w->r + b * n);
+        UNO_HIP(hipGetLastError());
     }
-    e = launch_fe_apply(g, kappa, u, w->p, UNO_F64, st);
-    if (e != UNO_OK) return e;
-    hipLaunchKernelGGL(k_sub, dim3(nb), dim3(kBlock), 0, st, g.total, (const double*)w->f, (const double*)w->p, w->r);
-    UNO_HIP(hipGetLastError());
     int k = 0;
     if (mixed) {
-        if (!w->kap32 && hipMalloc(&w->kap32, sizeof(float) * g.total) != hipSuccess) return UNO_ERR_NOMEM;
-        if (!w->y64 && hipMalloc(&w->y64, sizeof(double) * g.total) != hipSuccess) return UNO_ERR_NOMEM;
-        hipLaunchKernelGGL(k_convert<float>, dim3(nb), dim3(kBlock), 0, st, g.total, kappa, w->kap32);
-        e = pcg_loop<float>(g, w, kappa, w->kap32, u, o, pc, hist_len, st, &k);
+        if (!w->kap32 && hipMalloc(&w->kap32, sizeof(float) * n) != hipSuccess) return UNO_ERR_NOMEM;
+        if (!w->y64 && hipMalloc(&w->y64, sizeof(double) * n) != hipSuccess) return UNO_ERR_NOMEM;
+        hipLaunchKernelGGL(k_convert<float>, dim3(nb), dim3(kBlock), 0, st, n, kappa, w->kap32);
+        e = pcg_loop<float>(g, w, kappa, w->kap32, u, o, pc, hist_len, nrhs, st, &k);
     } else {
-        e = pcg_loop<double>(g, w, kappa, kappa, u, o, pc, hist_len, st, &k);
+        e = pcg_loop<double>(g, w, kappa, kappa, u, o, pc, hist_len, nrhs, st, &k);
     }
     if (e != UNO_OK) return e;
-    const CgState hs = *w->host_state;
+    std::vector<CgState> hs(w->host_state, w->host_state + nrhs);
     // zero-mean fluctuation (Sec. 5.1) and the true residual in FP64
-    hipLaunchKernelGGL(k_sum_parts, dim3(nb), dim3(kBlock), 0, st, g.total, (const double*)u, P.dp);
-    hipLaunchKernelGGL(k_sub_mean, dim3(nb), dim3(kBlock), 0, st, g.total, u, (const double*)P.dp, nb, w->state);
-    e = launch_fe_apply(g, kappa, u, w->p, UNO_F64, st);
-    if (e != UNO_OK) return e;
-    hipLaunchKernelGGL(k_resid_parts, dim3(nb), dim3(kBlock), 0, st, g.total, (const double*)w->f,
-                       (const double*)w->p, P.rs[0], P.rs[1]);
-    hipLaunchKernelGGL(k_resid_final, dim3(1), dim3(kBlock), 0, st, (const double*)P.rs[0], (const double*)P.rs[1], nb,
-                       w->state);
-    UNO_HIP(hipGetLastError());
-    UNO_HIP(hipMemcpyAsync(w->host_state, w->state, sizeof(CgState), hipMemcpyDeviceToHost, st));
-    const int iters = (hs.done != INT_MAX) ? hs.done : (hs.status != 0 ? hs.fail_iter : k);
-    if (res_hist) {
-        int nh = iters + 1;
+    for (int b = 0; b < nrhs; ++b) {
+        double* ub = u + b * n;
+        double* pa = P.rs[0] + (int64_t)b * w->npart;
+        double* pb = P.rs[1] + (int64_t)b * w->npart;
+        double* pd = P.dp + (int64_t)b * w->npart;
+        hipLaunchKernelGGL(k_sum_parts, dim3(nb), dim3(kBlock), 0, st, n, (const double*)ub, pd);
+        hipLaunchKernelGGL(k_sub_mean, dim3(nb), dim3(kBlock), 0, st, n, ub, (const double*)pd, nb, w->state + b);
+        e = launch_fe_apply(g, kappa, ub, w->p + b * n, UNO_F64, st);
+        if (e != UNO_OK) return e;
+        hipLaunchKernelGGL(k_resid_parts, dim3(nb), dim3(kBlock), 0, st, n, (const double*)(w->f + b * n),
+                           (const double*)(w->p + b * n), pa, pb);
+        hipLaunchKernelGGL(k_resid_final, dim3(1), dim3(kBlock), 0, st, (const double*)pa, (const double*)pb, nb,
+                           w->state + b);
+        UNO_HIP(hipGetLastError());
+    }
+    UNO_HIP(hipMemcpyAsync(w->host_state, w->state, sizeof(CgState) * nrhs, hipMemcpyDeviceToHost, st));
+    const int iters0 = (hs[0].done != INT_MAX) ? hs[0].done : (hs[0].status != 0 ? hs[0].fail_iter : k);
+    if (res_hist && nrhs == 1) {
+        int nh = iters0 + 1;
         if (nh > hist_len) nh = hist_len;
         UNO_HIP(hipMemcpyAsync(res_hist, w->hist, sizeof(double) * nh, hipMemcpyDeviceToHost, st));
     }
     UNO_HIP(hipStreamSynchronize(st));
-    const CgState& fin = *w->host_state;
-    if (info) {
-        info->iters = iters;
-        info->converged = (hs.status == 0 && hs.done != INT_MAX) ? 1 : 0;
-        info->rel_res = hs.r0max > 0.0 ? hs.rmax_last / hs.r0max : 0.0;
-        info->true_rel_res = fin.fmax > 0.0 ? fin.dmax / fin.fmax : 0.0;
-        info->r0_norm = hs.r0max;
+    bool failed = false;
+    for (int b = 0; b < nrhs; ++b) {
+        const CgState& h = hs[b];
+        const CgState& fin = w->host_state[b];
+        if (h.status != 0) failed = true;
+        if (info) {
+            uno_solve_info& I = info[b];
+            I.iters = (h.done != INT_MAX) ? h.done : (h.status != 0 ? h.fail_iter : k);
+            I.converged = (h.status == 0 && h.done != INT_MAX) ? 1 : 0;
+            I.rel_res = h.r0max > 0.0 ? h.rmax_last / h.r0max : 0.0;
+            I.true_rel_res = fin.fmax > 0.0 ? fin.dmax / fin.fmax : 0.0;
+            I.r0_norm = h.r0max;
+        }
     }
-    if (hs.status != 0) return UNO_ERR_BREAKDOWN;
-    return UNO_OK;
+    return failed ? UNO_ERR_BREAKDOWN : UNO_OK;
+}
+
+uno_status pcg_run(const Grid& g, const double* kappa, const double* macro_load3, const double* rhs, double* u,
+                   const uno_solve_opts* o, uno_solve_info* info, double* res_hist, hipStream_t st)
+{
+    return pcg_run_batch(g, kappa, 1, macro_load3, rhs, u, o, info, res_hist, st);
 }
 
 }  // namespace unocg

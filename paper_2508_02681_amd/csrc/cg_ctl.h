@@ -26,7 +26,27 @@ struct CgIter {
     const double* r;          // FP64 residual (for r.s in the preconditioner's last pass)
     double* part_rs;          // r.s partials of pass k
     double* part_ssum;        // sum(s) partials of pass k (FP32 mode: mean removal)
+    // several right-hand sides solved together (blockIdx.y = rhs index):
+    // strides between their vectors, partial buffers and scalar histories
+    int64_t vs;
+    int ps;
+    int hs;
 };
+
+// The control of right-hand side blockIdx.y (state, partials, history).
+__device__ __forceinline__ CgIter rhs_iter(CgIter c)
+{
+    const int b = blockIdx.y;
+    if (b == 0) return c;
+    if (c.st) c.st += b;
+    const int64_t po = (int64_t)b * c.ps;
+    if (c.part_rmax) c.part_rmax += po;
+    if (c.part_rs) c.part_rs += po;
+    if (c.part_ssum) c.part_ssum += po;
+    if (c.hist) c.hist += (int64_t)b * c.hs;
+    if (c.r) c.r += (int64_t)b * c.vs;
+    return c;
+}
 
 __device__ __forceinline__ bool loop_ended(const CgState* st, int k)
 {

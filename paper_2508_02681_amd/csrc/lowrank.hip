@@ -34,6 +34,7 @@ struct LowRankDev {
     int mx, m;          // learned half-widths along x (0 for one voxel layer) and y, z
     int kxn, kyn, kzn;  // 2mx+1, 2m+1, m+1
     double W;           // bypass theta0^2
+    int64_t gps, hsz;   // per right-hand side: row-chunk partial and H sizes (double2)
     const double2* twx; // exp(-2 pi i j / n_b) tables
     const double2* twy;
     const double2* twz;
@@ -61,6 +62,21 @@ __global__ void __launch_bounds__(256) k_lr_fwd(LowRankDev L, int ny_chunk, doub
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double slots[4];
+    if (blockIdx.y > 0) {  // right-hand side blockIdx.y of a batch
+        const int64_t vo = (int64_t)blockIdx.y * it.vs, po = (int64_t)blockIdx.y * it.ps;
+        r += vo;
+        if (UPDATE) {
+            u += vo;
+            d += vo;
+            p += vo;
+            part_dp += po;
+            gam += (int64_t)blockIdx.y * it.hs;
+            part_rmax += po;
+        }
+        Gp += (int64_t)blockIdx.y * L.gps;
+        if (part_rr) part_rr += po;
+        it = rhs_iter(it);
+    }
     const int nch = (L.n1 + ny_chunk - 1) / ny_chunk;
     const int x = blockIdx.x / nch, ch = blockIdx.x % nch;
     const int y0 = ch * ny_chunk;
@@ -200,6 +216,12 @@ __global__ void __launch_bounds__(64) k_lr_mid(LowRankDev L, int nch, const doub
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double slots[4];
+    if (blockIdx.y > 0) {
+        Gp += (int64_t)blockIdx.y * L.gps;
+        H += (int64_t)blockIdx.y * L.hsz;
+        if (part_corr) part_corr += (int64_t)blockIdx.y * it.ps;
+        it = rhs_iter(it);
+    }
     const int col = blockIdx.x;  // ky index * kzn + kz
     const int plane = L.kyn * L.kzn;
     double2* twx = (double2*)smem;  // n0
@@ -271,6 +293,13 @@ __global__ void __launch_bounds__(256) k_lr_inv(LowRankDev L, int y_chunk, const
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double slots[4];
+    if (blockIdx.y > 0) {
+        const int64_t vo = (int64_t)blockIdx.y * it.vs;
+        r += vo;
+        s += vo;
+        H += (int64_t)blockIdx.y * L.hsz;
+        it = rhs_iter(it);
+    }
     const int nch = (L.n1 + y_chunk - 1) / y_chunk;
     const int x = blockIdx.x / nch;
     const int y0 = (blockIdx.x % nch) * y_chunk;
@@ -402,6 +431,19 @@ __global__ void __launch_bounds__(256) k_lr_tile(GridDev g, TileGeom tg, LowRank
     const int tyi = b % tg.tiles_y;
     const int txi = b / tg.tiles_y;
     const int x0 = txi * TX, y0 = tyi * TY, z0 = tzi * TZ;
+    if (blockIdx.y > 0) {  // right-hand side blockIdx.y of a batch
+        const int64_t vo = (int64_t)blockIdx.y * it.vs, po = (int64_t)blockIdx.y * it.ps;
+        r += vo;
+        dold += vo;
+        dnew += vo;
+        p += vo;
+        H += (int64_t)blockIdx.y * L.hsz;
+        part_dp += po;
+        a.part_rr += po;
+        a.part_corr += po;
+        gam += (int64_t)blockIdx.y * it.hs;
+        it = rhs_iter(it);
+    }
 
     // every global load first: state, both partial sets, previous gamma, r
     // and d_old on the halo, conductivities, H planes, phase factors
@@ -711,6 +753,8 @@ uno_status lowrank_create(const Grid& g, const FftPlan& fp, int M, double W, con
     p->lds_t = dyn;
     const int64_t ngp = (int64_t)L.n0 * p->nch_a * plane;
     const int64_t nh = (int64_t)L.n0 * plane;
+    L.gps = ngp;
+    L.hsz = nh;
     if (hipMalloc(&p->table, sizeof(double) * nb) != hipSuccess ||
         hipMalloc(&p->Gp, sizeof(double2) * ngp) != hipSuccess || hipMalloc(&p->H, sizeof(double2) * nh) != hipSuccess) {
         (void)hipFree(p->table);
@@ -742,6 +786,11 @@ int lowrank_max_blocks(const LowRankPlan* p)
 }
 bool lowrank_fused(const LowRankPlan* p) { return p->fused; }
 int lowrank_update_blocks(const LowRankPlan* p) { return p->blocks_a; }
+void lowrank_scratch_size(const LowRankPlan* p, int64_t* ngp, int64_t* nh)
+{
+    *ngp = p->dev.gps;
+    *nh = p->dev.hsz;
+}
 
 static CgIter no_iter()
 {
@@ -750,12 +799,16 @@ static CgIter no_iter()
     return it;
 }
 
+static LrBatch own(const LowRankPlan* p) { return LrBatch{p->Gp, p->H, 1}; }
+
 // pass A on r (no update); also the initial transform of the CG loop
-// (part_rr, nullable: ||r||^2 partials for the fused flow)
-uno_status lowrank_forward(const LowRankPlan* p, const double* r, double* part_rr, hipStream_t st)
+// (part_rr, nullable: ||r||^2 partials for the fused flow; `strides`: the
+// vector and partial strides of a batch)
+uno_status lowrank_forward(const LowRankPlan* p, const double* r, double* part_rr, const LrBatch& bt,
+                           const CgIter& strides, hipStream_t st)
 {
-    uno_launch(UNO_KT_FFT_FWD, k_lr_fwd<false, double>, dim3(p->blocks_a), dim3(256), p->lds_a, st, p->dev, p->ya,
-               (double*)r, (double*)nullptr, (const double*)nullptr, (const double*)nullptr, p->Gp, no_iter(),
+    uno_launch(UNO_KT_FFT_FWD, k_lr_fwd<false, double>, dim3(p->blocks_a, bt.nrhs), dim3(256), p->lds_a, st, p->dev,
+               p->ya, (double*)r, (double*)nullptr, (const double*)nullptr, (const double*)nullptr, bt.Gp, strides,
                (const double*)nullptr, 0, (const double*)nullptr, (double*)nullptr, part_rr);
     return hip_status(hipGetLastError());
 }
@@ -764,21 +817,21 @@ uno_status lowrank_forward(const LowRankPlan* p, const double* r, double* part_r
 template <typename T>
 uno_status lowrank_update_forward(const LowRankPlan* p, double* r, double* u, const T* d, const T* pv,
                                   const CgIter& it, const double* part_dp, int np_dp, const double* gam,
-                                  double* part_rmax, double* part_rr, hipStream_t st)
+                                  double* part_rmax, double* part_rr, const LrBatch& bt, hipStream_t st)
 {
-    uno_launch(UNO_KT_UPDATE, k_lr_fwd<true, T>, dim3(p->blocks_a), dim3(256), p->lds_a, st, p->dev, p->ya, r, u, d, pv,
-               p->Gp, it, part_dp, np_dp, gam, part_rmax, part_rr);
+    uno_launch(UNO_KT_UPDATE, k_lr_fwd<true, T>, dim3(p->blocks_a, bt.nrhs), dim3(256), p->lds_a, st, p->dev, p->ya, r,
+               u, d, pv, bt.Gp, it, part_dp, np_dp, gam, part_rmax, part_rr);
     return hip_status(hipGetLastError());
 }
 
 template <int TX, bool NEAR>
 static void launch_lr_tile(const LowRankPlan* p, const GridDev& g, const double* kappa, const double* r,
                            const double* dold, double* dnew, double* pv, double* part_dp, const CgIter& it,
-                           const LrTileArgs& a, double* gam, hipStream_t st)
+                           const LrTileArgs& a, double* gam, const LrBatch& bt, hipStream_t st)
 {
     const TileChoice& c = p->tile;
-    const dim3 grid(c.blocks), blk(256);
-    const double2* H = p->H;
+    const dim3 grid(c.blocks, bt.nrhs), blk(256);
+    const double2* H = bt.H;
     switch (c.tz) {
         case 64:
             uno_launch(UNO_KT_MATVEC, k_lr_tile<TX, 64, NEAR>, grid, blk, p->lds_t, st, g, c.geom, p->dev, kappa, r, H,
@@ -798,12 +851,12 @@ static void launch_lr_tile(const LowRankPlan* p, const GridDev& g, const double*
 template <int TX>
 static void launch_lr_tile_tx(const LowRankPlan* p, const GridDev& g, const double* kappa, const double* r,
                               const double* dold, double* dnew, double* pv, double* part_dp, const CgIter& it,
-                              const LrTileArgs& a, double* gam, hipStream_t st)
+                              const LrTileArgs& a, double* gam, const LrBatch& bt, hipStream_t st)
 {
     if (tile_near(p->tile, g))
-        launch_lr_tile<TX, true>(p, g, kappa, r, dold, dnew, pv, part_dp, it, a, gam, st);
+        launch_lr_tile<TX, true>(p, g, kappa, r, dold, dnew, pv, part_dp, it, a, gam, bt, st);
     else
-        launch_lr_tile<TX, false>(p, g, kappa, r, dold, dnew, pv, part_dp, it, a, gam, st);
+        launch_lr_tile<TX, false>(p, g, kappa, r, dold, dnew, pv, part_dp, it, a, gam, bt, st);
 }
 
 // Fused FP64 CG pass, first half: pass B (convergence test, H, Parseval
@@ -811,20 +864,21 @@ static void launch_lr_tile_tx(const LowRankPlan* p, const GridDev& g, const doub
 // d = s + beta d_old, p = A d, d.p partials).  Returns the d.p partial count.
 uno_status lowrank_fused_pass(const LowRankPlan* p, const Grid& g, const double* kappa, const double* r,
                               const double* dold, double* dnew, double* pv, double* part_dp, const CgIter& it,
-                              double* part_corr, const double* part_rr, double* gam, hipStream_t st, int* np_dp)
+                              double* part_corr, const double* part_rr, double* gam, const LrBatch& bt,
+                              hipStream_t st, int* np_dp)
 {
     if (!p->fused) return UNO_ERR_SHAPE;
     const LowRankDev& L = p->dev;
-    uno_launch(UNO_KT_FFT_MID, k_lr_mid, dim3(L.kyn * L.kzn), dim3(64), p->lds_b, st, L, p->nch_a,
-               (const double*)p->table, (const double2*)p->Gp, p->H, it, part_corr);
+    uno_launch(UNO_KT_FFT_MID, k_lr_mid, dim3(L.kyn * L.kzn, bt.nrhs), dim3(64), p->lds_b, st, L, p->nch_a,
+               (const double*)p->table, (const double2*)bt.Gp, bt.H, it, part_corr);
     UNO_HIP(hipGetLastError());
     const LrTileArgs a{part_rr, p->blocks_a, part_corr, L.kyn * L.kzn};
     if (p->tile.tx == 1)
-        launch_lr_tile_tx<1>(p, g.dev, kappa, r, dold, dnew, pv, part_dp, it, a, gam, st);
+        launch_lr_tile_tx<1>(p, g.dev, kappa, r, dold, dnew, pv, part_dp, it, a, gam, bt, st);
     else if (p->tile.tx == 2)
-        launch_lr_tile_tx<2>(p, g.dev, kappa, r, dold, dnew, pv, part_dp, it, a, gam, st);
+        launch_lr_tile_tx<2>(p, g.dev, kappa, r, dold, dnew, pv, part_dp, it, a, gam, bt, st);
     else
-        launch_lr_tile_tx<4>(p, g.dev, kappa, r, dold, dnew, pv, part_dp, it, a, gam, st);
+        launch_lr_tile_tx<4>(p, g.dev, kappa, r, dold, dnew, pv, part_dp, it, a, gam, bt, st);
     UNO_HIP(hipGetLastError());
     *np_dp = p->tile.blocks;
     return UNO_OK;
@@ -833,19 +887,19 @@ uno_status lowrank_fused_pass(const LowRankPlan* p, const Grid& g, const double*
 // passes B and C (B tests convergence inside CG); C writes s and r.s partials
 template <typename T>
 uno_status lowrank_finish(const LowRankPlan* p, const double* r, T* s, const CgIter* itp, int* np_rs,
-                          hipStream_t st)
+                          const LrBatch& bt, hipStream_t st)
 {
     const LowRankDev& L = p->dev;
     const CgIter it = itp ? *itp : no_iter();
-    uno_launch(UNO_KT_FFT_MID, k_lr_mid, dim3(L.kyn * L.kzn), dim3(64), p->lds_b, st, L, p->nch_a,
-               (const double*)p->table, (const double2*)p->Gp, p->H, it, (double*)nullptr);
+    uno_launch(UNO_KT_FFT_MID, k_lr_mid, dim3(L.kyn * L.kzn, bt.nrhs), dim3(64), p->lds_b, st, L, p->nch_a,
+               (const double*)p->table, (const double2*)bt.Gp, bt.H, it, (double*)nullptr);
     UNO_HIP(hipGetLastError());
     if (itp)
-        uno_launch(UNO_KT_FFT_INV, k_lr_inv<true, T>, dim3(p->blocks_c), dim3(256), p->lds_c, st, L, p->yc, r,
-                   (const double2*)p->H, s, it);
+        uno_launch(UNO_KT_FFT_INV, k_lr_inv<true, T>, dim3(p->blocks_c, bt.nrhs), dim3(256), p->lds_c, st, L, p->yc, r,
+                   (const double2*)bt.H, s, it);
     else
-        uno_launch(UNO_KT_FFT_INV, k_lr_inv<false, T>, dim3(p->blocks_c), dim3(256), p->lds_c, st, L, p->yc, r,
-                   (const double2*)p->H, s, it);
+        uno_launch(UNO_KT_FFT_INV, k_lr_inv<false, T>, dim3(p->blocks_c, bt.nrhs), dim3(256), p->lds_c, st, L, p->yc,
+                   r, (const double2*)bt.H, s, it);
     UNO_HIP(hipGetLastError());
     if (np_rs) *np_rs = p->blocks_c;
     return UNO_OK;
@@ -853,18 +907,20 @@ uno_status lowrank_finish(const LowRankPlan* p, const double* r, T* s, const CgI
 
 uno_status lowrank_apply(const LowRankPlan* p, const double* r, double* s, hipStream_t st)
 {
-    uno_status e = lowrank_forward(p, r, nullptr, st);
+    uno_status e = lowrank_forward(p, r, nullptr, own(p), no_iter(), st);
     if (e != UNO_OK) return e;
-    return lowrank_finish<double>(p, r, s, nullptr, nullptr, st);
+    return lowrank_finish<double>(p, r, s, nullptr, nullptr, own(p), st);
 }
 
-template uno_status lowrank_finish<double>(const LowRankPlan*, const double*, double*, const CgIter*, int*, hipStream_t);
-template uno_status lowrank_finish<float>(const LowRankPlan*, const double*, float*, const CgIter*, int*, hipStream_t);
+template uno_status lowrank_finish<double>(const LowRankPlan*, const double*, double*, const CgIter*, int*,
+                                           const LrBatch&, hipStream_t);
+template uno_status lowrank_finish<float>(const LowRankPlan*, const double*, float*, const CgIter*, int*,
+                                          const LrBatch&, hipStream_t);
 template uno_status lowrank_update_forward<double>(const LowRankPlan*, double*, double*, const double*, const double*,
                                                    const CgIter&, const double*, int, const double*, double*, double*,
-                                                   hipStream_t);
+                                                   const LrBatch&, hipStream_t);
 template uno_status lowrank_update_forward<float>(const LowRankPlan*, double*, double*, const float*, const float*,
                                                   const CgIter&, const double*, int, const double*, double*, double*,
-                                                  hipStream_t);
+                                                  const LrBatch&, hipStream_t);
 
 }  // namespace unocg

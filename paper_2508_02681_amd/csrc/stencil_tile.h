@@ -123,6 +123,22 @@ __global__ void __launch_bounds__(256) k_stencil_tile(GridDev g, TileGeom tg, co
     const int tyi = b % tg.tiles_y;
     const int txi = b / tg.tiles_y;
     const int x0 = txi * TX, y0 = tyi * TY, z0 = tzi * TZ;
+    if (CG && blockIdx.y > 0) {  // right-hand side blockIdx.y of a batch
+        const int64_t vo = (int64_t)blockIdx.y * it.vs, po = (int64_t)blockIdx.y * it.ps;
+        s += vo;
+        dold += vo;
+        dnew += vo;
+        p += vo;
+        part_dp += po;
+        part_rs += po;
+        gam += (int64_t)blockIdx.y * it.hs;
+        if (MF) {
+            mf.part_s += po;
+            mf.part_dold += po;
+            mf.part_dnew += po;
+        }
+        it = rhs_iter(it);
+    }
 
     // every global load is issued before the first decision, so the loop
     // state, the partials, the previous gamma and the staged data overlap
@@ -297,20 +313,21 @@ inline TileChoice choose_tile(const Grid& g)
 template <typename T, bool CG, bool HEAD, int TX, bool NEAR>
 inline void launch_tile_near(const TileChoice& c, const GridDev& g, const T* kappa, const T* s, const T* dold, T* dnew,
                              T* p, double* part_dp, const CgIter& it, const double* part_rs, int np_rs, double* gam,
-                             hipStream_t st, const MeanFree& mf)
+                             hipStream_t st, const MeanFree& mf, int nrhs)
 {
+    const dim3 grid(c.blocks, nrhs);
     switch (c.tz) {
         case 64:
-            uno_launch(UNO_KT_MATVEC, k_stencil_tile<T, TX, 64, CG, HEAD, NEAR>, dim3(c.blocks), dim3(256), 0, st, g,
-                       c.geom, kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam, mf);
+            uno_launch(UNO_KT_MATVEC, k_stencil_tile<T, TX, 64, CG, HEAD, NEAR>, grid, dim3(256), 0, st, g, c.geom,
+                       kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam, mf);
             break;
         case 32:
-            uno_launch(UNO_KT_MATVEC, k_stencil_tile<T, TX, 32, CG, HEAD, NEAR>, dim3(c.blocks), dim3(256), 0, st, g,
-                       c.geom, kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam, mf);
+            uno_launch(UNO_KT_MATVEC, k_stencil_tile<T, TX, 32, CG, HEAD, NEAR>, grid, dim3(256), 0, st, g, c.geom,
+                       kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam, mf);
             break;
         default:
-            uno_launch(UNO_KT_MATVEC, k_stencil_tile<T, TX, 16, CG, HEAD, NEAR>, dim3(c.blocks), dim3(256), 0, st, g,
-                       c.geom, kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam, mf);
+            uno_launch(UNO_KT_MATVEC, k_stencil_tile<T, TX, 16, CG, HEAD, NEAR>, grid, dim3(256), 0, st, g, c.geom,
+                       kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam, mf);
             break;
     }
 }
@@ -324,27 +341,33 @@ inline bool tile_near(const TileChoice& c, const GridDev& g)
 template <typename T, bool CG, bool HEAD, int TX>
 inline void launch_tile_tx(const TileChoice& c, const GridDev& g, const T* kappa, const T* s, const T* dold, T* dnew,
                            T* p, double* part_dp, const CgIter& it, const double* part_rs, int np_rs, double* gam,
-                           hipStream_t st, const MeanFree& mf)
+                           hipStream_t st, const MeanFree& mf, int nrhs)
 {
     if (tile_near(c, g))
-        launch_tile_near<T, CG, HEAD, TX, true>(c, g, kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam, st, mf);
+        launch_tile_near<T, CG, HEAD, TX, true>(c, g, kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam, st, mf,
+                                                nrhs);
     else
-        launch_tile_near<T, CG, HEAD, TX, false>(c, g, kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam, st, mf);
+        launch_tile_near<T, CG, HEAD, TX, false>(c, g, kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam, st,
+                                                 mf, nrhs);
 }
 
-// Launches the tiled operator; returns the number of workgroups (= d.p partials).
+// Launches the tiled operator (nrhs right-hand sides along grid y); returns
+// the number of workgroups per right-hand side (= d.p partials).
 template <typename T, bool CG, bool HEAD>
 inline int launch_tile(const Grid& g, const T* kappa, const T* s, const T* dold, T* dnew, T* p, double* part_dp,
                        const CgIter& it, const double* part_rs, int np_rs, double* gam, hipStream_t st,
-                       const MeanFree& mf = MeanFree{nullptr, nullptr, nullptr})
+                       const MeanFree& mf = MeanFree{nullptr, nullptr, nullptr}, int nrhs = 1)
 {
     const TileChoice c = choose_tile(g);
     if (c.tx == 1)
-        launch_tile_tx<T, CG, HEAD, 1>(c, g.dev, kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam, st, mf);
+        launch_tile_tx<T, CG, HEAD, 1>(c, g.dev, kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam, st, mf,
+                                       nrhs);
     else if (c.tx == 2)
-        launch_tile_tx<T, CG, HEAD, 2>(c, g.dev, kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam, st, mf);
+        launch_tile_tx<T, CG, HEAD, 2>(c, g.dev, kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam, st, mf,
+                                       nrhs);
     else
-        launch_tile_tx<T, CG, HEAD, 4>(c, g.dev, kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam, st, mf);
+        launch_tile_tx<T, CG, HEAD, 4>(c, g.dev, kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam, st, mf,
+                                       nrhs);
     return c.blocks;
 }
 

@@ -138,24 +138,33 @@ struct CgState {
 // ---------------------------------------------------------------------------
 // UNO apply restricted to the learned modes (lowrank.hip)
 struct LowRankPlan;
+// row-chunk partials and H of nrhs right-hand sides (the plan's own for one)
+struct LrBatch {
+    double2* Gp;
+    double2* H;
+    int nrhs;
+};
 uno_status lowrank_create(const Grid& g, const FftPlan& fp, int M, double W, const std::vector<double>& cblock,
                           LowRankPlan** out);
 void lowrank_destroy(LowRankPlan* p);
 int lowrank_max_blocks(const LowRankPlan* p);
 int lowrank_update_blocks(const LowRankPlan* p);
+void lowrank_scratch_size(const LowRankPlan* p, int64_t* ngp, int64_t* nh);
 uno_status lowrank_apply(const LowRankPlan* p, const double* r, double* s, hipStream_t st);
-uno_status lowrank_forward(const LowRankPlan* p, const double* r, double* part_rr, hipStream_t st);
+uno_status lowrank_forward(const LowRankPlan* p, const double* r, double* part_rr, const LrBatch& bt,
+                           const CgIter& strides, hipStream_t st);
 template <typename T>
 uno_status lowrank_update_forward(const LowRankPlan* p, double* r, double* u, const T* d, const T* pv,
                                   const CgIter& it, const double* part_dp, int np_dp, const double* gam,
-                                  double* part_rmax, double* part_rr, hipStream_t st);
+                                  double* part_rmax, double* part_rr, const LrBatch& bt, hipStream_t st);
 bool lowrank_fused(const LowRankPlan* p);
 uno_status lowrank_fused_pass(const LowRankPlan* p, const Grid& g, const double* kappa, const double* r,
                               const double* dold, double* dnew, double* pv, double* part_dp, const CgIter& it,
-                              double* part_corr, const double* part_rr, double* gam, hipStream_t st, int* np_dp);
+                              double* part_corr, const double* part_rr, double* gam, const LrBatch& bt,
+                              hipStream_t st, int* np_dp);
 template <typename T>
 uno_status lowrank_finish(const LowRankPlan* p, const double* r, T* s, const CgIter* it, int* np_rs,
-                          hipStream_t st);
+                          const LrBatch& bt, hipStream_t st);
 int fft_c2r_blocks(const Grid& g, const FftPlan& p);
 
 }  // namespace unocg

@@ -1,0 +1,121 @@
+"""GPU: several load cases of one microstructure solved together
+(pcg_solve_batch, every pass kernel carrying all right-hand sides) give
+exactly the results of separate pcg_solve calls, and match the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import synth_inputs as si
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+@pytest.fixture(scope="module")
+def uno():
+    import paper_2508_02681_amd as u
+    u.lib()
+    assert torch.cuda.is_available()
+    return u
+
+
+def T(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+
+
+def _kappa(shape, seed):
+    ph, _ = si.rsa_inclusions(shape, 2, 4, 0.25, seed)
+    return si.two_phase_kappa(ph, 1.0, 100.0)
+
+
+def _precond(uno, shape, M, path=0):
+    th = si.random_theta(uno.num_weights(len(shape), M), 7, scale=0.05, spread=0.2)
+    p = uno.UnoPrecond.create(shape, M, th)
+    if path:
+        p.set_path(path)
+    return p
+
+
+# (shape, kind, M, path): the fused FP64 learned-mode flow, the four-kernel
+# learned-mode flow (block too large for the fused tile), Jacobi, none, and
+# the spectral path (run load by load)
+CASES = [
+    ((24, 20, 16), "uno", 3, 0),
+    ((64, 64, 64), "uno", 17, 0),
+    ((24, 20, 16), "jacobi", 0, 0),
+    ((20, 12, 16), "none", 0, 0),
+    ((16, 12, 10), "uno", 2, 1),
+    ((32, 32), "uno", 4, 0),
+    ((32, 32), "jacobi", 0, 0),
+]
+
+
+@pytest.mark.parametrize("shape,kind,M,path", CASES)
+def test_batch_equals_single_solves(uno, shape, kind, M, path):
+    kap = T(_kappa(shape, 41))
+    d = len(shape)
+    loads = np.eye(d)
+    p = _precond(uno, shape, M, path) if kind == "uno" else None
+    rtol = 1e-8
+    print("batch", shape, kind, M, path, flush=True)
+    ub, infos = uno.pcg_solve_batch(kap, macro_loads=loads, kind=kind, precond=p, rtol=rtol, max_iter=20000)
+    for j in range(d):
+        us, info = uno.pcg_solve(kap, macro_load=loads[j], kind=kind, precond=p, rtol=rtol, max_iter=20000)
+        assert infos[j]["converged"] and info["converged"]
+        assert infos[j]["iters"] == info["iters"]
+        assert torch.equal(ub[j], us), "load %d differs from the single solve" % j
+        assert infos[j]["rel_res"] == info["rel_res"]
+
+
+def test_batch_zero_load_among_others(uno):
+    """A zero load converges at pass 0 (u = 0) while the others run on."""
+    shape = (24, 20, 16)
+    kap = T(_kappa(shape, 42))
+    p = _precond(uno, shape, 3)
+    loads = np.array([[1.0, 0.0, 0.0], [0.0, 0.0, 0.0], [0.3, -0.2, 1.0]])
+    ub, infos = uno.pcg_solve_batch(kap, macro_loads=loads, kind="uno", precond=p, rtol=1e-8)
+    assert infos[1]["iters"] == 0 and infos[1]["converged"]
+    assert float(ub[1].abs().max()) == 0.0
+    for j in (0, 2):
+        us, info = uno.pcg_solve(kap, macro_load=loads[j], kind="uno", precond=p, rtol=1e-8)
+        assert infos[j]["iters"] == info["iters"] > 0
+        assert torch.equal(ub[j], us)
+
+
+def test_batch_effective_tensor_matches_oracle(orc, uno):
+    shape, M = (16, 16, 16), 3
+    kapn = _kappa(shape, 43)
+    kap = T(kapn)
+    p = _precond(uno, shape, M)
+    loads = np.eye(3)
+    ub, infos = uno.pcg_solve_batch(kap, macro_loads=loads, kind="uno", precond=p, rtol=1e-12)
+    assert all(i["converged"] for i in infos)
+    kb = uno.effective_tensor(kap, loads, ub)
+    sols = [orc.pcg(kapn, orc.rhs(kapn, g), "jacobi", rtol=1e-12)[0] for g in loads]
+    kbo = orc.effective_tensor(kapn, sols, list(loads))
+    assert np.abs(kb - kbo).max() / np.abs(kbo).max() < 1e-8
+
+
+def test_batch_rhs_argument_and_mixed_mode(uno):
+    """Device right-hand sides instead of macroscopic loads; the FP32 mode
+    (run load by load) gives the same results as single FP32 solves."""
+    shape = (20, 16, 12)
+    kap = T(_kappa(shape, 44))
+    p = _precond(uno, shape, 2, 2)
+    f = torch.stack([uno.uno_macro_rhs(kap, g) for g in np.eye(3)])
+    kw = dict(kind="uno", precond=p, rtol=1e-7, op_dtype=torch.float32, prec_dtype=torch.float32)
+    ub, infos = uno.pcg_solve_batch(kap, rhs=f, **kw)
+    for j in range(3):
+        us, info = uno.pcg_solve(kap, rhs=f[j], **kw)
+        assert infos[j]["iters"] == info["iters"]
+        assert torch.equal(ub[j], us)
+
+
+def test_batch_argument_errors(uno):
+    shape = (8, 8, 8)
+    kap = T(_kappa(shape, 45))
+    with pytest.raises(uno.UnoError):
+        uno.pcg_solve_batch(kap, macro_loads=np.zeros((0, 3)), kind="jacobi")
+    with pytest.raises(uno.UnoError):
+        uno.pcg_solve_batch(kap, macro_loads=np.ones((65, 3)), kind="jacobi")
