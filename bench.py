@@ -37,17 +37,18 @@ LOADS = np.eye(3)
 RTOL = 1e-6
 HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs of
-# this benchmark (64^3, M = 12), each scaled by what the counter reads for a
+# this benchmark (64^3, M = 12, three loads per launch), each scaled by what the counter reads for a
 # device copy of known size (FETCH x 2, WRITE x 1); the summary with its
-# commands is profiles/k_lr_tile_64cubed_hbm_counters.md.  Valid only for the
+# commands is profiles/uno_cg_64cubed_hbm_counters.md.  Valid only for the
 # kernel sources as they were when counted (TRAFFIC_SRC: hash of the files in
 # TRAFFIC_FILES); after any change the figure is withheld.
-TRAFFIC_FILES = ["lowrank.hip", "stencil_tile.h", "cg_ctl.h", "reduce.h"]
-TRAFFIC_SRC = "969670fcd4e6a152"
+TRAFFIC_FILES = ["lowrank.hip", "stencil_tile.h", "cg_ctl.h", "reduce.h", "cg.hip"]
+TRAFFIC_SRC = "630c4e1ce704ade9"
 TRAFFIC_BYTES = {
-    "k_lr_tile<2,32>": int((2 * 7727.3 + 3773.1) * 1024),
-    "k_lr_fwd<update,double>": int((2 * 4183.2 + 4451.1) * 1024),
-    "k_lr_mid": int((2 * 3377.5 + 370.5) * 1024),
+    "k_lr_fwd<update,double>": 34666713,
+    "k_stencil_tile<double,CG>": 41394308,
+    "k_lr_mid": 16458528,
+    "k_lr_inv<double>": 12990591,
 }
 
 
@@ -250,16 +251,17 @@ def main():
     nspec = SHAPE[0] * SHAPE[1] * (SHAPE[2] // 2 + 1)
     nblk = SHAPE[0] * (2 * M + 1) * (M + 1)   # learned block after the two partial DFTs (y, z)
     if learned:
-        # FP64 CG on the learned modes: pass B -> [pass C + operator] -> [update + pass A]
-        fams = {uno.KT_MATVEC: "k_lr_tile<2,32>", uno.KT_UPDATE: "k_lr_fwd<update,double>",
-                uno.KT_FFT_MID: "k_lr_mid"}
-        # algorithmic bytes per launch (FP64): the minimum each kernel must move
-        # (a launch carries the 3 load cases; kappa and the table are shared)
+        # FP64 CG on the learned modes: pass B -> pass C -> operator -> [update + pass A]
+        fams = {uno.KT_MATVEC: "k_stencil_tile<double,CG>", uno.KT_UPDATE: "k_lr_fwd<update,double>",
+                uno.KT_FFT_MID: "k_lr_mid", uno.KT_FFT_INV: "k_lr_inv<double>"}
+        # algorithmic bytes per launch (FP64), the minimum each kernel must
+        # move; a launch carries the 3 load cases, kappa and the table are shared
         nr = len(LOADS)
         bytes_per = {
-            uno.KT_MATVEC: nr * (n_dof * 8 * 4 + nblk * 16) + n_dof * 8,  # read r, d_old, H; write d_new, p; kappa
+            uno.KT_MATVEC: nr * n_dof * 8 * 4 + n_dof * 8,    # read s, d_old; write d_new, p; kappa
             uno.KT_UPDATE: nr * (n_dof * 8 * 6 + nblk * 16),  # read r, u, d, p; write r, u, block spectrum
             uno.KT_FFT_MID: nr * nblk * 16 * 2 + nblk * 8,     # block spectrum in/out; table
+            uno.KT_FFT_INV: nr * (n_dof * 8 * 2 + nblk * 16),  # read r, H; write s
         }
     else:
         fams = {uno.KT_MATVEC: "k_stencil_tile<double,CG>", uno.KT_UPDATE: "k_cg_update<double>",

@@ -123,8 +123,12 @@ uno_status uno_precond_apply(const uno_precond *p, const void *r, void *s, uno_d
  * learned block is small against the grid): since Phi equals the bypass W
  * outside the learned block, s = W r + T^H ((Phi - W) o T r) needs the
  * transform of r on the learned modes only.  UNO_PATH_SPECTRAL always runs the
- * full transform over the half spectrum. */
-enum { UNO_PATH_AUTO = 0, UNO_PATH_SPECTRAL = 1, UNO_PATH_LEARNED = 2 };
+ * full transform over the half spectrum.  UNO_PATH_FUSED: the learned-mode
+ * passes inside FP64 CG with the last one folded into the operator apply (s
+ * evaluated on each operator tile and its halo, r.s by Parseval); three
+ * kernels per CG pass instead of four, at about 3x the arithmetic of the
+ * last pass (UNO_ERR_SHAPE when the block does not fit the tile's LDS). */
+enum { UNO_PATH_AUTO = 0, UNO_PATH_SPECTRAL = 1, UNO_PATH_LEARNED = 2, UNO_PATH_FUSED = 3 };
 uno_status uno_precond_set_path(uno_precond *p, int32_t path);
 
 /* Copies the half-spectrum table (n[0] x .. x n[d-2] x (n[d-1]/2+1) values,

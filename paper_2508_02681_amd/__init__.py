@@ -217,7 +217,7 @@ class UnoPrecond:
                "uno_precond_apply")
         return s
 
-    PATH_AUTO, PATH_SPECTRAL, PATH_LEARNED = 0, 1, 2
+    PATH_AUTO, PATH_SPECTRAL, PATH_LEARNED, PATH_FUSED = 0, 1, 2, 3
 
     def set_path(self, path: int):
         """0 auto, 1 full spectral passes, 2 learned-mode passes (FP64)."""

@@ -436,8 +436,9 @@ uno_status uno_precond_apply(const uno_precond* p, const void* r, void* s, uno_d
 
 uno_status uno_precond_set_path(uno_precond* p, int32_t path)
 {
-    if (!p || path < UNO_PATH_AUTO || path > UNO_PATH_LEARNED) return UNO_ERR_ARG;
+    if (!p || path < UNO_PATH_AUTO || path > UNO_PATH_FUSED) return UNO_ERR_ARG;
     if (path == UNO_PATH_LEARNED && !p->lr) return UNO_ERR_SHAPE;
+    if (path == UNO_PATH_FUSED && !(p->lr && lowrank_fused(p->lr))) return UNO_ERR_SHAPE;
     p->path = path;
     return UNO_OK;
 }

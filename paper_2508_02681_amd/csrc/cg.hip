@@ -511,7 +511,7 @@ static uno_status enqueue_pass(const Grid& g, Workspace* w, int kind, const uno_
         CgIter it = iter_of(w, P, k, k0, rtol, hist_len, lowrank_update_blocks(pc->lr));
         const LrBatch bt = lr_batch(w, nrhs);
         if constexpr (sizeof(T) == sizeof(double)) {
-            if (lowrank_fused(pc->lr)) {
+            if (uno_use_fused(pc)) {
                 // fused FP64 flow: B (head, Parseval partials) -> [C + matvec] -> [update + A of pass k+1];
                 // ||r||^2 partials in rs[0], the learned-mode part of r.s in rs[1]
                 int np_dp = 0;
@@ -600,7 +600,7 @@ static uno_status pcg_loop(const Grid& g, Workspace* w, const double* kappa64, c
                                (const double*)w->r, sv, P.rmax, P.rs[0], P.ss[0], w->state, w->npart);
         UNO_HIP(hipGetLastError());
         if (lowrank) {  // transform of r for the first pass (and ||r||^2 in the fused flow)
-            const bool fused = sizeof(T) == sizeof(double) && lowrank_fused(pc->lr);
+            const bool fused = sizeof(T) == sizeof(double) && uno_use_fused(pc);
             const CgIter strides = iter_of(w, P, 0, 0, 0.0, 0, nb);
             return lowrank_forward(pc->lr, w->r, fused ? P.rs[0] : nullptr, lr_batch(w, nrhs), strides, st);
         }

@@ -190,3 +190,9 @@ inline bool uno_use_lowrank(const uno_precond* p)
 {
     return p->lr != nullptr && p->path != UNO_PATH_SPECTRAL;
 }
+
+// learned-mode passes with the last one folded into the operator (FP64 CG)
+inline bool uno_use_fused(const uno_precond* p)
+{
+    return uno_use_lowrank(p) && p->path == UNO_PATH_FUSED && unocg::lowrank_fused(p->lr);
+}

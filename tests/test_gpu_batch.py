@@ -37,11 +37,12 @@ def _precond(uno, shape, M, path=0):
     return p
 
 
-# (shape, kind, M, path): the fused FP64 learned-mode flow, the four-kernel
-# learned-mode flow (block too large for the fused tile), Jacobi, none, and
-# the spectral path (run load by load)
+# (shape, kind, M, path): the learned-mode flow, its fused variant, a block
+# too large for the fused tile, Jacobi, none, and the spectral path (run
+# load by load)
 CASES = [
     ((24, 20, 16), "uno", 3, 0),
+    ((24, 20, 16), "uno", 3, 3),
     ((64, 64, 64), "uno", 17, 0),
     ((24, 20, 16), "jacobi", 0, 0),
     ((20, 12, 16), "none", 0, 0),

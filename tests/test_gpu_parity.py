@@ -136,7 +136,7 @@ def test_pcg_2d_config1_matches_oracle(orc, uno, kind):
         assert rel(kb, kbo) < 1e-8
 
 
-@pytest.mark.parametrize("path", [1, 2])
+@pytest.mark.parametrize("path", [1, 2, 3])
 @pytest.mark.parametrize("shape,M", [((32, 32), 4), ((16, 16, 16), 3), ((12, 10, 15), 2), ((24, 20, 16), 2)])
 def test_pcg_uno_matches_oracle(orc, uno, shape, M, path):
     ph, _ = si.rsa_inclusions(shape, 2, 4, 0.3, 21)
