@@ -49,6 +49,7 @@ def _load():
     lib.orc_flux_average.argtypes = [i32, _ip, _dp, _dp, _dp, _dp, _dp]
     lib.orc_energy_average.argtypes = [i32, _ip, _dp, _dp, _dp, _dp, _dp, _dp]
     lib.orc_energy_average.restype = f64
+    lib.orc_energy_density.argtypes = [i32, _ip, _dp, _dp, _dp, _dp, _dp, _dp]
     lib.orc_fft_nd.argtypes = [i32, _ip, _dp, i32]
     lib.orc_uno_num_weights.argtypes = [i32, i32]
     lib.orc_uno_num_weights.restype = ctypes.c_int64
@@ -236,6 +237,27 @@ def energy_tensor(kappa, solutions, loads, L0=1.0, h=None) -> np.ndarray:
     G = np.array(loads, dtype=np.float64).T
     Gi = np.linalg.inv(G)
     return Gi.T @ E @ Gi
+
+
+def kbar_grad(kappa, solutions, loads, L0=1.0, h=None) -> np.ndarray:
+    """d kappa_bar_ij / d kappa_e for every voxel e (array d x d x grid): the
+    element energy densities D_ab(e) of the load pairs (exact total
+    derivatives of g_a . kappa_bar g_b at the discrete solutions), mapped
+    through kappa_bar = G^-T E G^-1 for the load matrix G = [g_1 ... g_d]."""
+    lib = _load()
+    kappa = _f64(kappa)
+    dim, n, hh = _shape_args(kappa.shape, L0, h)
+    d = len(loads)
+    D = np.zeros((d, d) + kappa.shape)
+    for a in range(d):
+        for b in range(a, d):
+            out = np.zeros(kappa.shape)
+            lib.orc_energy_density(dim, n.ctypes.data_as(_ip), _ptr(hh), _ptr(_f64(loads[a])), _ptr(_f64(solutions[a])),
+                                   _ptr(_f64(loads[b])), _ptr(_f64(solutions[b])), _ptr(out))
+            D[a, b] = out
+            D[b, a] = out
+    Gi = np.linalg.inv(np.array(loads, dtype=np.float64).T)
+    return np.einsum("ai,ab...,bj->ij...", Gi, D, Gi)
 
 
 def train_features(f_list, u_list):

@@ -278,6 +278,45 @@ double orc_energy_average(int dim, const int32_t *n, const double *h, const doub
     return acc / vol;
 }
 
+/* Per-element energy density of two load cases,
+ *   out[e] = (1/|Omega|) int_e (g1 + grad t1).(g2 + grad t2) dx,
+ * i.e. the derivative of the energy form (1/|Omega|) sum_e kappa_e
+ * int_e (...).(...) with respect to kappa_e at fixed fields.  At the discrete
+ * solutions of the periodic cell problem this is also the total derivative
+ * d(g1 . kappa_bar g2)/d kappa_e: the problem is self-adjoint, the solution
+ * of load 1 is the adjoint state of load 2, and the terms with the field
+ * sensitivities vanish by the Galerkin equations (Sec. 3.1 weak form).
+ * Gauss quadrature as in orc_energy_average. */
+void orc_energy_density(int dim, const int32_t *n, const double *h, const double *g1, const double *t1,
+                        const double *g2, const double *t2, double *out)
+{
+    orc_grid g = mk_grid(dim, n, h);
+    int na = 1 << dim;
+    int64_t nn = grid_size(&g);
+    double vol = 1.0;
+    for (int b = 0; b < dim; ++b) vol *= g.n[b] * g.h[b];
+    for (int64_t le = 0; le < nn; ++le) {
+        int e[ORC_MAXD];
+        unlin(&g, le, e);
+        double acc = 0.0;
+        for (int q = 0; q < n_gauss(&g); ++q) {
+            double xi[ORC_MAXD], w = gauss_point(&g, q, xi);
+            double a1[ORC_MAXD], a2[ORC_MAXD];
+            for (int c = 0; c < dim; ++c) { a1[c] = g1[c]; a2[c] = g2[c]; }
+            for (int a = 0; a < na; ++a) {
+                double ga[ORC_MAXD];
+                shape_grad(&g, a, xi, ga);
+                int64_t gn = elem_node(&g, e, a);
+                for (int c = 0; c < dim; ++c) { a1[c] += ga[c] * t1[gn]; a2[c] += ga[c] * t2[gn]; }
+            }
+            double dot = 0.0;
+            for (int c = 0; c < dim; ++c) dot += a1[c] * a2[c];
+            acc += w * dot;
+        }
+        out[le] = acc / vol;
+    }
+}
+
 /* ---------------------------------------------------------------------
  * Unitary discrete Fourier transform (the unitary transform T of Sec. 4.2.1
  * for periodic boundary conditions).  Recursive mixed-radix decimation in

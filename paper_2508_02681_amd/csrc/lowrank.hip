@@ -203,16 +203,54 @@ __global__ void __launch_bounds__(256) k_lr_fwd(LowRankDev L, int ny_chunk, doub
     }
 }
 
-// Pass B: one wavefront per (k_y, k_z) column: add the row-chunk partials,
-// transform along x, multiply by the table, transform back.  Inside CG it is
-// the first kernel of a pass and runs the convergence test.
+// Pass B: one workgroup of 256 threads per group of cb consecutive (k_y,
+// k_z) columns: add the row-chunk partials (reads of cb adjacent columns are
+// contiguous), transform along x, multiply by the table, transform back.
+// Inside CG it is the first kernel of a pass and runs the convergence test.
+// Both x-transforms are evaluated with Horner's rule in the unit-modulus
+// phase factor, split into even and odd powers (two independent chains).
 //
-// With part_corr, it also writes per column sum_kx C(k) |X(k)|^2: by
-// Parseval, r.s = W ||r||^2 + (sum of these), since the table holds
-// w(k_z) (Phi(k) - W) / n and X is the unnormalized DFT of r on the block.
-__global__ void __launch_bounds__(64) k_lr_mid(LowRankDev L, int nch, const double* __restrict__ C,
-                                               const double2* __restrict__ Gp, double2* __restrict__ H, CgIter it,
-                                               double* __restrict__ part_corr)
+// With part_corr, it also writes per workgroup sum C(k) |X(k)|^2 over its
+// columns: by Parseval, r.s = W ||r||^2 + (sum of these), since the table
+// holds w(k_z) (Phi(k) - W) / n and X is the unnormalized DFT of r on the
+// block.
+constexpr int kMidQB = 2;  // gathered (column, x) entries per thread held in registers
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b)
+{
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// sum_{j < m} a[j * stride] w^j, by Horner on even and odd j in w^2
+__device__ __forceinline__ double2 horner_eo(const double2* a, int stride, int m, double2 w)
+{
+    const double2 w2 = cmul(w, w);
+    double er = 0.0, ei = 0.0, orr = 0.0, oi = 0.0;
+    int j = (m - 1) & ~1;  // highest even index
+    if (j + 1 < m) {       // m even: the odd chain starts one step higher
+        const double2 h = a[(j + 1) * stride];
+        orr = h.x;
+        oi = h.y;
+    }
+    for (; j >= 0; j -= 2) {
+        const double2 he = a[j * stride];
+        const double ner = er * w2.x - ei * w2.y + he.x;
+        ei = er * w2.y + ei * w2.x + he.y;
+        er = ner;
+        if (j >= 1) {
+            const double2 ho = a[(j - 1) * stride];
+            const double nor = orr * w2.x - oi * w2.y + ho.x;
+            oi = orr * w2.y + oi * w2.x + ho.y;
+            orr = nor;
+        }
+    }
+    // E(w^2) + w O(w^2), E holding the even j, O the odd j
+    return make_double2(er + (orr * w.x - oi * w.y), ei + (orr * w.y + oi * w.x));
+}
+
+__global__ void __launch_bounds__(256) k_lr_mid(LowRankDev L, int nch, int cb, const double* __restrict__ C,
+                                                const double2* __restrict__ Gp, double2* __restrict__ H, CgIter it,
+                                                double* __restrict__ part_corr)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double slots[4];
@@ -222,67 +260,73 @@ __global__ void __launch_bounds__(64) k_lr_mid(LowRankDev L, int nch, const doub
         if (part_corr) part_corr += (int64_t)blockIdx.y * it.ps;
         it = rhs_iter(it);
     }
-    const int col = blockIdx.x;  // ky index * kzn + kz
     const int plane = L.kyn * L.kzn;
-    double2* twx = (double2*)smem;  // n0
-    double2* gx = twx + L.n0;       // n0
-    double2* X = gx + L.n0;         // kxn
-    // loads first: state and ||r||_inf partials (head of the CG pass), the
-    // row-chunk partials of this column, twiddles and the table entries
+    const int col0 = blockIdx.x * cb;
+    double2* gx = (double2*)smem;  // [x][cl]
+    double2* X = gx + L.n0 * cb;   // [kx][cl]
+    // loads first: state and ||r||_inf partials (head of the CG pass) and
+    // this thread's first gathered entries
     StateLoad sl;
     double share = 0.0;
     if (it.st) {
         sl = load_state(it.st);
         share = load_share<OpMax>(it.part_rmax, it.np_rmax);
     }
-    for (int j = threadIdx.x; j < L.n0; j += blockDim.x) {
-        twx[j] = L.twx[j];
+    const int ng = L.n0 * cb;
+    auto gather = [&](int q) {
+        const int cl = q % cb, x = q / cb;
+        const int col = col0 + cl;
         double re = 0.0, im = 0.0;
-        for (int c = 0; c < nch; ++c) {
-            const double2 a = Gp[((int64_t)j * nch + c) * plane + col];
-            re += a.x;
-            im += a.y;
+        if (col < plane) {
+            const double2* src = Gp + (int64_t)x * nch * plane + col;
+            for (int c = 0; c < nch; ++c) {
+                const double2 v = src[(int64_t)c * plane];
+                re += v.x;
+                im += v.y;
+            }
         }
-        gx[j] = make_double2(re, im);
+        return make_double2(re, im);
+    };
+    double2 gv[kMidQB];
+#pragma unroll
+    for (int u = 0; u < kMidQB; ++u) {
+        const int q = threadIdx.x + 256 * u;
+        gv[u] = (q < ng) ? gather(q) : make_double2(0.0, 0.0);
     }
     if (it.st && head_decide(it, sl, share, slots)) return;
+#pragma unroll
+    for (int u = 0; u < kMidQB; ++u) {
+        const int q = threadIdx.x + 256 * u;
+        if (q < ng) gx[q] = gv[u];
+    }
+    for (int q = threadIdx.x + 256 * kMidQB; q < ng; q += 256) gx[q] = gather(q);
     __syncthreads();
+    // X[kx][cl] = C(k) sum_x g[x] exp(-2 pi i (kx - mx) x / n0)
     double corr = 0.0;
-    for (int kxi = threadIdx.x; kxi < L.kxn; kxi += blockDim.x) {
-        const int step = mod_n(kxi - L.mx, L.n0);
-        double re = 0.0, im = 0.0;
-        int t = 0;
-#pragma unroll 8
-        for (int x = 0; x < L.n0; ++x) {
-            const double2 a = gx[x];
-            const double2 w = twx[t];
-            re += a.x * w.x - a.y * w.y;
-            im += a.x * w.y + a.y * w.x;
-            t += step;
-            if (t >= L.n0) t -= L.n0;
-        }
-        const double c = C[(int64_t)kxi * plane + col];
-        X[kxi] = make_double2(re * c, im * c);
-        corr += c * (re * re + im * im);
+    for (int o = threadIdx.x; o < L.kxn * cb; o += 256) {
+        const int cl = o % cb, kxi = o / cb;
+        const int col = col0 + cl;
+        const double2 w = L.twx[mod_n(kxi - L.mx, L.n0)];
+        const double2 v = horner_eo(gx + cl, cb, L.n0, w);
+        const double c = (col < plane) ? C[(int64_t)kxi * plane + col] : 0.0;
+        X[o] = make_double2(v.x * c, v.y * c);
+        corr += c * (v.x * v.x + v.y * v.y);
     }
     if (part_corr) {
         const double b = block_reduce<OpSum>(corr, slots);
-        if (threadIdx.x == 0) part_corr[col] = b;
+        if (threadIdx.x == 0) part_corr[blockIdx.x] = b;
     }
     __syncthreads();
-    for (int x = threadIdx.x; x < L.n0; x += blockDim.x) {
-        const int step = mod_n(x, L.n0);
-        int t = mod_n((int64_t)(-L.mx) * x, L.n0);
-        double re = 0.0, im = 0.0;
-        for (int kxi = 0; kxi < L.kxn; ++kxi) {
-            const double2 w = twx[t];  // conj(w) = exp(+2 pi i kx x / n0)
-            const double2 a = X[kxi];
-            re += a.x * w.x + a.y * w.y;
-            im += a.y * w.x - a.x * w.y;
-            t += step;
-            if (t >= L.n0) t -= L.n0;
-        }
-        H[(int64_t)x * plane + col] = make_double2(re, im);
+    // H[x][col] = sum_kx X[kx] exp(+2 pi i (kx - mx) x / n0)
+    for (int o = threadIdx.x; o < ng; o += 256) {
+        const int cl = o % cb, x = o / cb;
+        const int col = col0 + cl;
+        if (col >= plane) continue;
+        const double2 t = L.twx[x];                       // exp(-2 pi i x / n0)
+        const double2 w = make_double2(t.x, -t.y);        // exp(+2 pi i x / n0)
+        const double2 v = horner_eo(X + cl, cb, L.kxn, w);
+        const double2 sh = L.twx[mod_n((int64_t)L.mx * x, L.n0)];  // exp(-2 pi i mx x / n0)
+        H[(int64_t)x * plane + col] = cmul(v, sh);
     }
 }
 
@@ -692,6 +736,7 @@ struct LowRankPlan {
     int nch_a;
     int blocks_a, blocks_c;
     size_t lds_a, lds_b, lds_c;
+    int cb_mid, blocks_mid;  // columns per workgroup of pass B, its workgroups
     bool fused;       // the fused operator tile fits (FP64 CG flow)
     TileChoice tile;  // its tile shape
     size_t lds_t;     // its dynamic LDS
@@ -739,7 +784,10 @@ uno_status lowrank_create(const Grid& g, const FftPlan& fp, int M, double W, con
     p->blocks_c = L.n0 * ((L.n1 + p->yc - 1) / p->yc);
     const int plane = L.kyn * L.kzn;
     p->lds_a = sizeof(double2) * ((size_t)L.n2 + L.n1 + (size_t)p->ya * L.kzn) + sizeof(double) * (size_t)p->ya * L.n2;
-    p->lds_b = sizeof(double2) * (2 * (size_t)L.n0 + L.kxn);
+    p->cb_mid = 8;
+    while (p->cb_mid > 1 && sizeof(double2) * (size_t)p->cb_mid * (L.n0 + L.kxn) > 48 * 1024) p->cb_mid /= 2;
+    p->blocks_mid = (L.kyn * L.kzn + p->cb_mid - 1) / p->cb_mid;
+    p->lds_b = sizeof(double2) * (size_t)p->cb_mid * (L.n0 + L.kxn);
     p->lds_c = sizeof(double2) * ((size_t)L.n2 + L.n1 + (size_t)plane + (size_t)p->yc * L.kzn);
     if (p->lds_a > 60 * 1024 || p->lds_b > 60 * 1024 || p->lds_c > 60 * 1024) { delete p; return UNO_ERR_SHAPE; }
     // fused operator tile: the apply's tile shape, 2-deep in x if 4 does not fit
@@ -869,10 +917,10 @@ uno_status lowrank_fused_pass(const LowRankPlan* p, const Grid& g, const double*
 {
     if (!p->fused) return UNO_ERR_SHAPE;
     const LowRankDev& L = p->dev;
-    uno_launch(UNO_KT_FFT_MID, k_lr_mid, dim3(L.kyn * L.kzn, bt.nrhs), dim3(64), p->lds_b, st, L, p->nch_a,
-               (const double*)p->table, (const double2*)bt.Gp, bt.H, it, part_corr);
+    uno_launch(UNO_KT_FFT_MID, k_lr_mid, dim3(p->blocks_mid, bt.nrhs), dim3(256), p->lds_b, st, L, p->nch_a,
+               p->cb_mid, (const double*)p->table, (const double2*)bt.Gp, bt.H, it, part_corr);
     UNO_HIP(hipGetLastError());
-    const LrTileArgs a{part_rr, p->blocks_a, part_corr, L.kyn * L.kzn};
+    const LrTileArgs a{part_rr, p->blocks_a, part_corr, p->blocks_mid};
     if (p->tile.tx == 1)
         launch_lr_tile_tx<1>(p, g.dev, kappa, r, dold, dnew, pv, part_dp, it, a, gam, bt, st);
     else if (p->tile.tx == 2)
@@ -891,8 +939,8 @@ uno_status lowrank_finish(const LowRankPlan* p, const double* r, T* s, const CgI
 {
     const LowRankDev& L = p->dev;
     const CgIter it = itp ? *itp : no_iter();
-    uno_launch(UNO_KT_FFT_MID, k_lr_mid, dim3(L.kyn * L.kzn, bt.nrhs), dim3(64), p->lds_b, st, L, p->nch_a,
-               (const double*)p->table, (const double2*)bt.Gp, bt.H, it, (double*)nullptr);
+    uno_launch(UNO_KT_FFT_MID, k_lr_mid, dim3(p->blocks_mid, bt.nrhs), dim3(256), p->lds_b, st, L, p->nch_a,
+               p->cb_mid, (const double*)p->table, (const double2*)bt.Gp, bt.H, it, (double*)nullptr);
     UNO_HIP(hipGetLastError());
     if (itp)
         uno_launch(UNO_KT_FFT_INV, k_lr_inv<true, T>, dim3(p->blocks_c, bt.nrhs), dim3(256), p->lds_c, st, L, p->yc, r,
