@@ -200,6 +200,19 @@ uno_status pcg_solve_batch(const uno_grid *grid, const uno_material *mat, int32_
 uno_status effective_tensor(const uno_grid *grid, const uno_material *mat, int32_t nload,
                             const double *loads, const double *u, double *out, void *stream);
 
+/* Gradient of the effective conductivity with respect to every voxel
+ * conductivity.  The cell problem is self-adjoint (Sec. 3.1 weak form), so
+ * at the discrete solutions the derivative of g_a . kappa_bar g_b with
+ * respect to kappa_e is the element energy density (1/|Omega|) int_e
+ * (g_a + grad u_a).(g_b + grad u_b): no adjoint solve.  loads (host,
+ * nload x d, nload = d, invertible) and u (device, nload x n doubles) as
+ * for effective_tensor.  weights == NULL: out (device, d x d x n doubles)
+ * receives d kappa_bar_ij / d kappa_e at out[(i d + j) n + e]; otherwise
+ * (host, d x d) out (device, n doubles) receives sum_ij weights_ij
+ * d kappa_bar_ij / d kappa_e (a vector-Jacobian product).  Asynchronous. */
+uno_status effective_tensor_grad(const uno_grid *grid, int32_t nload, const double *loads, const double *u,
+                                 const double *weights, double *out, void *stream);
+
 /* ---- Second-order training of the weights (Sec. 4.4, c = 1) ---------- */
 /* Accumulates the features of eq. (features-c-1) over ns samples:
  *   alpha(k) += (1/ns_total) |f^(k)|^2, beta(k) += (2/ns_total) Re(conj(f^) u^)

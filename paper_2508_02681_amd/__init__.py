@@ -82,6 +82,7 @@ def lib():
         "pcg_solve": ([G, Mt, P(f64), vp, vp, P(uno_solve_opts), P(uno_solve_info), P(f64), vp], i),
         "pcg_solve_batch": ([G, Mt, i32, P(f64), vp, vp, P(uno_solve_opts), P(uno_solve_info), vp], i),
         "effective_tensor": ([G, Mt, i32, P(f64), vp, P(f64), vp], i),
+        "effective_tensor_grad": ([G, i32, P(f64), vp, P(f64), vp, vp], i),
         "uno_train_accumulate": ([G, i32, vp, vp, f64, vp, vp, vp], i),
         "uno_train_fit": ([G, i32, vp, vp, P(f64), i64, vp], i),
         "uno_timing_enable": ([i32], i),
@@ -334,6 +335,56 @@ def effective_tensor(kappa: torch.Tensor, loads, solutions: torch.Tensor, L0=1.0
                                   _dev(solutions, "solutions", torch.float64),
                                   out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _stream()), "effective_tensor")
     return out
+
+
+def effective_tensor_grad(shape, loads, solutions: torch.Tensor, weights=None, out: torch.Tensor | None = None,
+                          L0=1.0) -> torch.Tensor:
+    """d kappa_bar_ij / d kappa_e for every voxel (d x d x grid, device), or
+    with weights (d x d) the vector-Jacobian product sum_ij w_ij d kappa_bar_ij
+    / d kappa_e (grid).  solutions: the load cases' solutions (d x grid)."""
+    shape = tuple(shape)
+    g = make_grid(shape, L0)
+    d = len(shape)
+    ld = np.ascontiguousarray(loads, dtype=np.float64)
+    if ld.shape != (d, d):
+        raise ValueError("need d loads of d components")
+    w = None if weights is None else np.ascontiguousarray(weights, dtype=np.float64).reshape(d, d)
+    if out is None:
+        oshape = shape if w is not None else (d, d) + shape
+        out = torch.empty(oshape, dtype=torch.float64, device=solutions.device)
+    _check(lib().effective_tensor_grad(ctypes.byref(g), d, ld.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                       _dev(solutions, "solutions", torch.float64),
+                                       w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if w is not None else None,
+                                       _dev(out, "out", torch.float64), _stream()), "effective_tensor_grad")
+    return out
+
+
+class EffectiveConductivity(torch.autograd.Function):
+    """kappa_bar(kappa) with a hand-written backward: forward solves the d
+    unit load cases together (UNO-CG or Jacobi-CG), backward contracts the
+    incoming gradient with the element energy densities of the saved
+    solutions (the cell problem is self-adjoint: no adjoint solve, no stored
+    CG iterates)."""
+
+    @staticmethod
+    def forward(ctx, kappa, kind="jacobi", precond=None, rtol=1e-10):
+        d = kappa.dim()
+        loads = np.eye(d)
+        u, infos = pcg_solve_batch(kappa.detach(), macro_loads=loads, kind=kind, precond=precond, rtol=rtol)
+        if not all(i["converged"] for i in infos):
+            raise UnoError("effective conductivity: a cell problem did not converge")
+        kb = effective_tensor(kappa.detach(), loads, u)
+        ctx.save_for_backward(u)
+        ctx.shape = tuple(kappa.shape)
+        return torch.tensor(kb, dtype=torch.float64, device=kappa.device)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (u,) = ctx.saved_tensors
+        d = len(ctx.shape)
+        w = grad_out.detach().double().cpu().numpy()
+        gk = effective_tensor_grad(ctx.shape, np.eye(d), u, weights=w)
+        return gk, None, None, None
 
 
 def half_shape(shape):
