@@ -229,6 +229,17 @@ uno_status uno_train_accumulate(const uno_grid *grid, int32_t ns, const double *
 uno_status uno_train_fit(const uno_grid *grid, int32_t M, const double *alpha, const double *beta,
                          double *theta, int64_t ntheta, void *stream);
 
+/* Loss and gradient for a first-order training step of the weights
+ * (Algorithm 3, c = 1): with the features alpha, beta (device half
+ * spectrum, from uno_train_accumulate over a batch of pairs), loss (host)
+ * = sum over the full spectrum of alpha Phi^2 - beta Phi, which is the
+ * batch's mean ||P_theta f_j - u_j||^2 less its constant (1/Ns) sum
+ * ||u_j||^2 (T unitary), and grad (host, ntheta) = dloss/dtheta with Phi
+ * parametrized as in uno_precond_create (the hand-written backward through
+ * T: the transform is diagonalized away by Parseval).  Synchronous. */
+uno_status uno_train_loss_grad(const uno_grid *grid, int32_t M, const double *alpha, const double *beta,
+                               const double *theta, int64_t ntheta, double *loss, double *grad, void *stream);
+
 /* ---- Timing of one kernel family (for roofline accounting) ----------- */
 enum {
     UNO_KT_NONE = 0,

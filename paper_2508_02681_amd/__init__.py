@@ -85,6 +85,7 @@ def lib():
         "effective_tensor_grad": ([G, i32, P(f64), vp, P(f64), vp, vp], i),
         "uno_train_accumulate": ([G, i32, vp, vp, f64, vp, vp, vp], i),
         "uno_train_fit": ([G, i32, vp, vp, P(f64), i64, vp], i),
+        "uno_train_loss_grad": ([G, i32, vp, vp, P(f64), i64, P(f64), P(f64), vp], i),
         "uno_timing_enable": ([i32], i),
         "uno_timing_read": ([P(f64), P(i64)], i),
         "uno_shutdown": ([], i),
@@ -385,6 +386,36 @@ class EffectiveConductivity(torch.autograd.Function):
         w = grad_out.detach().double().cpu().numpy()
         gk = effective_tensor_grad(ctx.shape, np.eye(d), u, weights=w)
         return gk, None, None, None
+
+
+def uno_train_loss_grad(shape, M, alpha: torch.Tensor, beta: torch.Tensor, theta, L0=1.0):
+    """(loss, dloss/dtheta) of the batch features alpha, beta (half spectrum,
+    device) at theta; loss omits the constant (1/Ns) sum ||u_j||^2."""
+    g = make_grid(tuple(shape), L0)
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    grad = np.zeros_like(th)
+    loss = ctypes.c_double(0.0)
+    _check(lib().uno_train_loss_grad(ctypes.byref(g), int(M), _dev(alpha, "alpha", torch.float64),
+                                     _dev(beta, "beta", torch.float64), th.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                     th.size, ctypes.byref(loss), grad.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                     _stream()), "uno_train_loss_grad")
+    return loss.value, grad
+
+
+class UnoTrainLoss(torch.autograd.Function):
+    """Batch loss of the UNO weights (Algorithm 3) as a function of theta,
+    with the hand-written backward of uno_train_loss_grad."""
+
+    @staticmethod
+    def forward(ctx, theta, shape, M, alpha, beta):
+        loss, grad = uno_train_loss_grad(shape, M, alpha, beta, theta.detach().cpu().numpy())
+        ctx.save_for_backward(torch.tensor(grad, dtype=theta.dtype, device=theta.device))
+        return torch.tensor(loss, dtype=theta.dtype, device=theta.device)
+
+    @staticmethod
+    def backward(ctx, g):
+        (grad,) = ctx.saved_tensors
+        return g * grad, None, None, None, None
 
 
 def half_shape(shape):
