@@ -61,6 +61,64 @@ def kernel_sources_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def kernel_families(uno, shape, M, learned):
+    """Kernel families of one UNO-CG pass and their algorithmic bytes per
+    launch (FP64; a launch carries the 3 load cases, kappa and the table are
+    shared)."""
+    n = int(np.prod(shape))
+    nr = len(LOADS)
+    nspec = shape[0] * shape[1] * (shape[2] // 2 + 1)
+    nblk = shape[0] * (2 * M + 1) * (M + 1)   # learned block after the two partial DFTs (y, z)
+    if learned:
+        # pass B -> pass C -> operator -> [update + pass A]
+        fams = {uno.KT_MATVEC: "k_stencil_tile<double,CG>", uno.KT_UPDATE: "k_lr_fwd<update,double>",
+                uno.KT_FFT_MID: "k_lr_mid", uno.KT_FFT_INV: "k_lr_inv<double>"}
+        bytes_per = {
+            uno.KT_MATVEC: nr * n * 8 * 4 + n * 8,       # read s, d_old; write d_new, p; kappa
+            uno.KT_UPDATE: nr * (n * 8 * 6 + nblk * 16),  # read r, u, d, p; write r, u, block spectrum
+            uno.KT_FFT_MID: nr * nblk * 16 * 2 + nblk * 8,  # block spectrum in/out; table
+            uno.KT_FFT_INV: nr * (n * 8 * 2 + nblk * 16),  # read r, H; write s
+        }
+    else:  # spectral passes, one load per launch
+        fams = {uno.KT_MATVEC: "k_stencil_tile<double,CG>", uno.KT_UPDATE: "k_cg_update<double>",
+                uno.KT_FFT_FWD: "k_fft_r2c_z", uno.KT_FFT_MID: "k_fft_strided(mid)", uno.KT_FFT_INV: "k_fft_c2r_z"}
+        bytes_per = {
+            uno.KT_MATVEC: n * 8 * 5,
+            uno.KT_UPDATE: n * 8 * 6,               # read r, p, u, d; write r, u
+            uno.KT_FFT_FWD: n * 8 + nspec * 16,     # read r; write half spectrum
+            uno.KT_FFT_MID: nspec * 16 * 2 + nspec * 8,  # spectrum in/out + table
+            uno.KT_FFT_INV: nspec * 16 + n * 8 * 2,  # spectrum in; write s; read r (r.s)
+        }
+    return fams, bytes_per
+
+
+def family_times(uno, fams, run):
+    """Summed duration (ms) and launch count of each kernel family over one
+    call of run(), from start/stop events of the launches themselves."""
+    import torch
+    out = {}
+    for fam in fams:
+        uno.timing_enable(fam)
+        run()
+        torch.cuda.synchronize()
+        out[fam] = uno.timing_read()
+        uno.timing_enable(uno.KT_NONE)
+    return out
+
+
+def roofline_record(fams, bytes_per, fam_ms):
+    dom = max(fam_ms, key=lambda f: fam_ms[f][0])
+    tot, nl = fam_ms[dom]
+    avg_s = tot / max(nl, 1) / 1e3
+    achieved = bytes_per[dom] / avg_s / 1e9
+    per_us = {fams[f]: fam_ms[f][0] / max(fam_ms[f][1], 1) * 1e3 for f in fams}
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": fams[dom], "avg_us": round(avg_s * 1e6, 2), "bytes_per_launch": bytes_per[dom],
+            "per_family_us": {k: round(v, 2) for k, v in per_us.items()},
+            "per_family_GBs": {fams[f]: round(bytes_per[f] / max(per_us[fams[f]], 1e-9) / 1e3, 1) for f in fams}}
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -75,6 +133,7 @@ def parse():
     ap.add_argument("--jac-steps", type=int, default=4)
     ap.add_argument("--cpu-iters", type=int, default=20, help="oracle UNO-CG passes timed for cpu_baseline")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-192", action="store_true", help="skip the per-kernel roofline at 192^3")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this size first (reference for HBM counters)")
     return ap.parse_args()
@@ -248,48 +307,61 @@ def main():
     except RuntimeError:
         learned = False
     prec.set_path(prec.PATH_AUTO)
-    nspec = SHAPE[0] * SHAPE[1] * (SHAPE[2] // 2 + 1)
-    nblk = SHAPE[0] * (2 * M + 1) * (M + 1)   # learned block after the two partial DFTs (y, z)
-    if learned:
-        # FP64 CG on the learned modes: pass B -> pass C -> operator -> [update + pass A]
-        fams = {uno.KT_MATVEC: "k_stencil_tile<double,CG>", uno.KT_UPDATE: "k_lr_fwd<update,double>",
-                uno.KT_FFT_MID: "k_lr_mid", uno.KT_FFT_INV: "k_lr_inv<double>"}
-        # algorithmic bytes per launch (FP64), the minimum each kernel must
-        # move; a launch carries the 3 load cases, kappa and the table are shared
-        nr = len(LOADS)
-        bytes_per = {
-            uno.KT_MATVEC: nr * n_dof * 8 * 4 + n_dof * 8,    # read s, d_old; write d_new, p; kappa
-            uno.KT_UPDATE: nr * (n_dof * 8 * 6 + nblk * 16),  # read r, u, d, p; write r, u, block spectrum
-            uno.KT_FFT_MID: nr * nblk * 16 * 2 + nblk * 8,     # block spectrum in/out; table
-            uno.KT_FFT_INV: nr * (n_dof * 8 * 2 + nblk * 16),  # read r, H; write s
-        }
-    else:
-        fams = {uno.KT_MATVEC: "k_stencil_tile<double,CG>", uno.KT_UPDATE: "k_cg_update<double>",
-                uno.KT_FFT_FWD: "k_fft_r2c_z", uno.KT_FFT_MID: "k_fft_strided(mid)", uno.KT_FFT_INV: "k_fft_c2r_z"}
-        bytes_per = {
-            uno.KT_MATVEC: n_dof * 8 * 5,
-            uno.KT_UPDATE: n_dof * 8 * 6,             # read r, p, u, d; write r, u
-            uno.KT_FFT_FWD: n_dof * 8 + nspec * 16,   # read r; write half spectrum
-            uno.KT_FFT_MID: nspec * 16 * 2 + nspec * 8,  # spectrum in/out + table
-            uno.KT_FFT_INV: nspec * 16 + n_dof * 8 * 2,  # spectrum in; write s; read r (r.s)
-        }
-    fam_ms = {}
-    for fam in fams:
-        uno.timing_enable(fam)
-        step(0, "uno", prec)
-        torch.cuda.synchronize()
-        tot, nl = uno.timing_read()
-        uno.timing_enable(uno.KT_NONE)
-        fam_ms[fam] = (tot, nl)
-    dom = max(fam_ms, key=lambda f: fam_ms[f][0])
-    tot, nl = fam_ms[dom]
-    avg_s = tot / max(nl, 1) / 1e3
-    achieved = bytes_per[dom] / avg_s / 1e9
-    traffic = TRAFFIC_BYTES.get(fams[dom]) if (learned and kernel_sources_hash() == TRAFFIC_SRC) else None
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": fams[dom], "avg_us": round(avg_s * 1e6, 2), "bytes_per_launch": bytes_per[dom],
-                "per_family_us": {fams[f]: round(fam_ms[f][0] / max(fam_ms[f][1], 1) * 1e3, 2) for f in fams}}
+    fams, bytes_per = kernel_families(uno, SHAPE, M, learned)
+    fam_ms = family_times(uno, fams, lambda: step(0, "uno", prec))
+    roofline = roofline_record(fams, bytes_per, fam_ms)
+    if learned and kernel_sources_hash() == TRAFFIC_SRC:
+        roofline["traffic"] = TRAFFIC_BYTES.get(roofline["kernel"])
+    log("roofline (64^3): %s %.1f GB/s per launch (%.3f of peak)" %
+        (roofline["kernel"], roofline["achieved"], roofline["frac"]))
+
+    # ---------------- differentiation: d kappa_bar / d kappa_e, training step ----------------
+    k0 = kap_test[0]
+    ug, _ = uno.pcg_solve_batch(k0, macro_loads=LOADS, kind="uno", precond=prec, rtol=RTOL)
+    jac = torch.empty((3, 3) + SHAPE, dtype=torch.float64, device=dev)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    uno.effective_tensor_grad(SHAPE, LOADS, ug, out=jac)
+    ev0.record()
+    for _ in range(10):
+        uno.effective_tensor_grad(SHAPE, LOADS, ug, out=jac)
+    ev1.record()
+    torch.cuda.synchronize()
+    g_ms = ev0.elapsed_time(ev1) / 10
+    g_bytes = n_dof * 8 * (3 + 9)  # read the three solutions, write the 3 x 3 derivatives per voxel
+    euler = torch.einsum("ijxyz,xyz->ij", jac, k0).cpu().numpy()
+    kb0 = uno.effective_tensor(k0, LOADS, ug)
+    grad_rec = {"workload": "d kappa_bar / d kappa_e, all %d voxels, 64^3 test microstructure 1000" % n_dof,
+                "ms": round(g_ms, 4), "achieved_GBs": round(g_bytes / (g_ms * 1e-3) / 1e9, 1),
+                "euler_identity_rel_err": float(np.abs(euler - kb0).max() / np.abs(kb0).max())}
+    A = torch.zeros(hs, dtype=torch.float64, device=dev)
+    B = torch.zeros_like(A)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    uno.uno_train_accumulate(torch.stack(F[:16]), torch.stack(U[:16]), A, B, 16)
+    loss, gtheta = uno.uno_train_loss_grad(SHAPE, M, A, B, theta)
+    torch.cuda.synchronize()
+    grad_rec["training_step_batch16_ms"] = round((time.perf_counter() - t1) * 1e3, 3)
+    log("d kappa_bar/d kappa: %.3f ms (%.0f GB/s), Euler identity %.1e; training step (16 pairs) %.2f ms" %
+        (g_ms, grad_rec["achieved_GBs"], grad_rec["euler_identity_rel_err"], grad_rec["training_step_batch16_ms"]))
+
+    # ---------------- per-kernel roofline at the paper's grid size (192^3) ----------------
+    big = None
+    if not args.no_192:
+        cfgb = dict(cfg, shape=(192, 192, 192), r_min=12.0, r_max=24.0)
+        kb192 = torch.tensor(si.microstructure(cfgb, 7000)[0], device=dev)
+        pb = uno.UnoPrecond.create(cfgb["shape"], 12, si.random_theta(uno.num_weights(3, 12), 7001,
+                                                                        scale=0.02, spread=0.1))
+        fb, bb = kernel_families(uno, cfgb["shape"], 12, True)
+        ub = torch.zeros((3,) + cfgb["shape"], dtype=torch.float64, device=dev)
+
+        def run_big():
+            ub.zero_()
+            uno.pcg_solve_batch(kb192, macro_loads=LOADS, u=ub, kind="uno", precond=pb, rtol=1e-30, max_iter=40)
+
+        run_big()
+        big = roofline_record(fb, bb, family_times(uno, fb, run_big))
+        big["workload"] = "192^3, spheres r 12-24 vf 0.25, kappa 1/100, M = 12, three loads per launch, 40 passes"
+        log("roofline (192^3): " + ", ".join("%s %.0f GB/s" % (k, v) for k, v in big["per_family_GBs"].items()))
 
     # ---------------- CPU baseline: the oracle, bounded sample ----------------
     cpu = None
@@ -333,6 +405,8 @@ def main():
         "time_to_tol_speedup_uno_vs_jac": jac_t_solve / uno_t_solve,
         "kappa_bar_first": np.round(kbs[0], 6).tolist(),
         "roofline": roofline,
+        "roofline_192": big,
+        "differentiation": grad_rec,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -46,14 +46,15 @@ __device__ __forceinline__ int mod_n(int64_t v, int n)
     return r < 0 ? r + n : r;
 }
 
-// Pass A on the rows y0 .. y0+ny-1 of slab x: Z[y][kz] = sum_z r e^{-i kz z},
-// then the partial y-sum of these rows, Gp[x][chunk][ky][kz] =
-// sum_{y in rows} Z[y][kz] e^{-i ky y}; pass B adds the chunks in order.
+// Pass A on the rows [y_b, y_e) of slab x (one workgroup), taken ya rows at
+// a time: Z[y][kz] = sum_z r e^{-i kz z}, then the partial y-sum over the
+// workgroup's rows, Gp[x][chunk][ky][kz] = sum_y Z[y][kz] e^{-i ky y}
+// (accumulated in LDS over the row groups); pass B adds the chunks in order.
 // UPDATE (inside CG): the rows are first updated, r <- r - alpha p,
 // u <- u + alpha d, and partials of ||r||_inf are written; the transformed
 // rows are then those of the new residual (for the next pass).
 template <bool UPDATE, typename TD>
-__global__ void __launch_bounds__(256) k_lr_fwd(LowRankDev L, int ny_chunk, double* __restrict__ r,
+__global__ void __launch_bounds__(256) k_lr_fwd(LowRankDev L, int ya, int rb, double* __restrict__ r,
                                                 double* __restrict__ u, const TD* __restrict__ d,
                                                 const TD* __restrict__ p, double2* __restrict__ Gp, CgIter it,
                                                 const double* __restrict__ part_dp, int np_dp,
@@ -77,19 +78,18 @@ __global__ void __launch_bounds__(256) k_lr_fwd(LowRankDev L, int ny_chunk, doub
         if (part_rr) part_rr += po;
         it = rhs_iter(it);
     }
-    const int nch = (L.n1 + ny_chunk - 1) / ny_chunk;
+    const int nch = (L.n1 + rb - 1) / rb;
     const int x = blockIdx.x / nch, ch = blockIdx.x % nch;
-    const int y0 = ch * ny_chunk;
-    const int ny = min(ny_chunk, L.n1 - y0);
+    const int yb = ch * rb, ye = min(L.n1, yb + rb);
+    const int plane = L.kyn * L.kzn;
     double2* twz = (double2*)smem;                 // n2
     double2* twy = twz + L.n2;                     // n1
-    double2* Z = twy + L.n1;                       // ny_chunk x kzn
-    double* R = (double*)(Z + ny_chunk * L.kzn);   // ny_chunk x n2
-    const int64_t base = ((int64_t)x * L.n1 + y0) * L.n2;
-    const int cnt = ny * L.n2;
+    double2* Z = twy + L.n1;                       // ya x kzn
+    double2* Gacc = Z + ya * L.kzn;                // plane
+    double* R = (double*)(Gacc + plane);           // ya x n2
     double m = 0.0, sq = 0.0;
     // all global loads first (state, partials, gamma, the first PF elements
-    // of the four vectors, twiddles); decisions come after
+    // of the four vectors of the first row group, twiddles); decisions after
     constexpr int PF = 4;
     StateLoad sl;
     double dp_share = 0.0, gk = 0.0;
@@ -99,21 +99,26 @@ __global__ void __launch_bounds__(256) k_lr_fwd(LowRankDev L, int ny_chunk, doub
         dp_share = load_share<OpSum>(part_dp, np_dp);
         gk = gam[it.k];
     }
+    {
+        const int ny = min(ya, ye - yb);
+        const int64_t base = ((int64_t)x * L.n1 + yb) * L.n2;
 #pragma unroll
-    for (int j = 0; j < PF; ++j) {
-        const int q = threadIdx.x + 256 * j;
-        rv[j] = pv[j] = uv[j] = dv[j] = 0.0;
-        if (q < cnt) {
-            rv[j] = r[base + q];
-            if (UPDATE) {
-                pv[j] = (double)p[base + q];
-                uv[j] = u[base + q];
-                dv[j] = (double)d[base + q];
+        for (int j = 0; j < PF; ++j) {
+            const int q = threadIdx.x + 256 * j;
+            rv[j] = pv[j] = uv[j] = dv[j] = 0.0;
+            if (q < ny * L.n2) {
+                rv[j] = r[base + q];
+                if (UPDATE) {
+                    pv[j] = (double)p[base + q];
+                    uv[j] = u[base + q];
+                    dv[j] = (double)d[base + q];
+                }
             }
         }
     }
     for (int j = threadIdx.x; j < L.n2; j += 256) twz[j] = L.twz[j];
     for (int j = threadIdx.x; j < L.n1; j += 256) twy[j] = L.twy[j];
+    double alpha = 0.0;
     if (UPDATE) {
         if (ended(sl, it.k)) return;
         const double dp = combine_share<OpSum>(dp_share, slots);
@@ -121,78 +126,80 @@ __global__ void __launch_bounds__(256) k_lr_fwd(LowRankDev L, int ny_chunk, doub
             if (blockIdx.x == 0 && threadIdx.x == 0) { it.st->status = 1; it.st->fail_iter = it.k; }
             return;
         }
-        const double alpha = gk / dp;
+        alpha = gk / dp;
+    }
+    for (int q = threadIdx.x; q < plane; q += 256) Gacc[q] = make_double2(0.0, 0.0);
+    for (int y0 = yb; y0 < ye; y0 += ya) {
+        const int ny = min(ya, ye - y0);
+        const int cnt = ny * L.n2;
+        const int64_t base = ((int64_t)x * L.n1 + y0) * L.n2;
+        if (y0 == yb) {
 #pragma unroll
-        for (int j = 0; j < PF; ++j) {
-            const int q = threadIdx.x + 256 * j;
-            if (q < cnt) {
-                const double rn = rv[j] - alpha * pv[j];
-                r[base + q] = rn;
-                u[base + q] = uv[j] + alpha * dv[j];
-                R[q] = rn;
-                m = OpMax::apply(m, fabs(rn));
-                sq += rn * rn;
+            for (int j = 0; j < PF; ++j) {
+                const int q = threadIdx.x + 256 * j;
+                if (q < cnt) {
+                    double v = rv[j];
+                    if (UPDATE) {
+                        v = rv[j] - alpha * pv[j];
+                        r[base + q] = v;
+                        u[base + q] = uv[j] + alpha * dv[j];
+                        m = OpMax::apply(m, fabs(v));
+                    }
+                    R[q] = v;
+                    sq += v * v;
+                }
             }
         }
-        for (int q = threadIdx.x + 256 * PF; q < cnt; q += 256) {
+        for (int q = threadIdx.x + (y0 == yb ? 256 * PF : 0); q < cnt; q += 256) {
             const int64_t i = base + q;
-            const double rn = r[i] - alpha * (double)p[i];
-            r[i] = rn;
-            u[i] += alpha * (double)d[i];
-            R[q] = rn;
-            m = OpMax::apply(m, fabs(rn));
-            sq += rn * rn;
-        }
-    } else {
-#pragma unroll
-        for (int j = 0; j < PF; ++j) {
-            const int q = threadIdx.x + 256 * j;
-            if (q < cnt) {
-                R[q] = rv[j];
-                sq += rv[j] * rv[j];
+            double v = r[i];
+            if (UPDATE) {
+                v -= alpha * (double)p[i];
+                r[i] = v;
+                u[i] += alpha * (double)d[i];
+                m = OpMax::apply(m, fabs(v));
             }
-        }
-        for (int q = threadIdx.x + 256 * PF; q < cnt; q += 256) {
-            const double v = r[base + q];
             R[q] = v;
             sq += v * v;
         }
-    }
-    __syncthreads();
-    for (int q = threadIdx.x; q < ny * L.kzn; q += 256) {
-        const int yl = q / L.kzn, kz = q % L.kzn;
-        const double* row = R + yl * L.n2;
-        double re = 0.0, im = 0.0;
-        int t = 0;
+        __syncthreads();
+        for (int q = threadIdx.x; q < ny * L.kzn; q += 256) {
+            const int yl = q / L.kzn, kz = q % L.kzn;
+            const double* row = R + yl * L.n2;
+            double re = 0.0, im = 0.0;
+            int t = 0;
 #pragma unroll 8
-        for (int z = 0; z < L.n2; ++z) {
-            const double v = row[z];
-            const double2 w = twz[t];
-            re += v * w.x;
-            im += v * w.y;
-            t += kz;
-            if (t >= L.n2) t -= L.n2;
+            for (int z = 0; z < L.n2; ++z) {
+                const double v = row[z];
+                const double2 w = twz[t];
+                re += v * w.x;
+                im += v * w.y;
+                t += kz;
+                if (t >= L.n2) t -= L.n2;
+            }
+            Z[q] = make_double2(re, im);
         }
-        Z[q] = make_double2(re, im);
-    }
-    __syncthreads();
-    const int plane = L.kyn * L.kzn;
-    for (int q = threadIdx.x; q < plane; q += 256) {
-        const int kyi = q / L.kzn, kz = q % L.kzn;
-        const int step = mod_n(kyi - L.m, L.n1);
-        int t = mod_n((int64_t)(kyi - L.m) * y0, L.n1);
-        double re = 0.0, im = 0.0;
+        __syncthreads();
+        for (int q = threadIdx.x; q < plane; q += 256) {
+            const int kyi = q / L.kzn, kz = q % L.kzn;
+            const int step = mod_n(kyi - L.m, L.n1);
+            int t = mod_n((int64_t)(kyi - L.m) * y0, L.n1);
+            double re = 0.0, im = 0.0;
 #pragma unroll 4
-        for (int yl = 0; yl < ny; ++yl) {
-            const double2 a = Z[yl * L.kzn + kz];
-            const double2 w = twy[t];
-            re += a.x * w.x - a.y * w.y;
-            im += a.x * w.y + a.y * w.x;
-            t += step;
-            if (t >= L.n1) t -= L.n1;
+            for (int yl = 0; yl < ny; ++yl) {
+                const double2 a = Z[yl * L.kzn + kz];
+                const double2 w = twy[t];
+                re += a.x * w.x - a.y * w.y;
+                im += a.x * w.y + a.y * w.x;
+                t += step;
+                if (t >= L.n1) t -= L.n1;
+            }
+            Gacc[q].x += re;
+            Gacc[q].y += im;
         }
-        Gp[((int64_t)x * nch + ch) * plane + q] = make_double2(re, im);
+        __syncthreads();
     }
+    for (int q = threadIdx.x; q < plane; q += 256) Gp[((int64_t)x * nch + ch) * plane + q] = Gacc[q];
     if (UPDATE) {
         const double bm = block_reduce<OpMax>(m, slots);
         if (threadIdx.x == 0) part_rmax[blockIdx.x] = bm;
@@ -732,7 +739,8 @@ struct LowRankPlan {
     double* table;    // kxn x kyn x kzn, w(kz) C(k) / n
     double2* Gp;      // n0 x nch_a x kyn x kzn row-chunk partials
     double2* H;       // n0 x kyn x kzn
-    int ya, yc;       // rows per workgroup of passes A and C
+    int ya, yc;       // rows per group of pass A (in LDS at once), rows per workgroup of pass C
+    int rb;           // rows per workgroup of pass A
     int nch_a;
     int blocks_a, blocks_c;
     size_t lds_a, lds_b, lds_c;
@@ -779,11 +787,23 @@ uno_status lowrank_create(const Grid& g, const FftPlan& fp, int M, double W, con
     if (rows < 1) rows = 1;
     if (rows > L.n1) rows = L.n1;
     p->ya = p->yc = rows;
-    p->nch_a = (L.n1 + p->ya - 1) / p->ya;
+    // pass A: a workgroup sums its rows' partial DFTs itself, so the row
+    // chunks pass B gathers stay few: about 256 workgroups per right-hand
+    // side, each taking its rows ya at a time
+    {
+        const int want = (256 + L.n0 - 1) / L.n0;
+        int rb = (L.n1 + want - 1) / want;
+        rb = ((rb + p->ya - 1) / p->ya) * p->ya;
+        if (rb > L.n1) rb = L.n1;
+        if (p->ya > rb) p->ya = rb;
+        p->rb = rb;
+    }
+    p->nch_a = (L.n1 + p->rb - 1) / p->rb;
     p->blocks_a = L.n0 * p->nch_a;
     p->blocks_c = L.n0 * ((L.n1 + p->yc - 1) / p->yc);
     const int plane = L.kyn * L.kzn;
-    p->lds_a = sizeof(double2) * ((size_t)L.n2 + L.n1 + (size_t)p->ya * L.kzn) + sizeof(double) * (size_t)p->ya * L.n2;
+    p->lds_a = sizeof(double2) * ((size_t)L.n2 + L.n1 + (size_t)p->ya * L.kzn + plane) +
+               sizeof(double) * (size_t)p->ya * L.n2;
     p->cb_mid = 8;
     while (p->cb_mid > 1 && sizeof(double2) * (size_t)p->cb_mid * (L.n0 + L.kxn) > 48 * 1024) p->cb_mid /= 2;
     p->blocks_mid = (L.kyn * L.kzn + p->cb_mid - 1) / p->cb_mid;
@@ -856,7 +876,7 @@ uno_status lowrank_forward(const LowRankPlan* p, const double* r, double* part_r
                            const CgIter& strides, hipStream_t st)
 {
     uno_launch(UNO_KT_FFT_FWD, k_lr_fwd<false, double>, dim3(p->blocks_a, bt.nrhs), dim3(256), p->lds_a, st, p->dev,
-               p->ya, (double*)r, (double*)nullptr, (const double*)nullptr, (const double*)nullptr, bt.Gp, strides,
+               p->ya, p->rb, (double*)r, (double*)nullptr, (const double*)nullptr, (const double*)nullptr, bt.Gp, strides,
                (const double*)nullptr, 0, (const double*)nullptr, (double*)nullptr, part_rr);
     return hip_status(hipGetLastError());
 }
@@ -867,8 +887,8 @@ uno_status lowrank_update_forward(const LowRankPlan* p, double* r, double* u, co
                                   const CgIter& it, const double* part_dp, int np_dp, const double* gam,
                                   double* part_rmax, double* part_rr, const LrBatch& bt, hipStream_t st)
 {
-    uno_launch(UNO_KT_UPDATE, k_lr_fwd<true, T>, dim3(p->blocks_a, bt.nrhs), dim3(256), p->lds_a, st, p->dev, p->ya, r,
-               u, d, pv, bt.Gp, it, part_dp, np_dp, gam, part_rmax, part_rr);
+    uno_launch(UNO_KT_UPDATE, k_lr_fwd<true, T>, dim3(p->blocks_a, bt.nrhs), dim3(256), p->lds_a, st, p->dev, p->ya,
+               p->rb, r, u, d, pv, bt.Gp, it, part_dp, np_dp, gam, part_rmax, part_rr);
     return hip_status(hipGetLastError());
 }
 
