@@ -61,12 +61,12 @@ def kernel_sources_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def kernel_families(uno, shape, M, learned):
+def kernel_families(uno, shape, M, learned, nr, kappa_per_rhs):
     """Kernel families of one UNO-CG pass and their algorithmic bytes per
-    launch (FP64; a launch carries the 3 load cases, kappa and the table are
-    shared)."""
+    launch (FP64; a launch carries nr right-hand sides, each with its own
+    conductivity field or all with one; the table is shared)."""
     n = int(np.prod(shape))
-    nr = len(LOADS)
+    nk = nr if kappa_per_rhs else 1
     nspec = shape[0] * shape[1] * (shape[2] // 2 + 1)
     nblk = shape[0] * (2 * M + 1) * (M + 1)   # learned block after the two partial DFTs (y, z)
     if learned:
@@ -74,7 +74,7 @@ def kernel_families(uno, shape, M, learned):
         fams = {uno.KT_MATVEC: "k_stencil_tile<double,CG>", uno.KT_UPDATE: "k_lr_fwd<update,double>",
                 uno.KT_FFT_MID: "k_lr_mid", uno.KT_FFT_INV: "k_lr_inv<double>"}
         bytes_per = {
-            uno.KT_MATVEC: nr * n * 8 * 4 + n * 8,       # read s, d_old; write d_new, p; kappa
+            uno.KT_MATVEC: nr * n * 8 * 4 + nk * n * 8,  # read s, d_old, kappa; write d_new, p
             uno.KT_UPDATE: nr * (n * 8 * 6 + nblk * 16),  # read r, u, d, p; write r, u, block spectrum
             uno.KT_FFT_MID: nr * nblk * 16 * 2 + nblk * 8,  # block spectrum in/out; table
             uno.KT_FFT_INV: nr * (n * 8 * 2 + nblk * 16),  # read r, H; write s
@@ -231,35 +231,47 @@ def main():
     train_s = time.time() - t0
     log("trained M=%d in %.1fs" % (M, train_s))
 
-    sols = torch.zeros((3,) + SHAPE, dtype=torch.float64, device=dev)
+    # one step = every test microstructure x every load: nm x 3 solves
+    nm = len(kap_test)
+    kap_all = torch.stack([k for k in kap_test for _ in LOADS])
+    loads_all = np.tile(LOADS, (nm, 1))
+    sols = torch.zeros((nm * len(LOADS),) + SHAPE, dtype=torch.float64, device=dev)
+    nr_all = nm * len(LOADS)
 
-    def step(i, kind, precond, together=True, **kw):
-        """The 3 load cases of microstructure i (solved together, every pass
-        kernel carrying the three; or one after another), then kappa_bar."""
-        k = kap_test[i % len(kap_test)]
+    def step(kind, precond, mode="all", **kw):
+        """The whole hot path over the test set: rhs + CG for every load of
+        every microstructure, then kappa_bar of each.  mode "all": the nm x 3
+        solves carried together by every pass kernel; "micro": the 3 loads of
+        one microstructure together, microstructure after microstructure;
+        "single": one load at a time."""
         sols.zero_()
-        if together:
-            _, infos = uno.pcg_solve_batch(k, macro_loads=LOADS, u=sols, kind=kind, precond=precond, rtol=RTOL,
-                                           max_iter=50000, **kw)
+        if mode == "all":
+            _, infos = uno.pcg_solve_batch(kap_all, macro_loads=loads_all, u=sols, kind=kind, precond=precond,
+                                           rtol=RTOL, max_iter=50000, kappa_per_rhs=True, **kw)
+        elif mode == "micro":
+            infos = []
+            for i, k in enumerate(kap_test):
+                infos += uno.pcg_solve_batch(k, macro_loads=LOADS, u=sols[3 * i: 3 * i + 3], kind=kind,
+                                             precond=precond, rtol=RTOL, max_iter=50000, **kw)[1]
         else:
-            infos = [uno.pcg_solve(k, macro_load=g, u=sols[j], kind=kind, precond=precond, rtol=RTOL,
-                                   max_iter=50000, **kw)[1] for j, g in enumerate(LOADS)]
+            infos = [uno.pcg_solve(kap_all[j], macro_load=loads_all[j], u=sols[j], kind=kind, precond=precond,
+                                   rtol=RTOL, max_iter=50000, **kw)[1] for j in range(nr_all)]
         for info in infos:
             if not info["converged"]:
                 raise RuntimeError("solve did not converge: %s" % info)
-        kb = uno.effective_tensor(k, LOADS, sols)
-        return [info["iters"] for info in infos], kb
+        kbs = [uno.effective_tensor(k, LOADS, sols[3 * i: 3 * i + 3]) for i, k in enumerate(kap_test)]
+        return [info["iters"] for info in infos], kbs
 
-    def timed(kind, precond, steps, warmup, **kw):
-        for i in range(warmup):
-            step(i, kind, precond, **kw)
+    def timed(kind, precond, steps, warmup, mode="all", **kw):
+        for _ in range(warmup):
+            step(kind, precond, mode, **kw)
         torch.cuda.synchronize()
         t = time.perf_counter()
         all_its, kbs = [], []
-        for i in range(steps):
-            its, kb = step(i, kind, precond, **kw)
+        for _ in range(steps):
+            its, kb = step(kind, precond, mode, **kw)
             all_its += its
-            kbs.append(kb)
+            kbs += kb
         torch.cuda.synchronize()
         return time.perf_counter() - t, all_its, kbs
 
@@ -268,14 +280,15 @@ def main():
     ms_step = dt / args.steps * 1e3
     value = n_dof * sum(its) / dt
     uno_t_solve = dt / len(its) * 1e3
-    log("UNO-CG: %.2f ms/step, %.1f passes/solve, %.3e DOF*it/s, %.3f ms per solve" %
-        (ms_step, np.mean(its), value, uno_t_solve))
-    # the same loads one solve at a time (context for the batched step)
-    nseq = max(1, min(args.steps, 4))
-    dts, itss, _ = timed("uno", prec, nseq, 1, together=False)
+    log("UNO-CG: %.2f ms/step (%d solves), %.1f passes/solve, %.3e DOF*it/s, %.3f ms per solve" %
+        (ms_step, nr_all, np.mean(its), value, uno_t_solve))
+    # the same solves three loads at a time, and one load at a time (context)
+    dtq, itsq, _ = timed("uno", prec, 1, 1, mode="micro")
+    micro_t_solve = dtq / len(itsq) * 1e3
+    dts, itss, _ = timed("uno", prec, 1, 1, mode="single")
     seq_t_solve = dts / len(itss) * 1e3
-    log("UNO-CG one load at a time: %.3f ms per solve (%.2fx slower than together)" %
-        (seq_t_solve, seq_t_solve / uno_t_solve))
+    log("UNO-CG 3 loads per launch: %.3f ms per solve; one load at a time: %.3f ms per solve" %
+        (micro_t_solve, seq_t_solve))
     # ---------------- Jacobi-CG on the same microstructures ----------------
     dtj, itsj, _ = timed("jacobi", None, args.jac_steps, 1)
     jac_t_solve = dtj / len(itsj) * 1e3
@@ -284,14 +297,13 @@ def main():
 
     # ---------------- mixed precision: FP32 operator / preconditioner ----------------
     f32 = dict(op_dtype=torch.float32, prec_dtype=torch.float32)
-    nmix = max(1, min(args.steps, 4))
-    dtm, itsm, kbm = timed("uno", prec, nmix, 1, **f32)
-    kb_err = max(float(np.abs(a - b).max() / np.abs(b).max()) for a, b in zip(kbm, kbs[:nmix]))
+    dtm, itsm, kbm = timed("uno", prec, 1, 0, **f32)
+    kb_err = max(float(np.abs(a - b).max() / np.abs(b).max()) for a, b in zip(kbm, kbs[:nm]))
     log("UNO-CG FP32 op/prec: %.1f passes/solve, %.3f ms per solve, kappa_bar rel diff vs FP64 %.1e" %
         (np.mean(itsm), dtm / len(itsm) * 1e3, kb_err))
     prec_bf16 = uno.UnoPrecond.create(SHAPE, M, theta, table_dtype=torch.bfloat16)
-    dtb, itsb, kbb = timed("uno", prec_bf16, nmix, 1, **f32)
-    kb_err_b = max(float(np.abs(a - b).max() / np.abs(b).max()) for a, b in zip(kbb, kbs[:nmix]))
+    dtb, itsb, kbb = timed("uno", prec_bf16, 1, 0, **f32)
+    kb_err_b = max(float(np.abs(a - b).max() / np.abs(b).max()) for a, b in zip(kbb, kbs[:nm]))
     log("UNO-CG BF16 table: %.1f passes/solve, %.3f ms per solve, kappa_bar rel diff %.1e" %
         (np.mean(itsb), dtb / len(itsb) * 1e3, kb_err_b))
 
@@ -307,8 +319,8 @@ def main():
     except RuntimeError:
         learned = False
     prec.set_path(prec.PATH_AUTO)
-    fams, bytes_per = kernel_families(uno, SHAPE, M, learned)
-    fam_ms = family_times(uno, fams, lambda: step(0, "uno", prec))
+    fams, bytes_per = kernel_families(uno, SHAPE, M, learned, nr_all, True)
+    fam_ms = family_times(uno, fams, lambda: step("uno", prec))
     roofline = roofline_record(fams, bytes_per, fam_ms)
     if learned and kernel_sources_hash() == TRAFFIC_SRC:
         roofline["traffic"] = TRAFFIC_BYTES.get(roofline["kernel"])
@@ -351,7 +363,7 @@ def main():
         kb192 = torch.tensor(si.microstructure(cfgb, 7000)[0], device=dev)
         pb = uno.UnoPrecond.create(cfgb["shape"], 12, si.random_theta(uno.num_weights(3, 12), 7001,
                                                                         scale=0.02, spread=0.1))
-        fb, bb = kernel_families(uno, cfgb["shape"], 12, True)
+        fb, bb = kernel_families(uno, cfgb["shape"], 12, True, len(LOADS), False)
         ub = torch.zeros((3,) + cfgb["shape"], dtype=torch.float64, device=dev)
 
         def run_big():
@@ -391,11 +403,12 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "3D thermal 64^3 periodic hex8, spheres r 4-8 vf 0.25, kappa 1/100, "
-                               "3 loads per step solved together, UNO-CG to 1e-6 + effective tensor",
+                               "16 microstructures x 3 loads per step, solved together, UNO-CG to 1e-6 + effective tensors",
                    "grid": list(SHAPE), "loads_per_step": 3, "M": M, "train_pairs": len(F),
                    "microstructures": len(kap_test)},
         "uno_cg": {"passes_mean": float(np.mean(its)), "ms_per_solve": uno_t_solve, "dof_iters_per_s": value,
-                   "loads_together": 3, "ms_per_solve_one_at_a_time": seq_t_solve},
+                   "solves_per_launch": nr_all, "ms_per_solve_3_loads_per_launch": micro_t_solve,
+                   "ms_per_solve_one_at_a_time": seq_t_solve},
         "jac_cg": {"passes_mean": float(np.mean(itsj)), "ms_per_solve": jac_t_solve, "dof_iters_per_s": jac_rate},
         "fans_cg": {"passes_mean": float(np.mean(itsf)), "ms_per_solve": dtf / len(itsf) * 1e3},
         "uno_cg_fp32": {"passes_mean": float(np.mean(itsm)), "ms_per_solve": dtm / len(itsm) * 1e3,

@@ -174,10 +174,12 @@ uno_status pcg_solve(const uno_grid *grid, const uno_material *mat, const double
                      const double *rhs, double *u, const uno_solve_opts *opts, uno_solve_info *info,
                      double *res_hist, void *stream);
 
-/* nrhs independent solves with one conductivity field and preconditioner:
- * the load cases of one microstructure (Sec. 5.1: one cell problem per unit
- * macroscopic gradient; Sec. 4.5: batched solution of many problems).
- * Load j is uno_macro_rhs(gbar = macro_loads + d j) (host, nrhs x d) when
+/* nrhs independent solves with one preconditioner: the load cases of one
+ * microstructure (Sec. 5.1: one cell problem per unit macroscopic gradient)
+ * or of many (Sec. 4.5: batched solution of many problems).  mat->kappa is
+ * one conductivity field shared by all loads (kappa_per_rhs = 0) or nrhs
+ * fields, field j at + n j (kappa_per_rhs = 1).  Load j is
+ * uno_macro_rhs(gbar = macro_loads + d j) of its field (host, nrhs x d) when
  * macro_loads is non-NULL, else rhs + n j (device, nrhs x n doubles).
  * u (device, nrhs x n doubles) holds the initial guesses and receives the
  * zero-mean solutions; info (host, nullable) receives nrhs records.
@@ -187,7 +189,7 @@ uno_status pcg_solve(const uno_grid *grid, const uno_material *mat, const double
  * without the learned-mode passes and the FP32 mode are run load by load.
  * 1 <= nrhs <= 64.  Returns UNO_ERR_BREAKDOWN if any load broke down (see
  * info).  Synchronous. */
-uno_status pcg_solve_batch(const uno_grid *grid, const uno_material *mat, int32_t nrhs,
+uno_status pcg_solve_batch(const uno_grid *grid, const uno_material *mat, int32_t kappa_per_rhs, int32_t nrhs,
                            const double *macro_loads, const double *rhs, double *u,
                            const uno_solve_opts *opts, uno_solve_info *info, void *stream);
 
@@ -247,7 +249,8 @@ enum {
     UNO_KT_UPDATE = 2,   /* residual/solution update (+ Jacobi + r.s) */
     UNO_KT_FFT_FWD = 3,  /* first transform pass of the UNO apply */
     UNO_KT_FFT_MID = 4,  /* middle pass: transform, Phi multiply, inverse */
-    UNO_KT_FFT_INV = 5   /* last inverse pass (+ r.s) */
+    UNO_KT_FFT_INV = 5,  /* last inverse pass (+ r.s) */
+    UNO_KT_APPLY = 6     /* operator apply outside CG (fe_apply, residuals) */
 };
 /* Brackets every launch of kernel family `which` with start/stop HIP events
  * of the launch itself (hipExtLaunchKernelGGL) on its stream; UNO_KT_NONE

@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(_HERE, "libunocg.so")
 
 UNO_F64, UNO_F32, UNO_BF16 = 0, 1, 2
 UNO_PREC_NONE, UNO_PREC_JACOBI, UNO_PREC_UNO = 0, 1, 2
-KT_NONE, KT_MATVEC, KT_UPDATE, KT_FFT_FWD, KT_FFT_MID, KT_FFT_INV = 0, 1, 2, 3, 4, 5
+KT_NONE, KT_MATVEC, KT_UPDATE, KT_FFT_FWD, KT_FFT_MID, KT_FFT_INV, KT_APPLY = 0, 1, 2, 3, 4, 5, 6
 STATUS = {0: "UNO_OK", -1: "UNO_ERR_ARG", -2: "UNO_ERR_SHAPE", -3: "UNO_ERR_NOT_SPD",
           -4: "UNO_ERR_BREAKDOWN", -5: "UNO_ERR_DEVICE", -6: "UNO_ERR_NOMEM"}
 
@@ -80,7 +80,7 @@ def lib():
         "uno_precond_set_path": ([vp, i32], i),
         "uno_precond_destroy": ([vp], i),
         "pcg_solve": ([G, Mt, P(f64), vp, vp, P(uno_solve_opts), P(uno_solve_info), P(f64), vp], i),
-        "pcg_solve_batch": ([G, Mt, i32, P(f64), vp, vp, P(uno_solve_opts), P(uno_solve_info), vp], i),
+        "pcg_solve_batch": ([G, Mt, i32, i32, P(f64), vp, vp, P(uno_solve_opts), P(uno_solve_info), vp], i),
         "effective_tensor": ([G, Mt, i32, P(f64), vp, P(f64), vp], i),
         "effective_tensor_grad": ([G, i32, P(f64), vp, P(f64), vp, vp], i),
         "uno_train_accumulate": ([G, i32, vp, vp, f64, vp, vp, vp], i),
@@ -297,26 +297,31 @@ def _opts(kind, precond, rtol, max_iter, op_dtype, prec_dtype, graph_chunk):
 
 def pcg_solve_batch(kappa: torch.Tensor, macro_loads=None, rhs: torch.Tensor | None = None,
                     u: torch.Tensor | None = None, kind="jacobi", precond: UnoPrecond | None = None, rtol=1e-6,
-                    max_iter=100000, op_dtype=torch.float64, prec_dtype=torch.float64, graph_chunk=0, L0=1.0):
-    """nrhs solves with one conductivity field (the load cases of one
-    microstructure), all carried by every pass kernel.  macro_loads: nrhs x d
-    (host) or rhs: nrhs x shape (device).  Returns (u (nrhs x shape), [info])."""
-    g = make_grid(kappa.shape, L0)
-    d = len(kappa.shape)
+                    max_iter=100000, op_dtype=torch.float64, prec_dtype=torch.float64, graph_chunk=0,
+                    kappa_per_rhs=False, L0=1.0):
+    """nrhs solves carried together by every pass kernel: the load cases of
+    one conductivity field (kappa: grid), or with kappa_per_rhs one field per
+    right-hand side (kappa: nrhs x grid).  macro_loads: nrhs x d (host) or
+    rhs: nrhs x grid (device).  Returns (u (nrhs x grid), [info])."""
+    shape = tuple(kappa.shape[1:]) if kappa_per_rhs else tuple(kappa.shape)
+    g = make_grid(shape, L0)
+    d = len(shape)
     ml = None
     if macro_loads is not None:
         ml = np.ascontiguousarray(macro_loads, dtype=np.float64).reshape(-1, d)
         nrhs = ml.shape[0]
     else:
         nrhs = rhs.shape[0]
+    if kappa_per_rhs and kappa.shape[0] != nrhs:
+        raise ValueError("kappa_per_rhs needs one field per right-hand side")
     if u is None:
-        u = torch.zeros((nrhs,) + tuple(kappa.shape), dtype=torch.float64, device=kappa.device)
-    if tuple(u.shape) != (nrhs,) + tuple(kappa.shape):
+        u = torch.zeros((nrhs,) + shape, dtype=torch.float64, device=kappa.device)
+    if tuple(u.shape) != (nrhs,) + shape:
         raise ValueError("u must be nrhs x grid")
     o = _opts(kind, precond, rtol, max_iter, op_dtype, prec_dtype, graph_chunk)
     infos = (uno_solve_info * nrhs)()
     st = lib().pcg_solve_batch(
-        ctypes.byref(g), ctypes.byref(_mat(kappa)), nrhs,
+        ctypes.byref(g), ctypes.byref(_mat(kappa)), 1 if kappa_per_rhs else 0, nrhs,
         ml.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if ml is not None else None,
         _dev(rhs, "rhs", torch.float64) if rhs is not None else None,
         _dev(u, "u", torch.float64), ctypes.byref(o), infos, _stream())

@@ -16,8 +16,9 @@ namespace unocg {
 uno_status ws_release_all();
 uno_status pcg_run(const Grid& g, const double* kappa, const double* macro_load3, const double* rhs, double* u,
                    const uno_solve_opts* o, uno_solve_info* info, double* res_hist, hipStream_t st);
-uno_status pcg_run_batch(const Grid& g, const double* kappa, int nrhs, const double* macro_loads3, const double* rhs,
-                         double* u, const uno_solve_opts* o, uno_solve_info* info, double* res_hist, hipStream_t st);
+uno_status pcg_run_batch(const Grid& g, const double* kappa, int64_t ks, int nrhs, const double* macro_loads3,
+                         const double* rhs, double* u, const uno_solve_opts* o, uno_solve_info* info, double* res_hist,
+                         hipStream_t st);
 
 uno_status hip_status(hipError_t e)
 {
@@ -491,22 +492,23 @@ uno_status pcg_solve(const uno_grid* grid, const uno_material* mat, const double
     return pcg_run(g, (const double*)mat->kappa, macro_load ? g3 : nullptr, rhs, u, opts, info, res_hist, S(stream));
 }
 
-uno_status pcg_solve_batch(const uno_grid* grid, const uno_material* mat, int32_t nrhs, const double* macro_loads,
-                           const double* rhs, double* u, const uno_solve_opts* opts, uno_solve_info* info,
-                           void* stream)
+uno_status pcg_solve_batch(const uno_grid* grid, const uno_material* mat, int32_t kappa_per_rhs, int32_t nrhs,
+                           const double* macro_loads, const double* rhs, double* u, const uno_solve_opts* opts,
+                           uno_solve_info* info, void* stream)
 {
     Grid g;
     uno_status e = check_solve(grid, mat, opts, &g);
     if (e != UNO_OK) return e;
     if (nrhs < 1 || nrhs > 64 || !u || (!macro_loads && !rhs)) return UNO_ERR_ARG;
+    if (kappa_per_rhs != 0 && kappa_per_rhs != 1) return UNO_ERR_ARG;
     std::vector<double> g3;
     if (macro_loads) {
         g3.assign(3 * (size_t)nrhs, 0.0);
         for (int j = 0; j < nrhs; ++j)
             for (int b = 0; b < grid->dim; ++b) g3[3 * j + 3 - grid->dim + b] = macro_loads[grid->dim * j + b];
     }
-    return pcg_run_batch(g, (const double*)mat->kappa, nrhs, macro_loads ? g3.data() : nullptr, rhs, u, opts, info,
-                         nullptr, S(stream));
+    return pcg_run_batch(g, (const double*)mat->kappa, kappa_per_rhs ? g.total : 0, nrhs,
+                         macro_loads ? g3.data() : nullptr, rhs, u, opts, info, nullptr, S(stream));
 }
 
 uno_status effective_tensor(const uno_grid* grid, const uno_material* mat, int32_t nload, const double* loads,

@@ -80,11 +80,12 @@ template <typename T, int MODE>
 __global__ void __launch_bounds__(kBlock) k_cg_init(GridDev g, const T* __restrict__ dinv,
                                                     const double* __restrict__ r, T* __restrict__ s,
                                                     double* __restrict__ part_rmax, double* __restrict__ part_rs,
-                                                    double* __restrict__ part_ss, CgState* st, int ps)
+                                                    double* __restrict__ part_ss, CgState* st, int ps, int64_t ks)
 {
     __shared__ double slots[kBlock / 64];
     if (blockIdx.y > 0) {  // right-hand side blockIdx.y of a batch
         const int64_t vo = (int64_t)blockIdx.y * g.n, po = (int64_t)blockIdx.y * ps;
+        dinv += (int64_t)blockIdx.y * ks;
         r += vo;
         s += vo;
         part_rmax += po;
@@ -138,6 +139,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_update(GridDev g, const T* __rest
     __shared__ double slots[kBlock / 64];
     if (blockIdx.y > 0) {  // right-hand side blockIdx.y of a batch
         const int64_t vo = (int64_t)blockIdx.y * it.vs, po = (int64_t)blockIdx.y * it.ps;
+        dinv += (int64_t)blockIdx.y * it.ks;
         r += vo;
         u += vo;
         d += vo;
@@ -294,7 +296,7 @@ struct Workspace {
     int npart = 0;            // capacity of each partial buffer (per right-hand side)
     int nrhs_cap = 0;
     double *f = nullptr, *r = nullptr, *s = nullptr, *d[2] = {nullptr, nullptr}, *p = nullptr;
-    double* dinv = nullptr;   // inverse Jacobi diagonal of the current solve
+    double* dinv = nullptr;   // inverse Jacobi diagonal(s) of the current solve
     float* kap32 = nullptr;   // FP32 conductivities (mixed precision)
     double* y64 = nullptr;    // FP64 operator output for residual replacement (mixed precision)
     double* part = nullptr;   // 8 partial buffers: rmax, rs[2], dp, ss[2], ds[2]
@@ -321,16 +323,16 @@ void ws_free_vectors(Workspace* w)
     (void)hipFree(w->d[0]);
     (void)hipFree(w->d[1]);
     (void)hipFree(w->p);
+    (void)hipFree(w->dinv);
     (void)hipFree(w->state);
     (void)hipHostFree(w->host_state);
-    w->f = w->r = w->s = w->d[0] = w->d[1] = w->p = nullptr;
+    w->f = w->r = w->s = w->d[0] = w->d[1] = w->p = w->dinv = nullptr;
     w->state = w->host_state = nullptr;
 }
 
 void ws_free(Workspace* w)
 {
     ws_free_vectors(w);
-    (void)hipFree(w->dinv);
     (void)hipFree(w->kap32);
     (void)hipFree(w->y64);
     (void)hipFree(w->part);
@@ -357,10 +359,6 @@ uno_status ws_get(const Grid& g, const FftPlan* plan, const LowRankPlan* lr, int
         w->total = g.total;
         const int64_t nb = (g.total + kBlock - 1) / kBlock;
         w->nbr = (int)(nb < kMaxStreamBlocks ? nb : kMaxStreamBlocks);
-        if (hipMalloc(&w->dinv, sizeof(double) * (size_t)g.total) != hipSuccess) {
-            ws_free(w);
-            return UNO_ERR_NOMEM;
-        }
         g_ws.push_back(w);
     }
     if (nrhs > w->nrhs_cap) {
@@ -369,6 +367,7 @@ uno_status ws_get(const Grid& g, const FftPlan* plan, const LowRankPlan* lr, int
         bool ok = hipMalloc(&w->f, vb) == hipSuccess && hipMalloc(&w->r, vb) == hipSuccess &&
                   hipMalloc(&w->s, vb) == hipSuccess && hipMalloc(&w->d[0], vb) == hipSuccess &&
                   hipMalloc(&w->d[1], vb) == hipSuccess && hipMalloc(&w->p, vb) == hipSuccess &&
+                  hipMalloc(&w->dinv, vb) == hipSuccess &&
                   hipMalloc(&w->state, sizeof(CgState) * nrhs) == hipSuccess &&
                   hipHostMalloc(&w->host_state, sizeof(CgState) * nrhs, hipHostMallocDefault) == hipSuccess;
         if (!ok) {
@@ -467,7 +466,7 @@ Parts parts_of(Workspace* w)
 
 // np_update: workgroups of the update kernel (they write the ||r||_inf
 // partials read at the head of pass k > k0; pass k0 reads the init kernel's)
-CgIter iter_of(Workspace* w, const Parts& P, int k, int k0, double rtol, int hist_len, int np_update)
+CgIter iter_of(Workspace* w, const Parts& P, int k, int k0, double rtol, int hist_len, int np_update, int64_t ks)
 {
     CgIter it;
     memset(&it, 0, sizeof(it));
@@ -485,6 +484,7 @@ CgIter iter_of(Workspace* w, const Parts& P, int k, int k0, double rtol, int his
     it.vs = w->total;
     it.ps = w->npart;
     it.hs = w->hist_cap;
+    it.ks = ks;
     return it;
 }
 
@@ -497,7 +497,8 @@ LrBatch lr_batch(Workspace* w, int nrhs) { return LrBatch{w->lr_gp, w->lr_h, nrh
 // and every reduction stay FP64.
 template <typename T>
 static uno_status enqueue_pass(const Grid& g, Workspace* w, int kind, const uno_precond* pc, const T* kappa,
-                               double* u, int k, int k0, double rtol, int hist_len, int nrhs, hipStream_t st)
+                               int64_t ks, double* u, int k, int k0, double rtol, int hist_len, int nrhs,
+                               hipStream_t st)
 {
     const Parts P = parts_of(w);
     const int nb = w->nbr;
@@ -508,7 +509,7 @@ static uno_status enqueue_pass(const Grid& g, Workspace* w, int kind, const uno_
     int np_rs = nb;
     const MeanFree mf{P.ss[k & 1], P.ds[k & 1], P.ds[(k + 1) & 1]};
     if (kind == UNO_PREC_UNO && uno_use_lowrank(pc)) {
-        CgIter it = iter_of(w, P, k, k0, rtol, hist_len, lowrank_update_blocks(pc->lr));
+        CgIter it = iter_of(w, P, k, k0, rtol, hist_len, lowrank_update_blocks(pc->lr), ks);
         const LrBatch bt = lr_batch(w, nrhs);
         if constexpr (sizeof(T) == sizeof(double)) {
             if (uno_use_fused(pc)) {
@@ -531,7 +532,7 @@ static uno_status enqueue_pass(const Grid& g, Workspace* w, int kind, const uno_
         UNO_HIP(hipGetLastError());
         return lowrank_update_forward<T>(pc->lr, w->r, u, dnew, pv, it, P.dp, np_dp, w->gam, P.rmax, nullptr, bt, st);
     }
-    CgIter it = iter_of(w, P, k, k0, rtol, hist_len, nb);
+    CgIter it = iter_of(w, P, k, k0, rtol, hist_len, nb, ks);
     if (kind == UNO_PREC_UNO) {
         if (sizeof(T) != sizeof(double) || nrhs != 1) return UNO_ERR_ARG;  // spectral passes: FP64, one rhs
         uno_status e = uno_apply_passes(g, pc->plan, pc->table, UNO_F64, w->r, w->s, UNO_F64, w->spec, &it, &np_rs, st);
@@ -571,9 +572,9 @@ constexpr double kRestartFactor = 1e-3;
 
 // The CG loop for nrhs right-hand sides (restarts only with nrhs = 1).
 template <typename T>
-static uno_status pcg_loop(const Grid& g, Workspace* w, const double* kappa64, const T* kappa, double* u,
-                           const uno_solve_opts* o, const uno_precond* pc, int hist_len, int nrhs, hipStream_t st,
-                           int* k_end)
+static uno_status pcg_loop(const Grid& g, Workspace* w, const double* kappa64, const T* kappa, int64_t ks,
+                           double* u, const uno_solve_opts* o, const uno_precond* pc, int hist_len, int nrhs,
+                           hipStream_t st, int* k_end)
 {
     const int nb = w->nbr;
     const Parts P = parts_of(w);
@@ -583,25 +584,26 @@ static uno_status pcg_loop(const Grid& g, Workspace* w, const double* kappa64, c
     const int np_update = lowrank ? lowrank_update_blocks(pc->lr) : nb;
     const bool restarts = sizeof(T) == sizeof(float);
     if (restarts && nrhs != 1) return UNO_ERR_ARG;
-    if (o->kind == UNO_PREC_JACOBI)
-        hipLaunchKernelGGL(k_inv_diag<T>, dim3(nb), dim3(kBlock), 0, st, g.dev, kappa64, dinv);
+    if (o->kind == UNO_PREC_JACOBI)  // one inverse diagonal per conductivity field
+        for (int b = 0; b < (ks ? nrhs : 1); ++b)
+            hipLaunchKernelGGL(k_inv_diag<T>, dim3(nb), dim3(kBlock), 0, st, g.dev, kappa64 + b * ks, dinv + b * ks);
     // (re)start of the recurrence from the residual in w->r: s_0 = P r_0 and
     // the partials of the first pass
     auto start = [&]() -> uno_status {
         const dim3 grid(nb, nrhs);
         if (o->kind == UNO_PREC_NONE)
             hipLaunchKernelGGL((k_cg_init<T, 0>), grid, dim3(kBlock), 0, st, g.dev, (const T*)dinv,
-                               (const double*)w->r, sv, P.rmax, P.rs[0], P.ss[0], w->state, w->npart);
+                               (const double*)w->r, sv, P.rmax, P.rs[0], P.ss[0], w->state, w->npart, ks);
         else if (o->kind == UNO_PREC_JACOBI)
             hipLaunchKernelGGL((k_cg_init<T, 1>), grid, dim3(kBlock), 0, st, g.dev, (const T*)dinv,
-                               (const double*)w->r, sv, P.rmax, P.rs[0], P.ss[0], w->state, w->npart);
+                               (const double*)w->r, sv, P.rmax, P.rs[0], P.ss[0], w->state, w->npart, ks);
         else
             hipLaunchKernelGGL((k_cg_init<T, 2>), grid, dim3(kBlock), 0, st, g.dev, (const T*)dinv,
-                               (const double*)w->r, sv, P.rmax, P.rs[0], P.ss[0], w->state, w->npart);
+                               (const double*)w->r, sv, P.rmax, P.rs[0], P.ss[0], w->state, w->npart, ks);
         UNO_HIP(hipGetLastError());
         if (lowrank) {  // transform of r for the first pass (and ||r||^2 in the fused flow)
             const bool fused = sizeof(T) == sizeof(double) && uno_use_fused(pc);
-            const CgIter strides = iter_of(w, P, 0, 0, 0.0, 0, nb);
+            const CgIter strides = iter_of(w, P, 0, 0, 0.0, 0, nb, ks);
             return lowrank_forward(pc->lr, w->r, fused ? P.rs[0] : nullptr, lr_batch(w, nrhs), strides, st);
         }
         return UNO_OK;
@@ -617,10 +619,10 @@ static uno_status pcg_loop(const Grid& g, Workspace* w, const double* kappa64, c
     for (;;) {
         if (chunk > o->max_iter - k) chunk = o->max_iter - k;
         for (int c = 0; c < chunk; ++c, ++k) {
-            e = enqueue_pass<T>(g, w, o->kind, pc, kappa, u, k, k0, o->rtol, hist_len, nrhs, st);
+            e = enqueue_pass<T>(g, w, o->kind, pc, kappa, ks, u, k, k0, o->rtol, hist_len, nrhs, st);
             if (e != UNO_OK) return e;
         }
-        CgIter it = iter_of(w, P, k, k0, o->rtol, hist_len, np_update);
+        CgIter it = iter_of(w, P, k, k0, o->rtol, hist_len, np_update, ks);
         hipLaunchKernelGGL(k_cg_check, dim3(1, nrhs), dim3(kBlock), 0, st, it);
         UNO_HIP(hipGetLastError());
         UNO_HIP(hipMemcpyAsync(w->host_state, w->state, sizeof(CgState) * nrhs, hipMemcpyDeviceToHost, st));
@@ -682,8 +684,9 @@ static uno_status pcg_loop(const Grid& g, Workspace* w, const double* kappa64, c
 
 // nrhs solves with one operator (and preconditioner); load b: macro_loads +
 // 3 b (or rhs + b n), solution u + b n, info[b]
-uno_status pcg_run_batch(const Grid& g, const double* kappa, int nrhs, const double* macro_loads3, const double* rhs,
-                         double* u, const uno_solve_opts* o, uno_solve_info* info, double* res_hist, hipStream_t st)
+uno_status pcg_run_batch(const Grid& g, const double* kappa, int64_t ks, int nrhs, const double* macro_loads3,
+                         const double* rhs, double* u, const uno_solve_opts* o, uno_solve_info* info, double* res_hist,
+                         hipStream_t st)
 {
     const uno_precond* pc = (o->kind == UNO_PREC_UNO) ? o->uno : nullptr;
     const bool mixed = (o->op_t == UNO_F32);
@@ -694,7 +697,7 @@ uno_status pcg_run_batch(const Grid& g, const double* kappa, int nrhs, const dou
     if (!together) {
         uno_status worst = UNO_OK;
         for (int b = 0; b < nrhs; ++b) {
-            uno_status e = pcg_run_batch(g, kappa, 1, macro_loads3 ? macro_loads3 + 3 * b : nullptr,
+            uno_status e = pcg_run_batch(g, kappa + b * ks, 0, 1, macro_loads3 ? macro_loads3 + 3 * b : nullptr,
                                          rhs ? rhs + (int64_t)b * g.total : nullptr, u + (int64_t)b * g.total, o,
                                          info ? info + b : nullptr, nullptr, st);
             if (e == UNO_ERR_BREAKDOWN) worst = e;
@@ -714,12 +717,12 @@ uno_status pcg_run_batch(const Grid& g, const double* kappa, int nrhs, const dou
     for (int b = 0; b < nrhs; ++b) {
         double* fb = w->f + b * n;
         if (macro_loads3) {
-            e = launch_rhs(g, kappa, UNO_F64, macro_loads3 + 3 * b, fb, UNO_F64, st);
+            e = launch_rhs(g, kappa + b * ks, UNO_F64, macro_loads3 + 3 * b, fb, UNO_F64, st);
             if (e != UNO_OK) return e;
         } else {
             UNO_HIP(hipMemcpyAsync(fb, rhs + b * n, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
         }
-        e = launch_fe_apply(g, kappa, u + b * n, w->p + b * n, UNO_F64, st);
+        e = launch_fe_apply(g, kappa + b * ks, u + b * n, w->p + b * n, UNO_F64, st);
         if (e != UNO_OK) return e;
         hipLaunchKernelGGL(k_sub, dim3(nb), dim3(kBlock), 0, st, n, (const double*)fb, (const double*)(w->p + b * n),
                            w->r + b * n);
@@ -730,9 +733,9 @@ uno_status pcg_run_batch(const Grid& g, const double* kappa, int nrhs, const dou
         if (!w->kap32 && hipMalloc(&w->kap32, sizeof(float) * n) != hipSuccess) return UNO_ERR_NOMEM;
         if (!w->y64 && hipMalloc(&w->y64, sizeof(double) * n) != hipSuccess) return UNO_ERR_NOMEM;
         hipLaunchKernelGGL(k_convert<float>, dim3(nb), dim3(kBlock), 0, st, n, kappa, w->kap32);
-        e = pcg_loop<float>(g, w, kappa, w->kap32, u, o, pc, hist_len, nrhs, st, &k);
+        e = pcg_loop<float>(g, w, kappa, w->kap32, 0, u, o, pc, hist_len, nrhs, st, &k);
     } else {
-        e = pcg_loop<double>(g, w, kappa, kappa, u, o, pc, hist_len, nrhs, st, &k);
+        e = pcg_loop<double>(g, w, kappa, kappa, ks, u, o, pc, hist_len, nrhs, st, &k);
     }
     if (e != UNO_OK) return e;
     std::vector<CgState> hs(w->host_state, w->host_state + nrhs);
@@ -744,7 +747,7 @@ uno_status pcg_run_batch(const Grid& g, const double* kappa, int nrhs, const dou
         double* pd = P.dp + (int64_t)b * w->npart;
         hipLaunchKernelGGL(k_sum_parts, dim3(nb), dim3(kBlock), 0, st, n, (const double*)ub, pd);
         hipLaunchKernelGGL(k_sub_mean, dim3(nb), dim3(kBlock), 0, st, n, ub, (const double*)pd, nb, w->state + b);
-        e = launch_fe_apply(g, kappa, ub, w->p + b * n, UNO_F64, st);
+        e = launch_fe_apply(g, kappa + b * ks, ub, w->p + b * n, UNO_F64, st);
         if (e != UNO_OK) return e;
         hipLaunchKernelGGL(k_resid_parts, dim3(nb), dim3(kBlock), 0, st, n, (const double*)(w->f + b * n),
                            (const double*)(w->p + b * n), pa, pb);
@@ -780,7 +783,7 @@ uno_status pcg_run_batch(const Grid& g, const double* kappa, int nrhs, const dou
 uno_status pcg_run(const Grid& g, const double* kappa, const double* macro_load3, const double* rhs, double* u,
                    const uno_solve_opts* o, uno_solve_info* info, double* res_hist, hipStream_t st)
 {
-    return pcg_run_batch(g, kappa, 1, macro_load3, rhs, u, o, info, res_hist, st);
+    return pcg_run_batch(g, kappa, 0, 1, macro_load3, rhs, u, o, info, res_hist, st);
 }
 
 }  // namespace unocg

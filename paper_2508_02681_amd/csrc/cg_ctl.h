@@ -31,6 +31,7 @@ struct CgIter {
     int64_t vs;
     int ps;
     int hs;
+    int64_t ks;   // stride between the conductivity (and Jacobi) fields: 0 when shared
 };
 
 // The control of right-hand side blockIdx.y (state, partials, history).

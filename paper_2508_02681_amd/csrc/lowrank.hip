@@ -484,6 +484,7 @@ __global__ void __launch_bounds__(256) k_lr_tile(GridDev g, TileGeom tg, LowRank
     const int x0 = txi * TX, y0 = tyi * TY, z0 = tzi * TZ;
     if (blockIdx.y > 0) {  // right-hand side blockIdx.y of a batch
         const int64_t vo = (int64_t)blockIdx.y * it.vs, po = (int64_t)blockIdx.y * it.ps;
+        kappa += (int64_t)blockIdx.y * it.ks;
         r += vo;
         dold += vo;
         dnew += vo;

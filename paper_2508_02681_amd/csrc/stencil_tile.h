@@ -125,6 +125,7 @@ __global__ void __launch_bounds__(256) k_stencil_tile(GridDev g, TileGeom tg, co
     const int x0 = txi * TX, y0 = tyi * TY, z0 = tzi * TZ;
     if (CG && blockIdx.y > 0) {  // right-hand side blockIdx.y of a batch
         const int64_t vo = (int64_t)blockIdx.y * it.vs, po = (int64_t)blockIdx.y * it.ps;
+        kappa += (int64_t)blockIdx.y * it.ks;
         s += vo;
         dold += vo;
         dnew += vo;
@@ -316,18 +317,19 @@ inline void launch_tile_near(const TileChoice& c, const GridDev& g, const T* kap
                              hipStream_t st, const MeanFree& mf, int nrhs)
 {
     const dim3 grid(c.blocks, nrhs);
+    const int fam = CG ? UNO_KT_MATVEC : UNO_KT_APPLY;  // timing family
     switch (c.tz) {
         case 64:
-            uno_launch(UNO_KT_MATVEC, k_stencil_tile<T, TX, 64, CG, HEAD, NEAR>, grid, dim3(256), 0, st, g, c.geom,
-                       kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam, mf);
+            uno_launch(fam, k_stencil_tile<T, TX, 64, CG, HEAD, NEAR>, grid, dim3(256), 0, st, g, c.geom, kappa, s,
+                       dold, dnew, p, part_dp, it, part_rs, np_rs, gam, mf);
             break;
         case 32:
-            uno_launch(UNO_KT_MATVEC, k_stencil_tile<T, TX, 32, CG, HEAD, NEAR>, grid, dim3(256), 0, st, g, c.geom,
-                       kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam, mf);
+            uno_launch(fam, k_stencil_tile<T, TX, 32, CG, HEAD, NEAR>, grid, dim3(256), 0, st, g, c.geom, kappa, s,
+                       dold, dnew, p, part_dp, it, part_rs, np_rs, gam, mf);
             break;
         default:
-            uno_launch(UNO_KT_MATVEC, k_stencil_tile<T, TX, 16, CG, HEAD, NEAR>, grid, dim3(256), 0, st, g, c.geom,
-                       kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam, mf);
+            uno_launch(fam, k_stencil_tile<T, TX, 16, CG, HEAD, NEAR>, grid, dim3(256), 0, st, g, c.geom, kappa, s,
+                       dold, dnew, p, part_dp, it, part_rs, np_rs, gam, mf);
             break;
     }
 }

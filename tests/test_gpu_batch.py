@@ -120,3 +120,19 @@ def test_batch_argument_errors(uno):
         uno.pcg_solve_batch(kap, macro_loads=np.zeros((0, 3)), kind="jacobi")
     with pytest.raises(uno.UnoError):
         uno.pcg_solve_batch(kap, macro_loads=np.ones((65, 3)), kind="jacobi")
+
+
+@pytest.mark.parametrize("kind,M,path", [("uno", 3, 0), ("uno", 3, 3), ("jacobi", 0, 0)])
+def test_batch_of_microstructures_equals_single_solves(uno, kind, M, path):
+    """One conductivity field per right-hand side (several microstructures x
+    loads in one batch): every result equals that of its single solve."""
+    shape = (24, 20, 16)
+    kaps = [T(_kappa(shape, 70 + i)) for i in range(3)]
+    loads = np.array([[1.0, 0, 0], [0, 1.0, 0], [0, 0, 1.0], [0.5, 0.5, 0], [1.0, 0, 0], [0, 0, 1.0]])
+    kap_all = torch.stack([kaps[j % 3] for j in range(len(loads))])
+    p = _precond(uno, shape, M, path) if kind == "uno" else None
+    ub, infos = uno.pcg_solve_batch(kap_all, macro_loads=loads, kind=kind, precond=p, rtol=1e-8, kappa_per_rhs=True)
+    for j in range(len(loads)):
+        us, info = uno.pcg_solve(kap_all[j], macro_load=loads[j], kind=kind, precond=p, rtol=1e-8)
+        assert infos[j]["iters"] == info["iters"]
+        assert torch.equal(ub[j], us), "right-hand side %d differs from its single solve" % j
