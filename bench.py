@@ -37,18 +37,18 @@ LOADS = np.eye(3)
 RTOL = 1e-6
 HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs of
-# this benchmark (64^3, M = 12, three loads per launch), each scaled by what the counter reads for a
+# this benchmark (64^3, M = 12, 48 right-hand sides per launch), each scaled by what the counter reads for a
 # device copy of known size (FETCH x 2, WRITE x 1); the summary with its
 # commands is profiles/uno_cg_64cubed_hbm_counters.md.  Valid only for the
 # kernel sources as they were when counted (TRAFFIC_SRC: hash of the files in
 # TRAFFIC_FILES); after any change the figure is withheld.
 TRAFFIC_FILES = ["lowrank.hip", "stencil_tile.h", "cg_ctl.h", "reduce.h", "cg.hip"]
-TRAFFIC_SRC = "630c4e1ce704ade9"
-TRAFFIC_BYTES = {
-    "k_lr_fwd<update,double>": 34666713,
-    "k_stencil_tile<double,CG>": 41394308,
-    "k_lr_mid": 16458528,
-    "k_lr_inv<double>": 12990591,
+TRAFFIC_SRC = "ccddd2aff8c6cd99"
+TRAFFIC_BYTES = {  # per launch of the benchmark step (48 right-hand sides)
+    "k_stencil_tile<double,CG>": 825203886,
+    "k_lr_fwd<update,double>": 604339019,
+    "k_lr_mid": 133978183,
+    "k_lr_inv<double>": 242111246,
 }
 
 
