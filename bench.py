@@ -45,7 +45,7 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILES = ["lowrank.hip", "stencil_tile.h", "cg_ctl.h", "reduce.h", "cg.hip"]
 TRAFFIC_SRC = "ccddd2aff8c6cd99"
 TRAFFIC_BYTES = {  # per launch of the benchmark step (48 right-hand sides)
-    "k_stencil_tile<double,CG>": 825203886,
+    "k_stencil_march<double,CG>": 825203886,
     "k_lr_fwd<update,double>": 604339019,
     "k_lr_mid": 133978183,
     "k_lr_inv<double>": 242111246,
@@ -71,7 +71,7 @@ def kernel_families(uno, shape, M, learned, nr, kappa_per_rhs):
     nblk = shape[0] * (2 * M + 1) * (M + 1)   # learned block after the two partial DFTs (y, z)
     if learned:
         # pass B -> pass C -> operator -> [update + pass A]
-        fams = {uno.KT_MATVEC: "k_stencil_tile<double,CG>", uno.KT_UPDATE: "k_lr_fwd<update,double>",
+        fams = {uno.KT_MATVEC: "k_stencil_march<double,CG>", uno.KT_UPDATE: "k_lr_fwd<update,double>",
                 uno.KT_FFT_MID: "k_lr_mid", uno.KT_FFT_INV: "k_lr_inv<double>"}
         bytes_per = {
             uno.KT_MATVEC: nr * n * 8 * 4 + nk * n * 8,  # read s, d_old, kappa; write d_new, p
@@ -80,7 +80,7 @@ def kernel_families(uno, shape, M, learned, nr, kappa_per_rhs):
             uno.KT_FFT_INV: nr * (n * 8 * 2 + nblk * 16),  # read r, H; write s
         }
     else:  # spectral passes, one load per launch
-        fams = {uno.KT_MATVEC: "k_stencil_tile<double,CG>", uno.KT_UPDATE: "k_cg_update<double>",
+        fams = {uno.KT_MATVEC: "k_stencil_march<double,CG>", uno.KT_UPDATE: "k_cg_update<double>",
                 uno.KT_FFT_FWD: "k_fft_r2c_z", uno.KT_FFT_MID: "k_fft_strided(mid)", uno.KT_FFT_INV: "k_fft_c2r_z"}
         bytes_per = {
             uno.KT_MATVEC: n * 8 * 5,

@@ -385,7 +385,8 @@ uno_status ws_get(const Grid& g, const FftPlan* plan, const LowRankPlan* lr, int
         w->nrhs_cap = nrhs;
     }
     int need = w->nbr;
-    const int ntile = choose_tile(g).blocks;
+    int ntile = choose_tile(g).blocks;
+    if (march_max_blocks(g) > ntile) ntile = march_max_blocks(g);
     if (ntile > need) need = ntile;
     if (extra_parts > need) need = extra_parts;
     if (need > w->npart) {

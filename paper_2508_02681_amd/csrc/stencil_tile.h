@@ -1,13 +1,13 @@
-// LDS-tiled matrix-free operator apply (Sec. 3.1: the stiffness matrix of the
-// periodic linear FE discretization, applied without assembly).
+// Matrix-free operator apply (Sec. 3.1: the stiffness matrix of the periodic
+// linear FE discretization, applied without assembly).
 //
-// A workgroup of 256 threads owns a TX x TY x TZ tile of nodes (TY = 256 /
-// TZ).  It stages the vector on the tile plus a one-node halo and the
-// conductivities of the (TX+1) x (TY+1) x (TZ+1) voxels touching the tile in
-// LDS (periodic wrap on each coordinate), then each thread walks one (y, z)
-// column of the tile along x, keeping the 3 x 3 neighbourhood of three node
+// A workgroup of 256 threads owns a TY x TZ footprint of nodes (TY = 256 /
+// TZ) and marches along x over xb node planes.  Planes of the vector (with
+// a one-node halo in y and z) and of the conductivities of the voxels
+// touching them stream through a small ring of LDS planes (periodic wrap on
+// each coordinate); each thread keeps the 3 x 3 neighbourhood of three node
 // planes and the 2 x 2 voxel conductivities of two voxel planes in
-// registers: 9 + 4 LDS reads per node.
+// registers and rolls them along x: 9 + 4 LDS reads per node.
 //
 // Node-centred form of the assembled operator: node i touches the 8 voxels
 // i + sigma, sigma in {-1,0}^3, and
@@ -17,8 +17,8 @@
 // 0 -> both); w[m] is the brick element's corner coupling.
 //
 // CG variant (fused into Algorithm 1's direction update and matvec): the
-// staged vector is d = s + beta d_old, the tile's own d is written to d_new,
-// p = A d, and per-workgroup partials of d.p are written.
+// staged vector is d = s + beta d_old, the workgroup's own d is written to
+// d_new, p = A d, and per-workgroup partials of d.p are written.
 #pragma once
 
 #include "unocg_internal.h"
@@ -95,34 +95,51 @@ struct MeanFree {
     double* part_dnew;
 };
 
-// NEAR: every tile dimension fits in the grid, so staging coordinates lie in
+// The kernel: a workgroup owns a TY x TZ footprint and xb consecutive node
+// planes along x.  Planes of d (= s + beta d_old, shifted in FP32) and of
+// conductivities stream through a ring of three (d) and two (kappa) LDS
+// planes: each plane is loaded once per footprint, the loads of the next
+// plane are issued before the current plane is computed, and one barrier
+// per plane separates the ring writes from the reads.  Per node plane the
+// halo costs (TY+2)(TZ+2)/(TY TZ) of the plane; along x only the two end
+// planes of the march are extra.  Right-hand side blockIdx.y of a batch
+// reads its vectors at + blockIdx.y n (conductivities at + blockIdx.y ks).
+//
+// In FP32 the direction is kept mean-free: A 1 = 0 and sum(A d) = 0, so
+// shifting d by a constant leaves p, d.p, alpha, r and beta unchanged and
+// moves u by a constant (removed at the end); it avoids the cancellation a
+// large constant component causes in the FP32 stencil sums.
+//
+// NEAR: the footprint fits in the grid, so staging coordinates lie in
 // [-n, 2n) and wrap without a division (decided on the host per launch).
-template <typename T, int TX, int TZ, bool CG, bool HEAD, bool NEAR>
-__global__ void __launch_bounds__(256) k_stencil_tile(GridDev g, TileGeom tg, const T* __restrict__ kappa,
-                                                      const T* __restrict__ s, const T* __restrict__ dold,
-                                                      T* __restrict__ dnew, T* __restrict__ p,
-                                                      double* __restrict__ part_dp, CgIter it,
-                                                      const double* __restrict__ part_rs, int np_rs, double* gam,
-                                                      MeanFree mf)
+struct MarchGeom {
+    int tiles_y, tiles_z, xb, tiles_x;
+};
+
+template <typename T, int TZ, bool CG, bool HEAD, bool NEAR>
+__global__ void __launch_bounds__(256) k_stencil_march(GridDev g, MarchGeom mg, const T* __restrict__ kappa,
+                                                       const T* __restrict__ s, const T* __restrict__ dold,
+                                                       T* __restrict__ dnew, T* __restrict__ p,
+                                                       double* __restrict__ part_dp, CgIter it,
+                                                       const double* __restrict__ part_rs, int np_rs, double* gam,
+                                                       MeanFree mf)
 {
-    // In FP32 the direction is kept mean-free: A 1 = 0 and sum(A d) = 0, so
-    // shifting d by a constant leaves p, d.p, alpha, r and beta unchanged and
-    // moves u by a constant (removed at the end); it avoids the cancellation
-    // a large constant component causes in the FP32 stencil sums.
     constexpr bool MF = CG && sizeof(T) == 4;
     constexpr int TY = 256 / TZ;
-    constexpr int DX = TX + 2, DY = TY + 2, DZ = TZ + 2;
-    constexpr int KX = TX + 1, KY = TY + 1, KZ = TZ + 1;
-    __shared__ T Dl[DX * DY * DZ];
-    __shared__ T Kl[KX * KY * KZ];
+    constexpr int DY = TY + 2, DZ = TZ + 2, KY = TY + 1, KZ = TZ + 1;
+    constexpr int ND = DY * DZ, NK = KY * KZ;
+    constexpr int PD = (ND + 255) / 256, PK = (NK + 255) / 256;
+    __shared__ T Dr[3][ND];
+    __shared__ T Kr[2][NK];
     __shared__ double slots[4];
 
     int b = blockIdx.x;
-    const int tzi = b % tg.tiles_z;
-    b /= tg.tiles_z;
-    const int tyi = b % tg.tiles_y;
-    const int txi = b / tg.tiles_y;
-    const int x0 = txi * TX, y0 = tyi * TY, z0 = tzi * TZ;
+    const int tzi = b % mg.tiles_z;
+    b /= mg.tiles_z;
+    const int tyi = b % mg.tiles_y;
+    const int txi = b / mg.tiles_y;
+    const int x0 = txi * mg.xb, y0 = tyi * TY, z0 = tzi * TZ;
+    const int xe = min(g.n0, x0 + mg.xb);
     if (CG && blockIdx.y > 0) {  // right-hand side blockIdx.y of a batch
         const int64_t vo = (int64_t)blockIdx.y * it.vs, po = (int64_t)blockIdx.y * it.ps;
         kappa += (int64_t)blockIdx.y * it.ks;
@@ -140,9 +157,51 @@ __global__ void __launch_bounds__(256) k_stencil_tile(GridDev g, TileGeom tg, co
         }
         it = rhs_iter(it);
     }
+    auto wrapc = [](int v, int n) {
+        if constexpr (NEAR) return wrap_near(v, n);
+        else return wrap_mod(v, n);
+    };
+    // this thread's staging offsets within a plane (y, z wrapped once)
+    int doff[PD], koff[PK];
+#pragma unroll
+    for (int j = 0; j < PD; ++j) {
+        const int q = threadIdx.x + 256 * j;
+        doff[j] = -1;
+        if (q < ND) {
+            const int zl = q % DZ, yl = q / DZ;
+            doff[j] = wrapc(y0 - 1 + yl, g.n1) * g.n2 + wrapc(z0 - 1 + zl, g.n2);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < PK; ++j) {
+        const int q = threadIdx.x + 256 * j;
+        koff[j] = -1;
+        if (q < NK) {
+            const int zl = q % KZ, yl = q / KZ;
+            koff[j] = wrapc(y0 - 1 + yl, g.n1) * g.n2 + wrapc(z0 - 1 + zl, g.n2);
+        }
+    }
+    const bool have_dold = CG && it.k > it.k0;
+    const int64_t pl = (int64_t)g.n1 * g.n2;
+    auto load_d = [&](int xp, T* sv, T* dv) {
+        const int64_t base = (int64_t)wrapc(xp, g.n0) * pl;
+#pragma unroll
+        for (int j = 0; j < PD; ++j) {
+            sv[j] = dv[j] = (T)0;
+            if (doff[j] >= 0) {
+                sv[j] = s[base + doff[j]];
+                if (have_dold) dv[j] = dold[base + doff[j]];
+            }
+        }
+    };
+    auto load_k = [&](int xp, T* kv) {
+        const int64_t base = (int64_t)wrapc(xp, g.n0) * pl;
+#pragma unroll
+        for (int j = 0; j < PK; ++j) kv[j] = (koff[j] >= 0) ? kappa[base + koff[j]] : (T)0;
+    };
 
-    // every global load is issued before the first decision, so the loop
-    // state, the partials, the previous gamma and the staged data overlap
+    // loads first: loop state, partials, previous gamma, the first three d
+    // planes and the first two conductivity planes
     StateLoad sl;
     double head_share = 0.0, rs_share = 0.0, gprev = 1.0, ssum_share = 0.0, dsum_share = 0.0;
     if (CG) {
@@ -155,39 +214,12 @@ __global__ void __launch_bounds__(256) k_stencil_tile(GridDev g, TileGeom tg, co
             if (it.k > it.k0) dsum_share = load_share<OpSum>(mf.part_dold, gridDim.x);
         }
     }
-    constexpr int ND = DX * DY * DZ, NK = KX * KY * KZ;
-    constexpr int PD = (ND + 255) / 256, PK = (NK + 255) / 256;
-    // staging coordinates lie in [-1, n - 1 + T]; a single conditional wrap
-    // covers [-n, 2n) unless the tile is wider than the grid (small grids)
-    auto wrapc = [](int v, int n) {
-        if constexpr (NEAR) return wrap_near(v, n);
-        else return wrap_mod(v, n);
-    };
-    T sv[PD], dv[PD], kv[PK];
-#pragma unroll
-    for (int j = 0; j < PD; ++j) {
-        const int q = threadIdx.x + 256 * j;
-        sv[j] = dv[j] = (T)0;
-        if (q < ND) {
-            const int zl = q % DZ, t = q / DZ;  // constant divisors
-            const int yl = t % DY, xl = t / DY;
-            const int x = wrapc(x0 - 1 + xl, g.n0), y = wrapc(y0 - 1 + yl, g.n1), z = wrapc(z0 - 1 + zl, g.n2);
-            const int64_t idx = ((int64_t)x * g.n1 + y) * g.n2 + z;
-            sv[j] = s[idx];
-            if (CG && it.k > it.k0) dv[j] = dold[idx];
-        }
-    }
-#pragma unroll
-    for (int j = 0; j < PK; ++j) {
-        const int q = threadIdx.x + 256 * j;
-        kv[j] = (T)0;
-        if (q < NK) {
-            const int zl = q % KZ, t = q / KZ;
-            const int yl = t % KY, xl = t / KY;
-            const int x = wrapc(x0 - 1 + xl, g.n0), y = wrapc(y0 - 1 + yl, g.n1), z = wrapc(z0 - 1 + zl, g.n2);
-            kv[j] = kappa[((int64_t)x * g.n1 + y) * g.n2 + z];
-        }
-    }
+    T s0[PD], v0[PD], s1[PD], v1[PD], s2[PD], v2[PD], k0v[PK], k1v[PK];
+    load_d(x0 - 1, s0, v0);
+    load_d(x0, s1, v1);
+    load_d(x0 + 1, s2, v2);
+    load_k(x0 - 1, k0v);
+    load_k(x0, k1v);
     T beta = 0;
     bool first = true;
     if (CG) {
@@ -213,16 +245,26 @@ __global__ void __launch_bounds__(256) k_stencil_tile(GridDev g, TileGeom tg, co
         const double dsum = first ? 0.0 : combine_share<OpSum>(dsum_share, slots);
         shift = (T)((ssum + (double)beta * dsum) / (double)g.n);
     }
+    auto put_d = [&](int slot, const T* sv, const T* dv) {
 #pragma unroll
-    for (int j = 0; j < PD; ++j) {
-        const int q = threadIdx.x + 256 * j;
-        if (q < ND) Dl[q] = ((CG && !first) ? sv[j] + beta * dv[j] : sv[j]) - shift;
-    }
+        for (int j = 0; j < PD; ++j) {
+            const int q = threadIdx.x + 256 * j;
+            if (q < ND) Dr[slot][q] = ((CG && !first) ? sv[j] + beta * dv[j] : sv[j]) - shift;
+        }
+    };
+    auto put_k = [&](int slot, const T* kv) {
 #pragma unroll
-    for (int j = 0; j < PK; ++j) {
-        const int q = threadIdx.x + 256 * j;
-        if (q < NK) Kl[q] = kv[j];
-    }
+        for (int j = 0; j < PK; ++j) {
+            const int q = threadIdx.x + 256 * j;
+            if (q < NK) Kr[slot][q] = kv[j];
+        }
+    };
+    // ring slots by plane offset from x0 - 1: d in slot (offset % 3), kappa in (offset % 2)
+    put_d(0, s0, v0);
+    put_d(1, s1, v1);
+    put_d(2, s2, v2);
+    put_k(0, k0v);
+    put_k(1, k1v);
     __syncthreads();
 
     const int tz = threadIdx.x % TZ, ty = threadIdx.x / TZ;
@@ -233,28 +275,34 @@ __global__ void __launch_bounds__(256) k_stencil_tile(GridDev g, TileGeom tg, co
     for (int bb = 0; bb < 3; ++bb)
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            dm[bb][c] = Dl[(0 * DY + ty + bb) * DZ + tz + c];
-            d0[bb][c] = Dl[(1 * DY + ty + bb) * DZ + tz + c];
+            dm[bb][c] = Dr[0][(ty + bb) * DZ + tz + c];
+            d0[bb][c] = Dr[1][(ty + bb) * DZ + tz + c];
         }
 #pragma unroll
     for (int bb = 0; bb < 2; ++bb)
 #pragma unroll
-        for (int c = 0; c < 2; ++c) km[bb][c] = Kl[(0 * KY + ty + bb) * KZ + tz + c];
+        for (int c = 0; c < 2; ++c) km[bb][c] = Kr[0][(ty + bb) * KZ + tz + c];
     double dot = 0.0, dsum_own = 0.0;
-#pragma unroll
-    for (int xi = 0; xi < TX; ++xi) {
+    for (int x = x0; x < xe; ++x) {
+        const int j = x - x0 + 1;  // offset of plane x from x0 - 1
+        const bool more = x + 1 < xe;
+        // next planes in flight while this one is computed
+        if (more) {
+            load_d(x + 2, s0, v0);
+            load_k(x + 1, k0v);
+        }
+        const int sd = (j + 1) % 3, sk = j % 2;
 #pragma unroll
         for (int bb = 0; bb < 3; ++bb)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) dq[bb][c] = Dl[((xi + 2) * DY + ty + bb) * DZ + tz + c];
+            for (int c = 0; c < 3; ++c) dq[bb][c] = Dr[sd][(ty + bb) * DZ + tz + c];
 #pragma unroll
         for (int bb = 0; bb < 2; ++bb)
 #pragma unroll
-            for (int c = 0; c < 2; ++c) kp[bb][c] = Kl[((xi + 1) * KY + ty + bb) * KZ + tz + c];
-        const int x = x0 + xi;
-        if (yz_ok && x < g.n0) {
+            for (int c = 0; c < 2; ++c) kp[bb][c] = Kr[sk][(ty + bb) * KZ + tz + c];
+        if (yz_ok) {
             const T acc = stencil_node<T>(g, dm, d0, dq, km, kp);
-            const int64_t i = ((int64_t)x * g.n1 + y) * g.n2 + z;
+            const int64_t i = (int64_t)x * pl + (int64_t)y * g.n2 + z;
             p[i] = acc;
             if (CG) {
                 dnew[i] = d0[1][1];
@@ -273,6 +321,11 @@ __global__ void __launch_bounds__(256) k_stencil_tile(GridDev g, TileGeom tg, co
         for (int bb = 0; bb < 2; ++bb)
 #pragma unroll
             for (int c = 0; c < 2; ++c) km[bb][c] = kp[bb][c];
+        if (more) {  // plane x + 2 replaces plane x - 1, kappa plane x + 1 replaces x - 1
+            put_d((j + 2) % 3, s0, v0);
+            put_k((j + 1) % 2, k0v);
+        }
+        __syncthreads();
     }
     if (CG) {
         const double bd = block_reduce<OpSum>(dot, slots);
@@ -311,49 +364,61 @@ inline TileChoice choose_tile(const Grid& g)
     return c;
 }
 
-template <typename T, bool CG, bool HEAD, int TX, bool NEAR>
-inline void launch_tile_near(const TileChoice& c, const GridDev& g, const T* kappa, const T* s, const T* dold, T* dnew,
-                             T* p, double* part_dp, const CgIter& it, const double* part_rs, int np_rs, double* gam,
-                             hipStream_t st, const MeanFree& mf, int nrhs)
-{
-    const dim3 grid(c.blocks, nrhs);
-    const int fam = CG ? UNO_KT_MATVEC : UNO_KT_APPLY;  // timing family
-    switch (c.tz) {
-        case 64:
-            uno_launch(fam, k_stencil_tile<T, TX, 64, CG, HEAD, NEAR>, grid, dim3(256), 0, st, g, c.geom, kappa, s,
-                       dold, dnew, p, part_dp, it, part_rs, np_rs, gam, mf);
-            break;
-        case 32:
-            uno_launch(fam, k_stencil_tile<T, TX, 32, CG, HEAD, NEAR>, grid, dim3(256), 0, st, g, c.geom, kappa, s,
-                       dold, dnew, p, part_dp, it, part_rs, np_rs, gam, mf);
-            break;
-        default:
-            uno_launch(fam, k_stencil_tile<T, TX, 16, CG, HEAD, NEAR>, grid, dim3(256), 0, st, g, c.geom, kappa, s,
-                       dold, dnew, p, part_dp, it, part_rs, np_rs, gam, mf);
-            break;
-    }
-}
-
 // tile dimensions within the grid (single conditional wrap)
 inline bool tile_near(const TileChoice& c, const GridDev& g)
 {
     return c.tx <= g.n0 && 256 / c.tz <= g.n1 && c.tz <= g.n2;
 }
 
-template <typename T, bool CG, bool HEAD, int TX>
-inline void launch_tile_tx(const TileChoice& c, const GridDev& g, const T* kappa, const T* s, const T* dold, T* dnew,
-                           T* p, double* part_dp, const CgIter& it, const double* part_rs, int np_rs, double* gam,
-                           hipStream_t st, const MeanFree& mf, int nrhs)
+// Upper bound of the marching kernel's workgroups per right-hand side (xb >= 2).
+inline int march_max_blocks(const Grid& g)
 {
-    if (tile_near(c, g))
-        launch_tile_near<T, CG, HEAD, TX, true>(c, g, kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam, st, mf,
-                                                nrhs);
-    else
-        launch_tile_near<T, CG, HEAD, TX, false>(c, g, kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam, st,
-                                                 mf, nrhs);
+    const TileChoice c = choose_tile(g);
+    const int tx = g.n[0] < 2 ? 1 : (g.n[0] + 1) / 2;
+    return tx * c.geom.tiles_y * c.geom.tiles_z;
 }
 
-// Launches the tiled operator (nrhs right-hand sides along grid y); returns
+// Marching geometry: footprints of choose_tile's TY x TZ, and xb planes per
+// workgroup so that a launch has about 4096 workgroups (at least 2 planes).
+inline MarchGeom march_geom(const Grid& g, const TileChoice& c, int nrhs)
+{
+    MarchGeom m;
+    m.tiles_y = c.geom.tiles_y;
+    m.tiles_z = c.geom.tiles_z;
+    const int64_t yz = (int64_t)m.tiles_y * m.tiles_z * nrhs;
+    int64_t xb = (g.n[0] * yz + 4095) / 4096;
+    if (xb < 2) xb = 2;
+    if (xb > g.n[0]) xb = g.n[0];
+    m.xb = (int)xb;
+    m.tiles_x = (g.n[0] + m.xb - 1) / m.xb;
+    return m;
+}
+
+template <typename T, bool CG, bool HEAD, bool NEAR>
+inline void launch_march_near(const MarchGeom& m, int tz, const GridDev& g, const T* kappa, const T* s,
+                              const T* dold, T* dnew, T* p, double* part_dp, const CgIter& it,
+                              const double* part_rs, int np_rs, double* gam, hipStream_t st, const MeanFree& mf,
+                              int nrhs)
+{
+    const dim3 grid(m.tiles_x * m.tiles_y * m.tiles_z, nrhs);
+    const int fam = CG ? UNO_KT_MATVEC : UNO_KT_APPLY;  // timing family
+    switch (tz) {
+        case 64:
+            uno_launch(fam, k_stencil_march<T, 64, CG, HEAD, NEAR>, grid, dim3(256), 0, st, g, m, kappa, s, dold,
+                       dnew, p, part_dp, it, part_rs, np_rs, gam, mf);
+            break;
+        case 32:
+            uno_launch(fam, k_stencil_march<T, 32, CG, HEAD, NEAR>, grid, dim3(256), 0, st, g, m, kappa, s, dold,
+                       dnew, p, part_dp, it, part_rs, np_rs, gam, mf);
+            break;
+        default:
+            uno_launch(fam, k_stencil_march<T, 16, CG, HEAD, NEAR>, grid, dim3(256), 0, st, g, m, kappa, s, dold,
+                       dnew, p, part_dp, it, part_rs, np_rs, gam, mf);
+            break;
+    }
+}
+
+// Launches the operator apply (nrhs right-hand sides along grid y); returns
 // the number of workgroups per right-hand side (= d.p partials).
 template <typename T, bool CG, bool HEAD>
 inline int launch_tile(const Grid& g, const T* kappa, const T* s, const T* dold, T* dnew, T* p, double* part_dp,
@@ -361,16 +426,15 @@ inline int launch_tile(const Grid& g, const T* kappa, const T* s, const T* dold,
                        const MeanFree& mf = MeanFree{nullptr, nullptr, nullptr}, int nrhs = 1)
 {
     const TileChoice c = choose_tile(g);
-    if (c.tx == 1)
-        launch_tile_tx<T, CG, HEAD, 1>(c, g.dev, kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam, st, mf,
-                                       nrhs);
-    else if (c.tx == 2)
-        launch_tile_tx<T, CG, HEAD, 2>(c, g.dev, kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam, st, mf,
-                                       nrhs);
+    const MarchGeom m = march_geom(g, c, nrhs);
+    const bool near = 256 / c.tz <= g.n[1] && c.tz <= g.n[2];
+    if (near)
+        launch_march_near<T, CG, HEAD, true>(m, c.tz, g.dev, kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam,
+                                             st, mf, nrhs);
     else
-        launch_tile_tx<T, CG, HEAD, 4>(c, g.dev, kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam, st, mf,
-                                       nrhs);
-    return c.blocks;
+        launch_march_near<T, CG, HEAD, false>(m, c.tz, g.dev, kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs,
+                                              gam, st, mf, nrhs);
+    return m.tiles_x * m.tiles_y * m.tiles_z;
 }
 
 }  // namespace unocg
