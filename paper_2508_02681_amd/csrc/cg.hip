@@ -489,7 +489,10 @@ CgIter iter_of(Workspace* w, const Parts& P, int k, int k0, double rtol, int his
     return it;
 }
 
-LrBatch lr_batch(Workspace* w, int nrhs) { return LrBatch{w->lr_gp, w->lr_h, nrhs}; }
+LrBatch lr_batch(Workspace* w, const uno_precond* pc, int nrhs)
+{
+    return lowrank_batch(pc->lr, w->lr_gp, w->lr_h, nrhs);
+}
 
 }  // namespace
 
@@ -510,8 +513,8 @@ static uno_status enqueue_pass(const Grid& g, Workspace* w, int kind, const uno_
     int np_rs = nb;
     const MeanFree mf{P.ss[k & 1], P.ds[k & 1], P.ds[(k + 1) & 1]};
     if (kind == UNO_PREC_UNO && uno_use_lowrank(pc)) {
-        CgIter it = iter_of(w, P, k, k0, rtol, hist_len, lowrank_update_blocks(pc->lr), ks);
-        const LrBatch bt = lr_batch(w, nrhs);
+        CgIter it = iter_of(w, P, k, k0, rtol, hist_len, lowrank_update_blocks(pc->lr, nrhs), ks);
+        const LrBatch bt = lr_batch(w, pc, nrhs);
         if constexpr (sizeof(T) == sizeof(double)) {
             if (uno_use_fused(pc)) {
                 // fused FP64 flow: B (head, Parseval partials) -> [C + matvec] -> [update + A of pass k+1];
@@ -582,7 +585,7 @@ static uno_status pcg_loop(const Grid& g, Workspace* w, const double* kappa64, c
     T* sv = (T*)w->s;
     T* dinv = (T*)w->dinv;
     const bool lowrank = pc && uno_use_lowrank(pc);
-    const int np_update = lowrank ? lowrank_update_blocks(pc->lr) : nb;
+    const int np_update = lowrank ? lowrank_update_blocks(pc->lr, nrhs) : nb;
     const bool restarts = sizeof(T) == sizeof(float);
     if (restarts && nrhs != 1) return UNO_ERR_ARG;
     if (o->kind == UNO_PREC_JACOBI)  // one inverse diagonal per conductivity field
@@ -605,7 +608,7 @@ static uno_status pcg_loop(const Grid& g, Workspace* w, const double* kappa64, c
         if (lowrank) {  // transform of r for the first pass (and ||r||^2 in the fused flow)
             const bool fused = sizeof(T) == sizeof(double) && uno_use_fused(pc);
             const CgIter strides = iter_of(w, P, 0, 0, 0.0, 0, nb, ks);
-            return lowrank_forward(pc->lr, w->r, fused ? P.rs[0] : nullptr, lr_batch(w, nrhs), strides, st);
+            return lowrank_forward(pc->lr, w->r, fused ? P.rs[0] : nullptr, lr_batch(w, pc, nrhs), strides, st);
         }
         return UNO_OK;
     };

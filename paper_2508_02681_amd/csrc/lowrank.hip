@@ -337,7 +337,12 @@ __global__ void __launch_bounds__(256) k_lr_mid(LowRankDev L, int nch, int cb, c
     }
 }
 
-// Pass C: one workgroup per (x-slab, chunk of rows y).
+// Pass C: one workgroup per (x-slab, chunk of rows y).  Both partial
+// inverse transforms are evaluated with Horner's rule in the unit-modulus
+// phase factor: along y a thread owns one k_z column for two rows (each H
+// value read from LDS feeds two chains); along z a thread owns zpt points of
+// one row (each V value feeds zpt chains) and also loads, updates and writes
+// exactly those nodes.
 template <bool CG, typename TS>
 __global__ void __launch_bounds__(256) k_lr_inv(LowRankDev L, int y_chunk, const double* __restrict__ r,
                                                 const double2* __restrict__ H, TS* __restrict__ s, CgIter it)
@@ -356,70 +361,89 @@ __global__ void __launch_bounds__(256) k_lr_inv(LowRankDev L, int y_chunk, const
     const int y0 = (blockIdx.x % nch) * y_chunk;
     const int ny = min(y_chunk, L.n1 - y0);
     const int plane = L.kyn * L.kzn;
-    double2* twz = (double2*)smem;       // n2
-    double2* twy = twz + L.n2;           // n1
-    double2* Hs = twy + L.n1;            // kyn x kzn
+    double2* Hs = (double2*)smem;        // kyn x kzn
     double2* V = Hs + plane;             // ny x kzn
-    // loads first: state, the coefficient plane, twiddles and this thread's r
+    // z points of this thread: row t / tpr, z = t % tpr + tpr i
+    const int tpr = 256 / y_chunk;
+    const int row = threadIdx.x / tpr, part = threadIdx.x % tpr;
+    const bool row_ok = row < ny;
+    const int zpt = (L.n2 + tpr - 1) / tpr;
+    constexpr int ZB = 4;  // z points held in registers per round
+    const int64_t rbase = ((int64_t)x * L.n1 + y0 + row) * L.n2;
+    // loads first: state, the coefficient plane, phase factors and this thread's r
     StateLoad sl;
     if (CG) sl = load_state(it.st);
-    const int cnt = ny * L.n2;
-    const int64_t base = ((int64_t)x * L.n1 + y0) * L.n2;
-    constexpr int PF = 4;
-    double rv[PF];
+    double rv[ZB];
 #pragma unroll
-    for (int j = 0; j < PF; ++j) {
-        const int q = threadIdx.x + 256 * j;
-        rv[j] = (q < cnt) ? r[base + q] : 0.0;
+    for (int i = 0; i < ZB; ++i) {
+        const int z = part + tpr * i;
+        rv[i] = (row_ok && z < L.n2 && i < zpt) ? r[rbase + z] : 0.0;
     }
-    for (int j = threadIdx.x; j < L.n2; j += blockDim.x) twz[j] = L.twz[j];
-    for (int j = threadIdx.x; j < L.n1; j += blockDim.x) twy[j] = L.twy[j];
     for (int j = threadIdx.x; j < plane; j += blockDim.x) Hs[j] = H[(int64_t)x * plane + j];
     if (CG && ended(sl, it.k)) return;
     __syncthreads();
-    // V[y][kz] = sum_ky H[x][ky][kz] exp(+2 pi i ky y / n1)
-    for (int q = threadIdx.x; q < ny * L.kzn; q += blockDim.x) {
-        const int yl = q / L.kzn, kz = q % L.kzn;
-        const int y = y0 + yl;
-        const int step = mod_n(y, L.n1);
-        int t = mod_n((int64_t)(-L.m) * y, L.n1);
-        double re = 0.0, im = 0.0;
-        for (int kyi = 0; kyi < L.kyn; ++kyi) {
-            const double2 w = twy[t];
-            const double2 a = Hs[kyi * L.kzn + kz];
-            re += a.x * w.x + a.y * w.y;
-            im += a.y * w.x - a.x * w.y;
-            t += step;
-            if (t >= L.n1) t -= L.n1;
+    // V[y][kz] = exp(-i M phi_y) sum_kyi H[kyi][kz] w_y^kyi, w_y = exp(+2 pi i y / n1)
+    {
+        const int yh = (ny + 1) / 2;
+        for (int t = threadIdx.x; t < yh * L.kzn; t += blockDim.x) {
+            const int ya = t % yh, kz = t / yh;
+            const int yb = (ya + yh < ny) ? ya + yh : ya;
+            const double2 ta = L.twy[y0 + ya], tb = L.twy[y0 + yb];
+            const double2 wa = make_double2(ta.x, -ta.y), wb = make_double2(tb.x, -tb.y);
+            const double2* hcol = Hs + kz;
+            double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
+            for (int kyi = L.kyn - 1; kyi >= 0; --kyi) {
+                const double2 h = hcol[kyi * L.kzn];
+                const double nar = ar * wa.x - ai * wa.y + h.x;
+                ai = ar * wa.y + ai * wa.x + h.y;
+                ar = nar;
+                const double nbr = br * wb.x - bi * wb.y + h.x;
+                bi = br * wb.y + bi * wb.x + h.y;
+                br = nbr;
+            }
+            const double2 sa = L.twy[mod_n((int64_t)L.m * (y0 + ya), L.n1)];
+            const double2 sb = L.twy[mod_n((int64_t)L.m * (y0 + yb), L.n1)];
+            V[ya * L.kzn + kz] = make_double2(ar * sa.x - ai * sa.y, ar * sa.y + ai * sa.x);
+            if (yb != ya) V[yb * L.kzn + kz] = make_double2(br * sb.x - bi * sb.y, br * sb.y + bi * sb.x);
         }
-        V[q] = make_double2(re, im);
     }
     __syncthreads();
-    // s = W r + Re sum_kz V[y][kz] exp(+2 pi i kz z / n2)
-    auto node = [&](int q, double rq, double& ss) -> double {
-        const int yl = q / L.n2, z = q % L.n2;
-        double c = 0.0;
-        int t = 0;
-#pragma unroll 4
-        for (int kz = 0; kz < L.kzn; ++kz) {
-            const double2 w = twz[t];
-            const double2 a = V[yl * L.kzn + kz];
-            c += a.x * w.x + a.y * w.y;  // Re(a * conj(w))
-            t += z;
-            if (t >= L.n2) t -= L.n2;
-        }
-        const TS sv = (TS)(L.W * rq + c);
-        s[base + q] = sv;
-        ss += (double)sv;
-        return rq * (double)sv;
-    };
+    // s = W r + Re sum_kz V[row][kz] w_z^kz, w_z = exp(+2 pi i z / n2)
     double acc = 0.0, ssum = 0.0;
+    if (row_ok) {
+        const double2* vrow = V + row * L.kzn;
+        for (int i0 = 0; i0 < zpt; i0 += ZB) {
+            double ar[ZB], ai[ZB];
+            double2 w[ZB];
 #pragma unroll
-    for (int j = 0; j < PF; ++j) {
-        const int q = threadIdx.x + 256 * j;
-        if (q < cnt) acc += node(q, rv[j], ssum);
+            for (int i = 0; i < ZB; ++i) {
+                const int z = part + tpr * (i0 + i);
+                const double2 tz = L.twz[z < L.n2 ? z : 0];
+                w[i] = make_double2(tz.x, -tz.y);
+                ar[i] = ai[i] = 0.0;
+            }
+            for (int kz = L.kzn - 1; kz >= 0; --kz) {
+                const double2 v = vrow[kz];
+#pragma unroll
+                for (int i = 0; i < ZB; ++i) {
+                    const double nr = ar[i] * w[i].x - ai[i] * w[i].y + v.x;
+                    ai[i] = ar[i] * w[i].y + ai[i] * w[i].x + v.y;
+                    ar[i] = nr;
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < ZB; ++i) {
+                const int z = part + tpr * (i0 + i);
+                if (z < L.n2) {
+                    const double rq = (i0 == 0) ? rv[i] : r[rbase + z];
+                    const TS sv = (TS)(L.W * rq + ar[i]);
+                    s[rbase + z] = sv;
+                    ssum += (double)sv;
+                    acc += rq * (double)sv;
+                }
+            }
+        }
     }
-    for (int q = threadIdx.x + 256 * PF; q < cnt; q += 256) acc += node(q, r[base + q], ssum);
     if (CG) {
         const double b = block_reduce<OpSum>(acc, slots);
         if (threadIdx.x == 0) it.part_rs[blockIdx.x] = b;
@@ -429,7 +453,6 @@ __global__ void __launch_bounds__(256) k_lr_inv(LowRankDev L, int y_chunk, const
         }
     }
 }
-
 
 // Fused flow inside FP64 CG: pass C folded into the operator apply.  The
 // tile kernel evaluates s = W r + correction itself on its tile and halo
@@ -787,7 +810,8 @@ uno_status lowrank_create(const Grid& g, const FftPlan& fp, int M, double W, con
     int rows = 1024 / L.n2;
     if (rows < 1) rows = 1;
     if (rows > L.n1) rows = L.n1;
-    p->ya = p->yc = rows;
+    p->ya = rows;
+    p->yc = rows < 256 ? rows : 256;  // pass C: at least one thread per row
     // pass A: a workgroup sums its rows' partial DFTs itself, so the row
     // chunks pass B gathers stay few: about 256 workgroups per right-hand
     // side, each taking its rows ya at a time
@@ -809,7 +833,7 @@ uno_status lowrank_create(const Grid& g, const FftPlan& fp, int M, double W, con
     while (p->cb_mid > 1 && sizeof(double2) * (size_t)p->cb_mid * (L.n0 + L.kxn) > 48 * 1024) p->cb_mid /= 2;
     p->blocks_mid = (L.kyn * L.kzn + p->cb_mid - 1) / p->cb_mid;
     p->lds_b = sizeof(double2) * (size_t)p->cb_mid * (L.n0 + L.kxn);
-    p->lds_c = sizeof(double2) * ((size_t)L.n2 + L.n1 + (size_t)plane + (size_t)p->yc * L.kzn);
+    p->lds_c = sizeof(double2) * ((size_t)plane + (size_t)p->yc * L.kzn);
     if (p->lds_a > 60 * 1024 || p->lds_b > 60 * 1024 || p->lds_c > 60 * 1024) { delete p; return UNO_ERR_SHAPE; }
     // fused operator tile: the apply's tile shape, 2-deep in x if 4 does not fit
     p->tile = choose_tile(g);
@@ -854,7 +878,26 @@ int lowrank_max_blocks(const LowRankPlan* p)
     return m;
 }
 bool lowrank_fused(const LowRankPlan* p) { return p->fused; }
-int lowrank_update_blocks(const LowRankPlan* p) { return p->blocks_a; }
+LrBatch lowrank_batch(const LowRankPlan* p, double2* Gp, double2* H, int nrhs)
+{
+    LrBatch b{Gp, H, nrhs, p->rb, p->nch_a};
+    // at least ~2048 workgroups of pass A per launch; no more chunks than the plan's
+    const int64_t per = (int64_t)p->dev.n0 * nrhs;
+    int nch = (int)((2048 + per - 1) / per);
+    if (nch < p->nch_a) {
+        if (nch < 1) nch = 1;
+        int rb = (p->dev.n1 + nch - 1) / nch;
+        rb = ((rb + p->ya - 1) / p->ya) * p->ya;
+        if (rb > p->dev.n1) rb = p->dev.n1;
+        b.rb = rb;
+        b.nch = (p->dev.n1 + rb - 1) / rb;
+    }
+    return b;
+}
+int lowrank_update_blocks(const LowRankPlan* p, int nrhs)
+{
+    return p->dev.n0 * lowrank_batch(p, nullptr, nullptr, nrhs).nch;
+}
 void lowrank_scratch_size(const LowRankPlan* p, int64_t* ngp, int64_t* nh)
 {
     *ngp = p->dev.gps;
@@ -868,7 +911,7 @@ static CgIter no_iter()
     return it;
 }
 
-static LrBatch own(const LowRankPlan* p) { return LrBatch{p->Gp, p->H, 1}; }
+static LrBatch own(const LowRankPlan* p) { return lowrank_batch(p, p->Gp, p->H, 1); }
 
 // pass A on r (no update); also the initial transform of the CG loop
 // (part_rr, nullable: ||r||^2 partials for the fused flow; `strides`: the
@@ -876,8 +919,8 @@ static LrBatch own(const LowRankPlan* p) { return LrBatch{p->Gp, p->H, 1}; }
 uno_status lowrank_forward(const LowRankPlan* p, const double* r, double* part_rr, const LrBatch& bt,
                            const CgIter& strides, hipStream_t st)
 {
-    uno_launch(UNO_KT_FFT_FWD, k_lr_fwd<false, double>, dim3(p->blocks_a, bt.nrhs), dim3(256), p->lds_a, st, p->dev,
-               p->ya, p->rb, (double*)r, (double*)nullptr, (const double*)nullptr, (const double*)nullptr, bt.Gp, strides,
+    uno_launch(UNO_KT_FFT_FWD, k_lr_fwd<false, double>, dim3(p->dev.n0 * bt.nch, bt.nrhs), dim3(256), p->lds_a, st,
+               p->dev, p->ya, bt.rb, (double*)r, (double*)nullptr, (const double*)nullptr, (const double*)nullptr, bt.Gp, strides,
                (const double*)nullptr, 0, (const double*)nullptr, (double*)nullptr, part_rr);
     return hip_status(hipGetLastError());
 }
@@ -888,8 +931,8 @@ uno_status lowrank_update_forward(const LowRankPlan* p, double* r, double* u, co
                                   const CgIter& it, const double* part_dp, int np_dp, const double* gam,
                                   double* part_rmax, double* part_rr, const LrBatch& bt, hipStream_t st)
 {
-    uno_launch(UNO_KT_UPDATE, k_lr_fwd<true, T>, dim3(p->blocks_a, bt.nrhs), dim3(256), p->lds_a, st, p->dev, p->ya,
-               p->rb, r, u, d, pv, bt.Gp, it, part_dp, np_dp, gam, part_rmax, part_rr);
+    uno_launch(UNO_KT_UPDATE, k_lr_fwd<true, T>, dim3(p->dev.n0 * bt.nch, bt.nrhs), dim3(256), p->lds_a, st, p->dev,
+               p->ya, bt.rb, r, u, d, pv, bt.Gp, it, part_dp, np_dp, gam, part_rmax, part_rr);
     return hip_status(hipGetLastError());
 }
 
@@ -938,10 +981,10 @@ uno_status lowrank_fused_pass(const LowRankPlan* p, const Grid& g, const double*
 {
     if (!p->fused) return UNO_ERR_SHAPE;
     const LowRankDev& L = p->dev;
-    uno_launch(UNO_KT_FFT_MID, k_lr_mid, dim3(p->blocks_mid, bt.nrhs), dim3(256), p->lds_b, st, L, p->nch_a,
+    uno_launch(UNO_KT_FFT_MID, k_lr_mid, dim3(p->blocks_mid, bt.nrhs), dim3(256), p->lds_b, st, L, bt.nch,
                p->cb_mid, (const double*)p->table, (const double2*)bt.Gp, bt.H, it, part_corr);
     UNO_HIP(hipGetLastError());
-    const LrTileArgs a{part_rr, p->blocks_a, part_corr, p->blocks_mid};
+    const LrTileArgs a{part_rr, p->dev.n0 * bt.nch, part_corr, p->blocks_mid};
     if (p->tile.tx == 1)
         launch_lr_tile_tx<1>(p, g.dev, kappa, r, dold, dnew, pv, part_dp, it, a, gam, bt, st);
     else if (p->tile.tx == 2)
@@ -960,7 +1003,7 @@ uno_status lowrank_finish(const LowRankPlan* p, const double* r, T* s, const CgI
 {
     const LowRankDev& L = p->dev;
     const CgIter it = itp ? *itp : no_iter();
-    uno_launch(UNO_KT_FFT_MID, k_lr_mid, dim3(p->blocks_mid, bt.nrhs), dim3(256), p->lds_b, st, L, p->nch_a,
+    uno_launch(UNO_KT_FFT_MID, k_lr_mid, dim3(p->blocks_mid, bt.nrhs), dim3(256), p->lds_b, st, L, bt.nch,
                p->cb_mid, (const double*)p->table, (const double2*)bt.Gp, bt.H, it, (double*)nullptr);
     UNO_HIP(hipGetLastError());
     if (itp)

@@ -138,17 +138,22 @@ struct CgState {
 // ---------------------------------------------------------------------------
 // UNO apply restricted to the learned modes (lowrank.hip)
 struct LowRankPlan;
-// row-chunk partials and H of nrhs right-hand sides (the plan's own for one)
+// row-chunk partials and H of nrhs right-hand sides (the plan's own for one),
+// and the row split of pass A for that many: rb rows per workgroup, nch
+// chunks per x-slab (fewer, longer chunks when many right-hand sides fill
+// the chip anyway; pass B then gathers less)
 struct LrBatch {
     double2* Gp;
     double2* H;
     int nrhs;
+    int rb, nch;
 };
 uno_status lowrank_create(const Grid& g, const FftPlan& fp, int M, double W, const std::vector<double>& cblock,
                           LowRankPlan** out);
 void lowrank_destroy(LowRankPlan* p);
 int lowrank_max_blocks(const LowRankPlan* p);
-int lowrank_update_blocks(const LowRankPlan* p);
+int lowrank_update_blocks(const LowRankPlan* p, int nrhs);
+LrBatch lowrank_batch(const LowRankPlan* p, double2* Gp, double2* H, int nrhs);
 void lowrank_scratch_size(const LowRankPlan* p, int64_t* ngp, int64_t* nh);
 uno_status lowrank_apply(const LowRankPlan* p, const double* r, double* s, hipStream_t st);
 uno_status lowrank_forward(const LowRankPlan* p, const double* r, double* part_rr, const LrBatch& bt,
