@@ -51,6 +51,13 @@ def _load():
     lib.orc_energy_average.restype = f64
     lib.orc_energy_density.argtypes = [i32, _ip, _dp, _dp, _dp, _dp, _dp, _dp]
     lib.orc_fft_nd.argtypes = [i32, _ip, _dp, i32]
+    lib.orc_el_element_matrix.argtypes = [_ip, _dp, f64, f64, _dp]
+    lib.orc_el_apply.argtypes = [_ip, _dp, _dp, _dp, _dp, _dp]
+    lib.orc_el_diag.argtypes = [_ip, _dp, _dp, _dp, _dp]
+    lib.orc_el_rhs.argtypes = [_ip, _dp, _dp, _dp, _dp, _dp]
+    lib.orc_el_stress_average.argtypes = [_ip, _dp, _dp, _dp, _dp, _dp, _dp]
+    lib.orc_el_pcg.argtypes = [_ip, _dp, _dp, _dp, _dp, _dp, i32, f64, i32]
+    lib.orc_el_pcg.restype = i32
     lib.orc_uno_num_weights.argtypes = [i32, i32]
     lib.orc_uno_num_weights.restype = ctypes.c_int64
     lib.orc_uno_table.argtypes = [i32, _ip, i32, _dp, _dp]
@@ -293,3 +300,76 @@ def train_closed_form(M, alpha, beta) -> np.ndarray:
     theta = np.zeros(num_weights(dim, M))
     lib.orc_train_closed_form(dim, n.ctypes.data_as(_ip), int(M), _ptr(alpha), _ptr(beta), _ptr(theta))
     return theta
+
+
+# ---- linear elasticity, d = 3, c = 3 (Sec. 5.2); fields planar (3, *grid) ----
+
+def lame(E, nu):
+    """Lame coefficients of an isotropic material from Young's modulus and Poisson's ratio."""
+    E = np.asarray(E, dtype=np.float64)
+    return E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu)), E / (2.0 * (1.0 + nu))
+
+
+def el_element_matrix(shape, lam, mu, L0=1.0, h=None):
+    lib = _load()
+    _, n, hh = _shape_args(shape, L0, h)
+    K = np.zeros((24, 24))
+    lib.orc_el_element_matrix(n.ctypes.data_as(_ip), _ptr(hh), float(lam), float(mu), _ptr(K))
+    return K
+
+
+def el_apply(lam, mu, u, L0=1.0, h=None):
+    lib = _load()
+    lam, mu, u = _f64(lam), _f64(mu), _f64(u)
+    _, n, hh = _shape_args(lam.shape, L0, h)
+    y = np.zeros_like(u)
+    lib.orc_el_apply(n.ctypes.data_as(_ip), _ptr(hh), _ptr(lam), _ptr(mu), _ptr(u), _ptr(y))
+    return y
+
+
+def el_diag(lam, mu, L0=1.0, h=None):
+    lib = _load()
+    lam, mu = _f64(lam), _f64(mu)
+    _, n, hh = _shape_args(lam.shape, L0, h)
+    dg = np.zeros((3,) + lam.shape)
+    lib.orc_el_diag(n.ctypes.data_as(_ip), _ptr(hh), _ptr(lam), _ptr(mu), _ptr(dg))
+    return dg
+
+
+def el_rhs(lam, mu, eps, L0=1.0, h=None):
+    lib = _load()
+    lam, mu = _f64(lam), _f64(mu)
+    _, n, hh = _shape_args(lam.shape, L0, h)
+    f = np.zeros((3,) + lam.shape)
+    lib.orc_el_rhs(n.ctypes.data_as(_ip), _ptr(hh), _ptr(lam), _ptr(mu), _ptr(_f64(eps)), _ptr(f))
+    return f
+
+
+def el_stress_average(lam, mu, eps, u, L0=1.0, h=None):
+    lib = _load()
+    lam, mu = _f64(lam), _f64(mu)
+    _, n, hh = _shape_args(lam.shape, L0, h)
+    out = np.zeros(6)
+    lib.orc_el_stress_average(n.ctypes.data_as(_ip), _ptr(hh), _ptr(lam), _ptr(mu), _ptr(_f64(eps)), _ptr(_f64(u)),
+                              _ptr(out))
+    return out
+
+
+def el_pcg(lam, mu, f, kind="jacobi", rtol=1e-10, max_iter=100000, L0=1.0, h=None):
+    """Algorithm 1 for the elastic operator; returns (u, passes)."""
+    lib = _load()
+    lam, mu, f = _f64(lam), _f64(mu), _f64(f)
+    _, n, hh = _shape_args(lam.shape, L0, h)
+    u = np.zeros_like(f)
+    it = lib.orc_el_pcg(n.ctypes.data_as(_ip), _ptr(hh), _ptr(lam), _ptr(mu), _ptr(f), _ptr(u),
+                        1 if kind == "jacobi" else 0, float(rtol), int(max_iter))
+    return u, int(it)
+
+
+def el_effective_stiffness(lam, mu, solutions, loads=None, L0=1.0, h=None):
+    """6 x 6 Mandel stiffness from the stress averages of the six unit Mandel
+    strain loads (column j = <D (eps_j + eps(u_j))>)."""
+    loads = np.eye(6) if loads is None else np.asarray(loads, dtype=np.float64)
+    S = np.stack([el_stress_average(lam, mu, e, u, L0, h) for e, u in zip(loads, solutions)], axis=1)
+    return S @ np.linalg.inv(loads.T)
+

@@ -690,3 +690,226 @@ void orc_train_closed_form(int dim, const int32_t *n, int M, const double *alpha
     }
     free(As); free(Bs); free(key); free(grp);
 }
+
+/* =====================================================================
+ * Linear elasticity, d = 3, c = 3 (Sec. 5.2): displacement fluctuation u
+ * with three components stored planar (u[c * n + node]); strain and stress
+ * in the Mandel basis (App. A: e1 e1, e2 e2, e3 e3, sqrt2 sym(e1 e2),
+ * sqrt2 sym(e1 e3), sqrt2 sym(e2 e3)); isotropic stiffness
+ * D = 3 lambda P1 + 2 mu I_sym, i.e. in Mandel form lambda 1 1^T on the
+ * normal block plus 2 mu I6.  Trilinear hex8 elements, 2-point Gauss rule
+ * per axis (exact), periodic grid.
+ * ===================================================================== */
+
+static const double ORC_SQ2 = 1.41421356237309504880;
+
+/* Mandel strain rows of the B matrix for corner a at point xi: strain =
+ * sum_a B_a u_a, B_a[k][c] (k Mandel index, c displacement component) */
+static void el_bmat(const orc_grid *g, int a, const double *xi, double B[6][3])
+{
+    double gr[3];
+    shape_grad(g, a, xi, gr);
+    memset(B, 0, sizeof(double) * 18);
+    B[0][0] = gr[0];
+    B[1][1] = gr[1];
+    B[2][2] = gr[2];
+    B[3][0] = gr[1] / ORC_SQ2; B[3][1] = gr[0] / ORC_SQ2;
+    B[4][0] = gr[2] / ORC_SQ2; B[4][2] = gr[0] / ORC_SQ2;
+    B[5][1] = gr[2] / ORC_SQ2; B[5][2] = gr[1] / ORC_SQ2;
+}
+
+static void el_dmat(double lam, double mu, double D[6][6])
+{
+    memset(D, 0, sizeof(double) * 36);
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) D[i][j] = lam;
+    for (int i = 0; i < 6; ++i) D[i][i] += 2.0 * mu;
+}
+
+/* element stiffness K[(a,c)][(b,e)] = int B_a^T D B_b, 24 x 24, index a*3+c */
+void orc_el_element_matrix(const int32_t *n, const double *h, double lam, double mu, double *K)
+{
+    orc_grid g = mk_grid(3, n, h);
+    double D[6][6];
+    el_dmat(lam, mu, D);
+    memset(K, 0, sizeof(double) * 576);
+    for (int q = 0; q < n_gauss(&g); ++q) {
+        double xi[3], w = gauss_point(&g, q, xi);
+        double B[8][6][3];
+        for (int a = 0; a < 8; ++a) el_bmat(&g, a, xi, B[a]);
+        for (int a = 0; a < 8; ++a)
+            for (int c = 0; c < 3; ++c)
+                for (int b = 0; b < 8; ++b)
+                    for (int e = 0; e < 3; ++e) {
+                        double v = 0.0;
+                        for (int k = 0; k < 6; ++k)
+                            for (int l = 0; l < 6; ++l) v += B[a][k][c] * D[k][l] * B[b][l][e];
+                        K[(a * 3 + c) * 24 + b * 3 + e] += w * v;
+                    }
+    }
+}
+
+/* y = A(lambda, mu) u by the element loop */
+void orc_el_apply(const int32_t *n, const double *h, const double *lam, const double *mu, const double *u,
+                  double *y)
+{
+    orc_grid g = mk_grid(3, n, h);
+    int64_t nn = grid_size(&g);
+    double K1[576], K2[576];
+    orc_el_element_matrix(n, h, 1.0, 0.0, K1); /* lambda part */
+    orc_el_element_matrix(n, h, 0.0, 1.0, K2); /* mu part */
+    memset(y, 0, sizeof(double) * 3 * nn);
+    for (int64_t le = 0; le < nn; ++le) {
+        int e[3];
+        unlin(&g, le, e);
+        int64_t nd[8];
+        for (int a = 0; a < 8; ++a) nd[a] = elem_node(&g, e, a);
+        for (int a = 0; a < 8; ++a)
+            for (int c = 0; c < 3; ++c) {
+                double acc = 0.0;
+                for (int b = 0; b < 8; ++b)
+                    for (int f = 0; f < 3; ++f) {
+                        int ij = (a * 3 + c) * 24 + b * 3 + f;
+                        acc += (lam[le] * K1[ij] + mu[le] * K2[ij]) * u[f * nn + nd[b]];
+                    }
+                y[c * nn + nd[a]] += acc;
+            }
+    }
+}
+
+/* assembled diagonal (3 per node) */
+void orc_el_diag(const int32_t *n, const double *h, const double *lam, const double *mu, double *dg)
+{
+    orc_grid g = mk_grid(3, n, h);
+    int64_t nn = grid_size(&g);
+    double K1[576], K2[576];
+    orc_el_element_matrix(n, h, 1.0, 0.0, K1);
+    orc_el_element_matrix(n, h, 0.0, 1.0, K2);
+    memset(dg, 0, sizeof(double) * 3 * nn);
+    for (int64_t le = 0; le < nn; ++le) {
+        int e[3];
+        unlin(&g, le, e);
+        for (int a = 0; a < 8; ++a)
+            for (int b = 0; b < 8; ++b) {
+                if (elem_node(&g, e, a) != elem_node(&g, e, b)) continue; /* coinciding nodes on 1-voxel axes */
+                for (int c = 0; c < 3; ++c) {
+                    int ij = (a * 3 + c) * 24 + b * 3 + c;
+                    dg[c * nn + elem_node(&g, e, a)] += lam[le] * K1[ij] + mu[le] * K2[ij];
+                }
+            }
+    }
+}
+
+/* f = -sum_e int B^T D eps_bar (macroscopic Mandel strain eps_bar) */
+void orc_el_rhs(const int32_t *n, const double *h, const double *lam, const double *mu, const double *eps,
+                double *f)
+{
+    orc_grid g = mk_grid(3, n, h);
+    int64_t nn = grid_size(&g);
+    memset(f, 0, sizeof(double) * 3 * nn);
+    for (int64_t le = 0; le < nn; ++le) {
+        int e[3];
+        unlin(&g, le, e);
+        double D[6][6], sig[6];
+        el_dmat(lam[le], mu[le], D);
+        for (int k = 0; k < 6; ++k) {
+            sig[k] = 0.0;
+            for (int l = 0; l < 6; ++l) sig[k] += D[k][l] * eps[l];
+        }
+        for (int q = 0; q < n_gauss(&g); ++q) {
+            double xi[3], w = gauss_point(&g, q, xi);
+            for (int a = 0; a < 8; ++a) {
+                double B[6][3];
+                el_bmat(&g, a, xi, B);
+                for (int c = 0; c < 3; ++c) {
+                    double v = 0.0;
+                    for (int k = 0; k < 6; ++k) v += B[k][c] * sig[k];
+                    f[c * nn + elem_node(&g, e, a)] -= w * v;
+                }
+            }
+        }
+    }
+}
+
+/* volume average of the Mandel stress D (eps_bar + B u) */
+void orc_el_stress_average(const int32_t *n, const double *h, const double *lam, const double *mu,
+                           const double *eps, const double *u, double *out)
+{
+    orc_grid g = mk_grid(3, n, h);
+    int64_t nn = grid_size(&g);
+    double vol = 1.0;
+    for (int b = 0; b < 3; ++b) vol *= g.n[b] * g.h[b];
+    for (int k = 0; k < 6; ++k) out[k] = 0.0;
+    for (int64_t le = 0; le < nn; ++le) {
+        int e[3];
+        unlin(&g, le, e);
+        double D[6][6];
+        el_dmat(lam[le], mu[le], D);
+        for (int q = 0; q < n_gauss(&g); ++q) {
+            double xi[3], w = gauss_point(&g, q, xi);
+            double st[6];
+            for (int k = 0; k < 6; ++k) st[k] = eps[k];
+            for (int a = 0; a < 8; ++a) {
+                double B[6][3];
+                el_bmat(&g, a, xi, B);
+                int64_t nd = elem_node(&g, e, a);
+                for (int k = 0; k < 6; ++k)
+                    for (int c = 0; c < 3; ++c) st[k] += B[k][c] * u[c * nn + nd];
+            }
+            for (int k = 0; k < 6; ++k) {
+                double v = 0.0;
+                for (int l = 0; l < 6; ++l) v += D[k][l] * st[l];
+                out[k] += w * v;
+            }
+        }
+    }
+    for (int k = 0; k < 6; ++k) out[k] /= vol;
+}
+
+/* Algorithm 1 for the elastic operator: P = none (kind 0) or Jacobi (1);
+ * relative infinity-norm stop as in orc_pcg; componentwise mean removal at
+ * the end.  Returns the loop passes. */
+int orc_el_pcg(const int32_t *n, const double *h, const double *lam, const double *mu, const double *f, double *u,
+               int kind, double rtol, int max_iter)
+{
+    orc_grid g = mk_grid(3, n, h);
+    int64_t nn = grid_size(&g), N = 3 * nn;
+    double *r = (double *)malloc(sizeof(double) * N), *s = (double *)malloc(sizeof(double) * N);
+    double *d = (double *)calloc(N, sizeof(double)), *p = (double *)malloc(sizeof(double) * N);
+    double *dg = (double *)malloc(sizeof(double) * N);
+    orc_el_diag(n, h, lam, mu, dg);
+    orc_el_apply(n, h, lam, mu, u, p);
+    for (int64_t i = 0; i < N; ++i) r[i] = f[i] - p[i];
+    double r0 = 0.0;
+    for (int64_t i = 0; i < N; ++i) r0 = fmax(r0, fabs(r[i]));
+    double g1 = 1.0;
+    int k = 0;
+    for (;;) {
+        double rm = 0.0;
+        for (int64_t i = 0; i < N; ++i) rm = fmax(rm, fabs(r[i]));
+        if (!(rm > rtol * r0) || k >= max_iter) break;
+        for (int64_t i = 0; i < N; ++i) s[i] = kind == 1 ? r[i] / dg[i] : r[i];
+        double g0 = g1;
+        g1 = 0.0;
+        for (int64_t i = 0; i < N; ++i) g1 += r[i] * s[i];
+        double beta = (k == 0) ? 0.0 : g1 / g0;
+        for (int64_t i = 0; i < N; ++i) d[i] = s[i] + beta * d[i];
+        orc_el_apply(n, h, lam, mu, d, p);
+        double dp = 0.0;
+        for (int64_t i = 0; i < N; ++i) dp += d[i] * p[i];
+        double alpha = g1 / dp;
+        for (int64_t i = 0; i < N; ++i) {
+            r[i] -= alpha * p[i];
+            u[i] += alpha * d[i];
+        }
+        ++k;
+    }
+    for (int c = 0; c < 3; ++c) {
+        double m = 0.0;
+        for (int64_t i = 0; i < nn; ++i) m += u[c * nn + i];
+        m /= (double)nn;
+        for (int64_t i = 0; i < nn; ++i) u[c * nn + i] -= m;
+    }
+    free(r); free(s); free(d); free(p); free(dg);
+    return k;
+}
