@@ -215,6 +215,40 @@ uno_status effective_tensor(const uno_grid *grid, const uno_material *mat, int32
 uno_status effective_tensor_grad(const uno_grid *grid, int32_t nload, const double *loads, const double *u,
                                  const double *weights, double *out, void *stream);
 
+/* ---- Linear elasticity, d = 3, three nodal DOF (Sec. 5.2) ------------ */
+/* Periodic voxel grid (grid->dim = 3, every n >= 2), trilinear hex8
+ * elements, isotropic stiffness D = 3 lambda P1 + 2 mu I_sym per voxel
+ * (lambda, mu: device, n doubles each, voxel e = lower corner node e).
+ * Displacements are planar, component c of node i at u[c n + i] (3n
+ * doubles); strains and stresses use the Mandel basis of App. A
+ * (e1 e1, e2 e2, e3 e3, sqrt2 sym(e1 e2), sqrt2 sym(e1 e3), sqrt2 sym(e2 e3)).
+ *
+ * y = A(lambda, mu) u, the assembled stiffness applied matrix-free (Sec.
+ * 3.1).  u must not alias y.  Asynchronous. */
+uno_status el_apply(const uno_grid *grid, const double *lambda, const double *mu, const double *u, double *y,
+                    void *stream);
+/* f = -sum_e int_e B^T D eps_bar, the load of the fluctuation problem for
+ * the macroscopic Mandel strain eps_bar (host, 6 values), eq.
+ * (mechanical-decomposition).  Asynchronous. */
+uno_status el_macro_rhs(const uno_grid *grid, const double *lambda, const double *mu, const double *strain,
+                        double *f, void *stream);
+/* nrhs solves for the macroscopic strains (host, nrhs x 6) carried by every
+ * CG pass kernel (Algorithm 1 with P = none or the Jacobi diagonal; FP64
+ * only: opts->kind UNO_PREC_NONE or UNO_PREC_JACOBI, op_t = prec_t =
+ * UNO_F64).  lame_per_rhs = 0: one (lambda, mu) field pair for all loads;
+ * 1: nrhs pairs, pair j at + n j.  u (device, nrhs x 3n) holds the initial
+ * guesses and receives the zero-mean fluctuations; info (host, nullable)
+ * nrhs records.  1 <= nrhs <= 64.  Synchronous. */
+uno_status el_pcg_solve(const uno_grid *grid, const double *lambda, const double *mu, int32_t lame_per_rhs,
+                        int32_t nrhs, const double *strains, double *u, const uno_solve_opts *opts,
+                        uno_solve_info *info, void *stream);
+/* Effective stiffness (host out, 6 x 6 row-major, Mandel): column j of
+ * S = <D (eps_j + eps(u_j))> for the six loads eps_j (host, 6 x 6, rows)
+ * with solutions u (device, 6 x 3n), and out = S L^-T with L the loads as
+ * columns (invertible).  Synchronous. */
+uno_status el_effective_stiffness(const uno_grid *grid, const double *lambda, const double *mu, int32_t nload,
+                                  const double *strains, const double *u, double *out, void *stream);
+
 /* ---- Second-order training of the weights (Sec. 4.4, c = 1) ---------- */
 /* Accumulates the features of eq. (features-c-1) over ns samples:
  *   alpha(k) += (1/ns_total) |f^(k)|^2, beta(k) += (2/ns_total) Re(conj(f^) u^)

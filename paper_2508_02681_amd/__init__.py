@@ -83,6 +83,10 @@ def lib():
         "pcg_solve_batch": ([G, Mt, i32, i32, P(f64), vp, vp, P(uno_solve_opts), P(uno_solve_info), vp], i),
         "effective_tensor": ([G, Mt, i32, P(f64), vp, P(f64), vp], i),
         "effective_tensor_grad": ([G, i32, P(f64), vp, P(f64), vp, vp], i),
+        "el_apply": ([G, vp, vp, vp, vp, vp], i),
+        "el_macro_rhs": ([G, vp, vp, P(f64), vp, vp], i),
+        "el_pcg_solve": ([G, vp, vp, i32, i32, P(f64), vp, P(uno_solve_opts), P(uno_solve_info), vp], i),
+        "el_effective_stiffness": ([G, vp, vp, i32, P(f64), vp, P(f64), vp], i),
         "uno_train_accumulate": ([G, i32, vp, vp, f64, vp, vp, vp], i),
         "uno_train_fit": ([G, i32, vp, vp, P(f64), i64, vp], i),
         "uno_train_loss_grad": ([G, i32, vp, vp, P(f64), i64, P(f64), P(f64), vp], i),
@@ -421,6 +425,62 @@ class UnoTrainLoss(torch.autograd.Function):
     def backward(ctx, g):
         (grad,) = ctx.saved_tensors
         return g * grad, None, None, None, None
+
+
+# ---- linear elasticity, d = 3, c = 3: displacements (3, *grid) per load ----
+
+def _dptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def el_apply(lam: torch.Tensor, mu: torch.Tensor, u: torch.Tensor, y: torch.Tensor | None = None, L0=1.0):
+    """y = A(lambda, mu) u (u, y: 3 x grid)."""
+    g = make_grid(tuple(lam.shape), L0)
+    if y is None:
+        y = torch.empty_like(u)
+    _check(lib().el_apply(ctypes.byref(g), _dev(lam, "lambda", torch.float64), _dev(mu, "mu", torch.float64),
+                          _dev(u, "u", torch.float64), _dev(y, "y", torch.float64), _stream()), "el_apply")
+    return y
+
+
+def el_macro_rhs(lam: torch.Tensor, mu: torch.Tensor, strain, L0=1.0):
+    g = make_grid(tuple(lam.shape), L0)
+    f = torch.empty((3,) + tuple(lam.shape), dtype=torch.float64, device=lam.device)
+    e = np.ascontiguousarray(strain, dtype=np.float64).reshape(6)
+    _check(lib().el_macro_rhs(ctypes.byref(g), _dev(lam, "lambda", torch.float64), _dev(mu, "mu", torch.float64),
+                              _dptr(e), _dev(f, "f", torch.float64), _stream()), "el_macro_rhs")
+    return f
+
+
+def el_pcg_solve(lam: torch.Tensor, mu: torch.Tensor, strains, u: torch.Tensor | None = None, kind="jacobi",
+                 rtol=1e-6, max_iter=100000, graph_chunk=0, lame_per_rhs=False, L0=1.0):
+    """Jacobi-CG (or CG) for nrhs macroscopic Mandel strains (nrhs x 6).
+    lam, mu: grid (shared) or nrhs x grid (lame_per_rhs).  Returns
+    (u (nrhs x 3 x grid), [info])."""
+    shape = tuple(lam.shape[1:]) if lame_per_rhs else tuple(lam.shape)
+    g = make_grid(shape, L0)
+    e = np.ascontiguousarray(strains, dtype=np.float64).reshape(-1, 6)
+    nrhs = e.shape[0]
+    if u is None:
+        u = torch.zeros((nrhs, 3) + shape, dtype=torch.float64, device=lam.device)
+    o = _opts(kind, None, rtol, max_iter, torch.float64, torch.float64, graph_chunk)
+    infos = (uno_solve_info * nrhs)()
+    _check(lib().el_pcg_solve(ctypes.byref(g), _dev(lam, "lambda", torch.float64), _dev(mu, "mu", torch.float64),
+                              1 if lame_per_rhs else 0, nrhs, _dptr(e), _dev(u, "u", torch.float64), ctypes.byref(o),
+                              infos, _stream()), "el_pcg_solve")
+    return u, [dict(iters=I.iters, converged=bool(I.converged), rel_res=I.rel_res, true_rel_res=I.true_rel_res,
+                    r0_norm=I.r0_norm) for I in infos]
+
+
+def el_effective_stiffness(lam: torch.Tensor, mu: torch.Tensor, strains, u: torch.Tensor, L0=1.0) -> np.ndarray:
+    """6 x 6 Mandel effective stiffness from the six loads' solutions u (6 x 3 x grid)."""
+    g = make_grid(tuple(lam.shape), L0)
+    e = np.ascontiguousarray(strains, dtype=np.float64).reshape(6, 6)
+    out = np.zeros((6, 6))
+    _check(lib().el_effective_stiffness(ctypes.byref(g), _dev(lam, "lambda", torch.float64),
+                                        _dev(mu, "mu", torch.float64), 6, _dptr(e), _dev(u, "u", torch.float64),
+                                        _dptr(out), _stream()), "el_effective_stiffness")
+    return out
 
 
 def half_shape(shape):

@@ -10,12 +10,15 @@
 
 #include "unocg_internal.h"
 #include "reduce.h"
+#include "cg_ctl.h"
 
 namespace unocg {
 
 uno_status ws_release_all();
 uno_status pcg_run(const Grid& g, const double* kappa, const double* macro_load3, const double* rhs, double* u,
                    const uno_solve_opts* o, uno_solve_info* info, double* res_hist, hipStream_t st);
+uno_status pcg_run_el(const Grid& g, const double* lam, const double* mu, int64_t lks, int nrhs, const double* eps6,
+                      double* u, const uno_solve_opts* o, uno_solve_info* info, hipStream_t st);
 uno_status pcg_run_batch(const Grid& g, const double* kappa, int64_t ks, int nrhs, const double* macro_loads3,
                          const double* rhs, double* u, const uno_solve_opts* o, uno_solve_info* info, double* res_hist,
                          hipStream_t st);
@@ -511,6 +514,112 @@ uno_status pcg_solve_batch(const uno_grid* grid, const uno_material* mat, int32_
                          macro_loads ? g3.data() : nullptr, rhs, u, opts, info, nullptr, S(stream));
 }
 
+// ---- linear elasticity, c = 3 ----
+
+static uno_status el_grid(const uno_grid* grid, Grid* g)
+{
+    uno_status e = make_grid(grid, g);
+    if (e != UNO_OK) return e;
+    if (grid->dim != 3) return UNO_ERR_SHAPE;
+    for (int b = 0; b < 3; ++b)
+        if (g->n[b] < 2) return UNO_ERR_SHAPE;
+    return UNO_OK;
+}
+
+uno_status el_apply(const uno_grid* grid, const double* lambda, const double* mu, const double* u, double* y,
+                    void* stream)
+{
+    Grid g;
+    uno_status e = el_grid(grid, &g);
+    if (e != UNO_OK) return e;
+    if (!lambda || !mu || !u || !y || u == y) return UNO_ERR_ARG;
+    ElDev E;
+    e = el_dev(g, &E);
+    if (e != UNO_OK) return e;
+    CgIter none;
+    memset(&none, 0, sizeof(none));
+    return launch_el_apply<false, false>(E, g, lambda, mu, 0, u, nullptr, nullptr, y, nullptr, none, nullptr, 0,
+                                         nullptr, 1, S(stream));
+}
+
+uno_status el_macro_rhs(const uno_grid* grid, const double* lambda, const double* mu, const double* strain, double* f,
+                        void* stream)
+{
+    Grid g;
+    uno_status e = el_grid(grid, &g);
+    if (e != UNO_OK) return e;
+    if (!lambda || !mu || !strain || !f) return UNO_ERR_ARG;
+    for (int k = 0; k < 6; ++k)
+        if (!std::isfinite(strain[k])) return UNO_ERR_ARG;
+    ElDev E;
+    e = el_dev(g, &E);
+    if (e != UNO_OK) return e;
+    return launch_el_rhs(E, g, lambda, mu, strain, f, S(stream));
+}
+
+uno_status el_pcg_solve(const uno_grid* grid, const double* lambda, const double* mu, int32_t lame_per_rhs,
+                        int32_t nrhs, const double* strains, double* u, const uno_solve_opts* opts,
+                        uno_solve_info* info, void* stream)
+{
+    Grid g;
+    uno_status e = el_grid(grid, &g);
+    if (e != UNO_OK) return e;
+    if (!lambda || !mu || !strains || !u || !opts) return UNO_ERR_ARG;
+    if (nrhs < 1 || nrhs > 64 || (lame_per_rhs != 0 && lame_per_rhs != 1)) return UNO_ERR_ARG;
+    if (!(opts->rtol >= 0.0) || opts->max_iter < 1) return UNO_ERR_ARG;
+    for (int k = 0; k < 6 * nrhs; ++k)
+        if (!std::isfinite(strains[k])) return UNO_ERR_ARG;
+    return pcg_run_el(g, lambda, mu, lame_per_rhs ? g.total : 0, nrhs, strains, u, opts, info, S(stream));
+}
+
+uno_status el_effective_stiffness(const uno_grid* grid, const double* lambda, const double* mu, int32_t nload,
+                                  const double* strains, const double* u, double* out, void* stream)
+{
+    Grid g;
+    uno_status e = el_grid(grid, &g);
+    if (e != UNO_OK) return e;
+    if (!lambda || !mu || !strains || !u || !out || nload != 6) return UNO_ERR_ARG;
+    ElDev E;
+    e = el_dev(g, &E);
+    if (e != UNO_OK) return e;
+    // S[:, j] = <D (eps_j + eps(u_j))>; stiffness = S L^-T with L the 6 x 6 load rows
+    double Sm[6][6], L[6][6], Li[6][6];
+    for (int j = 0; j < 6; ++j) {
+        double col[6];
+        e = el_stress_average(E, g, lambda, mu, strains + 6 * j, u + (int64_t)j * 3 * g.total, col, S(stream));
+        if (e != UNO_OK) return e;
+        for (int k = 0; k < 6; ++k) Sm[k][j] = col[k];
+        for (int k = 0; k < 6; ++k) L[k][j] = strains[6 * j + k];  // columns are the loads
+    }
+    // Gauss-Jordan inverse of L
+    double m[6][12];
+    for (int i = 0; i < 6; ++i)
+        for (int j = 0; j < 12; ++j) m[i][j] = j < 6 ? L[i][j] : (j - 6 == i ? 1.0 : 0.0);
+    for (int c = 0; c < 6; ++c) {
+        int piv = c;
+        for (int i = c + 1; i < 6; ++i)
+            if (std::fabs(m[i][c]) > std::fabs(m[piv][c])) piv = i;
+        if (!(std::fabs(m[piv][c]) > 1e-300)) return UNO_ERR_ARG;
+        for (int j = 0; j < 12; ++j) std::swap(m[c][j], m[piv][j]);
+        const double pv = m[c][c];
+        for (int j = 0; j < 12; ++j) m[c][j] /= pv;
+        for (int i = 0; i < 6; ++i) {
+            if (i == c) continue;
+            const double f = m[i][c];
+            for (int j = 0; j < 12; ++j) m[i][j] -= f * m[c][j];
+        }
+    }
+    for (int i = 0; i < 6; ++i)
+        for (int j = 0; j < 6; ++j) Li[i][j] = m[i][j + 6];
+    for (int i = 0; i < 6; ++i)
+        for (int j = 0; j < 6; ++j) {
+            double a = 0.0;
+            for (int k = 0; k < 6; ++k) a += Sm[i][k] * Li[k][j];
+            out[i * 6 + j] = a;
+        }
+    return UNO_OK;
+}
+
 uno_status effective_tensor(const uno_grid* grid, const uno_material* mat, int32_t nload, const double* loads,
                             const double* u, double* out, void* stream)
 {
@@ -619,6 +728,7 @@ uno_status uno_shutdown(void)
         for (hipEvent_t e : g_tpool) (void)hipEventDestroy(e);
         g_tpool.clear();
     }
+    el_release_all();
     return ws_release_all();
 }
 

@@ -784,6 +784,160 @@ uno_status pcg_run_batch(const Grid& g, const double* kappa, int64_t ks, int nrh
     return failed ? UNO_ERR_BREAKDOWN : UNO_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Linear elasticity (c = 3, Sec. 5.2): Jacobi-CG or plain CG on the planar
+// 3n-vectors, nrhs macroscopic strains carried by every pass kernel.  The
+// update and init kernels run on the 3n-vector as on a scalar field; the
+// operator is the elastic gather (it tests convergence at the head of the
+// pass).  lks: stride of the Lame fields per right-hand side (0 if shared).
+uno_status pcg_run_el(const Grid& g, const double* lam, const double* mu, int64_t lks, int nrhs, const double* eps6,
+                      double* u, const uno_solve_opts* o, uno_solve_info* info, hipStream_t st)
+{
+    if (o->kind != UNO_PREC_NONE && o->kind != UNO_PREC_JACOBI) return UNO_ERR_ARG;
+    if (o->op_t != UNO_F64 || o->prec_t != UNO_F64) return UNO_ERR_ARG;
+    ElDev E;
+    uno_status e = el_dev(g, &E);
+    if (e != UNO_OK) return e;
+    const int64_t n = g.total, N = 3 * n;
+    Grid gv = g;  // workspace of 3n-vectors, keyed apart from the scalar problems
+    gv.n[0] = 3 * g.n[0];
+    gv.total = N;
+    GridDev gd = g.dev;
+    gd.n = N;
+    Workspace* w = nullptr;
+    const int hist_len = o->max_iter + 1;
+    e = ws_get(gv, nullptr, nullptr, el_blocks(g), hist_len, nrhs, &w);
+    if (e != UNO_OK) return e;
+    const int nb = w->nbr;
+    const Parts P = parts_of(w);
+    const int64_t dks = lks ? N : 0;  // Jacobi diagonals follow the Lame fields
+    for (int b = 0; b < nrhs; ++b) {
+        double* fb = w->f + b * N;
+        e = launch_el_rhs(E, g, lam + b * lks, mu + b * lks, eps6 + 6 * b, fb, st);
+        if (e != UNO_OK) return e;
+        CgIter none;
+        memset(&none, 0, sizeof(none));
+        e = launch_el_apply<false, false>(E, g, lam + b * lks, mu + b * lks, 0, u + b * N, nullptr, nullptr,
+                                          w->p + b * N, nullptr, none, nullptr, 0, nullptr, 1, st);
+        if (e != UNO_OK) return e;
+        hipLaunchKernelGGL(k_sub, dim3(nb), dim3(kBlock), 0, st, N, (const double*)fb, (const double*)(w->p + b * N),
+                           w->r + b * N);
+        // f and r_0 sum to zero per component in exact arithmetic (the
+        // translations span the kernel of A); the rounding residue of those
+        // sums lies outside the range of A and would stall CG once the
+        // consistent part is resolved, so it is removed here
+        double* pd = P.dp + (int64_t)b * w->npart;
+        for (int c = 0; c < 3; ++c)
+            for (double* v : {fb + c * n, w->r + b * N + c * n}) {
+                hipLaunchKernelGGL(k_sum_parts, dim3(nb), dim3(kBlock), 0, st, n, (const double*)v, pd);
+                hipLaunchKernelGGL(k_sub_mean, dim3(nb), dim3(kBlock), 0, st, n, v, (const double*)pd, nb,
+                                   w->state + b);
+            }
+    }
+    if (o->kind == UNO_PREC_JACOBI) {
+        e = launch_el_inv_diag(E, g, lam, mu, lks, lks ? nrhs : 1, w->dinv, st);
+        if (e != UNO_OK) return e;
+    }
+    const dim3 grid(nb, nrhs);
+    if (o->kind == UNO_PREC_JACOBI)
+        hipLaunchKernelGGL((k_cg_init<double, 1>), grid, dim3(kBlock), 0, st, gd, (const double*)w->dinv,
+                           (const double*)w->r, w->s, P.rmax, P.rs[0], P.ss[0], w->state, w->npart, dks);
+    else
+        hipLaunchKernelGGL((k_cg_init<double, 0>), grid, dim3(kBlock), 0, st, gd, (const double*)w->dinv,
+                           (const double*)w->r, w->s, P.rmax, P.rs[0], P.ss[0], w->state, w->npart, dks);
+    UNO_HIP(hipGetLastError());
+    int k = 0;
+    int chunk = o->graph_chunk > 0 ? o->graph_chunk : 8;
+    std::vector<int> prev_k(nrhs, -1);
+    std::vector<double> prev_r(nrhs, -1.0);
+    for (;;) {
+        if (chunk > o->max_iter - k) chunk = o->max_iter - k;
+        for (int c = 0; c < chunk; ++c, ++k) {
+            CgIter it = iter_of(w, P, k, 0, o->rtol, hist_len, nb, dks);
+            double* dold = w->d[k & 1];
+            double* dnew = w->d[(k + 1) & 1];
+            e = launch_el_apply<true, true>(E, g, lam, mu, lks, w->s, dold, dnew, w->p, P.dp, it, P.rs[k & 1], nb,
+                                            w->gam, nrhs, st);
+            if (e != UNO_OK) return e;
+            const int np_dp = el_blocks(g);
+            double* rs_next = P.rs[(k + 1) & 1];
+            double* ss_next = P.ss[(k + 1) & 1];
+            if (o->kind == UNO_PREC_JACOBI)
+                uno_launch(UNO_KT_UPDATE, k_cg_update<double, 1>, grid, dim3(kBlock), 0, st, gd,
+                           (const double*)w->dinv, w->r, u, (const double*)dnew, (const double*)w->p, w->s, it,
+                           (const double*)P.dp, np_dp, (const double*)w->gam, P.rmax, rs_next, ss_next);
+            else
+                uno_launch(UNO_KT_UPDATE, k_cg_update<double, 0>, grid, dim3(kBlock), 0, st, gd,
+                           (const double*)w->dinv, w->r, u, (const double*)dnew, (const double*)w->p, w->s, it,
+                           (const double*)P.dp, np_dp, (const double*)w->gam, P.rmax, rs_next, ss_next);
+            UNO_HIP(hipGetLastError());
+        }
+        CgIter it = iter_of(w, P, k, 0, o->rtol, hist_len, nb, dks);
+        hipLaunchKernelGGL(k_cg_check, dim3(1, nrhs), dim3(kBlock), 0, st, it);
+        UNO_HIP(hipGetLastError());
+        UNO_HIP(hipMemcpyAsync(w->host_state, w->state, sizeof(CgState) * nrhs, hipMemcpyDeviceToHost, st));
+        UNO_HIP(hipStreamSynchronize(st));
+        bool running = false;
+        int next = 4;
+        for (int b = 0; b < nrhs; ++b) {
+            const CgState& hs = w->host_state[b];
+            if (hs.status != 0 || hs.done != INT_MAX) continue;
+            running = true;
+            int nx = 16;
+            if (prev_r[b] > 0.0 && hs.rmax_last > 0.0 && hs.k_last > prev_k[b] && hs.rmax_last < prev_r[b]) {
+                const double rate = std::pow(hs.rmax_last / prev_r[b], 1.0 / (hs.k_last - prev_k[b]));
+                nx = (int)std::ceil(std::log(hs.tol_abs / hs.rmax_last) / std::log(rate) * 1.05) + 1;
+            }
+            if (nx > next) next = nx;
+        }
+        if (!running || k >= o->max_iter) break;
+        if (o->graph_chunk <= 0) chunk = next < 4 ? 4 : (next > 256 ? 256 : next);
+        for (int b = 0; b < nrhs; ++b) {
+            prev_k[b] = w->host_state[b].k_last;
+            prev_r[b] = w->host_state[b].rmax_last;
+        }
+    }
+    std::vector<CgState> hs(w->host_state, w->host_state + nrhs);
+    // zero-mean components and the true residual in FP64
+    for (int b = 0; b < nrhs; ++b) {
+        double* pd = P.dp + (int64_t)b * w->npart;
+        for (int c = 0; c < 3; ++c) {
+            double* uc = u + b * N + c * n;
+            hipLaunchKernelGGL(k_sum_parts, dim3(nb), dim3(kBlock), 0, st, n, (const double*)uc, pd);
+            hipLaunchKernelGGL(k_sub_mean, dim3(nb), dim3(kBlock), 0, st, n, uc, (const double*)pd, nb, w->state + b);
+        }
+        CgIter none;
+        memset(&none, 0, sizeof(none));
+        e = launch_el_apply<false, false>(E, g, lam + b * lks, mu + b * lks, 0, u + b * N, nullptr, nullptr,
+                                          w->p + b * N, nullptr, none, nullptr, 0, nullptr, 1, st);
+        if (e != UNO_OK) return e;
+        double* pa = P.rs[0] + (int64_t)b * w->npart;
+        double* pb = P.rs[1] + (int64_t)b * w->npart;
+        hipLaunchKernelGGL(k_resid_parts, dim3(nb), dim3(kBlock), 0, st, N, (const double*)(w->f + b * N),
+                           (const double*)(w->p + b * N), pa, pb);
+        hipLaunchKernelGGL(k_resid_final, dim3(1), dim3(kBlock), 0, st, (const double*)pa, (const double*)pb, nb,
+                           w->state + b);
+        UNO_HIP(hipGetLastError());
+    }
+    UNO_HIP(hipMemcpyAsync(w->host_state, w->state, sizeof(CgState) * nrhs, hipMemcpyDeviceToHost, st));
+    UNO_HIP(hipStreamSynchronize(st));
+    bool failed = false;
+    for (int b = 0; b < nrhs; ++b) {
+        const CgState& h = hs[b];
+        const CgState& fin = w->host_state[b];
+        if (h.status != 0) failed = true;
+        if (info) {
+            uno_solve_info& I = info[b];
+            I.iters = (h.done != INT_MAX) ? h.done : (h.status != 0 ? h.fail_iter : k);
+            I.converged = (h.status == 0 && h.done != INT_MAX) ? 1 : 0;
+            I.rel_res = h.r0max > 0.0 ? h.rmax_last / h.r0max : 0.0;
+            I.true_rel_res = fin.fmax > 0.0 ? fin.dmax / fin.fmax : 0.0;
+            I.r0_norm = h.r0max;
+        }
+    }
+    return failed ? UNO_ERR_BREAKDOWN : UNO_OK;
+}
+
 uno_status pcg_run(const Grid& g, const double* kappa, const double* macro_load3, const double* rhs, double* u,
                    const uno_solve_opts* o, uno_solve_info* info, double* res_hist, hipStream_t st)
 {

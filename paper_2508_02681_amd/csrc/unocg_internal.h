@@ -172,6 +172,27 @@ uno_status lowrank_finish(const LowRankPlan* p, const double* r, T* s, const CgI
                           const LrBatch& bt, hipStream_t st);
 int fft_c2r_blocks(const Grid& g, const FftPlan& p);
 
+// linear elasticity, c = 3 (elastic.hip)
+struct ElDev {
+    GridDev g;
+    double hvol;
+    double gc[3];        // centre gradient factor per axis 1 / (4 h_b)
+    const double* K;     // 2 x 576 unit element matrices (device)
+};
+uno_status el_dev(const Grid& g, ElDev* out);
+void el_release_all();
+int el_blocks(const Grid& g);
+template <bool CG, bool HEAD>
+uno_status launch_el_apply(const ElDev& E, const Grid& g, const double* lam, const double* mu, int64_t lks,
+                           const double* s, const double* dold, double* dnew, double* p, double* part_dp,
+                           const CgIter& it, const double* part_rs, int np_rs, double* gam, int nrhs, hipStream_t st);
+uno_status launch_el_inv_diag(const ElDev& E, const Grid& g, const double* lam, const double* mu, int64_t ks,
+                              int nfields, double* dinv, hipStream_t st);
+uno_status launch_el_rhs(const ElDev& E, const Grid& g, const double* lam, const double* mu, const double* eps,
+                         double* f, hipStream_t st);
+uno_status el_stress_average(const ElDev& E, const Grid& g, const double* lam, const double* mu, const double* eps,
+                             const double* u, double* out, hipStream_t st);
+
 }  // namespace unocg
 
 // uno_precond layout (opaque to callers)

@@ -1,0 +1,90 @@
+"""GPU: 3D linear elasticity (c = 3) — operator apply, rhs, Jacobi-CG with
+six Mandel loads carried together, effective stiffness — against the FP64
+oracle on the same seeded inputs."""
+import numpy as np
+import pytest
+import torch
+
+import synth_inputs as si
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+@pytest.fixture(scope="module")
+def uno():
+    import paper_2508_02681_amd as u
+    u.lib()
+    assert torch.cuda.is_available()
+    return u
+
+
+def T(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def _lame(orc, shape, seed, contrast=100.0):
+    ph, _ = si.rsa_inclusions(shape, 1 if min(shape) < 10 else 2, 2 if min(shape) < 10 else 4, 0.3, seed)
+    E = si.two_phase_kappa(ph, 1.0, contrast)
+    return orc.lame(E, 0.3)
+
+
+@pytest.mark.parametrize("shape", [(4, 5, 6), (8, 8, 8), (2, 3, 7), (13, 9, 11)])
+def test_el_apply_and_rhs_match_oracle(orc, uno, shape):
+    lam, mu = _lame(orc, shape, 80)
+    rng = np.random.default_rng(81)
+    u = rng.standard_normal((3,) + shape)
+    y = uno.el_apply(T(lam), T(mu), T(u)).cpu().numpy()
+    yo = orc.el_apply(lam, mu, u)
+    assert rel(y, yo) < 1e-12
+    eps = rng.standard_normal(6)
+    f = uno.el_macro_rhs(T(lam), T(mu), eps).cpu().numpy()
+    assert rel(f, orc.el_rhs(lam, mu, eps)) < 1e-12
+
+
+@pytest.mark.parametrize("shape", [(6, 6, 6), (10, 8, 12)])
+def test_el_jacobi_cg_and_stiffness_match_oracle(orc, uno, shape):
+    lam, mu = _lame(orc, shape, 82, 20.0)
+    loads = np.eye(6)
+    u, infos = uno.el_pcg_solve(T(lam), T(mu), loads, kind="jacobi", rtol=1e-12)
+    assert all(i["converged"] for i in infos)
+    sols = [orc.el_pcg(lam, mu, orc.el_rhs(lam, mu, loads[j]), "jacobi", rtol=1e-12) for j in range(6)]
+    for j in range(6):
+        assert rel(u[j].cpu().numpy(), sols[j][0]) < 1e-8
+        # the pass that first meets 1e-12 moves with the summation order near
+        # the rounding floor; the same 3 % band as the scalar solves
+        assert abs(infos[j]["iters"] - sols[j][1]) <= max(1, int(0.03 * sols[j][1]))
+    Db = uno.el_effective_stiffness(T(lam), T(mu), loads, u)
+    Do = orc.el_effective_stiffness(lam, mu, [s[0] for s in sols])
+    assert rel(Db, Do) < 1e-8
+
+
+def test_el_batch_equals_single_and_per_rhs_fields(orc, uno):
+    shape = (8, 6, 10)
+    fields = [_lame(orc, shape, 83 + i) for i in range(2)]
+    loads = np.array([[1, 0, 0, 0, 0, 0], [0, 0, 0, 1, 0, 0], [0.2, 0.3, -0.1, 0, 0.5, 0]], dtype=float)
+    lam_all = torch.stack([T(fields[j % 2][0]) for j in range(3)])
+    mu_all = torch.stack([T(fields[j % 2][1]) for j in range(3)])
+    ub, infos = uno.el_pcg_solve(lam_all, mu_all, loads, rtol=1e-9, lame_per_rhs=True)
+    for j in range(3):
+        us, info = uno.el_pcg_solve(lam_all[j], mu_all[j], loads[j:j + 1], rtol=1e-9)
+        assert infos[j]["iters"] == info[0]["iters"]
+        assert torch.equal(ub[j], us[0])
+
+
+def test_el_homogeneous_and_errors(uno):
+    shape = (6, 6, 6)
+    lam, mu = torch.full(shape, 2.0, dtype=torch.float64, device=DEV), torch.full(shape, 1.0, dtype=torch.float64,
+                                                                                    device=DEV)
+    u, infos = uno.el_pcg_solve(lam, mu, np.eye(6), rtol=1e-10)
+    assert all(i["converged"] for i in infos)
+    D = np.zeros((6, 6)); D[:3, :3] = 2.0; D += 2.0 * np.eye(6)
+    assert np.abs(uno.el_effective_stiffness(lam, mu, np.eye(6), u) - D).max() < 1e-12
+    with pytest.raises(uno.UnoError):
+        uno.el_apply(lam[:1], mu[:1], torch.zeros((3, 1, 6, 6), dtype=torch.float64, device=DEV))
