@@ -56,7 +56,15 @@ def _load():
     lib.orc_el_diag.argtypes = [_ip, _dp, _dp, _dp, _dp]
     lib.orc_el_rhs.argtypes = [_ip, _dp, _dp, _dp, _dp, _dp]
     lib.orc_el_stress_average.argtypes = [_ip, _dp, _dp, _dp, _dp, _dp, _dp]
-    lib.orc_el_pcg.argtypes = [_ip, _dp, _dp, _dp, _dp, _dp, i32, f64, i32]
+    lib.orc_el_pcg.argtypes = [_ip, _dp, _dp, _dp, _dp, _dp, i32, _dp, f64, i32]
+    lib.orc_psi3.argtypes = [_dp, _dp]
+    lib.orc_uno3_table.argtypes = [_ip, i32, _dp, _dp]
+    lib.orc_uno3_apply.argtypes = [_ip, _dp, _dp, _dp]
+    lib.orc_uno3_apply.restype = f64
+    lib.orc_train3_features.argtypes = [_ip, i32, _dp, _dp, _dp, _dp, _dp]
+    lib.orc_train3_loss.argtypes = [_ip, i32, _dp, _dp, _dp, f64]
+    lib.orc_train3_loss.restype = f64
+    lib.orc_train3_grad_hess.argtypes = [_ip, i32, _dp, _dp, _dp, _dp, _dp]
     lib.orc_el_pcg.restype = i32
     lib.orc_uno_num_weights.argtypes = [i32, i32]
     lib.orc_uno_num_weights.restype = ctypes.c_int64
@@ -355,14 +363,19 @@ def el_stress_average(lam, mu, eps, u, L0=1.0, h=None):
     return out
 
 
-def el_pcg(lam, mu, f, kind="jacobi", rtol=1e-10, max_iter=100000, L0=1.0, h=None):
-    """Algorithm 1 for the elastic operator; returns (u, passes)."""
+def el_pcg(lam, mu, f, kind="jacobi", rtol=1e-10, max_iter=100000, L0=1.0, h=None, table=None):
+    """Algorithm 1 for the elastic operator (kind "none", "jacobi" or "uno"
+    with a table of uno3_table); returns (u, passes)."""
     lib = _load()
     lam, mu, f = _f64(lam), _f64(mu), _f64(f)
     _, n, hh = _shape_args(lam.shape, L0, h)
     u = np.zeros_like(f)
-    it = lib.orc_el_pcg(n.ctypes.data_as(_ip), _ptr(hh), _ptr(lam), _ptr(mu), _ptr(f), _ptr(u),
-                        1 if kind == "jacobi" else 0, float(rtol), int(max_iter))
+    k = {"none": 0, "jacobi": 1, "uno": 2}[kind]
+    tab = _f64(table) if k == 2 else np.zeros(1)
+    if k == 2:
+        assert tab.shape == (6,) + lam.shape
+    it = lib.orc_el_pcg(n.ctypes.data_as(_ip), _ptr(hh), _ptr(lam), _ptr(mu), _ptr(f), _ptr(u), k, _ptr(tab),
+                        float(rtol), int(max_iter))
     return u, int(it)
 
 
@@ -373,3 +386,123 @@ def el_effective_stiffness(lam, mu, solutions, loads=None, L0=1.0, h=None):
     S = np.stack([el_stress_average(lam, mu, e, u, L0, h) for e, u in zip(loads, solutions)], axis=1)
     return S @ np.linalg.inv(loads.T)
 
+
+
+# ---- UNO preconditioner and its training for c = 3 (App. B) ----
+
+def psi3(w) -> np.ndarray:
+    """(q1..q6) = unique entries of psi(w) = L L^T (eq. local-param-3)."""
+    lib = _load()
+    w = _f64(w)
+    q = np.zeros(6)
+    lib.orc_psi3(_ptr(w), _ptr(q))
+    return q
+
+
+def q_matrix(q) -> np.ndarray:
+    """3 x 3 matrix of the table entries (q1, q2, q3, q4, q5, q6)."""
+    q1, q2, q3, q4, q5, q6 = q
+    return np.array([[q1, q3, q6], [q3, q2, q5], [q6, q5, q4]])
+
+
+def num_weights3(M: int) -> int:
+    return 6 * num_weights(3, M)
+
+
+def uno3_table(shape, M, theta) -> np.ndarray:
+    lib = _load()
+    check_modes(shape, M)
+    theta = _f64(theta)
+    assert theta.size == num_weights3(M)
+    _, n, _ = _shape_args(shape)
+    t = np.zeros((6,) + tuple(shape))
+    lib.orc_uno3_table(n.ctypes.data_as(_ip), int(M), _ptr(theta), _ptr(t))
+    return t
+
+
+def uno3_apply(table, r, return_imag=False):
+    lib = _load()
+    table, r = _f64(table), _f64(r)
+    _, n, _ = _shape_args(r.shape[1:])
+    s = np.zeros_like(r)
+    im = lib.orc_uno3_apply(n.ctypes.data_as(_ip), _ptr(table), _ptr(r), _ptr(s))
+    return (s, im) if return_imag else s
+
+
+def train3_features(f_list, u_list):
+    """(alpha (6, grid), beta (6, grid), delta) over the full Fourier grid."""
+    lib = _load()
+    f = _f64(np.stack(f_list))
+    u = _f64(np.stack(u_list))
+    ns = f.shape[0]
+    shape = f.shape[2:]
+    _, n, _ = _shape_args(shape)
+    a = np.zeros((6,) + shape)
+    b = np.zeros((6,) + shape)
+    dl = ctypes.c_double(0.0)
+    lib.orc_train3_features(n.ctypes.data_as(_ip), ns, _ptr(f), _ptr(u), _ptr(a), _ptr(b), ctypes.byref(dl))
+    return a, b, dl.value
+
+
+def train3_loss(theta, M, alpha, beta, delta) -> float:
+    lib = _load()
+    alpha, beta, theta = _f64(alpha), _f64(beta), _f64(theta)
+    _, n, _ = _shape_args(alpha.shape[1:])
+    return lib.orc_train3_loss(n.ctypes.data_as(_ip), int(M), _ptr(theta), _ptr(alpha), _ptr(beta), float(delta))
+
+
+def train3_grad_hess(theta, M, alpha, beta, hess=True):
+    lib = _load()
+    alpha, beta, theta = _f64(alpha), _f64(beta), _f64(theta)
+    _, n, _ = _shape_args(alpha.shape[1:])
+    nw = num_weights3(M)
+    g = np.zeros(nw)
+    H = np.zeros((nw, nw)) if hess else None
+    lib.orc_train3_grad_hess(n.ctypes.data_as(_ip), int(M), _ptr(theta), _ptr(alpha), _ptr(beta), _ptr(g),
+                             _ptr(H) if hess else None)
+    return (g, H) if hess else g
+
+
+def train3_init(M, alpha, beta) -> np.ndarray:
+    """Start of the Newton iteration: every slot isotropic, psi = a I, with a
+    the best single scalar multiple of the identity for the data."""
+    a_iso = (beta[0].sum() + beta[1].sum() + beta[3].sum()) / (2.0 * (alpha[0].sum() + alpha[1].sum() + alpha[3].sum()))
+    w = np.sqrt(max(a_iso, 1e-300) / 2.0)
+    theta = np.zeros(num_weights3(M))
+    theta.reshape(-1, 6)[:, [0, 1, 3]] = w
+    return theta
+
+
+def train3_newton(M, alpha, beta, delta, theta0=None, epochs=100, gtol=1e-10):
+    """Algorithm 4 (second-order training) with a Levenberg-Marquardt
+    safeguard: the step solves (H + lam I) d = -g, lam shrinks after a step
+    that lowers the loss and grows (the step is retried) otherwise.  With
+    lam -> 0 it is the Newton-Raphson step of the paper.  Stops when the
+    gradient has fallen by gtol or two steps no longer lower the loss beyond
+    rounding.  Returns (theta, losses)."""
+    theta = train3_init(M, alpha, beta) if theta0 is None else _f64(theta0).copy()
+    L = train3_loss(theta, M, alpha, beta, delta)
+    losses = [L]
+    lam = None
+    g0 = None
+    for _ in range(epochs):
+        g, H = train3_grad_hess(theta, M, alpha, beta)
+        g0 = np.abs(g).max() if g0 is None else g0
+        if np.abs(g).max() <= gtol * g0:
+            break
+        if len(losses) >= 3 and losses[-3] - losses[-1] <= 1e-14 * abs(losses[-1]):
+            break  # stationary to rounding
+        if lam is None:
+            lam = 1e-6 * np.abs(np.diag(H)).max()
+        while True:
+            d = np.linalg.solve(H + lam * np.eye(H.shape[0]), -g)
+            Ln = train3_loss(theta + d, M, alpha, beta, delta)
+            if Ln <= L:
+                theta, L = theta + d, Ln
+                lam = max(lam / 3.0, 1e-300)
+                break
+            lam *= 4.0
+            if lam > 1e300:
+                return theta, losses
+        losses.append(L)
+    return theta, losses

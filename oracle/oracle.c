@@ -869,8 +869,11 @@ void orc_el_stress_average(const int32_t *n, const double *h, const double *lam,
 /* Algorithm 1 for the elastic operator: P = none (kind 0) or Jacobi (1);
  * relative infinity-norm stop as in orc_pcg; componentwise mean removal at
  * the end.  Returns the loop passes. */
+double orc_uno3_apply(const int32_t *n, const double *table, const double *r, double *s);
+
+/* kind: 0 none, 1 Jacobi, 2 UNO table of orc_uno3_table */
 int orc_el_pcg(const int32_t *n, const double *h, const double *lam, const double *mu, const double *f, double *u,
-               int kind, double rtol, int max_iter)
+               int kind, const double *table, double rtol, int max_iter)
 {
     orc_grid g = mk_grid(3, n, h);
     int64_t nn = grid_size(&g), N = 3 * nn;
@@ -888,7 +891,9 @@ int orc_el_pcg(const int32_t *n, const double *h, const double *lam, const doubl
         double rm = 0.0;
         for (int64_t i = 0; i < N; ++i) rm = fmax(rm, fabs(r[i]));
         if (!(rm > rtol * r0) || k >= max_iter) break;
-        for (int64_t i = 0; i < N; ++i) s[i] = kind == 1 ? r[i] / dg[i] : r[i];
+        if (kind == 2) orc_uno3_apply(n, table, r, s);
+        else
+            for (int64_t i = 0; i < N; ++i) s[i] = kind == 1 ? r[i] / dg[i] : r[i];
         double g0 = g1;
         g1 = 0.0;
         for (int64_t i = 0; i < N; ++i) g1 += r[i] * s[i];
@@ -912,4 +917,315 @@ int orc_el_pcg(const int32_t *n, const double *h, const double *lam, const doubl
     }
     free(r); free(s); free(d); free(p); free(dg);
     return k;
+}
+
+/* =====================================================================
+ * UNO preconditioner, c = 3 (Sec. 4.2.2: eqs. fnocg-parametrization and
+ * fnocg-op-fundsol; App. B: eq. local-param-3 and the band matrix Q).
+ *   theta[6 s + m]: weights w_1..w_6 of slot s (s = 0 the bypass, s >= 1
+ *   the learned modes K in the order of the c = 1 table).
+ *   psi(w) = L L^T with L lower triangular, L_11 = w_1, L_22 = w_2,
+ *   L_21 = w_3, L_33 = w_4, L_32 = w_5, L_31 = w_6.
+ *   Phi(k) = psi(w^0) + psi(w^s) on a learned mode k (or its conjugate -k)
+ *   and psi(w^0) elsewhere; the same readings as for c = 1 (mean over k
+ *   and -k, zero mode 0).
+ * The table holds the unique blocks of Q per mode, in the paper's order
+ *   q1 = Phi_11, q2 = Phi_22, q3 = Phi_12, q4 = Phi_33, q5 = Phi_23,
+ *   q6 = Phi_13,
+ * planar: table[e n + l] for e = 0..5 (q_(e+1)), l the mode's C-order index.
+ * Displacement-like vectors are planar too: component c at [c n + node].
+ * ===================================================================== */
+
+static void psi3(const double *w, double q[6])
+{
+    double L[3][3] = {{w[0], 0.0, 0.0}, {w[2], w[1], 0.0}, {w[5], w[4], w[3]}};
+    double P[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            P[i][j] = 0.0;
+            for (int k = 0; k < 3; ++k) P[i][j] += L[i][k] * L[j][k];
+        }
+    q[0] = P[0][0]; q[1] = P[1][1]; q[2] = P[0][1];
+    q[3] = P[2][2]; q[4] = P[1][2]; q[5] = P[0][2];
+}
+
+void orc_psi3(const double *w, double *q) { psi3(w, q); }
+
+static void phi3_raw(int M, const double *theta, const int *k, double q[6])
+{
+    for (int e = 0; e < 6; ++e) q[e] = 0.0;
+    if (k[0] == 0 && k[1] == 0 && k[2] == 0) return;
+    psi3(theta, q);
+    int64_t s = learned_slot(3, M, k);
+    if (s == 0 && k[2] < 0) {
+        int mk[3] = {-k[0], -k[1], -k[2]};
+        s = learned_slot(3, M, mk);
+    }
+    if (s > 0) {
+        double t[6];
+        psi3(theta + 6 * s, t);
+        for (int e = 0; e < 6; ++e) q[e] += t[e];
+    }
+}
+
+void orc_uno3_table(const int32_t *n, int M, const double *theta, double *table)
+{
+    orc_grid g = mk_grid(3, n, (const double[3]){1, 1, 1});
+    int64_t nn = grid_size(&g);
+    for (int64_t l = 0; l < nn; ++l) {
+        int idx[3], k[3], mk[3];
+        unlin(&g, l, idx);
+        for (int b = 0; b < 3; ++b) { k[b] = centred(idx[b], g.n[b]); mk[b] = -k[b]; }
+        double a[6], b6[6];
+        phi3_raw(M, theta, k, a);
+        phi3_raw(M, theta, mk, b6);
+        for (int e = 0; e < 6; ++e) table[e * nn + l] = 0.5 * (a[e] + b6[e]);
+    }
+}
+
+/* s_i = T^H (sum_j Phi_ij o T r_j) (eq. fnocg-op-fundsol), T the unitary
+ * DFT of each component; returns max |Im| before it is discarded */
+double orc_uno3_apply(const int32_t *n, const double *table, const double *r, double *s)
+{
+    orc_grid g = mk_grid(3, n, (const double[3]){1, 1, 1});
+    int64_t nn = grid_size(&g);
+    cplx *a = (cplx *)malloc(sizeof(cplx) * 3 * nn);
+    cplx *b = (cplx *)malloc(sizeof(cplx) * 3 * nn);
+    for (int64_t i = 0; i < 3 * nn; ++i) a[i] = r[i];
+    for (int c = 0; c < 3; ++c) orc_fft_nd(3, n, (double *)(a + c * nn), -1);
+    static const int qi[3][3] = {{0, 2, 5}, {2, 1, 4}, {5, 4, 3}};
+    for (int64_t l = 0; l < nn; ++l)
+        for (int i = 0; i < 3; ++i) {
+            cplx v = 0.0;
+            for (int j = 0; j < 3; ++j) v += table[qi[i][j] * nn + l] * a[j * nn + l];
+            b[i * nn + l] = v;
+        }
+    for (int c = 0; c < 3; ++c) orc_fft_nd(3, n, (double *)(b + c * nn), +1);
+    double im = 0.0;
+    for (int64_t i = 0; i < 3 * nn; ++i) {
+        s[i] = creal(b[i]);
+        if (fabs(cimag(b[i])) > im) im = fabs(cimag(b[i]));
+    }
+    free(a);
+    free(b);
+    return im;
+}
+
+/* ---------------------------------------------------------------------
+ * Second-order training, c = 3 (Sec. 4.4 with App. B).  Features over the
+ * full Fourier grid (hats = unitary T, x/y/z = components 1/2/3):
+ *   alpha_1 = <|f^_x|^2>, alpha_2 = <|f^_y|^2>, alpha_4 = <|f^_z|^2>,
+ *   alpha_3 = <2 Re(conj f^_x f^_y)>, alpha_5 = <2 Re(conj f^_y f^_z)>,
+ *   alpha_6 = <2 Re(conj f^_x f^_z)>,
+ *   beta_1 = <2 Re(conj f^_x u^_x)>, beta_2 = <2 Re(conj f^_y u^_y)>,
+ *   beta_4 = <2 Re(conj f^_z u^_z)>,
+ *   beta_3 = <2 Re(conj f^_x u^_y + conj f^_y u^_x)>,
+ *   beta_5 = <2 Re(conj f^_y u^_z + conj f^_z u^_y)>,
+ *   beta_6 = <2 Re(conj f^_x u^_z + conj f^_z u^_x)>,
+ *   delta = <||u||^2>,  <.> the mean over the ns samples.
+ * (For real f the products conj(f^_x) f^_y + conj(f^_y) f^_x are real.)
+ * alpha, beta planar: [e n + l], e = 0..5 for index e + 1.
+ * ------------------------------------------------------------------- */
+void orc_train3_features(const int32_t *n, int ns, const double *f, const double *u, double *alpha, double *beta,
+                         double *delta)
+{
+    orc_grid g = mk_grid(3, n, (const double[3]){1, 1, 1});
+    int64_t nn = grid_size(&g);
+    cplx *fh = (cplx *)malloc(sizeof(cplx) * 3 * nn);
+    cplx *uh = (cplx *)malloc(sizeof(cplx) * 3 * nn);
+    memset(alpha, 0, sizeof(double) * 6 * nn);
+    memset(beta, 0, sizeof(double) * 6 * nn);
+    *delta = 0.0;
+    for (int j = 0; j < ns; ++j) {
+        const double *fj = f + (int64_t)j * 3 * nn, *uj = u + (int64_t)j * 3 * nn;
+        for (int64_t i = 0; i < 3 * nn; ++i) { fh[i] = fj[i]; uh[i] = uj[i]; }
+        for (int c = 0; c < 3; ++c) {
+            orc_fft_nd(3, n, (double *)(fh + c * nn), -1);
+            orc_fft_nd(3, n, (double *)(uh + c * nn), -1);
+        }
+        for (int64_t l = 0; l < nn; ++l) {
+            cplx fx = fh[l], fy = fh[nn + l], fz = fh[2 * nn + l];
+            cplx ux = uh[l], uy = uh[nn + l], uz = uh[2 * nn + l];
+            alpha[0 * nn + l] += creal(conj(fx) * fx) / ns;
+            alpha[1 * nn + l] += creal(conj(fy) * fy) / ns;
+            alpha[2 * nn + l] += 2.0 * creal(conj(fx) * fy) / ns;
+            alpha[3 * nn + l] += creal(conj(fz) * fz) / ns;
+            alpha[4 * nn + l] += 2.0 * creal(conj(fy) * fz) / ns;
+            alpha[5 * nn + l] += 2.0 * creal(conj(fx) * fz) / ns;
+            beta[0 * nn + l] += 2.0 * creal(conj(fx) * ux) / ns;
+            beta[1 * nn + l] += 2.0 * creal(conj(fy) * uy) / ns;
+            beta[2 * nn + l] += 2.0 * creal(conj(fx) * uy + conj(fy) * ux) / ns;
+            beta[3 * nn + l] += 2.0 * creal(conj(fz) * uz) / ns;
+            beta[4 * nn + l] += 2.0 * creal(conj(fy) * uz + conj(fz) * uy) / ns;
+            beta[5 * nn + l] += 2.0 * creal(conj(fx) * uz + conj(fz) * ux) / ns;
+        }
+        for (int64_t i = 0; i < 3 * nn; ++i) *delta += uj[i] * uj[i] / ns;
+    }
+    free(fh);
+    free(uh);
+}
+
+/* loss per mode from the table entries q (App. B), without delta */
+static double loss3_mode(const double *q, const double *a, const double *b)
+{
+    const double q1 = q[0], q2 = q[1], q3 = q[2], q4 = q[3], q5 = q[4], q6 = q[5];
+    return a[0] * (q1 * q1 + q3 * q3 + q6 * q6) + a[1] * (q2 * q2 + q3 * q3 + q5 * q5) +
+           a[2] * (q1 * q3 + q2 * q3 + q5 * q6) + a[3] * (q4 * q4 + q5 * q5 + q6 * q6) +
+           a[4] * (q2 * q5 + q3 * q6 + q4 * q5) + a[5] * (q1 * q6 + q3 * q5 + q4 * q6) -
+           (b[0] * q1 + b[1] * q2 + b[2] * q3 + b[3] * q4 + b[4] * q5 + b[5] * q6);
+}
+
+/* dL/dq per mode (App. B) */
+static void grad3_mode(const double *q, const double *a, const double *b, double g[6])
+{
+    const double q1 = q[0], q2 = q[1], q3 = q[2], q4 = q[3], q5 = q[4], q6 = q[5];
+    g[0] = 2 * a[0] * q1 + a[2] * q3 + a[5] * q6 - b[0];
+    g[1] = 2 * a[1] * q2 + a[2] * q3 + a[4] * q5 - b[1];
+    g[2] = 2 * a[0] * q3 + 2 * a[1] * q3 + a[2] * (q1 + q2) + a[4] * q6 + a[5] * q5 - b[2];
+    g[3] = 2 * a[3] * q4 + a[4] * q5 + a[5] * q6 - b[3];
+    g[4] = 2 * a[1] * q5 + a[2] * q6 + 2 * a[3] * q5 + a[4] * (q2 + q4) + a[5] * q3 - b[4];
+    g[5] = 2 * a[0] * q6 + a[2] * q5 + 2 * a[3] * q6 + a[4] * q3 + a[5] * (q1 + q4) - b[5];
+}
+
+/* d^2 L / dq dq per mode (App. B), 6 x 6 row-major */
+static void hess3_mode(const double *a, double H[36])
+{
+    memset(H, 0, sizeof(double) * 36);
+#define HQ(i, j, v) (H[(i - 1) * 6 + (j - 1)] = (v))
+    HQ(1, 1, 2 * a[0]); HQ(1, 3, a[2]); HQ(1, 6, a[5]);
+    HQ(2, 2, 2 * a[1]); HQ(2, 3, a[2]); HQ(2, 5, a[4]);
+    HQ(3, 1, a[2]); HQ(3, 2, a[2]); HQ(3, 3, 2 * (a[0] + a[1])); HQ(3, 5, a[5]); HQ(3, 6, a[4]);
+    HQ(4, 4, 2 * a[3]); HQ(4, 5, a[4]); HQ(4, 6, a[5]);
+    HQ(5, 2, a[4]); HQ(5, 3, a[5]); HQ(5, 4, a[4]); HQ(5, 5, 2 * (a[1] + a[3])); HQ(5, 6, a[2]);
+    HQ(6, 1, a[5]); HQ(6, 3, a[4]); HQ(6, 4, a[5]); HQ(6, 5, a[2]); HQ(6, 6, 2 * (a[0] + a[3]));
+#undef HQ
+}
+
+/* dpsi/dw: J[e][m] = d q_e / d w_m; d2psi/dw dw: D2[e][m][p] (constant) */
+static void psi3_jac(const double *w, double J[6][6])
+{
+    double Lw[6][3][3];  /* dL/dw_m */
+    memset(Lw, 0, sizeof(Lw));
+    Lw[0][0][0] = 1; Lw[1][1][1] = 1; Lw[2][1][0] = 1; Lw[3][2][2] = 1; Lw[4][2][1] = 1; Lw[5][2][0] = 1;
+    double L[3][3] = {{w[0], 0.0, 0.0}, {w[2], w[1], 0.0}, {w[5], w[4], w[3]}};
+    static const int pi[6] = {0, 1, 0, 2, 1, 0}, pj[6] = {0, 1, 1, 2, 2, 2};
+    for (int m = 0; m < 6; ++m)
+        for (int e = 0; e < 6; ++e) {
+            const int i = pi[e], j = pj[e];
+            double v = 0.0;  /* d (L L^T)_ij = dL_i . L_j + L_i . dL_j */
+            for (int k = 0; k < 3; ++k) v += Lw[m][i][k] * L[j][k] + L[i][k] * Lw[m][j][k];
+            J[e][m] = v;
+        }
+}
+
+static void psi3_hess(double D2[6][6][6])
+{
+    double Lw[6][3][3];
+    memset(Lw, 0, sizeof(Lw));
+    Lw[0][0][0] = 1; Lw[1][1][1] = 1; Lw[2][1][0] = 1; Lw[3][2][2] = 1; Lw[4][2][1] = 1; Lw[5][2][0] = 1;
+    static const int pi[6] = {0, 1, 0, 2, 1, 0}, pj[6] = {0, 1, 1, 2, 2, 2};
+    for (int e = 0; e < 6; ++e)
+        for (int m = 0; m < 6; ++m)
+            for (int p = 0; p < 6; ++p) {
+                const int i = pi[e], j = pj[e];
+                double v = 0.0;
+                for (int k = 0; k < 3; ++k) v += Lw[m][i][k] * Lw[p][j][k] + Lw[p][i][k] * Lw[m][j][k];
+                D2[e][m][p] = v;
+            }
+}
+
+/* the parameter slots a mode's table entry depends on, with weights:
+ * q(k) = psi(w^0) + 1/2 psi(w^s1) + 1/2 psi(w^s2), s1 = slot of k (or of
+ * -k through the conjugate set), s2 = the same for -k (0: none) */
+static void mode_slots(int M, const int *k, int64_t *s1, int64_t *s2)
+{
+    int mk[3] = {-k[0], -k[1], -k[2]};
+    *s1 = *s2 = 0;
+    if (k[0] == 0 && k[1] == 0 && k[2] == 0) return;
+    int64_t a = learned_slot(3, M, k);
+    if (a == 0 && k[2] < 0) a = learned_slot(3, M, mk);
+    int64_t b = learned_slot(3, M, mk);
+    if (b == 0 && mk[2] < 0) b = learned_slot(3, M, k);
+    *s1 = a;
+    *s2 = b;
+}
+
+double orc_train3_loss(const int32_t *n, int M, const double *theta, const double *alpha, const double *beta,
+                       double delta)
+{
+    orc_grid g = mk_grid(3, n, (const double[3]){1, 1, 1});
+    int64_t nn = grid_size(&g);
+    double *tab = (double *)malloc(sizeof(double) * 6 * nn);
+    orc_uno3_table(n, M, theta, tab);
+    double L = delta;
+    for (int64_t l = 0; l < nn; ++l) {
+        double q[6], a[6], b[6];
+        for (int e = 0; e < 6; ++e) { q[e] = tab[e * nn + l]; a[e] = alpha[e * nn + l]; b[e] = beta[e * nn + l]; }
+        L += loss3_mode(q, a, b);
+    }
+    free(tab);
+    return L;
+}
+
+/* gradient (nw = 6 (k_max + 1)) and dense Hessian (nw x nw, nullable) of
+ * the loss with respect to theta, by the chain rule through the table
+ * (Sec. 4.4, Newton-Raphson paragraph) */
+void orc_train3_grad_hess(const int32_t *n, int M, const double *theta, const double *alpha, const double *beta,
+                          double *grad, double *hess)
+{
+    orc_grid g = mk_grid(3, n, (const double[3]){1, 1, 1});
+    int64_t nn = grid_size(&g);
+    int64_t nw = 6 * orc_uno_num_weights(3, M);
+    double *tab = (double *)malloc(sizeof(double) * 6 * nn);
+    orc_uno3_table(n, M, theta, tab);
+    memset(grad, 0, sizeof(double) * nw);
+    if (hess) memset(hess, 0, sizeof(double) * nw * nw);
+    double D2[6][6][6];
+    psi3_hess(D2);
+    for (int64_t l = 0; l < nn; ++l) {
+        int idx[3], k[3];
+        unlin(&g, l, idx);
+        for (int b = 0; b < 3; ++b) k[b] = centred(idx[b], g.n[b]);
+        if (k[0] == 0 && k[1] == 0 && k[2] == 0) continue; /* the zero mode's entry is fixed to 0 */
+        double q[6], a[6], b[6], gq[6], Hq[36];
+        for (int e = 0; e < 6; ++e) { q[e] = tab[e * nn + l]; a[e] = alpha[e * nn + l]; b[e] = beta[e * nn + l]; }
+        grad3_mode(q, a, b, gq);
+        hess3_mode(a, Hq);
+        int64_t s1, s2;
+        mode_slots(M, k, &s1, &s2);
+        /* dq/dtheta as a list of (slot, weight) blocks */
+        int64_t sl[3] = {0, s1, s2};
+        double wt[3] = {1.0, 0.5, 0.5};
+        int nb = (s1 > 0) ? 3 : 1;
+        double J[3][6][6];
+        for (int t = 0; t < nb; ++t) {
+            psi3_jac(theta + 6 * sl[t], J[t]);
+            for (int e = 0; e < 6; ++e)
+                for (int m = 0; m < 6; ++m) J[t][e][m] *= wt[t];
+        }
+        for (int t = 0; t < nb; ++t)
+            for (int m = 0; m < 6; ++m) {
+                double v = 0.0;
+                for (int e = 0; e < 6; ++e) v += gq[e] * J[t][e][m];
+                grad[6 * sl[t] + m] += v;
+            }
+        if (!hess) continue;
+        for (int t = 0; t < nb; ++t)
+            for (int u = 0; u < nb; ++u)
+                for (int m = 0; m < 6; ++m)
+                    for (int p = 0; p < 6; ++p) {
+                        double v = 0.0;
+                        for (int e = 0; e < 6; ++e)
+                            for (int f = 0; f < 6; ++f) v += J[t][e][m] * Hq[e * 6 + f] * J[u][f][p];
+                        hess[(6 * sl[t] + m) * nw + 6 * sl[u] + p] += v;
+                    }
+        for (int t = 0; t < nb; ++t)
+            for (int m = 0; m < 6; ++m)
+                for (int p = 0; p < 6; ++p) {
+                    double v = 0.0;
+                    for (int e = 0; e < 6; ++e) v += gq[e] * wt[t] * D2[e][m][p];
+                    hess[(6 * sl[t] + m) * nw + 6 * sl[t] + p] += v;
+                }
+    }
+    free(tab);
 }
