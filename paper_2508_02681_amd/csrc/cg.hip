@@ -806,7 +806,7 @@ uno_status pcg_run_el(const Grid& g, const double* lam, const double* mu, int64_
     gd.n = N;
     Workspace* w = nullptr;
     const int hist_len = o->max_iter + 1;
-    e = ws_get(gv, nullptr, nullptr, el_blocks(g), hist_len, nrhs, &w);
+    e = ws_get(gv, nullptr, nullptr, el_march_blocks(g, nrhs), hist_len, nrhs, &w);
     if (e != UNO_OK) return e;
     const int nb = w->nbr;
     const Parts P = parts_of(w);
@@ -859,7 +859,7 @@ uno_status pcg_run_el(const Grid& g, const double* lam, const double* mu, int64_
             e = launch_el_apply<true, true>(E, g, lam, mu, lks, w->s, dold, dnew, w->p, P.dp, it, P.rs[k & 1], nb,
                                             w->gam, nrhs, st);
             if (e != UNO_OK) return e;
-            const int np_dp = el_blocks(g);
+            const int np_dp = el_march_blocks(g, nrhs);
             double* rs_next = P.rs[(k + 1) & 1];
             double* ss_next = P.ss[(k + 1) & 1];
             if (o->kind == UNO_PREC_JACOBI)

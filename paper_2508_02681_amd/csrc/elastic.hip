@@ -4,11 +4,11 @@
 // in the Mandel basis (App. A).  Displacements are planar: component c of
 // node i at u[c n + i].
 //
-// Node-centred gather: node i is corner s of the eight voxels e = i - s,
-// s in {0,1}^3, and
-//   (A u)_(i,a) = sum_s sum_t sum_b (lambda_e K^l + mu_e K^m)[(s,a),(t,b)] u_(e+t, b),
-// with K^l, K^m the unit element matrices of the lambda and mu parts
-// (24 x 24, exact 2-point Gauss integration), staged in LDS.
+// The operator is applied voxel by voxel with the element integrals
+// sum-factorized over the 2-point Gauss rule (exact for the trilinear brick),
+// marching along axis 0 with the corner forces summed in registers and LDS.
+// The unit element matrices K^l, K^m of the lambda and mu parts (24 x 24)
+// are kept for the Jacobi diagonal.
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -69,33 +69,147 @@ void el_element_matrices(const double h[3], double K[2][576])
 
 __device__ __forceinline__ int wrap_el(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
-// CG variant: the operand is d = s + beta d_old (beta, d_old as in the
-// thermal operator), d of the own node goes to d_new, p = A d, d.p partials.
-// lks: stride between the Lame fields of the right-hand sides (0 if shared).
+// Two-point Gauss interpolation of four values on the corners (p, q) of a
+// face to its four Gauss points (P (x) P) d, P = [[c0, c1], [c1, c0]]; the
+// second stage takes scaled weights (s0, s1) = (c0, c1) * scale.  P is
+// symmetric, so the same map is its own transpose.
+__device__ __forceinline__ void el_interp(const double d[4], double o[4], double c0, double c1, double s0, double s1)
+{
+    const double e0 = c0 * d[0] + c1 * d[1], e1 = c1 * d[0] + c0 * d[1];
+    const double e2 = c0 * d[2] + c1 * d[3], e3 = c1 * d[2] + c0 * d[3];
+    o[0] = s0 * e0 + s1 * e2;
+    o[1] = s0 * e1 + s1 * e3;
+    o[2] = s1 * e0 + s0 * e2;
+    o[3] = s1 * e1 + s0 * e3;
+}
+
+// Element forces of one voxel, f = int B^T D B u (exact 2-point Gauss rule,
+// sum-factorized).  U[i][v], f[i][v]: component i at corner v = 4a + 2b + c
+// (a, b, c the corner's offsets along axes 0, 1, 2).  The gradient of
+// component i along axis j at a Gauss point depends only on the two Gauss
+// coordinates transverse to j: it is the interpolation of the four corner
+// differences along j.  The stress at the eight points is summed along j
+// before the transposed interpolation brings it back to the corners.
+__device__ __forceinline__ void el_element(const ElDev& E, double lam, double mu, const double U[3][8],
+                                           double f[3][8])
+{
+    const double c0 = E.gp[0], c1 = E.gp[1];
+    double G[3][3][4];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const double* u = U[i];
+        const double d0[4] = {u[4] - u[0], u[5] - u[1], u[6] - u[2], u[7] - u[3]};  // along 0, (b, c)
+        const double d1[4] = {u[2] - u[0], u[3] - u[1], u[6] - u[4], u[7] - u[5]};  // along 1, (a, c)
+        const double d2[4] = {u[1] - u[0], u[3] - u[2], u[5] - u[4], u[7] - u[6]};  // along 2, (a, b)
+        el_interp(d0, G[i][0], c0, c1, E.gf[0][0], E.gf[0][1]);
+        el_interp(d1, G[i][1], c0, c1, E.gf[1][0], E.gf[1][1]);
+        el_interp(d2, G[i][2], c0, c1, E.gf[2][0], E.gf[2][1]);
+    }
+    double S[3][3][4];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) S[i][j][k] = 0.0;
+    const double mu2 = 2.0 * mu;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int q0 = q >> 2, q1 = (q >> 1) & 1, q2 = q & 1;
+        const int t0 = q1 * 2 + q2, t1 = q0 * 2 + q2, t2 = q0 * 2 + q1;
+        const double g00 = G[0][0][t0], g01 = G[0][1][t1], g02 = G[0][2][t2];
+        const double g10 = G[1][0][t0], g11 = G[1][1][t1], g12 = G[1][2][t2];
+        const double g20 = G[2][0][t0], g21 = G[2][1][t1], g22 = G[2][2][t2];
+        const double lt = lam * (g00 + g11 + g22);
+        const double s01 = mu * (g01 + g10), s02 = mu * (g02 + g20), s12 = mu * (g12 + g21);
+        S[0][0][t0] += lt + mu2 * g00;
+        S[1][1][t1] += lt + mu2 * g11;
+        S[2][2][t2] += lt + mu2 * g22;
+        S[0][1][t1] += s01;
+        S[1][0][t0] += s01;
+        S[0][2][t2] += s02;
+        S[2][0][t0] += s02;
+        S[1][2][t2] += s12;
+        S[2][1][t1] += s12;
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        double T0[4], T1[4], T2[4];
+        el_interp(S[i][0], T0, c0, c1, E.gb[0][0], E.gb[0][1]);
+        el_interp(S[i][1], T1, c0, c1, E.gb[1][0], E.gb[1][1]);
+        el_interp(S[i][2], T2, c0, c1, E.gb[2][0], E.gb[2][1]);
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+            const int a = v >> 2, b = (v >> 1) & 1, c = v & 1;
+            const double x0 = T0[b * 2 + c], x1 = T1[a * 2 + c], x2 = T2[a * 2 + b];
+            f[i][v] = (a ? x0 : -x0) + (b ? x1 : -x1) + (c ? x2 : -x2);
+        }
+    }
+}
+
+// y = A u as a march along axis 0.  A workgroup of 16 x 16 threads owns a
+// tile of 15 x 15 nodes in the (1, 2) plane and xb node planes; thread
+// (ty, tz) computes the voxel whose lower corner is node (y0 - 1 + ty,
+// z0 - 1 + tz) in each voxel plane x0 - 1 ... x0 + xb - 1 and owns that
+// node when ty, tz >= 1.  The voxel's corner forces go to
+//   corner a = 1 (next node plane): kept in registers for the next step,
+//   corners b or c = 1 (other threads' nodes): exchanged through LDS,
+// and the owner sums the four in-plane contributions.  The node planes
+// pass through a ring of three LDS planes (two in use, one being filled).
+//
+// CG variant: the operand is d = s + beta d_old (beta from gamma_k /
+// gamma_(k-1), gamma_k combined from the r.s partials), the owner writes
+// d_new, p = A d and the d.p partial of the workgroup.  lks: stride of the
+// Lame fields per right-hand side (0 if shared).
+constexpr int kElT = 16;        // threads per tile side
+constexpr int kElO = kElT - 1;  // owned nodes per tile side
+constexpr int kElL = kElT + 1;  // LDS node tile side
+
 template <bool CG, bool HEAD>
-__global__ void __launch_bounds__(256) k_el_apply(ElDev E, const double* __restrict__ lam, const double* __restrict__ mu,
-                                                  int64_t lks, const double* __restrict__ s,
-                                                  const double* __restrict__ dold, double* __restrict__ dnew,
-                                                  double* __restrict__ p, double* __restrict__ part_dp, CgIter it,
+__global__ void __launch_bounds__(256) k_el_march(ElDev E, ElGeom eg, const double* __restrict__ lam,
+                                                  const double* __restrict__ mu, int64_t lks,
+                                                  const double* __restrict__ s, const double* __restrict__ dold,
+                                                  double* __restrict__ dnew, double* __restrict__ p,
+                                                  double* __restrict__ part_dp, CgIter it,
                                                   const double* __restrict__ part_rs, int np_rs, double* gam)
 {
-    __shared__ double Ks[2 * 576];
+    __shared__ double Dl[3][3][kElL * kElL];  // ring slot, component, node
+    __shared__ double X[2][9][256];           // exchanged corner forces
     __shared__ double slots[4];
     const GridDev& g = E.g;
     const int64_t n = g.n;
-    if (CG && blockIdx.y > 0) {
-        const int64_t vo = (int64_t)blockIdx.y * it.vs, po = (int64_t)blockIdx.y * it.ps;
-        lam += (int64_t)blockIdx.y * lks;
-        mu += (int64_t)blockIdx.y * lks;
+    lam += (int64_t)blockIdx.y * lks;
+    mu += (int64_t)blockIdx.y * lks;
+    if (blockIdx.y > 0) {
+        const int64_t vo = (int64_t)blockIdx.y * it.vs;
         s += vo;
-        dold += vo;
-        dnew += vo;
         p += vo;
-        part_dp += po;
-        part_rs += po;
-        gam += (int64_t)blockIdx.y * it.hs;
-        it = rhs_iter(it);
+        if (CG) {
+            dold += vo;
+            dnew += vo;
+            part_dp += (int64_t)blockIdx.y * it.ps;
+            part_rs += (int64_t)blockIdx.y * it.ps;
+            gam += (int64_t)blockIdx.y * it.hs;
+            it = rhs_iter(it);
+        }
     }
+    const int t = threadIdx.x, ly = t >> 4, lz = t & 15;
+    int bid = blockIdx.x;
+    const int bz = bid % eg.tiles_z;
+    bid /= eg.tiles_z;
+    const int by = bid % eg.tiles_y, bx = bid / eg.tiles_y;
+    const int y0 = by * kElO, z0 = bz * kElO, x0 = bx * eg.xb;
+    const int nx = min(eg.xb, g.n0 - x0);
+    const int64_t plane = (int64_t)g.n1 * g.n2;
+    // this thread's node (and voxel) in the plane, and the extra node of the
+    // LDS tile it loads (row 16, then column 16)
+    const int64_t o0 = (int64_t)wrap_el(y0 - 1 + ly, g.n1) * g.n2 + wrap_el(z0 - 1 + lz, g.n2);
+    const bool has_x = t < 2 * kElL - 1;
+    const int xy = t < kElL ? kElT : t - kElL, xz = t < kElL ? t : kElT;
+    const int64_t o1 = (int64_t)wrap_el(y0 - 1 + xy, g.n1) * g.n2 + wrap_el(z0 - 1 + xz, g.n2);
+    const int l0 = ly * kElL + lz, l1 = xy * kElL + xz;
+    const bool own = ly >= 1 && lz >= 1 && y0 + ly - 1 < g.n1 && z0 + lz - 1 < g.n2;
+
     StateLoad sl;
     double head_share = 0.0, rs_share = 0.0, gprev = 1.0;
     if (CG) {
@@ -104,9 +218,8 @@ __global__ void __launch_bounds__(256) k_el_apply(ElDev E, const double* __restr
         rs_share = load_share<OpSum>(part_rs, np_rs);
         if (it.k > it.k0) gprev = gam[it.k - 1];
     }
-    for (int j = threadIdx.x; j < 2 * 576; j += 256) Ks[j] = E.K[j];
     double beta = 0.0;
-    bool first = true;
+    bool use_old = false;
     if (CG) {
         if (HEAD) {
             if (head_decide(it, sl, head_share, slots)) return;
@@ -121,48 +234,98 @@ __global__ void __launch_bounds__(256) k_el_apply(ElDev E, const double* __restr
             if (lead) { it.st->status = 1; it.st->fail_iter = k; }
             return;
         }
-        first = (k == it.k0);
-        beta = first ? 0.0 : gk / gprev;
+        use_old = k != it.k0;
+        beta = use_old ? gk / gprev : 0.0;
     }
-    __syncthreads();
-    const bool use_old = CG && !first;
-    double dot = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const int z = (int)(i % g.n2);
-        const int64_t q = i / g.n2;
-        const int y = (int)(q % g.n1), x = (int)(q / g.n1);
-        double acc[3] = {0.0, 0.0, 0.0};
-        for (int sc = 0; sc < 8; ++sc) {  // node i is corner sc of voxel e = i - sc
-            const int ex = wrap_el(x - (sc >> 2), g.n0), ey = wrap_el(y - ((sc >> 1) & 1), g.n1),
-                      ez = wrap_el(z - (sc & 1), g.n2);
-            const int64_t e = ((int64_t)ex * g.n1 + ey) * g.n2 + ez;
-            const double le = lam[e], me = mu[e];
-            for (int t = 0; t < 8; ++t) {
-                const int64_t j = ((int64_t)wrap_el(ex + (t >> 2), g.n0) * g.n1 + wrap_el(ey + ((t >> 1) & 1), g.n1)) *
-                                      g.n2 + wrap_el(ez + (t & 1), g.n2);
-                double dj[3];
+
+    // node plane m (global x0 - 1 + m) of the operand
+    double ps[3], pd[3], xs_[3], xd[3];
+    auto fetch = [&](int m) {
+        const int64_t b = (int64_t)wrap_el(x0 - 1 + m, g.n0) * plane;
 #pragma unroll
-                for (int b = 0; b < 3; ++b) {
-                    dj[b] = s[b * n + j];
-                    if (use_old) dj[b] += beta * dold[b * n + j];
-                }
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    const double* K0 = Ks + (sc * 3 + a) * 24 + t * 3;
-                    const double* K1 = K0 + 576;
-#pragma unroll
-                    for (int b = 0; b < 3; ++b) acc[a] += (le * K0[b] + me * K1[b]) * dj[b];
-                }
+        for (int i = 0; i < 3; ++i) {
+            ps[i] = s[i * n + b + o0];
+            if (use_old) pd[i] = dold[i * n + b + o0];
+            if (has_x) {
+                xs_[i] = s[i * n + b + o1];
+                if (use_old) xd[i] = dold[i * n + b + o1];
             }
         }
+    };
+    auto store = [&](int m) {
+        const int slot = m % 3;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            p[a * n + i] = acc[a];
-            if (CG) {
-                double di = s[a * n + i];
-                if (use_old) di += beta * dold[a * n + i];
-                dnew[a * n + i] = di;
-                dot += di * acc[a];
+        for (int i = 0; i < 3; ++i) {
+            const double d = use_old ? ps[i] + beta * pd[i] : ps[i];
+            Dl[slot][i][l0] = d;
+            if (has_x) Dl[slot][i][l1] = use_old ? xs_[i] + beta * xd[i] : xs_[i];
+            if (CG && own && m >= 1 && m <= nx) dnew[i * n + (int64_t)(x0 - 1 + m) * plane + o0] = d;
+        }
+    };
+    fetch(0);
+    store(0);
+    fetch(1);
+    store(1);
+    double le = lam[(int64_t)wrap_el(x0 - 1, g.n0) * plane + o0];
+    double me = mu[(int64_t)wrap_el(x0 - 1, g.n0) * plane + o0];
+    __syncthreads();
+
+    double carry[3][4];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) carry[i][k] = 0.0;
+    double dot = 0.0;
+    for (int j = 0; j <= nx; ++j) {
+        const bool more = j + 2 <= nx + 1;
+        if (more) fetch(j + 2);
+        double ln = 0.0, mn = 0.0;
+        if (j + 1 <= nx) {
+            const int64_t e = (int64_t)wrap_el(x0 + j, g.n0) * plane + o0;
+            ln = lam[e];
+            mn = mu[e];
+        }
+        double U[3][8], f[3][8];
+        const int sa = j % 3, sb = (j + 1) % 3;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            U[i][0] = Dl[sa][i][l0];
+            U[i][1] = Dl[sa][i][l0 + 1];
+            U[i][2] = Dl[sa][i][l0 + kElL];
+            U[i][3] = Dl[sa][i][l0 + kElL + 1];
+            U[i][4] = Dl[sb][i][l0];
+            U[i][5] = Dl[sb][i][l0 + 1];
+            U[i][6] = Dl[sb][i][l0 + kElL];
+            U[i][7] = Dl[sb][i][l0 + kElL + 1];
+        }
+        const double dself[3] = {U[0][0], U[1][0], U[2][0]};
+        el_element(E, le, me, U, f);
+        // node plane j - 1 + x0: corners a = 0 of this voxel plus the carry
+        double own_f[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const double c1 = carry[i][1] + f[i][1], c2 = carry[i][2] + f[i][2], c3 = carry[i][3] + f[i][3];
+            own_f[i] = carry[i][0] + f[i][0];
+            if (j >= 1) {
+                X[j & 1][i * 3 + 0][t] = c1;  // corner (0, 1): node (ly, lz + 1)
+                X[j & 1][i * 3 + 1][t] = c2;  // corner (1, 0): node (ly + 1, lz)
+                X[j & 1][i * 3 + 2][t] = c3;  // corner (1, 1)
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) carry[i][k] = f[i][4 + k];
+        }
+        if (more) store(j + 2);
+        le = ln;
+        me = mn;
+        __syncthreads();
+        if (j >= 1 && own) {
+            const int64_t b = (int64_t)(x0 - 1 + j) * plane + o0;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const double y = own_f[i] + X[j & 1][i * 3 + 0][t - 1] + X[j & 1][i * 3 + 1][t - kElT] +
+                                 X[j & 1][i * 3 + 2][t - kElT - 1];
+                p[i * n + b] = y;
+                if (CG) dot += dself[i] * y;
             }
         }
     }
@@ -299,6 +462,15 @@ uno_status el_dev(const Grid& g, ElDev* out)
     out->g = g.dev;
     out->hvol = g.h[0] * g.h[1] * g.h[2];
     for (int b = 0; b < 3; ++b) out->gc[b] = 1.0 / (4.0 * g.h[b]);
+    // shape function values at the two Gauss points, (1 +- 1/sqrt 3) / 2
+    out->gp[0] = 0.5 + 0.5 / std::sqrt(3.0);
+    out->gp[1] = 0.5 - 0.5 / std::sqrt(3.0);
+    const double wq = g.h[0] * g.h[1] * g.h[2] / 8.0;  // Gauss weight times voxel volume
+    for (int b = 0; b < 3; ++b)
+        for (int k = 0; k < 2; ++k) {
+            out->gf[b][k] = out->gp[k] / g.h[b];
+            out->gb[b][k] = out->gp[k] * wq / g.h[b];
+        }
     out->K = K;
     return UNO_OK;
 }
@@ -315,13 +487,39 @@ int el_blocks(const Grid& g)
     return (int)(nb < 1024 ? nb : 1024);
 }
 
+// tiles of 15 x 15 owned nodes in the (1, 2) plane; node planes per
+// workgroup chosen for about 4096 workgroups over all right-hand sides
+// (two fit a CU), at least 4 (each workgroup also computes the voxel plane
+// below its first node plane)
+ElGeom el_geom(const Grid& g, int nrhs)
+{
+    ElGeom eg;
+    eg.tiles_y = (g.n[1] + kElO - 1) / kElO;
+    eg.tiles_z = (g.n[2] + kElO - 1) / kElO;
+    const int64_t tiles = (int64_t)eg.tiles_y * eg.tiles_z * (nrhs > 0 ? nrhs : 1);
+    int xb = (int)((g.n[0] * tiles + 4095) / 4096);
+    if (xb < 4) xb = 4;
+    if (xb > g.n[0]) xb = g.n[0];
+    eg.tiles_x = (g.n[0] + xb - 1) / xb;
+    eg.xb = (g.n[0] + eg.tiles_x - 1) / eg.tiles_x;  // even split of the planes
+    return eg;
+}
+
+int el_march_blocks(const Grid& g, int nrhs)
+{
+    const ElGeom eg = el_geom(g, nrhs);
+    return eg.tiles_x * eg.tiles_y * eg.tiles_z;
+}
+
 template <bool CG, bool HEAD>
 uno_status launch_el_apply(const ElDev& E, const Grid& g, const double* lam, const double* mu, int64_t lks,
                            const double* s, const double* dold, double* dnew, double* p, double* part_dp,
                            const CgIter& it, const double* part_rs, int np_rs, double* gam, int nrhs, hipStream_t st)
 {
-    uno_launch(CG ? UNO_KT_MATVEC : UNO_KT_APPLY, k_el_apply<CG, HEAD>, dim3(el_blocks(g), nrhs), dim3(256), 0, st, E,
-               lam, mu, lks, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam);
+    const ElGeom eg = el_geom(g, nrhs);
+    uno_launch(CG ? UNO_KT_MATVEC : UNO_KT_APPLY, k_el_march<CG, HEAD>,
+               dim3(eg.tiles_x * eg.tiles_y * eg.tiles_z, nrhs), dim3(256), 0, st, E, eg, lam, mu, lks, s, dold,
+               dnew, p, part_dp, it, part_rs, np_rs, gam);
     return hip_status(hipGetLastError());
 }
 template uno_status launch_el_apply<false, false>(const ElDev&, const Grid&, const double*, const double*, int64_t,

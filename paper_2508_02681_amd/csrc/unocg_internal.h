@@ -177,8 +177,16 @@ struct ElDev {
     GridDev g;
     double hvol;
     double gc[3];        // centre gradient factor per axis 1 / (4 h_b)
+    double gp[2];        // 1D shape function values at the Gauss points
+    double gf[3][2];     // gp / h_b (gradient interpolation)
+    double gb[3][2];     // gp w / h_b, w = Gauss weight times voxel volume
     const double* K;     // 2 x 576 unit element matrices (device)
 };
+struct ElGeom {
+    int tiles_y, tiles_z, xb, tiles_x;
+};
+ElGeom el_geom(const Grid& g, int nrhs);
+int el_march_blocks(const Grid& g, int nrhs);
 uno_status el_dev(const Grid& g, ElDev* out);
 void el_release_all();
 int el_blocks(const Grid& g);
