@@ -233,15 +233,29 @@ uno_status el_apply(const uno_grid *grid, const double *lambda, const double *mu
 uno_status el_macro_rhs(const uno_grid *grid, const double *lambda, const double *mu, const double *strain,
                         double *f, void *stream);
 /* nrhs solves for the macroscopic strains (host, nrhs x 6) carried by every
- * CG pass kernel (Algorithm 1 with P = none or the Jacobi diagonal; FP64
- * only: opts->kind UNO_PREC_NONE or UNO_PREC_JACOBI, op_t = prec_t =
- * UNO_F64).  lame_per_rhs = 0: one (lambda, mu) field pair for all loads;
+ * CG pass kernel (Algorithm 1 with P = none, the Jacobi diagonal, or the
+ * preconditioner of el_uno_precond_create in opts->uno (Algorithm 2); FP64
+ * only: op_t = prec_t = UNO_F64).  lame_per_rhs = 0: one (lambda, mu) field pair for all loads;
  * 1: nrhs pairs, pair j at + n j.  u (device, nrhs x 3n) holds the initial
  * guesses and receives the zero-mean fluctuations; info (host, nullable)
  * nrhs records.  1 <= nrhs <= 64.  Synchronous. */
 uno_status el_pcg_solve(const uno_grid *grid, const double *lambda, const double *mu, int32_t lame_per_rhs,
                         int32_t nrhs, const double *strains, double *u, const uno_solve_opts *opts,
                         uno_solve_info *info, void *stream);
+/* UNO preconditioner for the elastic problem (c = 3): Phi(k) = psi(w^0) +
+ * psi(w^s) on the learned modes (and conjugates), psi(w^0) elsewhere, 0 at
+ * k = 0 (eqs. fnocg-parametrization, fnocg-op-fundsol), with psi(w) = L L^T
+ * of eq. (local-param-3), L = [w1 0 0; w3 w2 0; w6 w5 w4].  theta (host,
+ * ntheta = 6 (k_max + 1)): w^s at theta + 6 s, s = 0 the bypass and s >= 1
+ * the learned modes in the order of uno_precond_create; the table is the
+ * mean over k and -k.  Every 3 x 3 block must have its eigenvalues above
+ * eps_spd (the safety check of Sec. 4.2.3), else UNO_ERR_NOT_SPD.  Applied
+ * by the learned-mode passes (the block [-M..M]^2 x [0..M] must fit the
+ * staging, else UNO_ERR_SHAPE), FP64 only: uno_precond_apply with planar
+ * 3n-vectors (r must not alias s), and el_pcg_solve with kind UNO_PREC_UNO.
+ * Release with uno_precond_destroy.  Synchronous. */
+uno_status el_uno_precond_create(const uno_grid *grid, int32_t M, const double *theta, int64_t ntheta,
+                                 double eps_spd, uno_precond **out);
 /* Effective stiffness (host out, 6 x 6 row-major, Mandel): column j of
  * S = <D (eps_j + eps(u_j))> for the six loads eps_j (host, 6 x 6, rows)
  * with solutions u (device, 6 x 3n), and out = S L^-T with L the loads as

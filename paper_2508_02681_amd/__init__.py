@@ -74,6 +74,7 @@ def lib():
         "jac_precond_apply": ([G, Mt, vp, vp, i, vp], i),
         "uno_macro_rhs": ([G, Mt, P(f64), vp, i, vp], i),
         "uno_precond_create": ([G, i32, P(f64), i64, f64, i, P(vp)], i),
+        "el_uno_precond_create": ([G, i32, P(f64), i64, f64, P(vp)], i),
         "uno_precond_create_fans": ([G, f64, i, P(vp)], i),
         "uno_precond_apply": ([vp, vp, vp, i, vp], i),
         "uno_precond_table": ([vp, P(f64), i64], i),
@@ -202,6 +203,18 @@ class UnoPrecond:
         _check(lib().uno_precond_create(ctypes.byref(g), int(M), th.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                         th.size, float(eps_spd), _dt(table_dtype), ctypes.byref(h)),
                "uno_precond_create")
+        return cls(h, shape, L0)
+
+    @classmethod
+    def create_elastic(cls, shape, M, theta, eps_spd=1e-300, L0=1.0):
+        """Three nodal DOF (elasticity): theta holds 6 weights per slot
+        (psi(w) = L L^T, L = [w1 0 0; w3 w2 0; w6 w5 w4]); apply() takes
+        3 x grid vectors."""
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        g = make_grid(shape, L0)
+        h = ctypes.c_void_p()
+        _check(lib().el_uno_precond_create(ctypes.byref(g), int(M), th.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                           th.size, float(eps_spd), ctypes.byref(h)), "el_uno_precond_create")
         return cls(h, shape, L0)
 
     @classmethod
@@ -453,8 +466,10 @@ def el_macro_rhs(lam: torch.Tensor, mu: torch.Tensor, strain, L0=1.0):
 
 
 def el_pcg_solve(lam: torch.Tensor, mu: torch.Tensor, strains, u: torch.Tensor | None = None, kind="jacobi",
-                 rtol=1e-6, max_iter=100000, graph_chunk=0, lame_per_rhs=False, L0=1.0):
-    """Jacobi-CG (or CG) for nrhs macroscopic Mandel strains (nrhs x 6).
+                 rtol=1e-6, max_iter=100000, graph_chunk=0, lame_per_rhs=False, L0=1.0,
+                 precond: UnoPrecond | None = None):
+    """CG, Jacobi-CG or UNO-CG (kind "uno" with a UnoPrecond.create_elastic)
+    for nrhs macroscopic Mandel strains (nrhs x 6).
     lam, mu: grid (shared) or nrhs x grid (lame_per_rhs).  Returns
     (u (nrhs x 3 x grid), [info])."""
     shape = tuple(lam.shape[1:]) if lame_per_rhs else tuple(lam.shape)
@@ -463,7 +478,7 @@ def el_pcg_solve(lam: torch.Tensor, mu: torch.Tensor, strains, u: torch.Tensor |
     nrhs = e.shape[0]
     if u is None:
         u = torch.zeros((nrhs, 3) + shape, dtype=torch.float64, device=lam.device)
-    o = _opts(kind, None, rtol, max_iter, torch.float64, torch.float64, graph_chunk)
+    o = _opts(kind, precond, rtol, max_iter, torch.float64, torch.float64, graph_chunk)
     infos = (uno_solve_info * nrhs)()
     _check(lib().el_pcg_solve(ctypes.byref(g), _dev(lam, "lambda", torch.float64), _dev(mu, "mu", torch.float64),
                               1 if lame_per_rhs else 0, nrhs, _dptr(e), _dev(u, "u", torch.float64), ctypes.byref(o),

@@ -332,6 +332,7 @@ uno_status uno_precond_create(const uno_grid* grid, int32_t M, const double* the
     e = fft_plan_create(p->grid, &p->plan);
     if (e != UNO_OK) { precond_free(p); return e; }
     p->M = M;
+    p->nc = 1;
     const Grid& g = p->grid;
     const int nh = p->plan.nh;
     std::vector<double> phi(p->plan.nspec);
@@ -416,7 +417,107 @@ uno_status uno_precond_create_fans(const uno_grid* grid, double kappa_ref, uno_d
             }
     e = precond_finish(p, phi, 0.0, table_t, false);
     if (e != UNO_OK) { precond_free(p); return e; }
+    p->nc = 1;
     p->rs_blocks = fft_c2r_blocks(g, p->plan);
+    UNO_HIP(hipGetDevice(&p->device));
+    *out = p;
+    return UNO_OK;
+}
+
+// psi(w) = L L^T for three nodal DOF (App. B), entries q1..q6 =
+// (Phi_11, Phi_22, Phi_12, Phi_33, Phi_23, Phi_13)
+static void psi3(const double* w, double q[6])
+{
+    const double L[3][3] = {{w[0], 0.0, 0.0}, {w[2], w[1], 0.0}, {w[5], w[4], w[3]}};
+    auto dot = [&](int i, int j) { return L[i][0] * L[j][0] + L[i][1] * L[j][1] + L[i][2] * L[j][2]; };
+    q[0] = dot(0, 0);
+    q[1] = dot(1, 1);
+    q[2] = dot(0, 1);
+    q[3] = dot(2, 2);
+    q[4] = dot(1, 2);
+    q[5] = dot(0, 2);
+}
+
+// Phi(k) before the mean over k and -k: 0 at k = 0, psi(w^0) + psi(w^s) on
+// a learned mode or its conjugate, psi(w^0) elsewhere
+static void phi3_raw(int M, const double* theta, const int* k, double q[6])
+{
+    for (int e = 0; e < 6; ++e) q[e] = 0.0;
+    if (k[0] == 0 && k[1] == 0 && k[2] == 0) return;
+    psi3(theta, q);
+    int64_t s = uno_slot(3, M, k);
+    if (s == 0 && k[2] < 0) {
+        const int mk[3] = {-k[0], -k[1], -k[2]};
+        s = uno_slot(3, M, mk);
+    }
+    if (s) {
+        double t[6];
+        psi3(theta + 6 * s, t);
+        for (int e = 0; e < 6; ++e) q[e] += t[e];
+    }
+}
+
+// smallest eigenvalue of [q1 q3 q6; q3 q2 q5; q6 q5 q4] above eps: Cholesky
+// of the block less eps I
+static bool spd_above(const double q[6], double eps)
+{
+    const double a00 = q[0] - eps, a11 = q[1] - eps, a22 = q[3] - eps, a10 = q[2], a20 = q[5], a21 = q[4];
+    if (!(a00 > 0.0)) return false;
+    const double l00 = std::sqrt(a00), l10 = a10 / l00, l20 = a20 / l00;
+    const double d1 = a11 - l10 * l10;
+    if (!(d1 > 0.0)) return false;
+    const double l11 = std::sqrt(d1), l21 = (a21 - l20 * l10) / l11;
+    return a22 - l20 * l20 - l21 * l21 > 0.0;
+}
+
+uno_status el_uno_precond_create(const uno_grid* grid, int32_t M, const double* theta, int64_t ntheta,
+                                 double eps_spd, uno_precond** out)
+{
+    if (!out || !theta || !grid) return UNO_ERR_ARG;
+    *out = nullptr;
+    if (grid->dim != 3 || M < 0) return UNO_ERR_ARG;
+    uno_precond* p = new uno_precond();
+    memset(p, 0, sizeof(*p));
+    uno_status e = make_grid(grid, &p->grid);
+    if (e != UNO_OK) { delete p; return e; }
+    for (int b = 0; b < 3; ++b)
+        if (2 * M + 1 > grid->n[b]) { delete p; return UNO_ERR_SHAPE; }
+    if (ntheta != 6 * uno_nweights(3, M)) { delete p; return UNO_ERR_SHAPE; }
+    for (int64_t i = 0; i < ntheta; ++i)
+        if (!std::isfinite(theta[i])) { delete p; return UNO_ERR_ARG; }
+    const Grid& g = p->grid;
+    // safety check of eq. (fnocg-sanity-check): every block above eps_spd
+    // (outside the learned block Phi = psi(w^0), inside the mean over +-k)
+    double W6[6];
+    psi3(theta, W6);
+    if (!spd_above(W6, eps_spd)) { delete p; return UNO_ERR_NOT_SPD; }
+    const int mx = M, kxn = 2 * M + 1, kyn = 2 * M + 1, kzn = M + 1;
+    const int64_t nblock = (int64_t)kxn * kyn * kzn;
+    const double inv_n = 1.0 / (double)g.total;
+    std::vector<double> cb(6 * nblock);
+    for (int kxi = 0; kxi < kxn; ++kxi)
+        for (int kyi = 0; kyi < kyn; ++kyi)
+            for (int kz = 0; kz < kzn; ++kz) {
+                const int k[3] = {kxi - mx, kyi - M, kz}, mk[3] = {-k[0], -k[1], -k[2]};
+                double a[6], b[6], q[6];
+                phi3_raw(M, theta, k, a);
+                phi3_raw(M, theta, mk, b);
+                for (int e2 = 0; e2 < 6; ++e2) q[e2] = 0.5 * (a[e2] + b[e2]);
+                const bool zero = k[0] == 0 && k[1] == 0 && k[2] == 0;
+                if (!zero && !spd_above(q, eps_spd)) { delete p; return UNO_ERR_NOT_SPD; }
+                const double wz = (kz == 0 ? 1.0 : 2.0) * inv_n;
+                const int64_t l = ((int64_t)kxi * kyn + kyi) * kzn + kz;
+                for (int e2 = 0; e2 < 6; ++e2) cb[6 * l + e2] = (q[e2] - W6[e2]) * wz;
+            }
+    e = fft_plan_create(p->grid, &p->plan, true);
+    if (e != UNO_OK) { precond_free(p); return e; }
+    p->M = M;
+    p->nc = 3;
+    p->table_t = UNO_F64;
+    p->path = UNO_PATH_LEARNED;
+    e = lowrank_create(g, p->plan, M, 0.0, cb, &p->lr, 3, W6);
+    if (e != UNO_OK) { precond_free(p); return e; }
+    p->rs_blocks = lowrank_max_blocks(p->lr);
     UNO_HIP(hipGetDevice(&p->device));
     *out = p;
     return UNO_OK;
@@ -425,6 +526,10 @@ uno_status uno_precond_create_fans(const uno_grid* grid, double kappa_ref, uno_d
 uno_status uno_precond_apply(const uno_precond* p, const void* r, void* s, uno_dtype vec_t, void* stream)
 {
     if (!p || !r || !s) return UNO_ERR_ARG;
+    if (p->nc == 3) {  // elasticity: learned-mode passes in FP64 only
+        if (vec_t != UNO_F64 || r == s) return UNO_ERR_ARG;
+        return lowrank_apply(p->lr, (const double*)r, (double*)s, S(stream));
+    }
     if (vec_t == UNO_F64) {
         if (uno_use_lowrank(p)) {
             if (r == s) return UNO_ERR_ARG;  // the learned-mode passes read r after writing s
@@ -441,6 +546,7 @@ uno_status uno_precond_apply(const uno_precond* p, const void* r, void* s, uno_d
 uno_status uno_precond_set_path(uno_precond* p, int32_t path)
 {
     if (!p || path < UNO_PATH_AUTO || path > UNO_PATH_FUSED) return UNO_ERR_ARG;
+    if (p->nc == 3) return (path == UNO_PATH_AUTO || path == UNO_PATH_LEARNED) ? UNO_OK : UNO_ERR_SHAPE;
     if (path == UNO_PATH_LEARNED && !p->lr) return UNO_ERR_SHAPE;
     if (path == UNO_PATH_FUSED && !(p->lr && lowrank_fused(p->lr))) return UNO_ERR_SHAPE;
     p->path = path;
@@ -449,7 +555,7 @@ uno_status uno_precond_set_path(uno_precond* p, int32_t path)
 
 uno_status uno_precond_table(const uno_precond* p, double* out, int64_t nout)
 {
-    if (!p || !out || nout != p->plan.nspec) return UNO_ERR_ARG;
+    if (!p || !out || p->nc != 1 || nout != p->plan.nspec) return UNO_ERR_ARG;
     memcpy(out, p->table_host, sizeof(double) * nout);
     return UNO_OK;
 }
@@ -469,7 +575,7 @@ static uno_status check_solve(const uno_grid* grid, const uno_material* mat, con
     if (!(opts->rtol >= 0.0) || opts->max_iter < 1) return UNO_ERR_ARG;
     if (opts->kind < UNO_PREC_NONE || opts->kind > UNO_PREC_UNO) return UNO_ERR_ARG;
     if (opts->kind == UNO_PREC_UNO) {
-        if (!opts->uno) return UNO_ERR_ARG;
+        if (!opts->uno || opts->uno->nc != 1) return UNO_ERR_ARG;
         const Grid& pg = opts->uno->grid;
         if (pg.n[0] != g->n[0] || pg.n[1] != g->n[1] || pg.n[2] != g->n[2]) return UNO_ERR_SHAPE;
     }
@@ -569,6 +675,11 @@ uno_status el_pcg_solve(const uno_grid* grid, const double* lambda, const double
     if (!(opts->rtol >= 0.0) || opts->max_iter < 1) return UNO_ERR_ARG;
     for (int k = 0; k < 6 * nrhs; ++k)
         if (!std::isfinite(strains[k])) return UNO_ERR_ARG;
+    if (opts->kind == UNO_PREC_UNO) {
+        const uno_precond* pc = opts->uno;
+        if (!pc || pc->nc != 3) return UNO_ERR_ARG;
+        if (pc->grid.n[0] != g.n[0] || pc->grid.n[1] != g.n[1] || pc->grid.n[2] != g.n[2]) return UNO_ERR_SHAPE;
+    }
     return pcg_run_el(g, lambda, mu, lame_per_rhs ? g.total : 0, nrhs, strains, u, opts, info, S(stream));
 }
 

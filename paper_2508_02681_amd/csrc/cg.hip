@@ -793,8 +793,10 @@ uno_status pcg_run_batch(const Grid& g, const double* kappa, int64_t ks, int nrh
 uno_status pcg_run_el(const Grid& g, const double* lam, const double* mu, int64_t lks, int nrhs, const double* eps6,
                       double* u, const uno_solve_opts* o, uno_solve_info* info, hipStream_t st)
 {
-    if (o->kind != UNO_PREC_NONE && o->kind != UNO_PREC_JACOBI) return UNO_ERR_ARG;
+    if (o->kind != UNO_PREC_NONE && o->kind != UNO_PREC_JACOBI && o->kind != UNO_PREC_UNO) return UNO_ERR_ARG;
     if (o->op_t != UNO_F64 || o->prec_t != UNO_F64) return UNO_ERR_ARG;
+    const uno_precond* pc = (o->kind == UNO_PREC_UNO) ? o->uno : nullptr;
+    if (o->kind == UNO_PREC_UNO && !(pc && pc->nc == 3 && pc->lr)) return UNO_ERR_ARG;
     ElDev E;
     uno_status e = el_dev(g, &E);
     if (e != UNO_OK) return e;
@@ -806,7 +808,9 @@ uno_status pcg_run_el(const Grid& g, const double* lam, const double* mu, int64_
     gd.n = N;
     Workspace* w = nullptr;
     const int hist_len = o->max_iter + 1;
-    e = ws_get(gv, nullptr, nullptr, el_march_blocks(g, nrhs), hist_len, nrhs, &w);
+    int extra = el_march_blocks(g, nrhs);
+    if (pc && lowrank_max_blocks(pc->lr) > extra) extra = lowrank_max_blocks(pc->lr);
+    e = ws_get(gv, nullptr, pc ? pc->lr : nullptr, extra, hist_len, nrhs, &w);
     if (e != UNO_OK) return e;
     const int nb = w->nbr;
     const Parts P = parts_of(w);
@@ -842,10 +846,23 @@ uno_status pcg_run_el(const Grid& g, const double* lam, const double* mu, int64_
     if (o->kind == UNO_PREC_JACOBI)
         hipLaunchKernelGGL((k_cg_init<double, 1>), grid, dim3(kBlock), 0, st, gd, (const double*)w->dinv,
                            (const double*)w->r, w->s, P.rmax, P.rs[0], P.ss[0], w->state, w->npart, dks);
+    else if (o->kind == UNO_PREC_UNO)
+        hipLaunchKernelGGL((k_cg_init<double, 2>), grid, dim3(kBlock), 0, st, gd, (const double*)w->dinv,
+                           (const double*)w->r, w->s, P.rmax, P.rs[0], P.ss[0], w->state, w->npart, dks);
     else
         hipLaunchKernelGGL((k_cg_init<double, 0>), grid, dim3(kBlock), 0, st, gd, (const double*)w->dinv,
                            (const double*)w->r, w->s, P.rmax, P.rs[0], P.ss[0], w->state, w->npart, dks);
     UNO_HIP(hipGetLastError());
+    // UNO flow per pass: [B (head) + C: s = P r, r.s] -> [d = s + beta d, p = A d, d.p]
+    // -> [update + pass A of the next pass]; the first transform here
+    LrBatch bt{};
+    int np_update = nb;
+    if (pc) {
+        bt = lowrank_batch(pc->lr, w->lr_gp, w->lr_h, nrhs);
+        np_update = lowrank_update_blocks(pc->lr, nrhs);
+        e = lowrank_forward(pc->lr, w->r, nullptr, bt, iter_of(w, P, 0, 0, 0.0, 0, nb, dks), st);
+        if (e != UNO_OK) return e;
+    }
     int k = 0;
     int chunk = o->graph_chunk > 0 ? o->graph_chunk : 8;
     std::vector<int> prev_k(nrhs, -1);
@@ -853,9 +870,21 @@ uno_status pcg_run_el(const Grid& g, const double* lam, const double* mu, int64_
     for (;;) {
         if (chunk > o->max_iter - k) chunk = o->max_iter - k;
         for (int c = 0; c < chunk; ++c, ++k) {
-            CgIter it = iter_of(w, P, k, 0, o->rtol, hist_len, nb, dks);
+            CgIter it = iter_of(w, P, k, 0, o->rtol, hist_len, np_update, dks);
             double* dold = w->d[k & 1];
             double* dnew = w->d[(k + 1) & 1];
+            if (pc) {
+                int np_rs = 0;
+                e = lowrank_finish<double>(pc->lr, w->r, w->s, &it, &np_rs, bt, st);
+                if (e != UNO_OK) return e;
+                e = launch_el_apply<true, false>(E, g, lam, mu, lks, w->s, dold, dnew, w->p, P.dp, it, P.rs[k & 1],
+                                                 np_rs, w->gam, nrhs, st);
+                if (e != UNO_OK) return e;
+                e = lowrank_update_forward<double>(pc->lr, w->r, u, (const double*)dnew, (const double*)w->p, it, P.dp,
+                                                   el_march_blocks(g, nrhs), w->gam, P.rmax, nullptr, bt, st);
+                if (e != UNO_OK) return e;
+                continue;
+            }
             e = launch_el_apply<true, true>(E, g, lam, mu, lks, w->s, dold, dnew, w->p, P.dp, it, P.rs[k & 1], nb,
                                             w->gam, nrhs, st);
             if (e != UNO_OK) return e;
@@ -872,7 +901,7 @@ uno_status pcg_run_el(const Grid& g, const double* lam, const double* mu, int64_
                            (const double*)P.dp, np_dp, (const double*)w->gam, P.rmax, rs_next, ss_next);
             UNO_HIP(hipGetLastError());
         }
-        CgIter it = iter_of(w, P, k, 0, o->rtol, hist_len, nb, dks);
+        CgIter it = iter_of(w, P, k, 0, o->rtol, hist_len, np_update, dks);
         hipLaunchKernelGGL(k_cg_check, dim3(1, nrhs), dim3(kBlock), 0, st, it);
         UNO_HIP(hipGetLastError());
         UNO_HIP(hipMemcpyAsync(w->host_state, w->state, sizeof(CgState) * nrhs, hipMemcpyDeviceToHost, st));

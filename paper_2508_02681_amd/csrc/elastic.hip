@@ -525,6 +525,9 @@ uno_status launch_el_apply(const ElDev& E, const Grid& g, const double* lam, con
 template uno_status launch_el_apply<false, false>(const ElDev&, const Grid&, const double*, const double*, int64_t,
                                                   const double*, const double*, double*, double*, double*,
                                                   const CgIter&, const double*, int, double*, int, hipStream_t);
+template uno_status launch_el_apply<true, false>(const ElDev&, const Grid&, const double*, const double*, int64_t,
+                                                 const double*, const double*, double*, double*, double*,
+                                                 const CgIter&, const double*, int, double*, int, hipStream_t);
 template uno_status launch_el_apply<true, true>(const ElDev&, const Grid&, const double*, const double*, int64_t,
                                                 const double*, const double*, double*, double*, double*,
                                                 const CgIter&, const double*, int, double*, int, hipStream_t);

@@ -327,12 +327,17 @@ static bool factorize(int n, AxisPlan* a)
     return m == 1;
 }
 
-uno_status fft_plan_create(const Grid& g, FftPlan* p)
+uno_status fft_plan_create(const Grid& g, FftPlan* p, bool twiddles_only)
 {
     memset(p, 0, sizeof(*p));
     for (int b = 0; b < 3; ++b) {
         AxisPlan& a = p->ax[b];
-        if (!factorize(g.n[b], &a)) return UNO_ERR_SHAPE;
+        if (twiddles_only) {
+            if (g.n[b] < 1) return UNO_ERR_SHAPE;
+            a.n = g.n[b];
+        } else if (!factorize(g.n[b], &a)) {
+            return UNO_ERR_SHAPE;
+        }
         std::vector<double2> t64(a.n);
         std::vector<float2> t32(a.n);
         for (int j = 0; j < a.n; ++j) {

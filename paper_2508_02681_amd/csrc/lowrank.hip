@@ -19,6 +19,14 @@
 //      s = W r + correction (and the r.s partials inside CG).
 // The passes move about 3 vectors of the grid (read r twice, write s) plus a
 // small coefficient buffer, instead of five passes over the half spectrum.
+//
+// Three nodal DOF (c = 3, App. B): Phi(k) is a symmetric 3 x 3 block per
+// mode and W the bypass block psi(w^0), so s = W r + T^H (C o T r) with the
+// 3 x 3 blocks C = Phi - W mixing the components.  Vectors are planar
+// (component c at + c n), so passes A and C run over the 3 n0 slabs of the
+// stacked components unchanged; pass B transforms the three components of a
+// column along x, mixes them by C(k) and transforms back, and pass C adds
+// the bypass product W r at each node.
 #include <cmath>
 #include <cstring>
 
@@ -33,7 +41,9 @@ struct LowRankDev {
     int n0, n1, n2;
     int mx, m;          // learned half-widths along x (0 for one voxel layer) and y, z
     int kxn, kyn, kzn;  // 2mx+1, 2m+1, m+1
-    double W;           // bypass theta0^2
+    double W;           // bypass theta0^2 (c = 1)
+    int nc;             // nodal DOF: 1, or 3 (planar components, slabs c n0 + x)
+    double Wq[6];       // c = 3: bypass block entries q1..q6 (Phi_11, Phi_22, Phi_12, Phi_33, Phi_23, Phi_13)
     int64_t gps, hsz;   // per right-hand side: row-chunk partial and H sizes (double2)
     const double2* twx; // exp(-2 pi i j / n_b) tables
     const double2* twy;
@@ -337,13 +347,101 @@ __global__ void __launch_bounds__(256) k_lr_mid(LowRankDev L, int nch, int cb, c
     }
 }
 
+// Pass B for three components: the workgroup gathers the (k_y, k_z)
+// columns of the three component slabs, transforms each along x, mixes them
+// by the 3 x 3 block of the table (C6: entries q1..q6 per mode, times
+// w(k_z) / n) and transforms the three results back.  Inside CG it also runs
+// the convergence test at the head of the pass.
+__global__ void __launch_bounds__(256) k_lr_mid3(LowRankDev L, int nch, int cb, const double* __restrict__ C6,
+                                                 const double2* __restrict__ Gp, double2* __restrict__ H, CgIter it)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double slots[4];
+    if (blockIdx.y > 0) {
+        Gp += (int64_t)blockIdx.y * L.gps;
+        H += (int64_t)blockIdx.y * L.hsz;
+        it = rhs_iter(it);
+    }
+    const int plane = L.kyn * L.kzn;
+    const int col0 = blockIdx.x * cb;
+    const int ncol = L.n0 * cb, nxk = L.kxn * cb;
+    double2* gx = (double2*)smem;   // [c][x][cl]
+    double2* X = gx + 3 * ncol;     // [c][kx][cl]
+    StateLoad sl;
+    double share = 0.0;
+    if (it.st) {
+        sl = load_state(it.st);
+        share = load_share<OpMax>(it.part_rmax, it.np_rmax);
+    }
+    const int ng = 3 * ncol;
+    auto gather = [&](int q) {  // q = c ncol + x cb + cl
+        const int c = q / ncol, rem = q % ncol;
+        const int cl = rem % cb, x = rem / cb;
+        const int col = col0 + cl;
+        double re = 0.0, im = 0.0;
+        if (col < plane) {
+            const double2* src = Gp + (int64_t)(c * L.n0 + x) * nch * plane + col;
+            for (int ch = 0; ch < nch; ++ch) {
+                const double2 v = src[(int64_t)ch * plane];
+                re += v.x;
+                im += v.y;
+            }
+        }
+        return make_double2(re, im);
+    };
+    double2 gv[kMidQB];
+#pragma unroll
+    for (int u = 0; u < kMidQB; ++u) {
+        const int q = threadIdx.x + 256 * u;
+        gv[u] = (q < ng) ? gather(q) : make_double2(0.0, 0.0);
+    }
+    if (it.st && head_decide(it, sl, share, slots)) return;
+#pragma unroll
+    for (int u = 0; u < kMidQB; ++u) {
+        const int q = threadIdx.x + 256 * u;
+        if (q < ng) gx[q] = gv[u];
+    }
+    for (int q = threadIdx.x + 256 * kMidQB; q < ng; q += 256) gx[q] = gather(q);
+    __syncthreads();
+    for (int o = threadIdx.x; o < nxk; o += 256) {
+        const int cl = o % cb, kxi = o / cb;
+        const int col = col0 + cl;
+        const double2 w = L.twx[mod_n(kxi - L.mx, L.n0)];
+        const double2 a = horner_eo(gx + cl, cb, L.n0, w);
+        const double2 b = horner_eo(gx + ncol + cl, cb, L.n0, w);
+        const double2 c = horner_eo(gx + 2 * ncol + cl, cb, L.n0, w);
+        double q[6] = {0, 0, 0, 0, 0, 0};
+        if (col < plane) {
+            const double* t = C6 + ((int64_t)kxi * plane + col) * 6;
+#pragma unroll
+            for (int e = 0; e < 6; ++e) q[e] = t[e];
+        }
+        // [q1 q3 q6; q3 q2 q5; q6 q5 q4] (a, b, c)
+        X[o] = make_double2(q[0] * a.x + q[2] * b.x + q[5] * c.x, q[0] * a.y + q[2] * b.y + q[5] * c.y);
+        X[nxk + o] = make_double2(q[2] * a.x + q[1] * b.x + q[4] * c.x, q[2] * a.y + q[1] * b.y + q[4] * c.y);
+        X[2 * nxk + o] = make_double2(q[5] * a.x + q[4] * b.x + q[3] * c.x, q[5] * a.y + q[4] * b.y + q[3] * c.y);
+    }
+    __syncthreads();
+    for (int o = threadIdx.x; o < 3 * ncol; o += 256) {
+        const int c = o / ncol, rem = o % ncol;
+        const int cl = rem % cb, x = rem / cb;
+        const int col = col0 + cl;
+        if (col >= plane) continue;
+        const double2 t = L.twx[x];
+        const double2 w = make_double2(t.x, -t.y);
+        const double2 v = horner_eo(X + c * nxk + cl, cb, L.kxn, w);
+        const double2 sh = L.twx[mod_n((int64_t)L.mx * x, L.n0)];
+        H[(int64_t)(c * L.n0 + x) * plane + col] = cmul(v, sh);
+    }
+}
+
 // Pass C: one workgroup per (x-slab, chunk of rows y).  Both partial
 // inverse transforms are evaluated with Horner's rule in the unit-modulus
 // phase factor: along y a thread owns one k_z column for two rows (each H
 // value read from LDS feeds two chains); along z a thread owns zpt points of
 // one row (each V value feeds zpt chains) and also loads, updates and writes
 // exactly those nodes.
-template <bool CG, typename TS>
+template <bool CG, typename TS, int NC>
 __global__ void __launch_bounds__(256) k_lr_inv(LowRankDev L, int y_chunk, const double* __restrict__ r,
                                                 const double2* __restrict__ H, TS* __restrict__ s, CgIter it)
 {
@@ -436,7 +534,17 @@ __global__ void __launch_bounds__(256) k_lr_inv(LowRankDev L, int y_chunk, const
                 const int z = part + tpr * (i0 + i);
                 if (z < L.n2) {
                     const double rq = (i0 == 0) ? rv[i] : r[rbase + z];
-                    const TS sv = (TS)(L.W * rq + ar[i]);
+                    double byp = L.W * rq;
+                    if (NC == 3) {  // row comp of the bypass block times the three components
+                        const int c = x / L.n0;
+                        const int64_t cs = (int64_t)L.n0 * L.n1 * L.n2;
+                        const double r0 = r[rbase + z - c * cs], r1 = r[rbase + z + (1 - c) * cs],
+                                     r2 = r[rbase + z + (2 - c) * cs];
+                        byp = c == 0 ? L.Wq[0] * r0 + L.Wq[2] * r1 + L.Wq[5] * r2
+                                     : (c == 1 ? L.Wq[2] * r0 + L.Wq[1] * r1 + L.Wq[4] * r2
+                                               : L.Wq[5] * r0 + L.Wq[4] * r1 + L.Wq[3] * r2);
+                    }
+                    const TS sv = (TS)(byp + ar[i]);
                     s[rbase + z] = sv;
                     ssum += (double)sv;
                     acc += rq * (double)sv;
@@ -766,6 +874,7 @@ struct LowRankPlan {
     int ya, yc;       // rows per group of pass A (in LDS at once), rows per workgroup of pass C
     int rb;           // rows per workgroup of pass A
     int nch_a;
+    int slabs;        // x-slabs of passes A and C: nc n0
     int blocks_a, blocks_c;
     size_t lds_a, lds_b, lds_c;
     int cb_mid, blocks_mid;  // columns per workgroup of pass B, its workgroups
@@ -786,8 +895,9 @@ static size_t lr_tile_lds(const LowRankDev& L, int tx, int tz, size_t* dyn)
 }
 
 uno_status lowrank_create(const Grid& g, const FftPlan& fp, int M, double W, const std::vector<double>& cblock,
-                          LowRankPlan** out)
+                          LowRankPlan** out, int nc, const double* Wq)
 {
+    if (nc != 1 && nc != 3) return UNO_ERR_ARG;
     LowRankPlan* p = new LowRankPlan();
     memset(p, 0, sizeof(*p));
     LowRankDev& L = p->dev;
@@ -800,11 +910,15 @@ uno_status lowrank_create(const Grid& g, const FftPlan& fp, int M, double W, con
     L.kyn = 2 * M + 1;
     L.kzn = M + 1;
     L.W = W;
+    L.nc = nc;
+    for (int e = 0; e < 6; ++e) L.Wq[e] = (nc == 3) ? Wq[e] : 0.0;
     L.twx = fp.ax[0].tw64;
     L.twy = fp.ax[1].tw64;
     L.twz = fp.ax[2].tw64;
     const int64_t nb = (int64_t)L.kxn * L.kyn * L.kzn;
-    if ((int64_t)cblock.size() != nb) { delete p; return UNO_ERR_ARG; }
+    const int64_t ntab = nb * (nc == 3 ? 6 : 1);
+    if ((int64_t)cblock.size() != ntab) { delete p; return UNO_ERR_ARG; }
+    p->slabs = nc * L.n0;
     // rows per workgroup: about 1024 nodes, so the streaming part of pass A
     // (the CG update) and pass C spread over n / 1024 workgroups
     int rows = 1024 / L.n2;
@@ -816,7 +930,7 @@ uno_status lowrank_create(const Grid& g, const FftPlan& fp, int M, double W, con
     // chunks pass B gathers stay few: about 256 workgroups per right-hand
     // side, each taking its rows ya at a time
     {
-        const int want = (256 + L.n0 - 1) / L.n0;
+        const int want = (256 + p->slabs - 1) / p->slabs;
         int rb = (L.n1 + want - 1) / want;
         rb = ((rb + p->ya - 1) / p->ya) * p->ya;
         if (rb > L.n1) rb = L.n1;
@@ -824,15 +938,15 @@ uno_status lowrank_create(const Grid& g, const FftPlan& fp, int M, double W, con
         p->rb = rb;
     }
     p->nch_a = (L.n1 + p->rb - 1) / p->rb;
-    p->blocks_a = L.n0 * p->nch_a;
-    p->blocks_c = L.n0 * ((L.n1 + p->yc - 1) / p->yc);
+    p->blocks_a = p->slabs * p->nch_a;
+    p->blocks_c = p->slabs * ((L.n1 + p->yc - 1) / p->yc);
     const int plane = L.kyn * L.kzn;
     p->lds_a = sizeof(double2) * ((size_t)L.n2 + L.n1 + (size_t)p->ya * L.kzn + plane) +
                sizeof(double) * (size_t)p->ya * L.n2;
     p->cb_mid = 8;
-    while (p->cb_mid > 1 && sizeof(double2) * (size_t)p->cb_mid * (L.n0 + L.kxn) > 48 * 1024) p->cb_mid /= 2;
+    while (p->cb_mid > 1 && sizeof(double2) * (size_t)nc * p->cb_mid * (L.n0 + L.kxn) > 48 * 1024) p->cb_mid /= 2;
     p->blocks_mid = (L.kyn * L.kzn + p->cb_mid - 1) / p->cb_mid;
-    p->lds_b = sizeof(double2) * (size_t)p->cb_mid * (L.n0 + L.kxn);
+    p->lds_b = sizeof(double2) * (size_t)nc * p->cb_mid * (L.n0 + L.kxn);
     p->lds_c = sizeof(double2) * ((size_t)plane + (size_t)p->yc * L.kzn);
     if (p->lds_a > 60 * 1024 || p->lds_b > 60 * 1024 || p->lds_c > 60 * 1024) { delete p; return UNO_ERR_SHAPE; }
     // fused operator tile: the apply's tile shape, 2-deep in x if 4 does not fit
@@ -842,20 +956,20 @@ uno_status lowrank_create(const Grid& g, const FftPlan& fp, int M, double W, con
         p->tile.tx = 2;
         p->tile.blocks = ((g.n[0] + 1) / 2) * p->tile.geom.tiles_y * p->tile.geom.tiles_z;
     }
-    p->fused = lr_tile_lds(L, p->tile.tx, p->tile.tz, &dyn) <= 64 * 1024;
+    p->fused = nc == 1 && lr_tile_lds(L, p->tile.tx, p->tile.tz, &dyn) <= 64 * 1024;
     p->lds_t = dyn;
-    const int64_t ngp = (int64_t)L.n0 * p->nch_a * plane;
-    const int64_t nh = (int64_t)L.n0 * plane;
+    const int64_t ngp = (int64_t)p->slabs * p->nch_a * plane;
+    const int64_t nh = (int64_t)p->slabs * plane;
     L.gps = ngp;
     L.hsz = nh;
-    if (hipMalloc(&p->table, sizeof(double) * nb) != hipSuccess ||
+    if (hipMalloc(&p->table, sizeof(double) * ntab) != hipSuccess ||
         hipMalloc(&p->Gp, sizeof(double2) * ngp) != hipSuccess || hipMalloc(&p->H, sizeof(double2) * nh) != hipSuccess) {
         (void)hipFree(p->table);
         (void)hipFree(p->Gp);
         delete p;
         return UNO_ERR_NOMEM;
     }
-    UNO_HIP(hipMemcpy(p->table, cblock.data(), sizeof(double) * nb, hipMemcpyHostToDevice));
+    UNO_HIP(hipMemcpy(p->table, cblock.data(), sizeof(double) * ntab, hipMemcpyHostToDevice));
     *out = p;
     return UNO_OK;
 }
@@ -882,7 +996,7 @@ LrBatch lowrank_batch(const LowRankPlan* p, double2* Gp, double2* H, int nrhs)
 {
     LrBatch b{Gp, H, nrhs, p->rb, p->nch_a};
     // at least ~2048 workgroups of pass A per launch; no more chunks than the plan's
-    const int64_t per = (int64_t)p->dev.n0 * nrhs;
+    const int64_t per = (int64_t)p->slabs * nrhs;
     int nch = (int)((2048 + per - 1) / per);
     if (nch < p->nch_a) {
         if (nch < 1) nch = 1;
@@ -896,7 +1010,7 @@ LrBatch lowrank_batch(const LowRankPlan* p, double2* Gp, double2* H, int nrhs)
 }
 int lowrank_update_blocks(const LowRankPlan* p, int nrhs)
 {
-    return p->dev.n0 * lowrank_batch(p, nullptr, nullptr, nrhs).nch;
+    return p->slabs * lowrank_batch(p, nullptr, nullptr, nrhs).nch;
 }
 void lowrank_scratch_size(const LowRankPlan* p, int64_t* ngp, int64_t* nh)
 {
@@ -919,7 +1033,7 @@ static LrBatch own(const LowRankPlan* p) { return lowrank_batch(p, p->Gp, p->H, 
 uno_status lowrank_forward(const LowRankPlan* p, const double* r, double* part_rr, const LrBatch& bt,
                            const CgIter& strides, hipStream_t st)
 {
-    uno_launch(UNO_KT_FFT_FWD, k_lr_fwd<false, double>, dim3(p->dev.n0 * bt.nch, bt.nrhs), dim3(256), p->lds_a, st,
+    uno_launch(UNO_KT_FFT_FWD, k_lr_fwd<false, double>, dim3(p->slabs * bt.nch, bt.nrhs), dim3(256), p->lds_a, st,
                p->dev, p->ya, bt.rb, (double*)r, (double*)nullptr, (const double*)nullptr, (const double*)nullptr, bt.Gp, strides,
                (const double*)nullptr, 0, (const double*)nullptr, (double*)nullptr, part_rr);
     return hip_status(hipGetLastError());
@@ -931,7 +1045,7 @@ uno_status lowrank_update_forward(const LowRankPlan* p, double* r, double* u, co
                                   const CgIter& it, const double* part_dp, int np_dp, const double* gam,
                                   double* part_rmax, double* part_rr, const LrBatch& bt, hipStream_t st)
 {
-    uno_launch(UNO_KT_UPDATE, k_lr_fwd<true, T>, dim3(p->dev.n0 * bt.nch, bt.nrhs), dim3(256), p->lds_a, st, p->dev,
+    uno_launch(UNO_KT_UPDATE, k_lr_fwd<true, T>, dim3(p->slabs * bt.nch, bt.nrhs), dim3(256), p->lds_a, st, p->dev,
                p->ya, bt.rb, r, u, d, pv, bt.Gp, it, part_dp, np_dp, gam, part_rmax, part_rr);
     return hip_status(hipGetLastError());
 }
@@ -1003,15 +1117,29 @@ uno_status lowrank_finish(const LowRankPlan* p, const double* r, T* s, const CgI
 {
     const LowRankDev& L = p->dev;
     const CgIter it = itp ? *itp : no_iter();
-    uno_launch(UNO_KT_FFT_MID, k_lr_mid, dim3(p->blocks_mid, bt.nrhs), dim3(256), p->lds_b, st, L, bt.nch,
-               p->cb_mid, (const double*)p->table, (const double2*)bt.Gp, bt.H, it, (double*)nullptr);
-    UNO_HIP(hipGetLastError());
-    if (itp)
-        uno_launch(UNO_KT_FFT_INV, k_lr_inv<true, T>, dim3(p->blocks_c, bt.nrhs), dim3(256), p->lds_c, st, L, p->yc, r,
-                   (const double2*)bt.H, s, it);
+    if (L.nc == 3)
+        uno_launch(UNO_KT_FFT_MID, k_lr_mid3, dim3(p->blocks_mid, bt.nrhs), dim3(256), p->lds_b, st, L, bt.nch,
+                   p->cb_mid, (const double*)p->table, (const double2*)bt.Gp, bt.H, it);
     else
-        uno_launch(UNO_KT_FFT_INV, k_lr_inv<false, T>, dim3(p->blocks_c, bt.nrhs), dim3(256), p->lds_c, st, L, p->yc,
-                   r, (const double2*)bt.H, s, it);
+        uno_launch(UNO_KT_FFT_MID, k_lr_mid, dim3(p->blocks_mid, bt.nrhs), dim3(256), p->lds_b, st, L, bt.nch,
+                   p->cb_mid, (const double*)p->table, (const double2*)bt.Gp, bt.H, it, (double*)nullptr);
+    UNO_HIP(hipGetLastError());
+    const dim3 grid(p->blocks_c, bt.nrhs);
+    if (itp) {
+        if (L.nc == 3)
+            uno_launch(UNO_KT_FFT_INV, k_lr_inv<true, T, 3>, grid, dim3(256), p->lds_c, st, L, p->yc, r,
+                       (const double2*)bt.H, s, it);
+        else
+            uno_launch(UNO_KT_FFT_INV, k_lr_inv<true, T, 1>, grid, dim3(256), p->lds_c, st, L, p->yc, r,
+                       (const double2*)bt.H, s, it);
+    } else {
+        if (L.nc == 3)
+            uno_launch(UNO_KT_FFT_INV, k_lr_inv<false, T, 3>, grid, dim3(256), p->lds_c, st, L, p->yc, r,
+                       (const double2*)bt.H, s, it);
+        else
+            uno_launch(UNO_KT_FFT_INV, k_lr_inv<false, T, 1>, grid, dim3(256), p->lds_c, st, L, p->yc, r,
+                       (const double2*)bt.H, s, it);
+    }
     UNO_HIP(hipGetLastError());
     if (np_rs) *np_rs = p->blocks_c;
     return UNO_OK;

@@ -103,7 +103,9 @@ struct FftPlan {
     int64_t nspec;    // n0 n1 nh complex values
 };
 
-uno_status fft_plan_create(const Grid& g, FftPlan* p);
+// twiddles_only: the tables exp(-2 pi i j / n_b) for any n_b (what the
+// learned-mode passes use), without the factorization the full passes need
+uno_status fft_plan_create(const Grid& g, FftPlan* p, bool twiddles_only = false);
 void fft_plan_destroy(FftPlan* p);
 
 struct CgIter;  // per-pass control of the CG loop (cg_ctl.h)
@@ -148,8 +150,10 @@ struct LrBatch {
     int nrhs;
     int rb, nch;
 };
+// nc = 1: cblock kxn x kyn x kzn corrections, W the bypass; nc = 3: six
+// entries per block mode (q1..q6) and the bypass block Wq (6 entries)
 uno_status lowrank_create(const Grid& g, const FftPlan& fp, int M, double W, const std::vector<double>& cblock,
-                          LowRankPlan** out);
+                          LowRankPlan** out, int nc = 1, const double* Wq = nullptr);
 void lowrank_destroy(LowRankPlan* p);
 int lowrank_max_blocks(const LowRankPlan* p);
 int lowrank_update_blocks(const LowRankPlan* p, int nrhs);
@@ -215,6 +219,7 @@ struct uno_precond {
     void* spec;           // scratch spectrum (FP64 complex, nspec values)
     unocg::LowRankPlan* lr;  // learned-mode passes (UNO tables only), or null
     int path;             // UNO_PATH_*
+    int nc;               // nodal DOF the preconditioner acts on (1, or 3 for elasticity)
     int rs_blocks;        // most r.s partials any apply path writes
     int device;
 };

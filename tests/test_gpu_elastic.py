@@ -88,3 +88,57 @@ def test_el_homogeneous_and_errors(uno):
     assert np.abs(uno.el_effective_stiffness(lam, mu, np.eye(6), u) - D).max() < 1e-12
     with pytest.raises(uno.UnoError):
         uno.el_apply(lam[:1], mu[:1], torch.zeros((3, 1, 6, 6), dtype=torch.float64, device=DEV))
+
+
+# ---- UNO preconditioner for three nodal DOF ----
+
+def _theta3(orc, M, seed):
+    rng = np.random.default_rng(seed)
+    th = 0.3 * rng.standard_normal(orc.num_weights3(M))
+    th.reshape(-1, 6)[:, [0, 1, 3]] += 1.0
+    return th
+
+
+@pytest.mark.parametrize("shape,M", [((8, 8, 8), 2), ((12, 10, 9), 3), ((5, 7, 6), 1), ((16, 16, 16), 4)])
+def test_el_uno_apply_matches_oracle(orc, uno, shape, M):
+    th = _theta3(orc, M, 90 + M)
+    P = uno.UnoPrecond.create_elastic(shape, M, th)
+    rng = np.random.default_rng(91)
+    r = rng.standard_normal((3,) + shape)
+    s = P.apply(T(r)).cpu().numpy()
+    so = orc.uno3_apply(orc.uno3_table(shape, M, th), r)
+    assert rel(s, so) < 1e-12
+
+
+def test_el_uno_precond_rejects_indefinite_and_bad_sizes(orc, uno):
+    shape, M = (8, 8, 8), 2
+    th = _theta3(orc, M, 92)
+    bad = th.copy()
+    bad[:6] = 0.0  # bypass psi = 0: not SPD
+    with pytest.raises(uno.UnoError):
+        uno.UnoPrecond.create_elastic(shape, M, bad)
+    with pytest.raises(uno.UnoError):
+        uno.UnoPrecond.create_elastic(shape, M, th[:-1])
+    with pytest.raises(uno.UnoError):
+        uno.UnoPrecond.create_elastic((4, 4, 4), M, th)  # 2M + 1 > N
+
+
+@pytest.mark.parametrize("shape,M", [((8, 8, 8), 2), ((10, 12, 8), 2)])
+def test_el_uno_cg_matches_oracle(orc, uno, shape, M):
+    """UNO-CG for c = 3 (Algorithm 2): solution and pass count of the oracle,
+    six strains carried together."""
+    lam, mu = _lame(orc, shape, 93, 10.0)
+    th = _theta3(orc, M, 94)
+    P = uno.UnoPrecond.create_elastic(shape, M, th)
+    tab = orc.uno3_table(shape, M, th)
+    loads = np.eye(6)
+    u, infos = uno.el_pcg_solve(T(lam), T(mu), loads, kind="uno", precond=P, rtol=1e-10)
+    for j in range(6):
+        f = orc.el_rhs(lam, mu, loads[j])
+        uo, ito = orc.el_pcg(lam, mu, f, "uno", rtol=1e-10, table=tab)
+        assert infos[j]["converged"]
+        assert rel(u[j].cpu().numpy(), uo) < 1e-8
+        assert abs(infos[j]["iters"] - ito) <= max(1, int(0.03 * ito))
+    Db = uno.el_effective_stiffness(T(lam), T(mu), loads, u)
+    uj, _ = uno.el_pcg_solve(T(lam), T(mu), loads, rtol=1e-10)
+    assert rel(Db, uno.el_effective_stiffness(T(lam), T(mu), loads, uj)) < 1e-8
