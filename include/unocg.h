@@ -290,6 +290,30 @@ uno_status uno_train_fit(const uno_grid *grid, int32_t M, const double *alpha, c
 uno_status uno_train_loss_grad(const uno_grid *grid, int32_t M, const double *alpha, const double *beta,
                                const double *theta, int64_t ntheta, double *loss, double *grad, void *stream);
 
+/* ---- Second-order training for three nodal DOF (App. B) -------------- */
+/* Accumulates the twelve features of App. B over ns samples (f, u: device,
+ * ns x 3n, planar components): with hats the unitary DFT of each component,
+ * alpha_1 += |f^_x|^2 / ns_total, alpha_2 (y), alpha_4 (z),
+ * alpha_3 += 2 Re(conj f^_x f^_y) / ns_total, alpha_5 (y, z), alpha_6 (x, z),
+ * beta_1 += 2 Re(conj f^_x u^_x) / ns_total, beta_2, beta_4 likewise,
+ * beta_3 += 2 Re(conj f^_x u^_y + conj f^_y u^_x) / ns_total, beta_5, beta_6.
+ * alpha, beta: device, 6 x nspec doubles each (entry e - 1 of feature e at
+ * + (e - 1) nspec, nspec = n0 n1 (n2/2 + 1) half-spectrum modes),
+ * caller-zeroed before the first call.  Asynchronous. */
+uno_status el_uno_train_accumulate(const uno_grid *grid, int32_t ns, const double *f, const double *u,
+                                   double ns_total, double *alpha, double *beta, void *stream);
+/* Algorithm 4: Newton iterations on the loss of App. B in the weights of
+ * el_uno_precond_create (ntheta = 6 (k_max + 1), out in theta), from the
+ * features of el_uno_train_accumulate, at most max_epochs steps.  The two
+ * slots of a pair k, -k on the plane k_z = 0 share one weight vector.  Each
+ * step solves (H + lam I) dw = -g with a Levenberg-Marquardt shift lam that
+ * shrinks after a step lowering the loss and grows otherwise; it stops when
+ * the gradient has dropped by 1e-10 or two steps no longer lower the loss.
+ * loss (host, nullable): the final loss less its constant <||u||^2>.
+ * Synchronous. */
+uno_status el_uno_train_fit(const uno_grid *grid, int32_t M, const double *alpha, const double *beta,
+                            int32_t max_epochs, double *theta, int64_t ntheta, double *loss, void *stream);
+
 /* ---- Timing of one kernel family (for roofline accounting) ----------- */
 enum {
     UNO_KT_NONE = 0,

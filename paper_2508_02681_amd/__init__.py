@@ -75,6 +75,8 @@ def lib():
         "uno_macro_rhs": ([G, Mt, P(f64), vp, i, vp], i),
         "uno_precond_create": ([G, i32, P(f64), i64, f64, i, P(vp)], i),
         "el_uno_precond_create": ([G, i32, P(f64), i64, f64, P(vp)], i),
+        "el_uno_train_accumulate": ([G, i32, vp, vp, f64, vp, vp, vp], i),
+        "el_uno_train_fit": ([G, i32, vp, vp, i32, P(f64), i64, P(f64), vp], i),
         "uno_precond_create_fans": ([G, f64, i, P(vp)], i),
         "uno_precond_apply": ([vp, vp, vp, i, vp], i),
         "uno_precond_table": ([vp, P(f64), i64], i),
@@ -536,3 +538,29 @@ def timing_read():
 
 def shutdown():
     _check(lib().uno_shutdown(), "uno_shutdown")
+
+
+def el_uno_train_accumulate(f: torch.Tensor, u: torch.Tensor, alpha: torch.Tensor, beta: torch.Tensor, ns_total,
+                            L0=1.0):
+    """Adds the c = 3 features of the pairs f, u (ns x 3 x grid) into alpha,
+    beta (6 x n0 x n1 x (n2/2+1), device, zeroed by the caller)."""
+    shape = tuple(f.shape[2:])
+    g = make_grid(shape, L0)
+    _check(lib().el_uno_train_accumulate(ctypes.byref(g), int(f.shape[0]), _dev(f, "f", torch.float64),
+                                         _dev(u, "u", torch.float64), float(ns_total),
+                                         _dev(alpha, "alpha", torch.float64), _dev(beta, "beta", torch.float64),
+                                         _stream()), "el_uno_train_accumulate")
+
+
+def el_uno_train_fit(shape, M, alpha: torch.Tensor, beta: torch.Tensor, max_epochs=200, L0=1.0):
+    """Newton training (Algorithm 4) of the c = 3 weights; returns (theta, loss
+    less its constant)."""
+    g = make_grid(shape, L0)
+    nw = 6 * num_weights(3, M)
+    th = np.zeros(nw)
+    loss = ctypes.c_double(0.0)
+    _check(lib().el_uno_train_fit(ctypes.byref(g), int(M), _dev(alpha, "alpha", torch.float64),
+                                  _dev(beta, "beta", torch.float64), int(max_epochs),
+                                  th.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), nw, ctypes.byref(loss),
+                                  _stream()), "el_uno_train_fit")
+    return th, loss.value
