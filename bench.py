@@ -119,6 +119,98 @@ def roofline_record(fams, bytes_per, fam_ms):
             "per_family_GBs": {fams[f]: round(bytes_per[f] / max(per_us[fams[f]], 1e-9) / 1e3, 1) for f in fams}}
 
 
+def elastic_families(uno, shape, M, nr):
+    """Kernel families of one elastic UNO-CG pass (c = 3, planar components,
+    nr right-hand sides per launch, one Lame field pair) and their
+    algorithmic bytes per launch."""
+    n = int(np.prod(shape))
+    nblk = 3 * shape[0] * (2 * M + 1) * (M + 1)  # learned block of the three components after pass A
+    fams = {uno.KT_MATVEC: "k_el_march<CG>", uno.KT_UPDATE: "k_lr_fwd<update,double>(c=3)",
+            uno.KT_FFT_MID: "k_lr_mid3", uno.KT_FFT_INV: "k_lr_inv<double,c=3>"}
+    bytes_per = {
+        uno.KT_MATVEC: nr * 3 * n * 8 * 4 + 2 * n * 8,  # read s, d_old; write d_new, p; lambda, mu
+        uno.KT_UPDATE: nr * (3 * n * 8 * 6 + nblk * 16),  # read r, u, d, p; write r, u, block spectrum
+        uno.KT_FFT_MID: nr * nblk * 16 * 2 + nblk // 3 * 48,  # block spectrum in/out; 6 table entries
+        uno.KT_FFT_INV: nr * (3 * n * 8 * 2 + nblk * 16),  # read r, H; write s
+    }
+    return fams, bytes_per
+
+
+def elastic_record(uno, si, torch, dev, M):
+    """3D linear elasticity, 128^3, six Mandel loads: UNO-CG (trained on
+    Jacobi-CG solutions of two other microstructures) vs Jacobi-CG, FP64,
+    relative residual 1e-6, effective 6 x 6 stiffness."""
+    cfg = dict(si.CONFIG_EL_128)
+    shape = cfg["shape"]
+    n = int(np.prod(shape))
+    loads = np.eye(6)
+
+    def lame(seed):
+        E, frac = si.microstructure(cfg, seed)
+        nu = cfg["nu"]
+        return (torch.tensor(E * nu / ((1 + nu) * (1 - 2 * nu)), device=dev),
+                torch.tensor(E / (2 * (1 + nu)), device=dev), frac)
+
+    t0 = time.time()
+    fs, us = [], []
+    for seed in cfg["train_seeds"]:
+        L, Mu, _ = lame(seed)
+        u, _ = uno.el_pcg_solve(L, Mu, loads, rtol=1e-8)
+        fs += [uno.el_macro_rhs(L, Mu, loads[j]) for j in range(6)]
+        us += [u[j].clone() for j in range(6)]
+    nh = shape[2] // 2 + 1
+    A = torch.zeros((6, shape[0], shape[1], nh), dtype=torch.float64, device=dev)
+    B = torch.zeros_like(A)
+    uno.el_uno_train_accumulate(torch.stack(fs), torch.stack(us), A, B, len(fs))
+    th, _ = uno.el_uno_train_fit(shape, M, A, B)
+    P = uno.UnoPrecond.create_elastic(shape, M, th)
+    del fs, us, A, B
+    log("elastic 128^3: trained M = %d on %d pairs in %.1fs" % (M, 6 * len(cfg["train_seeds"]), time.time() - t0))
+    L, Mu, frac = lame(cfg["test_seeds"][0])
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(**kw):
+        uno.el_pcg_solve(L, Mu, loads, rtol=RTOL, max_iter=3, **kw)  # warm-up: workspace, plans
+        torch.cuda.synchronize()
+        ev0.record()
+        u, inf = uno.el_pcg_solve(L, Mu, loads, rtol=RTOL, **kw)
+        ev1.record()
+        torch.cuda.synchronize()
+        return u, inf, ev0.elapsed_time(ev1)
+
+    uu, iu, tu = timed(kind="uno", precond=P)
+    uj, ij, tj = timed(kind="jacobi")
+    Du = uno.el_effective_stiffness(L, Mu, loads, uu)
+    Dj = uno.el_effective_stiffness(L, Mu, loads, uj)
+    fams, bytes_per = elastic_families(uno, shape, M, 6)
+
+    def run():
+        uno.el_pcg_solve(L, Mu, loads, kind="uno", precond=P, rtol=RTOL)
+
+    fam_ms = family_times(uno, fams, run)
+    rec = roofline_record(fams, bytes_per, fam_ms)
+    its_u = [i["iters"] for i in iu]
+    its_j = [i["iters"] for i in ij]
+    out = {
+        "workload": "3D elasticity 128^3 periodic hex8 (3 DOF/node, 6.3M DOF), spheres r 8-16 vf %.2f, E 1/100, "
+                    "nu 0.3, 6 Mandel strain loads solved together, rel. residual 1e-6, FP64" % frac,
+        "M": M,
+        "uno_cg": {"passes": its_u, "ms_per_solve": tu / 6, "converged": all(i["converged"] for i in iu),
+                   "dof_iters_per_s": 3 * n * sum(its_u) / (tu * 1e-3)},
+        "jac_cg": {"passes": its_j, "ms_per_solve": tj / 6, "converged": all(i["converged"] for i in ij),
+                   "dof_iters_per_s": 3 * n * sum(its_j) / (tj * 1e-3)},
+        "time_to_tol_speedup_uno_vs_jac": tj / tu,
+        "stiffness_uno": np.round(Du, 6).tolist(),
+        "stiffness_rel_diff_uno_vs_jac": float(np.abs(Du - Dj).max() / np.abs(Dj).max()),
+        "per_kernel": {k: rec[k] for k in ("kernel", "avg_us", "per_family_us", "per_family_GBs")},
+    }
+    log("elastic 128^3: UNO-CG %.1f ms/solve (%d passes), Jac-CG %.1f ms/solve (%d passes), speedup %.2f" %
+        (tu / 6, max(its_u), tj / 6, max(its_j), tj / tu))
+    log("elastic 128^3 per kernel: " + ", ".join("%s %.0f us %.0f GB/s" % (k, rec["per_family_us"][k], v)
+                                                  for k, v in rec["per_family_GBs"].items()))
+    return out
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -134,6 +226,8 @@ def parse():
     ap.add_argument("--cpu-iters", type=int, default=20, help="oracle UNO-CG passes timed for cpu_baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-192", action="store_true", help="skip the per-kernel roofline at 192^3")
+    ap.add_argument("--no-elastic", action="store_true", help="skip the 128^3 elasticity record")
+    ap.add_argument("--el-M", type=int, default=8, help="mode parameter of the elastic UNO preconditioner")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this size first (reference for HBM counters)")
     return ap.parse_args()
@@ -356,6 +450,11 @@ def main():
     log("d kappa_bar/d kappa: %.3f ms (%.0f GB/s), Euler identity %.1e; training step (16 pairs) %.2f ms" %
         (g_ms, grad_rec["achieved_GBs"], grad_rec["euler_identity_rel_err"], grad_rec["training_step_batch16_ms"]))
 
+    # ---------------- 3D linear elasticity, 128^3 (c = 3) ----------------
+    el = None
+    if not args.no_elastic:
+        el = elastic_record(uno, si, torch, dev, args.el_M)
+
     # ---------------- per-kernel roofline at the paper's grid size (192^3) ----------------
     big = None
     if not args.no_192:
@@ -420,6 +519,7 @@ def main():
         "roofline": roofline,
         "roofline_192": big,
         "differentiation": grad_rec,
+        "elasticity_128": el,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

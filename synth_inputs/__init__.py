@@ -113,6 +113,12 @@ CONFIG_3D_64 = dict(shape=(64, 64, 64), r_min=4.0, r_max=8.0, vf=0.25, k_matrix=
                     train_seeds=list(range(64)), test_seeds=list(range(1000, 1016)), loads=3)
 
 
+# 3D linear elasticity: Young's modulus 1 in the matrix and 100 in the
+# spheres, Poisson's ratio 0.3 in both phases, six unit Mandel strain loads
+CONFIG_EL_128 = dict(shape=(128, 128, 128), r_min=8.0, r_max=16.0, vf=0.25, k_matrix=1.0, k_incl=100.0, nu=0.3,
+                     train_seeds=[5001, 5002], test_seeds=[5000], loads=6)
+
+
 def microstructure(cfg, seed):
     phase, frac = rsa_inclusions(cfg["shape"], cfg["r_min"], cfg["r_max"], cfg["vf"], seed)
     return two_phase_kappa(phase, cfg["k_matrix"], cfg["k_incl"]), frac
