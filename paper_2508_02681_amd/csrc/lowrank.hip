@@ -440,7 +440,9 @@ __global__ void __launch_bounds__(256) k_lr_mid3(LowRankDev L, int nch, int cb, 
 // phase factor: along y a thread owns one k_z column for two rows (each H
 // value read from LDS feeds two chains); along z a thread owns zpt points of
 // one row (each V value feeds zpt chains) and also loads, updates and writes
-// exactly those nodes.
+// exactly those nodes.  NC = 3: the workgroup takes the three components of
+// its slab, so each node's three residual values are read once for the
+// bypass block and the three corrections.
 template <bool CG, typename TS, int NC>
 __global__ void __launch_bounds__(256) k_lr_inv(LowRankDev L, int y_chunk, const double* __restrict__ r,
                                                 const double2* __restrict__ H, TS* __restrict__ s, CgIter it)
@@ -459,36 +461,43 @@ __global__ void __launch_bounds__(256) k_lr_inv(LowRankDev L, int y_chunk, const
     const int y0 = (blockIdx.x % nch) * y_chunk;
     const int ny = min(y_chunk, L.n1 - y0);
     const int plane = L.kyn * L.kzn;
-    double2* Hs = (double2*)smem;        // kyn x kzn
-    double2* V = Hs + plane;             // ny x kzn
+    const int64_t cs = (int64_t)L.n0 * L.n1 * L.n2;  // component stride (NC = 3)
+    double2* Hs = (double2*)smem;        // NC x kyn x kzn
+    double2* V = Hs + NC * plane;        // NC x ny x kzn
     // z points of this thread: row t / tpr, z = t % tpr + tpr i
     const int tpr = 256 / y_chunk;
     const int row = threadIdx.x / tpr, part = threadIdx.x % tpr;
     const bool row_ok = row < ny;
     const int zpt = (L.n2 + tpr - 1) / tpr;
-    constexpr int ZB = 4;  // z points held in registers per round
+    constexpr int ZB = NC == 1 ? 4 : 2;  // z points held in registers per round
     const int64_t rbase = ((int64_t)x * L.n1 + y0 + row) * L.n2;
-    // loads first: state, the coefficient plane, phase factors and this thread's r
+    // loads first: state, the coefficient planes, phase factors and this thread's r
     StateLoad sl;
     if (CG) sl = load_state(it.st);
-    double rv[ZB];
+    double rv[NC][ZB];
 #pragma unroll
-    for (int i = 0; i < ZB; ++i) {
-        const int z = part + tpr * i;
-        rv[i] = (row_ok && z < L.n2 && i < zpt) ? r[rbase + z] : 0.0;
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int i = 0; i < ZB; ++i) {
+            const int z = part + tpr * i;
+            rv[c][i] = (row_ok && z < L.n2 && i < zpt) ? r[c * cs + rbase + z] : 0.0;
+        }
+    for (int j = threadIdx.x; j < NC * plane; j += blockDim.x) {
+        const int c = j / plane, jj = j - c * plane;
+        Hs[j] = H[(int64_t)(c * L.n0 + x) * plane + jj];
     }
-    for (int j = threadIdx.x; j < plane; j += blockDim.x) Hs[j] = H[(int64_t)x * plane + j];
     if (CG && ended(sl, it.k)) return;
     __syncthreads();
-    // V[y][kz] = exp(-i M phi_y) sum_kyi H[kyi][kz] w_y^kyi, w_y = exp(+2 pi i y / n1)
+    // V[c][y][kz] = exp(-i M phi_y) sum_kyi H[c][kyi][kz] w_y^kyi, w_y = exp(+2 pi i y / n1)
     {
         const int yh = (ny + 1) / 2;
-        for (int t = threadIdx.x; t < yh * L.kzn; t += blockDim.x) {
-            const int ya = t % yh, kz = t / yh;
+        for (int t = threadIdx.x; t < NC * yh * L.kzn; t += blockDim.x) {
+            const int c = t / (yh * L.kzn), tt = t - c * yh * L.kzn;
+            const int ya = tt % yh, kz = tt / yh;
             const int yb = (ya + yh < ny) ? ya + yh : ya;
             const double2 ta = L.twy[y0 + ya], tb = L.twy[y0 + yb];
             const double2 wa = make_double2(ta.x, -ta.y), wb = make_double2(tb.x, -tb.y);
-            const double2* hcol = Hs + kz;
+            const double2* hcol = Hs + c * plane + kz;
             double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
             for (int kyi = L.kyn - 1; kyi >= 0; --kyi) {
                 const double2 h = hcol[kyi * L.kzn];
@@ -501,53 +510,64 @@ __global__ void __launch_bounds__(256) k_lr_inv(LowRankDev L, int y_chunk, const
             }
             const double2 sa = L.twy[mod_n((int64_t)L.m * (y0 + ya), L.n1)];
             const double2 sb = L.twy[mod_n((int64_t)L.m * (y0 + yb), L.n1)];
-            V[ya * L.kzn + kz] = make_double2(ar * sa.x - ai * sa.y, ar * sa.y + ai * sa.x);
-            if (yb != ya) V[yb * L.kzn + kz] = make_double2(br * sb.x - bi * sb.y, br * sb.y + bi * sb.x);
+            double2* vc = V + (int64_t)c * ny * L.kzn;
+            vc[ya * L.kzn + kz] = make_double2(ar * sa.x - ai * sa.y, ar * sa.y + ai * sa.x);
+            if (yb != ya) vc[yb * L.kzn + kz] = make_double2(br * sb.x - bi * sb.y, br * sb.y + bi * sb.x);
         }
     }
     __syncthreads();
     // s = W r + Re sum_kz V[row][kz] w_z^kz, w_z = exp(+2 pi i z / n2)
     double acc = 0.0, ssum = 0.0;
     if (row_ok) {
-        const double2* vrow = V + row * L.kzn;
         for (int i0 = 0; i0 < zpt; i0 += ZB) {
-            double ar[ZB], ai[ZB];
+            double ar[NC][ZB], ai[NC][ZB];
             double2 w[ZB];
 #pragma unroll
             for (int i = 0; i < ZB; ++i) {
                 const int z = part + tpr * (i0 + i);
                 const double2 tz = L.twz[z < L.n2 ? z : 0];
                 w[i] = make_double2(tz.x, -tz.y);
-                ar[i] = ai[i] = 0.0;
+#pragma unroll
+                for (int c = 0; c < NC; ++c) ar[c][i] = ai[c][i] = 0.0;
             }
             for (int kz = L.kzn - 1; kz >= 0; --kz) {
-                const double2 v = vrow[kz];
 #pragma unroll
-                for (int i = 0; i < ZB; ++i) {
-                    const double nr = ar[i] * w[i].x - ai[i] * w[i].y + v.x;
-                    ai[i] = ar[i] * w[i].y + ai[i] * w[i].x + v.y;
-                    ar[i] = nr;
+                for (int c = 0; c < NC; ++c) {
+                    const double2 v = V[((int64_t)c * ny + row) * L.kzn + kz];
+#pragma unroll
+                    for (int i = 0; i < ZB; ++i) {
+                        const double nr = ar[c][i] * w[i].x - ai[c][i] * w[i].y + v.x;
+                        ai[c][i] = ar[c][i] * w[i].y + ai[c][i] * w[i].x + v.y;
+                        ar[c][i] = nr;
+                    }
                 }
             }
 #pragma unroll
             for (int i = 0; i < ZB; ++i) {
                 const int z = part + tpr * (i0 + i);
                 if (z < L.n2) {
-                    const double rq = (i0 == 0) ? rv[i] : r[rbase + z];
-                    double byp = L.W * rq;
-                    if (NC == 3) {  // row comp of the bypass block times the three components
-                        const int c = x / L.n0;
-                        const int64_t cs = (int64_t)L.n0 * L.n1 * L.n2;
-                        const double r0 = r[rbase + z - c * cs], r1 = r[rbase + z + (1 - c) * cs],
-                                     r2 = r[rbase + z + (2 - c) * cs];
-                        byp = c == 0 ? L.Wq[0] * r0 + L.Wq[2] * r1 + L.Wq[5] * r2
-                                     : (c == 1 ? L.Wq[2] * r0 + L.Wq[1] * r1 + L.Wq[4] * r2
-                                               : L.Wq[5] * r0 + L.Wq[4] * r1 + L.Wq[3] * r2);
+                    double rq[NC];
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) rq[c] = (i0 == 0) ? rv[c][i] : r[c * cs + rbase + z];
+                    if (NC == 1) {
+                        const TS sv = (TS)(L.W * rq[0] + ar[0][i]);
+                        s[rbase + z] = sv;
+                        ssum += (double)sv;
+                        acc += rq[0] * (double)sv;
+                    } else {
+                        // bypass block [q1 q3 q6; q3 q2 q5; q6 q5 q4]
+                        const double* q = L.Wq;
+                        const double b0 = q[0] * rq[0] + q[2] * rq[1 % NC] + q[5] * rq[2 % NC];
+                        const double b1 = q[2] * rq[0] + q[1] * rq[1 % NC] + q[4] * rq[2 % NC];
+                        const double b2 = q[5] * rq[0] + q[4] * rq[1 % NC] + q[3] * rq[2 % NC];
+                        const TS s0 = (TS)(b0 + ar[0][i]), s1 = (TS)(b1 + ar[1 % NC][i]),
+                                 s2 = (TS)(b2 + ar[2 % NC][i]);
+                        s[rbase + z] = s0;
+                        s[cs + rbase + z] = s1;
+                        s[2 * cs + rbase + z] = s2;
+                        ssum += (double)s0 + (double)s1 + (double)s2;
+                        acc += rq[0] * (double)s0 + rq[1 % NC] * (double)s1 + rq[2 % NC] * (double)s2;
                     }
-                    const TS sv = (TS)(byp + ar[i]);
-                    s[rbase + z] = sv;
-                    ssum += (double)sv;
-                    acc += rq * (double)sv;
                 }
             }
         }
@@ -939,7 +959,7 @@ uno_status lowrank_create(const Grid& g, const FftPlan& fp, int M, double W, con
     }
     p->nch_a = (L.n1 + p->rb - 1) / p->rb;
     p->blocks_a = p->slabs * p->nch_a;
-    p->blocks_c = p->slabs * ((L.n1 + p->yc - 1) / p->yc);
+    p->blocks_c = L.n0 * ((L.n1 + p->yc - 1) / p->yc);  // pass C takes all components of a slab
     const int plane = L.kyn * L.kzn;
     p->lds_a = sizeof(double2) * ((size_t)L.n2 + L.n1 + (size_t)p->ya * L.kzn + plane) +
                sizeof(double) * (size_t)p->ya * L.n2;
@@ -947,7 +967,7 @@ uno_status lowrank_create(const Grid& g, const FftPlan& fp, int M, double W, con
     while (p->cb_mid > 1 && sizeof(double2) * (size_t)nc * p->cb_mid * (L.n0 + L.kxn) > 48 * 1024) p->cb_mid /= 2;
     p->blocks_mid = (L.kyn * L.kzn + p->cb_mid - 1) / p->cb_mid;
     p->lds_b = sizeof(double2) * (size_t)nc * p->cb_mid * (L.n0 + L.kxn);
-    p->lds_c = sizeof(double2) * ((size_t)plane + (size_t)p->yc * L.kzn);
+    p->lds_c = sizeof(double2) * (size_t)nc * ((size_t)plane + (size_t)p->yc * L.kzn);
     if (p->lds_a > 60 * 1024 || p->lds_b > 60 * 1024 || p->lds_c > 60 * 1024) { delete p; return UNO_ERR_SHAPE; }
     // fused operator tile: the apply's tile shape, 2-deep in x if 4 does not fit
     p->tile = choose_tile(g);
