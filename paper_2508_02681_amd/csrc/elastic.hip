@@ -4,8 +4,9 @@
 // in the Mandel basis (App. A).  Displacements are planar: component c of
 // node i at u[c n + i].
 //
-// The operator is applied voxel by voxel with the element integrals
-// sum-factorized over the 2-point Gauss rule (exact for the trilinear brick),
+// The operator is applied voxel by voxel with the element integrals over
+// the 2-point Gauss rule (exact for the trilinear brick) evaluated in the
+// Walsh-Hadamard basis, where the Gauss interpolations are diagonal,
 // marching along axis 0 with the corner forces summed in registers and LDS.
 // The unit element matrices K^l, K^m of the lambda and mu parts (24 x 24)
 // are kept for the Jacobi diagonal.
@@ -69,81 +70,94 @@ void el_element_matrices(const double h[3], double K[2][576])
 
 __device__ __forceinline__ int wrap_el(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
-// Two-point Gauss interpolation of four values on the corners (p, q) of a
-// face to its four Gauss points (P (x) P) d, P = [[c0, c1], [c1, c0]]; the
-// second stage takes scaled weights (s0, s1) = (c0, c1) * scale.  P is
-// symmetric, so the same map is its own transpose.
-__device__ __forceinline__ void el_interp(const double d[4], double o[4], double c0, double c1, double s0, double s1)
+// In-place 3D Walsh-Hadamard transform of the eight corner values,
+// x^(h) = sum_v x(v) (-1)^(h.v), v = 4a + 2b + c.
+__device__ __forceinline__ void had8(double x[8])
 {
-    const double e0 = c0 * d[0] + c1 * d[1], e1 = c1 * d[0] + c0 * d[1];
-    const double e2 = c0 * d[2] + c1 * d[3], e3 = c1 * d[2] + c0 * d[3];
-    o[0] = s0 * e0 + s1 * e2;
-    o[1] = s0 * e1 + s1 * e3;
-    o[2] = s1 * e0 + s0 * e2;
-    o[3] = s1 * e1 + s0 * e3;
+#pragma unroll
+    for (int s = 1; s < 8; s <<= 1)
+#pragma unroll
+        for (int v = 0; v < 8; ++v)
+            if (!(v & s)) {
+                const double a = x[v], b = x[v | s];
+                x[v] = a + b;
+                x[v | s] = a - b;
+            }
 }
 
-// Element forces of one voxel, f = int B^T D B u (exact 2-point Gauss rule,
-// sum-factorized).  U[i][v], f[i][v]: component i at corner v = 4a + 2b + c
-// (a, b, c the corner's offsets along axes 0, 1, 2).  The gradient of
-// component i along axis j at a Gauss point depends only on the two Gauss
-// coordinates transverse to j: it is the interpolation of the four corner
-// differences along j.  The stress at the eight points is summed along j
-// before the transposed interpolation brings it back to the corners.
-__device__ __forceinline__ void el_element(const ElDev& E, double lam, double mu, const double U[3][8],
-                                           double f[3][8])
+// index of h (bit of axis j clear) among the four such h, and back
+__host__ __device__ constexpr int el_tpos(int h, int j)
 {
-    const double c0 = E.gp[0], c1 = E.gp[1];
-    double G[3][3][4];
+    return ((h >> (3 - j)) << (2 - j)) | (h & ((1 << (2 - j)) - 1));
+}
+__host__ __device__ constexpr int el_tins(int t, int j)
+{
+    return ((t >> (2 - j)) << (3 - j)) | (t & ((1 << (2 - j)) - 1));
+}
+__host__ __device__ constexpr int el_pop(int h) { return (h & 1) + ((h >> 1) & 1) + ((h >> 2) & 1); }
+
+// Element forces of one voxel, f = int B^T D B u over the exact 2-point
+// Gauss rule, computed in the Walsh-Hadamard basis of the corners and of the
+// Gauss points.  The 1D interpolation from the two ends of an edge to its
+// two Gauss points is P = [[g0, g1], [g1, g0]] = H diag(1, r) H / 2 with
+// H = [[1, 1], [1, -1]] and r = 1/sqrt 3, so in that basis every
+// interpolation is a diagonal scaling:
+//   gradient:  g^_ij(h) = -(2/h_j) r^|h| U^_i(h + e_j) for h_j = 0 (0 for
+//              h_j = 1: the gradient along j does not vary along j),
+//   stress:    s^_ij(h) = lam delta_ij sum_k g^_kk(h) + mu (g^_ij + g^_ji)(h)
+//              (pointwise and constant on the voxel, so it commutes with the
+//              transform),
+//   forces:    Y_i(h + e_j) += -(2/h_j) r^|h| (w/8) s^_ij(h),
+//              f_i = Hadamard(Y_i),
+// |h| the number of set transverse bits, w/8 the Gauss weight times the
+// voxel volume over the 8 of the inverse transform; lw, mw carry the w/8.
+// U[i][v] in: corner values of component i; out: corner forces.
+__device__ __forceinline__ void el_element(const ElDev& E, double lw, double mw, double U[3][8])
+{
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        const double* u = U[i];
-        const double d0[4] = {u[4] - u[0], u[5] - u[1], u[6] - u[2], u[7] - u[3]};  // along 0, (b, c)
-        const double d1[4] = {u[2] - u[0], u[3] - u[1], u[6] - u[4], u[7] - u[5]};  // along 1, (a, c)
-        const double d2[4] = {u[1] - u[0], u[3] - u[2], u[5] - u[4], u[7] - u[6]};  // along 2, (a, b)
-        el_interp(d0, G[i][0], c0, c1, E.gf[0][0], E.gf[0][1]);
-        el_interp(d1, G[i][1], c0, c1, E.gf[1][0], E.gf[1][1]);
-        el_interp(d2, G[i][2], c0, c1, E.gf[2][0], E.gf[2][1]);
-    }
-    double S[3][3][4];
+    for (int i = 0; i < 3; ++i) had8(U[i]);
+    double g[3][3][4];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int j = 0; j < 3; ++j)
 #pragma unroll
-            for (int k = 0; k < 4; ++k) S[i][j][k] = 0.0;
-    const double mu2 = 2.0 * mu;
+            for (int t = 0; t < 4; ++t) {
+                const int h = el_tins(t, j);
+                g[i][j][t] = E.hc[j][el_pop(h)] * U[i][h | (4 >> j)];
+            }
+    double Y[3][8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const int q0 = q >> 2, q1 = (q >> 1) & 1, q2 = q & 1;
-        const int t0 = q1 * 2 + q2, t1 = q0 * 2 + q2, t2 = q0 * 2 + q1;
-        const double g00 = G[0][0][t0], g01 = G[0][1][t1], g02 = G[0][2][t2];
-        const double g10 = G[1][0][t0], g11 = G[1][1][t1], g12 = G[1][2][t2];
-        const double g20 = G[2][0][t0], g21 = G[2][1][t1], g22 = G[2][2][t2];
-        const double lt = lam * (g00 + g11 + g22);
-        const double s01 = mu * (g01 + g10), s02 = mu * (g02 + g20), s12 = mu * (g12 + g21);
-        S[0][0][t0] += lt + mu2 * g00;
-        S[1][1][t1] += lt + mu2 * g11;
-        S[2][2][t2] += lt + mu2 * g22;
-        S[0][1][t1] += s01;
-        S[1][0][t0] += s01;
-        S[0][2][t2] += s02;
-        S[2][0][t0] += s02;
-        S[1][2][t2] += s12;
-        S[2][1][t1] += s12;
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int v = 0; v < 8; ++v) Y[i][v] = 0.0;
+#pragma unroll
+    for (int h = 0; h < 8; ++h) {
+        if (h == 7) continue;  // every direction has a set bit: no term
+        double tr = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            if (!(h & (4 >> k))) tr += g[k][k][el_tpos(h, k)];
+        const double ltr = lw * tr;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            if (h & (4 >> j)) continue;
+            const double c = E.hc[j][el_pop(h)];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                double sij = g[i][j][el_tpos(h, j)];
+                if (!(h & (4 >> i))) sij += g[j][i][el_tpos(h, i)];
+                sij *= mw;
+                if (i == j) sij += ltr;
+                Y[i][h | (4 >> j)] += c * sij;
+            }
+        }
     }
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-        double T0[4], T1[4], T2[4];
-        el_interp(S[i][0], T0, c0, c1, E.gb[0][0], E.gb[0][1]);
-        el_interp(S[i][1], T1, c0, c1, E.gb[1][0], E.gb[1][1]);
-        el_interp(S[i][2], T2, c0, c1, E.gb[2][0], E.gb[2][1]);
+        had8(Y[i]);
 #pragma unroll
-        for (int v = 0; v < 8; ++v) {
-            const int a = v >> 2, b = (v >> 1) & 1, c = v & 1;
-            const double x0 = T0[b * 2 + c], x1 = T1[a * 2 + c], x2 = T2[a * 2 + b];
-            f[i][v] = (a ? x0 : -x0) + (b ? x1 : -x1) + (c ? x2 : -x2);
-        }
+        for (int v = 0; v < 8; ++v) U[i][v] = Y[i][v];
     }
 }
 
@@ -285,7 +299,7 @@ __global__ void __launch_bounds__(256) k_el_march(ElDev E, ElGeom eg, const doub
             ln = lam[e];
             mn = mu[e];
         }
-        double U[3][8], f[3][8];
+        double U[3][8];
         const int sa = j % 3, sb = (j + 1) % 3;
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
@@ -299,20 +313,20 @@ __global__ void __launch_bounds__(256) k_el_march(ElDev E, ElGeom eg, const doub
             U[i][7] = Dl[sb][i][l0 + kElL + 1];
         }
         const double dself[3] = {U[0][0], U[1][0], U[2][0]};
-        el_element(E, le, me, U, f);
+        el_element(E, le * E.w8, me * E.w8, U);  // U becomes the corner forces
         // node plane j - 1 + x0: corners a = 0 of this voxel plus the carry
         double own_f[3];
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            const double c1 = carry[i][1] + f[i][1], c2 = carry[i][2] + f[i][2], c3 = carry[i][3] + f[i][3];
-            own_f[i] = carry[i][0] + f[i][0];
+            const double c1 = carry[i][1] + U[i][1], c2 = carry[i][2] + U[i][2], c3 = carry[i][3] + U[i][3];
+            own_f[i] = carry[i][0] + U[i][0];
             if (j >= 1) {
                 X[j & 1][i * 3 + 0][t] = c1;  // corner (0, 1): node (ly, lz + 1)
                 X[j & 1][i * 3 + 1][t] = c2;  // corner (1, 0): node (ly + 1, lz)
                 X[j & 1][i * 3 + 2][t] = c3;  // corner (1, 1)
             }
 #pragma unroll
-            for (int k = 0; k < 4; ++k) carry[i][k] = f[i][4 + k];
+            for (int k = 0; k < 4; ++k) carry[i][k] = U[i][4 + k];
         }
         if (more) store(j + 2);
         le = ln;
@@ -462,15 +476,12 @@ uno_status el_dev(const Grid& g, ElDev* out)
     out->g = g.dev;
     out->hvol = g.h[0] * g.h[1] * g.h[2];
     for (int b = 0; b < 3; ++b) out->gc[b] = 1.0 / (4.0 * g.h[b]);
-    // shape function values at the two Gauss points, (1 +- 1/sqrt 3) / 2
-    out->gp[0] = 0.5 + 0.5 / std::sqrt(3.0);
-    out->gp[1] = 0.5 - 0.5 / std::sqrt(3.0);
-    const double wq = g.h[0] * g.h[1] * g.h[2] / 8.0;  // Gauss weight times voxel volume
+    // element constants of the Hadamard-basis form: -(2/h_b) r^m, r = 1/sqrt 3,
+    // and the Gauss weight times the voxel volume over 8
+    const double rr = 1.0 / std::sqrt(3.0);
     for (int b = 0; b < 3; ++b)
-        for (int k = 0; k < 2; ++k) {
-            out->gf[b][k] = out->gp[k] / g.h[b];
-            out->gb[b][k] = out->gp[k] * wq / g.h[b];
-        }
+        for (int m = 0; m < 3; ++m) out->hc[b][m] = -2.0 / g.h[b] * (m == 0 ? 1.0 : (m == 1 ? rr : rr * rr));
+    out->w8 = g.h[0] * g.h[1] * g.h[2] / 64.0;
     out->K = K;
     return UNO_OK;
 }

@@ -181,9 +181,8 @@ struct ElDev {
     GridDev g;
     double hvol;
     double gc[3];        // centre gradient factor per axis 1 / (4 h_b)
-    double gp[2];        // 1D shape function values at the Gauss points
-    double gf[3][2];     // gp / h_b (gradient interpolation)
-    double gb[3][2];     // gp w / h_b, w = Gauss weight times voxel volume
+    double hc[3][3];     // -(2/h_b) r^m, r = 1/sqrt 3 (Hadamard-basis element)
+    double w8;           // Gauss weight times voxel volume / 8
     const double* K;     // 2 x 576 unit element matrices (device)
 };
 struct ElGeom {
