@@ -215,6 +215,33 @@ uno_status effective_tensor(const uno_grid *grid, const uno_material *mat, int32
 uno_status effective_tensor_grad(const uno_grid *grid, int32_t nload, const double *loads, const double *u,
                                  const double *weights, double *out, void *stream);
 
+/* ---- Many problems of uneven sizes (the batched solution of Sec. 4.5 for
+ * the many-query setting of Sec. 1) ---------------------------------------- */
+/* One problem: its own grid, conductivity field and load cases. */
+typedef struct {
+    uno_grid grid;
+    const double *kappa;        /* device, n doubles (FP64) */
+    int32_t nload;              /* load cases, 1..3 */
+    const double *loads;        /* host, nload x dim macroscopic gradients */
+    double *u;                  /* device, nload x n: initial guesses in, zero-mean solutions out */
+    const uno_precond *uno;     /* preconditioner of this grid (opts->kind UNO_PREC_UNO), else ignored */
+    uno_solve_info *info;       /* host, nload records, nullable */
+} uno_problem;
+
+/* Solves the load cases of nprob independent problems (Algorithm 1 or 2,
+ * FP64; opts->kind, rtol, max_iter and graph_chunk apply to all, opts->uno
+ * is ignored in favour of each problem's).  Problems with the same grid and
+ * preconditioner form a class; the load cases of a class are carried
+ * together by every pass kernel (up to 64 per launch, each with its own
+ * conductivity field and stopping test), and the classes run concurrently,
+ * each on a stream of the library's own (default priority), forked from
+ * and joined back to `stream` (a preconditioner without the learned-mode
+ * passes solves its class's load cases one at a time).  The library copies each class's fields into
+ * workspace it allocates (held until uno_shutdown).  Returns the first
+ * error, or UNO_ERR_BREAKDOWN if any load case broke down (its info says
+ * which).  Synchronous. */
+uno_status pcg_solve_many(int32_t nprob, const uno_problem *probs, const uno_solve_opts *opts, void *stream);
+
 /* ---- Linear elasticity, d = 3, three nodal DOF (Sec. 5.2) ------------ */
 /* Periodic voxel grid (grid->dim = 3, every n >= 2), trilinear hex8
  * elements, isotropic stiffness D = 3 lambda P1 + 2 mu I_sym per voxel

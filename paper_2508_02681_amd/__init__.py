@@ -75,6 +75,7 @@ def lib():
         "uno_macro_rhs": ([G, Mt, P(f64), vp, i, vp], i),
         "uno_precond_create": ([G, i32, P(f64), i64, f64, i, P(vp)], i),
         "el_uno_precond_create": ([G, i32, P(f64), i64, f64, P(vp)], i),
+        "pcg_solve_many": ([i32, P(uno_problem), P(uno_solve_opts), vp], i),
         "el_uno_train_accumulate": ([G, i32, vp, vp, f64, vp, vp, vp], i),
         "el_uno_train_fit": ([G, i32, vp, vp, i32, P(f64), i64, P(f64), vp], i),
         "uno_precond_create_fans": ([G, f64, i, P(vp)], i),
@@ -498,6 +499,47 @@ def el_effective_stiffness(lam: torch.Tensor, mu: torch.Tensor, strains, u: torc
                                         _dev(mu, "mu", torch.float64), 6, _dptr(e), _dev(u, "u", torch.float64),
                                         _dptr(out), _stream()), "el_effective_stiffness")
     return out
+
+
+class uno_problem(ctypes.Structure):
+    _fields_ = [("grid", uno_grid), ("kappa", ctypes.c_void_p), ("nload", ctypes.c_int32),
+                ("loads", ctypes.POINTER(ctypes.c_double)), ("u", ctypes.c_void_p), ("uno", ctypes.c_void_p),
+                ("info", ctypes.POINTER(uno_solve_info))]
+
+
+def pcg_solve_many(problems, kind="uno", rtol=1e-6, max_iter=100000, graph_chunk=0, L0=1.0):
+    """Solves many problems of uneven sizes in one call.  problems: list of
+    dicts with "kappa" (device grid tensor), "loads" (nload x dim), optional
+    "u" (nload x grid, zero-initialized if absent) and "precond" (UnoPrecond
+    of that grid, for kind "uno").  Returns ([u], [[info]])."""
+    n = len(problems)
+    arr = (uno_problem * n)()
+    keep = []
+    us, infos = [], []
+    for i, P in enumerate(problems):
+        kap = P["kappa"]
+        shape = tuple(kap.shape)
+        loads = np.ascontiguousarray(P["loads"], dtype=np.float64).reshape(-1, len(shape))
+        nl = loads.shape[0]
+        u = P.get("u")
+        if u is None:
+            u = torch.zeros((nl,) + shape, dtype=torch.float64, device=kap.device)
+        inf = (uno_solve_info * nl)()
+        pr = P.get("precond")
+        arr[i].grid = make_grid(shape, L0)
+        arr[i].kappa = _dev(kap, "kappa", torch.float64)
+        arr[i].nload = nl
+        arr[i].loads = loads.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        arr[i].u = _dev(u, "u", torch.float64)
+        arr[i].uno = pr.handle if (pr is not None and kind == "uno") else None
+        arr[i].info = inf
+        keep += [loads, inf]
+        us.append(u)
+        infos.append(inf)
+    o = _opts(kind, None, rtol, max_iter, torch.float64, torch.float64, graph_chunk)
+    _check(lib().pcg_solve_many(n, arr, ctypes.byref(o), _stream()), "pcg_solve_many")
+    return us, [[dict(iters=I.iters, converged=bool(I.converged), rel_res=I.rel_res, true_rel_res=I.true_rel_res)
+                 for I in inf] for inf in infos]
 
 
 def half_shape(shape):

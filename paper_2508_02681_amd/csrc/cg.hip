@@ -18,6 +18,7 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "unocg_internal.h"
 #include "reduce.h"
@@ -290,6 +291,7 @@ constexpr int kMaxStreamBlocks = 512;
 // npart, state b at state + b, history b at hist + b hist_cap.
 struct Workspace {
     int device = -1;
+    int tag = 0;              // concurrent users of one grid shape hold distinct tags
     int n[3] = {0, 0, 0};
     int64_t total = 0;
     int nbr = 0;              // workgroups of the streaming CG kernels
@@ -314,6 +316,10 @@ struct Workspace {
 };
 
 std::vector<Workspace*> g_ws;
+std::mutex g_ws_mu;
+// workspace tag of the calling host thread (the many-problem solver runs one
+// class per thread, each with a tag of its own)
+thread_local int t_ws_tag = 0;
 
 void ws_free_vectors(Workspace* w)
 {
@@ -350,16 +356,21 @@ uno_status ws_get(const Grid& g, const FftPlan* plan, const LowRankPlan* lr, int
     int dev = 0;
     UNO_HIP(hipGetDevice(&dev));
     Workspace* w = nullptr;
-    for (Workspace* c : g_ws)
-        if (c->device == dev && c->n[0] == g.n[0] && c->n[1] == g.n[1] && c->n[2] == g.n[2]) w = c;
-    if (!w) {
-        w = new Workspace();
-        w->device = dev;
-        for (int b = 0; b < 3; ++b) w->n[b] = g.n[b];
-        w->total = g.total;
-        const int64_t nb = (g.total + kBlock - 1) / kBlock;
-        w->nbr = (int)(nb < kMaxStreamBlocks ? nb : kMaxStreamBlocks);
-        g_ws.push_back(w);
+    {
+        std::lock_guard<std::mutex> lk(g_ws_mu);
+        for (Workspace* c : g_ws)
+            if (c->device == dev && c->tag == t_ws_tag && c->n[0] == g.n[0] && c->n[1] == g.n[1] && c->n[2] == g.n[2])
+                w = c;
+        if (!w) {
+            w = new Workspace();
+            w->device = dev;
+            w->tag = t_ws_tag;
+            for (int b = 0; b < 3; ++b) w->n[b] = g.n[b];
+            w->total = g.total;
+            const int64_t nb = (g.total + kBlock - 1) / kBlock;
+            w->nbr = (int)(nb < kMaxStreamBlocks ? nb : kMaxStreamBlocks);
+            g_ws.push_back(w);
+        }
     }
     if (nrhs > w->nrhs_cap) {
         ws_free_vectors(w);
@@ -432,8 +443,11 @@ uno_status ws_get(const Grid& g, const FftPlan* plan, const LowRankPlan* lr, int
 
 }  // namespace
 
+void ws_set_tag(int tag) { t_ws_tag = tag; }
+
 uno_status ws_release_all()
 {
+    std::lock_guard<std::mutex> lk(g_ws_mu);
     for (Workspace* w : g_ws) ws_free(w);
     g_ws.clear();
     return UNO_OK;

@@ -1,0 +1,86 @@
+"""GPU: many problems of uneven sizes in one call (2D and 3D grids mixed,
+1-3 load cases each, Jacobi-CG and UNO-CG): every load case equals the
+oracle's solution, and equals the same problem solved on its own."""
+import numpy as np
+import pytest
+import torch
+
+import synth_inputs as si
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+@pytest.fixture(scope="module")
+def uno():
+    import paper_2508_02681_amd as u
+    u.lib()
+    assert torch.cuda.is_available()
+    return u
+
+
+def T(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+
+
+SHAPES = [(12, 12), (16, 20), (8, 8, 8), (10, 12, 8), (12, 12)]
+
+
+def work_list(seed):
+    rng = np.random.default_rng(seed)
+    probs = []
+    for i in range(11):
+        shape = SHAPES[i % len(SHAPES)]
+        ph, _ = si.rsa_inclusions(shape, 1.5, 2.5, 0.25, seed + i)
+        contrast = float(np.exp(rng.uniform(np.log(10.0), np.log(1000.0))))
+        kap = si.two_phase_kappa(ph, 1.0, contrast)
+        nl = 1 + i % 3 if len(shape) == 3 else 1 + i % 2
+        loads = rng.standard_normal((nl, len(shape)))
+        probs.append((kap, loads))
+    return probs
+
+
+def test_many_jacobi_matches_oracle_and_single(orc, uno):
+    probs = work_list(300)
+    us, infos = uno.pcg_solve_many([{"kappa": T(k), "loads": l} for k, l in probs], kind="jacobi", rtol=1e-10)
+    for (kap, loads), u, inf in zip(probs, us, infos):
+        assert len(inf) == len(loads)
+        ub, ib = uno.pcg_solve_batch(T(kap), macro_loads=loads, kind="jacobi", rtol=1e-10)
+        for j in range(len(loads)):
+            assert inf[j]["converged"]
+            uo, ito, _, _ = orc.pcg(kap, orc.rhs(kap, loads[j]), "jacobi", rtol=1e-10)
+            ug = u[j].cpu().numpy()
+            assert np.abs(ug - uo).max() < 1e-8 * np.abs(uo).max()
+            assert abs(inf[j]["iters"] - ito) <= max(1, int(0.03 * ito))
+            assert (u[j] - ub[j]).abs().max().item() < 1e-8 * ub[j].abs().max().item()
+
+
+def test_many_uno_per_grid_preconditioners(orc, uno):
+    probs = work_list(400)
+    pre = {}
+    for kap, _ in probs:
+        shape = kap.shape
+        if shape not in pre:
+            M = 2
+            pre[shape] = uno.UnoPrecond.create(shape, M, si.random_theta(uno.num_weights(len(shape), M), 7,
+                                                                         scale=0.05))
+    us, infos = uno.pcg_solve_many([{"kappa": T(k), "loads": l, "precond": pre[k.shape]} for k, l in probs],
+                                   kind="uno", rtol=1e-9)
+    for (kap, loads), u, inf in zip(probs, us, infos):
+        P = pre[kap.shape]
+        ub, ib = uno.pcg_solve_batch(T(kap), macro_loads=loads, kind="uno", precond=P, rtol=1e-9)
+        for j in range(len(loads)):
+            assert inf[j]["converged"]
+            assert abs(inf[j]["iters"] - ib[j]["iters"]) <= 1
+            scale = ub[j].abs().max().item()
+            assert (u[j] - ub[j]).abs().max().item() < 1e-7 * scale
+
+
+def test_many_errors_and_empty(uno):
+    assert uno.pcg_solve_many([], kind="jacobi") == ([], [])
+    k = T(np.ones((8, 8)))
+    with pytest.raises(uno.UnoError):
+        uno.pcg_solve_many([{"kappa": k, "loads": np.zeros((4, 2))}], kind="jacobi")  # 4 loads
+    with pytest.raises(uno.UnoError):
+        uno.pcg_solve_many([{"kappa": k, "loads": np.eye(2)}], kind="uno")  # no preconditioner
