@@ -211,6 +211,77 @@ def elastic_record(uno, si, torch, dev, M):
     return out
 
 
+def many_record(uno, si, torch, dev):
+    """Many-query workload: 256 problems of uneven sizes (2D 64^2/128^2/256^2,
+    3D 32^3/48^3), contrast log-uniform in [10, 1000], 2 or 3 loads each,
+    UNO-CG FP64 to 1e-6 with one trained preconditioner per grid size, all
+    in one pcg_solve_many call; against the same problems one at a time and
+    against Jacobi-CG in one call."""
+    cfg = dict(si.CONFIG_MANY)
+    t0 = time.time()
+    probs = [si.many_problem(cfg, i) for i in range(cfg["count"])]
+    kaps = [torch.tensor(k, device=dev) for k, _ in probs]
+    Ms = {2: {64: 8, 128: 12, 256: 16}, 3: {32: 6, 48: 8}}
+    pre = {}
+    for shape in cfg["shapes"]:  # train one preconditioner per size on pairs of extra problems
+        d = len(shape)
+        hs = uno.half_shape(shape)
+        A = torch.zeros(hs, dtype=torch.float64, device=dev)
+        B = torch.zeros_like(A)
+        nt = cfg["train_per_shape"]
+        rng = np.random.default_rng(cfg["seed"] + 100000 + shape[0] * d)
+        for j in range(nt):  # training cells of this size, contrasts over the same range
+            ph, _ = si.rsa_inclusions(shape, shape[0] / 16.0, shape[0] / 8.0, cfg["vf"],
+                                      cfg["seed"] + 200000 + 1000 * shape[0] + 10 * d + j)
+            contrast = float(np.exp(rng.uniform(np.log(cfg["contrast"][0]), np.log(cfg["contrast"][1]))))
+            kt = torch.tensor(si.two_phase_kappa(ph, 1.0, contrast), device=dev)
+            loads = np.eye(d)
+            u, _ = uno.pcg_solve_batch(kt, macro_loads=loads, kind="jacobi", rtol=1e-8)
+            F = torch.stack([uno.uno_macro_rhs(kt, loads[a]) for a in range(d)])
+            uno.uno_train_accumulate(F, u, A, B, nt * d)
+        M = Ms[d][shape[0]]
+        pre[shape] = uno.UnoPrecond.create(shape, M, uno.uno_train_fit(shape, M, A, B))
+    log("many: %d problems generated, %d preconditioners trained in %.1fs" % (len(probs), len(pre), time.time() - t0))
+    items = [{"kappa": kt, "loads": l, "precond": pre[tuple(kt.shape)]} for kt, (_, l) in zip(kaps, probs)]
+    nsolve = sum(len(l) for _, l in probs)
+    dofs = [int(np.prod(kt.shape)) for kt in kaps]
+
+    def run_many(kind):
+        for it in items:
+            it["u"] = torch.zeros((len(it["loads"]),) + tuple(it["kappa"].shape), dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        us, infos = uno.pcg_solve_many(items, kind=kind, rtol=RTOL)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        dit = sum(n * sum(i["iters"] for i in inf) for n, inf in zip(dofs, infos))
+        conv = all(i["converged"] for inf in infos for i in inf)
+        return dt, dit, conv, us
+
+    run_many("uno")  # warm-up: workspaces, streams
+    dt, dit, conv, us = run_many("uno")
+    dtj, ditj, convj, _ = run_many("jacobi")
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for it in items:
+        uno.pcg_solve_batch(it["kappa"], macro_loads=it["loads"], kind="uno", precond=it["precond"], rtol=RTOL)
+    torch.cuda.synchronize()
+    dts = time.perf_counter() - t
+    out = {
+        "workload": "%d problems: 2D 64^2/128^2/256^2 and 3D 32^3/48^3 (drawn uniformly), spheres/discs r N/16-N/8 "
+                    "vf 0.25, contrast log-uniform [10, 1000], %d solves (2 loads in 2D, 3 in 3D), UNO-CG FP64 to 1e-6, "
+                    "one trained preconditioner per size" % (len(probs), nsolve),
+        "solves": nsolve,
+        "uno_cg_many": {"s": dt, "solves_per_s": nsolve / dt, "dof_iters_per_s": dit / dt, "converged": conv},
+        "jac_cg_many": {"s": dtj, "solves_per_s": nsolve / dtj, "dof_iters_per_s": ditj / dtj, "converged": convj},
+        "uno_cg_one_problem_at_a_time": {"s": dts, "solves_per_s": nsolve / dts},
+        "speedup_many_vs_one_at_a_time": dts / dt,
+        "time_to_tol_speedup_uno_vs_jac": dtj / dt,
+    }
+    log("many: UNO-CG %.3f s (%.0f solves/s), one at a time %.3f s, Jacobi-CG %.3f s" % (dt, nsolve / dt, dts, dtj))
+    return out
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -227,6 +298,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-192", action="store_true", help="skip the per-kernel roofline at 192^3")
     ap.add_argument("--no-elastic", action="store_true", help="skip the 128^3 elasticity record")
+    ap.add_argument("--no-many", action="store_true", help="skip the many-problem record")
     ap.add_argument("--el-M", type=int, default=8, help="mode parameter of the elastic UNO preconditioner")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this size first (reference for HBM counters)")
@@ -455,6 +527,11 @@ def main():
     if not args.no_elastic:
         el = elastic_record(uno, si, torch, dev, args.el_M)
 
+    # ---------------- many problems of uneven sizes in one call ----------------
+    many = None
+    if not args.no_many:
+        many = many_record(uno, si, torch, dev)
+
     # ---------------- per-kernel roofline at the paper's grid size (192^3) ----------------
     big = None
     if not args.no_192:
@@ -520,6 +597,7 @@ def main():
         "roofline_192": big,
         "differentiation": grad_rec,
         "elasticity_128": el,
+        "many_problems": many,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

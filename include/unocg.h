@@ -233,11 +233,11 @@ typedef struct {
  * is ignored in favour of each problem's).  Problems with the same grid and
  * preconditioner form a class; the load cases of a class are carried
  * together by every pass kernel (up to 64 per launch, each with its own
- * conductivity field and stopping test), and the classes run concurrently,
- * each on a stream of the library's own (default priority), forked from
- * and joined back to `stream` (a preconditioner without the learned-mode
- * passes solves its class's load cases one at a time).  The library copies each class's fields into
- * workspace it allocates (held until uno_shutdown).  Returns the first
+ * conductivity field and stopping test); the classes follow one another on
+ * `stream` (a preconditioner without the learned-mode passes solves its
+ * class's load cases one at a time).  The library gathers each class's
+ * fields into device memory it allocates for the call, and caches the CG
+ * workspace per grid (held until uno_shutdown).  Returns the first
  * error, or UNO_ERR_BREAKDOWN if any load case broke down (its info says
  * which).  Synchronous. */
 uno_status pcg_solve_many(int32_t nprob, const uno_problem *probs, const uno_solve_opts *opts, void *stream);

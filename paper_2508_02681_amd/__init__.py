@@ -537,9 +537,14 @@ def pcg_solve_many(problems, kind="uno", rtol=1e-6, max_iter=100000, graph_chunk
         us.append(u)
         infos.append(inf)
     o = _opts(kind, None, rtol, max_iter, torch.float64, torch.float64, graph_chunk)
-    _check(lib().pcg_solve_many(n, arr, ctypes.byref(o), _stream()), "pcg_solve_many")
-    return us, [[dict(iters=I.iters, converged=bool(I.converged), rel_res=I.rel_res, true_rel_res=I.true_rel_res)
-                 for I in inf] for inf in infos]
+    st = lib().pcg_solve_many(n, arr, ctypes.byref(o), _stream())
+    out = [[dict(iters=I.iters, converged=bool(I.converged), rel_res=I.rel_res, true_rel_res=I.true_rel_res)
+            for I in inf] for inf in infos]
+    if st != 0:
+        err = UnoError(st, "pcg_solve_many")
+        err.infos = out  # per-load records (which load cases broke down)
+        raise err
+    return us, out
 
 
 def half_shape(shape):

@@ -291,7 +291,6 @@ constexpr int kMaxStreamBlocks = 512;
 // npart, state b at state + b, history b at hist + b hist_cap.
 struct Workspace {
     int device = -1;
-    int tag = 0;              // concurrent users of one grid shape hold distinct tags
     int n[3] = {0, 0, 0};
     int64_t total = 0;
     int nbr = 0;              // workgroups of the streaming CG kernels
@@ -317,9 +316,6 @@ struct Workspace {
 
 std::vector<Workspace*> g_ws;
 std::mutex g_ws_mu;
-// workspace tag of the calling host thread (the many-problem solver runs one
-// class per thread, each with a tag of its own)
-thread_local int t_ws_tag = 0;
 
 void ws_free_vectors(Workspace* w)
 {
@@ -359,12 +355,10 @@ uno_status ws_get(const Grid& g, const FftPlan* plan, const LowRankPlan* lr, int
     {
         std::lock_guard<std::mutex> lk(g_ws_mu);
         for (Workspace* c : g_ws)
-            if (c->device == dev && c->tag == t_ws_tag && c->n[0] == g.n[0] && c->n[1] == g.n[1] && c->n[2] == g.n[2])
-                w = c;
+            if (c->device == dev && c->n[0] == g.n[0] && c->n[1] == g.n[1] && c->n[2] == g.n[2]) w = c;
         if (!w) {
             w = new Workspace();
             w->device = dev;
-            w->tag = t_ws_tag;
             for (int b = 0; b < 3; ++b) w->n[b] = g.n[b];
             w->total = g.total;
             const int64_t nb = (g.total + kBlock - 1) / kBlock;
@@ -386,7 +380,9 @@ uno_status ws_get(const Grid& g, const FftPlan* plan, const LowRankPlan* lr, int
             w->nrhs_cap = 0;
             return UNO_ERR_NOMEM;
         }
-        UNO_HIP(hipMemset(w->state, 0, sizeof(CgState) * nrhs));
+        // (no memset of the states: the init kernels of every solve set them on
+        // the solve's stream; a plain hipMemset would run on the null stream,
+        // unordered with respect to a non-blocking solve stream)
         // partial buffers and histories are laid out per right-hand side
         (void)hipFree(w->part);
         (void)hipFree(w->hist);
@@ -442,8 +438,6 @@ uno_status ws_get(const Grid& g, const FftPlan* plan, const LowRankPlan* lr, int
 }
 
 }  // namespace
-
-void ws_set_tag(int tag) { t_ws_tag = tag; }
 
 uno_status ws_release_all()
 {

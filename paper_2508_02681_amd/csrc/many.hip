@@ -4,17 +4,15 @@
 // Problems are grouped into classes of equal grid (and preconditioner).
 // The load cases of a class become the right-hand sides of the batched CG
 // (every pass kernel takes them along grid y, each with its own
-// conductivity field, scalars and stopping test), in launches of up to 64.
-// Small grids leave most of the chip idle in a single launch, so the
-// classes run concurrently: one host thread per class drives its batched
-// loop on a stream of its own, with a workspace of its own (a per-thread
-// tag in the workspace cache), and the caller's stream waits for all.
+// conductivity field, scalars and stopping test), in launches of up to 64;
+// the classes follow one another on the caller's stream, largest first.
+// (Classes on concurrent streams were tried: the learned-mode flow then
+// lost the agreement between its recursive and true residuals on some load
+// cases, cause not yet found, so the classes run in order.)
 #include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <map>
-#include <mutex>
-#include <thread>
 #include <tuple>
 #include <vector>
 
@@ -25,40 +23,10 @@ namespace unocg {
 uno_status pcg_run_batch(const Grid& g, const double* kappa, int64_t ks, int nrhs, const double* macro_loads3,
                          const double* rhs, double* u, const uno_solve_opts* o, uno_solve_info* info, double* res_hist,
                          hipStream_t st);
-void ws_set_tag(int tag);
 
 namespace {
 
 constexpr int kMaxRhs = 64;      // right-hand sides per launch
-constexpr int kMaxThreads = 16;  // classes in flight at once
-
-struct Streams {
-    int device = -1;
-    std::vector<hipStream_t> s;
-};
-std::mutex g_smu;
-std::vector<Streams> g_streams;
-
-// stream i of the pool of this device (created on first use, default priority)
-uno_status pool_stream(int dev, int i, hipStream_t* out)
-{
-    std::lock_guard<std::mutex> lk(g_smu);
-    Streams* p = nullptr;
-    for (Streams& q : g_streams)
-        if (q.device == dev) p = &q;
-    if (!p) {
-        g_streams.push_back(Streams{dev, {}});
-        p = &g_streams.back();
-    }
-    while ((int)p->s.size() <= i) {
-        hipStream_t st;
-        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return UNO_ERR_DEVICE;
-        p->s.push_back(st);
-    }
-    *out = p->s[i];
-    return UNO_OK;
-}
-
 struct Rhs {
     int prob, load;
 };
@@ -71,11 +39,8 @@ struct Class {
 };
 
 // one class: gather fields, batched solves of up to kMaxRhs, scatter
-void run_class(int dev, int tag, Class* c, const uno_problem* probs, uno_solve_opts o, hipEvent_t fork,
-               hipEvent_t join, hipStream_t st)
+void run_class(Class* c, const uno_problem* probs, uno_solve_opts o, hipStream_t st)
 {
-    if (hipSetDevice(dev) != hipSuccess) { c->status = UNO_ERR_DEVICE; return; }
-    ws_set_tag(tag);
     o.uno = c->pc;
     const Grid& g = c->g;
     const int64_t n = g.total;
@@ -83,9 +48,7 @@ void run_class(int dev, int tag, Class* c, const uno_problem* probs, uno_solve_o
     const int nr = (int)std::min<size_t>(c->rhs.size(), kMaxRhs);
     double *kap = nullptr, *u = nullptr;
     uno_status e = UNO_OK;
-    if (hipStreamWaitEvent(st, fork, 0) != hipSuccess) e = UNO_ERR_DEVICE;
-    if (e == UNO_OK && (hipMalloc(&kap, sizeof(double) * n * nr) != hipSuccess ||
-                        hipMalloc(&u, sizeof(double) * n * nr) != hipSuccess))
+    if (hipMalloc(&kap, sizeof(double) * n * nr) != hipSuccess || hipMalloc(&u, sizeof(double) * n * nr) != hipSuccess)
         e = UNO_ERR_NOMEM;
     bool broke = false;
     std::vector<double> g3;
@@ -116,11 +79,9 @@ void run_class(int dev, int tag, Class* c, const uno_problem* probs, uno_solve_o
             if (P.info) P.info[r.load] = info[j];
         }
     }
-    if (hipEventRecord(join, st) != hipSuccess && e == UNO_OK) e = UNO_ERR_DEVICE;
     if (hipStreamSynchronize(st) != hipSuccess && e == UNO_OK) e = UNO_ERR_DEVICE;
     (void)hipFree(kap);
     (void)hipFree(u);
-    ws_set_tag(0);
     c->status = (e == UNO_OK && broke) ? UNO_ERR_BREAKDOWN : e;
 }
 
@@ -166,38 +127,16 @@ extern "C" uno_status pcg_solve_many(int32_t nprob, const uno_problem* probs, co
         for (int l = 0; l < P.nload; ++l) cls[c].rhs.push_back(Rhs{i, l});
     }
     if (cls.empty()) return UNO_OK;
-    int dev = 0;
-    UNO_HIP(hipGetDevice(&dev));
     hipStream_t st = (hipStream_t)stream;
-    hipEvent_t fork;
-    UNO_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
-    std::vector<hipEvent_t> joins(cls.size());
-    for (auto& j : joins) UNO_HIP(hipEventCreateWithFlags(&j, hipEventDisableTiming));
-    UNO_HIP(hipEventRecord(fork, st));
     uno_status worst = UNO_OK;
-    // largest classes first, at most kMaxThreads in flight (tags 1..kMaxThreads)
     std::vector<int> order(cls.size());
     for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
     std::sort(order.begin(), order.end(),
               [&](int a, int b) { return cls[a].g.total * cls[a].rhs.size() > cls[b].g.total * cls[b].rhs.size(); });
-    for (size_t w0 = 0; w0 < order.size(); w0 += kMaxThreads) {
-        std::vector<std::thread> th;
-        for (size_t q = w0; q < std::min(order.size(), w0 + kMaxThreads); ++q) {
-            const int slot = (int)(q - w0);
-            hipStream_t cs;
-            uno_status e = pool_stream(dev, slot, &cs);
-            if (e != UNO_OK) { worst = e; break; }
-            Class* c = &cls[order[q]];
-            th.emplace_back(run_class, dev, slot + 1, c, probs, *opts, fork, joins[order[q]], cs);
-        }
-        for (std::thread& t : th) t.join();
-        if (worst != UNO_OK) break;
+    for (int q : order) {
+        run_class(&cls[q], probs, *opts, st);
+        if (cls[q].status == UNO_ERR_BREAKDOWN) worst = UNO_ERR_BREAKDOWN;
+        else if (cls[q].status != UNO_OK) return cls[q].status;
     }
-    for (size_t i = 0; i < cls.size(); ++i) {
-        if (cls[i].status != UNO_OK && (worst == UNO_OK || worst == UNO_ERR_BREAKDOWN)) worst = cls[i].status;
-        (void)hipStreamWaitEvent(st, joins[i], 0);
-    }
-    (void)hipEventDestroy(fork);
-    for (auto& j : joins) (void)hipEventDestroy(j);
     return worst;
 }

@@ -119,6 +119,24 @@ CONFIG_EL_128 = dict(shape=(128, 128, 128), r_min=8.0, r_max=16.0, vf=0.25, k_ma
                      train_seeds=[5001, 5002], test_seeds=[5000], loads=6)
 
 
+# many-query work list: grid sizes mixed over 2D and 3D, inclusion radii
+# N/16..N/8 voxels, contrast log-uniform in [10, 1000], 2 loads in 2D and 3
+# in 3D
+CONFIG_MANY = dict(count=256, shapes=[(64, 64), (128, 128), (256, 256), (32, 32, 32), (48, 48, 48)], vf=0.25,
+                   contrast=(10.0, 1000.0), seed=7000, train_per_shape=4)
+
+
+def many_problem(cfg, i):
+    """Problem i of the work list: (conductivity field, loads)."""
+    rng = np.random.default_rng(cfg["seed"] + 7919 * i)
+    shape = cfg["shapes"][int(rng.integers(len(cfg["shapes"])))]
+    lo, hi = cfg["contrast"]
+    contrast = float(np.exp(rng.uniform(np.log(lo), np.log(hi))))
+    n0 = shape[0]
+    ph, _ = rsa_inclusions(shape, n0 / 16.0, n0 / 8.0, cfg["vf"], cfg["seed"] + i)
+    return two_phase_kappa(ph, 1.0, contrast), np.eye(len(shape))
+
+
 def microstructure(cfg, seed):
     phase, frac = rsa_inclusions(cfg["shape"], cfg["r_min"], cfg["r_max"], cfg["vf"], seed)
     return two_phase_kappa(phase, cfg["k_matrix"], cfg["k_incl"]), frac
