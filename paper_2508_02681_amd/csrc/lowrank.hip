@@ -528,7 +528,11 @@ __global__ void __launch_bounds__(256) k_lr_inv(LowRankDev L, int y_chunk, const
                 const double2 tz = L.twz[z < L.n2 ? z : 0];
                 w[i] = make_double2(tz.x, -tz.y);
 #pragma unroll
-                for (int c = 0; c < NC; ++c) ar[c][i] = ai[c][i] = 0.0;
+                for (int c = 0; c < NC; ++c) {
+                    ar[c][i] = ai[c][i] = 0.0;
+                    // this round's residual values, loaded ahead of the chains
+                    if (i0 > 0) rv[c][i] = (z < L.n2) ? r[c * cs + rbase + z] : 0.0;
+                }
             }
             for (int kz = L.kzn - 1; kz >= 0; --kz) {
 #pragma unroll
@@ -548,7 +552,7 @@ __global__ void __launch_bounds__(256) k_lr_inv(LowRankDev L, int y_chunk, const
                 if (z < L.n2) {
                     double rq[NC];
 #pragma unroll
-                    for (int c = 0; c < NC; ++c) rq[c] = (i0 == 0) ? rv[c][i] : r[c * cs + rbase + z];
+                    for (int c = 0; c < NC; ++c) rq[c] = rv[c][i];
                     if (NC == 1) {
                         const TS sv = (TS)(L.W * rq[0] + ar[0][i]);
                         s[rbase + z] = sv;
@@ -891,7 +895,8 @@ struct LowRankPlan {
     double* table;    // kxn x kyn x kzn, w(kz) C(k) / n
     double2* Gp;      // n0 x nch_a x kyn x kzn row-chunk partials
     double2* H;       // n0 x kyn x kzn
-    int ya, yc;       // rows per group of pass A (in LDS at once), rows per workgroup of pass C
+    int ya, yc;       // rows per group of pass A (in LDS at once), fewest rows per workgroup of pass C
+    int yc_max;       // most rows per workgroup of pass C (its LDS is sized for them)
     int rb;           // rows per workgroup of pass A
     int nch_a;
     int slabs;        // x-slabs of passes A and C: nc n0
@@ -967,7 +972,15 @@ uno_status lowrank_create(const Grid& g, const FftPlan& fp, int M, double W, con
     while (p->cb_mid > 1 && sizeof(double2) * (size_t)nc * p->cb_mid * (L.n0 + L.kxn) > 48 * 1024) p->cb_mid /= 2;
     p->blocks_mid = (L.kyn * L.kzn + p->cb_mid - 1) / p->cb_mid;
     p->lds_b = sizeof(double2) * (size_t)nc * p->cb_mid * (L.n0 + L.kxn);
-    p->lds_c = sizeof(double2) * (size_t)nc * ((size_t)plane + (size_t)p->yc * L.kzn);
+    // pass C takes up to 64 rows per workgroup when many right-hand sides
+    // fill the chip (fewer loads of the H plane per node, longer z chains)
+    p->yc_max = p->yc;
+    for (int y = 64; y > p->yc; y /= 2)
+        if (y <= L.n1 && sizeof(double2) * (size_t)nc * ((size_t)plane + (size_t)y * L.kzn) <= 60 * 1024) {
+            p->yc_max = y;
+            break;
+        }
+    p->lds_c = sizeof(double2) * (size_t)nc * ((size_t)plane + (size_t)p->yc_max * L.kzn);
     if (p->lds_a > 60 * 1024 || p->lds_b > 60 * 1024 || p->lds_c > 60 * 1024) { delete p; return UNO_ERR_SHAPE; }
     // fused operator tile: the apply's tile shape, 2-deep in x if 4 does not fit
     p->tile = choose_tile(g);
@@ -1014,7 +1027,15 @@ int lowrank_max_blocks(const LowRankPlan* p)
 bool lowrank_fused(const LowRankPlan* p) { return p->fused; }
 LrBatch lowrank_batch(const LowRankPlan* p, double2* Gp, double2* H, int nrhs)
 {
-    LrBatch b{Gp, H, nrhs, p->rb, p->nch_a};
+    LrBatch b{Gp, H, nrhs, p->rb, p->nch_a, p->yc};
+    // pass C: rows per workgroup for about 2048 workgroups per launch, a
+    // power of two between the plan's smallest and largest
+    {
+        const int64_t want = ((int64_t)p->dev.n0 * p->dev.n1 * nrhs + 2047) / 2048;
+        int yc = p->yc;
+        while (yc < p->yc_max && yc < want) yc *= 2;
+        b.yc = yc < p->yc_max ? yc : p->yc_max;
+    }
     // at least ~2048 workgroups of pass A per launch; no more chunks than the plan's
     const int64_t per = (int64_t)p->slabs * nrhs;
     int nch = (int)((2048 + per - 1) / per);
@@ -1144,24 +1165,25 @@ uno_status lowrank_finish(const LowRankPlan* p, const double* r, T* s, const CgI
         uno_launch(UNO_KT_FFT_MID, k_lr_mid, dim3(p->blocks_mid, bt.nrhs), dim3(256), p->lds_b, st, L, bt.nch,
                    p->cb_mid, (const double*)p->table, (const double2*)bt.Gp, bt.H, it, (double*)nullptr);
     UNO_HIP(hipGetLastError());
-    const dim3 grid(p->blocks_c, bt.nrhs);
+    const int nbc = L.n0 * ((L.n1 + bt.yc - 1) / bt.yc);
+    const dim3 grid(nbc, bt.nrhs);
     if (itp) {
         if (L.nc == 3)
-            uno_launch(UNO_KT_FFT_INV, k_lr_inv<true, T, 3>, grid, dim3(256), p->lds_c, st, L, p->yc, r,
+            uno_launch(UNO_KT_FFT_INV, k_lr_inv<true, T, 3>, grid, dim3(256), p->lds_c, st, L, bt.yc, r,
                        (const double2*)bt.H, s, it);
         else
-            uno_launch(UNO_KT_FFT_INV, k_lr_inv<true, T, 1>, grid, dim3(256), p->lds_c, st, L, p->yc, r,
+            uno_launch(UNO_KT_FFT_INV, k_lr_inv<true, T, 1>, grid, dim3(256), p->lds_c, st, L, bt.yc, r,
                        (const double2*)bt.H, s, it);
     } else {
         if (L.nc == 3)
-            uno_launch(UNO_KT_FFT_INV, k_lr_inv<false, T, 3>, grid, dim3(256), p->lds_c, st, L, p->yc, r,
+            uno_launch(UNO_KT_FFT_INV, k_lr_inv<false, T, 3>, grid, dim3(256), p->lds_c, st, L, bt.yc, r,
                        (const double2*)bt.H, s, it);
         else
-            uno_launch(UNO_KT_FFT_INV, k_lr_inv<false, T, 1>, grid, dim3(256), p->lds_c, st, L, p->yc, r,
+            uno_launch(UNO_KT_FFT_INV, k_lr_inv<false, T, 1>, grid, dim3(256), p->lds_c, st, L, bt.yc, r,
                        (const double2*)bt.H, s, it);
     }
     UNO_HIP(hipGetLastError());
-    if (np_rs) *np_rs = p->blocks_c;
+    if (np_rs) *np_rs = nbc;
     return UNO_OK;
 }
 

@@ -148,7 +148,8 @@ struct LrBatch {
     double2* Gp;
     double2* H;
     int nrhs;
-    int rb, nch;
+    int rb, nch;   // pass A: rows per workgroup, row chunks per slab
+    int yc;        // pass C: rows per workgroup
 };
 // nc = 1: cblock kxn x kyn x kzn corrections, W the bypass; nc = 3: six
 // entries per block mode (q1..q6) and the bypass block Wq (6 entries)
