@@ -1,0 +1,125 @@
+"""GPU parity at the full sizes of the elasticity and many-problem
+workloads, in the configurations the benchmark times: the 128^3 elastic
+operator and c = 3 UNO apply against the oracle on every node, the six
+Mandel solves checked by properties that hold at any size (true residual,
+symmetry of the stiffness, Voigt and Reuss bounds, agreement of UNO-CG and
+Jacobi-CG), and the 256-problem work list solved in one call."""
+import numpy as np
+import pytest
+import torch
+
+import synth_inputs as si
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+@pytest.fixture(scope="module")
+def uno():
+    import paper_2508_02681_amd as u
+    u.lib()
+    assert torch.cuda.is_available()
+    return u
+
+
+def T(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+
+
+def rel(a, b):
+    return np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(np.asarray(b)).max(), 1e-300)
+
+
+@pytest.fixture(scope="module")
+def el128(orc):
+    cfg = dict(si.CONFIG_EL_128)
+    E, _ = si.microstructure(cfg, cfg["test_seeds"][0])
+    lam, mu = orc.lame(E, cfg["nu"])
+    return cfg, lam, mu
+
+
+def test_el_128_operator_and_uno3_apply_match_oracle(orc, uno, el128):
+    cfg, lam, mu = el128
+    shape = cfg["shape"]
+    print("elastic 128^3 apply", flush=True)
+    rng = np.random.default_rng(60)
+    u = rng.standard_normal((3,) + shape)
+    y = uno.el_apply(T(lam), T(mu), T(u)).cpu().numpy()
+    assert rel(y, orc.el_apply(lam, mu, u)) < 1e-12
+    M = 8
+    th = 0.3 * rng.standard_normal(orc.num_weights3(M))
+    th.reshape(-1, 6)[:, [0, 1, 3]] += 1.0
+    P = uno.UnoPrecond.create_elastic(shape, M, th)
+    s = P.apply(T(u)).cpu().numpy()
+    assert rel(s, orc.uno3_apply(orc.uno3_table(shape, M, th), u)) < 1e-12
+
+
+def _bounds(lam, mu):
+    """Voigt <D> and Reuss <D^-1>^-1 (Mandel 6 x 6)."""
+    def D(l, m):
+        d = 2 * m * np.eye(6)
+        d[:3, :3] += l
+        return d
+    vals = {}
+    for l, m in zip(lam.ravel(), mu.ravel()):
+        vals[(l, m)] = vals.get((l, m), 0) + 1
+    n = lam.size
+    V = sum(c * D(l, m) for (l, m), c in vals.items()) / n
+    R = np.linalg.inv(sum(c * np.linalg.inv(D(l, m)) for (l, m), c in vals.items()) / n)
+    return V, R
+
+
+def test_el_128_six_loads_properties(orc, uno, el128):
+    cfg, lam, mu = el128
+    shape = cfg["shape"]
+    print("elastic 128^3 solves", flush=True)
+    loads = np.eye(6)
+    L, Mu = T(lam), T(mu)
+    uj, ij = uno.el_pcg_solve(L, Mu, loads, rtol=1e-6)
+    # a preconditioner trained on the Jacobi solutions of the two training
+    # microstructures (as the benchmark does)
+    nh = shape[2] // 2 + 1
+    A = torch.zeros((6, shape[0], shape[1], nh), dtype=torch.float64, device=DEV)
+    B = torch.zeros_like(A)
+    for seed in cfg["train_seeds"]:
+        E2, _ = si.microstructure(cfg, seed)
+        l2, m2 = orc.lame(E2, cfg["nu"])
+        u2, _ = uno.el_pcg_solve(T(l2), T(m2), loads, rtol=1e-8)
+        F = torch.stack([uno.el_macro_rhs(T(l2), T(m2), loads[j]) for j in range(6)])
+        uno.el_uno_train_accumulate(F, u2, A, B, 6 * len(cfg["train_seeds"]))
+    th, _ = uno.el_uno_train_fit(shape, 8, A, B)
+    P = uno.UnoPrecond.create_elastic(shape, 8, th)
+    uu, iu = uno.el_pcg_solve(L, Mu, loads, kind="uno", precond=P, rtol=1e-6)
+    for a, b in zip(ij, iu):
+        assert a["converged"] and b["converged"]
+        assert a["true_rel_res"] < 1e-5 and b["true_rel_res"] < 1e-5
+        assert b["iters"] < a["iters"]
+    Dj = uno.el_effective_stiffness(L, Mu, loads, uj)
+    Du = uno.el_effective_stiffness(L, Mu, loads, uu)
+    assert rel(Du, Dj) < 1e-5
+    assert np.abs(Du - Du.T).max() < 1e-5 * np.abs(Du).max()
+    V, R = _bounds(lam, mu)
+    S = 0.5 * (Du + Du.T)
+    assert np.linalg.eigvalsh(V - S).min() > -1e-6 * np.abs(V).max()
+    assert np.linalg.eigvalsh(S - R).min() > -1e-6 * np.abs(V).max()
+
+
+def test_many_problems_work_list(orc, uno):
+    cfg = dict(si.CONFIG_MANY)
+    print("many-problem work list", flush=True)
+    probs = [si.many_problem(cfg, i) for i in range(cfg["count"])]
+    items = [{"kappa": T(k), "loads": l} for k, l in probs]
+    us, infos = uno.pcg_solve_many(items, kind="jacobi", rtol=1e-6)
+    assert sum(len(i) for i in infos) == sum(len(l) for _, l in probs)
+    for inf in infos:
+        for I in inf:
+            assert I["converged"] and I["true_rel_res"] < 1e-5
+    # three small problems of the list at a tight tolerance against the oracle
+    small = [i for i, (k, _) in enumerate(probs) if k.shape == (64, 64)][:3]
+    us2, infos2 = uno.pcg_solve_many([items[i] for i in small], kind="jacobi", rtol=1e-10)
+    for i, u in zip(small, us2):
+        k, loads = probs[i]
+        for j in range(len(loads)):
+            uo, _, _, _ = orc.pcg(k, orc.rhs(k, loads[j]), "jacobi", rtol=1e-10)
+            assert rel(u[j].cpu().numpy(), uo) < 1e-7
