@@ -81,7 +81,8 @@ template <typename T, int MODE>
 __global__ void __launch_bounds__(kBlock) k_cg_init(GridDev g, const T* __restrict__ dinv,
                                                     const double* __restrict__ r, T* __restrict__ s,
                                                     double* __restrict__ part_rmax, double* __restrict__ part_rs,
-                                                    double* __restrict__ part_ss, CgState* st, int ps, int64_t ks)
+                                                    double* __restrict__ part_ss, CgState* st, int ps, int64_t ks,
+                                                    int reset = 1)
 {
     __shared__ double slots[kBlock / 64];
     if (blockIdx.y > 0) {  // right-hand side blockIdx.y of a batch
@@ -118,7 +119,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_init(GridDev g, const T* __restri
         part_rmax[blockIdx.x] = bm;
         part_rs[blockIdx.x] = bd;
         part_ss[blockIdx.x] = bs;
-        if (blockIdx.x == 0) {
+        if (reset && blockIdx.x == 0) {  // (a restart keeps the states: ended loads stay ended)
             st->done = INT_MAX;
             st->status = 0;
             st->fail_iter = -1;
@@ -299,6 +300,7 @@ struct Workspace {
     double *f = nullptr, *r = nullptr, *s = nullptr, *d[2] = {nullptr, nullptr}, *p = nullptr;
     double* dinv = nullptr;   // inverse Jacobi diagonal(s) of the current solve
     float* kap32 = nullptr;   // FP32 conductivities (mixed precision)
+    int kap32_cap = 0;        // fields it holds
     double* y64 = nullptr;    // FP64 operator output for residual replacement (mixed precision)
     double* part = nullptr;   // 8 partial buffers: rmax, rs[2], dp, ss[2], ds[2]
     double2* spec = nullptr;
@@ -582,7 +584,12 @@ static uno_status enqueue_pass(const Grid& g, Workspace* w, int kind, const uno_
 // residual equal to the true one.
 constexpr double kRestartFactor = 1e-3;
 
-// The CG loop for nrhs right-hand sides (restarts only with nrhs = 1).
+// The CG loop for nrhs right-hand sides.  FP32 mode: the residual
+// replacement restarts every right-hand side together (one pass index k0
+// for all) as soon as one of the running ones has dropped by the restart
+// factor since its last (re)start; a restart earlier than a load needs
+// costs it part of its Krylov space, not accuracy, and loads that have
+// ended keep their state.
 template <typename T>
 static uno_status pcg_loop(const Grid& g, Workspace* w, const double* kappa64, const T* kappa, int64_t ks,
                            double* u, const uno_solve_opts* o, const uno_precond* pc, int hist_len, int nrhs,
@@ -595,23 +602,22 @@ static uno_status pcg_loop(const Grid& g, Workspace* w, const double* kappa64, c
     const bool lowrank = pc && uno_use_lowrank(pc);
     const int np_update = lowrank ? lowrank_update_blocks(pc->lr, nrhs) : nb;
     const bool restarts = sizeof(T) == sizeof(float);
-    if (restarts && nrhs != 1) return UNO_ERR_ARG;
     if (o->kind == UNO_PREC_JACOBI)  // one inverse diagonal per conductivity field
         for (int b = 0; b < (ks ? nrhs : 1); ++b)
             hipLaunchKernelGGL(k_inv_diag<T>, dim3(nb), dim3(kBlock), 0, st, g.dev, kappa64 + b * ks, dinv + b * ks);
     // (re)start of the recurrence from the residual in w->r: s_0 = P r_0 and
     // the partials of the first pass
-    auto start = [&]() -> uno_status {
+    auto start = [&](int reset) -> uno_status {
         const dim3 grid(nb, nrhs);
         if (o->kind == UNO_PREC_NONE)
             hipLaunchKernelGGL((k_cg_init<T, 0>), grid, dim3(kBlock), 0, st, g.dev, (const T*)dinv,
-                               (const double*)w->r, sv, P.rmax, P.rs[0], P.ss[0], w->state, w->npart, ks);
+                               (const double*)w->r, sv, P.rmax, P.rs[0], P.ss[0], w->state, w->npart, ks, reset);
         else if (o->kind == UNO_PREC_JACOBI)
             hipLaunchKernelGGL((k_cg_init<T, 1>), grid, dim3(kBlock), 0, st, g.dev, (const T*)dinv,
-                               (const double*)w->r, sv, P.rmax, P.rs[0], P.ss[0], w->state, w->npart, ks);
+                               (const double*)w->r, sv, P.rmax, P.rs[0], P.ss[0], w->state, w->npart, ks, reset);
         else
             hipLaunchKernelGGL((k_cg_init<T, 2>), grid, dim3(kBlock), 0, st, g.dev, (const T*)dinv,
-                               (const double*)w->r, sv, P.rmax, P.rs[0], P.ss[0], w->state, w->npart, ks);
+                               (const double*)w->r, sv, P.rmax, P.rs[0], P.ss[0], w->state, w->npart, ks, reset);
         UNO_HIP(hipGetLastError());
         if (lowrank) {  // transform of r for the first pass (and ||r||^2 in the fused flow)
             const bool fused = sizeof(T) == sizeof(double) && uno_use_fused(pc);
@@ -620,14 +626,14 @@ static uno_status pcg_loop(const Grid& g, Workspace* w, const double* kappa64, c
         }
         return UNO_OK;
     };
-    uno_status e = start();
+    uno_status e = start(1);
     if (e != UNO_OK) return e;
     // passes in chunks; the host reads the states between chunks
     int k = 0, k0 = 0;
     int chunk = o->graph_chunk > 0 ? o->graph_chunk : 8;
     std::vector<int> prev_k(nrhs, -1);
     std::vector<double> prev_r(nrhs, -1.0);
-    double cycle_r = -1.0;
+    std::vector<double> cycle_r(nrhs, -1.0);
     for (;;) {
         if (chunk > o->max_iter - k) chunk = o->max_iter - k;
         for (int c = 0; c < chunk; ++c, ++k) {
@@ -646,19 +652,35 @@ static uno_status pcg_loop(const Grid& g, Workspace* w, const double* kappa64, c
         }
         if (!running || k >= o->max_iter) break;
         if (restarts) {
-            const CgState& hs = w->host_state[0];
-            if (cycle_r < 0.0) cycle_r = hs.r0max;
-            if (hs.rmax_last <= kRestartFactor * cycle_r) {
-                // residual replacement: r = f - A u (FP64), restart at pass k
-                e = launch_fe_apply(g, kappa64, u, w->y64, UNO_F64, st);
-                if (e != UNO_OK) return e;
-                hipLaunchKernelGGL(k_sub, dim3(nb), dim3(kBlock), 0, st, g.total, (const double*)w->f,
-                                   (const double*)w->y64, w->r);
-                e = start();
+            bool due = false;
+            for (int b = 0; b < nrhs; ++b) {
+                const CgState& hs = w->host_state[b];
+                if (hs.status != 0 || hs.done != INT_MAX) continue;
+                if (cycle_r[b] < 0.0) cycle_r[b] = hs.r0max;
+                if (hs.rmax_last <= kRestartFactor * cycle_r[b]) due = true;
+            }
+            if (due) {
+                // residual replacement, every load at once: r = f - A u (FP64;
+                // the FP64 products go to p, rewritten by the next pass anyway),
+                // restart at pass k
+                CgIter bi;
+                memset(&bi, 0, sizeof(bi));
+                bi.vs = g.total;
+                bi.ks = ks;
+                launch_tile<double, false, false>(g, kappa64, u, nullptr, nullptr, (double*)w->p, nullptr, bi, nullptr,
+                                                  0, nullptr, st, MeanFree{nullptr, nullptr, nullptr}, nrhs);
+                UNO_HIP(hipGetLastError());
+                hipLaunchKernelGGL(k_sub, dim3(nb), dim3(kBlock), 0, st, g.total * nrhs, (const double*)w->f,
+                                   (const double*)w->p, w->r);
+                for (int b = 0; b < nrhs; ++b) {
+                    const CgState& hs = w->host_state[b];
+                    if (hs.status != 0 || hs.done != INT_MAX) continue;
+                    cycle_r[b] = hs.rmax_last;
+                    prev_r[b] = -1.0;
+                }
+                e = start(0);
                 if (e != UNO_OK) return e;
                 k0 = k;
-                cycle_r = hs.rmax_last;
-                prev_r[0] = -1.0;
                 chunk = o->graph_chunk > 0 ? o->graph_chunk : 8;
                 continue;
             }
@@ -672,7 +694,7 @@ static uno_status pcg_loop(const Grid& g, Workspace* w, const double* kappa64, c
                 if (hs.status != 0 || hs.done != INT_MAX) continue;
                 double target = hs.tol_abs;
                 if (restarts) {
-                    const double lvl = kRestartFactor * cycle_r;
+                    const double lvl = kRestartFactor * cycle_r[b];
                     if (lvl > target) target = lvl;
                 }
                 int nx = 16;
@@ -705,7 +727,7 @@ uno_status pcg_run_batch(const Grid& g, const double* kappa, int64_t ks, int nrh
     if (mixed && pc && !uno_use_lowrank(pc)) return UNO_ERR_ARG;
     // one loop for all right-hand sides where every pass kernel takes them
     // along grid y; the spectral passes and the FP32 restarts go one by one
-    const bool together = nrhs == 1 || (!mixed && (!pc || uno_use_lowrank(pc)));
+    const bool together = nrhs == 1 || !pc || uno_use_lowrank(pc);
     if (!together) {
         uno_status worst = UNO_OK;
         for (int b = 0; b < nrhs; ++b) {
@@ -742,10 +764,19 @@ uno_status pcg_run_batch(const Grid& g, const double* kappa, int64_t ks, int nrh
     }
     int k = 0;
     if (mixed) {
-        if (!w->kap32 && hipMalloc(&w->kap32, sizeof(float) * n) != hipSuccess) return UNO_ERR_NOMEM;
+        // FP32 conductivities: one field, or one per right-hand side
+        const int nf = ks ? nrhs : 1;
+        if (w->kap32_cap < nf) {
+            (void)hipFree(w->kap32);
+            w->kap32 = nullptr;
+            w->kap32_cap = 0;
+            if (hipMalloc(&w->kap32, sizeof(float) * n * nf) != hipSuccess) return UNO_ERR_NOMEM;
+            w->kap32_cap = nf;
+        }
         if (!w->y64 && hipMalloc(&w->y64, sizeof(double) * n) != hipSuccess) return UNO_ERR_NOMEM;
-        hipLaunchKernelGGL(k_convert<float>, dim3(nb), dim3(kBlock), 0, st, n, kappa, w->kap32);
-        e = pcg_loop<float>(g, w, kappa, w->kap32, 0, u, o, pc, hist_len, nrhs, st, &k);
+        for (int b = 0; b < nf; ++b)
+            hipLaunchKernelGGL(k_convert<float>, dim3(nb), dim3(kBlock), 0, st, n, kappa + b * ks, w->kap32 + b * n);
+        e = pcg_loop<float>(g, w, kappa, w->kap32, ks, u, o, pc, hist_len, nrhs, st, &k);
     } else {
         e = pcg_loop<double>(g, w, kappa, kappa, ks, u, o, pc, hist_len, nrhs, st, &k);
     }

@@ -140,6 +140,11 @@ __global__ void __launch_bounds__(256) k_stencil_march(GridDev g, MarchGeom mg, 
     const int txi = b / mg.tiles_y;
     const int x0 = txi * mg.xb, y0 = tyi * TY, z0 = tzi * TZ;
     const int xe = min(g.n0, x0 + mg.xb);
+    if (!CG && blockIdx.y > 0) {  // plain applies of a batch: u, y at + it.vs, kappa at + it.ks
+        kappa += (int64_t)blockIdx.y * it.ks;
+        s += (int64_t)blockIdx.y * it.vs;
+        p += (int64_t)blockIdx.y * it.vs;
+    }
     if (CG && blockIdx.y > 0) {  // right-hand side blockIdx.y of a batch
         const int64_t vo = (int64_t)blockIdx.y * it.vs, po = (int64_t)blockIdx.y * it.ps;
         kappa += (int64_t)blockIdx.y * it.ks;
