@@ -299,6 +299,8 @@ def parse():
     ap.add_argument("--no-192", action="store_true", help="skip the per-kernel roofline at 192^3")
     ap.add_argument("--no-elastic", action="store_true", help="skip the 128^3 elasticity record")
     ap.add_argument("--no-many", action="store_true", help="skip the many-problem record")
+    ap.add_argument("--only", choices=["elastic", "many"], default=None,
+                    help="run only that record and print it (profiling runs of its kernels)")
     ap.add_argument("--el-M", type=int, default=8, help="mode parameter of the elastic UNO preconditioner")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this size first (reference for HBM counters)")
@@ -328,6 +330,11 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.only:
+        rec = elastic_record(uno, si, torch, dev, args.el_M) if args.only == "elastic" else \
+            many_record(uno, si, torch, dev)
+        print(json.dumps({args.only: rec}), flush=True)
+        return
     cfg = dict(si.CONFIG_3D_64)
     n_dof = int(np.prod(SHAPE))
 
