@@ -37,18 +37,20 @@ LOADS = np.eye(3)
 RTOL = 1e-6
 HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs of
-# this benchmark (64^3, M = 12, 48 right-hand sides per launch), each scaled by what the counter reads for a
-# device copy of known size (FETCH x 2, WRITE x 1); the summary with its
-# commands is profiles/uno_cg_64cubed_hbm_counters.md.  Valid only for the
-# kernel sources as they were when counted (TRAFFIC_SRC: hash of the files in
-# TRAFFIC_FILES); after any change the figure is withheld.
+# this benchmark (64^3, M = 12, 48 right-hand sides per launch; the mean over
+# the launches, loads that have converged returning at once), each scaled by
+# what the counter reads for a device copy of known size (FETCH x 2,
+# WRITE x 1); the summary with its commands is
+# profiles/uno_cg_64cubed_hbm_counters.md.  Valid only for the kernel sources
+# as they were when counted (TRAFFIC_SRC: hash of the files in TRAFFIC_FILES);
+# after any change the figure is withheld.
 TRAFFIC_FILES = ["lowrank.hip", "stencil_tile.h", "cg_ctl.h", "reduce.h", "cg.hip"]
-TRAFFIC_SRC = "88f71bf95f741e46"
+TRAFFIC_SRC = "176cdd806bb68a6e"
 TRAFFIC_BYTES = {  # per launch of the benchmark step (48 right-hand sides)
-    "k_stencil_march<double,CG>": 781298048,
-    "k_lr_fwd<update,double>": 491870582,
-    "k_lr_mid": 44006189,
-    "k_lr_inv<double>": 242104405,
+    "k_stencil_march<double,CG>": 780775535,
+    "k_lr_fwd<update,double>": 491866982,
+    "k_lr_mid": 41547994,
+    "k_lr_inv<double>": 174237440,
 }
 
 
@@ -61,12 +63,14 @@ def kernel_sources_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def kernel_families(uno, shape, M, learned, nr, kappa_per_rhs):
-    """Kernel families of one UNO-CG pass and their algorithmic bytes per
-    launch (FP64; a launch carries nr right-hand sides, each with its own
-    conductivity field or all with one; the table is shared)."""
+def kernel_families(uno, shape, M, learned, kappa_per_rhs):
+    """Kernel families of one UNO-CG pass and their algorithmic bytes
+    (FP64) as (per right-hand side that is still running, per launch): a
+    launch carries the right-hand sides of a batch, each with its own
+    conductivity field or all with one; the table is shared, and a load
+    that has converged returns at once from the kernels of later passes."""
     n = int(np.prod(shape))
-    nk = nr if kappa_per_rhs else 1
+    kap_rhs, kap_launch = (n * 8, 0) if kappa_per_rhs else (0, n * 8)
     nspec = shape[0] * shape[1] * (shape[2] // 2 + 1)
     nblk = shape[0] * (2 * M + 1) * (M + 1)   # learned block after the two partial DFTs (y, z)
     if learned:
@@ -74,64 +78,76 @@ def kernel_families(uno, shape, M, learned, nr, kappa_per_rhs):
         fams = {uno.KT_MATVEC: "k_stencil_march<double,CG>", uno.KT_UPDATE: "k_lr_fwd<update,double>",
                 uno.KT_FFT_MID: "k_lr_mid", uno.KT_FFT_INV: "k_lr_inv<double>"}
         bytes_per = {
-            uno.KT_MATVEC: nr * n * 8 * 4 + nk * n * 8,  # read s, d_old, kappa; write d_new, p
-            uno.KT_UPDATE: nr * (n * 8 * 6 + nblk * 16),  # read r, u, d, p; write r, u, block spectrum
-            uno.KT_FFT_MID: nr * nblk * 16 * 2 + nblk * 8,  # block spectrum in/out; table
-            uno.KT_FFT_INV: nr * (n * 8 * 2 + nblk * 16),  # read r, H; write s
+            uno.KT_MATVEC: (n * 8 * 4 + kap_rhs, kap_launch),  # read s, d_old, kappa; write d_new, p
+            uno.KT_UPDATE: (n * 8 * 6 + nblk * 16, 0),        # read r, u, d, p; write r, u, block spectrum
+            uno.KT_FFT_MID: (nblk * 16 * 2, nblk * 8),        # block spectrum in/out; table
+            uno.KT_FFT_INV: (n * 8 * 2 + nblk * 16, 0),       # read r, H; write s
         }
     else:  # spectral passes, one load per launch
         fams = {uno.KT_MATVEC: "k_stencil_march<double,CG>", uno.KT_UPDATE: "k_cg_update<double>",
                 uno.KT_FFT_FWD: "k_fft_r2c_z", uno.KT_FFT_MID: "k_fft_strided(mid)", uno.KT_FFT_INV: "k_fft_c2r_z"}
         bytes_per = {
-            uno.KT_MATVEC: n * 8 * 5,
-            uno.KT_UPDATE: n * 8 * 6,               # read r, p, u, d; write r, u
-            uno.KT_FFT_FWD: n * 8 + nspec * 16,     # read r; write half spectrum
-            uno.KT_FFT_MID: nspec * 16 * 2 + nspec * 8,  # spectrum in/out + table
-            uno.KT_FFT_INV: nspec * 16 + n * 8 * 2,  # spectrum in; write s; read r (r.s)
+            uno.KT_MATVEC: (n * 8 * 5, 0),
+            uno.KT_UPDATE: (n * 8 * 6, 0),               # read r, p, u, d; write r, u
+            uno.KT_FFT_FWD: (n * 8 + nspec * 16, 0),     # read r; write half spectrum
+            uno.KT_FFT_MID: (nspec * 16 * 2 + nspec * 8, 0),  # spectrum in/out + table
+            uno.KT_FFT_INV: (nspec * 16 + n * 8 * 2, 0),  # spectrum in; write s; read r (r.s)
         }
     return fams, bytes_per
 
 
 def family_times(uno, fams, run):
     """Summed duration (ms) and launch count of each kernel family over one
-    call of run(), from start/stop events of the launches themselves."""
+    call of run(), from start/stop events of the launches themselves, and
+    the passes of each right-hand side in that run (run() returns them)."""
     import torch
     out = {}
+    passes = None
     for fam in fams:
         uno.timing_enable(fam)
-        run()
+        passes = run()
         torch.cuda.synchronize()
         out[fam] = uno.timing_read()
         uno.timing_enable(uno.KT_NONE)
-    return out
+    return out, passes
 
 
-def roofline_record(fams, bytes_per, fam_ms):
+def roofline_record(fams, bytes_per, timed):
+    """Dominant family (largest total time): achieved = algorithmic bytes
+    of the run / its summed launch time, the bytes counting each right-hand
+    side for the passes it ran (sum of passes x per-load bytes) plus the
+    per-launch part; bytes_per_launch is that total over the launches."""
+    fam_ms, passes = timed
+    tot_passes = float(sum(passes))
+    def total_bytes(f):
+        per_rhs, per_launch = bytes_per[f]
+        return tot_passes * per_rhs + fam_ms[f][1] * per_launch
     dom = max(fam_ms, key=lambda f: fam_ms[f][0])
     tot, nl = fam_ms[dom]
     avg_s = tot / max(nl, 1) / 1e3
-    achieved = bytes_per[dom] / avg_s / 1e9
+    bpl = total_bytes(dom) / max(nl, 1)
+    achieved = bpl / avg_s / 1e9
     per_us = {fams[f]: fam_ms[f][0] / max(fam_ms[f][1], 1) * 1e3 for f in fams}
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": fams[dom], "avg_us": round(avg_s * 1e6, 2), "bytes_per_launch": bytes_per[dom],
+            "kernel": fams[dom], "avg_us": round(avg_s * 1e6, 2), "bytes_per_launch": round(bpl),
             "per_family_us": {k: round(v, 2) for k, v in per_us.items()},
-            "per_family_GBs": {fams[f]: round(bytes_per[f] / max(per_us[fams[f]], 1e-9) / 1e3, 1) for f in fams}}
+            "per_family_GBs": {fams[f]: round(total_bytes(f) / max(fam_ms[f][0], 1e-9) / 1e6, 1) for f in fams}}
 
 
-def elastic_families(uno, shape, M, nr):
+def elastic_families(uno, shape, M):
     """Kernel families of one elastic UNO-CG pass (c = 3, planar components,
-    nr right-hand sides per launch, one Lame field pair) and their
-    algorithmic bytes per launch."""
+    one Lame field pair for all right-hand sides) and their algorithmic
+    bytes as (per running right-hand side, per launch)."""
     n = int(np.prod(shape))
     nblk = 3 * shape[0] * (2 * M + 1) * (M + 1)  # learned block of the three components after pass A
     fams = {uno.KT_MATVEC: "k_el_march<CG>", uno.KT_UPDATE: "k_lr_fwd<update,double>(c=3)",
             uno.KT_FFT_MID: "k_lr_mid3", uno.KT_FFT_INV: "k_lr_inv<double,c=3>"}
     bytes_per = {
-        uno.KT_MATVEC: nr * 3 * n * 8 * 4 + 2 * n * 8,  # read s, d_old; write d_new, p; lambda, mu
-        uno.KT_UPDATE: nr * (3 * n * 8 * 6 + nblk * 16),  # read r, u, d, p; write r, u, block spectrum
-        uno.KT_FFT_MID: nr * nblk * 16 * 2 + nblk // 3 * 48,  # block spectrum in/out; 6 table entries
-        uno.KT_FFT_INV: nr * (3 * n * 8 * 2 + nblk * 16),  # read r, H; write s
+        uno.KT_MATVEC: (3 * n * 8 * 4, 2 * n * 8),    # read s, d_old; write d_new, p; lambda, mu
+        uno.KT_UPDATE: (3 * n * 8 * 6 + nblk * 16, 0),  # read r, u, d, p; write r, u, block spectrum
+        uno.KT_FFT_MID: (nblk * 16 * 2, nblk // 3 * 48),  # block spectrum in/out; 6 table entries
+        uno.KT_FFT_INV: (3 * n * 8 * 2 + nblk * 16, 0),  # read r, H; write s
     }
     return fams, bytes_per
 
@@ -182,13 +198,12 @@ def elastic_record(uno, si, torch, dev, M):
     uj, ij, tj = timed(kind="jacobi")
     Du = uno.el_effective_stiffness(L, Mu, loads, uu)
     Dj = uno.el_effective_stiffness(L, Mu, loads, uj)
-    fams, bytes_per = elastic_families(uno, shape, M, 6)
+    fams, bytes_per = elastic_families(uno, shape, M)
 
     def run():
-        uno.el_pcg_solve(L, Mu, loads, kind="uno", precond=P, rtol=RTOL)
+        return [i["iters"] for i in uno.el_pcg_solve(L, Mu, loads, kind="uno", precond=P, rtol=RTOL)[1]]
 
-    fam_ms = family_times(uno, fams, run)
-    rec = roofline_record(fams, bytes_per, fam_ms)
+    rec = roofline_record(fams, bytes_per, family_times(uno, fams, run))
     its_u = [i["iters"] for i in iu]
     its_j = [i["iters"] for i in ij]
     out = {
@@ -492,9 +507,8 @@ def main():
     except RuntimeError:
         learned = False
     prec.set_path(prec.PATH_AUTO)
-    fams, bytes_per = kernel_families(uno, SHAPE, M, learned, nr_all, True)
-    fam_ms = family_times(uno, fams, lambda: step("uno", prec))
-    roofline = roofline_record(fams, bytes_per, fam_ms)
+    fams, bytes_per = kernel_families(uno, SHAPE, M, learned, True)
+    roofline = roofline_record(fams, bytes_per, family_times(uno, fams, lambda: step("uno", prec)[0]))
     if learned and kernel_sources_hash() == TRAFFIC_SRC:
         roofline["traffic"] = TRAFFIC_BYTES.get(roofline["kernel"])
     log("roofline (64^3): %s %.1f GB/s per launch (%.3f of peak)" %
@@ -546,12 +560,14 @@ def main():
         kb192 = torch.tensor(si.microstructure(cfgb, 7000)[0], device=dev)
         pb = uno.UnoPrecond.create(cfgb["shape"], 12, si.random_theta(uno.num_weights(3, 12), 7001,
                                                                         scale=0.02, spread=0.1))
-        fb, bb = kernel_families(uno, cfgb["shape"], 12, True, len(LOADS), False)
+        fb, bb = kernel_families(uno, cfgb["shape"], 12, True, False)
         ub = torch.zeros((3,) + cfgb["shape"], dtype=torch.float64, device=dev)
 
         def run_big():
             ub.zero_()
-            uno.pcg_solve_batch(kb192, macro_loads=LOADS, u=ub, kind="uno", precond=pb, rtol=1e-30, max_iter=40)
+            _, inf = uno.pcg_solve_batch(kb192, macro_loads=LOADS, u=ub, kind="uno", precond=pb, rtol=1e-30,
+                                         max_iter=40)
+            return [i["iters"] for i in inf]
 
         run_big()
         big = roofline_record(fb, bb, family_times(uno, fb, run_big))
