@@ -208,7 +208,7 @@ __global__ void __launch_bounds__(256) k_el_march(ElDev E, ElGeom eg, const doub
         }
     }
     const int t = threadIdx.x, ly = t >> 4, lz = t & 15;
-    int bid = blockIdx.x;
+    int bid = xcd_tile(blockIdx.x, gridDim.x);
     const int bz = bid % eg.tiles_z;
     bid /= eg.tiles_z;
     const int by = bid % eg.tiles_y, bx = bid / eg.tiles_y;

@@ -133,7 +133,7 @@ __global__ void __launch_bounds__(256) k_stencil_march(GridDev g, MarchGeom mg, 
     __shared__ T Kr[2][NK];
     __shared__ double slots[4];
 
-    int b = blockIdx.x;
+    int b = xcd_tile(blockIdx.x, gridDim.x);
     const int tzi = b % mg.tiles_z;
     b /= mg.tiles_z;
     const int tyi = b % mg.tiles_y;

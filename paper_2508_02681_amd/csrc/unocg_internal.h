@@ -53,6 +53,17 @@ template <> struct cplx_t<float> { using type = float2; };
 bool ktimer_take(int fam, hipEvent_t* a, hipEvent_t* b);
 void ktimer_push(hipEvent_t a, hipEvent_t b);
 
+// Workgroups of a launch go to the 8 XCDs in turn (workgroup i to XCD
+// i mod 8, along grid x), and each XCD has an L2 of its own.  Tile kernels
+// whose neighbouring tiles share halo planes map workgroup i of n to this
+// tile index, so that each XCD works on one contiguous range of tiles and
+// the shared lines meet in one L2.  A bijection of [0, n).
+__device__ __forceinline__ int xcd_tile(int i, int n)
+{
+    const int q = n >> 3, r = n & 7, x = i & 7, j = i >> 3;
+    return x * q + (x < r ? x : r) + j;
+}
+
 template <typename... Formals, typename... Args>
 inline void uno_launch(int fam, void (*kernel)(Formals...), dim3 grid, dim3 block, size_t sh, hipStream_t st,
                        Args... args)
