@@ -106,6 +106,15 @@ std::vector<std::pair<hipEvent_t, hipEvent_t>> g_tev;
 // write-back between it and its neighbours, no event creation on the way).
 static std::vector<hipEvent_t> g_tpool;
 
+// device buffer of effective_tensor's flux partials, one per device
+struct FluxBuf {
+    int device;
+    double* p;
+    size_t cap;
+};
+static std::mutex g_flux_mu;
+static std::vector<FluxBuf> g_flux;
+
 static bool pool_pop(hipEvent_t* e)
 {
     if (!g_tpool.empty()) {
@@ -741,30 +750,46 @@ uno_status effective_tensor(const uno_grid* grid, const uno_material* mat, int32
     if (!mat || !mat->kappa || !loads || !u || !out || nload != d) return UNO_ERR_ARG;
     if (mat->dtype != UNO_F64 && mat->dtype != UNO_F32) return UNO_ERR_ARG;
     const int nb = (int)((g.total + kBlock - 1) / kBlock);
-    double* dpart = nullptr;
-    if (hipMalloc(&dpart, sizeof(double) * 3 * nb) != hipSuccess) return UNO_ERR_NOMEM;
-    std::vector<double> hpart(3 * (size_t)nb);
+    // flux partials of the d loads in a device buffer kept per device
+    // (grown on demand), read back in one copy
+    std::lock_guard<std::mutex> lk(g_flux_mu);
+    int dev = 0;
+    UNO_HIP(hipGetDevice(&dev));
+    FluxBuf* fb = nullptr;
+    for (FluxBuf& c : g_flux)
+        if (c.device == dev) fb = &c;
+    if (!fb) {
+        g_flux.push_back(FluxBuf{dev, nullptr, 0});
+        fb = &g_flux.back();
+    }
+    const size_t need = 3 * (size_t)nb * d;
+    if (fb->cap < need) {
+        (void)hipFree(fb->p);
+        fb->p = nullptr;
+        fb->cap = 0;
+        if (hipMalloc(&fb->p, sizeof(double) * need) != hipSuccess) return UNO_ERR_NOMEM;
+        fb->cap = need;
+    }
+    double* dpart = fb->p;
+    std::vector<double> hpart(need);
     double Q[3][3] = {{0}};  // Q[i][j]: component i of load j
-    for (int j = 0; j < d; ++j) {
+    for (int j = 0; j < d && e == UNO_OK; ++j) {
         double g3[3] = {0.0, 0.0, 0.0};
         for (int b = 0; b < d; ++b) g3[3 - d + b] = loads[j * d + b];
         int nbo = 0;
-        e = launch_flux(g, mat->kappa, mat->dtype, g3, u + (int64_t)j * g.total, dpart, &nbo, S(stream));
-        if (e != UNO_OK) break;
-        if (hipMemcpyAsync(hpart.data(), dpart, sizeof(double) * 3 * nb, hipMemcpyDeviceToHost, S(stream)) !=
-                hipSuccess ||
-            hipStreamSynchronize(S(stream)) != hipSuccess) {
-            e = UNO_ERR_DEVICE;
-            break;
-        }
+        e = launch_flux(g, mat->kappa, mat->dtype, g3, u + (int64_t)j * g.total, dpart + 3 * (size_t)nb * j, &nbo,
+                        S(stream));
+    }
+    if (e != UNO_OK) return e;
+    if (hipMemcpyAsync(hpart.data(), dpart, sizeof(double) * need, hipMemcpyDeviceToHost, S(stream)) != hipSuccess ||
+        hipStreamSynchronize(S(stream)) != hipSuccess)
+        return UNO_ERR_DEVICE;
+    for (int j = 0; j < d; ++j)
         for (int c = 0; c < d; ++c) {
             double acc = 0.0;
-            for (int b = 0; b < nb; ++b) acc += hpart[3 * (size_t)b + (3 - d + c)];
+            for (int b = 0; b < nb; ++b) acc += hpart[3 * (size_t)nb * j + 3 * (size_t)b + (3 - d + c)];
             Q[c][j] = acc / (double)g.total;
         }
-    }
-    (void)hipFree(dpart);
-    if (e != UNO_OK) return e;
     // out = Q G^-1 with G[:, j] = g_j  (Gauss-Jordan on the tiny d x d system)
     double G[3][6];
     for (int i = 0; i < d; ++i)
@@ -838,6 +863,11 @@ uno_status uno_shutdown(void)
         g_twhich = UNO_KT_NONE;
         for (hipEvent_t e : g_tpool) (void)hipEventDestroy(e);
         g_tpool.clear();
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_flux_mu);
+        for (FluxBuf& f : g_flux) (void)hipFree(f.p);
+        g_flux.clear();
     }
     el_release_all();
     return ws_release_all();

@@ -279,6 +279,107 @@ __global__ void __launch_bounds__(kBlock) k_resid_final(const double* __restrict
     }
 }
 
+// Right-hand sides of a batch: f_b = rhs of the macroscopic gradient b for
+// the conductivity field kappa + b ks (blockIdx.y = b), as k_rhs_node.
+struct Loads3 {
+    double g[64][3];
+};
+
+__global__ void __launch_bounds__(kBlock) k_rhs_batch(GridDev g, const double* __restrict__ kappa, int64_t ks,
+                                                      Loads3 L, double* __restrict__ f)
+{
+    const int b = blockIdx.y;
+    kappa += (int64_t)b * ks;
+    f += (int64_t)b * g.n;
+    const double c0 = L.g[b][0] * g.gcoef[0], c1 = L.g[b][1] * g.gcoef[1], c2 = L.g[b][2] * g.gcoef[2];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int z = (int)(i % g.n2);
+        const int64_t t = i / g.n2;
+        const int y = (int)(t % g.n1), x = (int)(t / g.n1);
+        double acc = 0.0;
+#pragma unroll
+        for (int s0 = 0; s0 < 2; ++s0)
+#pragma unroll
+            for (int s1 = 0; s1 < 2; ++s1)
+#pragma unroll
+                for (int s2 = 0; s2 < 2; ++s2) {
+                    // voxel x - 1 + s: the node is its upper corner along b for s_b = 0
+                    const int xe = (x - 1 + s0 < 0) ? x - 1 + s0 + g.n0 : x - 1 + s0;
+                    const int ye = (y - 1 + s1 < 0) ? y - 1 + s1 + g.n1 : y - 1 + s1;
+                    const int ze = (z - 1 + s2 < 0) ? z - 1 + s2 + g.n2 : z - 1 + s2;
+                    const double k = kappa[((int64_t)xe * g.n1 + ye) * g.n2 + ze];
+                    acc += k * ((s0 ? -c0 : c0) + (s1 ? -c1 : c1) + (s2 ? -c2 : c2));
+                }
+        f[i] = -g.hvol * acc;
+    }
+}
+
+// batched forms (blockIdx.y = right-hand side b: vectors at + b vs, partials
+// at + b ps, state b) of the mean removal and the true residual
+__global__ void __launch_bounds__(kBlock) k_sum_parts_b(int64_t n, const double* __restrict__ u,
+                                                        double* __restrict__ part, int64_t vs, int ps)
+{
+    __shared__ double slots[kBlock / 64];
+    u += (int64_t)blockIdx.y * vs;
+    part += (int64_t)blockIdx.y * ps;
+    double v = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        v += u[i];
+    const double b = block_reduce<OpSum>(v, slots);
+    if (threadIdx.x == 0) part[blockIdx.x] = b;
+}
+
+__global__ void __launch_bounds__(kBlock) k_sub_mean_b(int64_t n, double* __restrict__ u,
+                                                       const double* __restrict__ part, int np, CgState* st,
+                                                       int64_t vs, int ps)
+{
+    __shared__ double slots[kBlock / 64];
+    u += (int64_t)blockIdx.y * vs;
+    part += (int64_t)blockIdx.y * ps;
+    st += blockIdx.y;
+    const double mean = reduce_parts<OpSum>(part, np, slots) / (double)n;
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->mean = mean;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        u[i] -= mean;
+}
+
+__global__ void __launch_bounds__(kBlock) k_resid_parts_b(int64_t n, const double* __restrict__ f,
+                                                          const double* __restrict__ y, double* __restrict__ pa,
+                                                          double* __restrict__ pb, int64_t vs, int ps)
+{
+    __shared__ double slots[kBlock / 64];
+    f += (int64_t)blockIdx.y * vs;
+    y += (int64_t)blockIdx.y * vs;
+    pa += (int64_t)blockIdx.y * ps;
+    pb += (int64_t)blockIdx.y * ps;
+    double a = 0.0, b = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        a = OpMax::apply(a, fabs(f[i] - y[i]));
+        b = OpMax::apply(b, fabs(f[i]));
+    }
+    const double ra = block_reduce<OpMax>(a, slots);
+    const double rb = block_reduce<OpMax>(b, slots);
+    if (threadIdx.x == 0) {
+        pa[blockIdx.x] = ra;
+        pb[blockIdx.x] = rb;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_resid_final_b(const double* __restrict__ pa, const double* __restrict__ pb,
+                                                          int np, CgState* st, int ps)
+{
+    __shared__ double slots[kBlock / 64];
+    pa += (int64_t)blockIdx.y * ps;
+    pb += (int64_t)blockIdx.y * ps;
+    st += blockIdx.y;
+    const double a = reduce_parts<OpMax>(pa, np, slots);
+    const double b = reduce_parts<OpMax>(pb, np, slots);
+    if (threadIdx.x == 0) {
+        st->dmax = a;
+        st->fmax = b;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // driver
 
@@ -747,21 +848,26 @@ uno_status pcg_run_batch(const Grid& g, const double* kappa, int64_t ks, int nrh
     const int nb = w->nbr;
     const Parts P = parts_of(w);
     const int64_t n = g.total;
-    // rhs and initial residual r_0 = f - A u_0 (FP64), per right-hand side
-    for (int b = 0; b < nrhs; ++b) {
-        double* fb = w->f + b * n;
-        if (macro_loads3) {
-            e = launch_rhs(g, kappa + b * ks, UNO_F64, macro_loads3 + 3 * b, fb, UNO_F64, st);
-            if (e != UNO_OK) return e;
-        } else {
-            UNO_HIP(hipMemcpyAsync(fb, rhs + b * n, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
-        }
-        e = launch_fe_apply(g, kappa + b * ks, u + b * n, w->p + b * n, UNO_F64, st);
-        if (e != UNO_OK) return e;
-        hipLaunchKernelGGL(k_sub, dim3(nb), dim3(kBlock), 0, st, n, (const double*)fb, (const double*)(w->p + b * n),
-                           w->r + b * n);
-        UNO_HIP(hipGetLastError());
+    // rhs and initial residual r_0 = f - A u_0 (FP64), every right-hand side
+    // in one launch each
+    CgIter bi;
+    memset(&bi, 0, sizeof(bi));
+    bi.vs = n;
+    bi.ks = ks;
+    if (macro_loads3) {
+        Loads3 L;
+        memset(&L, 0, sizeof(L));
+        for (int b = 0; b < nrhs; ++b)
+            for (int a = 0; a < 3; ++a) L.g[b][a] = macro_loads3[3 * b + a];
+        hipLaunchKernelGGL(k_rhs_batch, dim3(nb, nrhs), dim3(kBlock), 0, st, g.dev, kappa, ks, L, w->f);
+    } else {
+        UNO_HIP(hipMemcpyAsync(w->f, rhs, sizeof(double) * n * nrhs, hipMemcpyDeviceToDevice, st));
     }
+    launch_tile<double, false, false>(g, kappa, u, nullptr, nullptr, w->p, nullptr, bi, nullptr, 0, nullptr, st,
+                                      MeanFree{nullptr, nullptr, nullptr}, nrhs);
+    hipLaunchKernelGGL(k_sub, dim3(nb), dim3(kBlock), 0, st, n * nrhs, (const double*)w->f, (const double*)w->p,
+                       w->r);
+    UNO_HIP(hipGetLastError());
     int k = 0;
     if (mixed) {
         // FP32 conductivities: one field, or one per right-hand side
@@ -782,20 +888,19 @@ uno_status pcg_run_batch(const Grid& g, const double* kappa, int64_t ks, int nrh
     }
     if (e != UNO_OK) return e;
     std::vector<CgState> hs(w->host_state, w->host_state + nrhs);
-    // zero-mean fluctuation (Sec. 5.1) and the true residual in FP64
-    for (int b = 0; b < nrhs; ++b) {
-        double* ub = u + b * n;
-        double* pa = P.rs[0] + (int64_t)b * w->npart;
-        double* pb = P.rs[1] + (int64_t)b * w->npart;
-        double* pd = P.dp + (int64_t)b * w->npart;
-        hipLaunchKernelGGL(k_sum_parts, dim3(nb), dim3(kBlock), 0, st, n, (const double*)ub, pd);
-        hipLaunchKernelGGL(k_sub_mean, dim3(nb), dim3(kBlock), 0, st, n, ub, (const double*)pd, nb, w->state + b);
-        e = launch_fe_apply(g, kappa + b * ks, ub, w->p + b * n, UNO_F64, st);
-        if (e != UNO_OK) return e;
-        hipLaunchKernelGGL(k_resid_parts, dim3(nb), dim3(kBlock), 0, st, n, (const double*)(w->f + b * n),
-                           (const double*)(w->p + b * n), pa, pb);
-        hipLaunchKernelGGL(k_resid_final, dim3(1), dim3(kBlock), 0, st, (const double*)pa, (const double*)pb, nb,
-                           w->state + b);
+    // zero-mean fluctuation (Sec. 5.1) and the true residual in FP64, every
+    // right-hand side in one launch each
+    {
+        const dim3 grid(nb, nrhs);
+        const int ps = w->npart;
+        hipLaunchKernelGGL(k_sum_parts_b, grid, dim3(kBlock), 0, st, n, (const double*)u, P.dp, n, ps);
+        hipLaunchKernelGGL(k_sub_mean_b, grid, dim3(kBlock), 0, st, n, u, (const double*)P.dp, nb, w->state, n, ps);
+        launch_tile<double, false, false>(g, kappa, u, nullptr, nullptr, w->p, nullptr, bi, nullptr, 0, nullptr, st,
+                                          MeanFree{nullptr, nullptr, nullptr}, nrhs);
+        hipLaunchKernelGGL(k_resid_parts_b, grid, dim3(kBlock), 0, st, n, (const double*)w->f, (const double*)w->p,
+                           P.rs[0], P.rs[1], n, ps);
+        hipLaunchKernelGGL(k_resid_final_b, dim3(1, nrhs), dim3(kBlock), 0, st, (const double*)P.rs[0],
+                           (const double*)P.rs[1], nb, w->state, ps);
         UNO_HIP(hipGetLastError());
     }
     UNO_HIP(hipMemcpyAsync(w->host_state, w->state, sizeof(CgState) * nrhs, hipMemcpyDeviceToHost, st));
