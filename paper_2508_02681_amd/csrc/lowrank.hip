@@ -109,9 +109,11 @@ __global__ void __launch_bounds__(256) k_lr_fwd(LowRankDev L, int ya, int rb, do
         dp_share = load_share<OpSum>(part_dp, np_dp);
         gk = gam[it.k];
     }
-    {
-        const int ny = min(ya, ye - yb);
-        const int64_t base = ((int64_t)x * L.n1 + yb) * L.n2;
+    // the first PF elements per thread of row group y0 into registers (the
+    // next group is fetched while the current one is transformed)
+    auto prefetch = [&](int y0) {
+        const int ny = min(ya, ye - y0);
+        const int64_t base = ((int64_t)x * L.n1 + y0) * L.n2;
 #pragma unroll
         for (int j = 0; j < PF; ++j) {
             const int q = threadIdx.x + 256 * j;
@@ -125,7 +127,8 @@ __global__ void __launch_bounds__(256) k_lr_fwd(LowRankDev L, int ya, int rb, do
                 }
             }
         }
-    }
+    };
+    prefetch(yb);
     for (int j = threadIdx.x; j < L.n2; j += 256) twz[j] = L.twz[j];
     for (int j = threadIdx.x; j < L.n1; j += 256) twy[j] = L.twy[j];
     double alpha = 0.0;
@@ -143,7 +146,7 @@ __global__ void __launch_bounds__(256) k_lr_fwd(LowRankDev L, int ya, int rb, do
         const int ny = min(ya, ye - y0);
         const int cnt = ny * L.n2;
         const int64_t base = ((int64_t)x * L.n1 + y0) * L.n2;
-        if (y0 == yb) {
+        {
 #pragma unroll
             for (int j = 0; j < PF; ++j) {
                 const int q = threadIdx.x + 256 * j;
@@ -160,7 +163,7 @@ __global__ void __launch_bounds__(256) k_lr_fwd(LowRankDev L, int ya, int rb, do
                 }
             }
         }
-        for (int q = threadIdx.x + (y0 == yb ? 256 * PF : 0); q < cnt; q += 256) {
+        for (int q = threadIdx.x + 256 * PF; q < cnt; q += 256) {
             const int64_t i = base + q;
             double v = r[i];
             if (UPDATE) {
@@ -172,22 +175,36 @@ __global__ void __launch_bounds__(256) k_lr_fwd(LowRankDev L, int ya, int rb, do
             R[q] = v;
             sq += v * v;
         }
+        if (y0 + ya < ye) prefetch(y0 + ya);
         __syncthreads();
         for (int q = threadIdx.x; q < ny * L.kzn; q += 256) {
             const int yl = q / L.kzn, kz = q % L.kzn;
             const double* row = R + yl * L.n2;
-            double re = 0.0, im = 0.0;
+            double re0 = 0.0, im0 = 0.0, re1 = 0.0, im1 = 0.0;  // even and odd z: two chains
             int t = 0;
-#pragma unroll 8
-            for (int z = 0; z < L.n2; ++z) {
-                const double v = row[z];
-                const double2 w = twz[t];
-                re += v * w.x;
-                im += v * w.y;
+            int z = 0;
+#pragma unroll 4
+            for (; z + 1 < L.n2; z += 2) {
+                const double v0 = row[z];
+                const double2 w0 = twz[t];
                 t += kz;
                 if (t >= L.n2) t -= L.n2;
+                const double v1 = row[z + 1];
+                const double2 w1 = twz[t];
+                t += kz;
+                if (t >= L.n2) t -= L.n2;
+                re0 += v0 * w0.x;
+                im0 += v0 * w0.y;
+                re1 += v1 * w1.x;
+                im1 += v1 * w1.y;
             }
-            Z[q] = make_double2(re, im);
+            if (z < L.n2) {
+                const double v0 = row[z];
+                const double2 w0 = twz[t];
+                re0 += v0 * w0.x;
+                im0 += v0 * w0.y;
+            }
+            Z[q] = make_double2(re0 + re1, im0 + im1);
         }
         __syncthreads();
         for (int q = threadIdx.x; q < plane; q += 256) {
