@@ -325,8 +325,8 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs every solve on a single MI355X "
-              "(multi-GPU sharding is design-only); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: every solve runs on a single MI355X "
+              "(sharding over several GPUs is not implemented); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
