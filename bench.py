@@ -261,12 +261,12 @@ def many_record(uno, si, torch, dev):
     nsolve = sum(len(l) for _, l in probs)
     dofs = [int(np.prod(kt.shape)) for kt in kaps]
 
-    def run_many(kind):
+    def run_many(kind, **kw):
         for it in items:
             it["u"] = torch.zeros((len(it["loads"]),) + tuple(it["kappa"].shape), dtype=torch.float64, device=dev)
         torch.cuda.synchronize()
         t = time.perf_counter()
-        us, infos = uno.pcg_solve_many(items, kind=kind, rtol=RTOL)
+        us, infos = uno.pcg_solve_many(items, kind=kind, rtol=RTOL, **kw)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t
         dit = sum(n * sum(i["iters"] for i in inf) for n, inf in zip(dofs, infos))
@@ -276,6 +276,9 @@ def many_record(uno, si, torch, dev):
     run_many("uno")  # warm-up: workspaces, streams
     dt, dit, conv, us = run_many("uno")
     dtj, ditj, convj, _ = run_many("jacobi")
+    f32 = dict(op_dtype=torch.float32, prec_dtype=torch.float32)
+    run_many("uno", **f32)
+    dtm, ditm, convm, _ = run_many("uno", **f32)
     torch.cuda.synchronize()
     t = time.perf_counter()
     for it in items:
@@ -289,11 +292,14 @@ def many_record(uno, si, torch, dev):
         "solves": nsolve,
         "uno_cg_many": {"s": dt, "solves_per_s": nsolve / dt, "dof_iters_per_s": dit / dt, "converged": conv},
         "jac_cg_many": {"s": dtj, "solves_per_s": nsolve / dtj, "dof_iters_per_s": ditj / dtj, "converged": convj},
+        "uno_cg_many_fp32": {"s": dtm, "solves_per_s": nsolve / dtm, "dof_iters_per_s": ditm / dtm,
+                             "converged": convm, "note": "FP32 operator and preconditioner, FP64 reductions"},
         "uno_cg_one_problem_at_a_time": {"s": dts, "solves_per_s": nsolve / dts},
         "speedup_many_vs_one_at_a_time": dts / dt,
         "time_to_tol_speedup_uno_vs_jac": dtj / dt,
     }
-    log("many: UNO-CG %.3f s (%.0f solves/s), one at a time %.3f s, Jacobi-CG %.3f s" % (dt, nsolve / dt, dts, dtj))
+    log("many: UNO-CG %.3f s (%.0f solves/s), FP32 %.3f s, one at a time %.3f s, Jacobi-CG %.3f s" %
+        (dt, nsolve / dt, dtm, dts, dtj))
     return out
 
 

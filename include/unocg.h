@@ -228,9 +228,10 @@ typedef struct {
     uno_solve_info *info;       /* host, nload records, nullable */
 } uno_problem;
 
-/* Solves the load cases of nprob independent problems (Algorithm 1 or 2,
- * FP64; opts->kind, rtol, max_iter and graph_chunk apply to all, opts->uno
- * is ignored in favour of each problem's).  Problems with the same grid and
+/* Solves the load cases of nprob independent problems (Algorithm 1 or 2;
+ * opts->kind, rtol, max_iter, graph_chunk and the precisions apply to all:
+ * FP64, or the FP32 mode of pcg_solve with FP64 residuals, reductions and
+ * stop test; opts->uno is ignored in favour of each problem's).  Problems with the same grid and
  * preconditioner form a class; the load cases of a class are carried
  * together by every pass kernel (up to 64 per launch, each with its own
  * conductivity field and stopping test); the classes follow one another on

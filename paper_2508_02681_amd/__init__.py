@@ -507,7 +507,8 @@ class uno_problem(ctypes.Structure):
                 ("info", ctypes.POINTER(uno_solve_info))]
 
 
-def pcg_solve_many(problems, kind="uno", rtol=1e-6, max_iter=100000, graph_chunk=0, L0=1.0):
+def pcg_solve_many(problems, kind="uno", rtol=1e-6, max_iter=100000, graph_chunk=0, L0=1.0,
+                   op_dtype=torch.float64, prec_dtype=torch.float64):
     """Solves many problems of uneven sizes in one call.  problems: list of
     dicts with "kappa" (device grid tensor), "loads" (nload x dim), optional
     "u" (nload x grid, zero-initialized if absent) and "precond" (UnoPrecond
@@ -536,7 +537,7 @@ def pcg_solve_many(problems, kind="uno", rtol=1e-6, max_iter=100000, graph_chunk
         keep += [loads, inf]
         us.append(u)
         infos.append(inf)
-    o = _opts(kind, None, rtol, max_iter, torch.float64, torch.float64, graph_chunk)
+    o = _opts(kind, None, rtol, max_iter, op_dtype, prec_dtype, graph_chunk)
     st = lib().pcg_solve_many(n, arr, ctypes.byref(o), _stream())
     out = [[dict(iters=I.iters, converged=bool(I.converged), rel_res=I.rel_res, true_rel_res=I.true_rel_res)
             for I in inf] for inf in infos]

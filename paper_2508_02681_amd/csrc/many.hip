@@ -96,7 +96,9 @@ extern "C" uno_status pcg_solve_many(int32_t nprob, const uno_problem* probs, co
     if (nprob < 0 || (nprob > 0 && !probs) || !opts) return UNO_ERR_ARG;
     if (!(opts->rtol >= 0.0) || opts->max_iter < 1) return UNO_ERR_ARG;
     if (opts->kind < UNO_PREC_NONE || opts->kind > UNO_PREC_UNO) return UNO_ERR_ARG;
-    if (opts->op_t != UNO_F64 || opts->prec_t != UNO_F64) return UNO_ERR_ARG;
+    const bool f64 = opts->op_t == UNO_F64 && opts->prec_t == UNO_F64;
+    const bool f32 = opts->op_t == UNO_F32 && opts->prec_t == UNO_F32;
+    if (!f64 && !f32) return UNO_ERR_ARG;
     // classes of equal grid shape, spacing and preconditioner
     std::map<std::tuple<int, int, int, int, double, double, double, const void*>, int> key;
     std::vector<Class> cls;
@@ -113,6 +115,7 @@ extern "C" uno_status pcg_solve_many(int32_t nprob, const uno_problem* probs, co
             pc = P.uno;
             if (!pc || pc->nc != 1) return UNO_ERR_ARG;
             if (pc->grid.n[0] != g.n[0] || pc->grid.n[1] != g.n[1] || pc->grid.n[2] != g.n[2]) return UNO_ERR_SHAPE;
+            if (f32 && !uno_use_lowrank(pc)) return UNO_ERR_ARG;  // FP32 UNO runs the learned-mode passes
         }
         const auto k = std::make_tuple(g.dim, g.n[0], g.n[1], g.n[2], g.h[0], g.h[1], g.h[2], (const void*)pc);
         auto it = key.find(k);

@@ -84,3 +84,27 @@ def test_many_errors_and_empty(uno):
         uno.pcg_solve_many([{"kappa": k, "loads": np.zeros((4, 2))}], kind="jacobi")  # 4 loads
     with pytest.raises(uno.UnoError):
         uno.pcg_solve_many([{"kappa": k, "loads": np.eye(2)}], kind="uno")  # no preconditioner
+
+
+def test_many_fp32_mode_matches_fp64(orc, uno):
+    """FP32 operator and preconditioner with FP64 reductions over the whole
+    work list: every effective tensor within 1e-5 of the FP64 one."""
+    probs = work_list(500)
+    pre = {}
+    for kap, _ in probs:
+        if kap.shape not in pre:
+            # M = 1: the learned-mode passes (which the FP32 mode needs) exist on every grid here
+            pre[kap.shape] = uno.UnoPrecond.create(kap.shape, 1, si.random_theta(uno.num_weights(len(kap.shape), 1),
+                                                                                7, scale=0.05))
+    items = [{"kappa": T(k), "loads": l, "precond": pre[k.shape]} for k, l in probs]
+    u64, i64 = uno.pcg_solve_many(items, kind="uno", rtol=1e-8)
+    items = [{"kappa": T(k), "loads": l, "precond": pre[k.shape]} for k, l in probs]
+    u32, i32 = uno.pcg_solve_many(items, kind="uno", rtol=1e-8, op_dtype=torch.float32, prec_dtype=torch.float32)
+    for (kap, loads), a, b, ia, ib in zip(probs, u64, u32, i64, i32):
+        assert all(i["converged"] for i in ia + ib)
+        d = len(kap.shape)
+        if len(loads) == d:
+            ka = uno.effective_tensor(T(kap), loads, a)
+            kb = uno.effective_tensor(T(kap), loads, b)
+            assert np.abs(kb - ka).max() < 1e-5 * np.abs(ka).max()
+        assert (a - b).abs().max().item() < 1e-4 * a.abs().max().item()
