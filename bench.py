@@ -215,6 +215,8 @@ def elastic_record(uno, si, torch, dev, M):
         "jac_cg": {"passes": its_j, "ms_per_solve": tj / 6, "converged": all(i["converged"] for i in ij),
                    "dof_iters_per_s": 3 * n * sum(its_j) / (tj * 1e-3)},
         "time_to_tol_speedup_uno_vs_jac": tj / tu,
+        "true_rel_res_max": {"uno_cg": max(i["true_rel_res"] for i in iu),
+                             "jac_cg": max(i["true_rel_res"] for i in ij)},
         "stiffness_uno": np.round(Du, 6).tolist(),
         "stiffness_rel_diff_uno_vs_jac": float(np.abs(Du - Dj).max() / np.abs(Dj).max()),
         "per_kernel": {k: rec[k] for k in ("kernel", "avg_us", "per_family_us", "per_family_GBs")},
@@ -260,6 +262,7 @@ def many_record(uno, si, torch, dev):
     items = [{"kappa": kt, "loads": l, "precond": pre[tuple(kt.shape)]} for kt, (_, l) in zip(kaps, probs)]
     nsolve = sum(len(l) for _, l in probs)
     dofs = [int(np.prod(kt.shape)) for kt in kaps]
+    worst = {}  # largest true relative residual at exit (FP64), per run
 
     def run_many(kind, **kw):
         for it in items:
@@ -271,6 +274,7 @@ def many_record(uno, si, torch, dev):
         dt = time.perf_counter() - t
         dit = sum(n * sum(i["iters"] for i in inf) for n, inf in zip(dofs, infos))
         conv = all(i["converged"] for inf in infos for i in inf)
+        worst[kind + ("_fp32" if kw else "")] = max(i["true_rel_res"] for inf in infos for i in inf)
         return dt, dit, conv, us
 
     run_many("uno")  # warm-up: workspaces, streams
@@ -296,6 +300,7 @@ def many_record(uno, si, torch, dev):
                              "converged": convm, "note": "FP32 operator and preconditioner, FP64 reductions"},
         "uno_cg_one_problem_at_a_time": {"s": dts, "solves_per_s": nsolve / dts},
         "speedup_many_vs_one_at_a_time": dts / dt,
+        "true_rel_res_max": worst,
         "time_to_tol_speedup_uno_vs_jac": dtj / dt,
     }
     log("many: UNO-CG %.3f s (%.0f solves/s), FP32 %.3f s, one at a time %.3f s, Jacobi-CG %.3f s" %
@@ -315,7 +320,8 @@ def parse():
     ap.add_argument("--train-seeds", type=int, default=64)
     ap.add_argument("--M", type=int, default=0, help="mode parameter (0 = pick from a small sweep)")
     ap.add_argument("--jac-steps", type=int, default=4)
-    ap.add_argument("--cpu-iters", type=int, default=20, help="oracle UNO-CG passes timed for cpu_baseline")
+    ap.add_argument("--cpu-iters", type=int, default=40, help="oracle UNO-CG passes timed for cpu_baseline")
+    ap.add_argument("--cpu-jac-iters", type=int, default=100, help="oracle Jacobi-CG passes timed beside it")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-192", action="store_true", help="skip the per-kernel roofline at 192^3")
     ap.add_argument("--no-elastic", action="store_true", help="skip the 128^3 elasticity record")
@@ -326,6 +332,24 @@ def parse():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this size first (reference for HBM counters)")
     return ap.parse_args()
+
+
+def copy_rate(torch, dev, mib=2048, reps=5):
+    """Achievable HBM rate on this device: a plain 2 GiB device-to-device copy
+    (read + write bytes) timed with events, best of a few."""
+    src = torch.ones(mib << 20, dtype=torch.uint8, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del src, dst
+    return round(2.0 * (mib << 20) / (best * 1e-3) / 1e9, 1)
 
 
 def main():
@@ -431,8 +455,9 @@ def main():
     loads_all = np.tile(LOADS, (nm, 1))
     sols = torch.zeros((nm * len(LOADS),) + SHAPE, dtype=torch.float64, device=dev)
     nr_all = nm * len(LOADS)
+    worst_true = {}  # largest true relative residual ||f - A u|| / ||f|| (FP64) at exit, per solver
 
-    def step(kind, precond, mode="all", **kw):
+    def step(kind, precond, mode="all", tag="uno_cg", **kw):
         """The whole hot path over the test set: rhs + CG for every load of
         every microstructure, then kappa_bar of each.  mode "all": the nm x 3
         solves carried together by every pass kernel; "micro": the 3 loads of
@@ -453,17 +478,18 @@ def main():
         for info in infos:
             if not info["converged"]:
                 raise RuntimeError("solve did not converge: %s" % info)
+        worst_true[tag] = max(worst_true.get(tag, 0.0), max(info["true_rel_res"] for info in infos))
         kbs = [uno.effective_tensor(k, LOADS, sols[3 * i: 3 * i + 3]) for i, k in enumerate(kap_test)]
         return [info["iters"] for info in infos], kbs
 
-    def timed(kind, precond, steps, warmup, mode="all", **kw):
+    def timed(kind, precond, steps, warmup, mode="all", tag="uno_cg", **kw):
         for _ in range(warmup):
-            step(kind, precond, mode, **kw)
+            step(kind, precond, mode, tag, **kw)
         torch.cuda.synchronize()
         t = time.perf_counter()
         all_its, kbs = [], []
         for _ in range(steps):
-            its, kb = step(kind, precond, mode, **kw)
+            its, kb = step(kind, precond, mode, tag, **kw)
             all_its += its
             kbs += kb
         torch.cuda.synchronize()
@@ -484,26 +510,26 @@ def main():
     log("UNO-CG 3 loads per launch: %.3f ms per solve; one load at a time: %.3f ms per solve" %
         (micro_t_solve, seq_t_solve))
     # ---------------- Jacobi-CG on the same microstructures ----------------
-    dtj, itsj, _ = timed("jacobi", None, args.jac_steps, 1)
+    dtj, itsj, _ = timed("jacobi", None, args.jac_steps, 1, tag="jac_cg")
     jac_t_solve = dtj / len(itsj) * 1e3
     jac_rate = n_dof * sum(itsj) / dtj
     log("Jac-CG: %.1f passes/solve, %.3e DOF*it/s, %.3f ms per solve" % (np.mean(itsj), jac_rate, jac_t_solve))
 
     # ---------------- mixed precision: FP32 operator / preconditioner ----------------
     f32 = dict(op_dtype=torch.float32, prec_dtype=torch.float32)
-    dtm, itsm, kbm = timed("uno", prec, 1, 0, **f32)
+    dtm, itsm, kbm = timed("uno", prec, 1, 0, tag="uno_cg_fp32", **f32)
     kb_err = max(float(np.abs(a - b).max() / np.abs(b).max()) for a, b in zip(kbm, kbs[:nm]))
     log("UNO-CG FP32 op/prec: %.1f passes/solve, %.3f ms per solve, kappa_bar rel diff vs FP64 %.1e" %
         (np.mean(itsm), dtm / len(itsm) * 1e3, kb_err))
     prec_bf16 = uno.UnoPrecond.create(SHAPE, M, theta, table_dtype=torch.bfloat16)
-    dtb, itsb, kbb = timed("uno", prec_bf16, 1, 0, **f32)
+    dtb, itsb, kbb = timed("uno", prec_bf16, 1, 0, tag="uno_cg_bf16_table", **f32)
     kb_err_b = max(float(np.abs(a - b).max() / np.abs(b).max()) for a, b in zip(kbb, kbs[:nm]))
     log("UNO-CG BF16 table: %.1f passes/solve, %.3f ms per solve, kappa_bar rel diff %.1e" %
         (np.mean(itsb), dtb / len(itsb) * 1e3, kb_err_b))
 
     # ---------------- FANS (reference-medium preconditioner) for context ----------------
     pf = uno.UnoPrecond.fans(SHAPE, 0.5 * (cfg["k_matrix"] + cfg["k_incl"]))
-    dtf, itsf, _ = timed("uno", pf, 1, 0)
+    dtf, itsf, _ = timed("uno", pf, 1, 0, tag="fans_cg")
     log("FANS-CG: %.1f passes/solve, %.3f ms per solve" % (np.mean(itsf), dtf / len(itsf) * 1e3))
 
     # ---------------- dominant kernel: live HIP-event timing ----------------
@@ -515,6 +541,7 @@ def main():
     prec.set_path(prec.PATH_AUTO)
     fams, bytes_per = kernel_families(uno, SHAPE, M, learned, True)
     roofline = roofline_record(fams, bytes_per, family_times(uno, fams, lambda: step("uno", prec)[0]))
+    roofline["copy_GBs"] = copy_rate(torch, dev)
     if learned and kernel_sources_hash() == TRAFFIC_SRC:
         roofline["traffic"] = TRAFFIC_BYTES.get(roofline["kernel"])
     log("roofline (64^3): %s %.1f GB/s per launch (%.3f of peak)" %
@@ -590,9 +617,19 @@ def main():
         t = time.perf_counter()
         _, it_cpu, _, _ = oracle.pcg(kap0, f, "uno", table=tab, rtol=RTOL, max_iter=args.cpu_iters)
         dtc = time.perf_counter() - t
+        t = time.perf_counter()
+        _, it_cj, _, _ = oracle.pcg(kap0, f, "jacobi", rtol=RTOL, max_iter=args.cpu_jac_iters)
+        dtcj = time.perf_counter() - t
         cpu = {"value": n_dof * it_cpu / dtc, "unit": "DOF*iters/s", "cores": 1, "kind": "oracle",
                "sample": "oracle UNO-CG (FP64, single thread) on test microstructure 1000, load e1, "
-                         "first %d passes of the same solve (%.1f s)" % (it_cpu, dtc)}
+                         "first %d passes of the same solve (%.1f s)" % (it_cpu, dtc),
+               "jac_cg": {"value": n_dof * it_cj / dtcj, "unit": "DOF*iters/s",
+                          "sample": "oracle Jacobi-CG, same microstructure and load, first %d passes (%.1f s)"
+                                    % (it_cj, dtcj)},
+               "ms_per_solve_est": {"uno_cg": dtc / it_cpu * float(np.mean(its)) * 1e3,
+                                    "jac_cg": dtcj / it_cj * float(np.mean(itsj)) * 1e3}}
+        log("oracle on one core: UNO-CG %.1f ms/pass, Jacobi-CG %.1f ms/pass" %
+            (dtc / it_cpu * 1e3, dtcj / it_cj * 1e3))
 
     out = {
         "metric": "DOF*iters/s (UNO-CG FP64, 3D 64^3, contrast 100, rel. residual 1e-6)",
@@ -622,6 +659,7 @@ def main():
                               "kappa_bar_rel_diff_vs_fp64": kb_err_b},
         "time_to_tol_speedup_uno_vs_jac": jac_t_solve / uno_t_solve,
         "kappa_bar_first": np.round(kbs[0], 6).tolist(),
+        "true_rel_res_max": worst_true,
         "roofline": roofline,
         "roofline_192": big,
         "differentiation": grad_rec,

@@ -685,6 +685,21 @@ static uno_status enqueue_pass(const Grid& g, Workspace* w, int kind, const uno_
 // residual equal to the true one.
 constexpr double kRestartFactor = 1e-3;
 
+// r = f - A u in FP64 for every right-hand side (A u goes to p, which the
+// next pass rewrites anyway)
+static void replace_residual(const Grid& g, Workspace* w, const double* kappa64, const double* u, int64_t ks,
+                             int nrhs, hipStream_t st)
+{
+    CgIter bi;
+    memset(&bi, 0, sizeof(bi));
+    bi.vs = g.total;
+    bi.ks = ks;
+    launch_tile<double, false, false>(g, kappa64, u, nullptr, nullptr, (double*)w->p, nullptr, bi, nullptr, 0,
+                                      nullptr, st, MeanFree{nullptr, nullptr, nullptr}, nrhs);
+    hipLaunchKernelGGL(k_sub, dim3(w->nbr), dim3(kBlock), 0, st, g.total * nrhs, (const double*)w->f,
+                       (const double*)w->p, w->r);
+}
+
 // The CG loop for nrhs right-hand sides.  FP32 mode: the residual
 // replacement restarts every right-hand side together (one pass index k0
 // for all) as soon as one of the running ones has dropped by the restart
@@ -751,6 +766,38 @@ static uno_status pcg_loop(const Grid& g, Workspace* w, const double* kappa64, c
             const CgState& hs = w->host_state[b];
             if (hs.status == 0 && hs.done == INT_MAX) running = true;
         }
+        if (!running && restarts && k < o->max_iter) {
+            // FP32 mode: the recursive residual of the last cycle drifts from
+            // f - A u by the FP32 operator's rounding; a load whose true
+            // residual (FP64) is still above its tolerance is reopened and
+            // the recurrence restarts from that residual
+            replace_residual(g, w, kappa64, u, ks, nrhs, st);
+            const dim3 grid(nb, nrhs);
+            hipLaunchKernelGGL(k_resid_parts_b, grid, dim3(kBlock), 0, st, g.total, (const double*)w->f,
+                               (const double*)w->p, P.rs[0], P.rs[1], g.total, w->npart);
+            hipLaunchKernelGGL(k_resid_final_b, dim3(1, nrhs), dim3(kBlock), 0, st, (const double*)P.rs[0],
+                               (const double*)P.rs[1], nb, w->state, w->npart);
+            UNO_HIP(hipGetLastError());
+            UNO_HIP(hipMemcpyAsync(w->host_state, w->state, sizeof(CgState) * nrhs, hipMemcpyDeviceToHost, st));
+            UNO_HIP(hipStreamSynchronize(st));
+            bool reopen = false;
+            for (int b = 0; b < nrhs; ++b) {
+                CgState& hs = w->host_state[b];
+                if (hs.status != 0 || hs.done == INT_MAX || !(hs.dmax > hs.tol_abs)) continue;
+                hs.done = INT_MAX;
+                cycle_r[b] = hs.dmax;
+                prev_r[b] = -1.0;
+                reopen = true;
+            }
+            if (reopen) {
+                UNO_HIP(hipMemcpyAsync(w->state, w->host_state, sizeof(CgState) * nrhs, hipMemcpyHostToDevice, st));
+                e = start(0);
+                if (e != UNO_OK) return e;
+                k0 = k;
+                chunk = o->graph_chunk > 0 ? o->graph_chunk : 8;
+                continue;
+            }
+        }
         if (!running || k >= o->max_iter) break;
         if (restarts) {
             bool due = false;
@@ -761,18 +808,8 @@ static uno_status pcg_loop(const Grid& g, Workspace* w, const double* kappa64, c
                 if (hs.rmax_last <= kRestartFactor * cycle_r[b]) due = true;
             }
             if (due) {
-                // residual replacement, every load at once: r = f - A u (FP64;
-                // the FP64 products go to p, rewritten by the next pass anyway),
-                // restart at pass k
-                CgIter bi;
-                memset(&bi, 0, sizeof(bi));
-                bi.vs = g.total;
-                bi.ks = ks;
-                launch_tile<double, false, false>(g, kappa64, u, nullptr, nullptr, (double*)w->p, nullptr, bi, nullptr,
-                                                  0, nullptr, st, MeanFree{nullptr, nullptr, nullptr}, nrhs);
-                UNO_HIP(hipGetLastError());
-                hipLaunchKernelGGL(k_sub, dim3(nb), dim3(kBlock), 0, st, g.total * nrhs, (const double*)w->f,
-                                   (const double*)w->p, w->r);
+                // residual replacement, every load at once, restart at pass k
+                replace_residual(g, w, kappa64, u, ks, nrhs, st);
                 for (int b = 0; b < nrhs; ++b) {
                     const CgState& hs = w->host_state[b];
                     if (hs.status != 0 || hs.done != INT_MAX) continue;

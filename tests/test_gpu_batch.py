@@ -133,6 +133,7 @@ def test_batch_mixed_precision_microstructures(orc, uno, kind):
     u, infos = uno.pcg_solve_batch(K, macro_loads=loads, kind=kind, precond=p, rtol=1e-7,
                                    op_dtype=torch.float32, prec_dtype=torch.float32, kappa_per_rhs=True)
     assert all(i["converged"] for i in infos)
+    assert all(i["true_rel_res"] <= 1e-7 * (1 + 1e-6) for i in infos)
     for m, kn in enumerate(kaps):
         sols = [orc.pcg(kn, orc.rhs(kn, g), "jacobi", rtol=1e-12)[0] for g in np.eye(3)]
         ko = orc.effective_tensor(kn, sols, np.eye(3))
