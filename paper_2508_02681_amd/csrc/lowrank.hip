@@ -96,7 +96,8 @@ __global__ void __launch_bounds__(256) k_lr_fwd(LowRankDev L, int ya, int rb, do
     double2* twy = twz + L.n2;                     // n1
     double2* Z = twy + L.n1;                       // ya x kzn
     double2* Gacc = Z + ya * L.kzn;                // plane
-    double* R = (double*)(Gacc + plane);           // ya x n2
+    double* R = (double*)(Gacc + plane);           // ya rows of n2 + 1 (padded against bank conflicts)
+    const int rs = L.n2 + 1;
     double m = 0.0, sq = 0.0;
     // all global loads first (state, partials, gamma, the first PF elements
     // of the four vectors of the first row group, twiddles); decisions after
@@ -129,6 +130,12 @@ __global__ void __launch_bounds__(256) k_lr_fwd(LowRankDev L, int ya, int rb, do
         }
     };
     prefetch(yb);
+    int rq[PF];  // padded LDS slot of element q: q + q / n2
+#pragma unroll
+    for (int j = 0; j < PF; ++j) {
+        const int q = threadIdx.x + 256 * j;
+        rq[j] = q + q / L.n2;
+    }
     for (int j = threadIdx.x; j < L.n2; j += 256) twz[j] = L.twz[j];
     for (int j = threadIdx.x; j < L.n1; j += 256) twy[j] = L.twy[j];
     double alpha = 0.0;
@@ -158,7 +165,7 @@ __global__ void __launch_bounds__(256) k_lr_fwd(LowRankDev L, int ya, int rb, do
                         u[base + q] = uv[j] + alpha * dv[j];
                         m = OpMax::apply(m, fabs(v));
                     }
-                    R[q] = v;
+                    R[rq[j]] = v;
                     sq += v * v;
                 }
             }
@@ -172,57 +179,48 @@ __global__ void __launch_bounds__(256) k_lr_fwd(LowRankDev L, int ya, int rb, do
                 u[i] += alpha * (double)d[i];
                 m = OpMax::apply(m, fabs(v));
             }
-            R[q] = v;
+            R[q + q / L.n2] = v;
             sq += v * v;
         }
         if (y0 + ya < ye) prefetch(y0 + ya);
         __syncthreads();
+        // Z[y][kz] = sum_z R[y][z] w^z, w = twz[kz], by Horner's rule in w^2
+        // over the even and the odd z (two independent chains), then E + w O
         for (int q = threadIdx.x; q < ny * L.kzn; q += 256) {
             const int yl = q / L.kzn, kz = q % L.kzn;
-            const double* row = R + yl * L.n2;
-            double re0 = 0.0, im0 = 0.0, re1 = 0.0, im1 = 0.0;  // even and odd z: two chains
-            int t = 0;
-            int z = 0;
-#pragma unroll 4
-            for (; z + 1 < L.n2; z += 2) {
-                const double v0 = row[z];
-                const double2 w0 = twz[t];
-                t += kz;
-                if (t >= L.n2) t -= L.n2;
-                const double v1 = row[z + 1];
-                const double2 w1 = twz[t];
-                t += kz;
-                if (t >= L.n2) t -= L.n2;
-                re0 += v0 * w0.x;
-                im0 += v0 * w0.y;
-                re1 += v1 * w1.x;
-                im1 += v1 * w1.y;
+            const double* row = R + yl * rs;
+            const double2 w = twz[kz], w2 = twz[mod_n(2 * kz, L.n2)];
+            double er = 0.0, ei = 0.0, or_ = 0.0, oi = 0.0;
+            int z = (L.n2 - 1) & ~1;  // last even z
+            if (z + 1 < L.n2) or_ = row[z + 1];
+            er = row[z];
+            for (z -= 2; z >= 0; z -= 2) {
+                const double ve = row[z], vo = row[z + 1];
+                const double ner = fma(er, w2.x, fma(-ei, w2.y, ve));
+                ei = fma(er, w2.y, ei * w2.x);
+                er = ner;
+                const double nor = fma(or_, w2.x, fma(-oi, w2.y, vo));
+                oi = fma(or_, w2.y, oi * w2.x);
+                or_ = nor;
             }
-            if (z < L.n2) {
-                const double v0 = row[z];
-                const double2 w0 = twz[t];
-                re0 += v0 * w0.x;
-                im0 += v0 * w0.y;
-            }
-            Z[q] = make_double2(re0 + re1, im0 + im1);
+            Z[q] = make_double2(er + or_ * w.x - oi * w.y, ei + or_ * w.y + oi * w.x);
         }
         __syncthreads();
+        // Gacc[ky][kz] += w^y0 sum_yl Z[yl][kz] w^yl, w = twy[ky mod n1], by
+        // Horner's rule over the rows of the group
         for (int q = threadIdx.x; q < plane; q += 256) {
             const int kyi = q / L.kzn, kz = q % L.kzn;
-            const int step = mod_n(kyi - L.m, L.n1);
-            int t = mod_n((int64_t)(kyi - L.m) * y0, L.n1);
+            const double2 w = twy[mod_n(kyi - L.m, L.n1)];
+            const double2 ph = twy[mod_n((int64_t)(kyi - L.m) * y0, L.n1)];
             double re = 0.0, im = 0.0;
-#pragma unroll 4
-            for (int yl = 0; yl < ny; ++yl) {
+            for (int yl = ny - 1; yl >= 0; --yl) {
                 const double2 a = Z[yl * L.kzn + kz];
-                const double2 w = twy[t];
-                re += a.x * w.x - a.y * w.y;
-                im += a.x * w.y + a.y * w.x;
-                t += step;
-                if (t >= L.n1) t -= L.n1;
+                const double nre = fma(re, w.x, fma(-im, w.y, a.x));
+                im = fma(re, w.y, fma(im, w.x, a.y));
+                re = nre;
             }
-            Gacc[q].x += re;
-            Gacc[q].y += im;
+            Gacc[q].x += re * ph.x - im * ph.y;
+            Gacc[q].y += re * ph.y + im * ph.x;
         }
         __syncthreads();
     }
@@ -984,7 +982,7 @@ uno_status lowrank_create(const Grid& g, const FftPlan& fp, int M, double W, con
     p->blocks_c = L.n0 * ((L.n1 + p->yc - 1) / p->yc);  // pass C takes all components of a slab
     const int plane = L.kyn * L.kzn;
     p->lds_a = sizeof(double2) * ((size_t)L.n2 + L.n1 + (size_t)p->ya * L.kzn + plane) +
-               sizeof(double) * (size_t)p->ya * L.n2;
+               sizeof(double) * (size_t)p->ya * (L.n2 + 1);
     p->cb_mid = 8;
     while (p->cb_mid > 1 && sizeof(double2) * (size_t)nc * p->cb_mid * (L.n0 + L.kxn) > 48 * 1024) p->cb_mid /= 2;
     p->blocks_mid = (L.kyn * L.kzn + p->cb_mid - 1) / p->cb_mid;
