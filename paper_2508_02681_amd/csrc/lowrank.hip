@@ -450,6 +450,152 @@ __global__ void __launch_bounds__(256) k_lr_mid3(LowRankDev L, int nch, int cb, 
     }
 }
 
+// Pass C for one component (the form the scalar problems use): one
+// workgroup per (x-slab, chunk of rows y).  Along y the partial
+// inverse transform is evaluated with Horner's rule in the unit-modulus
+// phase factor: a thread owns one k_z column for two rows (each H value read
+// from LDS feeds two chains).  Along z only the real part is needed, and the
+// points z and n2 - z share it: with V_k = a_k + i b_k and theta = 2 pi z / n2,
+//   Re sum_k V_k e^{+i k theta} = C - S,  Re sum_k V_k e^{-i k theta} = C + S,
+//   C = sum_k a_k cos k theta,  S = sum_k b_k sin k theta,
+// both by Clenshaw's recurrence y_k = c_k + 2 cos(theta) y_(k+1) - y_(k+2)
+// (two operations per step and series for two points, half of a complex
+// Horner step per point).  A thread owns pairs (z, n2 - z) of one row
+// (each V value feeds all its pairs) and also loads, updates and writes
+// exactly those nodes.  (For three components the pairs' recurrence state
+// costs more registers than the halved arithmetic saves: k_lr_inv below.)
+template <bool CG, typename TS>
+__global__ void __launch_bounds__(256) k_lr_inv_pairs(LowRankDev L, int y_chunk, const double* __restrict__ r,
+                                                      const double2* __restrict__ H, TS* __restrict__ s, CgIter it)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double slots[4];
+    if (blockIdx.y > 0) {
+        const int64_t vo = (int64_t)blockIdx.y * it.vs;
+        r += vo;
+        s += vo;
+        H += (int64_t)blockIdx.y * L.hsz;
+        it = rhs_iter(it);
+    }
+    const int nch = (L.n1 + y_chunk - 1) / y_chunk;
+    const int x = blockIdx.x / nch;
+    const int y0 = (blockIdx.x % nch) * y_chunk;
+    const int ny = min(y_chunk, L.n1 - y0);
+    const int plane = L.kyn * L.kzn;
+    double2* Hs = (double2*)smem;  // kyn x kzn
+    double2* V = Hs + plane;       // ny x kzn
+    // pairs of this thread: row t / tpr, pair j = t % tpr + tpr i, points
+    // z = j and n2 - j (one point for j = 0 and j = n2 / 2)
+    const int tpr = 256 / y_chunk;
+    const int row = threadIdx.x / tpr, part = threadIdx.x % tpr;
+    const bool row_ok = row < ny;
+    const int npair = L.n2 / 2 + 1;
+    const int ppt = (npair + tpr - 1) / tpr;
+    constexpr int ZB = 4;  // pairs held in registers per round
+    const int64_t rbase = ((int64_t)x * L.n1 + y0 + row) * L.n2;
+    // loads first: state, the coefficient plane and this thread's r
+    StateLoad sl;
+    if (CG) sl = load_state(it.st);
+    double rv[ZB], rw[ZB];  // r at z = j and at n2 - j
+    auto load_r = [&](int i0) {
+#pragma unroll
+        for (int i = 0; i < ZB; ++i) {
+            const int j = part + tpr * (i0 + i);
+            const bool ok = row_ok && j < npair && i0 + i < ppt;
+            const int zm = j == 0 ? 0 : L.n2 - j;
+            rv[i] = ok ? r[rbase + j] : 0.0;
+            rw[i] = (ok && zm != j) ? r[rbase + zm] : 0.0;
+        }
+    };
+    load_r(0);
+    for (int j = threadIdx.x; j < plane; j += blockDim.x) Hs[j] = H[(int64_t)x * plane + j];
+    if (CG && ended(sl, it.k)) return;
+    __syncthreads();
+    // V[y][kz] = exp(-i M phi_y) sum_kyi H[kyi][kz] w_y^kyi, w_y = exp(+2 pi i y / n1)
+    {
+        const int yh = (ny + 1) / 2;
+        for (int t = threadIdx.x; t < yh * L.kzn; t += blockDim.x) {
+            const int ya = t % yh, kz = t / yh;
+            const int yb = (ya + yh < ny) ? ya + yh : ya;
+            const double2 ta = L.twy[y0 + ya], tb = L.twy[y0 + yb];
+            const double2 wa = make_double2(ta.x, -ta.y), wb = make_double2(tb.x, -tb.y);
+            const double2* hcol = Hs + kz;
+            double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
+            for (int kyi = L.kyn - 1; kyi >= 0; --kyi) {
+                const double2 h = hcol[kyi * L.kzn];
+                const double nar = ar * wa.x - ai * wa.y + h.x;
+                ai = ar * wa.y + ai * wa.x + h.y;
+                ar = nar;
+                const double nbr = br * wb.x - bi * wb.y + h.x;
+                bi = br * wb.y + bi * wb.x + h.y;
+                br = nbr;
+            }
+            const double2 sa = L.twy[mod_n((int64_t)L.m * (y0 + ya), L.n1)];
+            const double2 sb = L.twy[mod_n((int64_t)L.m * (y0 + yb), L.n1)];
+            V[ya * L.kzn + kz] = make_double2(ar * sa.x - ai * sa.y, ar * sa.y + ai * sa.x);
+            if (yb != ya) V[yb * L.kzn + kz] = make_double2(br * sb.x - bi * sb.y, br * sb.y + bi * sb.x);
+        }
+    }
+    __syncthreads();
+    // s = W r + Re sum_kz V[row][kz] w_z^kz, w_z = exp(+2 pi i z / n2), for
+    // the pair (z, n2 - z) by Clenshaw's recurrence in cos(2 pi z / n2)
+    double acc = 0.0, ssum = 0.0;
+    if (row_ok) {
+        const double2* vrow = V + row * L.kzn;
+        for (int i0 = 0; i0 < ppt; i0 += ZB) {
+            double c2[ZB], sn[ZB], b1[ZB], b2[ZB], d1[ZB], d2[ZB];
+            if (i0 > 0) load_r(i0);
+#pragma unroll
+            for (int i = 0; i < ZB; ++i) {
+                const int j = part + tpr * (i0 + i);
+                const double2 tz = L.twz[j < npair ? j : 0];  // exp(-2 pi i j / n2)
+                c2[i] = 2.0 * tz.x;
+                sn[i] = -tz.y;
+                b1[i] = b2[i] = d1[i] = d2[i] = 0.0;
+            }
+            for (int kz = L.kzn - 1; kz >= 1; --kz) {
+                const double2 v = vrow[kz];
+#pragma unroll
+                for (int i = 0; i < ZB; ++i) {
+                    const double nb = fma(c2[i], b1[i], v.x) - b2[i];
+                    b2[i] = b1[i];
+                    b1[i] = nb;
+                    const double nd = fma(c2[i], d1[i], v.y) - d2[i];
+                    d2[i] = d1[i];
+                    d1[i] = nd;
+                }
+            }
+            const double a0 = vrow[0].x;
+#pragma unroll
+            for (int i = 0; i < ZB; ++i) {
+                const int j = part + tpr * (i0 + i);
+                if (j >= npair || i0 + i >= ppt) continue;
+                const int zm = j == 0 ? 0 : L.n2 - j;
+                const double C = fma(0.5 * c2[i], b1[i], a0) - b2[i];
+                const double S = d1[i] * sn[i];
+                const TS sp = (TS)(L.W * rv[i] + (C - S));
+                s[rbase + j] = sp;
+                ssum += (double)sp;
+                acc += rv[i] * (double)sp;
+                if (zm != j) {
+                    const TS sm = (TS)(L.W * rw[i] + (C + S));
+                    s[rbase + zm] = sm;
+                    ssum += (double)sm;
+                    acc += rw[i] * (double)sm;
+                }
+            }
+        }
+    }
+    if (CG) {
+        const double b = block_reduce<OpSum>(acc, slots);
+        if (threadIdx.x == 0) it.part_rs[blockIdx.x] = b;
+        if (sizeof(TS) == 4) {
+            const double bs = block_reduce<OpSum>(ssum, slots);
+            if (threadIdx.x == 0) it.part_ssum[blockIdx.x] = bs;
+        }
+    }
+}
+
 // Pass C: one workgroup per (x-slab, chunk of rows y).  Both partial
 // inverse transforms are evaluated with Horner's rule in the unit-modulus
 // phase factor: along y a thread owns one k_z column for two rows (each H
@@ -1187,14 +1333,14 @@ uno_status lowrank_finish(const LowRankPlan* p, const double* r, T* s, const CgI
             uno_launch(UNO_KT_FFT_INV, k_lr_inv<true, T, 3>, grid, dim3(256), p->lds_c, st, L, bt.yc, r,
                        (const double2*)bt.H, s, it);
         else
-            uno_launch(UNO_KT_FFT_INV, k_lr_inv<true, T, 1>, grid, dim3(256), p->lds_c, st, L, bt.yc, r,
+            uno_launch(UNO_KT_FFT_INV, k_lr_inv_pairs<true, T>, grid, dim3(256), p->lds_c, st, L, bt.yc, r,
                        (const double2*)bt.H, s, it);
     } else {
         if (L.nc == 3)
             uno_launch(UNO_KT_FFT_INV, k_lr_inv<false, T, 3>, grid, dim3(256), p->lds_c, st, L, bt.yc, r,
                        (const double2*)bt.H, s, it);
         else
-            uno_launch(UNO_KT_FFT_INV, k_lr_inv<false, T, 1>, grid, dim3(256), p->lds_c, st, L, bt.yc, r,
+            uno_launch(UNO_KT_FFT_INV, k_lr_inv_pairs<false, T>, grid, dim3(256), p->lds_c, st, L, bt.yc, r,
                        (const double2*)bt.H, s, it);
     }
     UNO_HIP(hipGetLastError());
