@@ -50,9 +50,11 @@ struct LowRankDev {
     const double2* twz;
 };
 
-__device__ __forceinline__ int mod_n(int64_t v, int n)
+// v mod n in [0, n); 32-bit (every use has |v| <= n^2 / 2 with n < 46341):
+// a 64-bit remainder is a long instruction sequence on this GPU
+__device__ __forceinline__ int mod_n(int v, int n)
 {
-    int r = (int)(v % n);
+    const int r = v % n;
     return r < 0 ? r + n : r;
 }
 
@@ -211,7 +213,7 @@ __global__ void __launch_bounds__(256) k_lr_fwd(LowRankDev L, int ya, int rb, do
         for (int q = threadIdx.x; q < plane; q += 256) {
             const int kyi = q / L.kzn, kz = q % L.kzn;
             const double2 w = twy[mod_n(kyi - L.m, L.n1)];
-            const double2 ph = twy[mod_n((int64_t)(kyi - L.m) * y0, L.n1)];
+            const double2 ph = twy[mod_n((kyi - L.m) * y0, L.n1)];
             double re = 0.0, im = 0.0;
             for (int yl = ny - 1; yl >= 0; --yl) {
                 const double2 a = Z[yl * L.kzn + kz];
@@ -357,7 +359,7 @@ __global__ void __launch_bounds__(256) k_lr_mid(LowRankDev L, int nch, int cb, c
         const double2 t = L.twx[x];                       // exp(-2 pi i x / n0)
         const double2 w = make_double2(t.x, -t.y);        // exp(+2 pi i x / n0)
         const double2 v = horner_eo(X + cl, cb, L.kxn, w);
-        const double2 sh = L.twx[mod_n((int64_t)L.mx * x, L.n0)];  // exp(-2 pi i mx x / n0)
+        const double2 sh = L.twx[mod_n(L.mx * x, L.n0)];  // exp(-2 pi i mx x / n0)
         H[(int64_t)x * plane + col] = cmul(v, sh);
     }
 }
@@ -445,7 +447,7 @@ __global__ void __launch_bounds__(256) k_lr_mid3(LowRankDev L, int nch, int cb, 
         const double2 t = L.twx[x];
         const double2 w = make_double2(t.x, -t.y);
         const double2 v = horner_eo(X + c * nxk + cl, cb, L.kxn, w);
-        const double2 sh = L.twx[mod_n((int64_t)L.mx * x, L.n0)];
+        const double2 sh = L.twx[mod_n(L.mx * x, L.n0)];
         H[(int64_t)(c * L.n0 + x) * plane + col] = cmul(v, sh);
     }
 }
@@ -530,8 +532,8 @@ __global__ void __launch_bounds__(256) k_lr_inv_pairs(LowRankDev L, int y_chunk,
                 bi = br * wb.y + bi * wb.x + h.y;
                 br = nbr;
             }
-            const double2 sa = L.twy[mod_n((int64_t)L.m * (y0 + ya), L.n1)];
-            const double2 sb = L.twy[mod_n((int64_t)L.m * (y0 + yb), L.n1)];
+            const double2 sa = L.twy[mod_n(L.m * (y0 + ya), L.n1)];
+            const double2 sb = L.twy[mod_n(L.m * (y0 + yb), L.n1)];
             V[ya * L.kzn + kz] = make_double2(ar * sa.x - ai * sa.y, ar * sa.y + ai * sa.x);
             if (yb != ya) V[yb * L.kzn + kz] = make_double2(br * sb.x - bi * sb.y, br * sb.y + bi * sb.x);
         }
@@ -669,8 +671,8 @@ __global__ void __launch_bounds__(256) k_lr_inv(LowRankDev L, int y_chunk, const
                 bi = br * wb.y + bi * wb.x + h.y;
                 br = nbr;
             }
-            const double2 sa = L.twy[mod_n((int64_t)L.m * (y0 + ya), L.n1)];
-            const double2 sb = L.twy[mod_n((int64_t)L.m * (y0 + yb), L.n1)];
+            const double2 sa = L.twy[mod_n(L.m * (y0 + ya), L.n1)];
+            const double2 sb = L.twy[mod_n(L.m * (y0 + yb), L.n1)];
             double2* vc = V + (int64_t)c * ny * L.kzn;
             vc[ya * L.kzn + kz] = make_double2(ar * sa.x - ai * sa.y, ar * sa.y + ai * sa.x);
             if (yb != ya) vc[yb * L.kzn + kz] = make_double2(br * sb.x - bi * sb.y, br * sb.y + bi * sb.x);
@@ -1084,6 +1086,9 @@ uno_status lowrank_create(const Grid& g, const FftPlan& fp, int M, double W, con
                           LowRankPlan** out, int nc, const double* Wq)
 {
     if (nc != 1 && nc != 3) return UNO_ERR_ARG;
+    // the kernels form the phase indices M j (j < n) in 32-bit integers
+    for (int b = 0; b < 3; ++b)
+        if ((int64_t)M * g.n[b] >= ((int64_t)1 << 30)) return UNO_ERR_SHAPE;
     LowRankPlan* p = new LowRankPlan();
     memset(p, 0, sizeof(*p));
     LowRankDev& L = p->dev;
