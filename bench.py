@@ -45,12 +45,12 @@ HBM_PEAK_GBS = 8000.0
 # as they were when counted (TRAFFIC_SRC: hash of the files in TRAFFIC_FILES);
 # after any change the figure is withheld.
 TRAFFIC_FILES = ["lowrank.hip", "stencil_tile.h", "cg_ctl.h", "reduce.h", "cg.hip"]
-TRAFFIC_SRC = "6f23f6acfaeffb9d"
+TRAFFIC_SRC = "176a36b940684efd"
 TRAFFIC_BYTES = {  # per launch of the benchmark step (48 right-hand sides)
-    "k_stencil_march<double,CG>": 447917020,
-    "k_lr_fwd<update,double>": 491897278,
-    "k_lr_mid": 41548041,
-    "k_lr_inv<double>": 174238000,
+    "k_stencil_march<double,CG>": 447925455,
+    "k_lr_fwd<update,double>": 491875947,
+    "k_lr_mid": 41540599,
+    "k_lr_inv_pairs<double>": 203446371,
 }
 
 
@@ -76,7 +76,7 @@ def kernel_families(uno, shape, M, learned, kappa_per_rhs):
     if learned:
         # pass B -> pass C -> operator -> [update + pass A]
         fams = {uno.KT_MATVEC: "k_stencil_march<double,CG>", uno.KT_UPDATE: "k_lr_fwd<update,double>",
-                uno.KT_FFT_MID: "k_lr_mid", uno.KT_FFT_INV: "k_lr_inv<double>"}
+                uno.KT_FFT_MID: "k_lr_mid", uno.KT_FFT_INV: "k_lr_inv_pairs<double>"}
         bytes_per = {
             uno.KT_MATVEC: (n * 8 * 4 + kap_rhs, kap_launch),  # read s, d_old, kappa; write d_new, p
             uno.KT_UPDATE: (n * 8 * 6 + nblk * 16, 0),        # read r, u, d, p; write r, u, block spectrum
@@ -132,7 +132,9 @@ def roofline_record(fams, bytes_per, timed):
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
             "kernel": fams[dom], "avg_us": round(avg_s * 1e6, 2), "bytes_per_launch": round(bpl),
             "per_family_us": {k: round(v, 2) for k, v in per_us.items()},
-            "per_family_GBs": {fams[f]: round(total_bytes(f) / max(fam_ms[f][0], 1e-9) / 1e6, 1) for f in fams}}
+            "per_family_GBs": {fams[f]: round(total_bytes(f) / max(fam_ms[f][0], 1e-9) / 1e6, 1) for f in fams},
+            "per_family_ms_per_run": {fams[f]: round(fam_ms[f][0], 3) for f in fams},
+            "per_family_launches": {fams[f]: int(fam_ms[f][1]) for f in fams}}
 
 
 def elastic_families(uno, shape, M):
@@ -219,7 +221,8 @@ def elastic_record(uno, si, torch, dev, M):
                              "jac_cg": max(i["true_rel_res"] for i in ij)},
         "stiffness_uno": np.round(Du, 6).tolist(),
         "stiffness_rel_diff_uno_vs_jac": float(np.abs(Du - Dj).max() / np.abs(Dj).max()),
-        "per_kernel": {k: rec[k] for k in ("kernel", "avg_us", "per_family_us", "per_family_GBs")},
+        "per_kernel": {k: rec[k] for k in ("kernel", "avg_us", "per_family_us", "per_family_GBs", "per_family_ms_per_run",
+                                           "per_family_launches")},
     }
     log("elastic 128^3: UNO-CG %.1f ms/solve (%d passes), Jac-CG %.1f ms/solve (%d passes), speedup %.2f" %
         (tu / 6, max(its_u), tj / 6, max(its_j), tj / tu))
