@@ -1,9 +1,10 @@
-"""GPU parity at the full sizes of the elasticity and many-problem
-workloads, in the configurations the benchmark times: the 128^3 elastic
-operator and c = 3 UNO apply against the oracle on every node, the six
-Mandel solves checked by properties that hold at any size (true residual,
-symmetry of the stiffness, Voigt and Reuss bounds, agreement of UNO-CG and
-Jacobi-CG), and the 256-problem work list solved in one call."""
+"""GPU parity at the full sizes of the benchmark's workloads, in the
+configurations it times: the 128^3 elastic operator and c = 3 UNO apply
+against the oracle on every node, the six Mandel solves checked by
+properties that hold at any size (true residual, symmetry of the stiffness,
+Voigt and Reuss bounds, agreement of UNO-CG and Jacobi-CG), the 256-problem
+work list solved in one call, and the 64^3 x 48 thermal batch with three
+of its solutions checked node by node against the oracle's equations."""
 import numpy as np
 import pytest
 import torch
@@ -123,3 +124,53 @@ def test_many_problems_work_list(orc, uno):
         for j in range(len(loads)):
             uo, _, _, _ = orc.pcg(k, orc.rhs(k, loads[j]), "jacobi", rtol=1e-10)
             assert rel(u[j].cpu().numpy(), uo) < 1e-7
+
+
+def test_headline_64_batch_of_48(orc, uno):
+    """The headline workload in the launch configuration the benchmark
+    times: 64^3, contrast 100, the 16 test microstructures x 3 unit loads
+    carried by one UNO-CG loop (M = 12, trained on Jacobi-CG pairs of 8
+    training microstructures), FP64 to 1e-6.  The oracle's own rhs and
+    operator (CPU, FP64) check three of the solutions node by node:
+    ||f - A u||_inf / ||f||_inf <= 1e-6 for the GPU's u.  Every effective
+    tensor is symmetric, lies between the Voigt and Reuss bounds, and
+    agrees with Jacobi-CG on the GPU to 1e-5."""
+    cfg = dict(si.CONFIG_3D_64)
+    shape = cfg["shape"]
+    print("64^3 x 48 batch", flush=True)
+    loads = np.eye(3)
+    hs = uno.half_shape(shape)
+    A = torch.zeros(hs, dtype=torch.float64, device=DEV)
+    B = torch.zeros_like(A)
+    train = cfg["train_seeds"][:8]
+    for seed in train:
+        kt = T(si.microstructure(cfg, seed)[0])
+        u2, _ = uno.pcg_solve_batch(kt, macro_loads=loads, kind="jacobi", rtol=1e-10, max_iter=20000)
+        F = torch.stack([uno.uno_macro_rhs(kt, loads[a]) for a in range(3)])
+        uno.uno_train_accumulate(F, u2, A, B, 3 * len(train))
+    M = 12
+    P = uno.UnoPrecond.create(shape, M, uno.uno_train_fit(shape, M, A, B))
+    kaps = [si.microstructure(cfg, s)[0] for s in cfg["test_seeds"]]
+    K = torch.stack([T(k) for k in kaps for _ in loads])
+    L48 = np.tile(loads, (len(kaps), 1))
+    u, infos = uno.pcg_solve_batch(K, macro_loads=L48, kind="uno", precond=P, rtol=1e-6, max_iter=50000,
+                                   kappa_per_rhs=True)
+    uj, ij = uno.pcg_solve_batch(K, macro_loads=L48, kind="jacobi", rtol=1e-10, max_iter=50000,
+                                 kappa_per_rhs=True)
+    for a, b in zip(infos, ij):
+        assert a["converged"] and b["converged"]
+        assert a["true_rel_res"] <= 1e-6 * (1 + 1e-6)
+        assert a["iters"] < b["iters"]
+    for j in (0, 22, 47):  # the oracle's rhs and operator on the GPU's solution
+        k = kaps[j // 3]
+        f = orc.rhs(k, L48[j])
+        res = f - orc.fe_apply(k, u[j].cpu().numpy())
+        assert np.abs(res).max() <= 1e-6 * (1 + 1e-6) * np.abs(f).max()
+    for m, k in enumerate(kaps):
+        ku = uno.effective_tensor(T(k), loads, u[3 * m: 3 * m + 3])
+        kj = uno.effective_tensor(T(k), loads, uj[3 * m: 3 * m + 3])
+        assert rel(ku, kj) < 1e-5
+        assert np.abs(ku - ku.T).max() < 1e-6 * np.abs(ku).max()
+        ev = np.linalg.eigvalsh(0.5 * (ku + ku.T))
+        voigt, reuss = k.mean(), 1.0 / (1.0 / k).mean()
+        assert ev.max() <= voigt * (1 + 1e-9) and ev.min() >= reuss * (1 - 1e-9)
