@@ -282,7 +282,8 @@ __device__ __forceinline__ double2 horner_eo(const double2* a, int stride, int m
     return make_double2(er + (orr * w.x - oi * w.y), ei + (orr * w.y + oi * w.x));
 }
 
-__global__ void __launch_bounds__(256) k_lr_mid(LowRankDev L, int nch, int cb, const double* __restrict__ C,
+template <int CB>  // columns per workgroup
+__global__ void __launch_bounds__(256) k_lr_mid(LowRankDev L, int nch, const double* __restrict__ C,
                                                 const double2* __restrict__ Gp, double2* __restrict__ H, CgIter it,
                                                 double* __restrict__ part_corr)
 {
@@ -295,9 +296,9 @@ __global__ void __launch_bounds__(256) k_lr_mid(LowRankDev L, int nch, int cb, c
         it = rhs_iter(it);
     }
     const int plane = L.kyn * L.kzn;
-    const int col0 = blockIdx.x * cb;
+    const int col0 = blockIdx.x * CB;
     double2* gx = (double2*)smem;  // [x][cl]
-    double2* X = gx + L.n0 * cb;   // [kx][cl]
+    double2* X = gx + L.n0 * CB;   // [kx][cl]
     // loads first: state and ||r||_inf partials (head of the CG pass) and
     // this thread's first gathered entries
     StateLoad sl;
@@ -306,9 +307,9 @@ __global__ void __launch_bounds__(256) k_lr_mid(LowRankDev L, int nch, int cb, c
         sl = load_state(it.st);
         share = load_share<OpMax>(it.part_rmax, it.np_rmax);
     }
-    const int ng = L.n0 * cb;
+    const int ng = L.n0 * CB;
     auto gather = [&](int q) {
-        const int cl = q % cb, x = q / cb;
+        const int cl = q % CB, x = q / CB;
         const int col = col0 + cl;
         double re = 0.0, im = 0.0;
         if (col < plane) {
@@ -337,11 +338,11 @@ __global__ void __launch_bounds__(256) k_lr_mid(LowRankDev L, int nch, int cb, c
     __syncthreads();
     // X[kx][cl] = C(k) sum_x g[x] exp(-2 pi i (kx - mx) x / n0)
     double corr = 0.0;
-    for (int o = threadIdx.x; o < L.kxn * cb; o += 256) {
-        const int cl = o % cb, kxi = o / cb;
+    for (int o = threadIdx.x; o < L.kxn * CB; o += 256) {
+        const int cl = o % CB, kxi = o / CB;
         const int col = col0 + cl;
         const double2 w = L.twx[mod_n(kxi - L.mx, L.n0)];
-        const double2 v = horner_eo(gx + cl, cb, L.n0, w);
+        const double2 v = horner_eo(gx + cl, CB, L.n0, w);
         const double c = (col < plane) ? C[(int64_t)kxi * plane + col] : 0.0;
         X[o] = make_double2(v.x * c, v.y * c);
         corr += c * (v.x * v.x + v.y * v.y);
@@ -353,12 +354,12 @@ __global__ void __launch_bounds__(256) k_lr_mid(LowRankDev L, int nch, int cb, c
     __syncthreads();
     // H[x][col] = sum_kx X[kx] exp(+2 pi i (kx - mx) x / n0)
     for (int o = threadIdx.x; o < ng; o += 256) {
-        const int cl = o % cb, x = o / cb;
+        const int cl = o % CB, x = o / CB;
         const int col = col0 + cl;
         if (col >= plane) continue;
         const double2 t = L.twx[x];                       // exp(-2 pi i x / n0)
         const double2 w = make_double2(t.x, -t.y);        // exp(+2 pi i x / n0)
-        const double2 v = horner_eo(X + cl, cb, L.kxn, w);
+        const double2 v = horner_eo(X + cl, CB, L.kxn, w);
         const double2 sh = L.twx[mod_n(L.mx * x, L.n0)];  // exp(-2 pi i mx x / n0)
         H[(int64_t)x * plane + col] = cmul(v, sh);
     }
@@ -1292,6 +1293,28 @@ static void launch_lr_tile_tx(const LowRankPlan* p, const GridDev& g, const doub
         launch_lr_tile<TX, false>(p, g, kappa, r, dold, dnew, pv, part_dp, it, a, gam, bt, st);
 }
 
+// pass B with the plan's columns per workgroup (8, 4, 2 or 1) as a constant
+static void launch_mid(const LowRankPlan* p, const LrBatch& bt, const CgIter& it, double* part_corr, hipStream_t st)
+{
+    const dim3 grid(p->blocks_mid, bt.nrhs), blk(256);
+    const double* C = (const double*)p->table;
+    const double2* Gp = bt.Gp;
+    switch (p->cb_mid) {
+        case 8:
+            uno_launch(UNO_KT_FFT_MID, k_lr_mid<8>, grid, blk, p->lds_b, st, p->dev, bt.nch, C, Gp, bt.H, it, part_corr);
+            break;
+        case 4:
+            uno_launch(UNO_KT_FFT_MID, k_lr_mid<4>, grid, blk, p->lds_b, st, p->dev, bt.nch, C, Gp, bt.H, it, part_corr);
+            break;
+        case 2:
+            uno_launch(UNO_KT_FFT_MID, k_lr_mid<2>, grid, blk, p->lds_b, st, p->dev, bt.nch, C, Gp, bt.H, it, part_corr);
+            break;
+        default:
+            uno_launch(UNO_KT_FFT_MID, k_lr_mid<1>, grid, blk, p->lds_b, st, p->dev, bt.nch, C, Gp, bt.H, it, part_corr);
+            break;
+    }
+}
+
 // Fused FP64 CG pass, first half: pass B (convergence test, H, Parseval
 // partials into part_corr), then the tile kernel (s on the fly, gamma,
 // d = s + beta d_old, p = A d, d.p partials).  Returns the d.p partial count.
@@ -1302,8 +1325,7 @@ uno_status lowrank_fused_pass(const LowRankPlan* p, const Grid& g, const double*
 {
     if (!p->fused) return UNO_ERR_SHAPE;
     const LowRankDev& L = p->dev;
-    uno_launch(UNO_KT_FFT_MID, k_lr_mid, dim3(p->blocks_mid, bt.nrhs), dim3(256), p->lds_b, st, L, bt.nch,
-               p->cb_mid, (const double*)p->table, (const double2*)bt.Gp, bt.H, it, part_corr);
+    launch_mid(p, bt, it, part_corr, st);
     UNO_HIP(hipGetLastError());
     const LrTileArgs a{part_rr, p->dev.n0 * bt.nch, part_corr, p->blocks_mid};
     if (p->tile.tx == 1)
@@ -1328,8 +1350,7 @@ uno_status lowrank_finish(const LowRankPlan* p, const double* r, T* s, const CgI
         uno_launch(UNO_KT_FFT_MID, k_lr_mid3, dim3(p->blocks_mid, bt.nrhs), dim3(256), p->lds_b, st, L, bt.nch,
                    p->cb_mid, (const double*)p->table, (const double2*)bt.Gp, bt.H, it);
     else
-        uno_launch(UNO_KT_FFT_MID, k_lr_mid, dim3(p->blocks_mid, bt.nrhs), dim3(256), p->lds_b, st, L, bt.nch,
-                   p->cb_mid, (const double*)p->table, (const double2*)bt.Gp, bt.H, it, (double*)nullptr);
+        launch_mid(p, bt, it, nullptr, st);
     UNO_HIP(hipGetLastError());
     const int nbc = L.n0 * ((L.n1 + bt.yc - 1) / bt.yc);
     const dim3 grid(nbc, bt.nrhs);
