@@ -148,7 +148,10 @@ typedef struct {
     uno_dtype op_t;          /* operator apply: UNO_F64, or UNO_F32 (with prec_t = UNO_F32) */
     uno_dtype prec_t;        /* preconditioner apply: UNO_F64, or UNO_F32 (with op_t = UNO_F32);
                                 FP32 mode keeps r, u, all reductions and the stop test in FP64
-                                and needs, for UNO, the learned-mode passes (uno_precond_set_path) */
+                                and needs, for UNO, the learned-mode passes (uno_precond_set_path);
+                                it replaces r by f - A u (FP64) whenever ||r||_inf has dropped by
+                                1e2 since the last replacement, and reopens a load whose FP64 true
+                                residual is above its tolerance when every load has ended */
     int32_t graph_chunk;     /* iterations per host check; 0 = adaptive */
 } uno_solve_opts;
 
@@ -185,8 +188,10 @@ uno_status pcg_solve(const uno_grid *grid, const uno_material *mat, const double
  * zero-mean solutions; info (host, nullable) receives nrhs records.
  * Every pass kernel carries all right-hand sides (grid y), each with its own
  * scalars and stopping test: a load that has converged stops updating, and
- * every result equals that of pcg_solve on the same load.  Preconditioners
- * without the learned-mode passes and the FP32 mode are run load by load.
+ * every result equals that of pcg_solve on the same load (in the FP32 mode
+ * the residual replacements of all loads happen together, so results agree
+ * with pcg_solve to the tolerance, not bitwise).  Preconditioners without
+ * the learned-mode passes are run load by load.
  * 1 <= nrhs <= 64.  Returns UNO_ERR_BREAKDOWN if any load broke down (see
  * info).  Synchronous. */
 uno_status pcg_solve_batch(const uno_grid *grid, const uno_material *mat, int32_t kappa_per_rhs, int32_t nrhs,
