@@ -192,7 +192,7 @@ uno_status pcg_solve(const uno_grid *grid, const uno_material *mat, const double
  * the residual replacements of all loads happen together, so results agree
  * with pcg_solve to the tolerance, not bitwise).  Preconditioners without
  * the learned-mode passes are run load by load.
- * 1 <= nrhs <= 64.  Returns UNO_ERR_BREAKDOWN if any load broke down (see
+ * 1 <= nrhs <= 256.  Returns UNO_ERR_BREAKDOWN if any load broke down (see
  * info).  Synchronous. */
 uno_status pcg_solve_batch(const uno_grid *grid, const uno_material *mat, int32_t kappa_per_rhs, int32_t nrhs,
                            const double *macro_loads, const double *rhs, double *u,
@@ -238,7 +238,7 @@ typedef struct {
  * FP64, or the FP32 mode of pcg_solve with FP64 residuals, reductions and
  * stop test; opts->uno is ignored in favour of each problem's).  Problems with the same grid and
  * preconditioner form a class; the load cases of a class are carried
- * together by every pass kernel (up to 64 per launch, each with its own
+ * together by every pass kernel (up to 256 per launch, each with its own
  * conductivity field and stopping test); the classes follow one another on
  * `stream` (a preconditioner without the learned-mode passes solves its
  * class's load cases one at a time).  The library gathers each class's

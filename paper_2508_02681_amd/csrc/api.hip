@@ -617,7 +617,7 @@ uno_status pcg_solve_batch(const uno_grid* grid, const uno_material* mat, int32_
     Grid g;
     uno_status e = check_solve(grid, mat, opts, &g);
     if (e != UNO_OK) return e;
-    if (nrhs < 1 || nrhs > 64 || !u || (!macro_loads && !rhs)) return UNO_ERR_ARG;
+    if (nrhs < 1 || nrhs > 256 || !u || (!macro_loads && !rhs)) return UNO_ERR_ARG;
     if (kappa_per_rhs != 0 && kappa_per_rhs != 1) return UNO_ERR_ARG;
     std::vector<double> g3;
     if (macro_loads) {

@@ -16,6 +16,7 @@
 // The search direction is double-buffered (d_old read around the node,
 // d_new written), which fuses the direction update into the operator apply.
 #include <climits>
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -281,8 +282,9 @@ __global__ void __launch_bounds__(kBlock) k_resid_final(const double* __restrict
 
 // Right-hand sides of a batch: f_b = rhs of the macroscopic gradient b for
 // the conductivity field kappa + b ks (blockIdx.y = b), as k_rhs_node.
+constexpr int kLoads3 = 64;
 struct Loads3 {
-    double g[64][3];
+    double g[kLoads3][3];
 };
 
 __global__ void __launch_bounds__(kBlock) k_rhs_batch(GridDev g, const double* __restrict__ kappa, int64_t ks,
@@ -899,11 +901,15 @@ uno_status pcg_run_batch(const Grid& g, const double* kappa, int64_t ks, int nrh
     bi.vs = n;
     bi.ks = ks;
     if (macro_loads3) {
-        Loads3 L;
-        memset(&L, 0, sizeof(L));
-        for (int b = 0; b < nrhs; ++b)
-            for (int a = 0; a < 3; ++a) L.g[b][a] = macro_loads3[3 * b + a];
-        hipLaunchKernelGGL(k_rhs_batch, dim3(nb, nrhs), dim3(kBlock), 0, st, g.dev, kappa, ks, L, w->f);
+        for (int b0 = 0; b0 < nrhs; b0 += kLoads3) {  // the loads travel as a kernel argument, kLoads3 a launch
+            const int m = std::min(kLoads3, nrhs - b0);
+            Loads3 L;
+            memset(&L, 0, sizeof(L));
+            for (int b = 0; b < m; ++b)
+                for (int a = 0; a < 3; ++a) L.g[b][a] = macro_loads3[3 * (b0 + b) + a];
+            hipLaunchKernelGGL(k_rhs_batch, dim3(nb, m), dim3(kBlock), 0, st, g.dev, kappa + b0 * ks, ks, L,
+                               w->f + (int64_t)b0 * n);
+        }
     } else {
         UNO_HIP(hipMemcpyAsync(w->f, rhs, sizeof(double) * n * nrhs, hipMemcpyDeviceToDevice, st));
     }

@@ -4,7 +4,7 @@
 // Problems are grouped into classes of equal grid (and preconditioner).
 // The load cases of a class become the right-hand sides of the batched CG
 // (every pass kernel takes them along grid y, each with its own
-// conductivity field, scalars and stopping test), in launches of up to 64;
+// conductivity field, scalars and stopping test), in launches of up to 256;
 // the classes follow one another on the caller's stream, largest first.
 // (Classes on concurrent streams were tried: the learned-mode flow then
 // lost the agreement between its recursive and true residuals on some load
@@ -26,7 +26,7 @@ uno_status pcg_run_batch(const Grid& g, const double* kappa, int64_t ks, int nrh
 
 namespace {
 
-constexpr int kMaxRhs = 64;      // right-hand sides per launch
+constexpr int kMaxRhs = 256;     // right-hand sides per launch
 struct Rhs {
     int prob, load;
 };

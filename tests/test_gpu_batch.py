@@ -147,7 +147,7 @@ def test_batch_argument_errors(uno):
     with pytest.raises(uno.UnoError):
         uno.pcg_solve_batch(kap, macro_loads=np.zeros((0, 3)), kind="jacobi")
     with pytest.raises(uno.UnoError):
-        uno.pcg_solve_batch(kap, macro_loads=np.ones((65, 3)), kind="jacobi")
+        uno.pcg_solve_batch(kap, macro_loads=np.ones((257, 3)), kind="jacobi")
 
 
 @pytest.mark.parametrize("kind,M,path", [("uno", 3, 0), ("uno", 3, 3), ("jacobi", 0, 0)])
@@ -163,4 +163,23 @@ def test_batch_of_microstructures_equals_single_solves(uno, kind, M, path):
     for j in range(len(loads)):
         us, info = uno.pcg_solve(kap_all[j], macro_load=loads[j], kind=kind, precond=p, rtol=1e-8)
         assert infos[j]["iters"] == info["iters"]
+        assert torch.equal(ub[j], us), "right-hand side %d differs from its single solve" % j
+
+
+@pytest.mark.parametrize("kind", ["uno", "jacobi"])
+def test_batch_of_150_loads_equals_single_solves(uno, kind):
+    """More right-hand sides than one launch of the right-hand-side kernel
+    takes (its loads travel as a kernel argument, 64 a launch): 150 loads
+    over 5 microstructures in one batch, every result equal to its single
+    solve."""
+    shape = (16, 12, 10)
+    kaps = [T(_kappa(shape, 90 + i)) for i in range(5)]
+    rng = np.random.default_rng(3)
+    loads = rng.standard_normal((150, 3))
+    kap_all = torch.stack([kaps[j % 5] for j in range(len(loads))])
+    p = _precond(uno, shape, 2) if kind == "uno" else None
+    ub, infos = uno.pcg_solve_batch(kap_all, macro_loads=loads, kind=kind, precond=p, rtol=1e-8, kappa_per_rhs=True)
+    for j in (0, 63, 64, 65, 127, 128, 149):
+        us, info = uno.pcg_solve(kap_all[j], macro_load=loads[j], kind=kind, precond=p, rtol=1e-8)
+        assert infos[j]["converged"] and infos[j]["iters"] == info["iters"]
         assert torch.equal(ub[j], us), "right-hand side %d differs from its single solve" % j
