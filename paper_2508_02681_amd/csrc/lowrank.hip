@@ -237,8 +237,8 @@ __global__ void __launch_bounds__(256) k_lr_fwd(LowRankDev L, int ya, int rb, do
     }
 }
 
-// Pass B: one workgroup of 256 threads per group of cb consecutive (k_y,
-// k_z) columns: add the row-chunk partials (reads of cb adjacent columns are
+// Pass B: one workgroup of 256 threads per group of CB consecutive (k_y,
+// k_z) columns: add the row-chunk partials (reads of CB adjacent columns are
 // contiguous), transform along x, multiply by the table, transform back.
 // Inside CG it is the first kernel of a pass and runs the convergence test.
 // Both x-transforms are evaluated with Horner's rule in the unit-modulus
