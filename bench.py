@@ -231,6 +231,72 @@ def elastic_record(uno, si, torch, dev, M):
     return out
 
 
+def paper192_record(uno, si, torch, dev):
+    """The paper's 3D thermal size and contrast (192^3, R = 5, synthetic
+    spheres standing in for its dataset): UNO-CG (trained untimed on the
+    Jacobi-CG solutions of four other microstructures, M picked on a fifth)
+    and Jacobi-CG to 1e-6, FP64, one load alone and the three loads
+    together.  Context next to the paper's published timings on other
+    hardware, not the headline."""
+    cfg = dict(si.CONFIG_3D_192_R5)
+    shape = cfg["shape"]
+    n = int(np.prod(shape))
+    loads = np.eye(3)
+    t0 = time.time()
+    hs = uno.half_shape(shape)
+    A = torch.zeros(hs, dtype=torch.float64, device=dev)
+    B = torch.zeros_like(A)
+    for seed in cfg["train_seeds"]:
+        kt = torch.tensor(si.microstructure(cfg, seed)[0], device=dev)
+        u2, _ = uno.pcg_solve_batch(kt, macro_loads=loads, kind="jacobi", rtol=1e-8, max_iter=50000)
+        F = torch.stack([uno.uno_macro_rhs(kt, loads[a]) for a in range(3)])
+        uno.uno_train_accumulate(F, u2, A, B, 3 * len(cfg["train_seeds"]))
+        del u2, F
+    kv = torch.tensor(si.microstructure(cfg, cfg["val_seed"])[0], device=dev)
+    best = None
+    for M in (8, 12, 16):
+        P = uno.UnoPrecond.create(shape, M, uno.uno_train_fit(shape, M, A, B))
+        uno.pcg_solve_batch(kv, macro_loads=loads, kind="uno", precond=P, rtol=RTOL)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        uno.pcg_solve_batch(kv, macro_loads=loads, kind="uno", precond=P, rtol=RTOL)
+        torch.cuda.synchronize()
+        tv = time.perf_counter() - t
+        if best is None or tv < best[0]:
+            best = (tv, M, P)
+    _, M, P = best
+    del A, B, kv
+    log("192^3 R = 5: trained on %d pairs, M = %d picked, in %.1fs" % (3 * len(cfg["train_seeds"]), M, time.time() - t0))
+    kt = torch.tensor(si.microstructure(cfg, cfg["test_seed"])[0], device=dev)
+
+    def timed(kind, precond, all_loads):
+        kw = dict(kind=kind, precond=precond, rtol=RTOL, max_iter=50000)
+        if all_loads:
+            f = lambda: uno.pcg_solve_batch(kt, macro_loads=loads, **kw)[1]
+        else:
+            f = lambda: [uno.pcg_solve(kt, macro_load=loads[0], **kw)[1]]
+        f()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        infos = f()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) * 1e3, infos
+
+    out = {"workload": "3D thermal 192^3 (%d DOF), spheres r 12-24 vf 0.25, kappa 1 / 0.2 (R = 5), FP64 to 1e-6; "
+                       "the paper's size and contrast with synthetic microstructures" % n, "M": M}
+    for kind, pc in (("uno_cg", P), ("jac_cg", None)):
+        t1, i1 = timed("uno" if pc else "jacobi", pc, False)
+        t3, i3 = timed("uno" if pc else "jacobi", pc, True)
+        out[kind] = {"ms_one_load": t1, "passes_one_load": i1[0]["iters"], "ms_per_solve_3_loads_together": t3 / 3,
+                     "passes_3_loads": [i["iters"] for i in i3],
+                     "true_rel_res_max": max(i["true_rel_res"] for i in i1 + i3)}
+    out["time_to_tol_ratio_one_load"] = out["jac_cg"]["ms_one_load"] / out["uno_cg"]["ms_one_load"]
+    log("192^3 R = 5: UNO-CG %.1f ms (%d passes) one load, Jac-CG %.1f ms (%d passes), ratio %.1f" %
+        (out["uno_cg"]["ms_one_load"], out["uno_cg"]["passes_one_load"], out["jac_cg"]["ms_one_load"],
+         out["jac_cg"]["passes_one_load"], out["time_to_tol_ratio_one_load"]))
+    return out
+
+
 def many_record(uno, si, torch, dev):
     """Many-query workload: 256 problems of uneven sizes (2D 64^2/128^2/256^2,
     3D 32^3/48^3), contrast log-uniform in [10, 1000], 2 or 3 loads each,
@@ -329,7 +395,8 @@ def parse():
     ap.add_argument("--no-192", action="store_true", help="skip the per-kernel roofline at 192^3")
     ap.add_argument("--no-elastic", action="store_true", help="skip the 128^3 elasticity record")
     ap.add_argument("--no-many", action="store_true", help="skip the many-problem record")
-    ap.add_argument("--only", choices=["elastic", "many"], default=None,
+    ap.add_argument("--no-paper192", action="store_true", help="skip the 192^3 R = 5 record (the paper's size)")
+    ap.add_argument("--only", choices=["elastic", "many", "paper192"], default=None,
                     help="run only that record and print it (profiling runs of its kernels)")
     ap.add_argument("--el-M", type=int, default=8, help="mode parameter of the elastic UNO preconditioner")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -379,8 +446,10 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     if args.only:
-        rec = elastic_record(uno, si, torch, dev, args.el_M) if args.only == "elastic" else \
-            many_record(uno, si, torch, dev)
+        recs = {"elastic": lambda: elastic_record(uno, si, torch, dev, args.el_M),
+                "many": lambda: many_record(uno, si, torch, dev),
+                "paper192": lambda: paper192_record(uno, si, torch, dev)}
+        rec = recs[args.only]()
         print(json.dumps({args.only: rec}), flush=True)
         return
     cfg = dict(si.CONFIG_3D_64)
@@ -589,6 +658,11 @@ def main():
     if not args.no_many:
         many = many_record(uno, si, torch, dev)
 
+    # ---------------- the paper's size and contrast: 192^3, R = 5 ----------------
+    paper192 = None
+    if not args.no_paper192:
+        paper192 = paper192_record(uno, si, torch, dev)
+
     # ---------------- per-kernel roofline at the paper's grid size (192^3) ----------------
     big = None
     if not args.no_192:
@@ -668,6 +742,7 @@ def main():
         "differentiation": grad_rec,
         "elasticity_128": el,
         "many_problems": many,
+        "paper_size_192_r5": paper192,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

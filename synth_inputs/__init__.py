@@ -119,6 +119,13 @@ CONFIG_EL_128 = dict(shape=(128, 128, 128), r_min=8.0, r_max=16.0, vf=0.25, k_ma
                      train_seeds=[5001, 5002], test_seeds=[5000], loads=6)
 
 
+# the paper's 3D thermal size and contrast (192^3, kappa 1 in the matrix and
+# 0.2 in the inclusions, R = 5) with this generator's spheres: context next
+# to the paper's published timings, not a parity case
+CONFIG_3D_192_R5 = dict(shape=(192, 192, 192), r_min=12.0, r_max=24.0, vf=0.25, k_matrix=1.0, k_incl=0.2,
+                        train_seeds=[8001, 8002, 8003, 8004], val_seed=8010, test_seed=8000, loads=3)
+
+
 # many-query work list: grid sizes mixed over 2D and 3D, inclusion radii
 # N/16..N/8 voxels, contrast log-uniform in [10, 1000], 2 loads in 2D and 3
 # in 3D
