@@ -723,7 +723,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "3D thermal 64^3 periodic hex8, spheres r 4-8 vf 0.25, kappa 1/100, "
                                "16 microstructures x 3 loads per step, solved together, UNO-CG to 1e-6 + effective tensors",
-                   "grid": list(SHAPE), "loads_per_microstructure": 3, "solves_per_step": nr_all, "M": M, "train_pairs": len(F),
+                   "grid": list(SHAPE), "loads_per_microstructure": 3, "solves_per_step": nr_all, "M": M,
+                   "train_pairs": len(F),
                    "microstructures": len(kap_test)},
         "uno_cg": {"passes_mean": float(np.mean(its)), "ms_per_solve": uno_t_solve, "dof_iters_per_s": value,
                    "solves_per_launch": nr_all, "ms_per_solve_3_loads_per_launch": micro_t_solve,
