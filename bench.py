@@ -8,9 +8,10 @@ gradient load cases per microstructure, relative residual 1e-6 in the
 infinity norm.  Synthetic seeded microstructures stand in for the paper's
 voxel datasets.
 
-One step = the whole hot path over one microstructure: for each of the 3
-loads, rhs + UNO-CG solve (operator apply, UNO preconditioner apply, CG
-recurrences) to 1e-6, then the effective 3x3 conductivity.  Inputs are
+One step = the whole hot path over the 16 test microstructures: the rhs
+and the UNO-CG solve (operator apply, UNO preconditioner apply, CG
+recurrences) to 1e-6 of their 48 load cases, carried together by every
+pass kernel, then the 16 effective 3x3 conductivities.  Inputs are
 resident in device memory before the timed region.  The UNO weights are
 trained beforehand (untimed) on solver-generated pairs: seeded random
 weights -> UNO-CG solves of training microstructures -> closed-form fit
