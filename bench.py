@@ -528,6 +528,7 @@ def main():
     loads_all = np.tile(LOADS, (nm, 1))
     sols = torch.zeros((nm * len(LOADS),) + SHAPE, dtype=torch.float64, device=dev)
     nr_all = nm * len(LOADS)
+    kap16 = torch.stack(kap_test)  # one field per microstructure, for the effective tensors
     worst_true = {}  # largest true relative residual ||f - A u|| / ||f|| (FP64) at exit, per solver
 
     def step(kind, precond, mode="all", tag="uno_cg", **kw):
@@ -552,7 +553,7 @@ def main():
             if not info["converged"]:
                 raise RuntimeError("solve did not converge: %s" % info)
         worst_true[tag] = max(worst_true.get(tag, 0.0), max(info["true_rel_res"] for info in infos))
-        kbs = [uno.effective_tensor(k, LOADS, sols[3 * i: 3 * i + 3]) for i, k in enumerate(kap_test)]
+        kbs = list(uno.effective_tensor_batch(kap16, LOADS, sols))
         return [info["iters"] for info in infos], kbs
 
     def timed(kind, precond, steps, warmup, mode="all", tag="uno_cg", **kw):

@@ -207,6 +207,16 @@ uno_status pcg_solve_batch(const uno_grid *grid, const uno_material *mat, int32_
 uno_status effective_tensor(const uno_grid *grid, const uno_material *mat, int32_t nload,
                             const double *loads, const double *u, double *out, void *stream);
 
+/* effective_tensor for nmat microstructures of one grid in one call (the
+ * batched solves of Sec. 4.5): mat->kappa holds nmat fields (field m at
+ * + m n, one dtype), loads (host, nload x d, nload = d) apply to every
+ * field, u (device) holds solution j of field m at + (m nload + j) n, and
+ * out (host, nmat x d x d) receives tensor m at + m d d.  The flux partials
+ * of all fields and loads are read back in one copy; each result equals
+ * effective_tensor on its field.  nmat >= 1.  Synchronous. */
+uno_status effective_tensor_batch(const uno_grid *grid, const uno_material *mat, int32_t nmat, int32_t nload,
+                                  const double *loads, const double *u, double *out, void *stream);
+
 /* Gradient of the effective conductivity with respect to every voxel
  * conductivity.  The cell problem is self-adjoint (Sec. 3.1 weak form), so
  * at the discrete solutions the derivative of g_a . kappa_bar g_b with

@@ -86,6 +86,7 @@ def lib():
         "pcg_solve": ([G, Mt, P(f64), vp, vp, P(uno_solve_opts), P(uno_solve_info), P(f64), vp], i),
         "pcg_solve_batch": ([G, Mt, i32, i32, P(f64), vp, vp, P(uno_solve_opts), P(uno_solve_info), vp], i),
         "effective_tensor": ([G, Mt, i32, P(f64), vp, P(f64), vp], i),
+        "effective_tensor_batch": ([G, Mt, i32, i32, P(f64), vp, P(f64), vp], i),
         "effective_tensor_grad": ([G, i32, P(f64), vp, P(f64), vp, vp], i),
         "el_apply": ([G, vp, vp, vp, vp, vp], i),
         "el_macro_rhs": ([G, vp, vp, P(f64), vp, vp], i),
@@ -360,6 +361,26 @@ def effective_tensor(kappa: torch.Tensor, loads, solutions: torch.Tensor, L0=1.0
                                   ld.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                   _dev(solutions, "solutions", torch.float64),
                                   out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _stream()), "effective_tensor")
+    return out
+
+
+def effective_tensor_batch(kappas: torch.Tensor, loads, solutions: torch.Tensor, L0=1.0) -> np.ndarray:
+    """kappa_bar (nmat x d x d) of nmat microstructures (kappas: nmat x grid)
+    from their solutions (nmat * d x grid, the d load cases of field m at
+    m d .. m d + d - 1), one read-back for all."""
+    nm = kappas.shape[0]
+    shape = tuple(kappas.shape[1:])
+    g = make_grid(shape, L0)
+    ld = np.ascontiguousarray(loads, dtype=np.float64)
+    d = len(shape)
+    if tuple(solutions.shape) != (nm * ld.shape[0],) + shape:
+        raise UnoError(-1, "effective_tensor_batch (solutions must be (nmat * nload,) + grid)")
+    out = np.zeros((nm, d, d))
+    _check(lib().effective_tensor_batch(ctypes.byref(g), ctypes.byref(_mat(kappas)), nm, ld.shape[0],
+                                        ld.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                        _dev(solutions, "solutions", torch.float64),
+                                        out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _stream()),
+           "effective_tensor_batch")
     return out
 
 

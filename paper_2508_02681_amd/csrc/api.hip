@@ -740,57 +740,10 @@ uno_status el_effective_stiffness(const uno_grid* grid, const double* lambda, co
     return UNO_OK;
 }
 
-uno_status effective_tensor(const uno_grid* grid, const uno_material* mat, int32_t nload, const double* loads,
-                            const double* u, double* out, void* stream)
+// out (d x d, row-major) = Q G^-1 with G[:, j] = g_j (Gauss-Jordan on the
+// tiny d x d system); Q[i][j]: component i of the mean flux of load j
+static uno_status solve_qg(int d, const double Q[3][3], const double* loads, double* out)
 {
-    Grid g;
-    uno_status e = make_grid(grid, &g);
-    if (e != UNO_OK) return e;
-    const int d = grid->dim;
-    if (!mat || !mat->kappa || !loads || !u || !out || nload != d) return UNO_ERR_ARG;
-    if (mat->dtype != UNO_F64 && mat->dtype != UNO_F32) return UNO_ERR_ARG;
-    const int nb = (int)((g.total + kBlock - 1) / kBlock);
-    // flux partials of the d loads in a device buffer kept per device
-    // (grown on demand), read back in one copy
-    std::lock_guard<std::mutex> lk(g_flux_mu);
-    int dev = 0;
-    UNO_HIP(hipGetDevice(&dev));
-    FluxBuf* fb = nullptr;
-    for (FluxBuf& c : g_flux)
-        if (c.device == dev) fb = &c;
-    if (!fb) {
-        g_flux.push_back(FluxBuf{dev, nullptr, 0});
-        fb = &g_flux.back();
-    }
-    const size_t need = 3 * (size_t)nb * d;
-    if (fb->cap < need) {
-        (void)hipFree(fb->p);
-        fb->p = nullptr;
-        fb->cap = 0;
-        if (hipMalloc(&fb->p, sizeof(double) * need) != hipSuccess) return UNO_ERR_NOMEM;
-        fb->cap = need;
-    }
-    double* dpart = fb->p;
-    std::vector<double> hpart(need);
-    double Q[3][3] = {{0}};  // Q[i][j]: component i of load j
-    for (int j = 0; j < d && e == UNO_OK; ++j) {
-        double g3[3] = {0.0, 0.0, 0.0};
-        for (int b = 0; b < d; ++b) g3[3 - d + b] = loads[j * d + b];
-        int nbo = 0;
-        e = launch_flux(g, mat->kappa, mat->dtype, g3, u + (int64_t)j * g.total, dpart + 3 * (size_t)nb * j, &nbo,
-                        S(stream));
-    }
-    if (e != UNO_OK) return e;
-    if (hipMemcpyAsync(hpart.data(), dpart, sizeof(double) * need, hipMemcpyDeviceToHost, S(stream)) != hipSuccess ||
-        hipStreamSynchronize(S(stream)) != hipSuccess)
-        return UNO_ERR_DEVICE;
-    for (int j = 0; j < d; ++j)
-        for (int c = 0; c < d; ++c) {
-            double acc = 0.0;
-            for (int b = 0; b < nb; ++b) acc += hpart[3 * (size_t)nb * j + 3 * (size_t)b + (3 - d + c)];
-            Q[c][j] = acc / (double)g.total;
-        }
-    // out = Q G^-1 with G[:, j] = g_j  (Gauss-Jordan on the tiny d x d system)
     double G[3][6];
     for (int i = 0; i < d; ++i)
         for (int j = 0; j < d; ++j) {
@@ -819,6 +772,75 @@ uno_status effective_tensor(const uno_grid* grid, const uno_material* mat, int32
             out[i * d + j] = acc;
         }
     return UNO_OK;
+}
+
+uno_status effective_tensor_batch(const uno_grid* grid, const uno_material* mat, int32_t nmat, int32_t nload,
+                                  const double* loads, const double* u, double* out, void* stream)
+{
+    Grid g;
+    uno_status e = make_grid(grid, &g);
+    if (e != UNO_OK) return e;
+    const int d = grid->dim;
+    if (!mat || !mat->kappa || !loads || !u || !out || nload != d || nmat < 1) return UNO_ERR_ARG;
+    if (mat->dtype != UNO_F64 && mat->dtype != UNO_F32) return UNO_ERR_ARG;
+    const size_t kbytes = mat->dtype == UNO_F64 ? sizeof(double) : sizeof(float);
+    const int nb = (int)((g.total + kBlock - 1) / kBlock);
+    // flux partials of every field and load in a device buffer kept per
+    // device (grown on demand), read back in one copy
+    std::lock_guard<std::mutex> lk(g_flux_mu);
+    int dev = 0;
+    UNO_HIP(hipGetDevice(&dev));
+    FluxBuf* fb = nullptr;
+    for (FluxBuf& c : g_flux)
+        if (c.device == dev) fb = &c;
+    if (!fb) {
+        g_flux.push_back(FluxBuf{dev, nullptr, 0});
+        fb = &g_flux.back();
+    }
+    const size_t per = 3 * (size_t)nb;  // partials of one load
+    const size_t need = per * d * (size_t)nmat;
+    if (fb->cap < need) {
+        (void)hipFree(fb->p);
+        fb->p = nullptr;
+        fb->cap = 0;
+        if (hipMalloc(&fb->p, sizeof(double) * need) != hipSuccess) return UNO_ERR_NOMEM;
+        fb->cap = need;
+    }
+    double* dpart = fb->p;
+    std::vector<double> hpart(need);
+    for (int m = 0; m < nmat && e == UNO_OK; ++m) {
+        const void* km = (const char*)mat->kappa + (size_t)m * g.total * kbytes;
+        for (int j = 0; j < d && e == UNO_OK; ++j) {
+            double g3[3] = {0.0, 0.0, 0.0};
+            for (int b = 0; b < d; ++b) g3[3 - d + b] = loads[j * d + b];
+            int nbo = 0;
+            const size_t lj = (size_t)m * d + j;
+            e = launch_flux(g, km, mat->dtype, g3, u + (int64_t)lj * g.total, dpart + per * lj, &nbo, S(stream));
+        }
+    }
+    if (e != UNO_OK) return e;
+    if (hipMemcpyAsync(hpart.data(), dpart, sizeof(double) * need, hipMemcpyDeviceToHost, S(stream)) != hipSuccess ||
+        hipStreamSynchronize(S(stream)) != hipSuccess)
+        return UNO_ERR_DEVICE;
+    for (int m = 0; m < nmat; ++m) {
+        double Q[3][3] = {{0}};
+        for (int j = 0; j < d; ++j)
+            for (int c = 0; c < d; ++c) {
+                const double* hp = hpart.data() + per * ((size_t)m * d + j);
+                double acc = 0.0;
+                for (int b = 0; b < nb; ++b) acc += hp[3 * (size_t)b + (3 - d + c)];
+                Q[c][j] = acc / (double)g.total;
+            }
+        e = solve_qg(d, Q, loads, out + (size_t)m * d * d);
+        if (e != UNO_OK) return e;
+    }
+    return UNO_OK;
+}
+
+uno_status effective_tensor(const uno_grid* grid, const uno_material* mat, int32_t nload, const double* loads,
+                            const double* u, double* out, void* stream)
+{
+    return effective_tensor_batch(grid, mat, 1, nload, loads, u, out, stream);
 }
 
 uno_status uno_timing_enable(int32_t which)

@@ -183,3 +183,24 @@ def test_batch_of_150_loads_equals_single_solves(uno, kind):
         us, info = uno.pcg_solve(kap_all[j], macro_load=loads[j], kind=kind, precond=p, rtol=1e-8)
         assert infos[j]["converged"] and infos[j]["iters"] == info["iters"]
         assert torch.equal(ub[j], us), "right-hand side %d differs from its single solve" % j
+
+
+def test_effective_tensor_batch_equals_single_calls(orc, uno):
+    """effective_tensor_batch over 5 microstructures equals effective_tensor
+    on each (same kernels, same summation order), and the oracle's tensor
+    to 1e-10 on one of them."""
+    shape = (12, 10, 14)
+    kaps = [_kappa(shape, 120 + i) for i in range(5)]
+    K = torch.stack([T(k) for k in kaps])
+    loads = np.eye(3)
+    u, _ = uno.pcg_solve_batch(torch.stack([K[m] for m in range(5) for _ in loads]),
+                               macro_loads=np.tile(loads, (5, 1)), kind="jacobi", rtol=1e-12, kappa_per_rhs=True)
+    kb = uno.effective_tensor_batch(K, loads, u)
+    assert kb.shape == (5, 3, 3)
+    for m in range(5):
+        assert np.array_equal(kb[m], uno.effective_tensor(K[m], loads, u[3 * m: 3 * m + 3]))
+    sols = [orc.pcg(kaps[2], orc.rhs(kaps[2], g), "jacobi", rtol=1e-12)[0] for g in loads]
+    ko = orc.effective_tensor(kaps[2], sols, loads)
+    assert np.abs(kb[2] - ko).max() < 1e-10 * np.abs(ko).max()
+    with pytest.raises(uno.UnoError):
+        uno.effective_tensor_batch(K, loads, u[:14])
