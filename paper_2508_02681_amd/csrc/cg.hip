@@ -383,7 +383,7 @@ __global__ void __launch_bounds__(kBlock) k_resid_final_b(const double* __restri
 }
 
 // ---------------------------------------------------------------------------
-// driver
+// host side: workspace, the CG loop, batch setup and finish
 
 namespace {
 
