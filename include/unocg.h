@@ -61,6 +61,7 @@ typedef struct {
     uno_dtype dtype;
 } uno_material;
 
+/* Name of a status code (library utility, no passage of the paper). */
 const char *uno_status_string(uno_status s);
 
 /* y = A(kappa) u: matrix-free stiffness apply of the periodic linear FE
@@ -118,7 +119,8 @@ uno_status uno_precond_create_fans(const uno_grid *grid, double kappa_ref, uno_d
 uno_status uno_precond_apply(const uno_precond *p, const void *r, void *s, uno_dtype vec_t, void *stream);
 
 /* Selects how FP64 applies of a UNO preconditioner are computed; both give
- * the same operator.  UNO_PATH_AUTO (default) and UNO_PATH_LEARNED use the
+ * the same operator (Sec. 4.2.2: modes outside the learned set carry only
+ * the bypass).  UNO_PATH_AUTO (default) and UNO_PATH_LEARNED use the
  * learned-mode passes when the preconditioner has them (UNO tables whose
  * learned block is small against the grid): since Phi equals the bypass W
  * outside the learned block, s = W r + T^H ((Phi - W) o T r) needs the
@@ -131,10 +133,13 @@ uno_status uno_precond_apply(const uno_precond *p, const void *r, void *s, uno_d
 enum { UNO_PATH_AUTO = 0, UNO_PATH_SPECTRAL = 1, UNO_PATH_LEARNED = 2, UNO_PATH_FUSED = 3 };
 uno_status uno_precond_set_path(uno_precond *p, int32_t path);
 
-/* Copies the half-spectrum table (n[0] x .. x n[d-2] x (n[d-1]/2+1) values,
- * C order, unscaled Phi) to host memory `out` (host). For inspection. */
+/* Copies the half-spectrum table Phi of eq. (fnocg-parametrization)
+ * (n[0] x .. x n[d-2] x (n[d-1]/2+1) values, C order, unscaled) to host
+ * memory `out` (host). For inspection. */
 uno_status uno_precond_table(const uno_precond *p, double *out, int64_t nout);
 
+/* Releases a preconditioner of uno_precond_create, uno_precond_create_fans
+ * or el_uno_precond_create (Sec. 4.2) and its device memory. */
 uno_status uno_precond_destroy(uno_precond *p);
 
 /* ---- Preconditioned CG (Algorithm 1 / Algorithm 2) ------------------ */
@@ -163,7 +168,8 @@ typedef struct {
     double r0_norm;       /* ||r_0||_inf */
 } uno_solve_info;
 
-/* Solves A(kappa) u = f for the zero-mean periodic fluctuation.
+/* Solves A(kappa) u = f for the zero-mean periodic fluctuation by
+ * preconditioned CG (Algorithm 1; Jacobi: Sec. 3.2, UNO: Algorithm 2).
  * f is uno_macro_rhs(gbar = macro_load) when macro_load (host, d values) is
  * non-NULL, else `rhs` (device, n doubles).  u (device, n doubles) holds the
  * initial guess on entry and the zero-mean solution on exit.
@@ -299,7 +305,8 @@ uno_status el_pcg_solve(const uno_grid *grid, const double *lambda, const double
  * Release with uno_precond_destroy.  Synchronous. */
 uno_status el_uno_precond_create(const uno_grid *grid, int32_t M, const double *theta, int64_t ntheta,
                                  double eps_spd, uno_precond **out);
-/* Effective stiffness (host out, 6 x 6 row-major, Mandel): column j of
+/* Effective stiffness (Sec. 5.2; Mandel basis, App. A) (host out, 6 x 6
+ * row-major): column j of
  * S = <D (eps_j + eps(u_j))> for the six loads eps_j (host, 6 x 6, rows)
  * with solutions u (device, 6 x 3n), and out = S L^-T with L the loads as
  * columns (invertible).  Synchronous. */
@@ -315,7 +322,7 @@ uno_status el_effective_stiffness(const uno_grid *grid, const double *lambda, co
 uno_status uno_train_accumulate(const uno_grid *grid, int32_t ns, const double *f, const double *u,
                                 double ns_total, double *alpha, double *beta, void *stream);
 
-/* Exact minimiser over theta (host, ntheta values) of the loss
+/* Exact minimiser (Sec. 4.4) over theta (host, ntheta values) of the loss
  * L = alpha.(Phi o Phi) - beta.Phi with Phi parametrized as in
  * uno_precond_create; alpha, beta: device half-spectrum features.
  * Synchronous. */
@@ -367,7 +374,8 @@ enum {
     UNO_KT_FFT_INV = 5,  /* last inverse pass (+ r.s) */
     UNO_KT_APPLY = 6     /* operator apply outside CG (fe_apply, residuals) */
 };
-/* Brackets every launch of kernel family `which` with start/stop HIP events
+/* Measurement utility (no passage of the paper).  Brackets every launch
+ * of kernel family `which` with start/stop HIP events
  * of the launch itself (hipExtLaunchKernelGGL) on its stream; UNO_KT_NONE
  * disables.  The events come from a pool and carry no system-scope fence.
  * uno_timing_read synchronizes those events and returns the summed duration
@@ -376,7 +384,8 @@ enum {
 uno_status uno_timing_enable(int32_t which);
 uno_status uno_timing_read(double *total_ms, int64_t *launches);
 
-/* Releases cached workspaces (all devices) and the timing event pool. */
+/* Library utility (no passage of the paper): releases cached workspaces
+ * (all devices) and the timing event pool. */
 uno_status uno_shutdown(void);
 
 #ifdef __cplusplus

@@ -24,6 +24,25 @@ def test_header_declares_the_hot_path_calls():
         assert req in names
 
 
+def test_every_declaration_cites_its_passage():
+    """The comment right above each declaration names the passage of the
+    paper it implements (section, equation, algorithm, appendix or table),
+    or says that the call is a library utility with no such passage."""
+    text = open(HEADER).read()
+    missing = []
+    for m in re.finditer(r"^(?:uno_status|const char \*)\s*(\w+)\(", text, flags=re.M):
+        pre = text[: m.start()]
+        i, j = pre.rfind("/*"), pre.rfind("*/")
+        between = pre[j + 2:] if j >= 0 else pre
+        between = re.sub(r"enum \{[^}]*\};", "", between)
+        between = re.sub(r"^(?:uno_status|const char \*)[^;]*;", "", between, flags=re.M)
+        comment = pre[i:j] if 0 <= i < j else ""
+        cited = re.search(r"Sec\.|eq\.|Algorithm|App\.|Table|no passage of the paper", comment)
+        if not cited or between.strip():
+            missing.append(m.group(1))
+    assert not missing, missing
+
+
 @pytest.mark.skipif(not os.path.exists(LIB), reason="library not built (run __graft_entry__.build())")
 def test_library_exports_every_declared_symbol():
     lib = ctypes.CDLL(LIB)
