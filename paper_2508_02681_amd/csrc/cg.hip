@@ -389,12 +389,19 @@ namespace {
 
 constexpr int kMaxStreamBlocks = 512;
 
-// Per-grid CG workspace.  Vectors, partial buffers, loop states and scalar
-// histories are held for up to nrhs_cap right-hand sides solved together:
-// vector b at + b n, partial buffer `kind` of b at part + (kind nrhs_cap + b)
-// npart, state b at state + b, history b at hist + b hist_cap.
+// CG workspace of one (device, grid shape, stream).  Vectors, partial
+// buffers, loop states and scalar histories are held for up to nrhs_cap
+// right-hand sides solved together: vector b at + b n, partial buffer `kind`
+// of b at part + (kind nrhs_cap + b) npart, state b at state + b, history b
+// at hist + b hist_cap.  A solve holds the workspace's mutex from ws_get to
+// its end: solves on different streams use different workspaces and run
+// concurrently; solves on one stream from several host threads take turns
+// (the device would order their kernels anyway, but they would share the
+// vectors, loop states and pinned host copy of the states).
 struct Workspace {
     int device = -1;
+    hipStream_t stream = nullptr;
+    std::mutex mu;
     int n[3] = {0, 0, 0};
     int64_t total = 0;
     int nbr = 0;              // workgroups of the streaming CG kernels
@@ -451,8 +458,10 @@ void ws_free(Workspace* w)
     delete w;
 }
 
+// The workspace of (current device, grid, stream), locked through *lease
+// for the caller's solve.
 uno_status ws_get(const Grid& g, const FftPlan* plan, const LowRankPlan* lr, int extra_parts, int hist_need, int nrhs,
-                  Workspace** out)
+                  hipStream_t stream, std::unique_lock<std::mutex>* lease, Workspace** out)
 {
     int dev = 0;
     UNO_HIP(hipGetDevice(&dev));
@@ -460,10 +469,13 @@ uno_status ws_get(const Grid& g, const FftPlan* plan, const LowRankPlan* lr, int
     {
         std::lock_guard<std::mutex> lk(g_ws_mu);
         for (Workspace* c : g_ws)
-            if (c->device == dev && c->n[0] == g.n[0] && c->n[1] == g.n[1] && c->n[2] == g.n[2]) w = c;
+            if (c->device == dev && c->stream == stream && c->n[0] == g.n[0] && c->n[1] == g.n[1] &&
+                c->n[2] == g.n[2])
+                w = c;
         if (!w) {
             w = new Workspace();
             w->device = dev;
+            w->stream = stream;
             for (int b = 0; b < 3; ++b) w->n[b] = g.n[b];
             w->total = g.total;
             const int64_t nb = (g.total + kBlock - 1) / kBlock;
@@ -471,6 +483,7 @@ uno_status ws_get(const Grid& g, const FftPlan* plan, const LowRankPlan* lr, int
             g_ws.push_back(w);
         }
     }
+    *lease = std::unique_lock<std::mutex>(w->mu);
     if (nrhs > w->nrhs_cap) {
         ws_free_vectors(w);
         const size_t vb = sizeof(double) * (size_t)g.total * nrhs;
@@ -547,7 +560,10 @@ uno_status ws_get(const Grid& g, const FftPlan* plan, const LowRankPlan* lr, int
 uno_status ws_release_all()
 {
     std::lock_guard<std::mutex> lk(g_ws_mu);
-    for (Workspace* w : g_ws) ws_free(w);
+    for (Workspace* w : g_ws) {
+        { std::lock_guard<std::mutex> wl(w->mu); }  // a solve still holding it finishes first
+        ws_free(w);
+    }
     g_ws.clear();
     return UNO_OK;
 }
@@ -726,19 +742,22 @@ static uno_status pcg_loop(const Grid& g, Workspace* w, const double* kappa64, c
     if (o->kind == UNO_PREC_JACOBI)  // one inverse diagonal per conductivity field
         for (int b = 0; b < (ks ? nrhs : 1); ++b)
             hipLaunchKernelGGL(k_inv_diag<T>, dim3(nb), dim3(kBlock), 0, st, g.dev, kappa64 + b * ks, dinv + b * ks);
-    // (re)start of the recurrence from the residual in w->r: s_0 = P r_0 and
-    // the partials of the first pass
-    auto start = [&](int reset) -> uno_status {
+    // (re)start of the recurrence at pass kk from the residual in w->r:
+    // s = P r and the partials pass kk reads (r.s and sum(s) in the buffers
+    // of kk's parity)
+    auto start = [&](int reset, int kk) -> uno_status {
         const dim3 grid(nb, nrhs);
+        double* rs0 = P.rs[kk & 1];
+        double* ss0 = P.ss[kk & 1];
         if (o->kind == UNO_PREC_NONE)
             hipLaunchKernelGGL((k_cg_init<T, 0>), grid, dim3(kBlock), 0, st, g.dev, (const T*)dinv,
-                               (const double*)w->r, sv, P.rmax, P.rs[0], P.ss[0], w->state, w->npart, ks, reset);
+                               (const double*)w->r, sv, P.rmax, rs0, ss0, w->state, w->npart, ks, reset);
         else if (o->kind == UNO_PREC_JACOBI)
             hipLaunchKernelGGL((k_cg_init<T, 1>), grid, dim3(kBlock), 0, st, g.dev, (const T*)dinv,
-                               (const double*)w->r, sv, P.rmax, P.rs[0], P.ss[0], w->state, w->npart, ks, reset);
+                               (const double*)w->r, sv, P.rmax, rs0, ss0, w->state, w->npart, ks, reset);
         else
             hipLaunchKernelGGL((k_cg_init<T, 2>), grid, dim3(kBlock), 0, st, g.dev, (const T*)dinv,
-                               (const double*)w->r, sv, P.rmax, P.rs[0], P.ss[0], w->state, w->npart, ks, reset);
+                               (const double*)w->r, sv, P.rmax, rs0, ss0, w->state, w->npart, ks, reset);
         UNO_HIP(hipGetLastError());
         if (lowrank) {  // transform of r for the first pass (and ||r||^2 in the fused flow)
             const bool fused = sizeof(T) == sizeof(double) && uno_use_fused(pc);
@@ -747,7 +766,7 @@ static uno_status pcg_loop(const Grid& g, Workspace* w, const double* kappa64, c
         }
         return UNO_OK;
     };
-    uno_status e = start(1);
+    uno_status e = start(1, 0);
     if (e != UNO_OK) return e;
     // passes in chunks; the host reads the states between chunks
     int k = 0, k0 = 0;
@@ -796,7 +815,7 @@ static uno_status pcg_loop(const Grid& g, Workspace* w, const double* kappa64, c
             }
             if (reopen) {
                 UNO_HIP(hipMemcpyAsync(w->state, w->host_state, sizeof(CgState) * nrhs, hipMemcpyHostToDevice, st));
-                e = start(0);
+                e = start(0, k);
                 if (e != UNO_OK) return e;
                 k0 = k;
                 chunk = o->graph_chunk > 0 ? o->graph_chunk : 8;
@@ -821,7 +840,7 @@ static uno_status pcg_loop(const Grid& g, Workspace* w, const double* kappa64, c
                     cycle_r[b] = hs.rmax_last;
                     prev_r[b] = -1.0;
                 }
-                e = start(0);
+                e = start(0, k);
                 if (e != UNO_OK) return e;
                 k0 = k;
                 chunk = o->graph_chunk > 0 ? o->graph_chunk : 8;
@@ -887,9 +906,10 @@ uno_status pcg_run_batch(const Grid& g, const double* kappa, int64_t ks, int nrh
         return worst;
     }
     Workspace* w = nullptr;
+    std::unique_lock<std::mutex> lease;
     const int hist_len = o->max_iter + 1;
     uno_status e = ws_get(g, pc ? &pc->plan : nullptr, pc ? pc->lr : nullptr, pc ? pc->rs_blocks : 0, hist_len, nrhs,
-                          &w);
+                          st, &lease, &w);
     if (e != UNO_OK) return e;
     const int nb = w->nbr;
     const Parts P = parts_of(w);
@@ -1004,7 +1024,8 @@ uno_status pcg_run_el(const Grid& g, const double* lam, const double* mu, int64_
     const int hist_len = o->max_iter + 1;
     int extra = el_march_blocks(g, nrhs);
     if (pc && lowrank_max_blocks(pc->lr) > extra) extra = lowrank_max_blocks(pc->lr);
-    e = ws_get(gv, nullptr, pc ? pc->lr : nullptr, extra, hist_len, nrhs, &w);
+    std::unique_lock<std::mutex> lease;
+    e = ws_get(gv, nullptr, pc ? pc->lr : nullptr, extra, hist_len, nrhs, st, &lease, &w);
     if (e != UNO_OK) return e;
     const int nb = w->nbr;
     const Parts P = parts_of(w);

@@ -304,3 +304,26 @@ def test_bf16_table_converges_to_same_solution(orc, uno):
     assert np.all((bits & 0xFFFF) == 0)  # representable in bfloat16
     kb, infos = _kbar_gpu(uno, kap, kind="uno", precond=p, rtol=1e-12)
     assert rel(kb, _kbar_oracle(orc, kap)) < 1e-8
+
+
+@pytest.mark.parametrize("kind", ["jacobi", "none"])
+@pytest.mark.parametrize("chunk", [1, 3])
+def test_fp32_restart_at_odd_pass(orc, uno, kind, chunk):
+    """FP32 mode with Jacobi or no preconditioner: residual replacements
+    (and the exit check's reopen) land on odd passes when the host checks
+    after every pass or every third one.  The restarted recurrence must read
+    r.s and sum(s) of the new residual: the solve converges with its true
+    FP64 residual within the tolerance, kappa_bar within 1e-5 of the oracle,
+    in no more than 1.5 times the FP64 solve's passes."""
+    shape = (24, 24, 24)
+    kap = _two_phase(shape, 33)
+    kw = dict(kind=kind, rtol=1e-8, max_iter=20000)
+    kb32, i32 = _kbar_gpu(uno, kap, op_dtype=torch.float32, prec_dtype=torch.float32, graph_chunk=chunk, **kw)
+    kb64, i64 = _kbar_gpu(uno, kap, graph_chunk=chunk, **kw)
+    err = rel(kb32, _kbar_oracle(orc, kap))
+    print("fp32 restarts", kind, chunk, [i["iters"] for i in i32], [i["iters"] for i in i64], "%.2e" % err, flush=True)
+    assert all(i["converged"] for i in i32)
+    assert all(i["true_rel_res"] <= 1e-8 for i in i32)
+    assert err < 1e-5
+    for a, b in zip(i32, i64):
+        assert a["iters"] <= 1.5 * b["iters"] + 10
