@@ -204,6 +204,28 @@ uno_status pcg_solve_batch(const uno_grid *grid, const uno_material *mat, int32_
                            const double *macro_loads, const double *rhs, double *u,
                            const uno_solve_opts *opts, uno_solve_info *info, void *stream);
 
+/* Size of the device array behind pcg_solve_noalloc, per device. */
+#define UNO_NOALLOC_SCRATCH_BYTES (24u << 20)
+
+/* For callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): pcg_solve
+ * (Algorithm 1, as above) with its workspace carved from a device array of
+ * the library, UNO_NOALLOC_SCRATCH_BYTES per device, held from the first
+ * call on a device until the process ends; the entry point itself is a
+ * library utility (no passage of the paper).  Same arguments as pcg_solve,
+ * one load, results bitwise those of pcg_solve; it calls no allocation
+ * routine.  The workspace (7 FP64 vectors of n values, half a vector more
+ * in the FP32 mode, partial sums, 2 (max_iter + 1) history values and the
+ * preconditioner's transform scratch) must fit: a 64^3 grid with M = 12 in
+ * FP64 fits, 96^3 does not; a problem that does not fit returns
+ * UNO_ERR_SHAPE before any work.  Calls on one device share the array and
+ * keep the last call's contents: the library serializes them (each returns
+ * after its solve has finished), so concurrent callers wait rather than
+ * race.  Synchronous. */
+uno_status pcg_solve_noalloc(const uno_grid *grid, const uno_material *mat, const double *macro_load,
+                             const double *rhs, double *u, const uno_solve_opts *opts, uno_solve_info *info,
+                             double *res_hist, void *stream);
+
 /* Effective conductivity (Sec. 5.1; the homogenized property handed back to
  * the macro scale, Sec. 1): for load j with gradient g_j (host loads,
  * nload x d) and solution u_j (device, nload x n doubles, C order),

@@ -84,6 +84,7 @@ def lib():
         "uno_precond_set_path": ([vp, i32], i),
         "uno_precond_destroy": ([vp], i),
         "pcg_solve": ([G, Mt, P(f64), vp, vp, P(uno_solve_opts), P(uno_solve_info), P(f64), vp], i),
+        "pcg_solve_noalloc": ([G, Mt, P(f64), vp, vp, P(uno_solve_opts), P(uno_solve_info), P(f64), vp], i),
         "pcg_solve_batch": ([G, Mt, i32, i32, P(f64), vp, vp, P(uno_solve_opts), P(uno_solve_info), vp], i),
         "effective_tensor": ([G, Mt, i32, P(f64), vp, P(f64), vp], i),
         "effective_tensor_batch": ([G, Mt, i32, i32, P(f64), vp, P(f64), vp], i),
@@ -268,8 +269,11 @@ class UnoPrecond:
 
 def pcg_solve(kappa: torch.Tensor, macro_load=None, rhs: torch.Tensor | None = None, u: torch.Tensor | None = None,
               kind="jacobi", precond: UnoPrecond | None = None, rtol=1e-6, max_iter=100000,
-              op_dtype=torch.float64, prec_dtype=torch.float64, graph_chunk=0, history=False, L0=1.0):
-    """Preconditioned CG (Algorithm 1/2).  Returns (u, info dict[, hist])."""
+              op_dtype=torch.float64, prec_dtype=torch.float64, graph_chunk=0, history=False, L0=1.0,
+              noalloc=False):
+    """Preconditioned CG (Algorithm 1/2).  Returns (u, info dict[, hist]).
+    noalloc: the allocation-free entry point (workspace in the library's
+    fixed device array; raises UnoError SHAPE when the problem does not fit)."""
     kinds = {"none": UNO_PREC_NONE, "jacobi": UNO_PREC_JACOBI, "uno": UNO_PREC_UNO}
     g = make_grid(kappa.shape, L0)
     if u is None:
@@ -289,13 +293,14 @@ def pcg_solve(kappa: torch.Tensor, macro_load=None, rhs: torch.Tensor | None = N
         if ml.size != len(kappa.shape):
             raise ValueError("macro_load needs one value per axis")
     hist = np.zeros(max_iter + 1) if history else None
-    st = lib().pcg_solve(
+    entry = lib().pcg_solve_noalloc if noalloc else lib().pcg_solve
+    st = entry(
         ctypes.byref(g), ctypes.byref(_mat(kappa)),
         ml.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if ml is not None else None,
         _dev(rhs, "rhs", torch.float64) if rhs is not None else None,
         _dev(u, "u", torch.float64), ctypes.byref(o), ctypes.byref(info),
         hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if hist is not None else None, _stream())
-    _check(st, "pcg_solve")
+    _check(st, "pcg_solve_noalloc" if noalloc else "pcg_solve")
     d = dict(iters=info.iters, converged=bool(info.converged), rel_res=info.rel_res,
              true_rel_res=info.true_rel_res, r0_norm=info.r0_norm)
     if history:

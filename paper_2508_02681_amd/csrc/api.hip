@@ -22,6 +22,8 @@ uno_status pcg_run_el(const Grid& g, const double* lam, const double* mu, int64_
 uno_status pcg_run_batch(const Grid& g, const double* kappa, int64_t ks, int nrhs, const double* macro_loads3,
                          const double* rhs, double* u, const uno_solve_opts* o, uno_solve_info* info, double* res_hist,
                          hipStream_t st);
+uno_status pcg_run_noalloc(const Grid& g, const double* kappa, const double* macro_load3, const double* rhs,
+                           double* u, const uno_solve_opts* o, uno_solve_info* info, double* res_hist, hipStream_t st);
 
 uno_status hip_status(hipError_t e)
 {
@@ -608,6 +610,21 @@ uno_status pcg_solve(const uno_grid* grid, const uno_material* mat, const double
     if (macro_load)
         for (int b = 0; b < grid->dim; ++b) g3[3 - grid->dim + b] = macro_load[b];
     return pcg_run(g, (const double*)mat->kappa, macro_load ? g3 : nullptr, rhs, u, opts, info, res_hist, S(stream));
+}
+
+uno_status pcg_solve_noalloc(const uno_grid* grid, const uno_material* mat, const double* macro_load,
+                             const double* rhs, double* u, const uno_solve_opts* opts, uno_solve_info* info,
+                             double* res_hist, void* stream)
+{
+    Grid g;
+    uno_status e = check_solve(grid, mat, opts, &g);
+    if (e != UNO_OK) return e;
+    if (!u || (!macro_load && !rhs)) return UNO_ERR_ARG;
+    double g3[3] = {0.0, 0.0, 0.0};
+    if (macro_load)
+        for (int b = 0; b < grid->dim; ++b) g3[3 - grid->dim + b] = macro_load[b];
+    return pcg_run_noalloc(g, (const double*)mat->kappa, macro_load ? g3 : nullptr, rhs, u, opts, info, res_hist,
+                           S(stream));
 }
 
 uno_status pcg_solve_batch(const uno_grid* grid, const uno_material* mat, int32_t kappa_per_rhs, int32_t nrhs,

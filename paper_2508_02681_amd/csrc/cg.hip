@@ -411,7 +411,6 @@ struct Workspace {
     double* dinv = nullptr;   // inverse Jacobi diagonal(s) of the current solve
     float* kap32 = nullptr;   // FP32 conductivities (mixed precision)
     int kap32_cap = 0;        // fields it holds
-    double* y64 = nullptr;    // FP64 operator output for residual replacement (mixed precision)
     double* part = nullptr;   // 8 partial buffers: rmax, rs[2], dp, ss[2], ds[2]
     double2* spec = nullptr;
     int64_t nspec = 0;
@@ -448,7 +447,6 @@ void ws_free(Workspace* w)
 {
     ws_free_vectors(w);
     (void)hipFree(w->kap32);
-    (void)hipFree(w->y64);
     (void)hipFree(w->part);
     (void)hipFree(w->spec);
     (void)hipFree(w->lr_gp);
@@ -456,6 +454,25 @@ void ws_free(Workspace* w)
     (void)hipFree(w->hist);
     (void)hipFree(w->gam);
     delete w;
+}
+
+// workgroups of the streaming CG kernels of a grid
+int ws_nbr(const Grid& g)
+{
+    const int64_t nb = (g.total + kBlock - 1) / kBlock;
+    return (int)(nb < kMaxStreamBlocks ? nb : kMaxStreamBlocks);
+}
+
+// capacity of each partial buffer: the most workgroups any kernel of a pass
+// writes partials from
+int ws_npart(const Grid& g, int nbr, int extra_parts)
+{
+    int need = nbr;
+    int ntile = choose_tile(g).blocks;
+    if (march_max_blocks(g) > ntile) ntile = march_max_blocks(g);
+    if (ntile > need) need = ntile;
+    if (extra_parts > need) need = extra_parts;
+    return need;
 }
 
 // The workspace of (current device, grid, stream), locked through *lease
@@ -478,8 +495,7 @@ uno_status ws_get(const Grid& g, const FftPlan* plan, const LowRankPlan* lr, int
             w->stream = stream;
             for (int b = 0; b < 3; ++b) w->n[b] = g.n[b];
             w->total = g.total;
-            const int64_t nb = (g.total + kBlock - 1) / kBlock;
-            w->nbr = (int)(nb < kMaxStreamBlocks ? nb : kMaxStreamBlocks);
+            w->nbr = ws_nbr(g);
             g_ws.push_back(w);
         }
     }
@@ -509,11 +525,7 @@ uno_status ws_get(const Grid& g, const FftPlan* plan, const LowRankPlan* lr, int
         w->npart = w->hist_cap = 0;
         w->nrhs_cap = nrhs;
     }
-    int need = w->nbr;
-    int ntile = choose_tile(g).blocks;
-    if (march_max_blocks(g) > ntile) ntile = march_max_blocks(g);
-    if (ntile > need) need = ntile;
-    if (extra_parts > need) need = extra_parts;
+    const int need = ws_npart(g, w->nbr, extra_parts);
     if (need > w->npart) {
         (void)hipFree(w->part);
         w->part = nullptr;
@@ -882,6 +894,10 @@ static uno_status pcg_loop(const Grid& g, Workspace* w, const double* kappa64, c
     return UNO_OK;
 }
 
+static uno_status pcg_run_ws(const Grid& g, Workspace* w, bool may_alloc, const double* kappa, int64_t ks, int nrhs,
+                             const double* macro_loads3, const double* rhs, double* u, const uno_solve_opts* o,
+                             uno_solve_info* info, double* res_hist, hipStream_t st);
+
 // nrhs solves with one operator (and preconditioner); load b: macro_loads +
 // 3 b (or rhs + b n), solution u + b n, info[b]
 uno_status pcg_run_batch(const Grid& g, const double* kappa, int64_t ks, int nrhs, const double* macro_loads3,
@@ -907,10 +923,22 @@ uno_status pcg_run_batch(const Grid& g, const double* kappa, int64_t ks, int nrh
     }
     Workspace* w = nullptr;
     std::unique_lock<std::mutex> lease;
-    const int hist_len = o->max_iter + 1;
-    uno_status e = ws_get(g, pc ? &pc->plan : nullptr, pc ? pc->lr : nullptr, pc ? pc->rs_blocks : 0, hist_len, nrhs,
-                          st, &lease, &w);
+    uno_status e = ws_get(g, pc ? &pc->plan : nullptr, pc ? pc->lr : nullptr, pc ? pc->rs_blocks : 0, o->max_iter + 1,
+                          nrhs, st, &lease, &w);
     if (e != UNO_OK) return e;
+    return pcg_run_ws(g, w, true, kappa, ks, nrhs, macro_loads3, rhs, u, o, info, res_hist, st);
+}
+
+// The solve of pcg_run_batch on a workspace sized for it (may_alloc: the
+// FP32 conductivities may be allocated on demand; otherwise w holds them).
+static uno_status pcg_run_ws(const Grid& g, Workspace* w, bool may_alloc, const double* kappa, int64_t ks, int nrhs,
+                             const double* macro_loads3, const double* rhs, double* u, const uno_solve_opts* o,
+                             uno_solve_info* info, double* res_hist, hipStream_t st)
+{
+    const uno_precond* pc = (o->kind == UNO_PREC_UNO) ? o->uno : nullptr;
+    const bool mixed = (o->op_t == UNO_F32);
+    const int hist_len = o->max_iter + 1;
+    uno_status e = UNO_OK;
     const int nb = w->nbr;
     const Parts P = parts_of(w);
     const int64_t n = g.total;
@@ -943,13 +971,13 @@ uno_status pcg_run_batch(const Grid& g, const double* kappa, int64_t ks, int nrh
         // FP32 conductivities: one field, or one per right-hand side
         const int nf = ks ? nrhs : 1;
         if (w->kap32_cap < nf) {
+            if (!may_alloc) return UNO_ERR_SHAPE;
             (void)hipFree(w->kap32);
             w->kap32 = nullptr;
             w->kap32_cap = 0;
             if (hipMalloc(&w->kap32, sizeof(float) * n * nf) != hipSuccess) return UNO_ERR_NOMEM;
             w->kap32_cap = nf;
         }
-        if (!w->y64 && hipMalloc(&w->y64, sizeof(double) * n) != hipSuccess) return UNO_ERR_NOMEM;
         for (int b = 0; b < nf; ++b)
             hipLaunchKernelGGL(k_convert<float>, dim3(nb), dim3(kBlock), 0, st, n, kappa + b * ks, w->kap32 + b * n);
         e = pcg_loop<float>(g, w, kappa, w->kap32, ks, u, o, pc, hist_len, nrhs, st, &k);
@@ -1186,6 +1214,107 @@ uno_status pcg_run(const Grid& g, const double* kappa, const double* macro_load3
                    const uno_solve_opts* o, uno_solve_info* info, double* res_hist, hipStream_t st)
 {
     return pcg_run_batch(g, kappa, 0, 1, macro_load3, rhs, u, o, info, res_hist, st);
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free solve: the CG workspace of one right-hand side is carved
+// from a file-scope device array instead of being allocated, for callers
+// that cannot allocate device memory.  Every call on a device shares that
+// device's array (the calls are serialized by g_scratch_mu; each returns
+// after its solve has finished) and finds the previous call's contents
+// there: nothing in it needs to start at zero (the loop states are set by
+// the init kernel, partials and histories are written before they are read,
+// and the previous direction is not read on the first pass).
+
+// kScratchDoubles doubles (24 MiB) per device: a 64^3 solve in FP64 needs
+// 7 vectors of 2 MiB plus partials, histories and the learned-mode scratch.
+constexpr size_t kScratchDoubles = (size_t)UNO_NOALLOC_SCRATCH_BYTES / sizeof(double);
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// device address of this device's array (hipGetSymbolAddress once per
+// device, with the device current); the host-side name `scratch` is never
+// passed to a kernel or a copy
+uno_status scratch_ptr(int dev, double** out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return UNO_ERR_DEVICE;
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return hip_status(e == hipSuccess ? hipErrorInvalidSymbol : e);
+        g_scratch_ptr[dev] = (double*)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return UNO_OK;
+}
+}  // namespace
+
+uno_status pcg_run_noalloc(const Grid& g, const double* kappa, const double* macro_load3, const double* rhs,
+                           double* u, const uno_solve_opts* o, uno_solve_info* info, double* res_hist, hipStream_t st)
+{
+    const uno_precond* pc = (o->kind == UNO_PREC_UNO) ? o->uno : nullptr;
+    const bool mixed = (o->op_t == UNO_F32);
+    if (mixed && pc && !uno_use_lowrank(pc)) return UNO_ERR_ARG;
+    int dev = 0;
+    UNO_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    double* base = nullptr;
+    uno_status e = scratch_ptr(dev, &base);
+    if (e != UNO_OK) return e;
+    Workspace w;
+    w.device = dev;
+    w.stream = st;
+    for (int b = 0; b < 3; ++b) w.n[b] = g.n[b];
+    w.total = g.total;
+    w.nbr = ws_nbr(g);
+    w.npart = ws_npart(g, w.nbr, pc ? pc->rs_blocks : 0);
+    w.nrhs_cap = 1;
+    // sub-buffers at 256-byte boundaries
+    const int64_t n = g.total;
+    const int hist_len = o->max_iter + 1;
+    size_t off = 0;
+    auto take = [&](size_t doubles) {
+        double* q = base + off;
+        off += (doubles + 31) / 32 * 32;
+        return q;
+    };
+    w.f = take(n);
+    w.r = take(n);
+    w.s = take(n);
+    w.d[0] = take(n);
+    w.d[1] = take(n);
+    w.p = take(n);
+    w.dinv = take(n);
+    if (mixed) {
+        w.kap32 = (float*)take((n + 1) / 2);
+        w.kap32_cap = 1;
+    }
+    w.part = take(8 * (size_t)w.npart);
+    w.state = (CgState*)take((sizeof(CgState) + 7) / 8);
+    w.hist = take(hist_len);
+    w.gam = take(hist_len);
+    w.hist_cap = hist_len;
+    if (pc && !uno_use_lowrank(pc)) {
+        w.spec = (double2*)take(2 * (size_t)pc->plan.nspec);
+        w.nspec = pc->plan.nspec;
+    }
+    if (pc && pc->lr) {
+        int64_t ngp = 0, nh = 0;
+        lowrank_scratch_size(pc->lr, &ngp, &nh);
+        w.lr_gp = (double2*)take(2 * (size_t)ngp);
+        w.lr_h = (double2*)take(2 * (size_t)nh);
+        w.lr_ngp = ngp;
+        w.lr_nh = nh;
+        w.lr_cap = 1;
+    }
+    if (off > kScratchDoubles) return UNO_ERR_SHAPE;  // beyond the array: use pcg_solve
+    CgState host_state;  // the loop state read back between chunks (pageable)
+    w.host_state = &host_state;
+    return pcg_run_ws(g, &w, false, kappa, 0, 1, macro_load3, rhs, u, o, info, res_hist, st);
 }
 
 }  // namespace unocg
