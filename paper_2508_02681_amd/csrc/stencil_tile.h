@@ -27,6 +27,19 @@
 
 namespace unocg {
 
+// A value the whole wavefront holds alike, moved to scalar registers.
+__device__ __forceinline__ double wave_uniform(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffLL));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ float wave_uniform(float v)
+{
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
 struct TileGeom {
     int tiles_y, tiles_z;
 };
@@ -95,15 +108,24 @@ struct MeanFree {
     double* part_dnew;
 };
 
-// The kernel: a workgroup owns a TY x TZ footprint and xb consecutive node
-// planes along x.  Planes of d (= s + beta d_old, shifted in FP32) and of
-// conductivities stream through a ring of three (d) and two (kappa) LDS
-// planes: each plane is loaded once per footprint, the loads of the next
-// plane are issued before the current plane is computed, and one barrier
-// per plane separates the ring writes from the reads.  Per node plane the
-// halo costs (TY+2)(TZ+2)/(TY TZ) of the plane; along x only the two end
-// planes of the march are extra.  Right-hand side blockIdx.y of a batch
-// reads its vectors at + blockIdx.y n (conductivities at + blockIdx.y ks).
+// The kernel: a workgroup owns a TY x TZ footprint (TY = 256 / TZ) and xb
+// consecutive node planes along x, and sweeps the input planes x0 - 1 ..
+// x0 + xb.  Input node plane xi (with a one-node halo in y and z) and voxel
+// plane xi stream through two LDS buffers, the loads of plane xi + 1 in
+// flight while plane xi is used, one barrier per plane.  Each thread keeps
+// three partial sums: input plane xi contributes to the outputs at xi + 1
+// (started), xi and xi - 1 (complete after it), so only the 3 x 3
+// neighbourhood of one plane and the 2 x 2 conductivities of two voxel
+// planes are live (9 + 4 LDS reads per node and plane).  Through voxel face
+// (sy, sz) in the y-z plane, plane xi contributes
+//   sum over the face's 4 nodes (b, c) of w[m] d[b][c] =: E[sy][sz],
+// with the weights of the neighbour-plane class (output xi -/+ 1) or the
+// same-plane class (output xi), times the conductivity of the voxel
+// (voxel plane xi - 1 for output xi - 1, xi for xi + 1, both for xi).
+// Per node plane the halo costs (TY+2)(TZ+2)/(TY TZ) of the plane; along x
+// only the two end planes of the sweep are extra.  Right-hand side
+// blockIdx.y of a batch reads its vectors at + blockIdx.y n (conductivities
+// at + blockIdx.y ks).
 //
 // In FP32 the direction is kept mean-free: A 1 = 0 and sum(A d) = 0, so
 // shifting d by a constant leaves p, d.p, alpha, r and beta unchanged and
@@ -129,7 +151,7 @@ __global__ void __launch_bounds__(256) k_stencil_march(GridDev g, MarchGeom mg, 
     constexpr int DY = TY + 2, DZ = TZ + 2, KY = TY + 1, KZ = TZ + 1;
     constexpr int ND = DY * DZ, NK = KY * KZ;
     constexpr int PD = (ND + 255) / 256, PK = (NK + 255) / 256;
-    __shared__ T Dr[3][ND];
+    __shared__ T Dr[2][ND];
     __shared__ T Kr[2][NK];
     __shared__ double slots[4];
 
@@ -186,27 +208,27 @@ __global__ void __launch_bounds__(256) k_stencil_march(GridDev g, MarchGeom mg, 
             koff[j] = wrapc(y0 - 1 + yl, g.n1) * g.n2 + wrapc(z0 - 1 + zl, g.n2);
         }
     }
-    const bool have_dold = CG && it.k > it.k0;
+    // d = s + beta d_old; on the first pass of a cycle beta = 0 and d_old is
+    // not yet written, so s stands in for it (s + 0 s = s exactly)
+    const T* __restrict__ dsrc = (CG && it.k > it.k0) ? dold : s;
     const int64_t pl = (int64_t)g.n1 * g.n2;
-    auto load_d = [&](int xp, T* sv, T* dv) {
+    T sv[PD], dv[PD], kv[PK];
+    // node plane xp and voxel plane xp (voxel xp lies between node planes xp and xp + 1)
+    auto load = [&](int xp) {
         const int64_t base = (int64_t)wrapc(xp, g.n0) * pl;
 #pragma unroll
         for (int j = 0; j < PD; ++j) {
             sv[j] = dv[j] = (T)0;
             if (doff[j] >= 0) {
                 sv[j] = s[base + doff[j]];
-                if (have_dold) dv[j] = dold[base + doff[j]];
+                if (CG) dv[j] = dsrc[base + doff[j]];
             }
         }
-    };
-    auto load_k = [&](int xp, T* kv) {
-        const int64_t base = (int64_t)wrapc(xp, g.n0) * pl;
 #pragma unroll
         for (int j = 0; j < PK; ++j) kv[j] = (koff[j] >= 0) ? kappa[base + koff[j]] : (T)0;
     };
 
-    // loads first: loop state, partials, previous gamma, the first three d
-    // planes and the first two conductivity planes
+    // loads first: loop state, partials, previous gamma and the first plane
     StateLoad sl;
     double head_share = 0.0, rs_share = 0.0, gprev = 1.0, ssum_share = 0.0, dsum_share = 0.0;
     if (CG) {
@@ -219,12 +241,7 @@ __global__ void __launch_bounds__(256) k_stencil_march(GridDev g, MarchGeom mg, 
             if (it.k > it.k0) dsum_share = load_share<OpSum>(mf.part_dold, gridDim.x);
         }
     }
-    T s0[PD], v0[PD], s1[PD], v1[PD], s2[PD], v2[PD], k0v[PK], k1v[PK];
-    load_d(x0 - 1, s0, v0);
-    load_d(x0, s1, v1);
-    load_d(x0 + 1, s2, v2);
-    load_k(x0 - 1, k0v);
-    load_k(x0, k1v);
+    load(x0 - 1);
     T beta = 0;
     bool first = true;
     if (CG) {
@@ -250,86 +267,85 @@ __global__ void __launch_bounds__(256) k_stencil_march(GridDev g, MarchGeom mg, 
         const double dsum = first ? 0.0 : combine_share<OpSum>(dsum_share, slots);
         shift = (T)((ssum + (double)beta * dsum) / (double)g.n);
     }
-    auto put_d = [&](int slot, const T* sv, const T* dv) {
+    // the same in every lane: held in scalar registers
+    beta = wave_uniform(beta);
+    shift = wave_uniform(shift);
+    auto put = [&](int slot) {
 #pragma unroll
         for (int j = 0; j < PD; ++j) {
             const int q = threadIdx.x + 256 * j;
-            if (q < ND) Dr[slot][q] = ((CG && !first) ? sv[j] + beta * dv[j] : sv[j]) - shift;
+            if (q < ND) Dr[slot][q] = (CG ? sv[j] + beta * dv[j] : sv[j]) - shift;
         }
-    };
-    auto put_k = [&](int slot, const T* kv) {
 #pragma unroll
         for (int j = 0; j < PK; ++j) {
             const int q = threadIdx.x + 256 * j;
             if (q < NK) Kr[slot][q] = kv[j];
         }
     };
-    // ring slots by plane offset from x0 - 1: d in slot (offset % 3), kappa in (offset % 2)
-    put_d(0, s0, v0);
-    put_d(1, s1, v1);
-    put_d(2, s2, v2);
-    put_k(0, k0v);
-    put_k(1, k1v);
+    put(0);
     __syncthreads();
 
     const int tz = threadIdx.x % TZ, ty = threadIdx.x / TZ;
     const int y = y0 + ty, z = z0 + tz;
     const bool yz_ok = (y < g.n1) && (z < g.n2);
-    T dm[3][3], d0[3][3], dq[3][3], km[2][2], kp[2][2];
-#pragma unroll
-    for (int bb = 0; bb < 3; ++bb)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            dm[bb][c] = Dr[0][(ty + bb) * DZ + tz + c];
-            d0[bb][c] = Dr[1][(ty + bb) * DZ + tz + c];
-        }
-#pragma unroll
-    for (int bb = 0; bb < 2; ++bb)
-#pragma unroll
-        for (int c = 0; c < 2; ++c) km[bb][c] = Kr[0][(ty + bb) * KZ + tz + c];
+    T km[2][2] = {{(T)0, (T)0}, {(T)0, (T)0}};
+    T acc_prev = 0, acc_cur = 0, dc_prev = 0;
     double dot = 0.0, dsum_own = 0.0;
-    for (int x = x0; x < xe; ++x) {
-        const int j = x - x0 + 1;  // offset of plane x from x0 - 1
-        const bool more = x + 1 < xe;
-        // next planes in flight while this one is computed
-        if (more) {
-            load_d(x + 2, s0, v0);
-            load_k(x + 1, k0v);
-        }
-        const int sd = (j + 1) % 3, sk = j % 2;
+    const int nsteps = xe - x0 + 2;
+    for (int t = 0; t < nsteps; ++t) {
+        const int xi = x0 - 1 + t;
+        const int slot = t & 1;
+        const bool more = t + 1 < nsteps;
+        if (more) load(xi + 1);  // next plane in flight while this one is used
+        T D[3][3], kp[2][2];
 #pragma unroll
         for (int bb = 0; bb < 3; ++bb)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) dq[bb][c] = Dr[sd][(ty + bb) * DZ + tz + c];
+            for (int c = 0; c < 3; ++c) D[bb][c] = Dr[slot][(ty + bb) * DZ + tz + c];
+        const bool has_kp = xi < xe;  // voxel planes x0 - 1 .. xe - 1
 #pragma unroll
         for (int bb = 0; bb < 2; ++bb)
 #pragma unroll
-            for (int c = 0; c < 2; ++c) kp[bb][c] = Kr[sk][(ty + bb) * KZ + tz + c];
-        if (yz_ok) {
-            const T acc = stencil_node<T>(g, dm, d0, dq, km, kp);
-            const int64_t i = (int64_t)x * pl + (int64_t)y * g.n2 + z;
-            p[i] = acc;
-            if (CG) {
-                dnew[i] = d0[1][1];
-                dot += (double)d0[1][1] * (double)acc;
-                if (MF) dsum_own += (double)d0[1][1];
-            }
-        }
+            for (int c = 0; c < 2; ++c) kp[bb][c] = has_kp ? Kr[slot][(ty + bb) * KZ + tz + c] : (T)0;
+        // row sums of w d along z per voxel column, neighbour-plane (rh) and
+        // same-plane (rl) weights; face (sy, sz) adds rows sy and sy + 1
+        T rh[3][2], rl[3][2];
 #pragma unroll
         for (int bb = 0; bb < 3; ++bb)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                dm[bb][c] = d0[bb][c];
-                d0[bb][c] = dq[bb][c];
+            for (int c = 0; c < 2; ++c) {
+                const int m0 = ((bb != 1) << 1) | (c != 1), m1 = ((bb != 1) << 1) | (c + 1 != 1);
+                rh[bb][c] = (T)g.w[4 | m0] * D[bb][c] + (T)g.w[4 | m1] * D[bb][c + 1];
+                rl[bb][c] = (T)g.w[m0] * D[bb][c] + (T)g.w[m1] * D[bb][c + 1];
             }
+        // outputs xi - 1 (through voxel plane xi - 1), xi (both) and xi + 1 (xi)
+        T accA = acc_prev, accB = acc_cur, accC = 0;
+#pragma unroll
+        for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const T eh = rh[bb][c] + rh[bb + 1][c], el = rl[bb][c] + rl[bb + 1][c];
+                accA += km[bb][c] * eh;
+                accB += (km[bb][c] + kp[bb][c]) * el;
+                accC += kp[bb][c] * eh;
+            }
+        if (t >= 2 && yz_ok) {  // output xi - 1 is complete
+            const int64_t i = (int64_t)(xi - 1) * pl + (int64_t)y * g.n2 + z;
+            p[i] = accA;
+            if (CG) {
+                dnew[i] = dc_prev;
+                dot += (double)dc_prev * (double)accA;
+                if (MF) dsum_own += (double)dc_prev;
+            }
+        }
+        acc_prev = accB;  // (meaningful from t = 1 while xi < xe)
+        dc_prev = D[1][1];
+        acc_cur = accC;   // (meaningful while xi + 1 < xe)
 #pragma unroll
         for (int bb = 0; bb < 2; ++bb)
 #pragma unroll
             for (int c = 0; c < 2; ++c) km[bb][c] = kp[bb][c];
-        if (more) {  // plane x + 2 replaces plane x - 1, kappa plane x + 1 replaces x - 1
-            put_d((j + 2) % 3, s0, v0);
-            put_k((j + 1) % 2, k0v);
-        }
+        if (more) put(slot ^ 1);
         __syncthreads();
     }
     if (CG) {
@@ -375,27 +391,36 @@ inline bool tile_near(const TileChoice& c, const GridDev& g)
     return c.tx <= g.n0 && 256 / c.tz <= g.n1 && c.tz <= g.n2;
 }
 
+// Footprint width of the operator march: whole 64-node rows where the
+// contiguous axis allows (measured: 64 x 4 footprints beat 32 x 8 by 3 % at
+// 64^3 x 48 and by 1 % at 192^3 x 3), else 32 or 16.
+inline int march_tz(const Grid& g) { return g.n[2] >= 64 ? 64 : (g.n[2] >= 24 ? 32 : 16); }
+
 // Upper bound of the marching kernel's workgroups per right-hand side (xb >= 2).
 inline int march_max_blocks(const Grid& g)
 {
-    const TileChoice c = choose_tile(g);
+    const int tz = march_tz(g), ty = 256 / tz;
     const int tx = g.n[0] < 2 ? 1 : (g.n[0] + 1) / 2;
-    return tx * c.geom.tiles_y * c.geom.tiles_z;
+    return tx * ((g.n[1] + ty - 1) / ty) * ((g.n[2] + tz - 1) / tz);
 }
 
-// Marching geometry: footprints of choose_tile's TY x TZ, and xb planes per
-// workgroup so that a launch has about 4096 workgroups (at least 2 planes).
-inline MarchGeom march_geom(const Grid& g, const TileChoice& c, int nrhs)
+// Marching geometry: TY x TZ footprints and the planes split evenly into
+// chunks of xb >= 2 so that a launch has about 2048 workgroups or more
+// (measured at 64^3 x 48: 2304 workgroups of 22 planes 111 us, 6144 of 8
+// planes 111 us, 4608 of 12 and 3072 of 16 planes 118-119 us, 1536 of 32
+// planes 127 us; 192^3 x 3: 199-204 us from 1728 to 6912 workgroups).
+inline MarchGeom march_geom(const Grid& g, int nrhs)
 {
+    const int tz = march_tz(g), ty = 256 / tz;
     MarchGeom m;
-    m.tiles_y = c.geom.tiles_y;
-    m.tiles_z = c.geom.tiles_z;
+    m.tiles_y = (g.n[1] + ty - 1) / ty;
+    m.tiles_z = (g.n[2] + tz - 1) / tz;
     const int64_t yz = (int64_t)m.tiles_y * m.tiles_z * nrhs;
-    int64_t xb = (g.n[0] * yz + 4095) / 4096;
+    int64_t xb = (g.n[0] * yz + 2047) / 2048;
     if (xb < 2) xb = 2;
     if (xb > g.n[0]) xb = g.n[0];
-    m.xb = (int)xb;
-    m.tiles_x = (g.n[0] + m.xb - 1) / m.xb;
+    m.tiles_x = (int)((g.n[0] + xb - 1) / xb);
+    m.xb = (g.n[0] + m.tiles_x - 1) / m.tiles_x;  // even split
     return m;
 }
 
@@ -430,14 +455,14 @@ inline int launch_tile(const Grid& g, const T* kappa, const T* s, const T* dold,
                        const CgIter& it, const double* part_rs, int np_rs, double* gam, hipStream_t st,
                        const MeanFree& mf = MeanFree{nullptr, nullptr, nullptr}, int nrhs = 1)
 {
-    const TileChoice c = choose_tile(g);
-    const MarchGeom m = march_geom(g, c, nrhs);
-    const bool near = 256 / c.tz <= g.n[1] && c.tz <= g.n[2];
+    const int tz = march_tz(g);
+    const MarchGeom m = march_geom(g, nrhs);
+    const bool near = 256 / tz <= g.n[1] && tz <= g.n[2];
     if (near)
-        launch_march_near<T, CG, HEAD, true>(m, c.tz, g.dev, kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam,
+        launch_march_near<T, CG, HEAD, true>(m, tz, g.dev, kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam,
                                              st, mf, nrhs);
     else
-        launch_march_near<T, CG, HEAD, false>(m, c.tz, g.dev, kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs,
+        launch_march_near<T, CG, HEAD, false>(m, tz, g.dev, kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs,
                                               gam, st, mf, nrhs);
     return m.tiles_x * m.tiles_y * m.tiles_z;
 }
