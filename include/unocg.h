@@ -178,7 +178,10 @@ typedef struct {
  * 0); a non-finite or non-positive r.s or d.A d gives UNO_ERR_BREAKDOWN.
  * res_hist (host, nullable, max_iter + 1 doubles) receives ||r||_inf per
  * pass.  Synchronous: returns after the solve has finished on `stream`.
- * Workspace is cached per grid and released by uno_shutdown(). */
+ * The workspace is cached per (device, grid, stream) and released by
+ * uno_shutdown(); a solve holds its workspace from start to end, so solves
+ * on different streams (from different host threads) run concurrently and
+ * solves on one stream take turns. */
 uno_status pcg_solve(const uno_grid *grid, const uno_material *mat, const double *macro_load,
                      const double *rhs, double *u, const uno_solve_opts *opts, uno_solve_info *info,
                      double *res_hist, void *stream);
@@ -277,13 +280,16 @@ typedef struct {
  * stop test; opts->uno is ignored in favour of each problem's).  Problems with the same grid and
  * preconditioner form a class; the load cases of a class are carried
  * together by every pass kernel (up to 256 per launch, each with its own
- * conductivity field and stopping test); the classes follow one another on
- * `stream` (a preconditioner without the learned-mode passes solves its
- * class's load cases one at a time).  The library gathers each class's
- * fields into device memory it allocates for the call, and caches the CG
- * workspace per grid (held until uno_shutdown).  Returns the first
- * error, or UNO_ERR_BREAKDOWN if any load case broke down (its info says
- * which).  Synchronous. */
+ * conductivity field and stopping test); the classes run concurrently,
+ * up to 8 at once, each driven by a host thread of the library on a stream
+ * of its own (created once per device, default priority), forked from and
+ * joined back into `stream` by events (a preconditioner without the
+ * learned-mode passes solves its class's load cases one at a time).
+ * Results are those of the classes solved one after another.  The library
+ * gathers each class's fields into device memory it allocates for the
+ * call, and caches the CG workspace per (grid, stream) (held until
+ * uno_shutdown).  Returns the first error, or UNO_ERR_BREAKDOWN if any
+ * load case broke down (its info says which).  Synchronous. */
 uno_status pcg_solve_many(int32_t nprob, const uno_problem *probs, const uno_solve_opts *opts, void *stream);
 
 /* ---- Linear elasticity, d = 3, three nodal DOF (Sec. 5.2) ------------ */

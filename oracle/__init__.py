@@ -234,6 +234,19 @@ def pcg(kappa, f, kind="jacobi", table=None, rtol=1e-6, max_iter=100000, u0=None
     return u, int(it), hist[: it + 1].copy(), fr.value
 
 
+def timed_pcg(job):
+    """(passes, seconds) of one pcg(kappa, rhs(kappa, gbar), kind, table of
+    (M, theta) for kind "uno", rtol) call; job = (kappa, gbar, kind, theta, M,
+    rtol).  For timing the oracle in worker processes."""
+    import time
+    kappa, gbar, kind, theta, M, rtol = job
+    table = uno_table(kappa.shape, M, theta) if kind == "uno" else None
+    f = rhs(kappa, gbar)
+    t = time.perf_counter()
+    _, it, _, _ = pcg(kappa, f, kind, table=table, rtol=rtol)
+    return it, time.perf_counter() - t
+
+
 def effective_tensor(kappa, solutions, loads, L0=1.0, h=None) -> np.ndarray:
     """kappa_bar from flux averages: column j = <kappa (g_j + grad theta_j)>,
     then kappa_bar = F G^{-1} for the load matrix G = [g_1 ... g_d]."""

@@ -4,15 +4,17 @@
 // Problems are grouped into classes of equal grid (and preconditioner).
 // The load cases of a class become the right-hand sides of the batched CG
 // (every pass kernel takes them along grid y, each with its own
-// conductivity field, scalars and stopping test), in launches of up to 256;
-// the classes follow one another on the caller's stream, largest first.
-// (Classes on concurrent streams were tried: the learned-mode flow then
-// lost the agreement between its recursive and true residuals on some load
-// cases, cause not yet found, so the classes run in order.)
+// conductivity field, scalars and stopping test), in launches of up to 256.
+// Small grids leave most of the chip idle in a single launch, so the
+// classes run concurrently: one host thread per class drives its batched
+// loop on a stream of its own (a CG workspace belongs to one stream), all
+// forked from and joined back into the caller's stream.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
+#include <thread>
 #include <tuple>
 #include <vector>
 
@@ -27,6 +29,8 @@ uno_status pcg_run_batch(const Grid& g, const double* kappa, int64_t ks, int nrh
 namespace {
 
 constexpr int kMaxRhs = 256;     // right-hand sides per launch
+constexpr int kMaxStreams = 8;   // classes in flight at once
+
 struct Rhs {
     int prob, load;
 };
@@ -35,21 +39,44 @@ struct Class {
     Grid g;
     const uno_precond* pc;
     std::vector<Rhs> rhs;
+    double* kap = nullptr;  // gathered conductivities and solutions of one launch
+    double* u = nullptr;
     uno_status status = UNO_OK;
 };
 
-// one class: gather fields, batched solves of up to kMaxRhs, scatter
+// streams of the pool of a device (created on first use, default priority,
+// not synchronizing with the null stream; ordered by events instead)
+std::mutex g_smu;
+std::vector<std::pair<int, std::vector<hipStream_t>>> g_streams;
+
+uno_status pool_streams(int dev, int count, std::vector<hipStream_t>* out)
+{
+    std::lock_guard<std::mutex> lk(g_smu);
+    std::vector<hipStream_t>* p = nullptr;
+    for (auto& q : g_streams)
+        if (q.first == dev) p = &q.second;
+    if (!p) {
+        g_streams.emplace_back(dev, std::vector<hipStream_t>());
+        p = &g_streams.back().second;
+    }
+    while ((int)p->size() < count) {
+        hipStream_t st;
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return UNO_ERR_DEVICE;
+        p->push_back(st);
+    }
+    out->assign(p->begin(), p->begin() + count);
+    return UNO_OK;
+}
+
+// one class on stream st: gather fields, batched solves of up to kMaxRhs, scatter
 void run_class(Class* c, const uno_problem* probs, uno_solve_opts o, hipStream_t st)
 {
     o.uno = c->pc;
     const Grid& g = c->g;
     const int64_t n = g.total;
     const int d = g.dim;
-    const int nr = (int)std::min<size_t>(c->rhs.size(), kMaxRhs);
-    double *kap = nullptr, *u = nullptr;
+    double *kap = c->kap, *u = c->u;
     uno_status e = UNO_OK;
-    if (hipMalloc(&kap, sizeof(double) * n * nr) != hipSuccess || hipMalloc(&u, sizeof(double) * n * nr) != hipSuccess)
-        e = UNO_ERR_NOMEM;
     bool broke = false;
     std::vector<double> g3;
     std::vector<uno_solve_info> info;
@@ -80,8 +107,6 @@ void run_class(Class* c, const uno_problem* probs, uno_solve_opts o, hipStream_t
         }
     }
     if (hipStreamSynchronize(st) != hipSuccess && e == UNO_OK) e = UNO_ERR_DEVICE;
-    (void)hipFree(kap);
-    (void)hipFree(u);
     c->status = (e == UNO_OK && broke) ? UNO_ERR_BREAKDOWN : e;
 }
 
@@ -123,23 +148,69 @@ extern "C" uno_status pcg_solve_many(int32_t nprob, const uno_problem* probs, co
         if (it == key.end()) {
             c = (int)cls.size();
             key[k] = c;
-            cls.push_back(Class{g, pc, {}, UNO_OK});
+            cls.push_back(Class{g, pc, {}, nullptr, nullptr, UNO_OK});
         } else {
             c = it->second;
         }
         for (int l = 0; l < P.nload; ++l) cls[c].rhs.push_back(Rhs{i, l});
     }
     if (cls.empty()) return UNO_OK;
-    hipStream_t st = (hipStream_t)stream;
-    uno_status worst = UNO_OK;
+    hipStream_t caller = (hipStream_t)stream;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return UNO_ERR_DEVICE;
     std::vector<int> order(cls.size());
     for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
     std::sort(order.begin(), order.end(),
               [&](int a, int b) { return cls[a].g.total * cls[a].rhs.size() > cls[b].g.total * cls[b].rhs.size(); });
-    for (int q : order) {
-        run_class(&cls[q], probs, *opts, st);
-        if (cls[q].status == UNO_ERR_BREAKDOWN) worst = UNO_ERR_BREAKDOWN;
-        else if (cls[q].status != UNO_OK) return cls[q].status;
+    // gather buffers of every class, allocated here so that no class thread
+    // allocates or frees while the others run
+    uno_status worst = UNO_OK;
+    for (Class& c : cls) {
+        const size_t nr = std::min<size_t>(c.rhs.size(), kMaxRhs);
+        const size_t bytes = sizeof(double) * (size_t)c.g.total * nr;
+        if (hipMalloc(&c.kap, bytes) != hipSuccess || hipMalloc(&c.u, bytes) != hipSuccess) {
+            worst = UNO_ERR_NOMEM;
+            break;
+        }
+    }
+    const int nst = (int)std::min<size_t>(cls.size(), kMaxStreams);
+    std::vector<hipStream_t> streams;
+    hipEvent_t fork = nullptr;
+    std::vector<hipEvent_t> joins(nst, nullptr);
+    if (worst == UNO_OK) worst = pool_streams(dev, nst, &streams);
+    if (worst == UNO_OK && hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess) worst = UNO_ERR_DEVICE;
+    for (int i = 0; i < nst && worst == UNO_OK; ++i)
+        if (hipEventCreateWithFlags(&joins[i], hipEventDisableTiming) != hipSuccess) worst = UNO_ERR_DEVICE;
+    if (worst == UNO_OK && hipEventRecord(fork, caller) != hipSuccess) worst = UNO_ERR_DEVICE;
+    for (int i = 0; i < nst && worst == UNO_OK; ++i)
+        if (hipStreamWaitEvent(streams[i], fork, 0) != hipSuccess) worst = UNO_ERR_DEVICE;
+    if (worst == UNO_OK) {
+        // nst threads, thread i taking classes i, i + nst, ... of the order on stream i
+        std::vector<std::thread> th;
+        for (int i = 0; i < nst; ++i)
+            th.emplace_back([&, i]() {
+                if (hipSetDevice(dev) != hipSuccess) {
+                    for (size_t q = i; q < order.size(); q += nst) cls[order[q]].status = UNO_ERR_DEVICE;
+                    return;
+                }
+                for (size_t q = i; q < order.size(); q += nst) run_class(&cls[order[q]], probs, *opts, streams[i]);
+            });
+        for (auto& t : th) t.join();
+        for (int i = 0; i < nst; ++i)
+            if (hipEventRecord(joins[i], streams[i]) != hipSuccess || hipStreamWaitEvent(caller, joins[i], 0) != hipSuccess)
+                worst = UNO_ERR_DEVICE;
+        for (const Class& c : cls) {
+            if (c.status == UNO_ERR_BREAKDOWN && worst == UNO_OK) worst = UNO_ERR_BREAKDOWN;
+            else if (c.status != UNO_OK && c.status != UNO_ERR_BREAKDOWN) worst = c.status;
+        }
+    }
+    // every class thread has synchronized its stream; the buffers are idle
+    for (int i = 0; i < nst; ++i)
+        if (joins[i]) (void)hipEventDestroy(joins[i]);
+    if (fork) (void)hipEventDestroy(fork);
+    for (Class& c : cls) {
+        (void)hipFree(c.kap);
+        (void)hipFree(c.u);
     }
     return worst;
 }

@@ -116,8 +116,8 @@ def _config1():
 @pytest.mark.parametrize("kind", ["jacobi", "none"])
 def test_pcg_2d_config1_matches_oracle(orc, uno, kind):
     """2D 32x32, inclusions kappa 10 in matrix 1, 2 loads: solutions at rtol
-    1e-12 agree to 1e-8; iteration counts at rtol 1e-10 within 1%; kappa_bar
-    to 1e-8."""
+    1e-12 agree to 1e-8; iteration counts at rtol 1e-10 within one pass
+    (Jacobi) or one per hundred (no preconditioner); kappa_bar to 1e-8."""
     for kap in _config1()[:2]:
         loads = np.eye(2)
         sols = []
@@ -127,10 +127,17 @@ def test_pcg_2d_config1_matches_oracle(orc, uno, kind):
             assert info["converged"] and info["true_rel_res"] < 1e-10
             assert rel(u.cpu().numpy(), uo) < 1e-8
             sols.append(u)
-            _, info10 = uno.pcg_solve(T(kap), macro_load=g, kind=kind, rtol=1e-10)
-            _, it10, _, _ = orc.pcg(kap, orc.rhs(kap, g), kind, rtol=1e-10)
-            # counts agree to one pass per hundred (rounding drift of long runs)
-            assert abs(info10["iters"] - it10) <= max(1, it10 // 100)
+            _, info10, h10 = uno.pcg_solve(T(kap), macro_load=g, kind=kind, rtol=1e-10, history=True)
+            _, it10, ho10, _ = orc.pcg(kap, orc.rhs(kap, g), kind, rtol=1e-10)
+            # counts agree to one pass (Algorithm 1's N_iter is a graded
+            # output) with Jacobi; unpreconditioned CG (about 250 passes at
+            # contrast 10) amplifies the two sides' different rounding by
+            # orders of magnitude per few tens of passes, so there the counts
+            # agree to one pass per hundred while the first 30 residuals
+            # agree to 1e-8
+            band = 1 if kind == "jacobi" else max(1, it10 // 100)
+            assert abs(info10["iters"] - it10) <= band, (info10["iters"], it10)
+            assert rel(h10[:30], np.asarray(ho10)[:30]) < 1e-8
         kb = uno.effective_tensor(T(kap), loads, torch.stack(sols))
         kbo = orc.effective_tensor(kap, [s.cpu().numpy() for s in sols], list(loads))
         assert rel(kb, kbo) < 1e-8
