@@ -378,6 +378,66 @@ def many_record(uno, si, torch, dev):
     return out
 
 
+def oracle_kbar_errors(kap, results):
+    """Relative difference (max entry / max entry) of each GPU kappa_bar of
+    one microstructure against the FP64 oracle's (Jacobi-CG to rtol 1e-10
+    for each load, the three loads in worker processes at once)."""
+    import multiprocessing as mp
+    import oracle
+    jobs = [(kap, g, "jacobi", None, 0, 1e-10) for g in LOADS]
+    t = time.perf_counter()
+    with mp.get_context("spawn").Pool(len(jobs)) as pool:
+        sols = pool.map(oracle.pcg_solution, jobs)
+    kb_o = oracle.effective_tensor(kap, sols, list(LOADS))
+    out = {"reference": "oracle Jacobi-CG (FP64) to rtol 1e-10 on test microstructure 1000, three loads",
+           "oracle_s": time.perf_counter() - t, "kappa_bar_oracle": np.round(kb_o, 8).tolist()}
+    for k, kb in results.items():
+        out[k] = float(np.abs(np.asarray(kb) - kb_o).max() / np.abs(kb_o).max())
+    log("kappa_bar vs FP64 oracle: " + ", ".join("%s %.1e" % (k, out[k]) for k in results))
+    return out
+
+
+def call_rooflines(uno, si, torch, dev, cfg, reps=20):
+    """The two C-ABI applies the hot path is built from, each timed on its
+    own at 192^3 (7.1M nodes, beyond the last-level cache): fe_apply (read
+    u, kappa; write y: 24 B/node FP64, 12 FP32) and uno_precond_apply (read r,
+    write s: 16 B/node, plus the learned-mode scratch; the table is 8125
+    values).  HIP events around reps back-to-back calls on the stream."""
+    shape = (192, 192, 192)
+    n = int(np.prod(shape))
+    kap = torch.tensor(si.microstructure(dict(cfg, shape=shape, r_min=12.0, r_max=24.0), 7000)[0], device=dev)
+    x = torch.tensor(si.random_field(shape, 11), device=dev)
+    p = uno.UnoPrecond.create(shape, 12, si.random_theta(uno.num_weights(3, 12), 12, scale=0.05, spread=0.1))
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def time_it(fn):
+        fn()
+        torch.cuda.synchronize()
+        ev0.record()
+        for _ in range(reps):
+            fn()
+        ev1.record()
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) * 1e3 / reps  # us per call
+
+    out = {"grid": list(shape), "peak_GBs": HBM_PEAK_GBS}
+    y = torch.empty_like(x)
+    k32, x32 = kap.float(), x.float()
+    y32 = torch.empty_like(x32)
+    s = torch.empty_like(x)
+    recs = [("fe_apply_f64", lambda: uno.fe_apply(kap, x, y), 24 * n),
+            ("fe_apply_f32", lambda: uno.fe_apply(k32, x32, y32), 12 * n),
+            ("uno_precond_apply_f64", lambda: p.apply(x, s), 16 * n)]
+    for name, fn, nbytes in recs:
+        us = time_it(fn)
+        gbs = nbytes / (us * 1e-6) / 1e9
+        out[name] = {"us": round(us, 2), "alg_bytes": nbytes, "achieved_GBs": round(gbs, 1),
+                     "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    log("192^3 calls: " + ", ".join("%s %.0f GB/s" % (k, v["achieved_GBs"]) for k, v in out.items()
+                                     if isinstance(v, dict)))
+    return out
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as fh:
@@ -438,6 +498,8 @@ def parse():
     ap.add_argument("--train-seeds", type=int, default=64)
     ap.add_argument("--M", type=int, default=0, help="mode parameter (0 = pick from a small sweep)")
     ap.add_argument("--jac-steps", type=int, default=4)
+    ap.add_argument("--no-oracle-ref", action="store_true", help="skip the FP64 oracle reference of kappa_bar")
+    ap.add_argument("--no-calls", action="store_true", help="skip the standalone fe_apply / uno_precond_apply rooflines")
     ap.add_argument("--cpu-workers", type=int, default=16,
                     help="most host cores the oracle's all-core baseline uses (one solve per core)")
     ap.add_argument("--no-cpu", action="store_true")
@@ -632,7 +694,7 @@ def main():
     log("UNO-CG 3 loads per launch: %.3f ms per solve; one load at a time: %.3f ms per solve" %
         (micro_t_solve, seq_t_solve))
     # ---------------- Jacobi-CG on the same microstructures ----------------
-    dtj, itsj, _ = timed("jacobi", None, args.jac_steps, 1, tag="jac_cg")
+    dtj, itsj, kbj = timed("jacobi", None, args.jac_steps, 1, tag="jac_cg")
     jac_t_solve = dtj / len(itsj) * 1e3
     jac_rate = n_dof * sum(itsj) / dtj
     log("Jac-CG: %.1f passes/solve, %.3e DOF*it/s, %.3f ms per solve" % (np.mean(itsj), jac_rate, jac_t_solve))
@@ -643,11 +705,6 @@ def main():
     kb_err = max(float(np.abs(a - b).max() / np.abs(b).max()) for a, b in zip(kbm, kbs[:nm]))
     log("UNO-CG FP32 op/prec: %.1f passes/solve, %.3f ms per solve, kappa_bar rel diff vs FP64 %.1e" %
         (np.mean(itsm), dtm / len(itsm) * 1e3, kb_err))
-    prec_bf16 = uno.UnoPrecond.create(SHAPE, M, theta, table_dtype=torch.bfloat16)
-    dtb, itsb, kbb = timed("uno", prec_bf16, 1, 0, tag="uno_cg_bf16_table", **f32)
-    kb_err_b = max(float(np.abs(a - b).max() / np.abs(b).max()) for a, b in zip(kbb, kbs[:nm]))
-    log("UNO-CG BF16 table: %.1f passes/solve, %.3f ms per solve, kappa_bar rel diff %.1e" %
-        (np.mean(itsb), dtb / len(itsb) * 1e3, kb_err_b))
 
     # ---------------- FANS (reference-medium preconditioner) for context ----------------
     pf = uno.UnoPrecond.fans(SHAPE, 0.5 * (cfg["k_matrix"] + cfg["k_incl"]))
@@ -734,6 +791,17 @@ def main():
         big["workload"] = "192^3, spheres r 12-24 vf 0.25, kappa 1/100, M = 12, three loads per launch, 40 passes"
         log("roofline (192^3): " + ", ".join("%s %.0f GB/s" % (k, v) for k, v in big["per_family_GBs"].items()))
 
+    # ---------------- kappa_bar of every solver against the FP64 oracle ----------------
+    oracle_err = None
+    if not args.no_oracle_ref:
+        oracle_err = oracle_kbar_errors(kap_test[0].cpu().numpy(),
+                                        {"uno_cg": kbs[0], "jac_cg": kbj[0], "uno_cg_fp32": kbm[0]})
+
+    # ---------------- the C-ABI calls fe_apply and uno_precond_apply at 192^3 ----------------
+    calls = None
+    if not args.no_calls:
+        calls = call_rooflines(uno, si, torch, dev, cfg)
+
     # ---------------- CPU baseline: the oracle, bounded sample ----------------
     cpu = None
     if not args.no_cpu:
@@ -764,8 +832,8 @@ def main():
         "fans_cg": {"passes_mean": float(np.mean(itsf)), "ms_per_solve": dtf / len(itsf) * 1e3},
         "uno_cg_fp32": {"passes_mean": float(np.mean(itsm)), "ms_per_solve": dtm / len(itsm) * 1e3,
                         "kappa_bar_rel_diff_vs_fp64": kb_err},
-        "uno_cg_bf16_table": {"passes_mean": float(np.mean(itsb)), "ms_per_solve": dtb / len(itsb) * 1e3,
-                              "kappa_bar_rel_diff_vs_fp64": kb_err_b},
+        "kappa_bar_error_vs_fp64_oracle": oracle_err,
+        "roofline_calls": calls,
         "time_to_tol_speedup_uno_vs_jac": jac_t_solve / uno_t_solve,
         "kappa_bar_first": np.round(kbs[0], 6).tolist(),
         "true_rel_res_max": worst_true,

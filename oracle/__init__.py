@@ -247,6 +247,13 @@ def timed_pcg(job):
     return it, time.perf_counter() - t
 
 
+def pcg_solution(job):
+    """The solution u of the same call as timed_pcg (for worker processes)."""
+    kappa, gbar, kind, theta, M, rtol = job
+    table = uno_table(kappa.shape, M, theta) if kind == "uno" else None
+    return pcg(kappa, rhs(kappa, gbar), kind, table=table, rtol=rtol)[0]
+
+
 def effective_tensor(kappa, solutions, loads, L0=1.0, h=None) -> np.ndarray:
     """kappa_bar from flux averages: column j = <kappa (g_j + grad theta_j)>,
     then kappa_bar = F G^{-1} for the load matrix G = [g_1 ... g_d]."""
