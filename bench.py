@@ -157,8 +157,9 @@ def elastic_families(uno, shape, M):
 
 def elastic_record(uno, si, torch, dev, M):
     """3D linear elasticity, 128^3, six Mandel loads: UNO-CG (trained on
-    Jacobi-CG solutions of two other microstructures) vs Jacobi-CG, FP64,
-    relative residual 1e-6, effective 6 x 6 stiffness."""
+    Jacobi-CG solutions of two other microstructures) in FP64 and in the FP32
+    mode vs Jacobi-CG FP64, relative residual 1e-6, effective 6 x 6
+    stiffness."""
     cfg = dict(si.CONFIG_EL_128)
     shape = cfg["shape"]
     n = int(np.prod(shape))
@@ -199,8 +200,11 @@ def elastic_record(uno, si, torch, dev, M):
 
     uu, iu, tu = timed(kind="uno", precond=P)
     uj, ij, tj = timed(kind="jacobi")
+    u32, i32, t32 = timed(kind="uno", precond=P, op_dtype=torch.float32)
     Du = uno.el_effective_stiffness(L, Mu, loads, uu)
     Dj = uno.el_effective_stiffness(L, Mu, loads, uj)
+    D32 = uno.el_effective_stiffness(L, Mu, loads, u32)
+    del u32
     fams, bytes_per = elastic_families(uno, shape, M)
 
     def run():
@@ -217,16 +221,24 @@ def elastic_record(uno, si, torch, dev, M):
                    "dof_iters_per_s": 3 * n * sum(its_u) / (tu * 1e-3)},
         "jac_cg": {"passes": its_j, "ms_per_solve": tj / 6, "converged": all(i["converged"] for i in ij),
                    "dof_iters_per_s": 3 * n * sum(its_j) / (tj * 1e-3)},
+        "uno_cg_fp32": {"passes": [i["iters"] for i in i32], "ms_per_solve": t32 / 6,
+                        "converged": all(i["converged"] for i in i32),
+                        "stiffness_rel_diff_vs_fp64_jac_cg": float(np.abs(D32 - Dj).max() / np.abs(Dj).max()),
+                        "note": "FP32 operator, preconditioner and direction; FP64 residuals, reductions, stop test"},
         "time_to_tol_speedup_uno_vs_jac": tj / tu,
+        "time_to_tol_speedup_uno_fp32_vs_jac_fp64": tj / t32,
         "true_rel_res_max": {"uno_cg": max(i["true_rel_res"] for i in iu),
-                             "jac_cg": max(i["true_rel_res"] for i in ij)},
+                             "jac_cg": max(i["true_rel_res"] for i in ij),
+                             "uno_cg_fp32": max(i["true_rel_res"] for i in i32)},
         "stiffness_uno": np.round(Du, 6).tolist(),
         "stiffness_rel_diff_uno_vs_jac": float(np.abs(Du - Dj).max() / np.abs(Dj).max()),
         "per_kernel": {k: rec[k] for k in ("kernel", "avg_us", "per_family_us", "per_family_GBs", "per_family_ms_per_run",
                                            "per_family_launches")},
     }
-    log("elastic 128^3: UNO-CG %.1f ms/solve (%d passes), Jac-CG %.1f ms/solve (%d passes), speedup %.2f" %
-        (tu / 6, max(its_u), tj / 6, max(its_j), tj / tu))
+    log("elastic 128^3: UNO-CG %.1f ms/solve (%d passes), Jac-CG %.1f ms/solve (%d passes), speedup %.2f; "
+        "UNO-CG FP32 %.1f ms/solve (%d passes), stiffness vs FP64 %.1e" %
+        (tu / 6, max(its_u), tj / 6, max(its_j), tj / tu, t32 / 6, max(i["iters"] for i in i32),
+         out["uno_cg_fp32"]["stiffness_rel_diff_vs_fp64_jac_cg"]))
     log("elastic 128^3 per kernel: " + ", ".join("%s %.0f us %.0f GB/s" % (k, rec["per_family_us"][k], v)
                                                   for k, v in rec["per_family_GBs"].items()))
     return out

@@ -311,8 +311,12 @@ uno_status el_macro_rhs(const uno_grid *grid, const double *lambda, const double
                         double *f, void *stream);
 /* nrhs solves for the macroscopic strains (host, nrhs x 6) carried by every
  * CG pass kernel (Algorithm 1 with P = none, the Jacobi diagonal, or the
- * preconditioner of el_uno_precond_create in opts->uno (Algorithm 2); FP64
- * only: op_t = prec_t = UNO_F64).  lame_per_rhs = 0: one (lambda, mu) field pair for all loads;
+ * preconditioner of el_uno_precond_create in opts->uno (Algorithm 2)).
+ * Precision: FP64 (op_t = prec_t = UNO_F64), or for UNO-CG the FP32 mode of
+ * pcg_solve (op_t = prec_t = UNO_F32: operator, preconditioner and the
+ * search direction in FP32, r, u, reductions and the stop test in FP64,
+ * residual replacement and exit check by the FP64 operator); Jacobi and
+ * plain CG in FP32 give UNO_ERR_ARG.  lame_per_rhs = 0: one (lambda, mu) field pair for all loads;
  * 1: nrhs pairs, pair j at + n j.  u (device, nrhs x 3n) holds the initial
  * guesses and receives the zero-mean fluctuations; info (host, nullable)
  * nrhs records.  1 <= nrhs <= 64.  Synchronous. */

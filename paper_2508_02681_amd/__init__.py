@@ -496,18 +496,19 @@ def el_macro_rhs(lam: torch.Tensor, mu: torch.Tensor, strain, L0=1.0):
 
 def el_pcg_solve(lam: torch.Tensor, mu: torch.Tensor, strains, u: torch.Tensor | None = None, kind="jacobi",
                  rtol=1e-6, max_iter=100000, graph_chunk=0, lame_per_rhs=False, L0=1.0,
-                 precond: UnoPrecond | None = None):
+                 precond: UnoPrecond | None = None, op_dtype=torch.float64):
     """CG, Jacobi-CG or UNO-CG (kind "uno" with a UnoPrecond.create_elastic)
     for nrhs macroscopic Mandel strains (nrhs x 6).
-    lam, mu: grid (shared) or nrhs x grid (lame_per_rhs).  Returns
-    (u (nrhs x 3 x grid), [info])."""
+    lam, mu: grid (shared) or nrhs x grid (lame_per_rhs).  op_dtype
+    torch.float32: the FP32 mode (UNO-CG).  Returns (u (nrhs x 3 x grid),
+    [info])."""
     shape = tuple(lam.shape[1:]) if lame_per_rhs else tuple(lam.shape)
     g = make_grid(shape, L0)
     e = np.ascontiguousarray(strains, dtype=np.float64).reshape(-1, 6)
     nrhs = e.shape[0]
     if u is None:
         u = torch.zeros((nrhs, 3) + shape, dtype=torch.float64, device=lam.device)
-    o = _opts(kind, precond, rtol, max_iter, torch.float64, torch.float64, graph_chunk)
+    o = _opts(kind, precond, rtol, max_iter, op_dtype, op_dtype, graph_chunk)
     infos = (uno_solve_info * nrhs)()
     _check(lib().el_pcg_solve(ctypes.byref(g), _dev(lam, "lambda", torch.float64), _dev(mu, "mu", torch.float64),
                               1 if lame_per_rhs else 0, nrhs, _dptr(e), _dev(u, "u", torch.float64), ctypes.byref(o),

@@ -733,6 +733,130 @@ static void replace_residual(const Grid& g, Workspace* w, const double* kappa64,
                        (const double*)w->p, w->r);
 }
 
+// Host side of the chunked CG loop (thermal and elastic).  pass(k, k0)
+// enqueues CG pass k of the cycle that started at pass k0, check(k, k0) the
+// convergence test after a chunk's last pass; the host reads the loop states
+// between chunks.  FP32 mode (restarts): residual() forms r = f - A u in
+// FP64 (the product in w->p), start(reset, k) restarts the recurrence at
+// pass k from w->r, true_res() writes ||f - A u||_inf and ||f||_inf of the
+// product in w->p into the states.  A residual replacement restarts every
+// right-hand side together (one pass index k0 for all) as soon as one of the
+// running ones has dropped by kRestartFactor since its last (re)start; a
+// restart earlier than a load needs costs it part of its Krylov space, not
+// accuracy, and loads that have ended keep their state.  When every load has
+// ended, a load whose true residual is still above its tolerance (the
+// recursive residual of the last cycle drifts from it by the FP32
+// operator's rounding) is reopened from that residual.
+template <class Pass, class Check, class Residual, class Start, class TrueRes>
+static uno_status run_chunks(Workspace* w, const uno_solve_opts* o, int nrhs, bool restarts, hipStream_t st,
+                             Pass pass, Check check, Residual residual, Start start, TrueRes true_res, int* k_end)
+{
+    const int chunk0 = o->graph_chunk > 0 ? o->graph_chunk : 8;
+    int k = 0, k0 = 0, chunk = chunk0;
+    std::vector<int> prev_k(nrhs, -1);
+    std::vector<double> prev_r(nrhs, -1.0);
+    std::vector<double> cycle_r(nrhs, -1.0);
+    auto read_states = [&]() -> uno_status {
+        UNO_HIP(hipMemcpyAsync(w->host_state, w->state, sizeof(CgState) * nrhs, hipMemcpyDeviceToHost, st));
+        UNO_HIP(hipStreamSynchronize(st));
+        return UNO_OK;
+    };
+    auto live = [](const CgState& hs) { return hs.status == 0 && hs.done == INT_MAX; };
+    uno_status e = UNO_OK;
+    for (;;) {
+        if (chunk > o->max_iter - k) chunk = o->max_iter - k;
+        for (int c = 0; c < chunk; ++c, ++k) {
+            e = pass(k, k0);
+            if (e != UNO_OK) return e;
+        }
+        check(k, k0);
+        UNO_HIP(hipGetLastError());
+        if ((e = read_states()) != UNO_OK) return e;
+        bool running = false;
+        for (int b = 0; b < nrhs; ++b)
+            if (live(w->host_state[b])) running = true;
+        if (!running && restarts && k < o->max_iter) {
+            // exit check of the FP32 mode
+            residual();
+            true_res();
+            UNO_HIP(hipGetLastError());
+            if ((e = read_states()) != UNO_OK) return e;
+            bool reopen = false;
+            for (int b = 0; b < nrhs; ++b) {
+                CgState& hs = w->host_state[b];
+                if (hs.status != 0 || hs.done == INT_MAX || !(hs.dmax > hs.tol_abs)) continue;
+                hs.done = INT_MAX;
+                cycle_r[b] = hs.dmax;
+                prev_r[b] = -1.0;
+                reopen = true;
+            }
+            if (reopen) {
+                UNO_HIP(hipMemcpyAsync(w->state, w->host_state, sizeof(CgState) * nrhs, hipMemcpyHostToDevice, st));
+                if ((e = start(0, k)) != UNO_OK) return e;
+                k0 = k;
+                chunk = chunk0;
+                continue;
+            }
+        }
+        if (!running || k >= o->max_iter) break;
+        if (restarts) {
+            bool due = false;
+            for (int b = 0; b < nrhs; ++b) {
+                const CgState& hs = w->host_state[b];
+                if (!live(hs)) continue;
+                if (cycle_r[b] < 0.0) cycle_r[b] = hs.r0max;
+                if (hs.rmax_last <= kRestartFactor * cycle_r[b]) due = true;
+            }
+            if (due) {
+                // residual replacement, every load at once, restart at pass k
+                residual();
+                for (int b = 0; b < nrhs; ++b) {
+                    const CgState& hs = w->host_state[b];
+                    if (!live(hs)) continue;
+                    cycle_r[b] = hs.rmax_last;
+                    prev_r[b] = -1.0;
+                }
+                if ((e = start(0, k)) != UNO_OK) return e;
+                k0 = k;
+                chunk = chunk0;
+                continue;
+            }
+        }
+        if (o->graph_chunk <= 0) {
+            // predict the passes still needed from the observed contraction
+            // rate; the slowest running right-hand side decides.  Three
+            // quarters of the prediction: a pass launched after every load
+            // has ended costs about as much as one more host check, and the
+            // rate over one chunk is noisy (64^3 x 48 loads: 112 passes
+            // launched for 106 needed, against 127 with a 5 % margin)
+            int next = 2;
+            for (int b = 0; b < nrhs; ++b) {
+                const CgState& hs = w->host_state[b];
+                if (!live(hs)) continue;
+                double target = hs.tol_abs;
+                if (restarts) {
+                    const double lvl = kRestartFactor * cycle_r[b];
+                    if (lvl > target) target = lvl;
+                }
+                int nx = 16;
+                if (prev_r[b] > 0.0 && hs.rmax_last > 0.0 && hs.k_last > prev_k[b] && hs.rmax_last < prev_r[b]) {
+                    const double rate = std::pow(hs.rmax_last / prev_r[b], 1.0 / (hs.k_last - prev_k[b]));
+                    const double need = std::log(target / hs.rmax_last) / std::log(rate);
+                    nx = (int)std::ceil(need * 0.75);
+                }
+                if (nx > next) next = nx;
+            }
+            chunk = next < 2 ? 2 : (next > 256 ? 256 : next);
+        }
+        for (int b = 0; b < nrhs; ++b) {
+            prev_k[b] = w->host_state[b].k_last;
+            prev_r[b] = w->host_state[b].rmax_last;
+        }
+    }
+    *k_end = k;
+    return UNO_OK;
+}
+
 // The CG loop for nrhs right-hand sides.  FP32 mode: the residual
 // replacement restarts every right-hand side together (one pass index k0
 // for all) as soon as one of the running ones has dropped by the restart
@@ -780,118 +904,21 @@ static uno_status pcg_loop(const Grid& g, Workspace* w, const double* kappa64, c
     };
     uno_status e = start(1, 0);
     if (e != UNO_OK) return e;
-    // passes in chunks; the host reads the states between chunks
-    int k = 0, k0 = 0;
-    int chunk = o->graph_chunk > 0 ? o->graph_chunk : 8;
-    std::vector<int> prev_k(nrhs, -1);
-    std::vector<double> prev_r(nrhs, -1.0);
-    std::vector<double> cycle_r(nrhs, -1.0);
-    for (;;) {
-        if (chunk > o->max_iter - k) chunk = o->max_iter - k;
-        for (int c = 0; c < chunk; ++c, ++k) {
-            e = enqueue_pass<T>(g, w, o->kind, pc, kappa, ks, u, k, k0, o->rtol, hist_len, nrhs, st);
-            if (e != UNO_OK) return e;
-        }
-        CgIter it = iter_of(w, P, k, k0, o->rtol, hist_len, np_update, ks);
+    auto pass = [&](int k, int k0) {
+        return enqueue_pass<T>(g, w, o->kind, pc, kappa, ks, u, k, k0, o->rtol, hist_len, nrhs, st);
+    };
+    auto check = [&](int k, int k0) {
+        const CgIter it = iter_of(w, P, k, k0, o->rtol, hist_len, np_update, ks);
         hipLaunchKernelGGL(k_cg_check, dim3(1, nrhs), dim3(kBlock), 0, st, it);
-        UNO_HIP(hipGetLastError());
-        UNO_HIP(hipMemcpyAsync(w->host_state, w->state, sizeof(CgState) * nrhs, hipMemcpyDeviceToHost, st));
-        UNO_HIP(hipStreamSynchronize(st));
-        bool running = false;
-        for (int b = 0; b < nrhs; ++b) {
-            const CgState& hs = w->host_state[b];
-            if (hs.status == 0 && hs.done == INT_MAX) running = true;
-        }
-        if (!running && restarts && k < o->max_iter) {
-            // FP32 mode: the recursive residual of the last cycle drifts from
-            // f - A u by the FP32 operator's rounding; a load whose true
-            // residual (FP64) is still above its tolerance is reopened and
-            // the recurrence restarts from that residual
-            replace_residual(g, w, kappa64, u, ks, nrhs, st);
-            const dim3 grid(nb, nrhs);
-            hipLaunchKernelGGL(k_resid_parts_b, grid, dim3(kBlock), 0, st, g.total, (const double*)w->f,
-                               (const double*)w->p, P.rs[0], P.rs[1], g.total, w->npart);
-            hipLaunchKernelGGL(k_resid_final_b, dim3(1, nrhs), dim3(kBlock), 0, st, (const double*)P.rs[0],
-                               (const double*)P.rs[1], nb, w->state, w->npart);
-            UNO_HIP(hipGetLastError());
-            UNO_HIP(hipMemcpyAsync(w->host_state, w->state, sizeof(CgState) * nrhs, hipMemcpyDeviceToHost, st));
-            UNO_HIP(hipStreamSynchronize(st));
-            bool reopen = false;
-            for (int b = 0; b < nrhs; ++b) {
-                CgState& hs = w->host_state[b];
-                if (hs.status != 0 || hs.done == INT_MAX || !(hs.dmax > hs.tol_abs)) continue;
-                hs.done = INT_MAX;
-                cycle_r[b] = hs.dmax;
-                prev_r[b] = -1.0;
-                reopen = true;
-            }
-            if (reopen) {
-                UNO_HIP(hipMemcpyAsync(w->state, w->host_state, sizeof(CgState) * nrhs, hipMemcpyHostToDevice, st));
-                e = start(0, k);
-                if (e != UNO_OK) return e;
-                k0 = k;
-                chunk = o->graph_chunk > 0 ? o->graph_chunk : 8;
-                continue;
-            }
-        }
-        if (!running || k >= o->max_iter) break;
-        if (restarts) {
-            bool due = false;
-            for (int b = 0; b < nrhs; ++b) {
-                const CgState& hs = w->host_state[b];
-                if (hs.status != 0 || hs.done != INT_MAX) continue;
-                if (cycle_r[b] < 0.0) cycle_r[b] = hs.r0max;
-                if (hs.rmax_last <= kRestartFactor * cycle_r[b]) due = true;
-            }
-            if (due) {
-                // residual replacement, every load at once, restart at pass k
-                replace_residual(g, w, kappa64, u, ks, nrhs, st);
-                for (int b = 0; b < nrhs; ++b) {
-                    const CgState& hs = w->host_state[b];
-                    if (hs.status != 0 || hs.done != INT_MAX) continue;
-                    cycle_r[b] = hs.rmax_last;
-                    prev_r[b] = -1.0;
-                }
-                e = start(0, k);
-                if (e != UNO_OK) return e;
-                k0 = k;
-                chunk = o->graph_chunk > 0 ? o->graph_chunk : 8;
-                continue;
-            }
-        }
-        if (o->graph_chunk <= 0) {
-            // predict the passes still needed from the observed contraction
-            // rate; the slowest running right-hand side decides.  Three
-            // quarters of the prediction: a pass launched after every load
-            // has ended costs about as much as one more host check, and the
-            // rate over one chunk is noisy (64^3 x 48 loads: 112 passes
-            // launched for 106 needed, against 127 with a 5 % margin)
-            int next = 2;
-            for (int b = 0; b < nrhs; ++b) {
-                const CgState& hs = w->host_state[b];
-                if (hs.status != 0 || hs.done != INT_MAX) continue;
-                double target = hs.tol_abs;
-                if (restarts) {
-                    const double lvl = kRestartFactor * cycle_r[b];
-                    if (lvl > target) target = lvl;
-                }
-                int nx = 16;
-                if (prev_r[b] > 0.0 && hs.rmax_last > 0.0 && hs.k_last > prev_k[b] && hs.rmax_last < prev_r[b]) {
-                    const double rate = std::pow(hs.rmax_last / prev_r[b], 1.0 / (hs.k_last - prev_k[b]));
-                    const double need = std::log(target / hs.rmax_last) / std::log(rate);
-                    nx = (int)std::ceil(need * 0.75);
-                }
-                if (nx > next) next = nx;
-            }
-            chunk = next < 2 ? 2 : (next > 256 ? 256 : next);
-        }
-        for (int b = 0; b < nrhs; ++b) {
-            prev_k[b] = w->host_state[b].k_last;
-            prev_r[b] = w->host_state[b].rmax_last;
-        }
-    }
-    *k_end = k;
-    return UNO_OK;
+    };
+    auto residual = [&]() { replace_residual(g, w, kappa64, u, ks, nrhs, st); };
+    auto true_res = [&]() {
+        hipLaunchKernelGGL(k_resid_parts_b, dim3(nb, nrhs), dim3(kBlock), 0, st, g.total, (const double*)w->f,
+                           (const double*)w->p, P.rs[0], P.rs[1], g.total, w->npart);
+        hipLaunchKernelGGL(k_resid_final_b, dim3(1, nrhs), dim3(kBlock), 0, st, (const double*)P.rs[0],
+                           (const double*)P.rs[1], nb, w->state, w->npart);
+    };
+    return run_chunks(w, o, nrhs, restarts, st, pass, check, residual, start, true_res, k_end);
 }
 
 static uno_status pcg_run_ws(const Grid& g, Workspace* w, bool may_alloc, const double* kappa, int64_t ks, int nrhs,
@@ -1027,16 +1054,150 @@ static uno_status pcg_run_ws(const Grid& g, Workspace* w, bool may_alloc, const 
 }
 
 // ---------------------------------------------------------------------------
-// Linear elasticity (c = 3, Sec. 5.2): Jacobi-CG or plain CG on the planar
-// 3n-vectors, nrhs macroscopic strains carried by every pass kernel.  The
-// update and init kernels run on the 3n-vector as on a scalar field; the
-// operator is the elastic gather (it tests convergence at the head of the
-// pass).  lks: stride of the Lame fields per right-hand side (0 if shared).
+// Linear elasticity (c = 3, Sec. 5.2): Jacobi-CG, plain CG or UNO-CG on the
+// planar 3n-vectors, nrhs macroscopic strains carried by every pass kernel.
+// The update and init kernels run on the 3n-vector as on a scalar field; the
+// operator is the elastic march (it tests convergence at the head of the
+// pass unless the UNO passes do).  lks: stride of the Lame fields per
+// right-hand side (0 if shared).  FP32 mode (UNO only): s, d, p and the Lame
+// fields in FP32, r, u, reductions and the stop test in FP64, with the
+// thermal mode's residual replacement and exit check (r = f - A u by the
+// FP64 operator).
+
+// per-component mean of the 3n-vectors v + b N (b < nrhs) removed
+static void el_remove_means(Workspace* w, const Parts& P, double* v, int64_t n, int nrhs, hipStream_t st)
+{
+    const int nb = w->nbr;
+    for (int b = 0; b < nrhs; ++b) {
+        double* pd = P.dp + (int64_t)b * w->npart;
+        for (int c = 0; c < 3; ++c) {
+            double* vc = v + b * 3 * n + c * n;
+            hipLaunchKernelGGL(k_sum_parts, dim3(nb), dim3(kBlock), 0, st, n, (const double*)vc, pd);
+            hipLaunchKernelGGL(k_sub_mean, dim3(nb), dim3(kBlock), 0, st, n, vc, (const double*)pd, nb, w->state + b);
+        }
+    }
+}
+
+// r = f - A u (FP64) for every right-hand side, A u in w->p
+static uno_status el_residual(const ElDev& E, const Grid& g, Workspace* w, const double* lam, const double* mu,
+                              int64_t lks, const double* u, int nrhs, hipStream_t st)
+{
+    const int64_t N = 3 * g.total;
+    CgIter none;
+    memset(&none, 0, sizeof(none));
+    for (int b = 0; b < nrhs; ++b) {
+        uno_status e = launch_el_apply<double, false, false>(E, g, lam + b * lks, mu + b * lks, 0, u + b * N, nullptr,
+                                                             nullptr, w->p + b * N, nullptr, none, nullptr, 0,
+                                                             nullptr, 1, st);
+        if (e != UNO_OK) return e;
+    }
+    hipLaunchKernelGGL(k_sub, dim3(w->nbr), dim3(kBlock), 0, st, N * nrhs, (const double*)w->f, (const double*)w->p,
+                       w->r);
+    return hip_status(hipGetLastError());
+}
+
+template <typename T>
+static uno_status el_loop(const ElDev& E, const Grid& g, const GridDev& gd, Workspace* w, const double* lam,
+                          const double* mu, const T* lamT, const T* muT, int64_t lks, double* u,
+                          const uno_solve_opts* o, const uno_precond* pc, int nrhs, hipStream_t st, int* k_end)
+{
+    const int nb = w->nbr;
+    const Parts P = parts_of(w);
+    const int hist_len = o->max_iter + 1;
+    const int64_t dks = lks ? 3 * g.total : 0;  // Jacobi diagonals follow the Lame fields
+    const bool restarts = sizeof(T) == sizeof(float);
+    T* sv = (T*)w->s;
+    T* pv = (T*)w->p;
+    LrBatch bt{};
+    int np_update = nb;
+    if (pc) {
+        bt = lowrank_batch(pc->lr, w->lr_gp, w->lr_h, nrhs);
+        np_update = lowrank_update_blocks(pc->lr, nrhs);
+    }
+    // (re)start at pass kk from w->r: ||r||_inf partials (and s_0 = P r_0 for
+    // Jacobi / none, r.s into the partials of kk's parity), the UNO flow's
+    // first transform
+    auto start = [&](int reset, int kk) -> uno_status {
+        const dim3 grid(nb, nrhs);
+        double* rs0 = P.rs[kk & 1];
+        double* ss0 = P.ss[kk & 1];
+        if (o->kind == UNO_PREC_JACOBI)
+            hipLaunchKernelGGL((k_cg_init<T, 1>), grid, dim3(kBlock), 0, st, gd, (const T*)w->dinv,
+                               (const double*)w->r, sv, P.rmax, rs0, ss0, w->state, w->npart, dks, reset);
+        else if (o->kind == UNO_PREC_UNO)
+            hipLaunchKernelGGL((k_cg_init<T, 2>), grid, dim3(kBlock), 0, st, gd, (const T*)w->dinv,
+                               (const double*)w->r, sv, P.rmax, rs0, ss0, w->state, w->npart, dks, reset);
+        else
+            hipLaunchKernelGGL((k_cg_init<T, 0>), grid, dim3(kBlock), 0, st, gd, (const T*)w->dinv,
+                               (const double*)w->r, sv, P.rmax, rs0, ss0, w->state, w->npart, dks, reset);
+        UNO_HIP(hipGetLastError());
+        if (pc) return lowrank_forward(pc->lr, w->r, nullptr, bt, iter_of(w, P, 0, 0, 0.0, 0, nb, dks), st);
+        return UNO_OK;
+    };
+    uno_status e = start(1, 0);
+    if (e != UNO_OK) return e;
+    // UNO flow per pass: [B (head) + C: s = P r, r.s] -> [d = s + beta d, p = A d, d.p]
+    // -> [update + pass A of the next pass]
+    auto pass = [&](int k, int k0) -> uno_status {
+        CgIter it = iter_of(w, P, k, k0, o->rtol, hist_len, np_update, dks);
+        T* dold = (T*)w->d[k & 1];
+        T* dnew = (T*)w->d[(k + 1) & 1];
+        if (pc) {
+            int np_rs = 0;
+            uno_status e2 = lowrank_finish<T>(pc->lr, w->r, sv, &it, &np_rs, bt, st);
+            if (e2 != UNO_OK) return e2;
+            e2 = launch_el_apply<T, true, false>(E, g, lamT, muT, lks, sv, dold, dnew, pv, P.dp, it, P.rs[k & 1],
+                                                 np_rs, w->gam, nrhs, st);
+            if (e2 != UNO_OK) return e2;
+            return lowrank_update_forward<T>(pc->lr, w->r, u, (const T*)dnew, (const T*)pv, it, P.dp,
+                                             el_march_blocks(g, nrhs), w->gam, P.rmax, nullptr, bt, st);
+        }
+        if constexpr (sizeof(T) == sizeof(double)) {
+            uno_status e2 = launch_el_apply<double, true, true>(E, g, lam, mu, lks, w->s, (const double*)dold,
+                                                                (double*)dnew, w->p, P.dp, it, P.rs[k & 1], nb,
+                                                                w->gam, nrhs, st);
+            if (e2 != UNO_OK) return e2;
+            const int np_dp = el_march_blocks(g, nrhs);
+            double* rs_next = P.rs[(k + 1) & 1];
+            double* ss_next = P.ss[(k + 1) & 1];
+            const dim3 grid(nb, nrhs);
+            if (o->kind == UNO_PREC_JACOBI)
+                uno_launch(UNO_KT_UPDATE, k_cg_update<double, 1>, grid, dim3(kBlock), 0, st, gd,
+                           (const double*)w->dinv, w->r, u, (const double*)dnew, (const double*)w->p, w->s, it,
+                           (const double*)P.dp, np_dp, (const double*)w->gam, P.rmax, rs_next, ss_next);
+            else
+                uno_launch(UNO_KT_UPDATE, k_cg_update<double, 0>, grid, dim3(kBlock), 0, st, gd,
+                           (const double*)w->dinv, w->r, u, (const double*)dnew, (const double*)w->p, w->s, it,
+                           (const double*)P.dp, np_dp, (const double*)w->gam, P.rmax, rs_next, ss_next);
+            return hip_status(hipGetLastError());
+        }
+        return UNO_ERR_ARG;  // FP32 mode runs UNO-CG only
+    };
+    auto check = [&](int k, int k0) {
+        const CgIter it = iter_of(w, P, k, k0, o->rtol, hist_len, np_update, dks);
+        hipLaunchKernelGGL(k_cg_check, dim3(1, nrhs), dim3(kBlock), 0, st, it);
+    };
+    const int64_t n = g.total, N = 3 * n;
+    auto residual = [&]() {
+        (void)el_residual(E, g, w, lam, mu, lks, u, nrhs, st);
+        el_remove_means(w, P, w->r, n, nrhs, st);  // as for r_0: the rounding residue lies outside range(A)
+    };
+    auto true_res = [&]() {
+        hipLaunchKernelGGL(k_resid_parts_b, dim3(nb, nrhs), dim3(kBlock), 0, st, N, (const double*)w->f,
+                           (const double*)w->p, P.rs[0], P.rs[1], N, w->npart);
+        hipLaunchKernelGGL(k_resid_final_b, dim3(1, nrhs), dim3(kBlock), 0, st, (const double*)P.rs[0],
+                           (const double*)P.rs[1], nb, w->state, w->npart);
+    };
+    return run_chunks(w, o, nrhs, restarts, st, pass, check, residual, start, true_res, k_end);
+}
+
 uno_status pcg_run_el(const Grid& g, const double* lam, const double* mu, int64_t lks, int nrhs, const double* eps6,
                       double* u, const uno_solve_opts* o, uno_solve_info* info, hipStream_t st)
 {
     if (o->kind != UNO_PREC_NONE && o->kind != UNO_PREC_JACOBI && o->kind != UNO_PREC_UNO) return UNO_ERR_ARG;
-    if (o->op_t != UNO_F64 || o->prec_t != UNO_F64) return UNO_ERR_ARG;
+    const bool f64 = o->op_t == UNO_F64 && o->prec_t == UNO_F64;
+    const bool mixed = o->op_t == UNO_F32 && o->prec_t == UNO_F32;
+    if (!f64 && !(mixed && o->kind == UNO_PREC_UNO)) return UNO_ERR_ARG;
     const uno_precond* pc = (o->kind == UNO_PREC_UNO) ? o->uno : nullptr;
     if (o->kind == UNO_PREC_UNO && !(pc && pc->nc == 3 && pc->lr)) return UNO_ERR_ARG;
     ElDev E;
@@ -1049,146 +1210,60 @@ uno_status pcg_run_el(const Grid& g, const double* lam, const double* mu, int64_
     GridDev gd = g.dev;
     gd.n = N;
     Workspace* w = nullptr;
-    const int hist_len = o->max_iter + 1;
     int extra = el_march_blocks(g, nrhs);
     if (pc && lowrank_max_blocks(pc->lr) > extra) extra = lowrank_max_blocks(pc->lr);
     std::unique_lock<std::mutex> lease;
-    e = ws_get(gv, nullptr, pc ? pc->lr : nullptr, extra, hist_len, nrhs, st, &lease, &w);
+    e = ws_get(gv, nullptr, pc ? pc->lr : nullptr, extra, o->max_iter + 1, nrhs, st, &lease, &w);
     if (e != UNO_OK) return e;
     const int nb = w->nbr;
     const Parts P = parts_of(w);
-    const int64_t dks = lks ? N : 0;  // Jacobi diagonals follow the Lame fields
     for (int b = 0; b < nrhs; ++b) {
-        double* fb = w->f + b * N;
-        e = launch_el_rhs(E, g, lam + b * lks, mu + b * lks, eps6 + 6 * b, fb, st);
+        e = launch_el_rhs(E, g, lam + b * lks, mu + b * lks, eps6 + 6 * b, w->f + b * N, st);
         if (e != UNO_OK) return e;
-        CgIter none;
-        memset(&none, 0, sizeof(none));
-        e = launch_el_apply<false, false>(E, g, lam + b * lks, mu + b * lks, 0, u + b * N, nullptr, nullptr,
-                                          w->p + b * N, nullptr, none, nullptr, 0, nullptr, 1, st);
-        if (e != UNO_OK) return e;
-        hipLaunchKernelGGL(k_sub, dim3(nb), dim3(kBlock), 0, st, N, (const double*)fb, (const double*)(w->p + b * N),
-                           w->r + b * N);
-        // f and r_0 sum to zero per component in exact arithmetic (the
-        // translations span the kernel of A); the rounding residue of those
-        // sums lies outside the range of A and would stall CG once the
-        // consistent part is resolved, so it is removed here
-        double* pd = P.dp + (int64_t)b * w->npart;
-        for (int c = 0; c < 3; ++c)
-            for (double* v : {fb + c * n, w->r + b * N + c * n}) {
-                hipLaunchKernelGGL(k_sum_parts, dim3(nb), dim3(kBlock), 0, st, n, (const double*)v, pd);
-                hipLaunchKernelGGL(k_sub_mean, dim3(nb), dim3(kBlock), 0, st, n, v, (const double*)pd, nb,
-                                   w->state + b);
-            }
     }
+    e = el_residual(E, g, w, lam, mu, lks, u, nrhs, st);
+    if (e != UNO_OK) return e;
+    // f and r_0 sum to zero per component in exact arithmetic (the
+    // translations span the kernel of A); the rounding residue of those
+    // sums lies outside the range of A and would stall CG once the
+    // consistent part is resolved, so it is removed here
+    el_remove_means(w, P, w->f, n, nrhs, st);
+    el_remove_means(w, P, w->r, n, nrhs, st);
     if (o->kind == UNO_PREC_JACOBI) {
         e = launch_el_inv_diag(E, g, lam, mu, lks, lks ? nrhs : 1, w->dinv, st);
         if (e != UNO_OK) return e;
     }
-    const dim3 grid(nb, nrhs);
-    if (o->kind == UNO_PREC_JACOBI)
-        hipLaunchKernelGGL((k_cg_init<double, 1>), grid, dim3(kBlock), 0, st, gd, (const double*)w->dinv,
-                           (const double*)w->r, w->s, P.rmax, P.rs[0], P.ss[0], w->state, w->npart, dks);
-    else if (o->kind == UNO_PREC_UNO)
-        hipLaunchKernelGGL((k_cg_init<double, 2>), grid, dim3(kBlock), 0, st, gd, (const double*)w->dinv,
-                           (const double*)w->r, w->s, P.rmax, P.rs[0], P.ss[0], w->state, w->npart, dks);
-    else
-        hipLaunchKernelGGL((k_cg_init<double, 0>), grid, dim3(kBlock), 0, st, gd, (const double*)w->dinv,
-                           (const double*)w->r, w->s, P.rmax, P.rs[0], P.ss[0], w->state, w->npart, dks);
-    UNO_HIP(hipGetLastError());
-    // UNO flow per pass: [B (head) + C: s = P r, r.s] -> [d = s + beta d, p = A d, d.p]
-    // -> [update + pass A of the next pass]; the first transform here
-    LrBatch bt{};
-    int np_update = nb;
-    if (pc) {
-        bt = lowrank_batch(pc->lr, w->lr_gp, w->lr_h, nrhs);
-        np_update = lowrank_update_blocks(pc->lr, nrhs);
-        e = lowrank_forward(pc->lr, w->r, nullptr, bt, iter_of(w, P, 0, 0, 0.0, 0, nb, dks), st);
-        if (e != UNO_OK) return e;
-    }
     int k = 0;
-    int chunk = o->graph_chunk > 0 ? o->graph_chunk : 8;
-    std::vector<int> prev_k(nrhs, -1);
-    std::vector<double> prev_r(nrhs, -1.0);
-    for (;;) {
-        if (chunk > o->max_iter - k) chunk = o->max_iter - k;
-        for (int c = 0; c < chunk; ++c, ++k) {
-            CgIter it = iter_of(w, P, k, 0, o->rtol, hist_len, np_update, dks);
-            double* dold = w->d[k & 1];
-            double* dnew = w->d[(k + 1) & 1];
-            if (pc) {
-                int np_rs = 0;
-                e = lowrank_finish<double>(pc->lr, w->r, w->s, &it, &np_rs, bt, st);
-                if (e != UNO_OK) return e;
-                e = launch_el_apply<true, false>(E, g, lam, mu, lks, w->s, dold, dnew, w->p, P.dp, it, P.rs[k & 1],
-                                                 np_rs, w->gam, nrhs, st);
-                if (e != UNO_OK) return e;
-                e = lowrank_update_forward<double>(pc->lr, w->r, u, (const double*)dnew, (const double*)w->p, it, P.dp,
-                                                   el_march_blocks(g, nrhs), w->gam, P.rmax, nullptr, bt, st);
-                if (e != UNO_OK) return e;
-                continue;
-            }
-            e = launch_el_apply<true, true>(E, g, lam, mu, lks, w->s, dold, dnew, w->p, P.dp, it, P.rs[k & 1], nb,
-                                            w->gam, nrhs, st);
-            if (e != UNO_OK) return e;
-            const int np_dp = el_march_blocks(g, nrhs);
-            double* rs_next = P.rs[(k + 1) & 1];
-            double* ss_next = P.ss[(k + 1) & 1];
-            if (o->kind == UNO_PREC_JACOBI)
-                uno_launch(UNO_KT_UPDATE, k_cg_update<double, 1>, grid, dim3(kBlock), 0, st, gd,
-                           (const double*)w->dinv, w->r, u, (const double*)dnew, (const double*)w->p, w->s, it,
-                           (const double*)P.dp, np_dp, (const double*)w->gam, P.rmax, rs_next, ss_next);
-            else
-                uno_launch(UNO_KT_UPDATE, k_cg_update<double, 0>, grid, dim3(kBlock), 0, st, gd,
-                           (const double*)w->dinv, w->r, u, (const double*)dnew, (const double*)w->p, w->s, it,
-                           (const double*)P.dp, np_dp, (const double*)w->gam, P.rmax, rs_next, ss_next);
-            UNO_HIP(hipGetLastError());
+    if (mixed) {
+        // FP32 Lame fields: lambda then mu, one pair per field
+        const int nf = lks ? nrhs : 1;
+        if (w->kap32_cap < nf) {  // a field of the 3n-vector workspace holds both (2n <= 3n floats)
+            (void)hipFree(w->kap32);
+            w->kap32 = nullptr;
+            w->kap32_cap = 0;
+            if (hipMalloc(&w->kap32, sizeof(float) * N * nf) != hipSuccess) return UNO_ERR_NOMEM;
+            w->kap32_cap = nf;
         }
-        CgIter it = iter_of(w, P, k, 0, o->rtol, hist_len, np_update, dks);
-        hipLaunchKernelGGL(k_cg_check, dim3(1, nrhs), dim3(kBlock), 0, st, it);
-        UNO_HIP(hipGetLastError());
-        UNO_HIP(hipMemcpyAsync(w->host_state, w->state, sizeof(CgState) * nrhs, hipMemcpyDeviceToHost, st));
-        UNO_HIP(hipStreamSynchronize(st));
-        bool running = false;
-        int next = 2;
-        for (int b = 0; b < nrhs; ++b) {
-            const CgState& hs = w->host_state[b];
-            if (hs.status != 0 || hs.done != INT_MAX) continue;
-            running = true;
-            int nx = 16;
-            if (prev_r[b] > 0.0 && hs.rmax_last > 0.0 && hs.k_last > prev_k[b] && hs.rmax_last < prev_r[b]) {
-                const double rate = std::pow(hs.rmax_last / prev_r[b], 1.0 / (hs.k_last - prev_k[b]));
-                nx = (int)std::ceil(std::log(hs.tol_abs / hs.rmax_last) / std::log(rate) * 0.75);
-            }
-            if (nx > next) next = nx;
-        }
-        if (!running || k >= o->max_iter) break;
-        if (o->graph_chunk <= 0) chunk = next < 2 ? 2 : (next > 256 ? 256 : next);  // as in pcg_loop
-        for (int b = 0; b < nrhs; ++b) {
-            prev_k[b] = w->host_state[b].k_last;
-            prev_r[b] = w->host_state[b].rmax_last;
-        }
+        float* lam32 = w->kap32;
+        float* mu32 = w->kap32 + n * nf;
+        hipLaunchKernelGGL(k_convert<float>, dim3(nb), dim3(kBlock), 0, st, n * nf, lam, lam32);
+        hipLaunchKernelGGL(k_convert<float>, dim3(nb), dim3(kBlock), 0, st, n * nf, mu, mu32);
+        e = el_loop<float>(E, g, gd, w, lam, mu, lam32, mu32, lks, u, o, pc, nrhs, st, &k);
+    } else {
+        e = el_loop<double>(E, g, gd, w, lam, mu, lam, mu, lks, u, o, pc, nrhs, st, &k);
     }
+    if (e != UNO_OK) return e;
     std::vector<CgState> hs(w->host_state, w->host_state + nrhs);
     // zero-mean components and the true residual in FP64
-    for (int b = 0; b < nrhs; ++b) {
-        double* pd = P.dp + (int64_t)b * w->npart;
-        for (int c = 0; c < 3; ++c) {
-            double* uc = u + b * N + c * n;
-            hipLaunchKernelGGL(k_sum_parts, dim3(nb), dim3(kBlock), 0, st, n, (const double*)uc, pd);
-            hipLaunchKernelGGL(k_sub_mean, dim3(nb), dim3(kBlock), 0, st, n, uc, (const double*)pd, nb, w->state + b);
-        }
-        CgIter none;
-        memset(&none, 0, sizeof(none));
-        e = launch_el_apply<false, false>(E, g, lam + b * lks, mu + b * lks, 0, u + b * N, nullptr, nullptr,
-                                          w->p + b * N, nullptr, none, nullptr, 0, nullptr, 1, st);
-        if (e != UNO_OK) return e;
-        double* pa = P.rs[0] + (int64_t)b * w->npart;
-        double* pb = P.rs[1] + (int64_t)b * w->npart;
-        hipLaunchKernelGGL(k_resid_parts, dim3(nb), dim3(kBlock), 0, st, N, (const double*)(w->f + b * N),
-                           (const double*)(w->p + b * N), pa, pb);
-        hipLaunchKernelGGL(k_resid_final, dim3(1), dim3(kBlock), 0, st, (const double*)pa, (const double*)pb, nb,
-                           w->state + b);
+    el_remove_means(w, P, u, n, nrhs, st);
+    e = el_residual(E, g, w, lam, mu, lks, u, nrhs, st);
+    if (e != UNO_OK) return e;
+    {
+        const dim3 grid(nb, nrhs);
+        hipLaunchKernelGGL(k_resid_parts_b, grid, dim3(kBlock), 0, st, N, (const double*)w->f, (const double*)w->p,
+                           P.rs[0], P.rs[1], N, w->npart);
+        hipLaunchKernelGGL(k_resid_final_b, dim3(1, nrhs), dim3(kBlock), 0, st, (const double*)P.rs[0],
+                           (const double*)P.rs[1], nb, w->state, w->npart);
         UNO_HIP(hipGetLastError());
     }
     UNO_HIP(hipMemcpyAsync(w->host_state, w->state, sizeof(CgState) * nrhs, hipMemcpyDeviceToHost, st));

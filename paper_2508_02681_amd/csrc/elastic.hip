@@ -72,14 +72,15 @@ __device__ __forceinline__ int wrap_el(int v, int n) { return v < 0 ? v + n : (v
 
 // In-place 3D Walsh-Hadamard transform of the eight corner values,
 // x^(h) = sum_v x(v) (-1)^(h.v), v = 4a + 2b + c.
-__device__ __forceinline__ void had8(double x[8])
+template <typename T>
+__device__ __forceinline__ void had8(T x[8])
 {
 #pragma unroll
     for (int s = 1; s < 8; s <<= 1)
 #pragma unroll
         for (int v = 0; v < 8; ++v)
             if (!(v & s)) {
-                const double a = x[v], b = x[v | s];
+                const T a = x[v], b = x[v | s];
                 x[v] = a + b;
                 x[v | s] = a - b;
             }
@@ -112,11 +113,12 @@ __host__ __device__ constexpr int el_pop(int h) { return (h & 1) + ((h >> 1) & 1
 // |h| the number of set transverse bits, w/8 the Gauss weight times the
 // voxel volume over the 8 of the inverse transform; lw, mw carry the w/8.
 // U[i][v] in: corner values of component i; out: corner forces.
-__device__ __forceinline__ void el_element(const ElDev& E, double lw, double mw, double U[3][8])
+template <typename T>
+__device__ __forceinline__ void el_element(const ElDev& E, T lw, T mw, T U[3][8])
 {
 #pragma unroll
     for (int i = 0; i < 3; ++i) had8(U[i]);
-    double g[3][3][4];
+    T g[3][3][4];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -124,28 +126,28 @@ __device__ __forceinline__ void el_element(const ElDev& E, double lw, double mw,
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 const int h = el_tins(t, j);
-                g[i][j][t] = E.hc[j][el_pop(h)] * U[i][h | (4 >> j)];
+                g[i][j][t] = (T)E.hc[j][el_pop(h)] * U[i][h | (4 >> j)];
             }
-    double Y[3][8];
+    T Y[3][8];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int v = 0; v < 8; ++v) Y[i][v] = 0.0;
+        for (int v = 0; v < 8; ++v) Y[i][v] = (T)0;
 #pragma unroll
     for (int h = 0; h < 8; ++h) {
         if (h == 7) continue;  // every direction has a set bit: no term
-        double tr = 0.0;
+        T tr = (T)0;
 #pragma unroll
         for (int k = 0; k < 3; ++k)
             if (!(h & (4 >> k))) tr += g[k][k][el_tpos(h, k)];
-        const double ltr = lw * tr;
+        const T ltr = lw * tr;
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
             if (h & (4 >> j)) continue;
-            const double c = E.hc[j][el_pop(h)];
+            const T c = (T)E.hc[j][el_pop(h)];
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
-                double sij = g[i][j][el_tpos(h, j)];
+                T sij = g[i][j][el_tpos(h, j)];
                 if (!(h & (4 >> i))) sij += g[j][i][el_tpos(h, i)];
                 sij *= mw;
                 if (i == j) sij += ltr;
@@ -179,16 +181,16 @@ constexpr int kElT = 16;        // threads per tile side
 constexpr int kElO = kElT - 1;  // owned nodes per tile side
 constexpr int kElL = kElT + 1;  // LDS node tile side
 
-template <bool CG, bool HEAD>
-__global__ void __launch_bounds__(256) k_el_march(ElDev E, ElGeom eg, const double* __restrict__ lam,
-                                                  const double* __restrict__ mu, int64_t lks,
-                                                  const double* __restrict__ s, const double* __restrict__ dold,
-                                                  double* __restrict__ dnew, double* __restrict__ p,
+template <typename T, bool CG, bool HEAD>
+__global__ void __launch_bounds__(256) k_el_march(ElDev E, ElGeom eg, const T* __restrict__ lam,
+                                                  const T* __restrict__ mu, int64_t lks,
+                                                  const T* __restrict__ s, const T* __restrict__ dold,
+                                                  T* __restrict__ dnew, T* __restrict__ p,
                                                   double* __restrict__ part_dp, CgIter it,
                                                   const double* __restrict__ part_rs, int np_rs, double* gam)
 {
-    __shared__ double Dl[3][3][kElL * kElL];  // ring slot, component, node
-    __shared__ double X[2][9][256];           // exchanged corner forces
+    __shared__ T Dl[3][3][kElL * kElL];  // ring slot, component, node
+    __shared__ T X[2][9][256];           // exchanged corner forces
     __shared__ double slots[4];
     const GridDev& g = E.g;
     const int64_t n = g.n;
@@ -232,7 +234,7 @@ __global__ void __launch_bounds__(256) k_el_march(ElDev E, ElGeom eg, const doub
         rs_share = load_share<OpSum>(part_rs, np_rs);
         if (it.k > it.k0) gprev = gam[it.k - 1];
     }
-    double beta = 0.0;
+    T beta = 0;
     bool use_old = false;
     if (CG) {
         if (HEAD) {
@@ -249,11 +251,11 @@ __global__ void __launch_bounds__(256) k_el_march(ElDev E, ElGeom eg, const doub
             return;
         }
         use_old = k != it.k0;
-        beta = use_old ? gk / gprev : 0.0;
+        beta = use_old ? (T)(gk / gprev) : (T)0;
     }
 
     // node plane m (global x0 - 1 + m) of the operand
-    double ps[3], pd[3], xs_[3], xd[3];
+    T ps[3], pd[3], xs_[3], xd[3];
     auto fetch = [&](int m) {
         const int64_t b = (int64_t)wrap_el(x0 - 1 + m, g.n0) * plane;
 #pragma unroll
@@ -270,7 +272,7 @@ __global__ void __launch_bounds__(256) k_el_march(ElDev E, ElGeom eg, const doub
         const int slot = m % 3;
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            const double d = use_old ? ps[i] + beta * pd[i] : ps[i];
+            const T d = use_old ? ps[i] + beta * pd[i] : ps[i];
             Dl[slot][i][l0] = d;
             if (has_x) Dl[slot][i][l1] = use_old ? xs_[i] + beta * xd[i] : xs_[i];
             if (CG && own && m >= 1 && m <= nx) dnew[i * n + (int64_t)(x0 - 1 + m) * plane + o0] = d;
@@ -280,26 +282,26 @@ __global__ void __launch_bounds__(256) k_el_march(ElDev E, ElGeom eg, const doub
     store(0);
     fetch(1);
     store(1);
-    double le = lam[(int64_t)wrap_el(x0 - 1, g.n0) * plane + o0];
-    double me = mu[(int64_t)wrap_el(x0 - 1, g.n0) * plane + o0];
+    T le = lam[(int64_t)wrap_el(x0 - 1, g.n0) * plane + o0];
+    T me = mu[(int64_t)wrap_el(x0 - 1, g.n0) * plane + o0];
     __syncthreads();
 
-    double carry[3][4];
+    T carry[3][4];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int k = 0; k < 4; ++k) carry[i][k] = 0.0;
+        for (int k = 0; k < 4; ++k) carry[i][k] = (T)0;
     double dot = 0.0;
     for (int j = 0; j <= nx; ++j) {
         const bool more = j + 2 <= nx + 1;
         if (more) fetch(j + 2);
-        double ln = 0.0, mn = 0.0;
+        T ln = 0, mn = 0;
         if (j + 1 <= nx) {
             const int64_t e = (int64_t)wrap_el(x0 + j, g.n0) * plane + o0;
             ln = lam[e];
             mn = mu[e];
         }
-        double U[3][8];
+        T U[3][8];
         const int sa = j % 3, sb = (j + 1) % 3;
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
@@ -312,13 +314,13 @@ __global__ void __launch_bounds__(256) k_el_march(ElDev E, ElGeom eg, const doub
             U[i][6] = Dl[sb][i][l0 + kElL];
             U[i][7] = Dl[sb][i][l0 + kElL + 1];
         }
-        const double dself[3] = {U[0][0], U[1][0], U[2][0]};
-        el_element(E, le * E.w8, me * E.w8, U);  // U becomes the corner forces
+        const T dself[3] = {U[0][0], U[1][0], U[2][0]};
+        el_element<T>(E, le * (T)E.w8, me * (T)E.w8, U);  // U becomes the corner forces
         // node plane j - 1 + x0: corners a = 0 of this voxel plus the carry
-        double own_f[3];
+        T own_f[3];
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            const double c1 = carry[i][1] + U[i][1], c2 = carry[i][2] + U[i][2], c3 = carry[i][3] + U[i][3];
+            const T c1 = carry[i][1] + U[i][1], c2 = carry[i][2] + U[i][2], c3 = carry[i][3] + U[i][3];
             own_f[i] = carry[i][0] + U[i][0];
             if (j >= 1) {
                 X[j & 1][i * 3 + 0][t] = c1;  // corner (0, 1): node (ly, lz + 1)
@@ -336,10 +338,10 @@ __global__ void __launch_bounds__(256) k_el_march(ElDev E, ElGeom eg, const doub
             const int64_t b = (int64_t)(x0 - 1 + j) * plane + o0;
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
-                const double y = own_f[i] + X[j & 1][i * 3 + 0][t - 1] + X[j & 1][i * 3 + 1][t - kElT] +
+                const T y = own_f[i] + X[j & 1][i * 3 + 0][t - 1] + X[j & 1][i * 3 + 1][t - kElT] +
                                  X[j & 1][i * 3 + 2][t - kElT - 1];
                 p[i * n + b] = y;
-                if (CG) dot += dself[i] * y;
+                if (CG) dot += (double)dself[i] * (double)y;
             }
         }
     }
@@ -522,26 +524,26 @@ int el_march_blocks(const Grid& g, int nrhs)
     return eg.tiles_x * eg.tiles_y * eg.tiles_z;
 }
 
-template <bool CG, bool HEAD>
-uno_status launch_el_apply(const ElDev& E, const Grid& g, const double* lam, const double* mu, int64_t lks,
-                           const double* s, const double* dold, double* dnew, double* p, double* part_dp,
-                           const CgIter& it, const double* part_rs, int np_rs, double* gam, int nrhs, hipStream_t st)
+template <typename T, bool CG, bool HEAD>
+uno_status launch_el_apply(const ElDev& E, const Grid& g, const T* lam, const T* mu, int64_t lks, const T* s,
+                           const T* dold, T* dnew, T* p, double* part_dp, const CgIter& it, const double* part_rs,
+                           int np_rs, double* gam, int nrhs, hipStream_t st)
 {
     const ElGeom eg = el_geom(g, nrhs);
-    uno_launch(CG ? UNO_KT_MATVEC : UNO_KT_APPLY, k_el_march<CG, HEAD>,
+    uno_launch(CG ? UNO_KT_MATVEC : UNO_KT_APPLY, k_el_march<T, CG, HEAD>,
                dim3(eg.tiles_x * eg.tiles_y * eg.tiles_z, nrhs), dim3(256), 0, st, E, eg, lam, mu, lks, s, dold,
                dnew, p, part_dp, it, part_rs, np_rs, gam);
     return hip_status(hipGetLastError());
 }
-template uno_status launch_el_apply<false, false>(const ElDev&, const Grid&, const double*, const double*, int64_t,
-                                                  const double*, const double*, double*, double*, double*,
-                                                  const CgIter&, const double*, int, double*, int, hipStream_t);
-template uno_status launch_el_apply<true, false>(const ElDev&, const Grid&, const double*, const double*, int64_t,
-                                                 const double*, const double*, double*, double*, double*,
-                                                 const CgIter&, const double*, int, double*, int, hipStream_t);
-template uno_status launch_el_apply<true, true>(const ElDev&, const Grid&, const double*, const double*, int64_t,
-                                                const double*, const double*, double*, double*, double*,
-                                                const CgIter&, const double*, int, double*, int, hipStream_t);
+#define UNO_EL_APPLY(T, CG, HEAD)                                                                               \
+    template uno_status launch_el_apply<T, CG, HEAD>(const ElDev&, const Grid&, const T*, const T*, int64_t,  \
+                                                     const T*, const T*, T*, T*, double*, const CgIter&,     \
+                                                     const double*, int, double*, int, hipStream_t);
+UNO_EL_APPLY(double, false, false)
+UNO_EL_APPLY(double, true, false)
+UNO_EL_APPLY(double, true, true)
+UNO_EL_APPLY(float, true, false)
+#undef UNO_EL_APPLY
 
 uno_status launch_el_inv_diag(const ElDev& E, const Grid& g, const double* lam, const double* mu, int64_t ks,
                               int nfields, double* dinv, hipStream_t st)

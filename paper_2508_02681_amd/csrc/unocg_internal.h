@@ -205,10 +205,10 @@ int el_march_blocks(const Grid& g, int nrhs);
 uno_status el_dev(const Grid& g, ElDev* out);
 void el_release_all();
 int el_blocks(const Grid& g);
-template <bool CG, bool HEAD>
-uno_status launch_el_apply(const ElDev& E, const Grid& g, const double* lam, const double* mu, int64_t lks,
-                           const double* s, const double* dold, double* dnew, double* p, double* part_dp,
-                           const CgIter& it, const double* part_rs, int np_rs, double* gam, int nrhs, hipStream_t st);
+template <typename T, bool CG, bool HEAD>
+uno_status launch_el_apply(const ElDev& E, const Grid& g, const T* lam, const T* mu, int64_t lks, const T* s,
+                           const T* dold, T* dnew, T* p, double* part_dp, const CgIter& it, const double* part_rs,
+                           int np_rs, double* gam, int nrhs, hipStream_t st);
 uno_status launch_el_inv_diag(const ElDev& E, const Grid& g, const double* lam, const double* mu, int64_t ks,
                               int nfields, double* dinv, hipStream_t st);
 uno_status launch_el_rhs(const ElDev& E, const Grid& g, const double* lam, const double* mu, const double* eps,

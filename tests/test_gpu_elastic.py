@@ -142,3 +142,33 @@ def test_el_uno_cg_matches_oracle(orc, uno, shape, M):
     Db = uno.el_effective_stiffness(T(lam), T(mu), loads, u)
     uj, _ = uno.el_pcg_solve(T(lam), T(mu), loads, rtol=1e-10)
     assert rel(Db, uno.el_effective_stiffness(T(lam), T(mu), loads, uj)) < 1e-8
+
+
+@pytest.mark.parametrize("shape,M", [((16, 16, 16), 4), ((12, 10, 9), 3)])
+def test_el_uno_cg_fp32_mode_matches_fp64_oracle(orc, uno, shape, M):
+    """UNO-CG in the FP32 mode (FP32 operator, preconditioner and direction;
+    FP64 residuals, reductions and stop test): every load's true FP64
+    residual within the tolerance, and the effective stiffness within 1e-5
+    of the FP64 oracle's (Jacobi-CG to 1e-10)."""
+    lam, mu = _lame(orc, shape, 95, 100.0)
+    th = _theta3(orc, M, 96)
+    P = uno.UnoPrecond.create_elastic(shape, M, th)
+    loads = np.eye(6)
+    u32, i32 = uno.el_pcg_solve(T(lam), T(mu), loads, kind="uno", precond=P, rtol=1e-8,
+                                op_dtype=torch.float32)
+    u64, i64 = uno.el_pcg_solve(T(lam), T(mu), loads, kind="uno", precond=P, rtol=1e-8)
+    print("el fp32", shape, [i["iters"] for i in i32], [i["iters"] for i in i64], flush=True)
+    for a in i32:
+        assert a["converged"] and a["true_rel_res"] <= 1e-8
+    sols = [orc.el_pcg(lam, mu, orc.el_rhs(lam, mu, loads[j]), "jacobi", rtol=1e-10)[0] for j in range(6)]
+    Do = orc.el_effective_stiffness(lam, mu, sols, loads)
+    D32 = uno.el_effective_stiffness(T(lam), T(mu), loads, u32)
+    assert rel(D32, Do) < 1e-5
+    assert rel(uno.el_effective_stiffness(T(lam), T(mu), loads, u64), Do) < 1e-7
+
+
+def test_el_fp32_mode_needs_uno(uno):
+    shape = (8, 8, 8)
+    lam = torch.ones(shape, dtype=torch.float64, device=DEV)
+    with pytest.raises(uno.UnoError):
+        uno.el_pcg_solve(lam, lam, np.eye(6)[:1], kind="jacobi", op_dtype=torch.float32)

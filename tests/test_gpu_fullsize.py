@@ -104,6 +104,13 @@ def test_el_128_six_loads_properties(orc, uno, el128):
     S = 0.5 * (Du + Du.T)
     assert np.linalg.eigvalsh(V - S).min() > -1e-6 * np.abs(V).max()
     assert np.linalg.eigvalsh(S - R).min() > -1e-6 * np.abs(V).max()
+    # the FP32 mode at the full size: true residuals within the tolerance,
+    # stiffness within 1e-5 of the FP64 Jacobi-CG result
+    u32, i32 = uno.el_pcg_solve(L, Mu, loads, kind="uno", precond=P, rtol=1e-6, op_dtype=torch.float32)
+    print("elastic 128^3 FP32 passes", [i["iters"] for i in i32], "FP64", [i["iters"] for i in iu], flush=True)
+    for a in i32:
+        assert a["converged"] and a["true_rel_res"] <= 1e-6
+    assert rel(uno.el_effective_stiffness(L, Mu, loads, u32), Dj) < 1e-5
 
 
 def test_many_problems_work_list(orc, uno):
