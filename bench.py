@@ -356,7 +356,8 @@ def many_record(uno, si, torch, dev):
         dt = time.perf_counter() - t
         dit = sum(n * sum(i["iters"] for i in inf) for n, inf in zip(dofs, infos))
         conv = all(i["converged"] for inf in infos for i in inf)
-        worst[kind + ("_fp32" if kw else "")] = max(i["true_rel_res"] for inf in infos for i in inf)
+        tag = kind + ("_fp32" if kw.get("op_dtype") is not None else "") + ("_graphs" if kw.get("use_graphs") else "")
+        worst[tag] = max(i["true_rel_res"] for inf in infos for i in inf)
         return dt, dit, conv, us
 
     run_many("uno")  # warm-up: workspaces, streams
@@ -365,6 +366,8 @@ def many_record(uno, si, torch, dev):
     f32 = dict(op_dtype=torch.float32, prec_dtype=torch.float32)
     run_many("uno", **f32)
     dtm, ditm, convm, _ = run_many("uno", **f32)
+    run_many("uno", use_graphs=True)  # warm-up: captured chunks
+    dtg, ditg, convg, _ = run_many("uno", use_graphs=True)
     torch.cuda.synchronize()
     t = time.perf_counter()
     for it in items:
@@ -380,13 +383,15 @@ def many_record(uno, si, torch, dev):
         "jac_cg_many": {"s": dtj, "solves_per_s": nsolve / dtj, "dof_iters_per_s": ditj / dtj, "converged": convj},
         "uno_cg_many_fp32": {"s": dtm, "solves_per_s": nsolve / dtm, "dof_iters_per_s": ditm / dtm,
                              "converged": convm, "note": "FP32 operator and preconditioner, FP64 reductions"},
+        "uno_cg_many_graphs": {"s": dtg, "solves_per_s": nsolve / dtg, "dof_iters_per_s": ditg / dtg,
+                               "converged": convg, "note": "passes replayed from captured hipGraphs of 8 passes"},
         "uno_cg_one_problem_at_a_time": {"s": dts, "solves_per_s": nsolve / dts},
         "speedup_many_vs_one_at_a_time": dts / dt,
         "true_rel_res_max": worst,
         "time_to_tol_speedup_uno_vs_jac": dtj / dt,
     }
-    log("many: UNO-CG %.3f s (%.0f solves/s), FP32 %.3f s, one at a time %.3f s, Jacobi-CG %.3f s" %
-        (dt, nsolve / dt, dtm, dts, dtj))
+    log("many: UNO-CG %.3f s (%.0f solves/s), graphs %.3f s, FP32 %.3f s, one at a time %.3f s, Jacobi-CG %.3f s" %
+        (dt, nsolve / dt, dtg, dtm, dts, dtj))
     return out
 
 
@@ -511,6 +516,7 @@ def parse():
     ap.add_argument("--M", type=int, default=0, help="mode parameter (0 = pick from a small sweep)")
     ap.add_argument("--jac-steps", type=int, default=4)
     ap.add_argument("--no-oracle-ref", action="store_true", help="skip the FP64 oracle reference of kappa_bar")
+    ap.add_argument("--no-autotune", action="store_true", help="operator shapes by rule instead of the autotuner")
     ap.add_argument("--no-calls", action="store_true", help="skip the standalone fe_apply / uno_precond_apply rooflines")
     ap.add_argument("--cpu-workers", type=int, default=16,
                     help="most host cores the oracle's all-core baseline uses (one solve per core)")
@@ -691,6 +697,13 @@ def main():
         torch.cuda.synchronize()
         return time.perf_counter() - t, all_its, kbs
 
+    # ---------------- operator shapes: the project's autotuner ----------------
+    tuned = {}
+    if not args.no_autotune:
+        for tag, dtp in (("f64", torch.float64), ("f32", torch.float32)):
+            tuned[tag] = uno.autotune_operator(SHAPE, nr_all, kappa_per_rhs=True, dtype=dtp)
+        log("autotuned operator march (64^3 x %d): %s" % (nr_all, tuned))
+
     # ---------------- timed: UNO-CG FP64 (headline) ----------------
     dt, its, kbs = timed("uno", prec, args.steps, args.warmup)
     ms_step = dt / args.steps * 1e3
@@ -703,8 +716,13 @@ def main():
     micro_t_solve = dtq / len(itsq) * 1e3
     dts, itss, _ = timed("uno", prec, 1, 1, mode="single")
     seq_t_solve = dts / len(itss) * 1e3
-    log("UNO-CG 3 loads per launch: %.3f ms per solve; one load at a time: %.3f ms per solve" %
-        (micro_t_solve, seq_t_solve))
+    dtsg, itssg, _ = timed("uno", prec, 1, 1, mode="single", use_graphs=True)
+    seq_t_solve_g = dtsg / len(itssg) * 1e3
+    dtg, itsg, _ = timed("uno", prec, max(1, args.steps // 2), 1, use_graphs=True)
+    all_t_solve_g = dtg / len(itsg) * 1e3
+    log("UNO-CG 3 loads per launch: %.3f ms per solve; one load at a time: %.3f ms per solve (graphs %.3f); "
+        "all %d together from graphs %.3f ms per solve" %
+        (micro_t_solve, seq_t_solve, seq_t_solve_g, nr_all, all_t_solve_g))
     # ---------------- Jacobi-CG on the same microstructures ----------------
     dtj, itsj, kbj = timed("jacobi", None, args.jac_steps, 1, tag="jac_cg")
     jac_t_solve = dtj / len(itsj) * 1e3
@@ -835,11 +853,13 @@ def main():
         "config": {"workload": "3D thermal 64^3 periodic hex8, spheres r 4-8 vf 0.25, kappa 1/100, "
                                "16 microstructures x 3 loads per step, solved together, UNO-CG to 1e-6 + effective tensors",
                    "grid": list(SHAPE), "loads_per_microstructure": 3, "solves_per_step": nr_all, "M": M,
-                   "train_pairs": len(F),
+                   "train_pairs": len(F), "operator_shape_autotuned": tuned,
                    "microstructures": len(kap_test)},
         "uno_cg": {"passes_mean": float(np.mean(its)), "ms_per_solve": uno_t_solve, "dof_iters_per_s": value,
                    "solves_per_launch": nr_all, "ms_per_solve_3_loads_per_launch": micro_t_solve,
-                   "ms_per_solve_one_at_a_time": seq_t_solve},
+                   "ms_per_solve_one_at_a_time": seq_t_solve,
+                   "ms_per_solve_one_at_a_time_graphs": seq_t_solve_g,
+                   "ms_per_solve_all_together_graphs": all_t_solve_g},
         "jac_cg": {"passes_mean": float(np.mean(itsj)), "ms_per_solve": jac_t_solve, "dof_iters_per_s": jac_rate},
         "fans_cg": {"passes_mean": float(np.mean(itsf)), "ms_per_solve": dtf / len(itsf) * 1e3},
         "uno_cg_fp32": {"passes_mean": float(np.mean(itsm)), "ms_per_solve": dtm / len(itsm) * 1e3,

@@ -158,6 +158,10 @@ typedef struct {
                                 1e2 since the last replacement, and reopens a load whose FP64 true
                                 residual is above its tolerance when every load has ended */
     int32_t graph_chunk;     /* iterations per host check; 0 = adaptive */
+    int32_t use_graphs;      /* 1: after the first 8 passes, run the passes as replays of a
+                                captured hipGraph of 8 passes (FP64, learned-mode or Jacobi /
+                                plain CG; kept per workspace, recaptured when a pointer or the
+                                preconditioner changes); results equal the eager launches' */
 } uno_solve_opts;
 
 typedef struct {
@@ -228,6 +232,21 @@ uno_status pcg_solve_batch(const uno_grid *grid, const uno_material *mat, int32_
 uno_status pcg_solve_noalloc(const uno_grid *grid, const uno_material *mat, const double *macro_load,
                              const double *rhs, double *u, const uno_solve_opts *opts, uno_solve_info *info,
                              double *res_hist, void *stream);
+
+/* Autotuner of the operator apply inside CG: a library utility, no passage of the paper.
+ * It times every candidate shape of the march kernel -- footprint
+ * width tz in {16, 32, 64} nodes along the contiguous axis (256 / tz rows)
+ * and planes per workgroup xb over the even splits of the first axis -- for
+ * nrhs right-hand sides of `grid` in precision dtype (UNO_F64 or UNO_F32)
+ * with one conductivity field per right-hand side (kappa_per_rhs = 1) or
+ * one shared, on synthetic operands it allocates on `stream`, and records
+ * the fastest; later solves with that (grid, nrhs, dtype, kappa_per_rhs) on
+ * this device use it (results then differ from the rule's shapes only in
+ * the rounding of the d.Ad partial sums).  tz, xb, us (host, nullable)
+ * receive the shape and its time per launch in microseconds.  Records are
+ * kept until uno_shutdown().  Synchronous. */
+uno_status uno_autotune_operator(const uno_grid *grid, int32_t nrhs, int32_t kappa_per_rhs, uno_dtype dtype,
+                                 void *stream, int32_t *tz, int32_t *xb, double *us);
 
 /* Effective conductivity (Sec. 5.1; the homogenized property handed back to
  * the macro scale, Sec. 1): for load j with gradient g_j (host loads,

@@ -45,7 +45,8 @@ class uno_material(ctypes.Structure):
 class uno_solve_opts(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("uno", ctypes.c_void_p), ("rtol", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("op_t", ctypes.c_int), ("prec_t", ctypes.c_int),
-                ("graph_chunk", ctypes.c_int32)]
+                ("graph_chunk", ctypes.c_int32),
+                ("use_graphs", ctypes.c_int32)]
 
 
 class uno_solve_info(ctypes.Structure):
@@ -99,6 +100,7 @@ def lib():
         "uno_timing_enable": ([i32], i),
         "uno_timing_read": ([P(f64), P(i64)], i),
         "uno_shutdown": ([], i),
+        "uno_autotune_operator": ([G, i32, i32, i, vp, P(i32), P(i32), P(f64)], i),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -270,7 +272,7 @@ class UnoPrecond:
 def pcg_solve(kappa: torch.Tensor, macro_load=None, rhs: torch.Tensor | None = None, u: torch.Tensor | None = None,
               kind="jacobi", precond: UnoPrecond | None = None, rtol=1e-6, max_iter=100000,
               op_dtype=torch.float64, prec_dtype=torch.float64, graph_chunk=0, history=False, L0=1.0,
-              noalloc=False):
+              noalloc=False, use_graphs=False):
     """Preconditioned CG (Algorithm 1/2).  Returns (u, info dict[, hist]).
     noalloc: the allocation-free entry point (workspace in the library's
     fixed device array; raises UnoError SHAPE when the problem does not fit)."""
@@ -286,6 +288,7 @@ def pcg_solve(kappa: torch.Tensor, macro_load=None, rhs: torch.Tensor | None = N
     o.op_t = _dt(op_dtype)
     o.prec_t = _dt(prec_dtype)
     o.graph_chunk = int(graph_chunk)
+    o.use_graphs = 1 if use_graphs else 0
     info = uno_solve_info()
     ml = None
     if macro_load is not None:
@@ -308,7 +311,7 @@ def pcg_solve(kappa: torch.Tensor, macro_load=None, rhs: torch.Tensor | None = N
     return u, d
 
 
-def _opts(kind, precond, rtol, max_iter, op_dtype, prec_dtype, graph_chunk):
+def _opts(kind, precond, rtol, max_iter, op_dtype, prec_dtype, graph_chunk, use_graphs=False):
     kinds = {"none": UNO_PREC_NONE, "jacobi": UNO_PREC_JACOBI, "uno": UNO_PREC_UNO}
     o = uno_solve_opts()
     o.kind = kinds[kind]
@@ -318,13 +321,14 @@ def _opts(kind, precond, rtol, max_iter, op_dtype, prec_dtype, graph_chunk):
     o.op_t = _dt(op_dtype)
     o.prec_t = _dt(prec_dtype)
     o.graph_chunk = int(graph_chunk)
+    o.use_graphs = 1 if use_graphs else 0
     return o
 
 
 def pcg_solve_batch(kappa: torch.Tensor, macro_loads=None, rhs: torch.Tensor | None = None,
                     u: torch.Tensor | None = None, kind="jacobi", precond: UnoPrecond | None = None, rtol=1e-6,
                     max_iter=100000, op_dtype=torch.float64, prec_dtype=torch.float64, graph_chunk=0,
-                    kappa_per_rhs=False, L0=1.0):
+                    kappa_per_rhs=False, L0=1.0, use_graphs=False):
     """nrhs solves carried together by every pass kernel: the load cases of
     one conductivity field (kappa: grid), or with kappa_per_rhs one field per
     right-hand side (kappa: nrhs x grid).  macro_loads: nrhs x d (host) or
@@ -344,7 +348,7 @@ def pcg_solve_batch(kappa: torch.Tensor, macro_loads=None, rhs: torch.Tensor | N
         u = torch.zeros((nrhs,) + shape, dtype=torch.float64, device=kappa.device)
     if tuple(u.shape) != (nrhs,) + shape:
         raise ValueError("u must be nrhs x grid")
-    o = _opts(kind, precond, rtol, max_iter, op_dtype, prec_dtype, graph_chunk)
+    o = _opts(kind, precond, rtol, max_iter, op_dtype, prec_dtype, graph_chunk, use_graphs)
     infos = (uno_solve_info * nrhs)()
     st = lib().pcg_solve_batch(
         ctypes.byref(g), ctypes.byref(_mat(kappa)), 1 if kappa_per_rhs else 0, nrhs,
@@ -496,7 +500,7 @@ def el_macro_rhs(lam: torch.Tensor, mu: torch.Tensor, strain, L0=1.0):
 
 def el_pcg_solve(lam: torch.Tensor, mu: torch.Tensor, strains, u: torch.Tensor | None = None, kind="jacobi",
                  rtol=1e-6, max_iter=100000, graph_chunk=0, lame_per_rhs=False, L0=1.0,
-                 precond: UnoPrecond | None = None, op_dtype=torch.float64):
+                 precond: UnoPrecond | None = None, op_dtype=torch.float64, use_graphs=False):
     """CG, Jacobi-CG or UNO-CG (kind "uno" with a UnoPrecond.create_elastic)
     for nrhs macroscopic Mandel strains (nrhs x 6).
     lam, mu: grid (shared) or nrhs x grid (lame_per_rhs).  op_dtype
@@ -508,7 +512,7 @@ def el_pcg_solve(lam: torch.Tensor, mu: torch.Tensor, strains, u: torch.Tensor |
     nrhs = e.shape[0]
     if u is None:
         u = torch.zeros((nrhs, 3) + shape, dtype=torch.float64, device=lam.device)
-    o = _opts(kind, precond, rtol, max_iter, op_dtype, op_dtype, graph_chunk)
+    o = _opts(kind, precond, rtol, max_iter, op_dtype, op_dtype, graph_chunk, use_graphs)
     infos = (uno_solve_info * nrhs)()
     _check(lib().el_pcg_solve(ctypes.byref(g), _dev(lam, "lambda", torch.float64), _dev(mu, "mu", torch.float64),
                               1 if lame_per_rhs else 0, nrhs, _dptr(e), _dev(u, "u", torch.float64), ctypes.byref(o),
@@ -535,7 +539,7 @@ class uno_problem(ctypes.Structure):
 
 
 def pcg_solve_many(problems, kind="uno", rtol=1e-6, max_iter=100000, graph_chunk=0, L0=1.0,
-                   op_dtype=torch.float64, prec_dtype=torch.float64):
+                   op_dtype=torch.float64, prec_dtype=torch.float64, use_graphs=False):
     """Solves many problems of uneven sizes in one call.  problems: list of
     dicts with "kappa" (device grid tensor), "loads" (nload x dim), optional
     "u" (nload x grid, zero-initialized if absent) and "precond" (UnoPrecond
@@ -564,7 +568,7 @@ def pcg_solve_many(problems, kind="uno", rtol=1e-6, max_iter=100000, graph_chunk
         keep += [loads, inf]
         us.append(u)
         infos.append(inf)
-    o = _opts(kind, None, rtol, max_iter, op_dtype, prec_dtype, graph_chunk)
+    o = _opts(kind, None, rtol, max_iter, op_dtype, prec_dtype, graph_chunk, use_graphs)
     st = lib().pcg_solve_many(n, arr, ctypes.byref(o), _stream())
     out = [[dict(iters=I.iters, converged=bool(I.converged), rel_res=I.rel_res, true_rel_res=I.true_rel_res)
             for I in inf] for inf in infos]
@@ -598,6 +602,17 @@ def uno_train_fit(shape, M, alpha: torch.Tensor, beta: torch.Tensor, L0=1.0) -> 
                                _dev(beta, "beta", torch.float64), th.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                th.size, _stream()), "uno_train_fit")
     return th
+
+
+def autotune_operator(shape, nrhs, kappa_per_rhs=False, dtype=torch.float64, L0=1.0) -> dict:
+    """Measures the operator march's shapes for nrhs right-hand sides of
+    this grid and records the fastest (used by later solves).  Returns
+    dict(tz, xb, us)."""
+    g = make_grid(shape, L0)
+    tz, xb, us = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_double(0.0)
+    _check(lib().uno_autotune_operator(ctypes.byref(g), int(nrhs), 1 if kappa_per_rhs else 0, _dt(dtype), _stream(),
+                                       ctypes.byref(tz), ctypes.byref(xb), ctypes.byref(us)), "uno_autotune_operator")
+    return dict(tz=tz.value, xb=xb.value, us=us.value)
 
 
 def timing_enable(which: int):

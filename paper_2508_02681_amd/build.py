@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libunocg.so")
 OBJDIR = os.path.join(HERE, "_build")
-SOURCES = ["api.hip", "stencil.hip", "fft.hip", "lowrank.hip", "cg.hip", "train.hip", "grad.hip", "elastic.hip", "train3.hip", "many.hip"]
+SOURCES = ["api.hip", "stencil.hip", "fft.hip", "lowrank.hip", "cg.hip", "train.hip", "grad.hip", "elastic.hip", "train3.hip", "many.hip", "autotune.hip"]
 ARCH = "gfx950"
 
 

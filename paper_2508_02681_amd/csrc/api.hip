@@ -3,6 +3,7 @@
 // mode table for periodic BC), the FANS table (Sec. 3.3.4), the effective
 // tensor (Sec. 5.1) and the closed-form c = 1 training fit (Sec. 4.4).
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -125,6 +126,18 @@ static bool pool_pop(hipEvent_t* e)
         return true;
     }
     return hipEventCreateWithFlags(e, hipEventDisableSystemFence) == hipSuccess;
+}
+
+bool ktimer_active()
+{
+    std::lock_guard<std::mutex> lk(g_tmu);
+    return g_twhich != UNO_KT_NONE;
+}
+
+uint64_t precond_serial()
+{
+    static std::atomic<uint64_t> next{1};
+    return next++;
 }
 
 bool ktimer_take(int fam, hipEvent_t* a, hipEvent_t* b)
@@ -385,6 +398,7 @@ uno_status uno_precond_create(const uno_grid* grid, int32_t M, const double* the
     p->rs_blocks = fft_c2r_blocks(g, p->plan);
     if (p->lr && lowrank_max_blocks(p->lr) > p->rs_blocks) p->rs_blocks = lowrank_max_blocks(p->lr);
     UNO_HIP(hipGetDevice(&p->device));
+    p->serial = precond_serial();
     *out = p;
     return UNO_OK;
 }
@@ -431,6 +445,7 @@ uno_status uno_precond_create_fans(const uno_grid* grid, double kappa_ref, uno_d
     p->nc = 1;
     p->rs_blocks = fft_c2r_blocks(g, p->plan);
     UNO_HIP(hipGetDevice(&p->device));
+    p->serial = precond_serial();
     *out = p;
     return UNO_OK;
 }
@@ -530,6 +545,7 @@ uno_status el_uno_precond_create(const uno_grid* grid, int32_t M, const double* 
     if (e != UNO_OK) { precond_free(p); return e; }
     p->rs_blocks = lowrank_max_blocks(p->lr);
     UNO_HIP(hipGetDevice(&p->device));
+    p->serial = precond_serial();
     *out = p;
     return UNO_OK;
 }
@@ -670,7 +686,7 @@ uno_status el_apply(const uno_grid* grid, const double* lambda, const double* mu
     if (e != UNO_OK) return e;
     CgIter none;
     memset(&none, 0, sizeof(none));
-    return launch_el_apply<false, false>(E, g, lambda, mu, 0, u, nullptr, nullptr, y, nullptr, none, nullptr, 0,
+    return launch_el_apply<double, false, false>(E, g, lambda, mu, 0, u, nullptr, nullptr, y, nullptr, none, nullptr, 0,
                                          nullptr, 1, S(stream));
 }
 
@@ -909,6 +925,7 @@ uno_status uno_shutdown(void)
         g_flux.clear();
     }
     el_release_all();
+    tune_release_all();
     return ws_release_all();
 }
 

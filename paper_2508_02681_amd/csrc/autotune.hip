@@ -1,0 +1,186 @@
+// Autotuner of the operator march (the CG pass's d = s + beta d_old,
+// p = A d, d.p kernel): for a grid, a number of right-hand sides, a vector
+// precision and a shared or per-right-hand-side conductivity field it
+// times every candidate shape -- footprint width tz in {16, 32, 64} (the
+// workgroup's 256 threads cover tz x 256/tz nodes) and the planes per
+// workgroup xb of the even splits of the marching axis -- on synthetic
+// operands and records the fastest; launch_tile then uses the record.
+#include <climits>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "unocg_internal.h"
+#include "reduce.h"
+#include "cg_ctl.h"
+#include "stencil_tile.h"
+
+namespace unocg {
+
+namespace {
+using TuneKey = std::tuple<int, int, int, int, int, int, int>;  // device, n0, n1, n2, nrhs, tsize, per-rhs kappa
+std::mutex g_tune_mu;
+std::map<TuneKey, MarchShape> g_tune;
+bool g_tune_any = false;
+
+TuneKey tune_key(int dev, const Grid& g, int nrhs, int tsize, bool per_rhs)
+{
+    return TuneKey{dev, g.n[0], g.n[1], g.n[2], nrhs, tsize, per_rhs ? 1 : 0};
+}
+
+__global__ void k_fill(int64_t n, double* __restrict__ a, double v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        a[i] = v;
+}
+
+template <typename T>
+uno_status sweep(const Grid& g, int nrhs, bool per_rhs, hipStream_t st, MarchShape* best, double* best_us)
+{
+    const int64_t n = g.total;
+    const int ps = march_max_blocks(g);
+    const size_t vb = sizeof(T) * (size_t)n * nrhs;
+    T *s = nullptr, *dold = nullptr, *kap = nullptr, *dnew = nullptr, *p = nullptr;
+    double *part_rs = nullptr, *part_dp = nullptr, *part_zero = nullptr, *part_out = nullptr, *gam = nullptr;
+    CgState* states = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    uno_status err = UNO_OK;
+    auto fail = [&](uno_status e) { if (err == UNO_OK) err = e; };
+    if (hipMalloc(&s, vb) != hipSuccess || hipMalloc(&dold, vb) != hipSuccess ||
+        hipMalloc(&kap, per_rhs ? vb : sizeof(T) * (size_t)n) != hipSuccess || hipMalloc(&dnew, vb) != hipSuccess ||
+        hipMalloc(&p, vb) != hipSuccess || hipMalloc(&part_rs, sizeof(double) * (size_t)ps * nrhs) != hipSuccess ||
+        hipMalloc(&part_dp, sizeof(double) * (size_t)ps * nrhs) != hipSuccess ||
+        hipMalloc(&part_zero, sizeof(double) * (size_t)ps * nrhs) != hipSuccess ||
+        hipMalloc(&part_out, sizeof(double) * (size_t)ps * nrhs) != hipSuccess ||
+        hipMalloc(&gam, sizeof(double) * 2 * (size_t)nrhs) != hipSuccess ||
+        hipMalloc(&states, sizeof(CgState) * (size_t)nrhs) != hipSuccess)
+        fail(UNO_ERR_NOMEM);
+    if (err == UNO_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) fail(UNO_ERR_DEVICE);
+    if (err == UNO_OK) {
+        // operands (their values do not change the time): zeros for the
+        // fields, r.s partials and gamma_0 of one so that every right-hand
+        // side runs pass 1 of its cycle
+        const int fb = 1024;
+        if (hipMemsetAsync(s, 0, vb, st) != hipSuccess || hipMemsetAsync(dold, 0, vb, st) != hipSuccess ||
+            hipMemsetAsync(kap, 0, per_rhs ? vb : sizeof(T) * (size_t)n, st) != hipSuccess)
+            fail(UNO_ERR_DEVICE);
+        hipLaunchKernelGGL(k_fill, dim3(fb), dim3(256), 0, st, (int64_t)ps * nrhs, part_rs, 1.0);
+        hipLaunchKernelGGL(k_fill, dim3(fb), dim3(256), 0, st, (int64_t)ps * nrhs, part_zero, 0.0);
+        hipLaunchKernelGGL(k_fill, dim3(fb), dim3(256), 0, st, (int64_t)2 * nrhs, gam, 1.0);
+        std::vector<CgState> hs(nrhs);
+        for (CgState& c : hs) {
+            memset(&c, 0, sizeof(c));
+            c.done = INT_MAX;
+            c.k_last = -1;
+            c.fail_iter = -1;
+        }
+        if (hipMemcpyAsync(states, hs.data(), sizeof(CgState) * nrhs, hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            fail(UNO_ERR_DEVICE);
+    }
+    CgIter it;
+    memset(&it, 0, sizeof(it));
+    it.k = 1;
+    it.k0 = 0;
+    it.st = states;
+    it.vs = n;
+    it.ps = ps;
+    it.hs = 2;
+    it.ks = per_rhs ? n : 0;
+    const MeanFree mf{part_rs, part_zero, part_out};
+    best->tz = 0;
+    *best_us = 1e30;
+    for (int tz = 16; tz <= 64 && err == UNO_OK; tz *= 2) {
+        if (256 / tz > g.n[1] || tz > g.n[2]) continue;
+        int last_xb = -1;
+        for (int tiles_x = 1; tiles_x <= (g.n[0] + 1) / 2 && err == UNO_OK; ++tiles_x) {
+            const MarchGeom m = march_geom_of(g, tz, (g.n[0] + tiles_x - 1) / tiles_x);
+            if (m.xb == last_xb) continue;
+            last_xb = m.xb;
+            const int64_t wg = (int64_t)m.tiles_x * m.tiles_y * m.tiles_z * nrhs;
+            if (wg < 256 && tiles_x < (g.n[0] + 1) / 2) continue;  // far too few workgroups for the chip
+            if (m.tiles_x * m.tiles_y * m.tiles_z > ps) continue;
+            auto launch = [&]() {
+                launch_march_near<T, true, false, true>(m, tz, g.dev, kap, s, dold, dnew, p, part_dp, it, part_rs, 1,
+                                                        gam, st, mf, nrhs);
+            };
+            launch();
+            launch();
+            if (hipEventRecord(e0, st) != hipSuccess) { fail(UNO_ERR_DEVICE); break; }
+            const int reps = 5;
+            for (int r = 0; r < reps; ++r) launch();
+            if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                fail(UNO_ERR_DEVICE);
+                break;
+            }
+            float ms = 0.0f;
+            if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { fail(UNO_ERR_DEVICE); break; }
+            const double us = 1e3 * ms / reps;
+            if (us < *best_us) {
+                *best_us = us;
+                best->tz = tz;
+                best->xb = m.xb;
+            }
+        }
+    }
+    if (err == UNO_OK && best->tz == 0) err = UNO_ERR_SHAPE;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    for (void* q : {(void*)s, (void*)dold, (void*)kap, (void*)dnew, (void*)p, (void*)part_rs, (void*)part_dp,
+                    (void*)part_zero, (void*)part_out, (void*)gam, (void*)states})
+        (void)hipFree(q);
+    return err;
+}
+}  // namespace
+
+bool march_tuned(const Grid& g, int nrhs, int tsize, bool kappa_per_rhs, MarchShape* out)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (!g_tune_any) return false;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    auto f = g_tune.find(tune_key(dev, g, nrhs, tsize, kappa_per_rhs));
+    if (f == g_tune.end()) return false;
+    *out = f->second;
+    return true;
+}
+
+void tune_release_all()
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.clear();
+    g_tune_any = false;
+}
+
+}  // namespace unocg
+
+using namespace unocg;
+
+extern "C" uno_status uno_autotune_operator(const uno_grid* grid, int32_t nrhs, int32_t kappa_per_rhs, uno_dtype dtype,
+                                            void* stream, int32_t* tz, int32_t* xb, double* us)
+{
+    Grid g;
+    uno_status e = make_grid(grid, &g);
+    if (e != UNO_OK) return e;
+    if (nrhs < 1 || nrhs > 256 || (kappa_per_rhs != 0 && kappa_per_rhs != 1)) return UNO_ERR_ARG;
+    if (dtype != UNO_F64 && dtype != UNO_F32) return UNO_ERR_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    MarchShape best;
+    double best_us = 0.0;
+    e = dtype == UNO_F64 ? sweep<double>(g, nrhs, kappa_per_rhs != 0, st, &best, &best_us)
+                         : sweep<float>(g, nrhs, kappa_per_rhs != 0, st, &best, &best_us);
+    if (e != UNO_OK) return e;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return UNO_ERR_DEVICE;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[tune_key(dev, g, nrhs, dtype == UNO_F64 ? 8 : 4, kappa_per_rhs != 0)] = best;
+        g_tune_any = true;
+    }
+    if (tz) *tz = best.tz;
+    if (xb) *xb = best.xb;
+    if (us) *us = best_us;
+    return UNO_OK;
+}

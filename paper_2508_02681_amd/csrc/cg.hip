@@ -139,6 +139,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_update(GridDev g, const T* __rest
                                                       const double* __restrict__ gam, double* __restrict__ part_rmax,
                                                       double* __restrict__ part_rs_next, double* __restrict__ part_ss_next)
 {
+    resolve_pass(it);
     __shared__ double slots[kBlock / 64];
     if (blockIdx.y > 0) {  // right-hand side blockIdx.y of a batch
         const int64_t vo = (int64_t)blockIdx.y * it.vs, po = (int64_t)blockIdx.y * it.ps;
@@ -214,8 +215,20 @@ __global__ void __launch_bounds__(kBlock) k_cg_update(GridDev g, const T* __rest
 // convergence test after the last pass of a chunk (one workgroup)
 __global__ void __launch_bounds__(kBlock) k_cg_check(CgIter it)
 {
+    resolve_pass(it);
     __shared__ double slots[kBlock / 64];
     (void)head_check(rhs_iter(it), slots);
+}
+
+// device pass index of graph-captured chunks: set before a series of
+// replays, advanced by the last node of each replay
+__global__ void k_set_pass(int* kdev, int k)
+{
+    if (threadIdx.x == 0) *kdev = k;
+}
+__global__ void k_advance_pass(int* kdev, int by)
+{
+    if (threadIdx.x == 0) *kdev += by;
 }
 
 // r = f - y
@@ -423,7 +436,26 @@ struct Workspace {
     double* hist = nullptr;
     double* gam = nullptr;
     int hist_cap = 0;
+    // captured chunks of passes (graph mode): the device pass index they
+    // read, the pass index kernels are recorded against while capturing, and
+    // the instantiated graphs with the arguments they were captured with
+    int* kdev = nullptr;
+    const int* capture_kdev = nullptr;
+    hipStream_t capture_stream = nullptr;
+    struct Graph {
+        std::vector<int64_t> key;
+        hipGraphExec_t exec;
+    };
+    std::vector<Graph> graphs;
 };
+
+// kernel arguments recorded in a workspace's graphs are stale once a buffer
+// of the workspace has been reallocated
+void ws_drop_graphs(Workspace* w)
+{
+    for (auto& gr : w->graphs) (void)hipGraphExecDestroy(gr.exec);
+    w->graphs.clear();
+}
 
 std::vector<Workspace*> g_ws;
 std::mutex g_ws_mu;
@@ -445,6 +477,9 @@ void ws_free_vectors(Workspace* w)
 
 void ws_free(Workspace* w)
 {
+    ws_drop_graphs(w);
+    (void)hipFree(w->kdev);
+    if (w->capture_stream) (void)hipStreamDestroy(w->capture_stream);
     ws_free_vectors(w);
     (void)hipFree(w->kap32);
     (void)hipFree(w->part);
@@ -501,6 +536,7 @@ uno_status ws_get(const Grid& g, const FftPlan* plan, const LowRankPlan* lr, int
     }
     *lease = std::unique_lock<std::mutex>(w->mu);
     if (nrhs > w->nrhs_cap) {
+        ws_drop_graphs(w);
         ws_free_vectors(w);
         const size_t vb = sizeof(double) * (size_t)g.total * nrhs;
         bool ok = hipMalloc(&w->f, vb) == hipSuccess && hipMalloc(&w->r, vb) == hipSuccess &&
@@ -525,14 +561,17 @@ uno_status ws_get(const Grid& g, const FftPlan* plan, const LowRankPlan* lr, int
         w->npart = w->hist_cap = 0;
         w->nrhs_cap = nrhs;
     }
+    if (!w->kdev && hipMalloc(&w->kdev, sizeof(int)) != hipSuccess) return UNO_ERR_NOMEM;
     const int need = ws_npart(g, w->nbr, extra_parts);
     if (need > w->npart) {
+        ws_drop_graphs(w);
         (void)hipFree(w->part);
         w->part = nullptr;
         if (hipMalloc(&w->part, sizeof(double) * 8 * (size_t)need * w->nrhs_cap) != hipSuccess) return UNO_ERR_NOMEM;
         w->npart = need;
     }
     if (plan && plan->nspec > w->nspec) {
+        ws_drop_graphs(w);
         (void)hipFree(w->spec);
         w->spec = nullptr;
         if (hipMalloc(&w->spec, sizeof(double2) * plan->nspec) != hipSuccess) return UNO_ERR_NOMEM;
@@ -542,6 +581,7 @@ uno_status ws_get(const Grid& g, const FftPlan* plan, const LowRankPlan* lr, int
         int64_t ngp = 0, nh = 0;
         lowrank_scratch_size(lr, &ngp, &nh);
         if (ngp != w->lr_ngp || nh != w->lr_nh || w->lr_cap < w->nrhs_cap) {
+            ws_drop_graphs(w);
             (void)hipFree(w->lr_gp);
             (void)hipFree(w->lr_h);
             w->lr_gp = w->lr_h = nullptr;
@@ -555,6 +595,7 @@ uno_status ws_get(const Grid& g, const FftPlan* plan, const LowRankPlan* lr, int
         }
     }
     if (hist_need > w->hist_cap) {
+        ws_drop_graphs(w);
         (void)hipFree(w->hist);
         (void)hipFree(w->gam);
         w->hist = w->gam = nullptr;
@@ -627,6 +668,7 @@ CgIter iter_of(Workspace* w, const Parts& P, int k, int k0, double rtol, int his
     it.ps = w->npart;
     it.hs = w->hist_cap;
     it.ks = ks;
+    it.kdev = w->capture_kdev;
     return it;
 }
 
@@ -747,11 +789,63 @@ static void replace_residual(const Grid& g, Workspace* w, const double* kappa64,
 // ended, a load whose true residual is still above its tolerance (the
 // recursive residual of the last cycle drifts from it by the FP32
 // operator's rounding) is reopened from that residual.
+// Graph mode (key non-empty): after the first chunk, passes run as replays
+// of one captured chunk of kGraphPasses passes (recorded once per
+// workspace and key, the key holding every argument the passes are
+// recorded with besides the workspace's own buffers); its kernels read the
+// index of the chunk's first pass from w->kdev, which the last node
+// advances.  Chunks then start at even pass indices, so the buffers chosen
+// by pass parity are those of the recorded offsets.
+constexpr int kGraphPasses = 8;
+
+template <class Pass>
+static uno_status graph_exec(Workspace* w, const std::vector<int64_t>& key, Pass pass, hipStream_t st,
+                             hipGraphExec_t* out)
+{
+    for (auto& gr : w->graphs)
+        if (gr.key == key) {
+            *out = gr.exec;
+            return UNO_OK;
+        }
+    if (w->graphs.size() >= 8) {  // a few live (grid, operand) combinations per stream
+        (void)hipGraphExecDestroy(w->graphs.front().exec);
+        w->graphs.erase(w->graphs.begin());
+    }
+    // recorded on a stream of the workspace's own (the caller's may be the
+    // null stream, which cannot be captured); replayed on the caller's
+    if (!w->capture_stream) UNO_HIP(hipStreamCreateWithFlags(&w->capture_stream, hipStreamNonBlocking));
+    hipStream_t cs = w->capture_stream;
+    hipGraph_t graph = nullptr;
+    UNO_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    w->capture_kdev = w->kdev;
+    uno_status e = UNO_OK;
+    // recorded at offsets 0 .. kGraphPasses - 1 with k0 = -1: every captured
+    // pass lies past the first pass of its cycle
+    for (int j = 0; j < kGraphPasses && e == UNO_OK; ++j) e = pass(j, -1, cs);
+    if (e == UNO_OK) hipLaunchKernelGGL(k_advance_pass, dim3(1), dim3(64), 0, cs, w->kdev, kGraphPasses);
+    w->capture_kdev = nullptr;
+    const hipError_t ec = hipStreamEndCapture(cs, &graph);
+    if (e != UNO_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return e;
+    }
+    UNO_HIP(ec);
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    UNO_HIP(ei);
+    w->graphs.push_back(Workspace::Graph{key, exec});
+    *out = exec;
+    return UNO_OK;
+}
+
 template <class Pass, class Check, class Residual, class Start, class TrueRes>
 static uno_status run_chunks(Workspace* w, const uno_solve_opts* o, int nrhs, bool restarts, hipStream_t st,
-                             Pass pass, Check check, Residual residual, Start start, TrueRes true_res, int* k_end)
+                             Pass pass, Check check, Residual residual, Start start, TrueRes true_res, int* k_end,
+                             const std::vector<int64_t>& graph_key = {})
 {
     const int chunk0 = o->graph_chunk > 0 ? o->graph_chunk : 8;
+    const bool graphs = !graph_key.empty() && w->kdev && !restarts && chunk0 % 2 == 0;
     int k = 0, k0 = 0, chunk = chunk0;
     std::vector<int> prev_k(nrhs, -1);
     std::vector<double> prev_r(nrhs, -1.0);
@@ -765,8 +859,21 @@ static uno_status run_chunks(Workspace* w, const uno_solve_opts* o, int nrhs, bo
     uno_status e = UNO_OK;
     for (;;) {
         if (chunk > o->max_iter - k) chunk = o->max_iter - k;
-        for (int c = 0; c < chunk; ++c, ++k) {
-            e = pass(k, k0);
+        int c = 0;
+        if (graphs && k >= chunk0) {
+            const int m = chunk / kGraphPasses;
+            if (m > 0) {
+                hipGraphExec_t exec;
+                if ((e = graph_exec(w, graph_key, pass, st, &exec)) != UNO_OK) return e;
+                hipLaunchKernelGGL(k_set_pass, dim3(1), dim3(64), 0, st, w->kdev, k);
+                UNO_HIP(hipGetLastError());
+                for (int r = 0; r < m; ++r) UNO_HIP(hipGraphLaunch(exec, st));
+                c = m * kGraphPasses;
+                k += c;
+            }
+        }
+        for (; c < chunk; ++c, ++k) {
+            e = pass(k, k0, st);
             if (e != UNO_OK) return e;
         }
         check(k, k0);
@@ -847,6 +954,7 @@ static uno_status run_chunks(Workspace* w, const uno_solve_opts* o, int nrhs, bo
                 if (nx > next) next = nx;
             }
             chunk = next < 2 ? 2 : (next > 256 ? 256 : next);
+            if (graphs) chunk = (chunk + kGraphPasses - 1) / kGraphPasses * kGraphPasses;
         }
         for (int b = 0; b < nrhs; ++b) {
             prev_k[b] = w->host_state[b].k_last;
@@ -904,8 +1012,8 @@ static uno_status pcg_loop(const Grid& g, Workspace* w, const double* kappa64, c
     };
     uno_status e = start(1, 0);
     if (e != UNO_OK) return e;
-    auto pass = [&](int k, int k0) {
-        return enqueue_pass<T>(g, w, o->kind, pc, kappa, ks, u, k, k0, o->rtol, hist_len, nrhs, st);
+    auto pass = [&](int k, int k0, hipStream_t sp) {
+        return enqueue_pass<T>(g, w, o->kind, pc, kappa, ks, u, k, k0, o->rtol, hist_len, nrhs, sp);
     };
     auto check = [&](int k, int k0) {
         const CgIter it = iter_of(w, P, k, k0, o->rtol, hist_len, np_update, ks);
@@ -918,7 +1026,14 @@ static uno_status pcg_loop(const Grid& g, Workspace* w, const double* kappa64, c
         hipLaunchKernelGGL(k_resid_final_b, dim3(1, nrhs), dim3(kBlock), 0, st, (const double*)P.rs[0],
                            (const double*)P.rs[1], nb, w->state, w->npart);
     };
-    return run_chunks(w, o, nrhs, restarts, st, pass, check, residual, start, true_res, k_end);
+    std::vector<int64_t> key;
+    if (o->use_graphs && !restarts && !ktimer_active() && (!pc || lowrank)) {
+        int64_t rt;
+        memcpy(&rt, &o->rtol, sizeof(rt));
+        key = {1, (int64_t)sizeof(T), o->kind, pc ? (int64_t)pc->serial : 0, pc ? pc->path : -1, nrhs, ks,
+               (int64_t)(uintptr_t)kappa, (int64_t)(uintptr_t)kappa64, (int64_t)(uintptr_t)u, hist_len, rt};
+    }
+    return run_chunks(w, o, nrhs, restarts, st, pass, check, residual, start, true_res, k_end, key);
 }
 
 static uno_status pcg_run_ws(const Grid& g, Workspace* w, bool may_alloc, const double* kappa, int64_t ks, int nrhs,
@@ -999,6 +1114,7 @@ static uno_status pcg_run_ws(const Grid& g, Workspace* w, bool may_alloc, const 
         const int nf = ks ? nrhs : 1;
         if (w->kap32_cap < nf) {
             if (!may_alloc) return UNO_ERR_SHAPE;
+            ws_drop_graphs(w);
             (void)hipFree(w->kap32);
             w->kap32 = nullptr;
             w->kap32_cap = 0;
@@ -1138,35 +1254,35 @@ static uno_status el_loop(const ElDev& E, const Grid& g, const GridDev& gd, Work
     if (e != UNO_OK) return e;
     // UNO flow per pass: [B (head) + C: s = P r, r.s] -> [d = s + beta d, p = A d, d.p]
     // -> [update + pass A of the next pass]
-    auto pass = [&](int k, int k0) -> uno_status {
+    auto pass = [&](int k, int k0, hipStream_t sp) -> uno_status {
         CgIter it = iter_of(w, P, k, k0, o->rtol, hist_len, np_update, dks);
         T* dold = (T*)w->d[k & 1];
         T* dnew = (T*)w->d[(k + 1) & 1];
         if (pc) {
             int np_rs = 0;
-            uno_status e2 = lowrank_finish<T>(pc->lr, w->r, sv, &it, &np_rs, bt, st);
+            uno_status e2 = lowrank_finish<T>(pc->lr, w->r, sv, &it, &np_rs, bt, sp);
             if (e2 != UNO_OK) return e2;
             e2 = launch_el_apply<T, true, false>(E, g, lamT, muT, lks, sv, dold, dnew, pv, P.dp, it, P.rs[k & 1],
-                                                 np_rs, w->gam, nrhs, st);
+                                                 np_rs, w->gam, nrhs, sp);
             if (e2 != UNO_OK) return e2;
             return lowrank_update_forward<T>(pc->lr, w->r, u, (const T*)dnew, (const T*)pv, it, P.dp,
-                                             el_march_blocks(g, nrhs), w->gam, P.rmax, nullptr, bt, st);
+                                             el_march_blocks(g, nrhs), w->gam, P.rmax, nullptr, bt, sp);
         }
         if constexpr (sizeof(T) == sizeof(double)) {
             uno_status e2 = launch_el_apply<double, true, true>(E, g, lam, mu, lks, w->s, (const double*)dold,
                                                                 (double*)dnew, w->p, P.dp, it, P.rs[k & 1], nb,
-                                                                w->gam, nrhs, st);
+                                                                w->gam, nrhs, sp);
             if (e2 != UNO_OK) return e2;
             const int np_dp = el_march_blocks(g, nrhs);
             double* rs_next = P.rs[(k + 1) & 1];
             double* ss_next = P.ss[(k + 1) & 1];
             const dim3 grid(nb, nrhs);
             if (o->kind == UNO_PREC_JACOBI)
-                uno_launch(UNO_KT_UPDATE, k_cg_update<double, 1>, grid, dim3(kBlock), 0, st, gd,
+                uno_launch(UNO_KT_UPDATE, k_cg_update<double, 1>, grid, dim3(kBlock), 0, sp, gd,
                            (const double*)w->dinv, w->r, u, (const double*)dnew, (const double*)w->p, w->s, it,
                            (const double*)P.dp, np_dp, (const double*)w->gam, P.rmax, rs_next, ss_next);
             else
-                uno_launch(UNO_KT_UPDATE, k_cg_update<double, 0>, grid, dim3(kBlock), 0, st, gd,
+                uno_launch(UNO_KT_UPDATE, k_cg_update<double, 0>, grid, dim3(kBlock), 0, sp, gd,
                            (const double*)w->dinv, w->r, u, (const double*)dnew, (const double*)w->p, w->s, it,
                            (const double*)P.dp, np_dp, (const double*)w->gam, P.rmax, rs_next, ss_next);
             return hip_status(hipGetLastError());
@@ -1188,7 +1304,15 @@ static uno_status el_loop(const ElDev& E, const Grid& g, const GridDev& gd, Work
         hipLaunchKernelGGL(k_resid_final_b, dim3(1, nrhs), dim3(kBlock), 0, st, (const double*)P.rs[0],
                            (const double*)P.rs[1], nb, w->state, w->npart);
     };
-    return run_chunks(w, o, nrhs, restarts, st, pass, check, residual, start, true_res, k_end);
+    std::vector<int64_t> key;
+    if (o->use_graphs && !restarts && !ktimer_active()) {
+        int64_t rt;
+        memcpy(&rt, &o->rtol, sizeof(rt));
+        key = {2, (int64_t)sizeof(T), o->kind, pc ? (int64_t)pc->serial : 0, nrhs, lks, (int64_t)(uintptr_t)lam,
+               (int64_t)(uintptr_t)mu, (int64_t)(uintptr_t)lamT, (int64_t)(uintptr_t)muT, (int64_t)(uintptr_t)u,
+               hist_len, rt};
+    }
+    return run_chunks(w, o, nrhs, restarts, st, pass, check, residual, start, true_res, k_end, key);
 }
 
 uno_status pcg_run_el(const Grid& g, const double* lam, const double* mu, int64_t lks, int nrhs, const double* eps6,
@@ -1238,6 +1362,7 @@ uno_status pcg_run_el(const Grid& g, const double* lam, const double* mu, int64_
         // FP32 Lame fields: lambda then mu, one pair per field
         const int nf = lks ? nrhs : 1;
         if (w->kap32_cap < nf) {  // a field of the 3n-vector workspace holds both (2n <= 3n floats)
+            ws_drop_graphs(w);
             (void)hipFree(w->kap32);
             w->kap32 = nullptr;
             w->kap32_cap = 0;

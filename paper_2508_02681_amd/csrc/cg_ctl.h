@@ -32,7 +32,17 @@ struct CgIter {
     int ps;
     int hs;
     int64_t ks;   // stride between the conductivity (and Jacobi) fields: 0 when shared
+    // graph-captured passes: k is the offset of the pass within the captured
+    // chunk and *kdev (device) the index of the chunk's first pass, set
+    // before the chunk runs (null: k is the pass index itself)
+    const int* kdev;
 };
+
+// The pass index of a kernel's CG pass (first statement of every pass kernel).
+__device__ __forceinline__ void resolve_pass(CgIter& it)
+{
+    if (it.kdev) it.k += *it.kdev;
+}
 
 // The control of right-hand side blockIdx.y (state, partials, history).
 __device__ __forceinline__ CgIter rhs_iter(CgIter c)

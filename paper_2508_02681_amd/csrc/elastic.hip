@@ -189,6 +189,7 @@ __global__ void __launch_bounds__(256) k_el_march(ElDev E, ElGeom eg, const T* _
                                                   double* __restrict__ part_dp, CgIter it,
                                                   const double* __restrict__ part_rs, int np_rs, double* gam)
 {
+    resolve_pass(it);
     __shared__ T Dl[3][3][kElL * kElL];  // ring slot, component, node
     __shared__ T X[2][9][256];           // exchanged corner forces
     __shared__ double slots[4];

@@ -73,6 +73,7 @@ __global__ void __launch_bounds__(256) k_lr_fwd(LowRankDev L, int ya, int rb, do
                                                 const double* __restrict__ gam, double* __restrict__ part_rmax,
                                                 double* __restrict__ part_rr)
 {
+    resolve_pass(it);
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double slots[4];
     if (blockIdx.y > 0) {  // right-hand side blockIdx.y of a batch
@@ -287,6 +288,7 @@ __global__ void __launch_bounds__(256) k_lr_mid(LowRankDev L, int nch, const dou
                                                 const double2* __restrict__ Gp, double2* __restrict__ H, CgIter it,
                                                 double* __restrict__ part_corr)
 {
+    resolve_pass(it);
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double slots[4];
     if (blockIdx.y > 0) {
@@ -373,6 +375,7 @@ __global__ void __launch_bounds__(256) k_lr_mid(LowRankDev L, int nch, const dou
 __global__ void __launch_bounds__(256) k_lr_mid3(LowRankDev L, int nch, int cb, const double* __restrict__ C6,
                                                  const double2* __restrict__ Gp, double2* __restrict__ H, CgIter it)
 {
+    resolve_pass(it);
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double slots[4];
     if (blockIdx.y > 0) {
@@ -471,6 +474,7 @@ template <bool CG, typename TS>
 __global__ void __launch_bounds__(256) k_lr_inv_pairs(LowRankDev L, int y_chunk, const double* __restrict__ r,
                                                       const double2* __restrict__ H, TS* __restrict__ s, CgIter it)
 {
+    resolve_pass(it);
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double slots[4];
     if (blockIdx.y > 0) {
@@ -611,6 +615,7 @@ template <bool CG, typename TS, int NC>
 __global__ void __launch_bounds__(256) k_lr_inv(LowRankDev L, int y_chunk, const double* __restrict__ r,
                                                 const double2* __restrict__ H, TS* __restrict__ s, CgIter it)
 {
+    resolve_pass(it);
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double slots[4];
     if (blockIdx.y > 0) {
@@ -782,6 +787,7 @@ __global__ void __launch_bounds__(256) k_lr_tile(GridDev g, TileGeom tg, LowRank
                                                  double* __restrict__ p, double* __restrict__ part_dp, CgIter it,
                                                  LrTileArgs a, double* gam)
 {
+    resolve_pass(it);
     constexpr int TY = 256 / TZ;
     constexpr int DX = TX + 2, DY = TY + 2, DZ = TZ + 2;
     constexpr int KX = TX + 1, KY = TY + 1, KZ = TZ + 1;

@@ -146,6 +146,7 @@ __global__ void __launch_bounds__(256) k_stencil_march(GridDev g, MarchGeom mg, 
                                                        const double* __restrict__ part_rs, int np_rs, double* gam,
                                                        MeanFree mf)
 {
+    resolve_pass(it);
     constexpr bool MF = CG && sizeof(T) == 4;
     constexpr int TY = 256 / TZ;
     constexpr int DY = TY + 2, DZ = TZ + 2, KY = TY + 1, KZ = TZ + 1;
@@ -391,37 +392,69 @@ inline bool tile_near(const TileChoice& c, const GridDev& g)
     return c.tx <= g.n0 && 256 / c.tz <= g.n1 && c.tz <= g.n2;
 }
 
-// Footprint width of the operator march: whole 64-node rows where the
-// contiguous axis allows (measured: 64 x 4 footprints beat 32 x 8 by 3 % at
-// 64^3 x 48 and by 1 % at 192^3 x 3), else 32 or 16.
-inline int march_tz(const Grid& g) { return g.n[2] >= 64 ? 64 : (g.n[2] >= 24 ? 32 : 16); }
+// Operator march shape of a (grid, right-hand sides, vector precision,
+// conductivity field per right-hand side or shared): the
+// footprint width tz (16, 32 or 64) and the planes per workgroup xb (>= 2,
+// or the whole axis when it is shorter).  uno_autotune_operator measures the
+// candidates and records the fastest (autotune.hip); without a record the
+// rules below apply.
+struct MarchShape {
+    int tz, xb;
+};
+bool march_tuned(const Grid& g, int nrhs, int tsize, bool kappa_per_rhs, MarchShape* out);
 
-// Upper bound of the marching kernel's workgroups per right-hand side (xb >= 2).
+// Footprint width by rule: whole 64-node rows where the contiguous axis
+// allows (measured: 64 x 4 footprints beat 32 x 8 by 3 % at 64^3 x 48 and by
+// 1 % at 192^3 x 3), else 32 or 16.
+inline int march_tz_rule(const Grid& g) { return g.n[2] >= 64 ? 64 : (g.n[2] >= 24 ? 32 : 16); }
+
+// Upper bound of the marching kernel's workgroups per right-hand side over
+// every footprint width (xb >= 2).
 inline int march_max_blocks(const Grid& g)
 {
-    const int tz = march_tz(g), ty = 256 / tz;
     const int tx = g.n[0] < 2 ? 1 : (g.n[0] + 1) / 2;
-    return tx * ((g.n[1] + ty - 1) / ty) * ((g.n[2] + tz - 1) / tz);
+    int most = 0;
+    for (int tz = 16; tz <= 64; tz *= 2) {
+        const int ty = 256 / tz;
+        const int b = tx * ((g.n[1] + ty - 1) / ty) * ((g.n[2] + tz - 1) / tz);
+        if (b > most) most = b;
+    }
+    return most;
 }
 
-// Marching geometry: TY x TZ footprints and the planes split evenly into
-// chunks of xb >= 2 so that a launch has about 2048 workgroups or more
-// (measured at 64^3 x 48: 2304 workgroups of 22 planes 111 us, 6144 of 8
-// planes 111 us, 4608 of 12 and 3072 of 16 planes 118-119 us, 1536 of 32
-// planes 127 us; 192^3 x 3: 199-204 us from 1728 to 6912 workgroups).
-inline MarchGeom march_geom(const Grid& g, int nrhs)
+// Marching geometry for footprint width tz and planes per workgroup xb0:
+// the planes split evenly into chunks of at most xb0.
+inline MarchGeom march_geom_of(const Grid& g, int tz, int64_t xb0)
 {
-    const int tz = march_tz(g), ty = 256 / tz;
+    const int ty = 256 / tz;
     MarchGeom m;
     m.tiles_y = (g.n[1] + ty - 1) / ty;
     m.tiles_z = (g.n[2] + tz - 1) / tz;
-    const int64_t yz = (int64_t)m.tiles_y * m.tiles_z * nrhs;
-    int64_t xb = (g.n[0] * yz + 2047) / 2048;
+    int64_t xb = xb0;
     if (xb < 2) xb = 2;
     if (xb > g.n[0]) xb = g.n[0];
     m.tiles_x = (int)((g.n[0] + xb - 1) / xb);
     m.xb = (g.n[0] + m.tiles_x - 1) / m.tiles_x;  // even split
     return m;
+}
+
+// Marching geometry of a launch: the recorded shape, else TY x TZ footprints
+// and the planes split evenly into chunks of xb >= 2 so that a launch has
+// about 2048 workgroups or more (measured at 64^3 x 48: 2304 workgroups of
+// 22 planes 111 us, 6144 of 8 planes 111 us, 4608 of 12 and 3072 of 16
+// planes 118-119 us, 1536 of 32 planes 127 us; 192^3 x 3: 199-204 us from
+// 1728 to 6912 workgroups).
+inline MarchGeom march_geom(const Grid& g, int nrhs, int tsize, bool kappa_per_rhs, int* tz_out)
+{
+    MarchShape sh;
+    if (march_tuned(g, nrhs, tsize, kappa_per_rhs, &sh)) {
+        *tz_out = sh.tz;
+        return march_geom_of(g, sh.tz, sh.xb);
+    }
+    const int tz = march_tz_rule(g), ty = 256 / tz;
+    *tz_out = tz;
+    const int64_t yz = (int64_t)((g.n[1] + ty - 1) / ty) * ((g.n[2] + tz - 1) / tz) * nrhs;
+    return march_geom_of(g, tz, (g.n[0] * yz + 2047) / 2048);
 }
 
 template <typename T, bool CG, bool HEAD, bool NEAR>
@@ -455,8 +488,8 @@ inline int launch_tile(const Grid& g, const T* kappa, const T* s, const T* dold,
                        const CgIter& it, const double* part_rs, int np_rs, double* gam, hipStream_t st,
                        const MeanFree& mf = MeanFree{nullptr, nullptr, nullptr}, int nrhs = 1)
 {
-    const int tz = march_tz(g);
-    const MarchGeom m = march_geom(g, nrhs);
+    int tz = 0;
+    const MarchGeom m = march_geom(g, nrhs, (int)sizeof(T), it.ks != 0, &tz);
     const bool near = 256 / tz <= g.n[1] && tz <= g.n[2];
     if (near)
         launch_march_near<T, CG, HEAD, true>(m, tz, g.dev, kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam,

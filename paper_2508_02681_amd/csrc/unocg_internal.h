@@ -51,6 +51,9 @@ template <> struct cplx_t<float> { using type = float2; };
 // launch carries start/stop events recorded around the dispatch itself
 // (hipExtLaunchKernelGGL), otherwise it is a plain launch.
 bool ktimer_take(int fam, hipEvent_t* a, hipEvent_t* b);
+bool ktimer_active();  // a kernel family is being timed (no stream capture then)
+void tune_release_all();  // forget the recorded operator shapes
+uint64_t precond_serial();
 void ktimer_push(hipEvent_t a, hipEvent_t b);
 
 // Workgroups of a launch go to the 8 XCDs in turn (workgroup i to XCD
@@ -233,6 +236,7 @@ struct uno_precond {
     int nc;               // nodal DOF the preconditioner acts on (1, or 3 for elasticity)
     int rs_blocks;        // most r.s partials any apply path writes
     int device;
+    uint64_t serial;      // distinct for every preconditioner the process creates (keys captured graphs)
 };
 
 // apply path of a preconditioner in FP64
