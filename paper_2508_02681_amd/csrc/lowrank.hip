@@ -283,6 +283,32 @@ __device__ __forceinline__ double2 horner_eo(const double2* a, int stride, int m
     return make_double2(er + (orr * w.x - oi * w.y), ei + (orr * w.y + oi * w.x));
 }
 
+// sum_{c < nch} src[c stride], added in the order c = 0, 1, ...; the loads
+// are issued four at a time so that they are in flight together
+__device__ __forceinline__ double2 chunk_sum(const double2* __restrict__ src, int nch, int64_t stride)
+{
+    double re = 0.0, im = 0.0;
+    int c = 0;
+    for (; c + 4 <= nch; c += 4) {
+        const double2 v0 = src[c * stride], v1 = src[(c + 1) * stride];
+        const double2 v2 = src[(c + 2) * stride], v3 = src[(c + 3) * stride];
+        re += v0.x;
+        im += v0.y;
+        re += v1.x;
+        im += v1.y;
+        re += v2.x;
+        im += v2.y;
+        re += v3.x;
+        im += v3.y;
+    }
+    for (; c < nch; ++c) {
+        const double2 v = src[c * stride];
+        re += v.x;
+        im += v.y;
+    }
+    return make_double2(re, im);
+}
+
 template <int CB>  // columns per workgroup
 __global__ void __launch_bounds__(256) k_lr_mid(LowRankDev L, int nch, const double* __restrict__ C,
                                                 const double2* __restrict__ Gp, double2* __restrict__ H, CgIter it,
@@ -313,16 +339,8 @@ __global__ void __launch_bounds__(256) k_lr_mid(LowRankDev L, int nch, const dou
     auto gather = [&](int q) {
         const int cl = q % CB, x = q / CB;
         const int col = col0 + cl;
-        double re = 0.0, im = 0.0;
-        if (col < plane) {
-            const double2* src = Gp + (int64_t)x * nch * plane + col;
-            for (int c = 0; c < nch; ++c) {
-                const double2 v = src[(int64_t)c * plane];
-                re += v.x;
-                im += v.y;
-            }
-        }
-        return make_double2(re, im);
+        if (col >= plane) return make_double2(0.0, 0.0);
+        return chunk_sum(Gp + (int64_t)x * nch * plane + col, nch, plane);
     };
     double2 gv[kMidQB];
 #pragma unroll
@@ -399,16 +417,8 @@ __global__ void __launch_bounds__(256) k_lr_mid3(LowRankDev L, int nch, int cb, 
         const int c = q / ncol, rem = q % ncol;
         const int cl = rem % cb, x = rem / cb;
         const int col = col0 + cl;
-        double re = 0.0, im = 0.0;
-        if (col < plane) {
-            const double2* src = Gp + (int64_t)(c * L.n0 + x) * nch * plane + col;
-            for (int ch = 0; ch < nch; ++ch) {
-                const double2 v = src[(int64_t)ch * plane];
-                re += v.x;
-                im += v.y;
-            }
-        }
-        return make_double2(re, im);
+        if (col >= plane) return make_double2(0.0, 0.0);
+        return chunk_sum(Gp + (int64_t)(c * L.n0 + x) * nch * plane + col, nch, plane);
     };
     double2 gv[kMidQB];
 #pragma unroll
@@ -1125,10 +1135,12 @@ uno_status lowrank_create(const Grid& g, const FftPlan& fp, int M, double W, con
     p->ya = rows;
     p->yc = rows < 256 ? rows : 256;  // pass C: at least one thread per row
     // pass A: a workgroup sums its rows' partial DFTs itself, so the row
-    // chunks pass B gathers stay few: about 256 workgroups per right-hand
-    // side, each taking its rows ya at a time
+    // chunks pass B gathers stay few: enough workgroups for one right-hand
+    // side to fill the chip (about 2048, at most 64 chunks per slab), each
+    // taking its rows ya at a time; batches take fewer chunks
     {
-        const int want = (256 + p->slabs - 1) / p->slabs;
+        int want = (2048 + p->slabs - 1) / p->slabs;
+        if (want > 64) want = 64;
         int rb = (L.n1 + want - 1) / want;
         rb = ((rb + p->ya - 1) / p->ya) * p->ya;
         if (rb > L.n1) rb = L.n1;
@@ -1200,7 +1212,11 @@ int lowrank_max_blocks(const LowRankPlan* p)
 bool lowrank_fused(const LowRankPlan* p) { return p->fused; }
 LrBatch lowrank_batch(const LowRankPlan* p, double2* Gp, double2* H, int nrhs)
 {
-    LrBatch b{Gp, H, nrhs, p->rb, p->nch_a, p->yc};
+    LrBatch b{Gp, H, nrhs, p->rb, p->nch_a, p->yc, p->cb_mid};
+    // pass B: fewer columns per workgroup while a launch has under about
+    // 1024 workgroups (each column is transformed alone, so the grouping
+    // changes no result)
+    while (b.cb > 1 && (int64_t)((p->dev.kyn * p->dev.kzn + b.cb - 1) / b.cb) * nrhs < 1024) b.cb /= 2;
     // pass C: rows per workgroup for about 2048 workgroups per launch, a
     // power of two between the plan's smallest and largest
     {
@@ -1299,24 +1315,27 @@ static void launch_lr_tile_tx(const LowRankPlan* p, const GridDev& g, const doub
         launch_lr_tile<TX, false>(p, g, kappa, r, dold, dnew, pv, part_dp, it, a, gam, bt, st);
 }
 
-// pass B with the plan's columns per workgroup (8, 4, 2 or 1) as a constant
-static void launch_mid(const LowRankPlan* p, const LrBatch& bt, const CgIter& it, double* part_corr, hipStream_t st)
+// pass B with cb (8, 4, 2 or 1) columns per workgroup as a constant
+static void launch_mid(const LowRankPlan* p, const LrBatch& bt, int cb, const CgIter& it, double* part_corr,
+                       hipStream_t st)
 {
-    const dim3 grid(p->blocks_mid, bt.nrhs), blk(256);
+    const LowRankDev& L = p->dev;
+    const dim3 grid((L.kyn * L.kzn + cb - 1) / cb, bt.nrhs), blk(256);
+    const size_t lds = sizeof(double2) * (size_t)cb * (L.n0 + L.kxn);
     const double* C = (const double*)p->table;
     const double2* Gp = bt.Gp;
-    switch (p->cb_mid) {
+    switch (cb) {
         case 8:
-            uno_launch(UNO_KT_FFT_MID, k_lr_mid<8>, grid, blk, p->lds_b, st, p->dev, bt.nch, C, Gp, bt.H, it, part_corr);
+            uno_launch(UNO_KT_FFT_MID, k_lr_mid<8>, grid, blk, lds, st, L, bt.nch, C, Gp, bt.H, it, part_corr);
             break;
         case 4:
-            uno_launch(UNO_KT_FFT_MID, k_lr_mid<4>, grid, blk, p->lds_b, st, p->dev, bt.nch, C, Gp, bt.H, it, part_corr);
+            uno_launch(UNO_KT_FFT_MID, k_lr_mid<4>, grid, blk, lds, st, L, bt.nch, C, Gp, bt.H, it, part_corr);
             break;
         case 2:
-            uno_launch(UNO_KT_FFT_MID, k_lr_mid<2>, grid, blk, p->lds_b, st, p->dev, bt.nch, C, Gp, bt.H, it, part_corr);
+            uno_launch(UNO_KT_FFT_MID, k_lr_mid<2>, grid, blk, lds, st, L, bt.nch, C, Gp, bt.H, it, part_corr);
             break;
         default:
-            uno_launch(UNO_KT_FFT_MID, k_lr_mid<1>, grid, blk, p->lds_b, st, p->dev, bt.nch, C, Gp, bt.H, it, part_corr);
+            uno_launch(UNO_KT_FFT_MID, k_lr_mid<1>, grid, blk, lds, st, L, bt.nch, C, Gp, bt.H, it, part_corr);
             break;
     }
 }
@@ -1331,7 +1350,7 @@ uno_status lowrank_fused_pass(const LowRankPlan* p, const Grid& g, const double*
 {
     if (!p->fused) return UNO_ERR_SHAPE;
     const LowRankDev& L = p->dev;
-    launch_mid(p, bt, it, part_corr, st);
+    launch_mid(p, bt, p->cb_mid, it, part_corr, st);  // the plan's grouping: part_corr has blocks_mid partials
     UNO_HIP(hipGetLastError());
     const LrTileArgs a{part_rr, p->dev.n0 * bt.nch, part_corr, p->blocks_mid};
     if (p->tile.tx == 1)
@@ -1353,10 +1372,11 @@ uno_status lowrank_finish(const LowRankPlan* p, const double* r, T* s, const CgI
     const LowRankDev& L = p->dev;
     const CgIter it = itp ? *itp : no_iter();
     if (L.nc == 3)
-        uno_launch(UNO_KT_FFT_MID, k_lr_mid3, dim3(p->blocks_mid, bt.nrhs), dim3(256), p->lds_b, st, L, bt.nch,
-                   p->cb_mid, (const double*)p->table, (const double2*)bt.Gp, bt.H, it);
+        uno_launch(UNO_KT_FFT_MID, k_lr_mid3, dim3((L.kyn * L.kzn + bt.cb - 1) / bt.cb, bt.nrhs), dim3(256),
+                   sizeof(double2) * 3 * (size_t)bt.cb * (L.n0 + L.kxn), st, L, bt.nch, bt.cb,
+                   (const double*)p->table, (const double2*)bt.Gp, bt.H, it);
     else
-        launch_mid(p, bt, it, nullptr, st);
+        launch_mid(p, bt, bt.cb, it, nullptr, st);
     UNO_HIP(hipGetLastError());
     const int nbc = L.n0 * ((L.n1 + bt.yc - 1) / bt.yc);
     const dim3 grid(nbc, bt.nrhs);
