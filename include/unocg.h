@@ -235,18 +235,28 @@ uno_status pcg_solve_noalloc(const uno_grid *grid, const uno_material *mat, cons
 
 /* Autotuner of the operator apply inside CG: a library utility, no passage of the paper.
  * It times every candidate shape of the march kernel -- footprint
- * width tz in {16, 32, 64} nodes along the contiguous axis (256 / tz rows)
- * and planes per workgroup xb over the even splits of the first axis -- for
+ * width tz in {16, 32, 64} nodes along the contiguous axis, rows per thread
+ * ry in {1, 2} (ry 256 / tz rows; ry = 2 for tz of 32 and 64) and planes
+ * per workgroup xb over the even splits of the first axis -- for
  * nrhs right-hand sides of `grid` in precision dtype (UNO_F64 or UNO_F32)
  * with one conductivity field per right-hand side (kappa_per_rhs = 1) or
  * one shared, on synthetic operands it allocates on `stream`, and records
  * the fastest; later solves with that (grid, nrhs, dtype, kappa_per_rhs) on
  * this device use it (results then differ from the rule's shapes only in
- * the rounding of the d.Ad partial sums).  tz, xb, us (host, nullable)
+ * the rounding of the d.Ad partial sums).  tz, ry, xb, us (host, nullable)
  * receive the shape and its time per launch in microseconds.  Records are
  * kept until uno_shutdown().  Synchronous. */
 uno_status uno_autotune_operator(const uno_grid *grid, int32_t nrhs, int32_t kappa_per_rhs, uno_dtype dtype,
-                                 void *stream, int32_t *tz, int32_t *xb, double *us);
+                                 void *stream, int32_t *tz, int32_t *ry, int32_t *xb, double *us);
+
+/* Records a march shape for (grid, nrhs, dtype, kappa_per_rhs) on the
+ * current device as uno_autotune_operator would (a library utility,
+ * no passage of the paper): to reuse a shape measured earlier, or to pin one.
+ * tz in {16, 32, 64}, ry in {1, 2} (ry = 2 with tz of 32 or 64), xb >= 1
+ * planes per workgroup (clipped to [2, n0] at launch).  UNO_ERR_ARG for a
+ * shape that is not built.  Host only, no device work. */
+uno_status uno_set_operator_shape(const uno_grid *grid, int32_t nrhs, int32_t kappa_per_rhs, uno_dtype dtype,
+                                  int32_t tz, int32_t ry, int32_t xb);
 
 /* Effective conductivity (Sec. 5.1; the homogenized property handed back to
  * the macro scale, Sec. 1): for load j with gradient g_j (host loads,

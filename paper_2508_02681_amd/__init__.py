@@ -100,7 +100,8 @@ def lib():
         "uno_timing_enable": ([i32], i),
         "uno_timing_read": ([P(f64), P(i64)], i),
         "uno_shutdown": ([], i),
-        "uno_autotune_operator": ([G, i32, i32, i, vp, P(i32), P(i32), P(f64)], i),
+        "uno_autotune_operator": ([G, i32, i32, i, vp, P(i32), P(i32), P(i32), P(f64)], i),
+        "uno_set_operator_shape": ([G, i32, i32, i, i32, i32, i32], i),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -607,12 +608,21 @@ def uno_train_fit(shape, M, alpha: torch.Tensor, beta: torch.Tensor, L0=1.0) -> 
 def autotune_operator(shape, nrhs, kappa_per_rhs=False, dtype=torch.float64, L0=1.0) -> dict:
     """Measures the operator march's shapes for nrhs right-hand sides of
     this grid and records the fastest (used by later solves).  Returns
-    dict(tz, xb, us)."""
+    dict(tz, ry, xb, us)."""
     g = make_grid(shape, L0)
-    tz, xb, us = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_double(0.0)
+    tz, ry, xb, us = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_double(0.0)
     _check(lib().uno_autotune_operator(ctypes.byref(g), int(nrhs), 1 if kappa_per_rhs else 0, _dt(dtype), _stream(),
-                                       ctypes.byref(tz), ctypes.byref(xb), ctypes.byref(us)), "uno_autotune_operator")
-    return dict(tz=tz.value, xb=xb.value, us=us.value)
+                                       ctypes.byref(tz), ctypes.byref(ry), ctypes.byref(xb), ctypes.byref(us)),
+           "uno_autotune_operator")
+    return dict(tz=tz.value, ry=ry.value, xb=xb.value, us=us.value)
+
+
+def set_operator_shape(shape, nrhs, tz, ry, xb, kappa_per_rhs=False, dtype=torch.float64, L0=1.0):
+    """Records the operator march shape (tz, ry, xb) for nrhs right-hand
+    sides of this grid, as autotune_operator would."""
+    g = make_grid(shape, L0)
+    _check(lib().uno_set_operator_shape(ctypes.byref(g), int(nrhs), 1 if kappa_per_rhs else 0, _dt(dtype), int(tz),
+                                        int(ry), int(xb)), "uno_set_operator_shape")
 
 
 def timing_enable(which: int):

@@ -1,8 +1,9 @@
 // Autotuner of the operator march (the CG pass's d = s + beta d_old,
 // p = A d, d.p kernel): for a grid, a number of right-hand sides, a vector
 // precision and a shared or per-right-hand-side conductivity field it
-// times every candidate shape -- footprint width tz in {16, 32, 64} (the
-// workgroup's 256 threads cover tz x 256/tz nodes) and the planes per
+// times every candidate shape -- footprint width tz in {16, 32, 64} and
+// rows per thread ry in {1, 2} (the workgroup's 256 threads cover tz x
+// ry 256/tz nodes; ry = 2 for tz of 32 and 64) and the planes per
 // workgroup xb of the even splits of the marching axis -- on synthetic
 // operands and records the fastest; launch_tile then uses the record.
 #include <climits>
@@ -92,19 +93,20 @@ uno_status sweep(const Grid& g, int nrhs, bool per_rhs, hipStream_t st, MarchSha
     const MeanFree mf{part_rs, part_zero, part_out};
     best->tz = 0;
     *best_us = 1e30;
-    for (int tz = 16; tz <= 64 && err == UNO_OK; tz *= 2) {
-        if (256 / tz > g.n[1] || tz > g.n[2]) continue;
+    for (int shape = 0; shape < 6 && err == UNO_OK; ++shape) {
+        const int tz = 16 << (shape % 3), ry = 1 + shape / 3;
+        if (!march_shape_built(tz, ry) || 256 / tz * ry > g.n[1] || tz > g.n[2]) continue;
         int last_xb = -1;
         for (int tiles_x = 1; tiles_x <= (g.n[0] + 1) / 2 && err == UNO_OK; ++tiles_x) {
-            const MarchGeom m = march_geom_of(g, tz, (g.n[0] + tiles_x - 1) / tiles_x);
+            const MarchGeom m = march_geom_of(g, tz, ry, (g.n[0] + tiles_x - 1) / tiles_x);
             if (m.xb == last_xb) continue;
             last_xb = m.xb;
             const int64_t wg = (int64_t)m.tiles_x * m.tiles_y * m.tiles_z * nrhs;
             if (wg < 256 && tiles_x < (g.n[0] + 1) / 2) continue;  // far too few workgroups for the chip
             if (m.tiles_x * m.tiles_y * m.tiles_z > ps) continue;
             auto launch = [&]() {
-                launch_march_near<T, true, false, true>(m, tz, g.dev, kap, s, dold, dnew, p, part_dp, it, part_rs, 1,
-                                                        gam, st, mf, nrhs);
+                launch_march_near<T, true, false, true>(m, tz, ry, g.dev, kap, s, dold, dnew, p, part_dp, it, part_rs,
+                                                        1, gam, st, mf, nrhs);
             };
             launch();
             launch();
@@ -121,6 +123,7 @@ uno_status sweep(const Grid& g, int nrhs, bool per_rhs, hipStream_t st, MarchSha
             if (us < *best_us) {
                 *best_us = us;
                 best->tz = tz;
+                best->ry = ry;
                 best->xb = m.xb;
             }
         }
@@ -159,7 +162,7 @@ void tune_release_all()
 using namespace unocg;
 
 extern "C" uno_status uno_autotune_operator(const uno_grid* grid, int32_t nrhs, int32_t kappa_per_rhs, uno_dtype dtype,
-                                            void* stream, int32_t* tz, int32_t* xb, double* us)
+                                            void* stream, int32_t* tz, int32_t* ry, int32_t* xb, double* us)
 {
     Grid g;
     uno_status e = make_grid(grid, &g);
@@ -180,7 +183,25 @@ extern "C" uno_status uno_autotune_operator(const uno_grid* grid, int32_t nrhs, 
         g_tune_any = true;
     }
     if (tz) *tz = best.tz;
+    if (ry) *ry = best.ry;
     if (xb) *xb = best.xb;
     if (us) *us = best_us;
+    return UNO_OK;
+}
+
+extern "C" uno_status uno_set_operator_shape(const uno_grid* grid, int32_t nrhs, int32_t kappa_per_rhs,
+                                             uno_dtype dtype, int32_t tz, int32_t ry, int32_t xb)
+{
+    Grid g;
+    uno_status e = make_grid(grid, &g);
+    if (e != UNO_OK) return e;
+    if (nrhs < 1 || nrhs > 256 || (kappa_per_rhs != 0 && kappa_per_rhs != 1)) return UNO_ERR_ARG;
+    if (dtype != UNO_F64 && dtype != UNO_F32) return UNO_ERR_ARG;
+    if (!march_shape_built(tz, ry) || xb < 1) return UNO_ERR_ARG;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return UNO_ERR_DEVICE;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[tune_key(dev, g, nrhs, dtype == UNO_F64 ? 8 : 4, kappa_per_rhs != 0)] = MarchShape{tz, ry, xb};
+    g_tune_any = true;
     return UNO_OK;
 }

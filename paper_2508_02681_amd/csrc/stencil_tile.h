@@ -1,13 +1,14 @@
 // Matrix-free operator apply (Sec. 3.1: the stiffness matrix of the periodic
 // linear FE discretization, applied without assembly).
 //
-// A workgroup of 256 threads owns a TY x TZ footprint of nodes (TY = 256 /
-// TZ) and marches along x over xb node planes.  Planes of the vector (with
-// a one-node halo in y and z) and of the conductivities of the voxels
-// touching them stream through a small ring of LDS planes (periodic wrap on
-// each coordinate); each thread keeps the 3 x 3 neighbourhood of three node
-// planes and the 2 x 2 voxel conductivities of two voxel planes in
-// registers and rolls them along x: 9 + 4 LDS reads per node.
+// A workgroup of 256 threads owns a TY x TZ footprint of nodes (TY = RY 256
+// / TZ: each thread takes RY consecutive rows) and marches along x over xb
+// node planes.  Planes of the vector (with a one-node halo in y and z) and
+// of the conductivities of the voxels touching them stream through a small
+// ring of LDS planes (periodic wrap on each coordinate); each thread keeps
+// the (RY + 2) x 3 neighbourhood of its rows in three node planes and the
+// (RY + 1) x 2 voxel conductivities of two voxel planes in registers and
+// rolls them along x: (3 (RY + 2) + 2 (RY + 1)) / RY LDS reads per node.
 //
 // Node-centred form of the assembled operator: node i touches the 8 voxels
 // i + sigma, sigma in {-1,0}^3, and
@@ -108,7 +109,7 @@ struct MeanFree {
     double* part_dnew;
 };
 
-// The kernel: a workgroup owns a TY x TZ footprint (TY = 256 / TZ) and xb
+// The kernel: a workgroup owns a TY x TZ footprint (TY = RY 256 / TZ) and xb
 // consecutive node planes along x, and sweeps the input planes x0 - 1 ..
 // x0 + xb.  Input node plane xi (with a one-node halo in y and z) and voxel
 // plane xi stream through two LDS buffers, the loads of plane xi + 1 in
@@ -116,7 +117,8 @@ struct MeanFree {
 // three partial sums: input plane xi contributes to the outputs at xi + 1
 // (started), xi and xi - 1 (complete after it), so only the 3 x 3
 // neighbourhood of one plane and the 2 x 2 conductivities of two voxel
-// planes are live (9 + 4 LDS reads per node and plane).  Through voxel face
+// planes are live per row (rows of one thread share the staged rows
+// between them).  Through voxel face
 // (sy, sz) in the y-z plane, plane xi contributes
 //   sum over the face's 4 nodes (b, c) of w[m] d[b][c] =: E[sy][sz],
 // with the weights of the neighbour-plane class (output xi -/+ 1) or the
@@ -138,7 +140,7 @@ struct MarchGeom {
     int tiles_y, tiles_z, xb, tiles_x;
 };
 
-template <typename T, int TZ, bool CG, bool HEAD, bool NEAR>
+template <typename T, int TZ, int RY, bool CG, bool HEAD, bool NEAR>
 __global__ void __launch_bounds__(256) k_stencil_march(GridDev g, MarchGeom mg, const T* __restrict__ kappa,
                                                        const T* __restrict__ s, const T* __restrict__ dold,
                                                        T* __restrict__ dnew, T* __restrict__ p,
@@ -148,7 +150,7 @@ __global__ void __launch_bounds__(256) k_stencil_march(GridDev g, MarchGeom mg, 
 {
     resolve_pass(it);
     constexpr bool MF = CG && sizeof(T) == 4;
-    constexpr int TY = 256 / TZ;
+    constexpr int TY = 256 / TZ * RY;  // footprint rows: RY rows per thread
     constexpr int DY = TY + 2, DZ = TZ + 2, KY = TY + 1, KZ = TZ + 1;
     constexpr int ND = DY * DZ, NK = KY * KZ;
     constexpr int PD = (ND + 255) / 256, PK = (NK + 255) / 256;
@@ -286,11 +288,17 @@ __global__ void __launch_bounds__(256) k_stencil_march(GridDev g, MarchGeom mg, 
     put(0);
     __syncthreads();
 
-    const int tz = threadIdx.x % TZ, ty = threadIdx.x / TZ;
-    const int y = y0 + ty, z = z0 + tz;
-    const bool yz_ok = (y < g.n1) && (z < g.n2);
-    T km[2][2] = {{(T)0, (T)0}, {(T)0, (T)0}};
-    T acc_prev = 0, acc_cur = 0, dc_prev = 0;
+    const int tz = threadIdx.x % TZ, ty = threadIdx.x / TZ * RY;  // first of the thread's RY rows
+    const int z = z0 + tz;
+    bool yz_ok[RY];
+#pragma unroll
+    for (int j = 0; j < RY; ++j) yz_ok[j] = (y0 + ty + j < g.n1) && (z < g.n2);
+    T km[RY + 1][2];
+    T acc_prev[RY], acc_cur[RY], dc_prev[RY];
+#pragma unroll
+    for (int bb = 0; bb <= RY; ++bb) km[bb][0] = km[bb][1] = (T)0;
+#pragma unroll
+    for (int j = 0; j < RY; ++j) acc_prev[j] = acc_cur[j] = dc_prev[j] = (T)0;
     double dot = 0.0, dsum_own = 0.0;
     const int nsteps = xe - x0 + 2;
     for (int t = 0; t < nsteps; ++t) {
@@ -298,52 +306,57 @@ __global__ void __launch_bounds__(256) k_stencil_march(GridDev g, MarchGeom mg, 
         const int slot = t & 1;
         const bool more = t + 1 < nsteps;
         if (more) load(xi + 1);  // next plane in flight while this one is used
-        T D[3][3], kp[2][2];
+        T D[RY + 2][3], kp[RY + 1][2];
 #pragma unroll
-        for (int bb = 0; bb < 3; ++bb)
+        for (int bb = 0; bb < RY + 2; ++bb)
 #pragma unroll
             for (int c = 0; c < 3; ++c) D[bb][c] = Dr[slot][(ty + bb) * DZ + tz + c];
         const bool has_kp = xi < xe;  // voxel planes x0 - 1 .. xe - 1
 #pragma unroll
-        for (int bb = 0; bb < 2; ++bb)
+        for (int bb = 0; bb < RY + 1; ++bb)
 #pragma unroll
             for (int c = 0; c < 2; ++c) kp[bb][c] = has_kp ? Kr[slot][(ty + bb) * KZ + tz + c] : (T)0;
-        // row sums of w d along z per voxel column, neighbour-plane (rh) and
-        // same-plane (rl) weights; face (sy, sz) adds rows sy and sy + 1
-        T rh[3][2], rl[3][2];
 #pragma unroll
-        for (int bb = 0; bb < 3; ++bb)
+        for (int j = 0; j < RY; ++j) {
+            // row sums of w d along z per voxel column over rows j .. j + 2
+            // of the staged plane (j + 1 the output's own row), neighbour-
+            // plane (rh) and same-plane (rl) weights; face (sy, sz) adds rows
+            // sy and sy + 1.  Outputs xi - 1 (through voxel plane xi - 1), xi
+            // (both) and xi + 1 (xi)
+            T rh[3][2], rl[3][2];
 #pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                const int m0 = ((bb != 1) << 1) | (c != 1), m1 = ((bb != 1) << 1) | (c + 1 != 1);
-                rh[bb][c] = (T)g.w[4 | m0] * D[bb][c] + (T)g.w[4 | m1] * D[bb][c + 1];
-                rl[bb][c] = (T)g.w[m0] * D[bb][c] + (T)g.w[m1] * D[bb][c + 1];
+            for (int bb = 0; bb < 3; ++bb)
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const int m0 = ((bb != 1) << 1) | (c != 1), m1 = ((bb != 1) << 1) | (c + 1 != 1);
+                    rh[bb][c] = (T)g.w[4 | m0] * D[j + bb][c] + (T)g.w[4 | m1] * D[j + bb][c + 1];
+                    rl[bb][c] = (T)g.w[m0] * D[j + bb][c] + (T)g.w[m1] * D[j + bb][c + 1];
+                }
+            T accA = acc_prev[j], accB = acc_cur[j], accC = 0;
+#pragma unroll
+            for (int sy = 0; sy < 2; ++sy)
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const T eh = rh[sy][c] + rh[sy + 1][c], el = rl[sy][c] + rl[sy + 1][c];
+                    accA += km[j + sy][c] * eh;
+                    accB += (km[j + sy][c] + kp[j + sy][c]) * el;
+                    accC += kp[j + sy][c] * eh;
+                }
+            if (t >= 2 && yz_ok[j]) {  // output xi - 1 is complete
+                const int64_t i = (int64_t)(xi - 1) * pl + (int64_t)(y0 + ty + j) * g.n2 + z;
+                p[i] = accA;
+                if (CG) {
+                    dnew[i] = dc_prev[j];
+                    dot += (double)dc_prev[j] * (double)accA;
+                    if (MF) dsum_own += (double)dc_prev[j];
+                }
             }
-        // outputs xi - 1 (through voxel plane xi - 1), xi (both) and xi + 1 (xi)
-        T accA = acc_prev, accB = acc_cur, accC = 0;
-#pragma unroll
-        for (int bb = 0; bb < 2; ++bb)
-#pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                const T eh = rh[bb][c] + rh[bb + 1][c], el = rl[bb][c] + rl[bb + 1][c];
-                accA += km[bb][c] * eh;
-                accB += (km[bb][c] + kp[bb][c]) * el;
-                accC += kp[bb][c] * eh;
-            }
-        if (t >= 2 && yz_ok) {  // output xi - 1 is complete
-            const int64_t i = (int64_t)(xi - 1) * pl + (int64_t)y * g.n2 + z;
-            p[i] = accA;
-            if (CG) {
-                dnew[i] = dc_prev;
-                dot += (double)dc_prev * (double)accA;
-                if (MF) dsum_own += (double)dc_prev;
-            }
+            acc_prev[j] = accB;  // (meaningful from t = 1 while xi < xe)
+            dc_prev[j] = D[j + 1][1];
+            acc_cur[j] = accC;   // (meaningful while xi + 1 < xe)
         }
-        acc_prev = accB;  // (meaningful from t = 1 while xi < xe)
-        dc_prev = D[1][1];
-        acc_cur = accC;   // (meaningful while xi + 1 < xe)
 #pragma unroll
-        for (int bb = 0; bb < 2; ++bb)
+        for (int bb = 0; bb < RY + 1; ++bb)
 #pragma unroll
             for (int c = 0; c < 2; ++c) km[bb][c] = kp[bb][c];
         if (more) put(slot ^ 1);
@@ -394,12 +407,13 @@ inline bool tile_near(const TileChoice& c, const GridDev& g)
 
 // Operator march shape of a (grid, right-hand sides, vector precision,
 // conductivity field per right-hand side or shared): the
-// footprint width tz (16, 32 or 64) and the planes per workgroup xb (>= 2,
+// footprint width tz (16, 32 or 64), the rows per thread ry (1, or 2 with
+// tz of 32 or 64: fewer halo rows per node) and the planes per workgroup xb (>= 2,
 // or the whole axis when it is shorter).  uno_autotune_operator measures the
 // candidates and records the fastest (autotune.hip); without a record the
 // rules below apply.
 struct MarchShape {
-    int tz, xb;
+    int tz, ry, xb;
 };
 bool march_tuned(const Grid& g, int nrhs, int tsize, bool kappa_per_rhs, MarchShape* out);
 
@@ -422,11 +436,11 @@ inline int march_max_blocks(const Grid& g)
     return most;
 }
 
-// Marching geometry for footprint width tz and planes per workgroup xb0:
-// the planes split evenly into chunks of at most xb0.
-inline MarchGeom march_geom_of(const Grid& g, int tz, int64_t xb0)
+// Marching geometry for footprint width tz, ry rows per thread and planes
+// per workgroup xb0: the planes split evenly into chunks of at most xb0.
+inline MarchGeom march_geom_of(const Grid& g, int tz, int ry, int64_t xb0)
 {
-    const int ty = 256 / tz;
+    const int ty = 256 / tz * ry;
     MarchGeom m;
     m.tiles_y = (g.n[1] + ty - 1) / ty;
     m.tiles_z = (g.n[2] + tz - 1) / tz;
@@ -444,38 +458,51 @@ inline MarchGeom march_geom_of(const Grid& g, int tz, int64_t xb0)
 // 22 planes 111 us, 6144 of 8 planes 111 us, 4608 of 12 and 3072 of 16
 // planes 118-119 us, 1536 of 32 planes 127 us; 192^3 x 3: 199-204 us from
 // 1728 to 6912 workgroups).
-inline MarchGeom march_geom(const Grid& g, int nrhs, int tsize, bool kappa_per_rhs, int* tz_out)
+inline MarchGeom march_geom(const Grid& g, int nrhs, int tsize, bool kappa_per_rhs, int* tz_out, int* ry_out)
 {
     MarchShape sh;
     if (march_tuned(g, nrhs, tsize, kappa_per_rhs, &sh)) {
         *tz_out = sh.tz;
-        return march_geom_of(g, sh.tz, sh.xb);
+        *ry_out = sh.ry;
+        return march_geom_of(g, sh.tz, sh.ry, sh.xb);
     }
     const int tz = march_tz_rule(g), ty = 256 / tz;
     *tz_out = tz;
+    *ry_out = 1;
     const int64_t yz = (int64_t)((g.n[1] + ty - 1) / ty) * ((g.n[2] + tz - 1) / tz) * nrhs;
-    return march_geom_of(g, tz, (g.n[0] * yz + 2047) / 2048);
+    return march_geom_of(g, tz, 1, (g.n[0] * yz + 2047) / 2048);
 }
 
+// the footprints built: (tz, ry) in {(64, 1), (32, 1), (16, 1), (64, 2), (32, 2)}
+inline bool march_shape_built(int tz, int ry) { return ry == 1 ? (tz == 16 || tz == 32 || tz == 64) : (ry == 2 && tz >= 32 && tz <= 64); }
+
 template <typename T, bool CG, bool HEAD, bool NEAR>
-inline void launch_march_near(const MarchGeom& m, int tz, const GridDev& g, const T* kappa, const T* s,
+inline void launch_march_near(const MarchGeom& m, int tz, int ry, const GridDev& g, const T* kappa, const T* s,
                               const T* dold, T* dnew, T* p, double* part_dp, const CgIter& it,
                               const double* part_rs, int np_rs, double* gam, hipStream_t st, const MeanFree& mf,
                               int nrhs)
 {
     const dim3 grid(m.tiles_x * m.tiles_y * m.tiles_z, nrhs);
     const int fam = CG ? UNO_KT_MATVEC : UNO_KT_APPLY;  // timing family
-    switch (tz) {
-        case 64:
-            uno_launch(fam, k_stencil_march<T, 64, CG, HEAD, NEAR>, grid, dim3(256), 0, st, g, m, kappa, s, dold,
+    switch (ry * 100 + tz) {
+        case 164:
+            uno_launch(fam, k_stencil_march<T, 64, 1, CG, HEAD, NEAR>, grid, dim3(256), 0, st, g, m, kappa, s, dold,
                        dnew, p, part_dp, it, part_rs, np_rs, gam, mf);
             break;
-        case 32:
-            uno_launch(fam, k_stencil_march<T, 32, CG, HEAD, NEAR>, grid, dim3(256), 0, st, g, m, kappa, s, dold,
+        case 132:
+            uno_launch(fam, k_stencil_march<T, 32, 1, CG, HEAD, NEAR>, grid, dim3(256), 0, st, g, m, kappa, s, dold,
+                       dnew, p, part_dp, it, part_rs, np_rs, gam, mf);
+            break;
+        case 264:
+            uno_launch(fam, k_stencil_march<T, 64, 2, CG, HEAD, NEAR>, grid, dim3(256), 0, st, g, m, kappa, s, dold,
+                       dnew, p, part_dp, it, part_rs, np_rs, gam, mf);
+            break;
+        case 232:
+            uno_launch(fam, k_stencil_march<T, 32, 2, CG, HEAD, NEAR>, grid, dim3(256), 0, st, g, m, kappa, s, dold,
                        dnew, p, part_dp, it, part_rs, np_rs, gam, mf);
             break;
         default:
-            uno_launch(fam, k_stencil_march<T, 16, CG, HEAD, NEAR>, grid, dim3(256), 0, st, g, m, kappa, s, dold,
+            uno_launch(fam, k_stencil_march<T, 16, 1, CG, HEAD, NEAR>, grid, dim3(256), 0, st, g, m, kappa, s, dold,
                        dnew, p, part_dp, it, part_rs, np_rs, gam, mf);
             break;
     }
@@ -488,14 +515,14 @@ inline int launch_tile(const Grid& g, const T* kappa, const T* s, const T* dold,
                        const CgIter& it, const double* part_rs, int np_rs, double* gam, hipStream_t st,
                        const MeanFree& mf = MeanFree{nullptr, nullptr, nullptr}, int nrhs = 1)
 {
-    int tz = 0;
-    const MarchGeom m = march_geom(g, nrhs, (int)sizeof(T), it.ks != 0, &tz);
-    const bool near = 256 / tz <= g.n[1] && tz <= g.n[2];
+    int tz = 0, ry = 1;
+    const MarchGeom m = march_geom(g, nrhs, (int)sizeof(T), it.ks != 0, &tz, &ry);
+    const bool near = 256 / tz * ry <= g.n[1] && tz <= g.n[2];
     if (near)
-        launch_march_near<T, CG, HEAD, true>(m, tz, g.dev, kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs, gam,
-                                             st, mf, nrhs);
+        launch_march_near<T, CG, HEAD, true>(m, tz, ry, g.dev, kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs,
+                                             gam, st, mf, nrhs);
     else
-        launch_march_near<T, CG, HEAD, false>(m, tz, g.dev, kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs,
+        launch_march_near<T, CG, HEAD, false>(m, tz, ry, g.dev, kappa, s, dold, dnew, p, part_dp, it, part_rs, np_rs,
                                               gam, st, mf, nrhs);
     return m.tiles_x * m.tiles_y * m.tiles_z;
 }

@@ -41,7 +41,7 @@ def test_autotune_shared_field_then_solve(orc, uno):
     before, ib = uno.pcg_solve_batch(T(kap), macro_loads=loads, kind="jacobi", rtol=1e-12)
     rec = uno.autotune_operator(shape, 3, kappa_per_rhs=False)
     print("autotuned", shape, rec, flush=True)
-    assert rec["tz"] in (16, 32, 64) and 2 <= rec["xb"] <= shape[0] and rec["us"] > 0
+    assert rec["tz"] in (16, 32, 64) and rec["ry"] in (1, 2) and 2 <= rec["xb"] <= shape[0] and rec["us"] > 0
     after, ia = uno.pcg_solve_batch(T(kap), macro_loads=loads, kind="jacobi", rtol=1e-12)
     for j, g in enumerate(loads):
         uo, _, _, _ = orc.pcg(kap, orc.rhs(kap, g), "jacobi", rtol=1e-12)
@@ -69,3 +69,44 @@ def test_autotune_per_rhs_fields_batch(uno):
     for a, b in zip(ir, ig):
         assert b["converged"] and abs(a["iters"] - b["iters"]) <= max(1, int(0.03 * a["iters"]))
     assert rel(got.cpu().numpy(), ref.cpu().numpy()) < 1e-8
+
+
+MARCH_SHAPES = [(64, 1), (32, 1), (16, 1), (64, 2), (32, 2)]
+
+
+@pytest.mark.parametrize("tz,ry", MARCH_SHAPES)
+def test_every_march_shape_matches_oracle(orc, uno, tz, ry):
+    """Each built footprint (tz, ry), pinned through set_operator_shape, on a
+    grid ragged along y and z (37 rows, 70 = 64 + 6 columns) and with
+    several plane counts per workgroup: the apply equals the oracle's."""
+    shape = (13, 37, 70)
+    print("march shape", tz, ry, flush=True)
+    kap = si.random_field(shape, 81, 0.1, 10.0)
+    u = si.random_field(shape, 82)
+    ref = orc.fe_apply(kap, u)
+    for xb in (2, 5, 13):
+        uno.set_operator_shape(shape, 1, tz, ry, xb)
+        y = uno.fe_apply(T(kap), T(u)).cpu().numpy()
+        assert rel(y, ref) < 1e-12, (tz, ry, xb)
+        uno.set_operator_shape(shape, 1, tz, ry, xb, dtype=torch.float32)
+        y32 = uno.fe_apply(torch.tensor(kap, dtype=torch.float32, device=DEV),
+                           torch.tensor(u, dtype=torch.float32, device=DEV)).cpu().numpy()
+        ref32 = orc.fe_apply(kap.astype(np.float32), u.astype(np.float32))
+        assert rel(y32, ref32) < 1e-5, (tz, ry, xb)
+
+
+@pytest.mark.parametrize("tz,ry", [(64, 2), (32, 2)])
+def test_two_row_march_inside_cg_matches_oracle(orc, uno, tz, ry):
+    """The two-row footprints inside batched CG (the fused direction update,
+    d.p partials) on a grid smaller than the 64-wide footprint along z:
+    solutions equal the oracle's to the solve tolerance."""
+    shape = (16, 24, 40)
+    kap = _kappa(shape, 83)
+    loads = np.eye(3)
+    uno.set_operator_shape(shape, 3, tz, ry, 3)
+    got, info = uno.pcg_solve_batch(T(kap), macro_loads=loads, kind="jacobi", rtol=1e-12)
+    for j, g in enumerate(loads):
+        uo, its, _, _ = orc.pcg(kap, orc.rhs(kap, g), "jacobi", rtol=1e-12)
+        assert info[j]["converged"]
+        assert rel(got[j].cpu().numpy(), uo) < 1e-8
+        assert abs(info[j]["iters"] - its) <= max(1, int(0.01 * its))
