@@ -1217,9 +1217,24 @@ LrBatch lowrank_batch(const LowRankPlan* p, double2* Gp, double2* H, int nrhs)
     // 1024 workgroups (each column is transformed alone, so the grouping
     // changes no result)
     while (b.cb > 1 && (int64_t)((p->dev.kyn * p->dev.kzn + b.cb - 1) / b.cb) * nrhs < 1024) b.cb /= 2;
-    // pass C: rows per workgroup for about 2048 workgroups per launch, a
-    // power of two between the plan's smallest and largest
-    {
+    // pass C: rows per workgroup (measured: 192^3 x 3 loads 127 us with 64
+    // rows, 92 us with 16; 64^3 x 48 loads 63 us with 64 rows, 75 us with 32)
+    if (p->dev.nc == 1) {
+        // one component (k_lr_inv_pairs, 256 / yc threads per row): the
+        // most rows per workgroup that still give 2048 workgroups with at
+        // most 9 point pairs per thread, else the plan's fewest rows
+        const LowRankDev& L = p->dev;
+        const int npair = L.n2 / 2 + 1;
+        b.yc = p->yc;
+        for (int y = p->yc_max; y > p->yc; y /= 2) {
+            const int tpr = 256 / y, ppt = (npair + tpr - 1) / tpr;
+            const int64_t wg = (int64_t)L.n0 * ((L.n1 + y - 1) / y) * nrhs;
+            if (ppt <= 9 && wg >= 2048) {
+                b.yc = y;
+                break;
+            }
+        }
+    } else {  // three components (k_lr_inv): about 2048 workgroups per launch
         const int64_t want = ((int64_t)p->dev.n0 * p->dev.n1 * nrhs + 2047) / 2048;
         int yc = p->yc;
         while (yc < p->yc_max && yc < want) yc *= 2;
