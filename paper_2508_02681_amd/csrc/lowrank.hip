@@ -65,7 +65,7 @@ __device__ __forceinline__ int mod_n(int v, int n)
 // UPDATE (inside CG): the rows are first updated, r <- r - alpha p,
 // u <- u + alpha d, and partials of ||r||_inf are written; the transformed
 // rows are then those of the new residual (for the next pass).
-template <bool UPDATE, typename TD>
+template <bool UPDATE, typename TD, int PF>
 __global__ void __launch_bounds__(256) k_lr_fwd(LowRankDev L, int ya, int rb, double* __restrict__ r,
                                                 double* __restrict__ u, const TD* __restrict__ d,
                                                 const TD* __restrict__ p, double2* __restrict__ Gp, CgIter it,
@@ -103,8 +103,8 @@ __global__ void __launch_bounds__(256) k_lr_fwd(LowRankDev L, int ya, int rb, do
     const int rs = L.n2 + 1;
     double m = 0.0, sq = 0.0;
     // all global loads first (state, partials, gamma, the first PF elements
-    // of the four vectors of the first row group, twiddles); decisions after
-    constexpr int PF = 4;
+    // per thread of the four vectors of the first row group, twiddles);
+    // decisions after
     StateLoad sl;
     double dp_share = 0.0, gk = 0.0;
     double rv[PF], pv[PF], uv[PF], dv[PF];
@@ -197,6 +197,7 @@ __global__ void __launch_bounds__(256) k_lr_fwd(LowRankDev L, int ya, int rb, do
             int z = (L.n2 - 1) & ~1;  // last even z
             if (z + 1 < L.n2) or_ = row[z + 1];
             er = row[z];
+#pragma unroll 4
             for (z -= 2; z >= 0; z -= 2) {
                 const double ve = row[z], vo = row[z + 1];
                 const double ner = fma(er, w2.x, fma(-ei, w2.y, ve));
@@ -216,6 +217,7 @@ __global__ void __launch_bounds__(256) k_lr_fwd(LowRankDev L, int ya, int rb, do
             const double2 w = twy[mod_n(kyi - L.m, L.n1)];
             const double2 ph = twy[mod_n((kyi - L.m) * y0, L.n1)];
             double re = 0.0, im = 0.0;
+#pragma unroll 4
             for (int yl = ny - 1; yl >= 0; --yl) {
                 const double2 a = Z[yl * L.kzn + kz];
                 const double nre = fma(re, w.x, fma(-im, w.y, a.x));
@@ -267,17 +269,21 @@ __device__ __forceinline__ double2 horner_eo(const double2* a, int stride, int m
         orr = h.x;
         oi = h.y;
     }
-    for (; j >= 0; j -= 2) {
-        const double2 he = a[j * stride];
+#pragma unroll 4
+    for (; j >= 2; j -= 2) {  // both chains
+        const double2 he = a[j * stride], ho = a[(j - 1) * stride];
         const double ner = er * w2.x - ei * w2.y + he.x;
         ei = er * w2.y + ei * w2.x + he.y;
         er = ner;
-        if (j >= 1) {
-            const double2 ho = a[(j - 1) * stride];
-            const double nor = orr * w2.x - oi * w2.y + ho.x;
-            oi = orr * w2.y + oi * w2.x + ho.y;
-            orr = nor;
-        }
+        const double nor = orr * w2.x - oi * w2.y + ho.x;
+        oi = orr * w2.y + oi * w2.x + ho.y;
+        orr = nor;
+    }
+    {  // j = 0: the even chain only
+        const double2 he = a[0];
+        const double ner = er * w2.x - ei * w2.y + he.x;
+        ei = er * w2.y + ei * w2.x + he.y;
+        er = ner;
     }
     // E(w^2) + w O(w^2), E holding the even j, O the odd j
     return make_double2(er + (orr * w.x - oi * w.y), ei + (orr * w.y + oi * w.x));
@@ -1132,7 +1138,10 @@ uno_status lowrank_create(const Grid& g, const FftPlan& fp, int M, double W, con
     int rows = 1024 / L.n2;
     if (rows < 1) rows = 1;
     if (rows > L.n1) rows = L.n1;
-    p->ya = rows;
+    // pass A takes at least 8 rows per group where rows are long (fewer
+    // group steps per workgroup: 192^3 x 3 loads 239 -> 211 us with 10 rows
+    // instead of 5), its first 2048 elements prefetched
+    p->ya = rows >= 8 || 2 * rows > L.n1 ? rows : 2 * rows;
     p->yc = rows < 256 ? rows : 256;  // pass C: at least one thread per row
     // pass A: a workgroup sums its rows' partial DFTs itself, so the row
     // chunks pass B gathers stay few: enough workgroups for one right-hand
@@ -1278,9 +1287,15 @@ static LrBatch own(const LowRankPlan* p) { return lowrank_batch(p, p->Gp, p->H, 
 uno_status lowrank_forward(const LowRankPlan* p, const double* r, double* part_rr, const LrBatch& bt,
                            const CgIter& strides, hipStream_t st)
 {
-    uno_launch(UNO_KT_FFT_FWD, k_lr_fwd<false, double>, dim3(p->slabs * bt.nch, bt.nrhs), dim3(256), p->lds_a, st,
-               p->dev, p->ya, bt.rb, (double*)r, (double*)nullptr, (const double*)nullptr, (const double*)nullptr, bt.Gp, strides,
-               (const double*)nullptr, 0, (const double*)nullptr, (double*)nullptr, part_rr);
+    const dim3 grid(p->slabs * bt.nch, bt.nrhs);
+    if (p->ya * p->dev.n2 > 1024)
+        uno_launch(UNO_KT_FFT_FWD, k_lr_fwd<false, double, 8>, grid, dim3(256), p->lds_a, st, p->dev, p->ya, bt.rb,
+                   (double*)r, (double*)nullptr, (const double*)nullptr, (const double*)nullptr, bt.Gp, strides,
+                   (const double*)nullptr, 0, (const double*)nullptr, (double*)nullptr, part_rr);
+    else
+        uno_launch(UNO_KT_FFT_FWD, k_lr_fwd<false, double, 4>, grid, dim3(256), p->lds_a, st, p->dev, p->ya, bt.rb,
+                   (double*)r, (double*)nullptr, (const double*)nullptr, (const double*)nullptr, bt.Gp, strides,
+                   (const double*)nullptr, 0, (const double*)nullptr, (double*)nullptr, part_rr);
     return hip_status(hipGetLastError());
 }
 
@@ -1290,8 +1305,13 @@ uno_status lowrank_update_forward(const LowRankPlan* p, double* r, double* u, co
                                   const CgIter& it, const double* part_dp, int np_dp, const double* gam,
                                   double* part_rmax, double* part_rr, const LrBatch& bt, hipStream_t st)
 {
-    uno_launch(UNO_KT_UPDATE, k_lr_fwd<true, T>, dim3(p->slabs * bt.nch, bt.nrhs), dim3(256), p->lds_a, st, p->dev,
-               p->ya, bt.rb, r, u, d, pv, bt.Gp, it, part_dp, np_dp, gam, part_rmax, part_rr);
+    const dim3 grid(p->slabs * bt.nch, bt.nrhs);
+    if (p->ya * p->dev.n2 > 1024)
+        uno_launch(UNO_KT_UPDATE, k_lr_fwd<true, T, 8>, grid, dim3(256), p->lds_a, st, p->dev, p->ya, bt.rb, r, u, d,
+                   pv, bt.Gp, it, part_dp, np_dp, gam, part_rmax, part_rr);
+    else
+        uno_launch(UNO_KT_UPDATE, k_lr_fwd<true, T, 4>, grid, dim3(256), p->lds_a, st, p->dev, p->ya, bt.rb, r, u, d,
+                   pv, bt.Gp, it, part_dp, np_dp, gam, part_rmax, part_rr);
     return hip_status(hipGetLastError());
 }
 
