@@ -517,6 +517,10 @@ def parse():
     ap.add_argument("--jac-steps", type=int, default=4)
     ap.add_argument("--no-oracle-ref", action="store_true", help="skip the FP64 oracle reference of kappa_bar")
     ap.add_argument("--no-autotune", action="store_true", help="operator shapes by rule instead of the autotuner")
+    ap.add_argument("--march-shape", default="",
+                    help="TZ,RY,XB: pin the FP64 operator march shape of the 48-load step (e.g. the autotuner's "
+                         "pick of an earlier run) instead of tuning it; for counter runs, where the tuner's timings "
+                         "are distorted")
     ap.add_argument("--no-calls", action="store_true", help="skip the standalone fe_apply / uno_precond_apply rooflines")
     ap.add_argument("--cpu-workers", type=int, default=16,
                     help="most host cores the oracle's all-core baseline uses (one solve per core)")
@@ -704,9 +708,14 @@ def main():
 
     # ---------------- operator shapes: the project's autotuner ----------------
     tuned = {}
+    if args.march_shape:
+        tz, ry, xb = (int(v) for v in args.march_shape.split(","))
+        uno.set_operator_shape(SHAPE, nr_all, tz, ry, xb, kappa_per_rhs=True, dtype=torch.float64)
+        tuned["f64"] = dict(tz=tz, ry=ry, xb=xb, pinned=True)
     if not args.no_autotune:
         for tag, dtp in (("f64", torch.float64), ("f32", torch.float32)):
-            tuned[tag] = uno.autotune_operator(SHAPE, nr_all, kappa_per_rhs=True, dtype=dtp)
+            if tag not in tuned:
+                tuned[tag] = uno.autotune_operator(SHAPE, nr_all, kappa_per_rhs=True, dtype=dtp)
         log("autotuned operator march (64^3 x %d): %s" % (nr_all, tuned))
 
     # ---------------- timed: UNO-CG FP64 (headline) ----------------
