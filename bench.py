@@ -745,10 +745,23 @@ def main():
 
     # ---------------- mixed precision: FP32 operator / preconditioner ----------------
     f32 = dict(op_dtype=torch.float32, prec_dtype=torch.float32)
-    dtm, itsm, kbm = timed("uno", prec, 1, 0, tag="uno_cg_fp32", **f32)
+    dtm, itsm, kbm = timed("uno", prec, 2, 1, tag="uno_cg_fp32", **f32)
     kb_err = max(float(np.abs(a - b).max() / np.abs(b).max()) for a, b in zip(kbm, kbs[:nm]))
     log("UNO-CG FP32 op/prec: %.1f passes/solve, %.3f ms per solve, kappa_bar rel diff vs FP64 %.1e" %
         (np.mean(itsm), dtm / len(itsm) * 1e3, kb_err))
+    # where the FP32 step's time goes: every kernel family's summed launch
+    # time over one step (the restarts' FP64 operator applies and transforms
+    # are families of their own)
+    f32_fams = {uno.KT_MATVEC: "operator march (FP32, CG)", uno.KT_UPDATE: "pass A + update (FP32 d, p)",
+                uno.KT_FFT_MID: "pass B", uno.KT_FFT_INV: "pass C (FP32 s)",
+                uno.KT_APPLY: "FP64 operator applies (residual replacement, exit check)",
+                uno.KT_FFT_FWD: "pass A without update (restarts)"}
+    ft32, _ = family_times(uno, f32_fams, lambda: step("uno", prec, "all", "uno_cg_fp32", **f32)[0])
+    fp32_families = {name: {"ms_per_step": round(ft32[f][0], 3), "launches": int(ft32[f][1]),
+                            "us_per_launch": round(ft32[f][0] / max(ft32[f][1], 1) * 1e3, 2)}
+                     for f, name in f32_fams.items()}
+    log("FP32 step by family (ms): %s of %.2f ms" % ({k: v["ms_per_step"] for k, v in fp32_families.items()},
+                                                    dtm / 2 * 1e3))
 
     # ---------------- FANS (reference-medium preconditioner) for context ----------------
     pf = uno.UnoPrecond.fans(SHAPE, 0.5 * (cfg["k_matrix"] + cfg["k_incl"]))
@@ -877,6 +890,7 @@ def main():
         "jac_cg": {"passes_mean": float(np.mean(itsj)), "ms_per_solve": jac_t_solve, "dof_iters_per_s": jac_rate},
         "fans_cg": {"passes_mean": float(np.mean(itsf)), "ms_per_solve": dtf / len(itsf) * 1e3},
         "uno_cg_fp32": {"passes_mean": float(np.mean(itsm)), "ms_per_solve": dtm / len(itsm) * 1e3,
+                        "ms_per_step": dtm / 2 * 1e3, "kernel_families_one_step": fp32_families,
                         "kappa_bar_rel_diff_vs_fp64": kb_err},
         "kappa_bar_error_vs_fp64_oracle": oracle_err,
         "roofline_calls": calls,
