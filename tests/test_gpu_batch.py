@@ -49,6 +49,7 @@ CASES = [
     ((16, 12, 10), "uno", 2, 1),
     ((32, 32), "uno", 4, 0),
     ((32, 32), "jacobi", 0, 0),
+    ((8, 18, 150), "uno", 3, 0),
 ]
 
 

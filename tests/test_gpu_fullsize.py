@@ -3,8 +3,9 @@ configurations it times: the 128^3 elastic operator and c = 3 UNO apply
 against the oracle on every node, the six Mandel solves checked by
 properties that hold at any size (true residual, symmetry of the stiffness,
 Voigt and Reuss bounds, agreement of UNO-CG and Jacobi-CG), the 256-problem
-work list solved in one call, and the 64^3 x 48 thermal batch with three
-of its solutions checked node by node against the oracle's equations."""
+work list solved in one call, the 64^3 x 48 thermal batch with three of
+its solutions checked node by node against the oracle's equations, and
+the paper's 192^3 R = 5 size with one load per launch."""
 import numpy as np
 import pytest
 import torch
@@ -181,3 +182,38 @@ def test_headline_64_batch_of_48(orc, uno):
         ev = np.linalg.eigvalsh(0.5 * (ku + ku.T))
         voigt, reuss = k.mean(), 1.0 / (1.0 / k).mean()
         assert ev.max() <= voigt * (1 + 1e-9) and ev.min() >= reuss * (1 - 1e-9)
+
+
+def test_paper_size_192_one_load(orc, uno):
+    """The paper's thermal size and contrast (192^3, R = 5) in the launch
+    configuration of the benchmark's record: UNO-CG with M = 16, trained on
+    the Jacobi-CG solutions of the four training microstructures, one load
+    per launch, FP64 to 1e-6 -- pass A with twenty row chunks per slab and
+    ten rows per group, pass C with a few rows per workgroup.  The oracle's
+    rhs and operator check the solution on every node; the learned-mode
+    apply of one vector equals the oracle's full transform."""
+    cfg = dict(si.CONFIG_3D_192_R5)
+    shape = cfg["shape"]
+    print("192^3 R = 5 one load", flush=True)
+    loads = np.eye(3)
+    hs = uno.half_shape(shape)
+    A = torch.zeros(hs, dtype=torch.float64, device=DEV)
+    B = torch.zeros_like(A)
+    for seed in cfg["train_seeds"]:
+        kt = T(si.microstructure(cfg, seed)[0])
+        u2, _ = uno.pcg_solve_batch(kt, macro_loads=loads, kind="jacobi", rtol=1e-8, max_iter=50000)
+        F = torch.stack([uno.uno_macro_rhs(kt, loads[a]) for a in range(3)])
+        uno.uno_train_accumulate(F, u2, A, B, 3 * len(cfg["train_seeds"]))
+        del u2, F, kt
+    M = 16
+    th = uno.uno_train_fit(shape, M, A, B)
+    P = uno.UnoPrecond.create(shape, M, th)
+    k = si.microstructure(cfg, cfg["test_seed"])[0]
+    u, info = uno.pcg_solve(T(k), macro_load=loads[0], kind="uno", precond=P, rtol=1e-6, max_iter=50000)
+    assert info["converged"] and info["true_rel_res"] <= 1e-6 * (1 + 1e-6)
+    f = orc.rhs(k, loads[0])
+    res = f - orc.fe_apply(k, u.cpu().numpy())
+    assert np.abs(res).max() <= 1e-6 * (1 + 1e-6) * np.abs(f).max()
+    r = si.random_field(shape, 9)
+    s = P.apply(T(r)).cpu().numpy()
+    assert rel(s, orc.uno_apply(th, M, r)) < 1e-12

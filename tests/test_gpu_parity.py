@@ -67,6 +67,10 @@ UNO_CASES = [((8, 8), 2), ((12, 10), 3), ((15, 9), 2), ((10, 12, 8), 2), ((9, 15
 
 
 UNO_CASES += [((64, 64, 64), 12), ((32, 24, 20), 3), ((40, 36), 4), ((12, 9, 16), 1)]
+# long rows (n2 > 128): pass A takes twice the rows per group and prefetches
+# 8 elements per thread, pass C gets a few rows per workgroup; odd n2 (135)
+# leaves a point without a partner at z = 0 only
+UNO_CASES += [((10, 20, 150), 4), ((8, 18, 135), 3)]
 
 
 @pytest.mark.parametrize("path", [1, 2])
@@ -144,7 +148,8 @@ def test_pcg_2d_config1_matches_oracle(orc, uno, kind):
 
 
 @pytest.mark.parametrize("path", [1, 2, 3])
-@pytest.mark.parametrize("shape,M", [((32, 32), 4), ((16, 16, 16), 3), ((12, 10, 15), 2), ((24, 20, 16), 2)])
+@pytest.mark.parametrize("shape,M", [((32, 32), 4), ((16, 16, 16), 3), ((12, 10, 15), 2), ((24, 20, 16), 2),
+                                     ((8, 18, 150), 3)])
 def test_pcg_uno_matches_oracle(orc, uno, shape, M, path):
     ph, _ = si.rsa_inclusions(shape, 2, 4, 0.3, 21)
     kap = si.two_phase_kappa(ph, 1.0, 100.0)
