@@ -765,7 +765,7 @@ def main():
 
     # ---------------- FANS (reference-medium preconditioner) for context ----------------
     pf = uno.UnoPrecond.fans(SHAPE, 0.5 * (cfg["k_matrix"] + cfg["k_incl"]))
-    dtf, itsf, _ = timed("uno", pf, 1, 0, tag="fans_cg")
+    dtf, itsf, _ = timed("uno", pf, 1, 1, tag="fans_cg")
     log("FANS-CG: %.1f passes/solve, %.3f ms per solve" % (np.mean(itsf), dtf / len(itsf) * 1e3))
 
     # ---------------- dominant kernel: live HIP-event timing ----------------

@@ -200,11 +200,13 @@ uno_status pcg_solve(const uno_grid *grid, const uno_material *mat, const double
  * u (device, nrhs x n doubles) holds the initial guesses and receives the
  * zero-mean solutions; info (host, nullable) receives nrhs records.
  * Every pass kernel carries all right-hand sides (grid y), each with its own
- * scalars and stopping test: a load that has converged stops updating, and
- * every result equals that of pcg_solve on the same load (in the FP32 mode
- * the residual replacements of all loads happen together, so results agree
- * with pcg_solve to the tolerance, not bitwise).  Preconditioners without
- * the learned-mode passes are run load by load.
+ * scalars and stopping test: a load that has converged stops updating.
+ * Results equal those of pcg_solve on the same load bitwise when the
+ * batch's launch shapes are the single solve's (few loads on small grids);
+ * larger batches group the per-workgroup partial sums differently, which
+ * changes results by rounding only; in the FP32 mode the residual
+ * replacements of all loads happen together, so results agree with
+ * pcg_solve to the tolerance.  The spectral passes (FP64) are batched too.
  * 1 <= nrhs <= 256.  Returns UNO_ERR_BREAKDOWN if any load broke down (see
  * info).  Synchronous. */
 uno_status pcg_solve_batch(const uno_grid *grid, const uno_material *mat, int32_t kappa_per_rhs, int32_t nrhs,
@@ -312,8 +314,7 @@ typedef struct {
  * conductivity field and stopping test); the classes run concurrently,
  * up to 8 at once, each driven by a host thread of the library on a stream
  * of its own (created once per device, default priority), forked from and
- * joined back into `stream` by events (a preconditioner without the
- * learned-mode passes solves its class's load cases one at a time).
+ * joined back into `stream` by events.
  * Results are those of the classes solved one after another.  The library
  * gathers each class's fields into device memory it allocates for the
  * call, and caches the CG workspace per (grid, stream) (held until

@@ -426,7 +426,8 @@ struct Workspace {
     int kap32_cap = 0;        // fields it holds
     double* part = nullptr;   // 8 partial buffers: rmax, rs[2], dp, ss[2], ds[2]
     double2* spec = nullptr;
-    int64_t nspec = 0;
+    int64_t nspec = 0;  // spectral scratch per right-hand side (double2), for spec_cap of them
+    int spec_cap = 0;
     double2* lr_gp = nullptr; // learned-mode scratch per right-hand side
     double2* lr_h = nullptr;
     int64_t lr_ngp = 0, lr_nh = 0;
@@ -570,12 +571,15 @@ uno_status ws_get(const Grid& g, const FftPlan* plan, const LowRankPlan* lr, int
         if (hipMalloc(&w->part, sizeof(double) * 8 * (size_t)need * w->nrhs_cap) != hipSuccess) return UNO_ERR_NOMEM;
         w->npart = need;
     }
-    if (plan && plan->nspec > w->nspec) {
+    if (plan && (plan->nspec > w->nspec || w->spec_cap < w->nrhs_cap)) {
         ws_drop_graphs(w);
         (void)hipFree(w->spec);
         w->spec = nullptr;
-        if (hipMalloc(&w->spec, sizeof(double2) * plan->nspec) != hipSuccess) return UNO_ERR_NOMEM;
+        w->nspec = w->spec_cap = 0;
+        if (hipMalloc(&w->spec, sizeof(double2) * (size_t)plan->nspec * w->nrhs_cap) != hipSuccess)
+            return UNO_ERR_NOMEM;
         w->nspec = plan->nspec;
+        w->spec_cap = w->nrhs_cap;
     }
     if (lr) {
         int64_t ngp = 0, nh = 0;
@@ -721,8 +725,9 @@ static uno_status enqueue_pass(const Grid& g, Workspace* w, int kind, const uno_
     }
     CgIter it = iter_of(w, P, k, k0, rtol, hist_len, nb, ks);
     if (kind == UNO_PREC_UNO) {
-        if (sizeof(T) != sizeof(double) || nrhs != 1) return UNO_ERR_ARG;  // spectral passes: FP64, one rhs
-        uno_status e = uno_apply_passes(g, pc->plan, pc->table, UNO_F64, w->r, w->s, UNO_F64, w->spec, &it, &np_rs, st);
+        if (sizeof(T) != sizeof(double)) return UNO_ERR_ARG;  // spectral passes: FP64
+        uno_status e = uno_apply_passes(g, pc->plan, pc->table, UNO_F64, w->r, w->s, UNO_F64, w->spec, &it, &np_rs, st,
+                                        nrhs, w->nspec);
         if (e != UNO_OK) return e;
     }
     int np_dp;
@@ -1049,20 +1054,8 @@ uno_status pcg_run_batch(const Grid& g, const double* kappa, int64_t ks, int nrh
     const uno_precond* pc = (o->kind == UNO_PREC_UNO) ? o->uno : nullptr;
     const bool mixed = (o->op_t == UNO_F32);
     if (mixed && pc && !uno_use_lowrank(pc)) return UNO_ERR_ARG;
-    // one loop for all right-hand sides where every pass kernel takes them
-    // along grid y; the spectral passes and the FP32 restarts go one by one
-    const bool together = nrhs == 1 || !pc || uno_use_lowrank(pc);
-    if (!together) {
-        uno_status worst = UNO_OK;
-        for (int b = 0; b < nrhs; ++b) {
-            uno_status e = pcg_run_batch(g, kappa + b * ks, 0, 1, macro_loads3 ? macro_loads3 + 3 * b : nullptr,
-                                         rhs ? rhs + (int64_t)b * g.total : nullptr, u + (int64_t)b * g.total, o,
-                                         info ? info + b : nullptr, nullptr, st);
-            if (e == UNO_ERR_BREAKDOWN) worst = e;
-            else if (e != UNO_OK) return e;
-        }
-        return worst;
-    }
+    // one loop for all right-hand sides, every pass kernel taking them along
+    // grid y (the spectral passes too)
     Workspace* w = nullptr;
     std::unique_lock<std::mutex> lease;
     uno_status e = ws_get(g, pc ? &pc->plan : nullptr, pc ? pc->lr : nullptr, pc ? pc->rs_blocks : 0, o->max_iter + 1,
@@ -1501,6 +1494,7 @@ uno_status pcg_run_noalloc(const Grid& g, const double* kappa, const double* mac
     if (pc && !uno_use_lowrank(pc)) {
         w.spec = (double2*)take(2 * (size_t)pc->plan.nspec);
         w.nspec = pc->plan.nspec;
+        w.spec_cap = 1;
     }
     if (pc && pc->lr) {
         int64_t ngp = 0, nh = 0;

@@ -174,10 +174,15 @@ __device__ typename V2<T>::t* transform_lds(typename V2<T>::t* buf0, typename V2
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_fft_r2c_z(int64_t rows, int nl, AxisDev ax, int nh,
                                                       const T* __restrict__ x, typename V2<T>::t* __restrict__ S,
-                                                      CgIter it)
+                                                      int64_t sst, CgIter it)
 {
     using C = typename V2<T>::t;
     __shared__ double slots[kBlock / 64];
+    if (blockIdx.y > 0) {  // right-hand side blockIdx.y of a batch
+        x += (int64_t)blockIdx.y * it.vs;
+        S += (int64_t)blockIdx.y * sst;
+        it = rhs_iter(it);
+    }
     if (it.st && head_check(it, slots)) return;
     extern __shared__ __align__(16) unsigned char smem[];
     const int n = ax.n;
@@ -209,10 +214,14 @@ __global__ void __launch_bounds__(kBlock) k_fft_r2c_z(int64_t rows, int nl, Axis
 // table (same layout as S), inverse.
 template <typename T, int SIGN, bool MID, typename TT>
 __global__ void __launch_bounds__(kBlock) k_fft_strided(int64_t nlines, int64_t st, int nl, AxisDev ax,
-                                                        typename V2<T>::t* __restrict__ S, const TT* __restrict__ table,
-                                                        CgIter it)
+                                                        typename V2<T>::t* __restrict__ S, int64_t sst,
+                                                        const TT* __restrict__ table, CgIter it)
 {
     using C = typename V2<T>::t;
+    if (blockIdx.y > 0) {
+        S += (int64_t)blockIdx.y * sst;
+        it = rhs_iter(it);
+    }
     if (it.st && loop_ended(it.st, it.k)) return;
     extern __shared__ __align__(16) unsigned char smem[];
     const int n = ax.n;
@@ -260,10 +269,15 @@ __global__ void __launch_bounds__(kBlock) k_fft_strided(int64_t nlines, int64_t 
 // CG it also writes the per-workgroup partials of r.s (FP64).
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_fft_c2r_z(int64_t rows, int nl, AxisDev ax, int nh,
-                                                      const typename V2<T>::t* __restrict__ S, T* __restrict__ out,
-                                                      CgIter it)
+                                                      const typename V2<T>::t* __restrict__ S, int64_t sst,
+                                                      T* __restrict__ out, CgIter it)
 {
     using C = typename V2<T>::t;
+    if (blockIdx.y > 0) {
+        S += (int64_t)blockIdx.y * sst;
+        out += (int64_t)blockIdx.y * it.vs;
+        it = rhs_iter(it);
+    }
     if (it.st && loop_ended(it.st, it.k)) return;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double slots[kBlock / 64];
@@ -387,9 +401,12 @@ int fft_c2r_blocks(const Grid& g, const FftPlan& p)
     return (int)((pairs + nl - 1) / nl);
 }
 
+// nrhs right-hand sides along grid y: vectors at + b it.vs, spectra at
+// + b sst (one when itp is null)
 template <typename T, typename TT>
 static uno_status run_passes(const Grid& g, const FftPlan& p, const TT* table, const T* r, T* s,
-                             typename V2<T>::t* S, const CgIter* itp, int* np_rs, hipStream_t stream, bool f64)
+                             typename V2<T>::t* S, const CgIter* itp, int* np_rs, hipStream_t stream, bool f64,
+                             int nrhs, int64_t sst)
 {
     using C = typename V2<T>::t;
     CgIter it;
@@ -404,7 +421,8 @@ static uno_status run_passes(const Grid& g, const FftPlan& p, const TT* table, c
         int64_t pairs = (rows + 1) / 2;
         int nb = (int)((pairs + nl - 1) / nl);
         size_t sh = 2 * sizeof(C) * (size_t)nl * az.n;
-        uno_launch(UNO_KT_FFT_FWD, k_fft_r2c_z<T>, dim3(nb), dim3(kBlock), sh, stream, rows, nl, az, nh, r, S, it);
+        uno_launch(UNO_KT_FFT_FWD, k_fft_r2c_z<T>, dim3(nb, nrhs), dim3(kBlock), sh, stream, rows, nl, az, nh, r, S, sst,
+                   it);
         UNO_HIP(hipGetLastError());
     }
     // pass 2: y forward (st = nh, outer = n0)
@@ -414,8 +432,8 @@ static uno_status run_passes(const Grid& g, const FftPlan& p, const TT* table, c
         int64_t nlines = (int64_t)g.n[0] * nh;
         int nb = (int)((nlines + nl - 1) / nl);
         size_t sh = 2 * sizeof(C) * (size_t)nl * ay.n;
-        hipLaunchKernelGGL((k_fft_strided<T, -1, false, TT>), dim3(nb), dim3(kBlock), sh, stream, nlines, (int64_t)nh, nl,
-                           ay, S, table, it);
+        hipLaunchKernelGGL((k_fft_strided<T, -1, false, TT>), dim3(nb, nrhs), dim3(kBlock), sh, stream, nlines,
+                           (int64_t)nh, nl, ay, S, sst, table, it);
         UNO_HIP(hipGetLastError());
     }
     // pass 3: x forward, multiply, inverse (st = n1 nh, outer = 1)
@@ -425,8 +443,8 @@ static uno_status run_passes(const Grid& g, const FftPlan& p, const TT* table, c
         int64_t nlines = (int64_t)g.n[1] * nh;
         int nb = (int)((nlines + nl - 1) / nl);
         size_t sh = 2 * sizeof(C) * (size_t)nl * ax.n;
-        uno_launch(UNO_KT_FFT_MID, k_fft_strided<T, -1, true, TT>, dim3(nb), dim3(kBlock), sh, stream, nlines, nlines, nl,
-                   ax, S, table, it);
+        uno_launch(UNO_KT_FFT_MID, k_fft_strided<T, -1, true, TT>, dim3(nb, nrhs), dim3(kBlock), sh, stream, nlines,
+                   nlines, nl, ax, S, sst, table, it);
         UNO_HIP(hipGetLastError());
     }
     // pass 4: y inverse
@@ -435,8 +453,8 @@ static uno_status run_passes(const Grid& g, const FftPlan& p, const TT* table, c
         int64_t nlines = (int64_t)g.n[0] * nh;
         int nb = (int)((nlines + nl - 1) / nl);
         size_t sh = 2 * sizeof(C) * (size_t)nl * ay.n;
-        hipLaunchKernelGGL((k_fft_strided<T, +1, false, TT>), dim3(nb), dim3(kBlock), sh, stream, nlines, (int64_t)nh, nl,
-                           ay, S, table, it);
+        hipLaunchKernelGGL((k_fft_strided<T, +1, false, TT>), dim3(nb, nrhs), dim3(kBlock), sh, stream, nlines,
+                           (int64_t)nh, nl, ay, S, sst, table, it);
         UNO_HIP(hipGetLastError());
     }
     // pass 5
@@ -446,7 +464,8 @@ static uno_status run_passes(const Grid& g, const FftPlan& p, const TT* table, c
         int64_t pairs = (rows + 1) / 2;
         int nb = (int)((pairs + nl - 1) / nl);
         size_t sh = 2 * sizeof(C) * (size_t)nl * az.n;
-        uno_launch(UNO_KT_FFT_INV, k_fft_c2r_z<T>, dim3(nb), dim3(kBlock), sh, stream, rows, nl, az, nh, (const C*)S, s, it);
+        uno_launch(UNO_KT_FFT_INV, k_fft_c2r_z<T>, dim3(nb, nrhs), dim3(kBlock), sh, stream, rows, nl, az, nh,
+                   (const C*)S, sst, s, it);
         if (np_rs) *np_rs = nb;
         UNO_HIP(hipGetLastError());
     }
@@ -454,18 +473,20 @@ static uno_status run_passes(const Grid& g, const FftPlan& p, const TT* table, c
 }
 
 uno_status uno_apply_passes(const Grid& g, const FftPlan& p, const void* table, uno_dtype table_t, const void* r,
-                            void* s, uno_dtype vec_t, void* spec, const CgIter* it, int* np_rs, hipStream_t stream)
+                            void* s, uno_dtype vec_t, void* spec, const CgIter* it, int* np_rs, hipStream_t stream,
+                            int nrhs, int64_t sst)
 {
+    if (nrhs < 1 || (nrhs > 1 && !it)) return UNO_ERR_ARG;  // batches carry their strides in it
     if (vec_t == UNO_F64) {
         if (table_t != UNO_F64) return UNO_ERR_ARG;
         return run_passes<double, double>(g, p, (const double*)table, (const double*)r, (double*)s, (double2*)spec, it,
-                                          np_rs, stream, true);
+                                          np_rs, stream, true, nrhs, sst);
     }
     if (vec_t == UNO_F32) {
         if (it) return UNO_ERR_ARG;  // the FP32 path forms r.s in the CG update kernels
         if (table_t == UNO_F32)
             return run_passes<float, float>(g, p, (const float*)table, (const float*)r, (float*)s, (float2*)spec,
-                                            nullptr, nullptr, stream, false);
+                                            nullptr, nullptr, stream, false, 1, 0);
         return UNO_ERR_ARG;
     }
     return UNO_ERR_ARG;
@@ -485,7 +506,8 @@ uno_status fft_forward_real(const Grid& g, const FftPlan& p, const double* x, do
         int64_t pairs = (rows + 1) / 2;
         int nb = (int)((pairs + nl - 1) / nl);
         size_t sh = 2 * sizeof(double2) * (size_t)nl * az.n;
-        hipLaunchKernelGGL(k_fft_r2c_z<double>, dim3(nb), dim3(kBlock), sh, stream, rows, nl, az, nh, x, spec, none);
+        hipLaunchKernelGGL(k_fft_r2c_z<double>, dim3(nb), dim3(kBlock), sh, stream, rows, nl, az, nh, x, spec,
+                           (int64_t)0, none);
         UNO_HIP(hipGetLastError());
     }
     AxisDev ay = axis_dev(p.ax[1], true);
@@ -495,7 +517,7 @@ uno_status fft_forward_real(const Grid& g, const FftPlan& p, const double* x, do
         int nb = (int)((nlines + nl - 1) / nl);
         size_t sh = 2 * sizeof(double2) * (size_t)nl * ay.n;
         hipLaunchKernelGGL((k_fft_strided<double, -1, false, double>), dim3(nb), dim3(kBlock), sh, stream, nlines,
-                           (int64_t)nh, nl, ay, spec, (const double*)nullptr, none);
+                           (int64_t)nh, nl, ay, spec, (int64_t)0, (const double*)nullptr, none);
         UNO_HIP(hipGetLastError());
     }
     AxisDev ax = axis_dev(p.ax[0], true);
@@ -505,7 +527,7 @@ uno_status fft_forward_real(const Grid& g, const FftPlan& p, const double* x, do
         int nb = (int)((nlines + nl - 1) / nl);
         size_t sh = 2 * sizeof(double2) * (size_t)nl * ax.n;
         hipLaunchKernelGGL((k_fft_strided<double, -1, false, double>), dim3(nb), dim3(kBlock), sh, stream, nlines,
-                           nlines, nl, ax, spec, (const double*)nullptr, none);
+                           nlines, nl, ax, spec, (int64_t)0, (const double*)nullptr, none);
         UNO_HIP(hipGetLastError());
     }
     return UNO_OK;

@@ -128,10 +128,12 @@ struct CgIter;  // per-pass control of the CG loop (cg_ctl.h)
 // the vector precision.  it != nullptr: the passes belong to CG pass it->k,
 // the first one runs the convergence test of that pass, every one returns at
 // once when the loop has ended, and the last one writes per-workgroup r.s
-// partials (their count is returned in *np_rs).
+// partials (their count is returned in *np_rs).  nrhs > 1 (FP64 inside CG
+// only): right-hand side b along grid y, its vectors at + b it->vs, its
+// spectrum at + b sst.
 uno_status uno_apply_passes(const Grid& g, const FftPlan& p, const void* table, uno_dtype table_t,
                             const void* r, void* s, uno_dtype vec_t, void* spec, const CgIter* it, int* np_rs,
-                            hipStream_t stream);
+                            hipStream_t stream, int nrhs = 1, int64_t sst = 0);
 
 // Forward transform of nbatch real fields into half spectra (training).
 uno_status fft_forward_real(const Grid& g, const FftPlan& p, const double* x, double2* spec,
