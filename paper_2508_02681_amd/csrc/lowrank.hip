@@ -362,16 +362,53 @@ __global__ void __launch_bounds__(256) k_lr_mid(LowRankDev L, int nch, const dou
     }
     for (int q = threadIdx.x + 256 * kMidQB; q < ng; q += 256) gx[q] = gather(q);
     __syncthreads();
-    // X[kx][cl] = C(k) sum_x g[x] exp(-2 pi i (kx - mx) x / n0)
+    // X[kx][cl] = C(k) sum_x g[x] exp(-2 pi i (kx - mx) x / n0).  With few
+    // (kx, column) items per workgroup (few columns per workgroup: few
+    // right-hand sides) the x range is cut into P parts of at least 8
+    // points, each a Horner chain of its own times the phase of its first
+    // point, added in part order: P times shorter dependent chains
     double corr = 0.0;
-    for (int o = threadIdx.x; o < L.kxn * CB; o += 256) {
-        const int cl = o % CB, kxi = o / CB;
-        const int col = col0 + cl;
-        const double2 w = L.twx[mod_n(kxi - L.mx, L.n0)];
-        const double2 v = horner_eo(gx + cl, CB, L.n0, w);
-        const double c = (col < plane) ? C[(int64_t)kxi * plane + col] : 0.0;
-        X[o] = make_double2(v.x * c, v.y * c);
-        corr += c * (v.x * v.x + v.y * v.y);
+    const int items = L.kxn * CB;
+    int P = 256 / items;
+    if (P > 8) P = 8;
+    if (P > L.n0 / 8) P = L.n0 / 8;
+    if (P <= 1) {
+        for (int o = threadIdx.x; o < items; o += 256) {
+            const int cl = o % CB, kxi = o / CB;
+            const int col = col0 + cl;
+            const double2 w = L.twx[mod_n(kxi - L.mx, L.n0)];
+            const double2 v = horner_eo(gx + cl, CB, L.n0, w);
+            const double c = (col < plane) ? C[(int64_t)kxi * plane + col] : 0.0;
+            X[o] = make_double2(v.x * c, v.y * c);
+            corr += c * (v.x * v.x + v.y * v.y);
+        }
+    } else {
+        double2* Xp = X + items;  // P x items partial sums (P items <= 256)
+        const int len = (L.n0 + P - 1) / P;
+        for (int o = threadIdx.x; o < P * items; o += 256) {
+            const int part = o / items, oi = o - part * items;
+            const int cl = oi % CB, kx = oi / CB - L.mx;
+            const int x0 = part * len, m = min(len, L.n0 - x0);
+            double2 v = make_double2(0.0, 0.0);
+            if (m > 0) {
+                v = horner_eo(gx + x0 * CB + cl, CB, m, L.twx[mod_n(kx, L.n0)]);
+                v = cmul(v, L.twx[mod_n(kx * x0, L.n0)]);  // exp(-2 pi i kx x0 / n0)
+            }
+            Xp[o] = v;
+        }
+        __syncthreads();
+        for (int o = threadIdx.x; o < items; o += 256) {
+            double2 v = Xp[o];
+            for (int part = 1; part < P; ++part) {
+                v.x += Xp[part * items + o].x;
+                v.y += Xp[part * items + o].y;
+            }
+            const int cl = o % CB, kxi = o / CB;
+            const int col = col0 + cl;
+            const double c = (col < plane) ? C[(int64_t)kxi * plane + col] : 0.0;
+            X[o] = make_double2(v.x * c, v.y * c);
+            corr += c * (v.x * v.x + v.y * v.y);
+        }
     }
     if (part_corr) {
         const double b = block_reduce<OpSum>(corr, slots);
@@ -1165,7 +1202,7 @@ uno_status lowrank_create(const Grid& g, const FftPlan& fp, int M, double W, con
     p->cb_mid = 8;
     while (p->cb_mid > 1 && sizeof(double2) * (size_t)nc * p->cb_mid * (L.n0 + L.kxn) > 48 * 1024) p->cb_mid /= 2;
     p->blocks_mid = (L.kyn * L.kzn + p->cb_mid - 1) / p->cb_mid;
-    p->lds_b = sizeof(double2) * (size_t)nc * p->cb_mid * (L.n0 + L.kxn);
+    p->lds_b = sizeof(double2) * ((size_t)nc * p->cb_mid * (L.n0 + L.kxn) + 256);
     // pass C takes up to 64 rows per workgroup when many right-hand sides
     // fill the chip (fewer loads of the H plane per node, longer z chains)
     p->yc_max = p->yc;
@@ -1356,7 +1393,7 @@ static void launch_mid(const LowRankPlan* p, const LrBatch& bt, int cb, const Cg
 {
     const LowRankDev& L = p->dev;
     const dim3 grid((L.kyn * L.kzn + cb - 1) / cb, bt.nrhs), blk(256);
-    const size_t lds = sizeof(double2) * (size_t)cb * (L.n0 + L.kxn);
+    const size_t lds = sizeof(double2) * ((size_t)cb * (L.n0 + L.kxn) + 256);  // + the x-range partials
     const double* C = (const double*)p->table;
     const double2* Gp = bt.Gp;
     switch (cb) {
