@@ -107,7 +107,10 @@ __global__ void __launch_bounds__(256) k_lr_fwd(LowRankDev L, int ya, int rb, do
     // decisions after
     StateLoad sl;
     double dp_share = 0.0, gk = 0.0;
-    double rv[PF], pv[PF], uv[PF], dv[PF];
+    // d and p stay in their storage type until used: a conversion at the
+    // load would wait for it and serialise the prefetch with the transform
+    double rv[PF], uv[PF];
+    TD pv[PF], dv[PF];
     if (UPDATE) {
         sl = load_state(it.st);
         dp_share = load_share<OpSum>(part_dp, np_dp);
@@ -121,13 +124,14 @@ __global__ void __launch_bounds__(256) k_lr_fwd(LowRankDev L, int ya, int rb, do
 #pragma unroll
         for (int j = 0; j < PF; ++j) {
             const int q = threadIdx.x + 256 * j;
-            rv[j] = pv[j] = uv[j] = dv[j] = 0.0;
+            rv[j] = uv[j] = 0.0;
+            pv[j] = dv[j] = TD(0);
             if (q < ny * L.n2) {
                 rv[j] = r[base + q];
                 if (UPDATE) {
-                    pv[j] = (double)p[base + q];
+                    pv[j] = p[base + q];
                     uv[j] = u[base + q];
-                    dv[j] = (double)d[base + q];
+                    dv[j] = d[base + q];
                 }
             }
         }
@@ -163,9 +167,9 @@ __global__ void __launch_bounds__(256) k_lr_fwd(LowRankDev L, int ya, int rb, do
                 if (q < cnt) {
                     double v = rv[j];
                     if (UPDATE) {
-                        v = rv[j] - alpha * pv[j];
+                        v = rv[j] - alpha * (double)pv[j];
                         r[base + q] = v;
-                        u[base + q] = uv[j] + alpha * dv[j];
+                        u[base + q] = uv[j] + alpha * (double)dv[j];
                         m = OpMax::apply(m, fabs(v));
                     }
                     R[rq[j]] = v;
