@@ -112,8 +112,10 @@ struct MeanFree {
 // The kernel: a workgroup owns a TY x TZ footprint (TY = RY 256 / TZ) and xb
 // consecutive node planes along x, and sweeps the input planes x0 - 1 ..
 // x0 + xb.  Input node plane xi (with a one-node halo in y and z) and voxel
-// plane xi stream through two LDS buffers, the loads of plane xi + 1 in
-// flight while plane xi is used, one barrier per plane.  Each thread keeps
+// plane xi stream through two LDS buffers, the loads of planes xi + 1 and
+// xi + 2 in flight while plane xi is used (a workgroup's sweep is a chain of
+// dependent steps, and a few workgroups per CU hold the chip's memory
+// parallelism), one barrier per plane.  Each thread keeps
 // three partial sums: input plane xi contributes to the outputs at xi + 1
 // (started), xi and xi - 1 (complete after it), so only the 3 x 3
 // neighbourhood of one plane and the 2 x 2 conductivities of two voxel
@@ -191,12 +193,16 @@ __global__ void __launch_bounds__(256) k_stencil_march(GridDev g, MarchGeom mg, 
         if constexpr (NEAR) return wrap_near(v, n);
         else return wrap_mod(v, n);
     };
-    // this thread's staging offsets within a plane (y, z wrapped once)
+    // this thread's staging offsets within a plane (y, z wrapped once);
+    // slots past the staged plane read its first node and are not stored,
+    // so that every load is unconditional (no branch between the loads of
+    // a plane and their use, which lets the next plane's loads stay in
+    // flight across the wait for this one's)
     int doff[PD], koff[PK];
 #pragma unroll
     for (int j = 0; j < PD; ++j) {
         const int q = threadIdx.x + 256 * j;
-        doff[j] = -1;
+        doff[j] = 0;
         if (q < ND) {
             const int zl = q % DZ, yl = q / DZ;
             doff[j] = wrapc(y0 - 1 + yl, g.n1) * g.n2 + wrapc(z0 - 1 + zl, g.n2);
@@ -205,7 +211,7 @@ __global__ void __launch_bounds__(256) k_stencil_march(GridDev g, MarchGeom mg, 
 #pragma unroll
     for (int j = 0; j < PK; ++j) {
         const int q = threadIdx.x + 256 * j;
-        koff[j] = -1;
+        koff[j] = 0;
         if (q < NK) {
             const int zl = q % KZ, yl = q / KZ;
             koff[j] = wrapc(y0 - 1 + yl, g.n1) * g.n2 + wrapc(z0 - 1 + zl, g.n2);
@@ -215,20 +221,22 @@ __global__ void __launch_bounds__(256) k_stencil_march(GridDev g, MarchGeom mg, 
     // not yet written, so s stands in for it (s + 0 s = s exactly)
     const T* __restrict__ dsrc = (CG && it.k > it.k0) ? dold : s;
     const int64_t pl = (int64_t)g.n1 * g.n2;
-    T sv[PD], dv[PD], kv[PK];
+    // a plane's values in registers between its load and its LDS store; two
+    // sets, so that the loads of two planes are in flight during each step
+    struct Stage {
+        T s[PD], d[PD], k[PK];
+    };
+    Stage ra, rb;
     // node plane xp and voxel plane xp (voxel xp lies between node planes xp and xp + 1)
-    auto load = [&](int xp) {
+    auto load = [&](Stage& R, int xp) {
         const int64_t base = (int64_t)wrapc(xp, g.n0) * pl;
 #pragma unroll
         for (int j = 0; j < PD; ++j) {
-            sv[j] = dv[j] = (T)0;
-            if (doff[j] >= 0) {
-                sv[j] = s[base + doff[j]];
-                if (CG) dv[j] = dsrc[base + doff[j]];
-            }
+            R.s[j] = s[base + doff[j]];
+            if (CG) R.d[j] = dsrc[base + doff[j]];
         }
 #pragma unroll
-        for (int j = 0; j < PK; ++j) kv[j] = (koff[j] >= 0) ? kappa[base + koff[j]] : (T)0;
+        for (int j = 0; j < PK; ++j) R.k[j] = kappa[base + koff[j]];
     };
 
     // loads first: loop state, partials, previous gamma and the first plane
@@ -244,7 +252,8 @@ __global__ void __launch_bounds__(256) k_stencil_march(GridDev g, MarchGeom mg, 
             if (it.k > it.k0) dsum_share = load_share<OpSum>(mf.part_dold, gridDim.x);
         }
     }
-    load(x0 - 1);
+    load(ra, x0 - 1);
+    load(rb, x0);  // the sweep has at least three input planes (xe > x0)
     T beta = 0;
     bool first = true;
     if (CG) {
@@ -273,19 +282,19 @@ __global__ void __launch_bounds__(256) k_stencil_march(GridDev g, MarchGeom mg, 
     // the same in every lane: held in scalar registers
     beta = wave_uniform(beta);
     shift = wave_uniform(shift);
-    auto put = [&](int slot) {
+    auto put = [&](const Stage& R, int slot) {
 #pragma unroll
         for (int j = 0; j < PD; ++j) {
             const int q = threadIdx.x + 256 * j;
-            if (q < ND) Dr[slot][q] = (CG ? sv[j] + beta * dv[j] : sv[j]) - shift;
+            if (q < ND) Dr[slot][q] = (CG ? R.s[j] + beta * R.d[j] : R.s[j]) - shift;
         }
 #pragma unroll
         for (int j = 0; j < PK; ++j) {
             const int q = threadIdx.x + 256 * j;
-            if (q < NK) Kr[slot][q] = kv[j];
+            if (q < NK) Kr[slot][q] = R.k[j];
         }
     };
-    put(0);
+    put(ra, 0);
     __syncthreads();
 
     const int tz = threadIdx.x % TZ, ty = threadIdx.x / TZ * RY;  // first of the thread's RY rows
@@ -301,66 +310,77 @@ __global__ void __launch_bounds__(256) k_stencil_march(GridDev g, MarchGeom mg, 
     for (int j = 0; j < RY; ++j) acc_prev[j] = acc_cur[j] = dc_prev[j] = (T)0;
     double dot = 0.0, dsum_own = 0.0;
     const int nsteps = xe - x0 + 2;
-    for (int t = 0; t < nsteps; ++t) {
-        const int xi = x0 - 1 + t;
-        const int slot = t & 1;
-        const bool more = t + 1 < nsteps;
-        if (more) load(xi + 1);  // next plane in flight while this one is used
-        T D[RY + 2][3], kp[RY + 1][2];
+    // steps in pairs, so that the two register sets swap roles statically:
+    // at step t, `next` holds plane xi + 1 (stored to LDS after the step's
+    // arithmetic) and `ahead` receives plane xi + 2
+    for (int t0 = 0; t0 < nsteps; t0 += 2) {
 #pragma unroll
-        for (int bb = 0; bb < RY + 2; ++bb)
+        for (int h = 0; h < 2; ++h) {
+            const int t = t0 + h;
+            if (t >= nsteps) break;
+            Stage& next = h ? ra : rb;
+            Stage& ahead = h ? rb : ra;
+            const int xi = x0 - 1 + t;
+            const int slot = t & 1;
+            const bool more = t + 1 < nsteps;
+            // (the last two steps reload plane xe, recently read: no branch)
+        load(ahead, min(xi + 2, xe));
+            T D[RY + 2][3], kp[RY + 1][2];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) D[bb][c] = Dr[slot][(ty + bb) * DZ + tz + c];
-        const bool has_kp = xi < xe;  // voxel planes x0 - 1 .. xe - 1
+            for (int bb = 0; bb < RY + 2; ++bb)
 #pragma unroll
-        for (int bb = 0; bb < RY + 1; ++bb)
+                for (int c = 0; c < 3; ++c) D[bb][c] = Dr[slot][(ty + bb) * DZ + tz + c];
+            const bool has_kp = xi < xe;  // voxel planes x0 - 1 .. xe - 1
 #pragma unroll
-            for (int c = 0; c < 2; ++c) kp[bb][c] = has_kp ? Kr[slot][(ty + bb) * KZ + tz + c] : (T)0;
+            for (int bb = 0; bb < RY + 1; ++bb)
 #pragma unroll
-        for (int j = 0; j < RY; ++j) {
-            // row sums of w d along z per voxel column over rows j .. j + 2
-            // of the staged plane (j + 1 the output's own row), neighbour-
-            // plane (rh) and same-plane (rl) weights; face (sy, sz) adds rows
-            // sy and sy + 1.  Outputs xi - 1 (through voxel plane xi - 1), xi
-            // (both) and xi + 1 (xi)
-            T rh[3][2], rl[3][2];
+                for (int c = 0; c < 2; ++c) kp[bb][c] = has_kp ? Kr[slot][(ty + bb) * KZ + tz + c] : (T)0;
 #pragma unroll
-            for (int bb = 0; bb < 3; ++bb)
+            for (int j = 0; j < RY; ++j) {
+                // row sums of w d along z per voxel column over rows j .. j + 2
+                // of the staged plane (j + 1 the output's own row), neighbour-
+                // plane (rh) and same-plane (rl) weights; face (sy, sz) adds rows
+                // sy and sy + 1.  Outputs xi - 1 (through voxel plane xi - 1), xi
+                // (both) and xi + 1 (xi)
+                T rh[3][2], rl[3][2];
 #pragma unroll
-                for (int c = 0; c < 2; ++c) {
-                    const int m0 = ((bb != 1) << 1) | (c != 1), m1 = ((bb != 1) << 1) | (c + 1 != 1);
-                    rh[bb][c] = (T)g.w[4 | m0] * D[j + bb][c] + (T)g.w[4 | m1] * D[j + bb][c + 1];
-                    rl[bb][c] = (T)g.w[m0] * D[j + bb][c] + (T)g.w[m1] * D[j + bb][c + 1];
+                for (int bb = 0; bb < 3; ++bb)
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) {
+                        const int m0 = ((bb != 1) << 1) | (c != 1), m1 = ((bb != 1) << 1) | (c + 1 != 1);
+                        rh[bb][c] = (T)g.w[4 | m0] * D[j + bb][c] + (T)g.w[4 | m1] * D[j + bb][c + 1];
+                        rl[bb][c] = (T)g.w[m0] * D[j + bb][c] + (T)g.w[m1] * D[j + bb][c + 1];
+                    }
+                T accA = acc_prev[j], accB = acc_cur[j], accC = 0;
+#pragma unroll
+                for (int sy = 0; sy < 2; ++sy)
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) {
+                        const T eh = rh[sy][c] + rh[sy + 1][c], el = rl[sy][c] + rl[sy + 1][c];
+                        accA += km[j + sy][c] * eh;
+                        accB += (km[j + sy][c] + kp[j + sy][c]) * el;
+                        accC += kp[j + sy][c] * eh;
+                    }
+                if (t >= 2 && yz_ok[j]) {  // output xi - 1 is complete
+                    const int64_t i = (int64_t)(xi - 1) * pl + (int64_t)(y0 + ty + j) * g.n2 + z;
+                    p[i] = accA;
+                    if (CG) {
+                        dnew[i] = dc_prev[j];
+                        dot += (double)dc_prev[j] * (double)accA;
+                        if (MF) dsum_own += (double)dc_prev[j];
+                    }
                 }
-            T accA = acc_prev[j], accB = acc_cur[j], accC = 0;
-#pragma unroll
-            for (int sy = 0; sy < 2; ++sy)
-#pragma unroll
-                for (int c = 0; c < 2; ++c) {
-                    const T eh = rh[sy][c] + rh[sy + 1][c], el = rl[sy][c] + rl[sy + 1][c];
-                    accA += km[j + sy][c] * eh;
-                    accB += (km[j + sy][c] + kp[j + sy][c]) * el;
-                    accC += kp[j + sy][c] * eh;
-                }
-            if (t >= 2 && yz_ok[j]) {  // output xi - 1 is complete
-                const int64_t i = (int64_t)(xi - 1) * pl + (int64_t)(y0 + ty + j) * g.n2 + z;
-                p[i] = accA;
-                if (CG) {
-                    dnew[i] = dc_prev[j];
-                    dot += (double)dc_prev[j] * (double)accA;
-                    if (MF) dsum_own += (double)dc_prev[j];
-                }
+                acc_prev[j] = accB;  // (meaningful from t = 1 while xi < xe)
+                dc_prev[j] = D[j + 1][1];
+                acc_cur[j] = accC;   // (meaningful while xi + 1 < xe)
             }
-            acc_prev[j] = accB;  // (meaningful from t = 1 while xi < xe)
-            dc_prev[j] = D[j + 1][1];
-            acc_cur[j] = accC;   // (meaningful while xi + 1 < xe)
+#pragma unroll
+            for (int bb = 0; bb < RY + 1; ++bb)
+#pragma unroll
+                for (int c = 0; c < 2; ++c) km[bb][c] = kp[bb][c];
+            if (more) put(next, slot ^ 1);
+            __syncthreads();
         }
-#pragma unroll
-        for (int bb = 0; bb < RY + 1; ++bb)
-#pragma unroll
-            for (int c = 0; c < 2; ++c) km[bb][c] = kp[bb][c];
-        if (more) put(slot ^ 1);
-        __syncthreads();
     }
     if (CG) {
         const double bd = block_reduce<OpSum>(dot, slots);
