@@ -652,8 +652,11 @@ Parts parts_of(Workspace* w)
 }
 
 // np_update: workgroups of the update kernel (they write the ||r||_inf
-// partials read at the head of pass k > k0; pass k0 reads the init kernel's)
-CgIter iter_of(Workspace* w, const Parts& P, int k, int k0, double rtol, int hist_len, int np_update, int64_t ks)
+// partials read at the head of pass k > kr; pass kr, the last pass whose
+// residual the init kernel took (0, a residual replacement or a restart),
+// reads the init kernel's)
+CgIter iter_of(Workspace* w, const Parts& P, int k, int k0, int kr, double rtol, int hist_len, int np_update,
+               int64_t ks)
 {
     CgIter it;
     memset(&it, 0, sizeof(it));
@@ -661,7 +664,7 @@ CgIter iter_of(Workspace* w, const Parts& P, int k, int k0, double rtol, int his
     it.k0 = k0;
     it.st = w->state;
     it.part_rmax = P.rmax;
-    it.np_rmax = (k == k0) ? w->nbr : np_update;
+    it.np_rmax = (k == kr) ? w->nbr : np_update;
     it.rtol = rtol;
     it.hist = w->hist;
     it.hist_len = hist_len;
@@ -688,7 +691,7 @@ LrBatch lr_batch(Workspace* w, const uno_precond* pc, int nrhs)
 // and every reduction stay FP64.
 template <typename T>
 static uno_status enqueue_pass(const Grid& g, Workspace* w, int kind, const uno_precond* pc, const T* kappa,
-                               int64_t ks, double* u, int k, int k0, double rtol, int hist_len, int nrhs,
+                               int64_t ks, double* u, int k, int k0, int kr, double rtol, int hist_len, int nrhs,
                                hipStream_t st)
 {
     const Parts P = parts_of(w);
@@ -700,7 +703,7 @@ static uno_status enqueue_pass(const Grid& g, Workspace* w, int kind, const uno_
     int np_rs = nb;
     const MeanFree mf{P.ss[k & 1], P.ds[k & 1], P.ds[(k + 1) & 1]};
     if (kind == UNO_PREC_UNO && uno_use_lowrank(pc)) {
-        CgIter it = iter_of(w, P, k, k0, rtol, hist_len, lowrank_update_blocks(pc->lr, nrhs), ks);
+        CgIter it = iter_of(w, P, k, k0, kr, rtol, hist_len, lowrank_update_blocks(pc->lr, nrhs), ks);
         const LrBatch bt = lr_batch(w, pc, nrhs);
         if constexpr (sizeof(T) == sizeof(double)) {
             if (uno_use_fused(pc)) {
@@ -723,7 +726,7 @@ static uno_status enqueue_pass(const Grid& g, Workspace* w, int kind, const uno_
         UNO_HIP(hipGetLastError());
         return lowrank_update_forward<T>(pc->lr, w->r, u, dnew, pv, it, P.dp, np_dp, w->gam, P.rmax, nullptr, bt, st);
     }
-    CgIter it = iter_of(w, P, k, k0, rtol, hist_len, nb, ks);
+    CgIter it = iter_of(w, P, k, k0, kr, rtol, hist_len, nb, ks);
     if (kind == UNO_PREC_UNO) {
         if (sizeof(T) != sizeof(double)) return UNO_ERR_ARG;  // spectral passes: FP64
         uno_status e = uno_apply_passes(g, pc->plan, pc->table, UNO_F64, w->r, w->s, UNO_F64, w->spec, &it, &np_rs, st,
@@ -756,13 +759,17 @@ static uno_status enqueue_pass(const Grid& g, Workspace* w, int kind, const uno_
 }
 
 // Residual replacement of the FP32 mode: when ||r|| has dropped by this
-// factor since the last (re)start, r is recomputed as f - A u in FP64 and
-// the recurrence restarts (d = s).  FP32 stencil sums lose accuracy on smooth
-// directions (cancellation ~ 1e-7 cond(A)); the restart keeps the recursive
-// residual equal to the true one.  The factor was chosen by measurement
-// (64^3 x 48 loads to 1e-6, FP32 ms per solve: 1e-1.5 0.81, 1e-2 0.73,
-// 1e-2.5 0.94, 1e-3 0.83, 1e-4 0.77, 1e-5 0.85 with 140 instead of 104
-// passes); short cycles also keep the last cycle's drift small.
+// factor since the last replacement, r is recomputed as f - A u in FP64 and
+// the recurrence continues with it (the search direction is kept: the
+// replaced residual differs from the recursive one by the FP32 operator's
+// rounding only, so the directions stay conjugate to that accuracy and no
+// Krylov space is lost, the reliable update of van der Vorst and Ye).  FP32
+// stencil sums lose accuracy on smooth directions (cancellation ~ 1e-7
+// cond(A)); the replacement keeps the recursive residual equal to the true
+// one.  The factor was chosen by measurement when a replacement also
+// restarted the direction (64^3 x 48 loads to 1e-6, FP32 ms per solve:
+// 1e-1.5 0.81, 1e-2 0.73, 1e-2.5 0.94, 1e-3 0.83, 1e-4 0.77, 1e-5 0.85);
+// short cycles also keep the last cycle's drift small.
 constexpr double kRestartFactor = 1e-2;
 
 // r = f - A u in FP64 for every right-hand side (A u goes to p, which the
@@ -780,20 +787,22 @@ static void replace_residual(const Grid& g, Workspace* w, const double* kappa64,
                        (const double*)w->p, w->r);
 }
 
-// Host side of the chunked CG loop (thermal and elastic).  pass(k, k0)
-// enqueues CG pass k of the cycle that started at pass k0, check(k, k0) the
-// convergence test after a chunk's last pass; the host reads the loop states
-// between chunks.  FP32 mode (restarts): residual() forms r = f - A u in
-// FP64 (the product in w->p), start(reset, k) restarts the recurrence at
-// pass k from w->r, true_res() writes ||f - A u||_inf and ||f||_inf of the
-// product in w->p into the states.  A residual replacement restarts every
-// right-hand side together (one pass index k0 for all) as soon as one of the
-// running ones has dropped by kRestartFactor since its last (re)start; a
-// restart earlier than a load needs costs it part of its Krylov space, not
-// accuracy, and loads that have ended keep their state.  When every load has
-// ended, a load whose true residual is still above its tolerance (the
-// recursive residual of the last cycle drifts from it by the FP32
-// operator's rounding) is reopened from that residual.
+// Host side of the chunked CG loop (thermal and elastic).  pass(k, k0, kr)
+// enqueues CG pass k of the cycle that started at pass k0 (d = s there),
+// the residual last taken by the init kernel at pass kr; check(k, k0, kr)
+// the convergence test after a chunk's last pass; the host reads the loop
+// states between chunks.  FP32 mode (restarts): residual() forms
+// r = f - A u in FP64 (the product in w->p), start(reset, k) takes the
+// residual in w->r at pass k (s = P r and the partials pass k reads),
+// true_res() writes ||f - A u||_inf and ||f||_inf of the product in w->p
+// into the states.  A residual replacement replaces the residual of every
+// running right-hand side together (at one pass index kr for all) as soon
+// as one of them has dropped by kRestartFactor since its last replacement;
+// the search directions continue, and loads that have ended keep their
+// state.  When every load has ended, a load whose true residual is still
+// above its tolerance (the recursive residual of the last cycle drifts from
+// it by the FP32 operator's rounding) is reopened from that residual, with
+// a restarted direction (k0 = k: its d is that of its last pass).
 // Graph mode (key non-empty): after the first chunk, passes run as replays
 // of one captured chunk of kGraphPasses passes (recorded once per
 // workspace and key, the key holding every argument the passes are
@@ -826,7 +835,7 @@ static uno_status graph_exec(Workspace* w, const std::vector<int64_t>& key, Pass
     uno_status e = UNO_OK;
     // recorded at offsets 0 .. kGraphPasses - 1 with k0 = -1: every captured
     // pass lies past the first pass of its cycle
-    for (int j = 0; j < kGraphPasses && e == UNO_OK; ++j) e = pass(j, -1, cs);
+    for (int j = 0; j < kGraphPasses && e == UNO_OK; ++j) e = pass(j, -1, -1, cs);
     if (e == UNO_OK) hipLaunchKernelGGL(k_advance_pass, dim3(1), dim3(64), 0, cs, w->kdev, kGraphPasses);
     w->capture_kdev = nullptr;
     const hipError_t ec = hipStreamEndCapture(cs, &graph);
@@ -851,7 +860,7 @@ static uno_status run_chunks(Workspace* w, const uno_solve_opts* o, int nrhs, bo
 {
     const int chunk0 = o->graph_chunk > 0 ? o->graph_chunk : 8;
     const bool graphs = !graph_key.empty() && w->kdev && !restarts && chunk0 % 2 == 0;
-    int k = 0, k0 = 0, chunk = chunk0;
+    int k = 0, k0 = 0, kr = 0, chunk = chunk0;
     std::vector<int> prev_k(nrhs, -1);
     std::vector<double> prev_r(nrhs, -1.0);
     std::vector<double> cycle_r(nrhs, -1.0);
@@ -878,10 +887,10 @@ static uno_status run_chunks(Workspace* w, const uno_solve_opts* o, int nrhs, bo
             }
         }
         for (; c < chunk; ++c, ++k) {
-            e = pass(k, k0, st);
+            e = pass(k, k0, kr, st);
             if (e != UNO_OK) return e;
         }
-        check(k, k0);
+        check(k, k0, kr);
         UNO_HIP(hipGetLastError());
         if ((e = read_states()) != UNO_OK) return e;
         bool running = false;
@@ -905,7 +914,7 @@ static uno_status run_chunks(Workspace* w, const uno_solve_opts* o, int nrhs, bo
             if (reopen) {
                 UNO_HIP(hipMemcpyAsync(w->state, w->host_state, sizeof(CgState) * nrhs, hipMemcpyHostToDevice, st));
                 if ((e = start(0, k)) != UNO_OK) return e;
-                k0 = k;
+                k0 = kr = k;
                 chunk = chunk0;
                 continue;
             }
@@ -920,7 +929,8 @@ static uno_status run_chunks(Workspace* w, const uno_solve_opts* o, int nrhs, bo
                 if (hs.rmax_last <= kRestartFactor * cycle_r[b]) due = true;
             }
             if (due) {
-                // residual replacement, every load at once, restart at pass k
+                // residual replacement, every load at once, at pass k; the
+                // search direction continues (k0 kept)
                 residual();
                 for (int b = 0; b < nrhs; ++b) {
                     const CgState& hs = w->host_state[b];
@@ -929,7 +939,7 @@ static uno_status run_chunks(Workspace* w, const uno_solve_opts* o, int nrhs, bo
                     prev_r[b] = -1.0;
                 }
                 if ((e = start(0, k)) != UNO_OK) return e;
-                k0 = k;
+                kr = k;
                 chunk = chunk0;
                 continue;
             }
@@ -940,7 +950,11 @@ static uno_status run_chunks(Workspace* w, const uno_solve_opts* o, int nrhs, bo
             // quarters of the prediction: a pass launched after every load
             // has ended costs about as much as one more host check, and the
             // rate over one chunk is noisy (64^3 x 48 loads: 112 passes
-            // launched for 106 needed, against 127 with a 5 % margin)
+            // launched for 106 needed, against 127 with a 5 % margin).  A
+            // chunk is at most twice the last one: the maximum norm of a CG
+            // residual can stall over a chunk, and a rate near 1 would
+            // otherwise launch up to 256 passes past the last load's end
+            // (measured in the FP32 mode: 337 launches for 106 passes)
             int next = 2;
             for (int b = 0; b < nrhs; ++b) {
                 const CgState& hs = w->host_state[b];
@@ -958,6 +972,7 @@ static uno_status run_chunks(Workspace* w, const uno_solve_opts* o, int nrhs, bo
                 }
                 if (nx > next) next = nx;
             }
+            if (next > 2 * chunk) next = 2 * chunk;
             chunk = next < 2 ? 2 : (next > 256 ? 256 : next);
             if (graphs) chunk = (chunk + kGraphPasses - 1) / kGraphPasses * kGraphPasses;
         }
@@ -970,12 +985,11 @@ static uno_status run_chunks(Workspace* w, const uno_solve_opts* o, int nrhs, bo
     return UNO_OK;
 }
 
-// The CG loop for nrhs right-hand sides.  FP32 mode: the residual
-// replacement restarts every right-hand side together (one pass index k0
-// for all) as soon as one of the running ones has dropped by the restart
-// factor since its last (re)start; a restart earlier than a load needs
-// costs it part of its Krylov space, not accuracy, and loads that have
-// ended keep their state.
+// The CG loop for nrhs right-hand sides.  FP32 mode: the residual of every
+// running right-hand side is replaced together (one pass index for all) as
+// soon as one of them has dropped by the restart factor since its last
+// replacement; search directions continue, and loads that have ended keep
+// their state.
 template <typename T>
 static uno_status pcg_loop(const Grid& g, Workspace* w, const double* kappa64, const T* kappa, int64_t ks,
                            double* u, const uno_solve_opts* o, const uno_precond* pc, int hist_len, int nrhs,
@@ -1010,18 +1024,18 @@ static uno_status pcg_loop(const Grid& g, Workspace* w, const double* kappa64, c
         UNO_HIP(hipGetLastError());
         if (lowrank) {  // transform of r for the first pass (and ||r||^2 in the fused flow)
             const bool fused = sizeof(T) == sizeof(double) && uno_use_fused(pc);
-            const CgIter strides = iter_of(w, P, 0, 0, 0.0, 0, nb, ks);
+            const CgIter strides = iter_of(w, P, 0, 0, 0, 0.0, 0, nb, ks);
             return lowrank_forward(pc->lr, w->r, fused ? P.rs[0] : nullptr, lr_batch(w, pc, nrhs), strides, st);
         }
         return UNO_OK;
     };
     uno_status e = start(1, 0);
     if (e != UNO_OK) return e;
-    auto pass = [&](int k, int k0, hipStream_t sp) {
-        return enqueue_pass<T>(g, w, o->kind, pc, kappa, ks, u, k, k0, o->rtol, hist_len, nrhs, sp);
+    auto pass = [&](int k, int k0, int kr, hipStream_t sp) {
+        return enqueue_pass<T>(g, w, o->kind, pc, kappa, ks, u, k, k0, kr, o->rtol, hist_len, nrhs, sp);
     };
-    auto check = [&](int k, int k0) {
-        const CgIter it = iter_of(w, P, k, k0, o->rtol, hist_len, np_update, ks);
+    auto check = [&](int k, int k0, int kr) {
+        const CgIter it = iter_of(w, P, k, k0, kr, o->rtol, hist_len, np_update, ks);
         hipLaunchKernelGGL(k_cg_check, dim3(1, nrhs), dim3(kBlock), 0, st, it);
     };
     auto residual = [&]() { replace_residual(g, w, kappa64, u, ks, nrhs, st); };
@@ -1240,15 +1254,15 @@ static uno_status el_loop(const ElDev& E, const Grid& g, const GridDev& gd, Work
             hipLaunchKernelGGL((k_cg_init<T, 0>), grid, dim3(kBlock), 0, st, gd, (const T*)w->dinv,
                                (const double*)w->r, sv, P.rmax, rs0, ss0, w->state, w->npart, dks, reset);
         UNO_HIP(hipGetLastError());
-        if (pc) return lowrank_forward(pc->lr, w->r, nullptr, bt, iter_of(w, P, 0, 0, 0.0, 0, nb, dks), st);
+        if (pc) return lowrank_forward(pc->lr, w->r, nullptr, bt, iter_of(w, P, 0, 0, 0, 0.0, 0, nb, dks), st);
         return UNO_OK;
     };
     uno_status e = start(1, 0);
     if (e != UNO_OK) return e;
     // UNO flow per pass: [B (head) + C: s = P r, r.s] -> [d = s + beta d, p = A d, d.p]
     // -> [update + pass A of the next pass]
-    auto pass = [&](int k, int k0, hipStream_t sp) -> uno_status {
-        CgIter it = iter_of(w, P, k, k0, o->rtol, hist_len, np_update, dks);
+    auto pass = [&](int k, int k0, int kr, hipStream_t sp) -> uno_status {
+        CgIter it = iter_of(w, P, k, k0, kr, o->rtol, hist_len, np_update, dks);
         T* dold = (T*)w->d[k & 1];
         T* dnew = (T*)w->d[(k + 1) & 1];
         if (pc) {
@@ -1282,8 +1296,8 @@ static uno_status el_loop(const ElDev& E, const Grid& g, const GridDev& gd, Work
         }
         return UNO_ERR_ARG;  // FP32 mode runs UNO-CG only
     };
-    auto check = [&](int k, int k0) {
-        const CgIter it = iter_of(w, P, k, k0, o->rtol, hist_len, np_update, dks);
+    auto check = [&](int k, int k0, int kr) {
+        const CgIter it = iter_of(w, P, k, k0, kr, o->rtol, hist_len, np_update, dks);
         hipLaunchKernelGGL(k_cg_check, dim3(1, nrhs), dim3(kBlock), 0, st, it);
     };
     const int64_t n = g.total, N = 3 * n;

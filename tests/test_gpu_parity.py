@@ -339,3 +339,24 @@ def test_fp32_restart_at_odd_pass(orc, uno, kind, chunk):
     assert err < 1e-5
     for a, b in zip(i32, i64):
         assert a["iters"] <= 1.5 * b["iters"] + 10
+
+
+@pytest.mark.parametrize("kind", ["jacobi", "none"])
+def test_fp32_replacement_keeps_direction(orc, uno, kind):
+    """FP32 mode in a batch: a residual replacement keeps the search
+    directions (the reliable update), so across several replacements (rtol
+    1e-9, one per two decades) the FP32 solves need about the FP64 solves'
+    passes, not the extra passes of restarted cycles; each load's true FP64
+    residual meets the tolerance and its solution equals the oracle's."""
+    shape = (24, 20, 28)
+    kap = _two_phase(shape, 35)
+    loads = np.eye(3)
+    kw = dict(kind=kind, rtol=1e-9, max_iter=20000)
+    u32, i32 = uno.pcg_solve_batch(T(kap), macro_loads=loads, op_dtype=torch.float32, prec_dtype=torch.float32, **kw)
+    _, i64 = uno.pcg_solve_batch(T(kap), macro_loads=loads, **kw)
+    print("fp32 replacements", kind, [i["iters"] for i in i32], [i["iters"] for i in i64], flush=True)
+    for j, g in enumerate(loads):
+        assert i32[j]["converged"] and i32[j]["true_rel_res"] <= 1e-9
+        assert i32[j]["iters"] <= 1.06 * i64[j]["iters"] + 4
+        uo, _, _, _ = orc.pcg(kap, orc.rhs(kap, g), "jacobi", rtol=1e-11)
+        assert rel(u32[j].cpu().numpy(), uo) < 1e-6
