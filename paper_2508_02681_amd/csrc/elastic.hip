@@ -223,7 +223,9 @@ __global__ void __launch_bounds__(256) k_el_march(ElDev E, ElGeom eg, const T* _
     const int64_t o0 = (int64_t)wrap_el(y0 - 1 + ly, g.n1) * g.n2 + wrap_el(z0 - 1 + lz, g.n2);
     const bool has_x = t < 2 * kElL - 1;
     const int xy = t < kElL ? kElT : t - kElL, xz = t < kElL ? t : kElT;
-    const int64_t o1 = (int64_t)wrap_el(y0 - 1 + xy, g.n1) * g.n2 + wrap_el(z0 - 1 + xz, g.n2);
+    // (threads without an extra node load their own node twice: every load
+    // is unconditional, see fetch)
+    const int64_t o1 = has_x ? (int64_t)wrap_el(y0 - 1 + xy, g.n1) * g.n2 + wrap_el(z0 - 1 + xz, g.n2) : o0;
     const int l0 = ly * kElL + lz, l1 = xy * kElL + xz;
     const bool own = ly >= 1 && lz >= 1 && y0 + ly - 1 < g.n1 && z0 + lz - 1 < g.n2;
 
@@ -255,34 +257,52 @@ __global__ void __launch_bounds__(256) k_el_march(ElDev E, ElGeom eg, const T* _
         beta = use_old ? (T)(gk / gprev) : (T)0;
     }
 
-    // node plane m (global x0 - 1 + m) of the operand
-    T ps[3], pd[3], xs_[3], xd[3];
-    auto fetch = [&](int m) {
+    // node plane m (global x0 - 1 + m) of the operand, in registers between
+    // its loads and its LDS store.  Every load is unconditional (d_old is
+    // read on the first pass of a cycle too, and not used), so that no
+    // branch lies between the loads of a plane and the wait for them, and
+    // the waits before a store leave a later plane's loads in flight.  FP64:
+    // two sets, the loads of plane j + 3 issued at step j (the element
+    // arithmetic of two steps hides them); FP32 keeps one set (plane j + 2),
+    // which holds its 4 waves per SIMD.
+    constexpr bool DEEP = sizeof(T) == sizeof(double);
+    struct Stage {
+        T ps[3], pd[3], xs[3], xd[3];
+    };
+    Stage ra, rb;
+    auto fetch = [&](Stage& R, int m) {
         const int64_t b = (int64_t)wrap_el(x0 - 1 + m, g.n0) * plane;
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            ps[i] = s[i * n + b + o0];
-            if (use_old) pd[i] = dold[i * n + b + o0];
-            if (has_x) {
-                xs_[i] = s[i * n + b + o1];
-                if (use_old) xd[i] = dold[i * n + b + o1];
+            R.ps[i] = s[i * n + b + o0];
+            R.xs[i] = s[i * n + b + o1];
+            if (CG) {
+                R.pd[i] = dold[i * n + b + o0];
+                R.xd[i] = dold[i * n + b + o1];
             }
         }
     };
-    auto store = [&](int m) {
+    auto store = [&](const Stage& R, int m) {
         const int slot = m % 3;
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            const T d = use_old ? ps[i] + beta * pd[i] : ps[i];
+            const T d = use_old ? R.ps[i] + beta * R.pd[i] : R.ps[i];
             Dl[slot][i][l0] = d;
-            if (has_x) Dl[slot][i][l1] = use_old ? xs_[i] + beta * xd[i] : xs_[i];
+            if (has_x) Dl[slot][i][l1] = use_old ? R.xs[i] + beta * R.xd[i] : R.xs[i];
             if (CG && own && m >= 1 && m <= nx) dnew[i * n + (int64_t)(x0 - 1 + m) * plane + o0] = d;
         }
     };
-    fetch(0);
-    store(0);
-    fetch(1);
-    store(1);
+    fetch(ra, 0);
+    if (DEEP) {
+        fetch(rb, 1);
+        store(ra, 0);
+        store(rb, 1);
+        fetch(ra, min(2, nx + 1));
+    } else {
+        store(ra, 0);
+        fetch(ra, 1);
+        store(ra, 1);
+    }
     T le = lam[(int64_t)wrap_el(x0 - 1, g.n0) * plane + o0];
     T me = mu[(int64_t)wrap_el(x0 - 1, g.n0) * plane + o0];
     __syncthreads();
@@ -293,56 +313,65 @@ __global__ void __launch_bounds__(256) k_el_march(ElDev E, ElGeom eg, const T* _
 #pragma unroll
         for (int k = 0; k < 4; ++k) carry[i][k] = (T)0;
     double dot = 0.0;
-    for (int j = 0; j <= nx; ++j) {
-        const bool more = j + 2 <= nx + 1;
-        if (more) fetch(j + 2);
-        T ln = 0, mn = 0;
-        if (j + 1 <= nx) {
-            const int64_t e = (int64_t)wrap_el(x0 + j, g.n0) * plane + o0;
-            ln = lam[e];
-            mn = mu[e];
-        }
-        T U[3][8];
-        const int sa = j % 3, sb = (j + 1) % 3;
+    // steps in pairs, so that the register sets swap roles statically: `cur`
+    // holds plane j + 2 (stored at the end of step j), `nxt` receives the
+    // plane fetched at step j (the last steps reload plane nx + 1)
+    for (int j0 = 0; j0 <= nx; j0 += 2) {
 #pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            U[i][0] = Dl[sa][i][l0];
-            U[i][1] = Dl[sa][i][l0 + 1];
-            U[i][2] = Dl[sa][i][l0 + kElL];
-            U[i][3] = Dl[sa][i][l0 + kElL + 1];
-            U[i][4] = Dl[sb][i][l0];
-            U[i][5] = Dl[sb][i][l0 + 1];
-            U[i][6] = Dl[sb][i][l0 + kElL];
-            U[i][7] = Dl[sb][i][l0 + kElL + 1];
-        }
-        const T dself[3] = {U[0][0], U[1][0], U[2][0]};
-        el_element<T>(E, le * (T)E.w8, me * (T)E.w8, U);  // U becomes the corner forces
-        // node plane j - 1 + x0: corners a = 0 of this voxel plus the carry
-        T own_f[3];
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            const T c1 = carry[i][1] + U[i][1], c2 = carry[i][2] + U[i][2], c3 = carry[i][3] + U[i][3];
-            own_f[i] = carry[i][0] + U[i][0];
-            if (j >= 1) {
-                X[j & 1][i * 3 + 0][t] = c1;  // corner (0, 1): node (ly, lz + 1)
-                X[j & 1][i * 3 + 1][t] = c2;  // corner (1, 0): node (ly + 1, lz)
-                X[j & 1][i * 3 + 2][t] = c3;  // corner (1, 1)
-            }
-#pragma unroll
-            for (int k = 0; k < 4; ++k) carry[i][k] = U[i][4 + k];
-        }
-        if (more) store(j + 2);
-        le = ln;
-        me = mn;
-        __syncthreads();
-        if (j >= 1 && own) {
-            const int64_t b = (int64_t)(x0 - 1 + j) * plane + o0;
+        for (int h = 0; h < 2; ++h) {
+            const int j = j0 + h;
+            if (j > nx) break;
+            Stage& cur = (DEEP && h) ? rb : ra;
+            Stage& nxt = DEEP ? (h ? ra : rb) : ra;
+            const bool more = j + 2 <= nx + 1;
+            // Lame values of voxel plane x0 + j, used at step j + 1 (the last
+            // step reloads plane x0 + nx - 1, unused); loaded before the
+            // operand plane, so that their wait leaves that plane in flight
+            const int64_t e = (int64_t)wrap_el(x0 + min(j, nx - 1), g.n0) * plane + o0;
+            const T ln = lam[e], mn = mu[e];
+            fetch(nxt, min(j + (DEEP ? 3 : 2), nx + 1));
+            T U[3][8];
+            const int sa = j % 3, sb = (j + 1) % 3;
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
-                const T y = own_f[i] + X[j & 1][i * 3 + 0][t - 1] + X[j & 1][i * 3 + 1][t - kElT] +
-                                 X[j & 1][i * 3 + 2][t - kElT - 1];
-                p[i * n + b] = y;
-                if (CG) dot += (double)dself[i] * (double)y;
+                U[i][0] = Dl[sa][i][l0];
+                U[i][1] = Dl[sa][i][l0 + 1];
+                U[i][2] = Dl[sa][i][l0 + kElL];
+                U[i][3] = Dl[sa][i][l0 + kElL + 1];
+                U[i][4] = Dl[sb][i][l0];
+                U[i][5] = Dl[sb][i][l0 + 1];
+                U[i][6] = Dl[sb][i][l0 + kElL];
+                U[i][7] = Dl[sb][i][l0 + kElL + 1];
+            }
+            const T dself[3] = {U[0][0], U[1][0], U[2][0]};
+            el_element<T>(E, le * (T)E.w8, me * (T)E.w8, U);  // U becomes the corner forces
+            // node plane j - 1 + x0: corners a = 0 of this voxel plus the carry
+            T own_f[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const T c1 = carry[i][1] + U[i][1], c2 = carry[i][2] + U[i][2], c3 = carry[i][3] + U[i][3];
+                own_f[i] = carry[i][0] + U[i][0];
+                if (j >= 1) {
+                    X[j & 1][i * 3 + 0][t] = c1;  // corner (0, 1): node (ly, lz + 1)
+                    X[j & 1][i * 3 + 1][t] = c2;  // corner (1, 0): node (ly + 1, lz)
+                    X[j & 1][i * 3 + 2][t] = c3;  // corner (1, 1)
+                }
+#pragma unroll
+                for (int k = 0; k < 4; ++k) carry[i][k] = U[i][4 + k];
+            }
+            if (more) store(cur, j + 2);
+            le = ln;
+            me = mn;
+            __syncthreads();
+            if (j >= 1 && own) {
+                const int64_t b = (int64_t)(x0 - 1 + j) * plane + o0;
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    const T y = own_f[i] + X[j & 1][i * 3 + 0][t - 1] + X[j & 1][i * 3 + 1][t - kElT] +
+                                     X[j & 1][i * 3 + 2][t - kElT - 1];
+                    p[i * n + b] = y;
+                    if (CG) dot += (double)dself[i] * (double)y;
+                }
             }
         }
     }
