@@ -1425,7 +1425,6 @@ uno_status lowrank_fused_pass(const LowRankPlan* p, const Grid& g, const double*
                               hipStream_t st, int* np_dp)
 {
     if (!p->fused) return UNO_ERR_SHAPE;
-    const LowRankDev& L = p->dev;
     launch_mid(p, bt, p->cb_mid, it, part_corr, st);  // the plan's grouping: part_corr has blocks_mid partials
     UNO_HIP(hipGetLastError());
     const LrTileArgs a{part_rr, p->dev.n0 * bt.nch, part_corr, p->blocks_mid};
