@@ -262,6 +262,16 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b)
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
+// One Horner step (re, im) <- (re, im) w + h in complex arithmetic, as four
+// nested fused multiply-adds (the compiler contracts the plain expression
+// into six operations)
+__device__ __forceinline__ void horner_step(double& re, double& im, double2 w, double2 h)
+{
+    const double nr = fma(re, w.x, fma(-im, w.y, h.x));
+    im = fma(re, w.y, fma(im, w.x, h.y));
+    re = nr;
+}
+
 // sum_{j < m} a[j * stride] w^j, by Horner on even and odd j in w^2
 __device__ __forceinline__ double2 horner_eo(const double2* a, int stride, int m, double2 w)
 {
@@ -275,20 +285,10 @@ __device__ __forceinline__ double2 horner_eo(const double2* a, int stride, int m
     }
 #pragma unroll 4
     for (; j >= 2; j -= 2) {  // both chains
-        const double2 he = a[j * stride], ho = a[(j - 1) * stride];
-        const double ner = er * w2.x - ei * w2.y + he.x;
-        ei = er * w2.y + ei * w2.x + he.y;
-        er = ner;
-        const double nor = orr * w2.x - oi * w2.y + ho.x;
-        oi = orr * w2.y + oi * w2.x + ho.y;
-        orr = nor;
+        horner_step(er, ei, w2, a[j * stride]);
+        horner_step(orr, oi, w2, a[(j - 1) * stride]);
     }
-    {  // j = 0: the even chain only
-        const double2 he = a[0];
-        const double ner = er * w2.x - ei * w2.y + he.x;
-        ei = er * w2.y + ei * w2.x + he.y;
-        er = ner;
-    }
+    horner_step(er, ei, w2, a[0]);  // j = 0: the even chain only
     // E(w^2) + w O(w^2), E holding the even j, O the odd j
     return make_double2(er + (orr * w.x - oi * w.y), ei + (orr * w.y + oi * w.x));
 }
@@ -587,12 +587,8 @@ __global__ void __launch_bounds__(256) k_lr_inv_pairs(LowRankDev L, int y_chunk,
             double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
             for (int kyi = L.kyn - 1; kyi >= 0; --kyi) {
                 const double2 h = hcol[kyi * L.kzn];
-                const double nar = ar * wa.x - ai * wa.y + h.x;
-                ai = ar * wa.y + ai * wa.x + h.y;
-                ar = nar;
-                const double nbr = br * wb.x - bi * wb.y + h.x;
-                bi = br * wb.y + bi * wb.x + h.y;
-                br = nbr;
+                horner_step(ar, ai, wa, h);
+                horner_step(br, bi, wb, h);
             }
             const double2 sa = L.twy[mod_n(L.m * (y0 + ya), L.n1)];
             const double2 sb = L.twy[mod_n(L.m * (y0 + yb), L.n1)];
@@ -727,12 +723,8 @@ __global__ void __launch_bounds__(256) k_lr_inv(LowRankDev L, int y_chunk, const
             double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
             for (int kyi = L.kyn - 1; kyi >= 0; --kyi) {
                 const double2 h = hcol[kyi * L.kzn];
-                const double nar = ar * wa.x - ai * wa.y + h.x;
-                ai = ar * wa.y + ai * wa.x + h.y;
-                ar = nar;
-                const double nbr = br * wb.x - bi * wb.y + h.x;
-                bi = br * wb.y + bi * wb.x + h.y;
-                br = nbr;
+                horner_step(ar, ai, wa, h);
+                horner_step(br, bi, wb, h);
             }
             const double2 sa = L.twy[mod_n(L.m * (y0 + ya), L.n1)];
             const double2 sb = L.twy[mod_n(L.m * (y0 + yb), L.n1)];
@@ -765,11 +757,7 @@ __global__ void __launch_bounds__(256) k_lr_inv(LowRankDev L, int y_chunk, const
                 for (int c = 0; c < NC; ++c) {
                     const double2 v = V[((int64_t)c * ny + row) * L.kzn + kz];
 #pragma unroll
-                    for (int i = 0; i < ZB; ++i) {
-                        const double nr = ar[c][i] * w[i].x - ai[c][i] * w[i].y + v.x;
-                        ai[c][i] = ar[c][i] * w[i].y + ai[c][i] * w[i].x + v.y;
-                        ar[c][i] = nr;
-                    }
+                    for (int i = 0; i < ZB; ++i) horner_step(ar[c][i], ai[c][i], w[i], v);
                 }
             }
 #pragma unroll
@@ -997,12 +985,8 @@ __global__ void __launch_bounds__(256) k_lr_tile(GridDev g, TileGeom tg, LowRank
             const double2* hcol = Hl + xl * plane + kz;
             double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
             auto step = [&](const double2 h) {
-                const double nar = ar * wa.x - ai * wa.y + h.x;
-                ai = ar * wa.y + ai * wa.x + h.y;
-                ar = nar;
-                const double nbr = br * wb.x - bi * wb.y + h.x;
-                bi = br * wb.y + bi * wb.x + h.y;
-                br = nbr;
+                horner_step(ar, ai, wa, h);
+                horner_step(br, bi, wb, h);
             };
             int kyi = L.kyn - 1;
             for (; kyi >= 3; kyi -= 4) {  // four LDS reads in flight per round
