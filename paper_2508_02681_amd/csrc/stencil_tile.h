@@ -324,7 +324,7 @@ __global__ void __launch_bounds__(256) k_stencil_march(GridDev g, MarchGeom mg, 
             const int slot = t & 1;
             const bool more = t + 1 < nsteps;
             // (the last two steps reload plane xe, recently read: no branch)
-        load(ahead, min(xi + 2, xe));
+            load(ahead, min(xi + 2, xe));
             T D[RY + 2][3], kp[RY + 1][2];
 #pragma unroll
             for (int bb = 0; bb < RY + 2; ++bb)
