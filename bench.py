@@ -779,6 +779,14 @@ def main():
                      for f, name in f32_fams.items()}
     log("FP32 step by family (ms): %s of %.2f ms" % ({k: v["ms_per_step"] for k, v in fp32_families.items()},
                                                     dtm / 2 * 1e3))
+    # the BF16 preconditioner mode: the FP32 mode with the learned-mode
+    # passes' table and spectrum stored in BF16 (kept as the default only if
+    # it costs no extra passes)
+    bf16 = dict(op_dtype=torch.float32, prec_dtype=torch.bfloat16)
+    dtb, itsb, kbb = timed("uno", prec, 2, 1, tag="uno_cg_bf16", **bf16)
+    kb_err_b = max(float(np.abs(a - b).max() / np.abs(b).max()) for a, b in zip(kbb, kbs[:nm]))
+    log("UNO-CG BF16 precond (FP32 op): %.1f passes/solve (FP32 mode %.1f), %.3f ms per solve, kappa_bar rel diff "
+        "vs FP64 %.1e" % (np.mean(itsb), np.mean(itsm), dtb / len(itsb) * 1e3, kb_err_b))
 
     # ---------------- FANS (reference-medium preconditioner) for context ----------------
     pf = uno.UnoPrecond.fans(SHAPE, 0.5 * (cfg["k_matrix"] + cfg["k_incl"]))
@@ -871,7 +879,8 @@ def main():
     oracle_err = None
     if not args.no_oracle_ref:
         oracle_err = oracle_kbar_errors(kap_test[0].cpu().numpy(),
-                                        {"uno_cg": kbs[0], "jac_cg": kbj[0], "uno_cg_fp32": kbm[0]})
+                                        {"uno_cg": kbs[0], "jac_cg": kbj[0], "uno_cg_fp32": kbm[0],
+                                         "uno_cg_bf16": kbb[0]})
 
     # ---------------- the C-ABI calls fe_apply and uno_precond_apply at 192^3 ----------------
     calls = None
@@ -911,6 +920,10 @@ def main():
         "uno_cg_fp32": {"passes_mean": float(np.mean(itsm)), "ms_per_solve": dtm / len(itsm) * 1e3,
                         "ms_per_step": dtm / 2 * 1e3, "kernel_families_one_step": fp32_families,
                         "kappa_bar_rel_diff_vs_fp64": kb_err},
+        "uno_cg_bf16": {"passes_mean": float(np.mean(itsb)), "ms_per_solve": dtb / len(itsb) * 1e3,
+                        "kappa_bar_rel_diff_vs_fp64": kb_err_b,
+                        "note": "FP32 mode with the learned-mode passes' table, row-chunk partials and per-mode "
+                                "coefficients stored in BF16 (FP64 arithmetic and recurrences)"},
         "kappa_bar_error_vs_fp64_oracle": oracle_err,
         "roofline_calls": calls,
         "time_to_tol_speedup_uno_vs_jac": jac_t_solve / uno_t_solve,

@@ -155,8 +155,13 @@ typedef struct {
                                 FP32 mode keeps r, u, all reductions and the stop test in FP64
                                 and needs, for UNO, the learned-mode passes (uno_precond_set_path);
                                 it replaces r by f - A u (FP64) whenever ||r||_inf has dropped by
-                                1e2 since the last replacement, and reopens a load whose FP64 true
-                                residual is above its tolerance when every load has ended */
+                                1e2 since the last replacement (the search direction continues),
+                                and reopens a load whose FP64 true residual is above its
+                                tolerance when every load has ended.  UNO_BF16 (with
+                                op_t = UNO_F32, UNO-CG with the learned-mode passes of a
+                                one-DOF preconditioner): the FP32 mode with the passes' table,
+                                row-chunk partials and per-mode coefficients stored in BF16
+                                (rounded to nearest even; their arithmetic stays FP64) */
     int32_t graph_chunk;     /* iterations per host check; 0 = adaptive */
     int32_t use_graphs;      /* 1: after the first 8 passes, run the passes as replays of a
                                 captured hipGraph of 8 passes (FP64, learned-mode or Jacobi /

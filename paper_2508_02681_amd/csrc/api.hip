@@ -608,10 +608,13 @@ static uno_status check_solve(const uno_grid* grid, const uno_material* mat, con
     }
     if (mat->dtype != UNO_F64) return UNO_ERR_ARG;
     // FP64 throughout, or the mixed mode: FP32 operator and preconditioner
-    // applies, FP64 residual / solution recurrences, reductions and stop test
+    // applies, FP64 residual / solution recurrences, reductions and stop
+    // test; for UNO-CG also with the preconditioner's table and spectrum in
+    // BF16
     const bool f64 = opts->op_t == UNO_F64 && opts->prec_t == UNO_F64;
     const bool mixed = opts->op_t == UNO_F32 && opts->prec_t == UNO_F32;
-    if (!f64 && !mixed) return UNO_ERR_ARG;
+    const bool bf16 = opts->op_t == UNO_F32 && opts->prec_t == UNO_BF16 && opts->kind == UNO_PREC_UNO;
+    if (!f64 && !mixed && !bf16) return UNO_ERR_ARG;
     return UNO_OK;
 }
 

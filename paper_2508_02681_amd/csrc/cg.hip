@@ -430,6 +430,7 @@ struct Workspace {
     int spec_cap = 0;
     double2* lr_gp = nullptr; // learned-mode scratch per right-hand side
     double2* lr_h = nullptr;
+    bool lr_bf = false;       // the current solve stores that scratch in BF16
     int64_t lr_ngp = 0, lr_nh = 0;
     int lr_cap = 0;
     CgState* state = nullptr;
@@ -681,7 +682,9 @@ CgIter iter_of(Workspace* w, const Parts& P, int k, int k0, int kr, double rtol,
 
 LrBatch lr_batch(Workspace* w, const uno_precond* pc, int nrhs)
 {
-    return lowrank_batch(pc->lr, w->lr_gp, w->lr_h, nrhs);
+    LrBatch b = lowrank_batch(pc->lr, w->lr_gp, w->lr_h, nrhs);
+    b.bf = w->lr_bf;
+    return b;
 }
 
 }  // namespace
@@ -1068,6 +1071,9 @@ uno_status pcg_run_batch(const Grid& g, const double* kappa, int64_t ks, int nrh
     const uno_precond* pc = (o->kind == UNO_PREC_UNO) ? o->uno : nullptr;
     const bool mixed = (o->op_t == UNO_F32);
     if (mixed && pc && !uno_use_lowrank(pc)) return UNO_ERR_ARG;
+    // BF16 mode: the FP32 mode with the learned-mode passes' table and
+    // spectrum stored in BF16 (one nodal DOF)
+    if (o->prec_t == UNO_BF16 && (!mixed || !pc || pc->nc != 1)) return UNO_ERR_ARG;
     // one loop for all right-hand sides, every pass kernel taking them along
     // grid y (the spectral passes too)
     Workspace* w = nullptr;
@@ -1086,6 +1092,8 @@ static uno_status pcg_run_ws(const Grid& g, Workspace* w, bool may_alloc, const 
 {
     const uno_precond* pc = (o->kind == UNO_PREC_UNO) ? o->uno : nullptr;
     const bool mixed = (o->op_t == UNO_F32);
+    if (o->prec_t == UNO_BF16 && (!mixed || !pc || pc->nc != 1 || !uno_use_lowrank(pc))) return UNO_ERR_ARG;
+    w->lr_bf = o->prec_t == UNO_BF16;  // (the workspace is leased to this solve)
     const int hist_len = o->max_iter + 1;
     uno_status e = UNO_OK;
     const int nb = w->nbr;

@@ -29,6 +29,7 @@
 // the bypass product W r at each node.
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 
 #include "unocg_internal.h"
 #include "reduce.h"
@@ -58,6 +59,37 @@ __device__ __forceinline__ int mod_n(int v, int n)
     return r < 0 ? r + n : r;
 }
 
+// Storage of the preconditioner's spectrum and table.  FP64 (double2 per
+// complex value, double per table entry), or in the BF16 mode two BF16
+// numbers in 32 bits per complex value (real part in the low half) and one
+// per table entry: values are rounded to FP32 and then to the nearest BF16
+// (ties to even), and widened exactly on load; the arithmetic stays FP64.
+__device__ __forceinline__ uint32_t bf16_bits(double v)
+{
+    const uint32_t b = __float_as_uint((float)v);
+    return (b + 0x7fffu + ((b >> 16) & 1u)) >> 16;
+}
+__device__ __forceinline__ double2 sp_get(const double2* p, int64_t i) { return p[i]; }
+__device__ __forceinline__ double2 sp_get(const uint32_t* p, int64_t i)
+{
+    const uint32_t v = p[i];
+    return make_double2((double)__uint_as_float(v << 16), (double)__uint_as_float(v & 0xffff0000u));
+}
+__device__ __forceinline__ void sp_put(double2* p, int64_t i, double2 v) { p[i] = v; }
+__device__ __forceinline__ void sp_put(uint32_t* p, int64_t i, double2 v)
+{
+    p[i] = bf16_bits(v.x) | (bf16_bits(v.y) << 16);
+}
+__device__ __forceinline__ double tab_get(const double* c, int64_t i) { return c[i]; }
+__device__ __forceinline__ double tab_get(const uint16_t* c, int64_t i)
+{
+    return (double)__uint_as_float((uint32_t)c[i] << 16);
+}
+template <bool BF>
+using SpT = std::conditional_t<BF, uint32_t, double2>;
+template <bool BF>
+using TabT = std::conditional_t<BF, uint16_t, double>;
+
 // Pass A on the rows [y_b, y_e) of slab x (one workgroup), taken ya rows at
 // a time: Z[y][kz] = sum_z r e^{-i kz z}, then the partial y-sum over the
 // workgroup's rows, Gp[x][chunk][ky][kz] = sum_y Z[y][kz] e^{-i ky y}
@@ -65,10 +97,10 @@ __device__ __forceinline__ int mod_n(int v, int n)
 // UPDATE (inside CG): the rows are first updated, r <- r - alpha p,
 // u <- u + alpha d, and partials of ||r||_inf are written; the transformed
 // rows are then those of the new residual (for the next pass).
-template <bool UPDATE, typename TD, int PF>
+template <bool UPDATE, typename TD, int PF, bool BF = false>
 __global__ void __launch_bounds__(256) k_lr_fwd(LowRankDev L, int ya, int rb, double* __restrict__ r,
                                                 double* __restrict__ u, const TD* __restrict__ d,
-                                                const TD* __restrict__ p, double2* __restrict__ Gp, CgIter it,
+                                                const TD* __restrict__ p, SpT<BF>* __restrict__ Gp, CgIter it,
                                                 const double* __restrict__ part_dp, int np_dp,
                                                 const double* __restrict__ gam, double* __restrict__ part_rmax,
                                                 double* __restrict__ part_rr)
@@ -233,7 +265,7 @@ __global__ void __launch_bounds__(256) k_lr_fwd(LowRankDev L, int ya, int rb, do
         }
         __syncthreads();
     }
-    for (int q = threadIdx.x; q < plane; q += 256) Gp[((int64_t)x * nch + ch) * plane + q] = Gacc[q];
+    for (int q = threadIdx.x; q < plane; q += 256) sp_put(Gp, ((int64_t)x * nch + ch) * plane + q, Gacc[q]);
     if (UPDATE) {
         const double bm = block_reduce<OpMax>(m, slots);
         if (threadIdx.x == 0) part_rmax[blockIdx.x] = bm;
@@ -295,13 +327,14 @@ __device__ __forceinline__ double2 horner_eo(const double2* a, int stride, int m
 
 // sum_{c < nch} src[c stride], added in the order c = 0, 1, ...; the loads
 // are issued four at a time so that they are in flight together
-__device__ __forceinline__ double2 chunk_sum(const double2* __restrict__ src, int nch, int64_t stride)
+template <typename SP>
+__device__ __forceinline__ double2 chunk_sum(const SP* __restrict__ src, int nch, int64_t stride)
 {
     double re = 0.0, im = 0.0;
     int c = 0;
     for (; c + 4 <= nch; c += 4) {
-        const double2 v0 = src[c * stride], v1 = src[(c + 1) * stride];
-        const double2 v2 = src[(c + 2) * stride], v3 = src[(c + 3) * stride];
+        const double2 v0 = sp_get(src, c * stride), v1 = sp_get(src, (c + 1) * stride);
+        const double2 v2 = sp_get(src, (c + 2) * stride), v3 = sp_get(src, (c + 3) * stride);
         re += v0.x;
         im += v0.y;
         re += v1.x;
@@ -312,16 +345,16 @@ __device__ __forceinline__ double2 chunk_sum(const double2* __restrict__ src, in
         im += v3.y;
     }
     for (; c < nch; ++c) {
-        const double2 v = src[c * stride];
+        const double2 v = sp_get(src, c * stride);
         re += v.x;
         im += v.y;
     }
     return make_double2(re, im);
 }
 
-template <int CB>  // columns per workgroup
-__global__ void __launch_bounds__(256) k_lr_mid(LowRankDev L, int nch, const double* __restrict__ C,
-                                                const double2* __restrict__ Gp, double2* __restrict__ H, CgIter it,
+template <int CB, bool BF = false>  // columns per workgroup, BF16 storage
+__global__ void __launch_bounds__(256) k_lr_mid(LowRankDev L, int nch, const TabT<BF>* __restrict__ C,
+                                                const SpT<BF>* __restrict__ Gp, SpT<BF>* __restrict__ H, CgIter it,
                                                 double* __restrict__ part_corr)
 {
     resolve_pass(it);
@@ -382,7 +415,7 @@ __global__ void __launch_bounds__(256) k_lr_mid(LowRankDev L, int nch, const dou
             const int col = col0 + cl;
             const double2 w = L.twx[mod_n(kxi - L.mx, L.n0)];
             const double2 v = horner_eo(gx + cl, CB, L.n0, w);
-            const double c = (col < plane) ? C[(int64_t)kxi * plane + col] : 0.0;
+            const double c = (col < plane) ? tab_get(C, (int64_t)kxi * plane + col) : 0.0;
             X[o] = make_double2(v.x * c, v.y * c);
             corr += c * (v.x * v.x + v.y * v.y);
         }
@@ -409,7 +442,7 @@ __global__ void __launch_bounds__(256) k_lr_mid(LowRankDev L, int nch, const dou
             }
             const int cl = o % CB, kxi = o / CB;
             const int col = col0 + cl;
-            const double c = (col < plane) ? C[(int64_t)kxi * plane + col] : 0.0;
+            const double c = (col < plane) ? tab_get(C, (int64_t)kxi * plane + col) : 0.0;
             X[o] = make_double2(v.x * c, v.y * c);
             corr += c * (v.x * v.x + v.y * v.y);
         }
@@ -428,7 +461,7 @@ __global__ void __launch_bounds__(256) k_lr_mid(LowRankDev L, int nch, const dou
         const double2 w = make_double2(t.x, -t.y);        // exp(+2 pi i x / n0)
         const double2 v = horner_eo(X + cl, CB, L.kxn, w);
         const double2 sh = L.twx[mod_n(L.mx * x, L.n0)];  // exp(-2 pi i mx x / n0)
-        H[(int64_t)x * plane + col] = cmul(v, sh);
+        sp_put(H, (int64_t)x * plane + col, cmul(v, sh));
     }
 }
 
@@ -527,9 +560,9 @@ __global__ void __launch_bounds__(256) k_lr_mid3(LowRankDev L, int nch, int cb, 
 // (each V value feeds all its pairs) and also loads, updates and writes
 // exactly those nodes.  (For three components the pairs' recurrence state
 // costs more registers than the halved arithmetic saves: k_lr_inv below.)
-template <bool CG, typename TS>
+template <bool CG, typename TS, bool BF = false>
 __global__ void __launch_bounds__(256) k_lr_inv_pairs(LowRankDev L, int y_chunk, const double* __restrict__ r,
-                                                      const double2* __restrict__ H, TS* __restrict__ s, CgIter it)
+                                                      const SpT<BF>* __restrict__ H, TS* __restrict__ s, CgIter it)
 {
     resolve_pass(it);
     extern __shared__ __align__(16) unsigned char smem[];
@@ -572,7 +605,7 @@ __global__ void __launch_bounds__(256) k_lr_inv_pairs(LowRankDev L, int y_chunk,
         }
     };
     load_r(0);
-    for (int j = threadIdx.x; j < plane; j += blockDim.x) Hs[j] = H[(int64_t)x * plane + j];
+    for (int j = threadIdx.x; j < plane; j += blockDim.x) Hs[j] = sp_get(H, (int64_t)x * plane + j);
     if (CG && ended(sl, it.k)) return;
     __syncthreads();
     // V[y][kz] = exp(-i M phi_y) sum_kyi H[kyi][kz] w_y^kyi, w_y = exp(+2 pi i y / n1)
@@ -1104,6 +1137,7 @@ __global__ void __launch_bounds__(256) k_lr_tile(GridDev g, TileGeom tg, LowRank
 struct LowRankPlan {
     LowRankDev dev;
     double* table;    // kxn x kyn x kzn, w(kz) C(k) / n
+    uint16_t* table_bf;  // the same in BF16 (one nodal DOF; the BF16 preconditioner mode)
     double2* Gp;      // n0 x nch_a x kyn x kzn row-chunk partials
     double2* H;       // n0 x kyn x kzn
     int ya, yc;       // rows per group of pass A (in LDS at once), fewest rows per workgroup of pass C
@@ -1215,13 +1249,25 @@ uno_status lowrank_create(const Grid& g, const FftPlan& fp, int M, double W, con
     L.gps = ngp;
     L.hsz = nh;
     if (hipMalloc(&p->table, sizeof(double) * ntab) != hipSuccess ||
-        hipMalloc(&p->Gp, sizeof(double2) * ngp) != hipSuccess || hipMalloc(&p->H, sizeof(double2) * nh) != hipSuccess) {
+        hipMalloc(&p->Gp, sizeof(double2) * ngp) != hipSuccess || hipMalloc(&p->H, sizeof(double2) * nh) != hipSuccess ||
+        (nc == 1 && hipMalloc(&p->table_bf, sizeof(uint16_t) * ntab) != hipSuccess)) {
         (void)hipFree(p->table);
         (void)hipFree(p->Gp);
+        (void)hipFree(p->H);
         delete p;
         return UNO_ERR_NOMEM;
     }
     UNO_HIP(hipMemcpy(p->table, cblock.data(), sizeof(double) * ntab, hipMemcpyHostToDevice));
+    if (nc == 1) {  // rounded to FP32, then to the nearest BF16 (ties to even), as the kernels round
+        std::vector<uint16_t> tb(ntab);
+        for (int64_t i = 0; i < ntab; ++i) {
+            const float f = (float)cblock[i];
+            uint32_t b;
+            memcpy(&b, &f, sizeof(b));
+            tb[i] = (uint16_t)((b + 0x7fffu + ((b >> 16) & 1u)) >> 16);
+        }
+        UNO_HIP(hipMemcpy(p->table_bf, tb.data(), sizeof(uint16_t) * ntab, hipMemcpyHostToDevice));
+    }
     *out = p;
     return UNO_OK;
 }
@@ -1230,6 +1276,7 @@ void lowrank_destroy(LowRankPlan* p)
 {
     if (!p) return;
     (void)hipFree(p->table);
+    (void)hipFree(p->table_bf);
     (void)hipFree(p->Gp);
     (void)hipFree(p->H);
     delete p;
@@ -1313,7 +1360,21 @@ uno_status lowrank_forward(const LowRankPlan* p, const double* r, double* part_r
                            const CgIter& strides, hipStream_t st)
 {
     const dim3 grid(p->slabs * bt.nch, bt.nrhs);
-    if (p->ya * p->dev.n2 > 1024)
+    const bool pf8 = p->ya * p->dev.n2 > 1024;
+    if (bt.bf) {
+        if (p->dev.nc != 1) return UNO_ERR_ARG;
+        uint32_t* gb = (uint32_t*)bt.Gp;
+        if (pf8)
+            uno_launch(UNO_KT_FFT_FWD, k_lr_fwd<false, double, 8, true>, grid, dim3(256), p->lds_a, st, p->dev, p->ya,
+                       bt.rb, (double*)r, (double*)nullptr, (const double*)nullptr, (const double*)nullptr, gb,
+                       strides, (const double*)nullptr, 0, (const double*)nullptr, (double*)nullptr, part_rr);
+        else
+            uno_launch(UNO_KT_FFT_FWD, k_lr_fwd<false, double, 4, true>, grid, dim3(256), p->lds_a, st, p->dev, p->ya,
+                       bt.rb, (double*)r, (double*)nullptr, (const double*)nullptr, (const double*)nullptr, gb,
+                       strides, (const double*)nullptr, 0, (const double*)nullptr, (double*)nullptr, part_rr);
+        return hip_status(hipGetLastError());
+    }
+    if (pf8)
         uno_launch(UNO_KT_FFT_FWD, k_lr_fwd<false, double, 8>, grid, dim3(256), p->lds_a, st, p->dev, p->ya, bt.rb,
                    (double*)r, (double*)nullptr, (const double*)nullptr, (const double*)nullptr, bt.Gp, strides,
                    (const double*)nullptr, 0, (const double*)nullptr, (double*)nullptr, part_rr);
@@ -1331,7 +1392,22 @@ uno_status lowrank_update_forward(const LowRankPlan* p, double* r, double* u, co
                                   double* part_rmax, double* part_rr, const LrBatch& bt, hipStream_t st)
 {
     const dim3 grid(p->slabs * bt.nch, bt.nrhs);
-    if (p->ya * p->dev.n2 > 1024)
+    const bool pf8 = p->ya * p->dev.n2 > 1024;
+    if constexpr (sizeof(T) == sizeof(float)) {  // the BF16 mode runs with the FP32 vectors
+        if (bt.bf) {
+            if (p->dev.nc != 1) return UNO_ERR_ARG;
+            uint32_t* gb = (uint32_t*)bt.Gp;
+            if (pf8)
+                uno_launch(UNO_KT_UPDATE, k_lr_fwd<true, T, 8, true>, grid, dim3(256), p->lds_a, st, p->dev, p->ya,
+                           bt.rb, r, u, d, pv, gb, it, part_dp, np_dp, gam, part_rmax, part_rr);
+            else
+                uno_launch(UNO_KT_UPDATE, k_lr_fwd<true, T, 4, true>, grid, dim3(256), p->lds_a, st, p->dev, p->ya,
+                           bt.rb, r, u, d, pv, gb, it, part_dp, np_dp, gam, part_rmax, part_rr);
+            return hip_status(hipGetLastError());
+        }
+    }
+    if (bt.bf) return UNO_ERR_ARG;
+    if (pf8)
         uno_launch(UNO_KT_UPDATE, k_lr_fwd<true, T, 8>, grid, dim3(256), p->lds_a, st, p->dev, p->ya, bt.rb, r, u, d,
                    pv, bt.Gp, it, part_dp, np_dp, gam, part_rmax, part_rr);
     else
@@ -1382,6 +1458,30 @@ static void launch_mid(const LowRankPlan* p, const LrBatch& bt, int cb, const Cg
     const LowRankDev& L = p->dev;
     const dim3 grid((L.kyn * L.kzn + cb - 1) / cb, bt.nrhs), blk(256);
     const size_t lds = sizeof(double2) * ((size_t)cb * (L.n0 + L.kxn) + 256);  // + the x-range partials
+    if (bt.bf) {
+        const uint16_t* Cb = p->table_bf;
+        const uint32_t* Gb = (const uint32_t*)bt.Gp;
+        uint32_t* Hb = (uint32_t*)bt.H;
+        switch (cb) {
+            case 8:
+                uno_launch(UNO_KT_FFT_MID, k_lr_mid<8, true>, grid, blk, lds, st, L, bt.nch, Cb, Gb, Hb, it,
+                           part_corr);
+                break;
+            case 4:
+                uno_launch(UNO_KT_FFT_MID, k_lr_mid<4, true>, grid, blk, lds, st, L, bt.nch, Cb, Gb, Hb, it,
+                           part_corr);
+                break;
+            case 2:
+                uno_launch(UNO_KT_FFT_MID, k_lr_mid<2, true>, grid, blk, lds, st, L, bt.nch, Cb, Gb, Hb, it,
+                           part_corr);
+                break;
+            default:
+                uno_launch(UNO_KT_FFT_MID, k_lr_mid<1, true>, grid, blk, lds, st, L, bt.nch, Cb, Gb, Hb, it,
+                           part_corr);
+                break;
+        }
+        return;
+    }
     const double* C = (const double*)p->table;
     const double2* Gp = bt.Gp;
     switch (cb) {
@@ -1408,7 +1508,7 @@ uno_status lowrank_fused_pass(const LowRankPlan* p, const Grid& g, const double*
                               double* part_corr, const double* part_rr, double* gam, const LrBatch& bt,
                               hipStream_t st, int* np_dp)
 {
-    if (!p->fused) return UNO_ERR_SHAPE;
+    if (!p->fused || bt.bf) return UNO_ERR_SHAPE;
     launch_mid(p, bt, p->cb_mid, it, part_corr, st);  // the plan's grouping: part_corr has blocks_mid partials
     UNO_HIP(hipGetLastError());
     const LrTileArgs a{part_rr, p->dev.n0 * bt.nch, part_corr, p->blocks_mid};
@@ -1430,6 +1530,7 @@ uno_status lowrank_finish(const LowRankPlan* p, const double* r, T* s, const CgI
 {
     const LowRankDev& L = p->dev;
     const CgIter it = itp ? *itp : no_iter();
+    if (bt.bf && (L.nc != 1 || sizeof(T) != sizeof(float))) return UNO_ERR_ARG;
     if (L.nc == 3)
         uno_launch(UNO_KT_FFT_MID, k_lr_mid3, dim3((L.kyn * L.kzn + bt.cb - 1) / bt.cb, bt.nrhs), dim3(256),
                    sizeof(double2) * 3 * (size_t)bt.cb * (L.n0 + L.kxn), st, L, bt.nch, bt.cb,
@@ -1439,6 +1540,20 @@ uno_status lowrank_finish(const LowRankPlan* p, const double* r, T* s, const CgI
     UNO_HIP(hipGetLastError());
     const int nbc = L.n0 * ((L.n1 + bt.yc - 1) / bt.yc);
     const dim3 grid(nbc, bt.nrhs);
+    if constexpr (sizeof(T) == sizeof(float)) {
+        if (bt.bf) {
+            const uint32_t* Hb = (const uint32_t*)bt.H;
+            if (itp)
+                uno_launch(UNO_KT_FFT_INV, k_lr_inv_pairs<true, T, true>, grid, dim3(256), p->lds_c, st, L, bt.yc, r,
+                           Hb, s, it);
+            else
+                uno_launch(UNO_KT_FFT_INV, k_lr_inv_pairs<false, T, true>, grid, dim3(256), p->lds_c, st, L, bt.yc, r,
+                           Hb, s, it);
+            UNO_HIP(hipGetLastError());
+            if (np_rs) *np_rs = nbc;
+            return UNO_OK;
+        }
+    }
     if (itp) {
         if (L.nc == 3)
             uno_launch(UNO_KT_FFT_INV, k_lr_inv<true, T, 3>, grid, dim3(256), p->lds_c, st, L, bt.yc, r,

@@ -122,7 +122,8 @@ extern "C" uno_status pcg_solve_many(int32_t nprob, const uno_problem* probs, co
     if (!(opts->rtol >= 0.0) || opts->max_iter < 1) return UNO_ERR_ARG;
     if (opts->kind < UNO_PREC_NONE || opts->kind > UNO_PREC_UNO) return UNO_ERR_ARG;
     const bool f64 = opts->op_t == UNO_F64 && opts->prec_t == UNO_F64;
-    const bool f32 = opts->op_t == UNO_F32 && opts->prec_t == UNO_F32;
+    const bool f32 = opts->op_t == UNO_F32 && (opts->prec_t == UNO_F32 ||
+                                               (opts->prec_t == UNO_BF16 && opts->kind == UNO_PREC_UNO));
     if (!f64 && !f32) return UNO_ERR_ARG;
     // classes of equal grid shape, spacing and preconditioner
     std::map<std::tuple<int, int, int, int, double, double, double, const void*>, int> key;

@@ -167,6 +167,7 @@ struct LrBatch {
     int rb, nch;   // pass A: rows per workgroup, row chunks per slab
     int yc;        // pass C: rows per workgroup
     int cb;        // pass B: columns per workgroup (outside the fused flow)
+    bool bf = false;  // BF16 storage of Gp, H and the table (one nodal DOF, outside the fused flow)
 };
 // nc = 1: cblock kxn x kyn x kzn corrections, W the bypass; nc = 3: six
 // entries per block mode (q1..q6) and the bypass block Wq (6 entries)

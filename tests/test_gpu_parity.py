@@ -304,6 +304,53 @@ def test_mixed_precision_kbar_within_1e5(orc, uno, kind):
     assert err < 1e-5
 
 
+def test_bf16_spectrum_mode(orc, uno):
+    """BF16 preconditioner mode (FP32 operator and vectors; the learned-mode
+    passes' table, row-chunk partials and per-mode coefficients stored in
+    BF16, their arithmetic and every recurrence FP64): the solutions reach
+    the tolerance with their true FP64 residual and kappa_bar is within 1e-5
+    of the FP64 oracle; the residual history departs from the FP32 mode's by
+    the BF16 rounding (the storage is in effect) but stays close to it."""
+    shape, M = (24, 24, 24), 4
+    kap = _two_phase(shape, 31)
+    th = si.random_theta(uno.num_weights(3, M), 5, scale=0.05, spread=0.2)
+    p = uno.UnoPrecond.create(shape, M, th)
+    p.set_path(2)
+    kw = dict(kind="uno", precond=p, rtol=1e-8, op_dtype=torch.float32)
+    kb, infos = _kbar_gpu(uno, kap, prec_dtype=torch.bfloat16, **kw)
+    err = rel(kb, _kbar_oracle(orc, kap))
+    _, i32 = _kbar_gpu(uno, kap, prec_dtype=torch.float32, **kw)
+    print("bf16 mode kappa_bar rel err %.2e" % err, [i["iters"] for i in infos], "fp32", [i["iters"] for i in i32],
+          flush=True)
+    assert all(i["converged"] and i["true_rel_res"] < 1e-8 for i in infos)
+    assert err < 1e-5
+    g = np.array([1.0, 0.0, 0.0])
+    _, _, h16 = uno.pcg_solve(T(kap), macro_load=g, prec_dtype=torch.bfloat16, history=True, **kw)
+    _, _, h32 = uno.pcg_solve(T(kap), macro_load=g, prec_dtype=torch.float32, history=True, **kw)
+    d = rel(np.asarray(h16)[1:6], np.asarray(h32)[1:6])
+    print("bf16 mode: first residuals against the FP32 mode's, rel diff %.2e" % d, flush=True)
+    assert 1e-7 < d < 5e-2
+
+
+def test_bf16_mode_batch_and_refusals(uno):
+    """The BF16 mode carries a batch of loads like the FP32 mode; it needs
+    UNO-CG with the FP32 operator (Jacobi or an FP64 operator are refused)."""
+    shape, M = (16, 20, 24), 3
+    kap = _two_phase(shape, 36)
+    th = si.random_theta(uno.num_weights(3, M), 8, scale=0.05, spread=0.2)
+    p = uno.UnoPrecond.create(shape, M, th)
+    loads = np.eye(3)
+    _, infos = uno.pcg_solve_batch(T(kap), macro_loads=loads, kind="uno", precond=p, rtol=1e-8,
+                                   op_dtype=torch.float32, prec_dtype=torch.bfloat16)
+    assert all(i["converged"] and i["true_rel_res"] < 1e-8 for i in infos)
+    g = np.array([0.0, 1.0, 0.0])
+    with pytest.raises(uno.UnoError):
+        uno.pcg_solve(T(kap), macro_load=g, kind="jacobi", rtol=1e-8, op_dtype=torch.float32,
+                      prec_dtype=torch.bfloat16)
+    with pytest.raises(uno.UnoError):
+        uno.pcg_solve(T(kap), macro_load=g, kind="uno", precond=p, rtol=1e-8, prec_dtype=torch.bfloat16)
+
+
 def test_bf16_table_converges_to_same_solution(orc, uno):
     """A table rounded to bfloat16 changes the preconditioner, not the
     solution: FP64 UNO-CG still matches the oracle to 1e-8."""
