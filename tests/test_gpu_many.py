@@ -111,6 +111,31 @@ def test_many_fp32_mode_matches_fp64(orc, uno):
         assert (a - b).abs().max().item() < 1e-4 * a.abs().max().item()
 
 
+def test_many_bf16_mode_matches_fp64(uno):
+    """The BF16 preconditioner storage mode over the whole work list (FP32
+    operator; the learned-mode passes' table and spectrum in BF16): every
+    solve reaches its tolerance with its true FP64 residual, and every
+    effective tensor is within 1e-5 of the FP64 one."""
+    probs = work_list(500)
+    pre = {}
+    for kap, _ in probs:
+        if kap.shape not in pre:
+            pre[kap.shape] = uno.UnoPrecond.create(kap.shape, 1, si.random_theta(uno.num_weights(len(kap.shape), 1),
+                                                                                7, scale=0.05))
+    items = [{"kappa": T(k), "loads": l, "precond": pre[k.shape]} for k, l in probs]
+    u64, i64 = uno.pcg_solve_many(items, kind="uno", rtol=1e-8)
+    items = [{"kappa": T(k), "loads": l, "precond": pre[k.shape]} for k, l in probs]
+    u16, i16 = uno.pcg_solve_many(items, kind="uno", rtol=1e-8, op_dtype=torch.float32, prec_dtype=torch.bfloat16)
+    for (kap, loads), a, b, ia, ib in zip(probs, u64, u16, i64, i16):
+        assert all(i["converged"] for i in ia + ib)
+        assert all(i["true_rel_res"] <= 1e-8 * (1 + 1e-6) for i in ia + ib)
+        d = len(kap.shape)
+        if len(loads) == d:
+            ka = uno.effective_tensor(T(kap), loads, a)
+            kb = uno.effective_tensor(T(kap), loads, b)
+            assert np.abs(kb - ka).max() < 1e-5 * np.abs(ka).max()
+
+
 @pytest.mark.parametrize("kind", ["jacobi", "uno"])
 def test_many_fp32_mode_true_residual_at_exit(uno, kind):
     """FP32 mode on larger high-contrast cells (2D 256^2 and 128^2, 3D 32^3,
